@@ -1,0 +1,174 @@
+/*
+ * lmfmm -- layered-medium Nystrom boundary integral solver for 2D Helmholtz
+ * scattering on MI355X (gfx950).
+ *
+ * Method: Xia, Yuan, Wang, Cai, "Fast boundary integral method for acoustic
+ * wave scattering in two-dimensional layered media".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All functions are extern "C" and return lm_status.  Negative values are
+ *   errors (outputs undefined), positive values are warnings (outputs
+ *   written), LM_OK is 0.  lm_last_error() returns a thread-local message for
+ *   the last non-OK status of the calling thread.
+ * - Complex numbers are interleaved (re, im) pairs: c128 = 2 x double,
+ *   c64 = 2 x float.
+ * - "host" pointers are read during the call only and are copied; "device"
+ *   pointers are HIP device allocations owned by the caller (for example
+ *   torch tensors); the library never frees them.
+ * - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is enqueued on that stream; calls that return host results
+ *   (reports, info) synchronise it.
+ * - Element numbering: element j of scatterer m is the chord from node j to
+ *   node j+1 (the last node connects to the first) of the m-th polygon, and
+ *   elements are numbered scatterer by scatterer in input order.  Every
+ *   [n_rhs][N] array uses this numbering; vector r occupies entries
+ *   [r*N, (r+1)*N).
+ * - Handles are opaque; create functions copy their inputs; each handle is
+ *   freed by its destroy function.  Only the lm_server_* / lm_submit /
+ *   lm_poll / lm_cancel entry points are thread-safe.
+ */
+#ifndef LMFMM_H
+#define LMFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lm_layers_s* lm_layers;
+typedef struct lm_geom_s* lm_geom;
+typedef struct lm_server_s* lm_server;
+
+typedef enum {
+  LM_OK = 0,
+  LM_NOT_CONVERGED = 1, /* GMRES stopped at max_iter; outputs written */
+  LM_EINVAL = -1,       /* invalid argument (NaN, bad sizes, bad geometry) */
+  LM_ENOMEM = -2,       /* device or host allocation failed / over budget */
+  LM_EHIP = -3,         /* a HIP runtime call failed */
+  LM_ENOTFOUND = -4,    /* unknown request id */
+  LM_ECANCELLED = -5,   /* request was cancelled */
+  LM_EINTERNAL = -6
+} lm_status;
+
+/* LM_FP64: every step in double precision (the plain form).
+ * LM_MIXED: near-field and translation arithmetic in FP32 accumulated in
+ * FP32; spectral coefficients, singular self terms, GMRES Arnoldi/Givens in
+ * FP64 (the served form). */
+typedef enum { LM_FP64 = 0, LM_MIXED = 1 } lm_precision;
+
+const char* lm_last_error(void);
+
+/* Library version string, e.g. "lmfmm 0.1 gfx950". */
+const char* lm_version(void);
+
+/* ---------------------------------------------------------------- medium --
+ * Sec. 2.1: L+1 layers l = 0..L (top to bottom), interfaces y = -d[l] for
+ * l = 0..L-1 with d strictly increasing, wavenumbers k[l] > 0, and weights
+ * eta[l] > 0 of the transmission condition [eta du/dn] = 0 (eta == NULL means
+ * all ones).  n_layers = L+1 >= 2, at most LM_MAX_LAYERS.
+ * Errors: LM_EINVAL for NaN/inf, non-increasing d, k <= 0, eta <= 0. */
+#define LM_MAX_LAYERS 8
+lm_status lm_create_layers(int n_layers, const double* d_host, const double* k_host,
+                           const double* eta_host, lm_layers* out);
+lm_status lm_destroy_layers(lm_layers layers);
+
+/* -------------------------------------------------------------- geometry --
+ * Sec. 3.3 (eq. linearSystem): each scatterer boundary is a closed polygon
+ * of nodes; element = chord between consecutive nodes, collocation point =
+ * chord midpoint, |Gamma_e| = chord length, layer = layer of the midpoint
+ * (a midpoint within 1e-12 of an interface belongs to the upper layer).
+ *
+ * node_offsets_host: n_scatterers+1 increasing int64, node_offsets[0] = 0,
+ *   each polygon has >= 3 nodes.
+ * nodes_xy_host: 2*node_offsets[n_scatterers] doubles, (x, y) per node.
+ * opts: NULL for defaults.
+ *   method: LM_DENSE assembles the full matrix by direct Sommerfeld
+ *           quadrature (O(N^2) memory, intended for N <= ~16k);
+ *           LM_FMM uses the layered fast multipole method (Sec. 4.1);
+ *           LM_AUTO picks DENSE for N <= 4096.
+ *   p: expansion order (default 20); leaf_size: target points per leaf
+ *   (default 48); precond: build the overlapping domain-decomposition
+ *   preconditioner of Sec. 4.2 (default 1 for FMM, 0 for dense).
+ * The handle keeps a reference to `layers`, which must outlive it.
+ * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */
+typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;
+typedef struct {
+  int method;
+  int p;
+  int leaf_size;
+  int precond;
+} lm_geom_opts;
+lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* node_offsets_host,
+                             const double* nodes_xy_host, const lm_geom_opts* opts, void* hip_stream,
+                             lm_geom* out);
+/* n_elements, bytes of device memory held by the handle, and the method in use. */
+lm_status lm_geometry_info(lm_geom geom, int64_t* n_elements, int64_t* device_bytes, int* method);
+/* Element data in input numbering (host outputs, any may be NULL):
+ * cx, cy, w: double[N]; layer: int32[N]. */
+lm_status lm_geometry_elements(lm_geom geom, double* cx, double* cy, double* w, int32_t* layer);
+lm_status lm_destroy_geometry(lm_geom geom);
+
+/* ---------------------------------------------------------------- matvec --
+ * y = K x for n_rhs vectors (eq. Llayerscomponent, unscaled form):
+ *   (K x)_i = sum_{e != i, layer e == layer i} |Gamma_e| G^f(c_i|c_e) x_e
+ *           + sum_e |Gamma_e| G^r(c_i|c_e) x_e + I^s_i x_i,
+ * i.e. the paper's system with the eta scaling divided out row by row (the
+ * paper's source-first eta-scaled system has the same solution).
+ * x_dev, y_dev: device [n_rhs][N]; c128 for LM_FP64, c64 for LM_MIXED.
+ * x and y must not overlap. */
+lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev,
+                    void* hip_stream);
+
+/* ------------------------------------------------------------------- rhs --
+ * g = -u^inc - u^b on Gamma_0 and -u^b elsewhere (eq. homogeneousscattering)
+ * for plane waves travelling along (cos t, -sin t), t = theta_host[r] in
+ * radians, 0 < t < pi.  g_dev: device c128 [n_rhs][N]. */
+lm_status lm_rhs(lm_geom geom, int n_rhs, const double* theta_host, void* g_dev, void* hip_stream);
+
+/* ----------------------------------------------------------------- solve --
+ * GMRES for K phi = g (Sec. 3.3, Sec. 5): x0 = 0, restarted every `restart`
+ * iterations, right preconditioning by the domain-decomposition
+ * preconditioner when precond != 0 and the geometry has one; stops when
+ * ||g - K phi|| <= tol ||g|| for every right-hand side or after max_iter.
+ * Arnoldi (classical Gram-Schmidt, two passes) and Givens rotations are FP64
+ * for both precisions.  phi_dev: device c128 [n_rhs][N] (output).
+ * reports_host: n_rhs entries (output).  Returns LM_NOT_CONVERGED if any
+ * right-hand side missed the tolerance. */
+typedef struct {
+  double tol;
+  int max_iter;
+  int restart;
+  int precond;
+} lm_gmres_opts;
+typedef struct {
+  int iterations;
+  double rel_residual;
+} lm_solve_report;
+lm_status lm_gmres_solve(lm_geom geom, int precision, int n_rhs, const double* theta_host,
+                         const lm_gmres_opts* opts, void* phi_dev, lm_solve_report* reports_host,
+                         void* hip_stream);
+/* Same solver for caller-provided right-hand sides g_dev (device c128 [n_rhs][N]). */
+lm_status lm_gmres_solve_rhs(lm_geom geom, int precision, int n_rhs, const void* g_dev,
+                             const lm_gmres_opts* opts, void* phi_dev, lm_solve_report* reports_host,
+                             void* hip_stream);
+
+/* ------------------------------------------------------------- far field --
+ * Far-field pattern of the scattered field (eq. integralrep in the
+ * stationary-phase limit): for 0 < t < pi (top layer)
+ *   u^s(R, t) ~ e^{i k_0 R}/sqrt(R) * u_inf(t),
+ *   u_inf(t) = e^{-i pi/4} sqrt(k_0/2pi) sin t sum_e |Gamma_e| phi_e a_e(k_0 cos t),
+ * and the mirror formula with k_L for pi < t < 2pi (bottom layer); a_e is the
+ * spectral source factor of the free-space part and of every reaction
+ * component reaching the top (bottom) layer.
+ * phi_dev: device c128 [n_rhs][N]; obs_host: n_obs angles in radians (none
+ * horizontal); out_dev: device c128 [n_rhs][n_obs]. */
+lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, const double* obs_host,
+                       void* out_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMFMM_H */

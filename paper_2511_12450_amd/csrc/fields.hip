@@ -1,0 +1,160 @@
+// Right-hand side (incident + background field) and far-field patterns.
+#include "lm_internal.hpp"
+
+// ------------------------------------------------------------------- rhs --
+// Sec. 2.2: u^b = A_l e^{i(kx x + k_{l,y} y)} + B_l e^{i(kx x - k_{l,y} y)} with
+// A_0 = R~_{01} e^{2 i k_{0,y} d_0}, A_l = R~_{l,l+1} T~_{0l} e^{2 i k_{l,y} d_l},
+// B_l = T~_{0l} (B_0 = 0, A_L = 0), all at lam = kx = k_0 cos(theta).
+struct BgAmp {
+  double kx;
+  zd ky[LM_MAXL], A[LM_MAXL], B[LM_MAXL];
+};
+
+__global__ void k_background(MediumDev m, int R, const double* __restrict__ theta, BgAmp* __restrict__ amp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const double kx = m.k[0] * cos(theta[r]);
+  StackAt st;
+  stack_at(m, zd(kx, 0.0), st);
+  BgAmp a;
+  a.kx = kx;
+  for (int l = 0; l <= m.L; ++l) {
+    a.ky[l] = st.ky[l];
+    a.A[l] = a.B[l] = zd(0.0, 0.0);
+  }
+  a.A[0] = st.Rdn[0] * zexp(zd(0.0, 2.0 * m.d[0]) * st.ky[0]);
+  for (int l = 1; l <= m.L; ++l) {
+    zd T = gen_transmission(m, st, 0, l);
+    a.B[l] = T;
+    if (l < m.L) a.A[l] = st.Rdn[l] * T * zexp(zd(0.0, 2.0 * m.d[l]) * st.ky[l]);
+  }
+  amp[r] = a;
+}
+
+__global__ void k_rhs(int N, int R, const BgAmp* __restrict__ amp, const double* __restrict__ cx,
+                      const double* __restrict__ cy, const int* __restrict__ lay, const double* __restrict__ theta,
+                      const MediumDev m, double2* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const BgAmp& a = amp[r];
+  const int l = lay[i];
+  const double x = cx[i], y = cy[i];
+  const zd ex = zexp(zd(0.0, a.kx * x));
+  zd u = a.A[l] * zexp(zd(0.0, y) * a.ky[l]) + a.B[l] * zexp(zd(0.0, -y) * a.ky[l]);
+  if (l == 0) u += zexp(zd(0.0, -m.k[0] * sin(theta[r]) * y));
+  u = -(u * ex);
+  g[(int64_t)r * N + i] = make_double2(u.re, u.im);
+}
+
+lm_status rhs_launch(lm_geom_s* g, int R, const double* theta_host, void* g_dev, hipStream_t s) {
+  DevBuf th, amp;
+  LM_TRY(upload(th, theta_host, R * sizeof(double), s));
+  LM_TRY(amp.alloc(R * sizeof(BgAmp)));
+  hipLaunchKernelGGL(k_background, dim3(div_up(R, 64)), dim3(64), 0, s, g->m, R, th.as<double>(), amp.as<BgAmp>());
+  LM_TRY_HIP(hipGetLastError());
+  const int N = (int)g->N;
+  hipLaunchKernelGGL(k_rhs, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(), g->d_cx.as<double>(),
+                     g->d_cy.as<double>(), g->d_layer.as<int>(), th.as<double>(), g->m, (double2*)g_dev);
+  LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+  return LM_OK;
+}
+
+// -------------------------------------------------------------- far field --
+// Stationary phase of the single-layer representation (eq. integralrep) in
+// side form: for an observation direction in the top layer the target side is
+// B of layer 0 (h_t = y + d_0), so u^s ~ e^{i k_0 R}/sqrt(R) u_inf with
+//   u_inf = e^{-i pi/4} sqrt(k_0/2pi) |sin t| sum_e |Gamma_e| phi_e e^{-i lam x_e} a_e,
+//   a_e = [l_e = 0] i/(2 k_{0,y}) e^{-i k_{0,y} y_e}
+//       + e^{i k_{0,y} d_0} sum_s S^{(B,s)}_{0 l_e}(lam) e^{i k_{l_e,y} h_s(y_e)},
+// lam = k_0 cos t; the bottom layer mirrors this with side T of layer L.
+constexpr int FF_RB = 8;
+
+__global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, const double* __restrict__ obs,
+                                                   const double* __restrict__ cx, const double* __restrict__ cy,
+                                                   const double* __restrict__ w, const int* __restrict__ lay,
+                                                   const double2* __restrict__ phi, double2* __restrict__ out,
+                                                   int n_obs) {
+  const int o = blockIdx.x;
+  const int r0 = blockIdx.y * FF_RB;
+  const int nr = min(FF_RB, R - r0);
+  const double th = obs[o];
+  const bool top = sin(th) > 0.0;
+  const int lt = top ? 0 : m.L;
+  const int tside = top ? SIDE_B : SIDE_T;
+  const double kk = m.k[lt];
+  const double lam = kk * cos(th);
+  __shared__ double2 Ssh[LM_MAXL][2];  // S^{(tside, s)}_{lt, ls}, premultiplied by the target constant
+  __shared__ double2 kysh[LM_MAXL];
+  if (threadIdx.x <= (unsigned)m.L) {
+    const int ls = threadIdx.x;
+    StackAt st;
+    stack_at(m, zd(lam, 0.0), st);
+    zd S[4];
+    for (int c = 0; c < 4; ++c) S[c] = zd(0.0, 0.0);
+    side_densities(m, st, lt, ls, 0xFu, S);
+    const zd tc = top ? zexp(zd(0.0, m.d[0]) * st.ky[0]) : zexp(zd(0.0, -m.d[m.L - 1]) * st.ky[m.L]);
+    for (int s = 0; s < 2; ++s) {
+      const int c = tside + 2 * s;
+      const zd v = (side_exists(m, lt, tside) && side_exists(m, ls, s)) ? S[c] * tc : zd(0.0, 0.0);
+      Ssh[ls][s] = make_double2(v.re, v.im);
+    }
+    kysh[ls] = make_double2(st.ky[ls].re, st.ky[ls].im);
+  }
+  __syncthreads();
+  zd acc[FF_RB];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    const int l = lay[e];
+    const double y = cy[e];
+    zd a(0.0, 0.0);
+    const zd kyl(kysh[l].x, kysh[l].y);
+    if (l == lt) a += (zd(0.0, 0.5) / kyl) * zexp(zd(0.0, top ? -y : y) * kyl);
+    for (int s = 0; s < 2; ++s) {
+      if (!side_exists(m, l, s)) continue;
+      a += zd(Ssh[l][s].x, Ssh[l][s].y) * zexp(zd(0.0, side_h(m, l, s, y)) * kyl);
+    }
+    a = a * zexp(zd(0.0, -lam * cx[e])) * w[e];
+    for (int q = 0; q < FF_RB; ++q) {
+      if (q < nr) {
+        const double2 p = phi[(int64_t)(r0 + q) * N + e];
+        acc[q] += a * zd(p.x, p.y);
+      }
+    }
+  }
+  __shared__ double red[2][FF_RB][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = 0; q < FF_RB; ++q) {
+    double a = acc[q].re, b = acc[q].im;
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
+    }
+    if (lane == 0) {
+      red[0][q][wv] = a;
+      red[1][q][wv] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nr) {
+    const int q = threadIdx.x;
+    zd v(red[0][q][0] + red[0][q][1] + red[0][q][2] + red[0][q][3],
+         red[1][q][0] + red[1][q][1] + red[1][q][2] + red[1][q][3]);
+    const zd pre = zexp(zd(0.0, -0.25 * M_PI)) * (sqrt(kk / (2.0 * M_PI)) * fabs(sin(th)));
+    v = v * pre;
+    out[(int64_t)(r0 + q) * n_obs + o] = make_double2(v.re, v.im);
+  }
+}
+
+lm_status farfield_launch(lm_geom_s* g, int R, const void* phi, int n_obs, const double* obs_host, void* out,
+                          hipStream_t s) {
+  DevBuf ob;
+  LM_TRY(upload(ob, obs_host, n_obs * sizeof(double), s));
+  const int N = (int)g->N;
+  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, g->m, N, R, ob.as<double>(),
+                     g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
+                     (const double2*)phi, (double2*)out, n_obs);
+  LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipStreamSynchronize(s));
+  return LM_OK;
+}

@@ -1,0 +1,122 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/lmfmm.h"
+#include "spectral.hpp"
+
+// ----------------------------------------------------------------- errors --
+void lm_set_error(const char* fmt, ...);
+
+#define LM_TRY_HIP(expr)                                                             \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      lm_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return e_ == hipErrorOutOfMemory ? LM_ENOMEM : LM_EHIP;                        \
+    }                                                                                \
+  } while (0)
+
+#define LM_CHECK(cond, status, ...)  \
+  do {                               \
+    if (!(cond)) {                   \
+      lm_set_error(__VA_ARGS__);     \
+      return status;                 \
+    }                                \
+  } while (0)
+
+#define LM_TRY(expr)               \
+  do {                             \
+    lm_status s_ = (expr);         \
+    if (s_ < 0) return s_;         \
+  } while (0)
+
+// ----------------------------------------------------------- device memory --
+// Owning device buffer (hipMalloc / hipFree).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  lm_status alloc(size_t n) {
+    release();
+    if (n == 0) return LM_OK;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      lm_set_error("hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+      return LM_ENOMEM;
+    }
+    bytes = n;
+    return LM_OK;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+lm_status upload(DevBuf& b, const void* host, size_t bytes, hipStream_t s);
+
+// ------------------------------------------------------------------ layers --
+struct lm_layers_s {
+  MediumDev m;
+};
+
+// ----------------------------------------------------------------- geometry --
+struct FmmPlan;   // fmm.hip
+struct Precond;   // precond.hip
+
+struct lm_geom_s {
+  const lm_layers_s* layers = nullptr;
+  MediumDev m;
+  int64_t N = 0;
+  int method = LM_DENSE;
+  int p = 20;
+  int leaf_size = 48;
+  // host element data, input numbering
+  std::vector<double> cx, cy, w;
+  std::vector<int32_t> layer;
+  // device element data, input numbering
+  DevBuf d_cx, d_cy, d_w, d_layer;
+  // dense path
+  DevBuf d_K;          // complex128 row-major [N][N]
+  DevBuf d_K32;        // complex64 copy for the mixed form
+  // fast path
+  FmmPlan* fmm = nullptr;
+  Precond* pre = nullptr;
+  int64_t device_bytes() const;
+  ~lm_geom_s();
+};
+
+// ------------------------------------------------------------ entry points --
+lm_status dense_assemble(lm_geom_s* g, hipStream_t s);
+lm_status dense_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status rhs_launch(lm_geom_s* g, int n_rhs, const double* theta_host, void* g_dev, hipStream_t s);
+lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_host,
+                          void* out, hipStream_t s);
+lm_status gmres_run(lm_geom_s* g, int precision, int n_rhs, const void* g_dev, const lm_gmres_opts* o,
+                    void* phi_dev, lm_solve_report* rep, hipStream_t s);
+
+lm_status fmm_build(lm_geom_s* g, hipStream_t s);
+void fmm_free(FmmPlan* f);
+int64_t fmm_bytes(const FmmPlan* f);
+lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+
+lm_status precond_build(lm_geom_s* g, hipStream_t s);
+void precond_free(Precond* p);
+int64_t precond_bytes(const Precond* p);
+lm_status precond_apply(lm_geom_s* g, int n_rhs, const void* x, void* y, hipStream_t s);
+
+inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }

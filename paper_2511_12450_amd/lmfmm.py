@@ -1,0 +1,219 @@
+"""Thin ctypes binding of liblmfmm.so (the C-ABI in include/lmfmm.h).
+
+Argument marshalling only: every step of the computation runs inside the
+library (host runtime + HIP kernels).  torch provides device memory and the
+current stream.  There is no fallback: if the library is missing or a call
+fails, an exception is raised.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmfmm.so")
+
+LM_OK, LM_NOT_CONVERGED = 0, 1
+LM_FP64, LM_MIXED = 0, 1
+LM_AUTO, LM_DENSE, LM_FMM = 0, 1, 2
+
+_lib = None
+
+
+class LmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lmfmm status {status}: {msg}")
+        self.status = status
+
+
+class GeomOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int), ("precond", ctypes.c_int)]
+
+
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
+                ("precond", ctypes.c_int)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+_SIGS = {
+    "lm_last_error": ([], ctypes.c_char_p),
+    "lm_version": ([], ctypes.c_char_p),
+    "lm_create_layers": ([_ip, _dp, _dp, _dp, ctypes.POINTER(_vp)], _ip),
+    "lm_destroy_layers": ([_vp], _ip),
+    "lm_create_geometry": ([_vp, _ip, ctypes.POINTER(ctypes.c_int64), _dp, ctypes.POINTER(GeomOpts), _vp,
+                            ctypes.POINTER(_vp)], _ip),
+    "lm_geometry_info": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int)], _ip),
+    "lm_geometry_elements": ([_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)], _ip),
+    "lm_destroy_geometry": ([_vp], _ip),
+    "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
+    "lm_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
+    "lm_gmres_solve": ([_vp, _ip, _ip, _dp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp], _ip),
+    "lm_gmres_solve_rhs": ([_vp, _ip, _ip, _vp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp],
+                           _ip),
+    "lm_far_field": ([_vp, _ip, _vp, _ip, _dp, _vp, _vp], _ip),
+}
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status < 0:
+        raise LmError(status, lib().lm_last_error().decode())
+    return status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _tptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Layers:
+    """Sec. 2.1 medium: interfaces y = -d[l], wavenumbers k, weights eta."""
+
+    def __init__(self, d, k, eta=None):
+        d = np.ascontiguousarray(np.atleast_1d(d), dtype=np.float64)
+        k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+        e = None if eta is None else np.ascontiguousarray(np.atleast_1d(eta), dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().lm_create_layers(k.size, _dptr(d), _dptr(k), None if e is None else _dptr(e), ctypes.byref(h)))
+        self.h = h
+        self.d, self.k = d, k
+
+    def close(self):
+        if self.h:
+            lib().lm_destroy_layers(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    """Elements of closed node polygons (Sec. 3.3) plus the operator data."""
+
+    def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1):
+        off = np.ascontiguousarray(node_offsets, dtype=np.int64)
+        xy = np.ascontiguousarray(nodes_xy, dtype=np.float64)
+        o = GeomOpts(method, p, leaf_size, precond)
+        h = ctypes.c_void_p()
+        _check(lib().lm_create_geometry(layers.h, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        _dptr(xy), ctypes.byref(o), _stream(), ctypes.byref(h)))
+        self.h = h
+        self.layers = layers  # keeps the medium alive
+        n = ctypes.c_int64()
+        b = ctypes.c_int64()
+        m = ctypes.c_int()
+        _check(lib().lm_geometry_info(h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(m)))
+        self.n, self.device_bytes, self.method = n.value, b.value, m.value
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        lay = Layers(w.d, w.k, w.eta)
+        off, xy = w.flat_nodes()
+        return cls(lay, off, xy, **kw)
+
+    def elements(self):
+        cx, cy, ww = (np.empty(self.n) for _ in range(3))
+        lay = np.empty(self.n, dtype=np.int32)
+        _check(lib().lm_geometry_elements(self.h, _dptr(cx), _dptr(cy), _dptr(ww),
+                                          lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return cx, cy, ww, lay
+
+    def close(self):
+        if self.h:
+            lib().lm_destroy_geometry(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operations on torch device tensors -----------------------------------
+    def matvec(self, x, y=None, precision=LM_FP64):
+        import torch
+        dt = torch.complex128 if precision == LM_FP64 else torch.complex64
+        x = x.reshape(-1, self.n)
+        assert x.dtype == dt and x.is_cuda and x.is_contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().lm_matvec(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
+        return y
+
+    def rhs(self, theta_rad):
+        import torch
+        th = np.ascontiguousarray(np.atleast_1d(theta_rad), dtype=np.float64)
+        g = torch.empty((th.size, self.n), dtype=torch.complex128, device="cuda")
+        _check(lib().lm_rhs(self.h, th.size, _dptr(th), _tptr(g), _stream()))
+        return g
+
+    def solve(self, theta_rad, tol=1e-8, max_iter=500, restart=200, precond=1, precision=LM_FP64):
+        import torch
+        th = np.ascontiguousarray(np.atleast_1d(theta_rad), dtype=np.float64)
+        phi = torch.empty((th.size, self.n), dtype=torch.complex128, device="cuda")
+        rep = (SolveReport * th.size)()
+        o = GmresOpts(tol, max_iter, restart, precond)
+        st = _check(lib().lm_gmres_solve(self.h, precision, th.size, _dptr(th), ctypes.byref(o), _tptr(phi), rep,
+                                         _stream()))
+        return phi, [(r.iterations, r.rel_residual) for r in rep], st
+
+    def solve_rhs(self, g, tol=1e-8, max_iter=500, restart=200, precond=1, precision=LM_FP64):
+        import torch
+        g = g.reshape(-1, self.n).contiguous()
+        phi = torch.empty_like(g)
+        rep = (SolveReport * g.shape[0])()
+        o = GmresOpts(tol, max_iter, restart, precond)
+        st = _check(lib().lm_gmres_solve_rhs(self.h, precision, g.shape[0], _tptr(g), ctypes.byref(o), _tptr(phi),
+                                             rep, _stream()))
+        return phi, [(r.iterations, r.rel_residual) for r in rep], st
+
+    def far_field(self, phi, obs_rad):
+        import torch
+        phi = phi.reshape(-1, self.n).contiguous()
+        ob = np.ascontiguousarray(np.atleast_1d(obs_rad), dtype=np.float64)
+        out = torch.empty((phi.shape[0], ob.size), dtype=torch.complex128, device="cuda")
+        _check(lib().lm_far_field(self.h, phi.shape[0], _tptr(phi), ob.size, _dptr(ob), _tptr(out), _stream()))
+        return out
+
+
+def far_field_angles():
+    """341 angles per side: 5..175 deg (top) and 185..355 deg (bottom), 0.5 deg steps."""
+    top = np.radians(np.arange(5.0, 175.0 + 1e-9, 0.5))
+    bot = np.radians(np.arange(185.0, 355.0 + 1e-9, 0.5))
+    return np.concatenate([top, bot])
