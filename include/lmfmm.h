@@ -109,6 +109,11 @@ lm_status lm_geometry_info(lm_geom geom, int64_t* n_elements, int64_t* device_by
  * cx, cy, w: double[N]; layer: int32[N]. */
 lm_status lm_geometry_elements(lm_geom geom, double* cx, double* cy, double* w, int32_t* layer);
 lm_status lm_destroy_geometry(lm_geom geom);
+/* Size of the fast-method plan (all zero for LM_DENSE), host output of 8
+ * int64: boxes, M2L list entries, free-space M2L classes, reaction M2L
+ * operators (Sommerfeld tables), reaction near-field pairs, free-space leaf
+ * level, reaction finest level, free-space near-field leaf pairs. */
+lm_status lm_fmm_stats(lm_geom geom, int64_t* out8);
 
 /* ---------------------------------------------------------------- matvec --
  * y = K x for n_rhs vectors (eq. Llayerscomponent, unscaled form):

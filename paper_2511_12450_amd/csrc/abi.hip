@@ -171,6 +171,12 @@ extern "C" lm_status lm_geometry_elements(lm_geom g, double* cx, double* cy, dou
   return LM_OK;
 }
 
+extern "C" lm_status lm_fmm_stats(lm_geom g, int64_t* out8) {
+  LM_CHECK(g && out8, LM_EINVAL, "bad arguments");
+  fmm_stats(g->fmm, out8);
+  return LM_OK;
+}
+
 extern "C" lm_status lm_destroy_geometry(lm_geom g) {
   delete g;
   return LM_OK;

@@ -1,20 +1,985 @@
-// Layered-medium fast multipole method (Sec. 4.1).
-#include "lm_internal.hpp"
+// Layered-medium fast multipole matvec (Sec. 4.1 of the paper).
+//
+// y = K x with K the unscaled Nystrom matrix (eq. Llayerscomponent):
+//   free-space part  -- one quadtree per layer over its elements, classical
+//                       Helmholtz FMM (P2M, M2M, M2L, L2L, L2P, near P2P);
+//   reaction part    -- for each of the 4L^2 components (target side,
+//                       source side) an FMM between the two "side trees":
+//                       quadtrees in (x, h) where h is the distance to the
+//                       interface of that side (the effective location of
+//                       targets / polarization coordinate of sources of
+//                       eqs. equivalent_imag_for_source/_for_target, measured
+//                       from the interface), with M2L operators built from
+//                       Sommerfeld-quadrature tables (eq. metoleimage);
+//   self terms       -- I^s (eq. ApproximateComputation).
+//
+// Tree layout.  All trees share one x-grid (origin x0) and the level widths
+// w_l = w_top / 2^l; rows count from h = 0.  A free-space tree refines
+// uniformly to level lf.  A side tree refines only boxes of row 0 (those
+// touching the interface): in image space (target at +h, source image at -h)
+// only row-0 boxes of both trees are ever adjacent, so every other box is a
+// leaf; the finest level lr is about one element length wide, which leaves
+// only pairs of elements within one element length of the same interface in
+// the near field.  Interaction lists at level l >= 1 are the children of
+// image-adjacent parents that are not image-adjacent themselves (25 classes
+// per level and component: dx in -3..3 boxes, rows 0/1 each); at level 0
+// every non-adjacent pair interacts.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <unordered_map>
 
-struct FmmPlan {
-  int dummy;
+#include "fmm_math.hpp"
+#include "lm_internal.hpp"
+#include "m2l_table.hpp"
+
+namespace {
+
+constexpr int WG = 64;
+constexpr int MAXP = 31;  // 2p+1 <= 63 fits one 64-lane wavefront
+constexpr int MAXPP = 2 * MAXP + 1;
+
+struct BoxDev {
+  double cx, ch, k;
+  int tree, level, parent, pos;
+  int pt0, npt, child0, nchild;
 };
 
-lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
-  (void)g;
-  (void)s;
-  lm_set_error("the FMM method is not available in this build");
-  return LM_EINVAL;
-}
+inline int64_t bkey(int i, int j) { return ((int64_t)i << 32) | (uint32_t)j; }
+
+}  // namespace
+
+struct FmmPlan {
+  int p = 20, P = 41;
+  int nlev = 0, lf = 0, lr = 0;
+  double w_top = 0, x0 = 0;
+  int n_boxes = 0;
+  std::vector<BoxDev> boxes;
+  std::vector<int> level_ptr;     // boxes of level l: ids [level_ptr[l], level_ptr[l+1])
+  std::vector<int> leaf_free, leaf_B, leaf_T;  // leaf boxes by tree class
+  std::vector<int> parents_by_level;           // boxes with children, grouped by level
+  std::vector<int> parents_ptr;
+  std::vector<int> children;
+  std::vector<int> pt_elem;
+  std::vector<double> pt_xh;      // (x, h) per point
+  // M2L lists
+  std::vector<int> m2l_tgt, m2l_ptr, m2l_src, m2l_tab;  // tab >= 0 reaction table, < 0: free table -(id+1)
+  std::vector<double> free_geo;   // (k, dx, dh) per free table
+  std::vector<int> reac_meta;     // (lt, ls, comp) per reaction table
+  std::vector<double> reac_geo;   // (dx, ht, hs)
+  // free near field
+  std::vector<int> near_tgt, near_ptr, near_src;
+  // reaction near field (CSR by element)
+  std::vector<int> rn_ptr, rn_src;
+  std::vector<unsigned> rn_mask;
+  // M2M / L2L operators F_j(d), d = child centre - parent centre; [layer][level][pos][4p+1]
+  std::vector<zd> ftab;
+  std::vector<int> tree_layer;
+  int n_layers = 0;
+  int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  DevBuf d_boxes, d_children, d_pt_elem, d_pt_xh;
+  DevBuf d_leaf_free, d_leaf_B, d_leaf_T, d_parents;
+  DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
+  DevBuf d_free_tab, d_reac_tab, d_ftab;
+  DevBuf d_near_tgt, d_near_ptr, d_near_src;
+  DevBuf d_rn_ptr, d_rn_src, d_rn_val;
+  DevBuf d_self, d_me, d_le, d_tree_layer;
+  int64_t bytes() const {
+    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
+                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_free_tab, &d_reac_tab,
+                           &d_ftab, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
+                           &d_self, &d_me, &d_le, &d_tree_layer};
+    int64_t b = 0;
+    for (auto* d : all) b += d->bytes;
+    return b;
+  }
+};
+
 void fmm_free(FmmPlan* f) { delete f; }
-int64_t fmm_bytes(const FmmPlan* f) { return f ? 0 : 0; }
-lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s) {
-  (void)g; (void)precision; (void)n_rhs; (void)x; (void)y; (void)s;
-  lm_set_error("the FMM method is not available in this build");
-  return LM_EINVAL;
+int64_t fmm_bytes(const FmmPlan* f) { return f ? f->bytes() : 0; }
+void fmm_stats(const FmmPlan* f, int64_t* out) {
+  for (int i = 0; i < 8; ++i) out[i] = f ? f->stats[i] : 0;
+}
+
+// =========================================================== setup kernels ==
+
+// Hankel values G_j(D), j = -2p..2p, for each free-space M2L class.
+__global__ void k_free_tables(int n, int p, const double* __restrict__ geo, double2* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int J = 2 * p;
+  zd G[2 * (2 * MAXP) + 1];
+  zd hb[2 * MAXP + 1];
+  fm::g_seq(geo[3 * t], geo[3 * t + 1], geo[3 * t + 2], J, G, hb);
+  for (int j = 0; j <= 2 * J; ++j) out[(int64_t)t * (2 * J + 1) + j] = make_double2(G[j].re, G[j].im);
+}
+
+// Reaction M2L operator per class: one workgroup per table, nodes in chunks.
+constexpr int TAB_CHUNK = 16;
+__global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, const int* __restrict__ meta,
+                                                     const double* __restrict__ geo, double2* __restrict__ out) {
+  const int t = blockIdx.x;
+  const int P = 2 * p + 1;
+  const int lt = meta[3 * t], ls = meta[3 * t + 1], comp = meta[3 * t + 2];
+  const double dx = geo[3 * t], ht = geo[3 * t + 1], hs = geo[3 * t + 2];
+  __shared__ double2 A[TAB_CHUNK][MAXPP];
+  __shared__ double2 B[TAB_CHUNK][MAXPP];
+  ClassNodes cn;
+  class_nodes(cn, m.kmax, dx, ht + hs, p);
+  const int Q = cn.total();
+  constexpr int EPT = (MAXPP * MAXPP + 255) / 256;
+  zd acc[EPT];
+  for (int q0 = 0; q0 < Q; q0 += TAB_CHUNK) {
+    const int tid = threadIdx.x;
+    if (tid < TAB_CHUNK) {
+      const int q = q0 + tid;
+      if (q < Q) {
+        zd f, a, ai, b, bi;
+        class_factor(m, lt, ls, comp, cn, ht, hs, q, f, a, ai, b, bi);
+        zd up = f, dn = f;
+        A[tid][p] = make_double2(f.re, f.im);
+        for (int j = 1; j <= p; ++j) {
+          up = up * a;
+          dn = dn * ai;
+          A[tid][p + j] = make_double2(up.re, up.im);
+          A[tid][p - j] = make_double2(dn.re, dn.im);
+        }
+        zd nb = -b, nbi = -bi;
+        up = zd(1.0, 0.0);
+        dn = zd(1.0, 0.0);
+        B[tid][p] = make_double2(1.0, 0.0);
+        for (int j = 1; j <= p; ++j) {
+          up = up * nb;
+          dn = dn * nbi;
+          B[tid][p + j] = make_double2(up.re, up.im);
+          B[tid][p - j] = make_double2(dn.re, dn.im);
+        }
+      } else {
+        for (int j = 0; j < P; ++j) {
+          A[tid][j] = make_double2(0.0, 0.0);
+          B[tid][j] = make_double2(0.0, 0.0);
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      if (idx >= P * P) break;
+      const int n = idx / P, mm = idx % P;  // column-major: [n][m]
+      zd s = acc[e];
+      for (int q = 0; q < TAB_CHUNK; ++q) {
+        const double2 x = A[q][mm], y = B[q][n];
+        s.re += x.x * y.x - x.y * y.y;
+        s.im += x.x * y.y + x.y * y.x;
+      }
+      acc[e] = s;
+    }
+    __syncthreads();
+  }
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = threadIdx.x + 256 * e;
+    if (idx >= P * P) break;
+    out[(int64_t)t * P * P + idx] = make_double2(acc[e].re, acc[e].im);
+  }
+}
+
+// Reaction near-field entries |Gamma_s| G^mask(c_t | c_s) by direct quadrature.
+__global__ void k_reac_near(MediumDev m, int n, const int* __restrict__ tgt, const int* __restrict__ src,
+                            const unsigned* __restrict__ mask, const double* __restrict__ cx,
+                            const double* __restrict__ cy, const double* __restrict__ w, const int* __restrict__ lay,
+                            double2* __restrict__ val) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = tgt[t], e = src[t];
+  const zd v = lmq::reaction_direct(m, lay[i], lay[e], fabs(cx[i] - cx[e]), cy[i], cy[e], mask[t]) * w[e];
+  val[t] = make_double2(v.re, v.im);
+}
+
+// ========================================================== matvec kernels ==
+
+// P2M: a_n = sum_s q_s J_n(k rho_s) e^{-i n theta_s}, q_s = |Gamma_s| x_s.
+__global__ void __launch_bounds__(WG) k_p2m(int p, const int* __restrict__ leaves, const BoxDev* __restrict__ boxes,
+                                            const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
+                                            const double* __restrict__ w, const double2* __restrict__ x,
+                                            double2* __restrict__ me) {
+  const int b = leaves[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1;
+  __shared__ double Jq_re[WG][MAXP + 1];
+  __shared__ double Jq_im[WG][MAXP + 1];
+  __shared__ double th[WG];
+  const int n = (int)threadIdx.x - p;
+  zd acc(0.0, 0.0);
+  for (int s0 = 0; s0 < B.npt; s0 += WG) {
+    const int s = s0 + threadIdx.x;
+    if (s < B.npt) {
+      const int pi = B.pt0 + s;
+      const double2 xh = pt_xh[pi];
+      const double dx = xh.x - B.cx, dh = xh.y - B.ch;
+      const int e = pt_elem[pi];
+      const double2 xv = x[e];
+      const double we = w[e];
+      double J[MAXP + 1];
+      fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
+      for (int j = 0; j <= p; ++j) {
+        Jq_re[threadIdx.x][j] = J[j] * we * xv.x;
+        Jq_im[threadIdx.x][j] = J[j] * we * xv.y;
+      }
+      th[threadIdx.x] = atan2(dh, dx);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)P) {
+      const int cnt = min(WG, B.npt - s0);
+      const int an = n < 0 ? -n : n;
+      const double sg = (n < 0 && (an & 1)) ? -1.0 : 1.0;
+      for (int j = 0; j < cnt; ++j) {
+        double sn, cs;
+        sincos(-n * th[j], &sn, &cs);
+        const double re = Jq_re[j][an] * sg, im = Jq_im[j][an] * sg;
+        acc.re += re * cs - im * sn;
+        acc.im += re * sn + im * cs;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)P) me[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
+}
+
+// Operator F_j(d) for the box's layer/level/position: ftab[((layer*nlev + level)*4 + pos)*(4p+1) + j + 2p]
+__device__ __forceinline__ const double2* ftab_row(const double2* ftab, int nlev, int p, int layer, int level, int pos) {
+  return ftab + ((int64_t)((layer * nlev + level) * 4 + pos)) * (4 * p + 1) + 2 * p;
+}
+
+// M2M: a^C_n = sum_children sum_m F_{m-n}(C - c) a^c_m = sum (-1)^{m-n} F_{m-n}(c - C) a_m.
+__global__ void __launch_bounds__(WG) k_m2m(int p, int nlev, const int* __restrict__ parents,
+                                            const BoxDev* __restrict__ boxes, const int* __restrict__ children,
+                                            const int* __restrict__ tree_layer, const double2* __restrict__ ftab,
+                                            double2* __restrict__ me) {
+  const int b = parents[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1;
+  __shared__ double2 a[MAXPP];
+  __shared__ double2 f[4 * MAXP + 1];
+  const int n = (int)threadIdx.x - p;
+  zd acc(0.0, 0.0);
+  for (int c = 0; c < B.nchild; ++c) {
+    const int cb = children[B.child0 + c];
+    const BoxDev C = boxes[cb];
+    if (threadIdx.x < (unsigned)P) a[threadIdx.x] = me[(int64_t)cb * P + threadIdx.x];
+    const double2* fr = ftab_row(ftab, nlev, p, tree_layer[C.tree], C.level, C.pos);
+    for (int j = threadIdx.x; j <= 4 * p; j += WG) f[j] = fr[j - 2 * p];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)P) {
+      for (int mm = -p; mm <= p; ++mm) {
+        const int d = mm - n;
+        const double2 fv = f[d + 2 * p];
+        const double sg = (d & 1) ? -1.0 : 1.0;
+        const double2 av = a[mm + p];
+        acc.re += sg * (fv.x * av.x - fv.y * av.y);
+        acc.im += sg * (fv.x * av.y + fv.y * av.x);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)P) me[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
+}
+
+// M2L for every target box with a list (all levels): b_m = sum over list.
+//   free entry  (tab < 0): b_m += (i/4) sum_n G_{n-m}(c_t - c_s) a_n
+//   reaction    (tab >= 0): b_m += sum_n Ttilde[n][m] a_n
+__global__ void __launch_bounds__(WG) k_m2l(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
+                                            const int* __restrict__ src, const int* __restrict__ tab,
+                                            const double2* __restrict__ free_tab,
+                                            const double2* __restrict__ reac_tab, const double2* __restrict__ me,
+                                            double2* __restrict__ le) {
+  const int b = tgts[blockIdx.x];
+  const int P = 2 * p + 1;
+  __shared__ double2 a[MAXPP];
+  __shared__ double2 g[4 * MAXP + 1];
+  const int mrow = (int)threadIdx.x;  // m + p
+  zd acc(0.0, 0.0);
+  for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
+    const int s = src[e], t = tab[e];
+    if (threadIdx.x < (unsigned)P) a[threadIdx.x] = me[(int64_t)s * P + threadIdx.x];
+    if (t < 0) {
+      const double2* gr = free_tab + (int64_t)(-t - 1) * (4 * p + 1);
+      for (int j = threadIdx.x; j <= 4 * p; j += WG) g[j] = gr[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)P) {
+      if (t < 0) {
+        zd s2(0.0, 0.0);
+        for (int nn = 0; nn < P; ++nn) {
+          const double2 gv = g[nn - mrow + 2 * p];
+          const double2 av = a[nn];
+          s2.re += gv.x * av.x - gv.y * av.y;
+          s2.im += gv.x * av.y + gv.y * av.x;
+        }
+        acc.re -= 0.25 * s2.im;  // (i/4) * s2
+        acc.im += 0.25 * s2.re;
+      } else {
+        const double2* T = reac_tab + (int64_t)t * P * P + mrow;
+        for (int nn = 0; nn < P; ++nn) {
+          const double2 tv = T[(int64_t)nn * P];
+          const double2 av = a[nn];
+          acc.re += tv.x * av.x - tv.y * av.y;
+          acc.im += tv.x * av.y + tv.y * av.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)P) le[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
+}
+
+// L2L: b^c_n += sum_m F_{m-n}(c - C) b^C_m, for every box of one level with a parent.
+__global__ void __launch_bounds__(WG) k_l2l(int p, int nlev, int first, const BoxDev* __restrict__ boxes,
+                                            const int* __restrict__ tree_layer, const double2* __restrict__ ftab,
+                                            double2* __restrict__ le) {
+  const int b = first + blockIdx.x;
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1;
+  __shared__ double2 a[MAXPP];
+  __shared__ double2 f[4 * MAXP + 1];
+  if (threadIdx.x < (unsigned)P) a[threadIdx.x] = le[(int64_t)B.parent * P + threadIdx.x];
+  const double2* fr = ftab_row(ftab, nlev, p, tree_layer[B.tree], B.level, B.pos);
+  for (int j = threadIdx.x; j <= 4 * p; j += WG) f[j] = fr[j - 2 * p];
+  __syncthreads();
+  if (threadIdx.x < (unsigned)P) {
+    const int n = (int)threadIdx.x - p;
+    const double2 old = le[(int64_t)b * P + threadIdx.x];
+    zd acc(old.x, old.y);
+    for (int mm = -p; mm <= p; ++mm) {
+      const double2 fv = f[mm - n + 2 * p];
+      const double2 av = a[mm + p];
+      acc.re += fv.x * av.x - fv.y * av.y;
+      acc.im += fv.x * av.y + fv.y * av.x;
+    }
+    le[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
+  }
+}
+
+// L2P: y_e (=/+=) sum_m b_m J_m(k rho) e^{i m theta} for the points of each leaf.
+__global__ void __launch_bounds__(WG) k_l2p(int p, int accumulate, const int* __restrict__ leaves,
+                                            const BoxDev* __restrict__ boxes, const int* __restrict__ pt_elem,
+                                            const double2* __restrict__ pt_xh, const double2* __restrict__ le,
+                                            double2* __restrict__ y) {
+  const int b = leaves[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1;
+  __shared__ double2 L[MAXPP];
+  if (threadIdx.x < (unsigned)P) L[threadIdx.x] = le[(int64_t)b * P + threadIdx.x];
+  __syncthreads();
+  for (int s = threadIdx.x; s < B.npt; s += WG) {
+    const int pi = B.pt0 + s;
+    const double2 xh = pt_xh[pi];
+    const double dx = xh.x - B.cx, dh = xh.y - B.ch;
+    double J[MAXP + 1];
+    fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
+    const zd e1 = fm::cis(atan2(dh, dx));
+    double2 l0 = L[p];
+    zd acc(l0.x * J[0], l0.y * J[0]);
+    zd ep(1.0, 0.0);
+    for (int j = 1; j <= p; ++j) {
+      ep = ep * e1;
+      const double sg = (j & 1) ? -1.0 : 1.0;
+      const double2 lp = L[p + j], lm = L[p - j];
+      const zd cp = zd(lp.x, lp.y) * ep, cm = zd(lm.x, lm.y) * conj(ep);
+      acc += (cp + cm * sg) * J[j];
+    }
+    const int e = pt_elem[pi];
+    if (accumulate) {
+      const double2 o = y[e];
+      y[e] = make_double2(o.x + acc.re, o.y + acc.im);
+    } else {
+      y[e] = make_double2(acc.re, acc.im);
+    }
+  }
+}
+
+// Free-space near field: y_t += sum_{s in neighbour leaves, s != t} (i/4) H0(k|z_t - z_s|) |Gamma_s| x_s.
+__global__ void __launch_bounds__(128) k_p2p(const int* __restrict__ tgts, const int* __restrict__ ptr,
+                                             const int* __restrict__ srcs, const BoxDev* __restrict__ boxes,
+                                             const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
+                                             const double* __restrict__ w, const double2* __restrict__ x,
+                                             double2* __restrict__ y) {
+  const int b = tgts[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const double k = B.k;
+  __shared__ double sx[128], sh[128], qre[128], qim[128];
+  __shared__ int se[128];
+  for (int t0 = 0; t0 < B.npt; t0 += 128) {
+    const int t = t0 + threadIdx.x;
+    const bool act = t < B.npt;
+    double tx = 0, th = 0;
+    int te = -1;
+    if (act) {
+      const double2 xh = pt_xh[B.pt0 + t];
+      tx = xh.x;
+      th = xh.y;
+      te = pt_elem[B.pt0 + t];
+    }
+    zd acc(0.0, 0.0);
+    for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
+      const BoxDev S = boxes[srcs[e]];
+      for (int s0 = 0; s0 < S.npt; s0 += 128) {
+        const int s = s0 + threadIdx.x;
+        __syncthreads();
+        if (s < S.npt) {
+          const double2 xh = pt_xh[S.pt0 + s];
+          const int el = pt_elem[S.pt0 + s];
+          sx[threadIdx.x] = xh.x;
+          sh[threadIdx.x] = xh.y;
+          se[threadIdx.x] = el;
+          const double2 xv = x[el];
+          qre[threadIdx.x] = w[el] * xv.x;
+          qim[threadIdx.x] = w[el] * xv.y;
+        }
+        __syncthreads();
+        if (act) {
+          const int cnt = min(128, S.npt - s0);
+          for (int j = 0; j < cnt; ++j) {
+            if (se[j] == te) continue;
+            const double r = hypot(tx - sx[j], th - sh[j]);
+            const double jr = j0(k * r), yr = y0(k * r);
+            // (i/4)(J0 + i Y0) q
+            const double gre = -0.25 * yr, gim = 0.25 * jr;
+            acc.re += gre * qre[j] - gim * qim[j];
+            acc.im += gre * qim[j] + gim * qre[j];
+          }
+        }
+      }
+    }
+    if (act) {
+      const double2 o = y[te];
+      y[te] = make_double2(o.x + acc.re, o.y + acc.im);
+    }
+  }
+}
+
+// Reaction near field and self term: y_i += sum_j K_ij x_j + I^s_i x_i.
+__global__ void k_near_self(int N, const int* __restrict__ ptr, const int* __restrict__ src,
+                            const double2* __restrict__ val, const double2* __restrict__ self,
+                            const double2* __restrict__ x, double2* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double2 sv = self[i], xi = x[i];
+  double re = sv.x * xi.x - sv.y * xi.y, im = sv.x * xi.y + sv.y * xi.x;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const double2 v = val[e], xv = x[src[e]];
+    re += v.x * xv.x - v.y * xv.y;
+    im += v.x * xv.y + v.y * xv.x;
+  }
+  const double2 o = y[i];
+  y[i] = make_double2(o.x + re, o.y + im);
+}
+
+// ================================================================ host side ==
+
+namespace {
+
+struct TreeB {
+  int layer, side;
+  bool reac;
+  double k;
+  std::vector<int> el;
+  std::vector<double> x, h;
+  std::vector<int> leaf_lev;
+  std::vector<std::vector<int64_t>> keys;            // per level, sorted
+  std::vector<std::unordered_map<int64_t, int>> idx;  // per level: key -> global box id
+};
+
+static constexpr double kEulerGamma = 0.57721566490153286061;
+
+template <typename T>
+lm_status up(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  return upload(b, v.data(), v.size() * sizeof(T), s);
+}
+
+}  // namespace
+
+lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
+  FmmPlan* F = new (std::nothrow) FmmPlan();
+  LM_CHECK(F, LM_ENOMEM, "host allocation failed");
+  g->fmm = F;
+  const MediumDev& m = g->m;
+  const int L = m.L;
+  const int64_t N = g->N;
+  const int p = g->p;
+  LM_CHECK(p >= 4 && p <= MAXP, LM_EINVAL, "the FMM needs 4 <= p <= %d", MAXP);
+  F->p = p;
+  F->P = 2 * p + 1;
+  F->n_layers = L + 1;
+
+  // ---- grid -----------------------------------------------------------------
+  double xmin = 1e300, xmax = -1e300;
+  for (int64_t e = 0; e < N; ++e) {
+    xmin = std::min(xmin, g->cx[e]);
+    xmax = std::max(xmax, g->cx[e]);
+  }
+  std::vector<double> wsort(g->w);
+  std::nth_element(wsort.begin(), wsort.begin() + N / 2, wsort.end());
+  const double hmed = wsort[N / 2];
+  F->w_top = 4.0 / m.kmax;
+  F->x0 = xmin - 1e-7 * (1.0 + std::fabs(xmin)) - 0.5 * hmed;
+
+  // trees: free tree per layer (side B, or T for the bottom layer), side trees
+  std::vector<TreeB> T;
+  std::vector<int> tree_layer;
+  for (int l = 0; l <= L; ++l) {
+    TreeB t;
+    t.layer = l;
+    t.side = l < L ? SIDE_B : SIDE_T;
+    t.reac = false;
+    t.k = m.k[l];
+    T.push_back(t);
+  }
+  for (int l = 0; l <= L; ++l)
+    for (int sd = 0; sd < 2; ++sd)
+      if (side_exists(m, l, sd)) {
+        TreeB t;
+        t.layer = l;
+        t.side = sd;
+        t.reac = true;
+        t.k = m.k[l];
+        T.push_back(t);
+      }
+  for (int64_t e = 0; e < N; ++e) {
+    const int l = g->layer[e];
+    for (auto& t : T) {
+      if (t.layer != l) continue;
+      t.el.push_back((int)e);
+      t.x.push_back(g->cx[e]);
+      t.h.push_back(std::max(0.0, side_h(m, l, t.side, g->cy[e])));
+    }
+  }
+  // free leaf level: mean points per non-empty leaf <= leaf_size
+  int lf = 0;
+  for (; lf < 12; ++lf) {
+    const double w = F->w_top / (1 << lf);
+    int64_t nbox = 0, npt = 0;
+    for (auto& t : T) {
+      if (t.reac) continue;
+      std::unordered_map<int64_t, int> cnt;
+      for (size_t i = 0; i < t.el.size(); ++i)
+        cnt[bkey((int)std::floor((t.x[i] - F->x0) / w), (int)std::floor(t.h[i] / w))]++;
+      nbox += cnt.size();
+      npt += t.el.size();
+    }
+    if (nbox == 0 || (double)npt / nbox <= g->leaf_size) break;
+  }
+  int lr = (int)std::ceil(std::log2(F->w_top / hmed));
+  lr = std::max(lr, lf);
+  lr = std::min(lr, 16);
+  F->lf = lf;
+  F->lr = lr;
+  F->nlev = lr + 1;
+  const int nlev = F->nlev;
+  auto wl = [&](int l) { return F->w_top / (double)(1 << l); };
+
+  // ---- boxes ----------------------------------------------------------------
+  for (auto& t : T) {
+    t.keys.assign(nlev, {});
+    t.idx.assign(nlev, {});
+    t.leaf_lev.resize(t.el.size());
+    for (size_t i = 0; i < t.el.size(); ++i) {
+      int ll;
+      if (!t.reac) {
+        ll = lf;
+      } else {
+        ll = 0;
+        while (ll < lr && t.h[i] < wl(ll)) ++ll;
+      }
+      t.leaf_lev[i] = ll;
+      for (int l = 0; l <= ll; ++l) {
+        const int64_t kk = bkey((int)std::floor((t.x[i] - F->x0) / wl(l)), (int)std::floor(t.h[i] / wl(l)));
+        t.idx[l].emplace(kk, -1);
+      }
+    }
+    for (int l = 0; l < nlev; ++l) {
+      for (auto& kv : t.idx[l]) t.keys[l].push_back(kv.first);
+      std::sort(t.keys[l].begin(), t.keys[l].end());
+    }
+  }
+  F->level_ptr.assign(nlev + 1, 0);
+  for (int l = 0; l < nlev; ++l) {
+    F->level_ptr[l] = (int)F->boxes.size();
+    for (size_t ti = 0; ti < T.size(); ++ti) {
+      auto& t = T[ti];
+      for (int64_t kk : t.keys[l]) {
+        const int i = (int)(kk >> 32), j = (int)(uint32_t)kk;
+        BoxDev b;
+        b.cx = F->x0 + (i + 0.5) * wl(l);
+        b.ch = (j + 0.5) * wl(l);
+        b.k = t.k;
+        b.tree = (int)ti;
+        b.level = l;
+        b.parent = l > 0 ? t.idx[l - 1].at(bkey(i >> 1, j >> 1)) : -1;
+        b.pos = (i & 1) + 2 * (j & 1);
+        b.pt0 = b.npt = b.child0 = b.nchild = 0;
+        t.idx[l][kk] = (int)F->boxes.size();
+        F->boxes.push_back(b);
+      }
+    }
+  }
+  F->level_ptr[nlev] = (int)F->boxes.size();
+  F->n_boxes = (int)F->boxes.size();
+  for (auto& t : T) tree_layer.push_back(t.layer);
+  // children (CSR)
+  {
+    std::vector<std::vector<int>> ch(F->n_boxes);
+    for (int b = 0; b < F->n_boxes; ++b)
+      if (F->boxes[b].parent >= 0) ch[F->boxes[b].parent].push_back(b);
+    for (int b = 0; b < F->n_boxes; ++b) {
+      F->boxes[b].child0 = (int)F->children.size();
+      F->boxes[b].nchild = (int)ch[b].size();
+      for (int c : ch[b]) F->children.push_back(c);
+    }
+    F->parents_ptr.assign(nlev + 1, 0);
+    for (int l = 0; l < nlev; ++l) {
+      F->parents_ptr[l] = (int)F->parents_by_level.size();
+      for (int b = F->level_ptr[l]; b < F->level_ptr[l + 1]; ++b)
+        if (F->boxes[b].nchild) F->parents_by_level.push_back(b);
+    }
+    F->parents_ptr[nlev] = (int)F->parents_by_level.size();
+  }
+  // points grouped by leaf box
+  for (size_t ti = 0; ti < T.size(); ++ti) {
+    auto& t = T[ti];
+    std::vector<std::pair<int, int>> order;  // (leaf box, local point)
+    for (size_t i = 0; i < t.el.size(); ++i) {
+      const int l = t.leaf_lev[i];
+      const int64_t kk = bkey((int)std::floor((t.x[i] - F->x0) / wl(l)), (int)std::floor(t.h[i] / wl(l)));
+      order.push_back({t.idx[l].at(kk), (int)i});
+    }
+    std::sort(order.begin(), order.end());
+    for (size_t q = 0; q < order.size(); ++q) {
+      const int b = order[q].first, i = order[q].second;
+      if (F->boxes[b].npt == 0) F->boxes[b].pt0 = (int)F->pt_elem.size();
+      F->boxes[b].npt++;
+      F->pt_elem.push_back(t.el[i]);
+      F->pt_xh.push_back(t.x[i]);
+      F->pt_xh.push_back(t.h[i]);
+    }
+  }
+  for (int b = 0; b < F->n_boxes; ++b) {
+    const BoxDev& B = F->boxes[b];
+    if (!B.npt) continue;
+    const TreeB& t = T[B.tree];
+    if (!t.reac) F->leaf_free.push_back(b);
+    else if (t.side == SIDE_B) F->leaf_B.push_back(b);
+    else F->leaf_T.push_back(b);
+  }
+
+  // ---- M2M / L2L operators F_j(child - parent) ---------------------------------
+  {
+    const int J = 2 * p;
+    F->ftab.assign((size_t)(L + 1) * nlev * 4 * (2 * J + 1), zd(0.0, 0.0));
+    std::vector<zd> buf(2 * J + 1);
+    std::vector<double> jb(J + 1);
+    for (int l = 0; l <= L; ++l)
+      for (int lev = 1; lev < nlev; ++lev)
+        for (int pos = 0; pos < 4; ++pos) {
+          const double d = 0.5 * wl(lev);
+          const double dx = (pos & 1) ? 0.5 * d : -0.5 * d;
+          const double dh = (pos & 2) ? 0.5 * d : -0.5 * d;
+          // child centre - parent centre = (+-w_lev/2, +-w_lev/2)
+          fm::f_seq(m.k[l], 2.0 * dx, 2.0 * dh, J, buf.data(), jb.data());
+          std::copy(buf.begin(), buf.end(), F->ftab.begin() + ((size_t)((l * nlev + lev) * 4 + pos)) * (2 * J + 1));
+        }
+  }
+
+  // ---- interaction lists --------------------------------------------------------
+  std::map<std::tuple<int, int, int, int>, int> free_id;               // (layer, level, di, dj)
+  std::map<std::tuple<int, int, int, int, int, int>, int> reac_id;     // (tt, ts, level, di, jt, js)
+  auto free_tab = [&](int layer, int lev, int di, int dj) {
+    auto key = std::make_tuple(layer, lev, di, dj);
+    auto it = free_id.find(key);
+    if (it != free_id.end()) return it->second;
+    const int id = (int)free_id.size();
+    free_id[key] = id;
+    F->free_geo.push_back(m.k[layer]);
+    F->free_geo.push_back(di * wl(lev));
+    F->free_geo.push_back(dj * wl(lev));
+    return id;
+  };
+  auto reac_tab = [&](int tt, int ts, int lev, int di, int jt, int js) {
+    auto key = std::make_tuple(tt, ts, lev, di, jt, js);
+    auto it = reac_id.find(key);
+    if (it != reac_id.end()) return it->second;
+    const int id = (int)reac_id.size();
+    reac_id[key] = id;
+    F->reac_meta.push_back(T[tt].layer);
+    F->reac_meta.push_back(T[ts].layer);
+    F->reac_meta.push_back(T[tt].side + 2 * T[ts].side);
+    F->reac_geo.push_back(di * wl(lev));
+    F->reac_geo.push_back((jt + 0.5) * wl(lev));
+    F->reac_geo.push_back((js + 0.5) * wl(lev));
+    return id;
+  };
+  auto ij = [&](int b) {
+    const BoxDev& B = F->boxes[b];
+    const double w = wl(B.level);
+    return std::make_pair((int)std::lround((B.cx - F->x0) / w - 0.5), (int)std::lround(B.ch / w - 0.5));
+  };
+  for (int b = 0; b < F->n_boxes; ++b) {
+    const BoxDev& B = F->boxes[b];
+    const TreeB& tb = T[B.tree];
+    const int lev = B.level;
+    auto [it, jt] = ij(b);
+    std::vector<std::pair<int, int>> lst;  // (source, tab)
+    if (!tb.reac) {
+      if (lev == 0) {
+        for (int64_t kk : tb.keys[0]) {
+          const int is = (int)(kk >> 32), js = (int)(uint32_t)kk;
+          if (std::abs(is - it) <= 1 && std::abs(js - jt) <= 1) continue;
+          lst.push_back({tb.idx[0].at(kk), -1 - free_tab(tb.layer, 0, it - is, jt - js)});
+        }
+      } else {
+        auto [Ip, Jp] = ij(B.parent);
+        for (int dI = -1; dI <= 1; ++dI)
+          for (int dJ = -1; dJ <= 1; ++dJ) {
+            auto q = tb.idx[lev - 1].find(bkey(Ip + dI, Jp + dJ));
+            if (Ip + dI < 0 || Jp + dJ < 0 || q == tb.idx[lev - 1].end()) continue;
+            const BoxDev& Q = F->boxes[q->second];
+            for (int c = 0; c < Q.nchild; ++c) {
+              const int cb = F->children[Q.child0 + c];
+              auto [is, js] = ij(cb);
+              if (std::abs(is - it) <= 1 && std::abs(js - jt) <= 1) continue;
+              lst.push_back({cb, -1 - free_tab(tb.layer, lev, it - is, jt - js)});
+            }
+          }
+      }
+    } else {
+      // reaction: every source side tree
+      for (size_t ts = 0; ts < T.size(); ++ts) {
+        const TreeB& sb = T[ts];
+        if (!sb.reac) continue;
+        if (lev == 0) {
+          for (int64_t kk : sb.keys[0]) {
+            const int is = (int)(kk >> 32), js = (int)(uint32_t)kk;
+            if (std::abs(is - it) <= 1 && jt == 0 && js == 0) continue;
+            lst.push_back({sb.idx[0].at(kk), reac_tab(B.tree, (int)ts, 0, it - is, jt, js)});
+          }
+        } else {
+          auto [Ip, Jp] = ij(B.parent);
+          (void)Jp;
+          for (int dI = -1; dI <= 1; ++dI) {
+            if (Ip + dI < 0) continue;
+            auto q = sb.idx[lev - 1].find(bkey(Ip + dI, 0));
+            if (q == sb.idx[lev - 1].end()) continue;
+            const BoxDev& Q = F->boxes[q->second];
+            for (int c = 0; c < Q.nchild; ++c) {
+              const int cb = F->children[Q.child0 + c];
+              auto [is, js] = ij(cb);
+              if (std::abs(is - it) <= 1 && jt == 0 && js == 0) continue;
+              lst.push_back({cb, reac_tab(B.tree, (int)ts, lev, it - is, jt, js)});
+            }
+          }
+        }
+      }
+    }
+    if (lst.empty()) continue;
+    F->m2l_tgt.push_back(b);
+    F->m2l_ptr.push_back((int)F->m2l_src.size());
+    for (auto& e : lst) {
+      F->m2l_src.push_back(e.first);
+      F->m2l_tab.push_back(e.second);
+    }
+  }
+  F->m2l_ptr.push_back((int)F->m2l_src.size());
+
+  // free near field (leaf level lf)
+  for (int b : F->leaf_free) {
+    const BoxDev& B = F->boxes[b];
+    const TreeB& tb = T[B.tree];
+    auto [it, jt] = ij(b);
+    F->near_tgt.push_back(b);
+    F->near_ptr.push_back((int)F->near_src.size());
+    for (int di = -1; di <= 1; ++di)
+      for (int dj = -1; dj <= 1; ++dj) {
+        if (it + di < 0 || jt + dj < 0) continue;
+        auto q = tb.idx[B.level].find(bkey(it + di, jt + dj));
+        if (q != tb.idx[B.level].end()) F->near_src.push_back(q->second);
+      }
+  }
+  F->near_ptr.push_back((int)F->near_src.size());
+
+  // reaction near field: row-0 leaves at level lr adjacent in image space
+  {
+    std::unordered_map<int64_t, unsigned> pairs;
+    for (size_t tt = 0; tt < T.size(); ++tt) {
+      if (!T[tt].reac) continue;
+      for (int64_t kt : T[tt].keys[lr]) {
+        if ((uint32_t)kt != 0) continue;
+        const int it = (int)(kt >> 32);
+        const BoxDev& Bt = F->boxes[T[tt].idx[lr].at(kt)];
+        for (size_t ts = 0; ts < T.size(); ++ts) {
+          if (!T[ts].reac) continue;
+          const unsigned bit = 1u << (T[tt].side + 2 * T[ts].side);
+          for (int di = -1; di <= 1; ++di) {
+            if (it + di < 0) continue;
+            auto q = T[ts].idx[lr].find(bkey(it + di, 0));
+            if (q == T[ts].idx[lr].end()) continue;
+            const BoxDev& Bs = F->boxes[q->second];
+            for (int a = 0; a < Bt.npt; ++a)
+              for (int c = 0; c < Bs.npt; ++c) {
+                const int64_t key = ((int64_t)F->pt_elem[Bt.pt0 + a] << 32) | (uint32_t)F->pt_elem[Bs.pt0 + c];
+                pairs[key] |= bit;
+              }
+          }
+        }
+      }
+    }
+    std::vector<std::pair<int64_t, unsigned>> pv(pairs.begin(), pairs.end());
+    std::sort(pv.begin(), pv.end());
+    F->rn_ptr.assign(N + 1, 0);
+    for (auto& e : pv) {
+      F->rn_ptr[(e.first >> 32) + 1]++;
+      F->rn_src.push_back((int)(uint32_t)e.first);
+      F->rn_mask.push_back(e.second);
+    }
+    for (int64_t i = 0; i < N; ++i) F->rn_ptr[i + 1] += F->rn_ptr[i];
+  }
+
+  // ---- upload and device setup ---------------------------------------------------
+  LM_TRY(up(F->d_boxes, F->boxes, s));
+  LM_TRY(up(F->d_children, F->children, s));
+  LM_TRY(up(F->d_pt_elem, F->pt_elem, s));
+  LM_TRY(up(F->d_pt_xh, F->pt_xh, s));
+  LM_TRY(up(F->d_leaf_free, F->leaf_free, s));
+  LM_TRY(up(F->d_leaf_B, F->leaf_B, s));
+  LM_TRY(up(F->d_leaf_T, F->leaf_T, s));
+  LM_TRY(up(F->d_parents, F->parents_by_level, s));
+  LM_TRY(up(F->d_m2l_tgt, F->m2l_tgt, s));
+  LM_TRY(up(F->d_m2l_ptr, F->m2l_ptr, s));
+  LM_TRY(up(F->d_m2l_src, F->m2l_src, s));
+  LM_TRY(up(F->d_m2l_tab, F->m2l_tab, s));
+  LM_TRY(up(F->d_near_tgt, F->near_tgt, s));
+  LM_TRY(up(F->d_near_ptr, F->near_ptr, s));
+  LM_TRY(up(F->d_near_src, F->near_src, s));
+  LM_TRY(up(F->d_rn_ptr, F->rn_ptr, s));
+  LM_TRY(up(F->d_rn_src, F->rn_src, s));
+  {
+    std::vector<double2> ft(F->ftab.size());
+    for (size_t i = 0; i < ft.size(); ++i) ft[i] = make_double2(F->ftab[i].re, F->ftab[i].im);
+    LM_TRY(up(F->d_ftab, ft, s));
+    F->tree_layer = tree_layer;
+    LM_TRY(up(F->d_tree_layer, F->tree_layer, s));
+  }
+  {
+    std::vector<double2> self(N);
+    for (int64_t e = 0; e < N; ++e) {
+      const double k = m.k[g->layer[e]], w = g->w[e];
+      self[e] = make_double2(-(kEulerGamma + std::log(k * w / 4.0) - 1.0) / (2.0 * M_PI) * w, 0.25 * w);
+    }
+    LM_TRY(up(F->d_self, self, s));
+  }
+  // free-space Hankel tables
+  const int nfree = (int)free_id.size(), nreac = (int)reac_id.size();
+  LM_TRY(F->d_free_tab.alloc((size_t)std::max(nfree, 1) * (4 * p + 1) * sizeof(double2)));
+  if (nfree) {
+    DevBuf geo;
+    LM_TRY(up(geo, F->free_geo, s));
+    hipLaunchKernelGGL(k_free_tables, dim3(div_up(nfree, 64)), dim3(64), 0, s, nfree, p, geo.as<double>(),
+                       F->d_free_tab.as<double2>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  // reaction tables
+  LM_TRY(F->d_reac_tab.alloc((size_t)std::max(nreac, 1) * F->P * F->P * sizeof(double2)));
+  if (nreac) {
+    DevBuf meta, geo;
+    LM_TRY(up(meta, F->reac_meta, s));
+    LM_TRY(up(geo, F->reac_geo, s));
+    hipLaunchKernelGGL(k_reac_tables, dim3(nreac), dim3(256), 0, s, m, p, meta.as<int>(), geo.as<double>(),
+                       F->d_reac_tab.as<double2>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  // reaction near-field entries
+  const int nrn = (int)F->rn_src.size();
+  LM_TRY(F->d_rn_val.alloc((size_t)std::max(nrn, 1) * sizeof(double2)));
+  if (nrn) {
+    std::vector<int> tgt(nrn);
+    for (int64_t i = 0; i < N; ++i)
+      for (int e = F->rn_ptr[i]; e < F->rn_ptr[i + 1]; ++e) tgt[e] = (int)i;
+    DevBuf dt, dm;
+    LM_TRY(up(dt, tgt, s));
+    LM_TRY(up(dm, F->rn_mask, s));
+    hipLaunchKernelGGL(k_reac_near, dim3(div_up(nrn, 64)), dim3(64), 0, s, m, nrn, dt.as<int>(), F->d_rn_src.as<int>(),
+                       dm.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(),
+                       g->d_layer.as<int>(), F->d_rn_val.as<double2>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  LM_TRY(F->d_me.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
+  LM_TRY(F->d_le.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
+  F->stats[0] = F->n_boxes;
+  F->stats[1] = (int64_t)F->m2l_src.size();
+  F->stats[2] = nfree;
+  F->stats[3] = nreac;
+  F->stats[4] = nrn;
+  F->stats[5] = F->lf;
+  F->stats[6] = F->lr;
+  F->stats[7] = (int64_t)F->near_src.size();
+  return LM_OK;
+}
+
+lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s) {
+  FmmPlan* F = g->fmm;
+  LM_CHECK(F, LM_EINTERNAL, "no FMM plan");
+  LM_CHECK(precision == LM_FP64, LM_EINVAL, "the FMM matvec supports LM_FP64 only in this build");
+  const int N = (int)g->N, p = F->p, P = F->P;
+  const BoxDev* boxes = F->d_boxes.as<BoxDev>();
+  const int* tl = F->d_tree_layer.as<int>();
+  for (int r = 0; r < n_rhs; ++r) {
+    const double2* x = (const double2*)xv + (int64_t)r * N;
+    double2* y = (double2*)yv + (int64_t)r * N;
+    double2* me = F->d_me.as<double2>();
+    double2* le = F->d_le.as<double2>();
+    // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
+    const std::vector<int>* leaves[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
+    const DevBuf* dleaves[3] = {&F->d_leaf_free, &F->d_leaf_B, &F->d_leaf_T};
+    for (int c = 0; c < 3; ++c)
+      if (!leaves[c]->empty())
+        hipLaunchKernelGGL(k_p2m, dim3(leaves[c]->size()), dim3(WG), 0, s, p, dleaves[c]->as<int>(), boxes,
+                           F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, me);
+    // M2M, finest parents first
+    for (int l = F->nlev - 2; l >= 0; --l) {
+      const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
+      if (n)
+        hipLaunchKernelGGL(k_m2m, dim3(n), dim3(WG), 0, s, p, F->nlev, F->d_parents.as<int>() + F->parents_ptr[l],
+                           boxes, F->d_children.as<int>(), tl, F->d_ftab.as<double2>(), me);
+    }
+    // M2L (every level at once); boxes without a list start from zero
+    LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * P * sizeof(double2), s));
+    if (!F->m2l_tgt.empty())
+      hipLaunchKernelGGL(k_m2l, dim3(F->m2l_tgt.size()), dim3(WG), 0, s, p, F->d_m2l_tgt.as<int>(),
+                         F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_tab.as<int>(),
+                         F->d_free_tab.as<double2>(), F->d_reac_tab.as<double2>(), me, le);
+    // L2L, coarse to fine
+    for (int l = 1; l < F->nlev; ++l) {
+      const int n = F->level_ptr[l + 1] - F->level_ptr[l];
+      if (n)
+        hipLaunchKernelGGL(k_l2l, dim3(n), dim3(WG), 0, s, p, F->nlev, F->level_ptr[l], boxes, tl,
+                           F->d_ftab.as<double2>(), le);
+    }
+    // L2P: free trees write, side trees accumulate (each element once per launch)
+    for (int c = 0; c < 3; ++c)
+      if (!leaves[c]->empty())
+        hipLaunchKernelGGL(k_l2p, dim3(leaves[c]->size()), dim3(WG), 0, s, p, c > 0 ? 1 : 0, dleaves[c]->as<int>(),
+                           boxes, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, y);
+    // near fields and self terms
+    if (!F->near_tgt.empty())
+      hipLaunchKernelGGL(k_p2p, dim3(F->near_tgt.size()), dim3(128), 0, s, F->d_near_tgt.as<int>(),
+                         F->d_near_ptr.as<int>(), F->d_near_src.as<int>(), boxes, F->d_pt_elem.as<int>(),
+                         F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, y);
+    hipLaunchKernelGGL(k_near_self, dim3(div_up(N, 256)), dim3(256), 0, s, N, F->d_rn_ptr.as<int>(),
+                       F->d_rn_src.as<int>(), F->d_rn_val.as<double2>(), F->d_self.as<double2>(), x, y);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  return LM_OK;
 }

@@ -46,13 +46,14 @@ struct PairSides {
   double Dmin;
 };
 
-LM_HD PairSides pair_sides(const MediumDev& m, int lt, int ls, double yt, double ys) {
+LM_HD PairSides pair_sides(const MediumDev& m, int lt, int ls, double yt, double ys, unsigned want) {
   PairSides p;
   p.mask = 0;
   p.Dmin = 1e300;
   for (int c = 0; c < 4; ++c) {
     int t = c & 1, s = c >> 1;
     p.ht[c] = p.hs[c] = 0.0;
+    if (!((want >> c) & 1u)) continue;
     if (!side_exists(m, lt, t) || !side_exists(m, ls, s)) continue;
     p.mask |= 1u << c;
     p.ht[c] = fmax(side_h(m, lt, t, yt), 0.0);
@@ -77,9 +78,11 @@ LM_HD zd integrand(const MediumDev& m, int lt, int ls, const PairSides& p, zd la
 }
 
 // G^r(r | r') for target (layer lt, height yt), source (layer ls, height ys)
-// at horizontal distance X = |x - x'|.
-LM_HD zd reaction_direct(const MediumDev& m, int lt, int ls, double X, double yt, double ys) {
-  PairSides p = pair_sides(m, lt, ls, yt, ys);
+// at horizontal distance X = |x - x'|, summed over the components in `want`
+// (bit c = target side + 2 * source side; default all).
+LM_HD zd reaction_direct(const MediumDev& m, int lt, int ls, double X, double yt, double ys,
+                         unsigned want = 0xFu) {
+  PairSides p = pair_sides(m, lt, ls, yt, ys, want);
   if (!p.mask) return zd(0.0, 0.0);
   const double T = m.kmax + 1.5;
   const double Xs = fmax(X, 1e-300);

@@ -52,6 +52,7 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int)], _ip),
     "lm_geometry_elements": ([_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)], _ip),
     "lm_destroy_geometry": ([_vp], _ip),
+    "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
     "lm_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
     "lm_gmres_solve": ([_vp, _ip, _ip, _dp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp], _ip),
@@ -153,6 +154,15 @@ class Geometry:
         _check(lib().lm_geometry_elements(self.h, _dptr(cx), _dptr(cy), _dptr(ww),
                                           lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return cx, cy, ww, lay
+
+    def fmm_stats(self):
+        """boxes, M2L entries, free classes, reaction tables, reaction near pairs,
+        free leaf level, reaction finest level, free near leaf pairs."""
+        out = (ctypes.c_int64 * 8)()
+        _check(lib().lm_fmm_stats(self.h, out))
+        keys = ("boxes", "m2l_entries", "free_classes", "reaction_tables", "reaction_near_pairs",
+                "free_leaf_level", "reaction_finest_level", "free_near_leaf_pairs")
+        return dict(zip(keys, list(out)))
 
     def close(self):
         if self.h:
