@@ -109,11 +109,12 @@ lm_status lm_geometry_info(lm_geom geom, int64_t* n_elements, int64_t* device_by
  * cx, cy, w: double[N]; layer: int32[N]. */
 lm_status lm_geometry_elements(lm_geom geom, double* cx, double* cy, double* w, int32_t* layer);
 lm_status lm_destroy_geometry(lm_geom geom);
-/* Size of the fast-method plan (all zero for LM_DENSE), host output of 8
- * int64: boxes, M2L list entries, free-space M2L classes, reaction M2L
- * operators (Sommerfeld tables), reaction near-field pairs, free-space leaf
- * level, reaction finest level, free-space near-field leaf pairs. */
-lm_status lm_fmm_stats(lm_geom geom, int64_t* out8);
+/* Size of the fast-method plan (all zero for LM_DENSE), host output of 10
+ * int64: boxes, free-space M2L entries, reaction M2L entries, free-space M2L
+ * classes, reaction M2L operators (Sommerfeld tables), reaction near-field
+ * element pairs, free-space leaf level, reaction finest level, free-space
+ * near-field leaf pairs, free-space near-field element pairs. */
+lm_status lm_fmm_stats(lm_geom geom, int64_t* out10);
 
 /* ---------------------------------------------------------------- matvec --
  * y = K x for n_rhs vectors (eq. Llayerscomponent, unscaled form):
@@ -125,6 +126,15 @@ lm_status lm_fmm_stats(lm_geom geom, int64_t* out8);
  * x and y must not overlap. */
 lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev,
                     void* hip_stream);
+
+/* Runs reps FMM matvecs (as lm_matvec) and returns in out8_host the average
+ * duration in ms of each stage, measured with HIP events recorded on
+ * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L (all
+ * levels, free-space and reaction), [3] L2L, [4] L2P, [5] free-space near
+ * field, [6] reaction near field + self terms, [7] whole matvec.  Synchronises
+ * the stream.  LM_EINVAL for a dense geometry. */
+lm_status lm_matvec_stage_times(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, int reps,
+                                void* hip_stream, double* out8_host);
 
 /* ------------------------------------------------------------------- rhs --
  * g = -u^inc - u^b on Gamma_0 and -u^b elsewhere (eq. homogeneousscattering)

@@ -171,9 +171,9 @@ extern "C" lm_status lm_geometry_elements(lm_geom g, double* cx, double* cy, dou
   return LM_OK;
 }
 
-extern "C" lm_status lm_fmm_stats(lm_geom g, int64_t* out8) {
-  LM_CHECK(g && out8, LM_EINVAL, "bad arguments");
-  fmm_stats(g->fmm, out8);
+extern "C" lm_status lm_fmm_stats(lm_geom g, int64_t* out10) {
+  LM_CHECK(g && out10, LM_EINVAL, "bad arguments");
+  fmm_stats(g->fmm, out10);
   return LM_OK;
 }
 
@@ -199,6 +199,15 @@ extern "C" lm_status lm_matvec(lm_geom g, int precision, int n_rhs, const void* 
   LM_CHECK(n_rhs >= 1, LM_EINVAL, "n_rhs must be >= 1");
   LM_CHECK(x && y && x != y, LM_EINVAL, "x and y must be distinct device pointers");
   return geom_matvec(g, precision, n_rhs, x, y, (hipStream_t)hip_stream);
+}
+
+extern "C" lm_status lm_matvec_stage_times(lm_geom g, int precision, int n_rhs, const void* x, void* y, int reps,
+                                           void* hip_stream, double* out8) {
+  LM_CHECK(g && out8 && reps >= 1, LM_EINVAL, "bad arguments");
+  LM_TRY(check_prec(precision));
+  LM_CHECK(n_rhs >= 1 && x && y && x != y, LM_EINVAL, "x and y must be distinct device pointers");
+  LM_CHECK(g->method == LM_FMM, LM_EINVAL, "stage timing is defined for the FMM method");
+  return fmm_stage_times(g, precision, n_rhs, x, y, reps, (hipStream_t)hip_stream, out8);
 }
 
 extern "C" lm_status lm_rhs(lm_geom g, int n_rhs, const double* theta, void* g_dev, void* hip_stream) {

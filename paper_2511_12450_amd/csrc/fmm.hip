@@ -34,73 +34,18 @@
 #include "lm_internal.hpp"
 #include "m2l_table.hpp"
 
+#include "fmm_plan.hpp"
+
 namespace {
-
 constexpr int WG = 64;
-constexpr int MAXP = 31;  // 2p+1 <= 63 fits one 64-lane wavefront
 constexpr int MAXPP = 2 * MAXP + 1;
-
-struct BoxDev {
-  double cx, ch, k;
-  int tree, level, parent, pos;
-  int pt0, npt, child0, nchild;
-};
-
 inline int64_t bkey(int i, int j) { return ((int64_t)i << 32) | (uint32_t)j; }
-
 }  // namespace
-
-struct FmmPlan {
-  int p = 20, P = 41;
-  int nlev = 0, lf = 0, lr = 0;
-  double w_top = 0, x0 = 0;
-  int n_boxes = 0;
-  std::vector<BoxDev> boxes;
-  std::vector<int> level_ptr;     // boxes of level l: ids [level_ptr[l], level_ptr[l+1])
-  std::vector<int> leaf_free, leaf_B, leaf_T;  // leaf boxes by tree class
-  std::vector<int> parents_by_level;           // boxes with children, grouped by level
-  std::vector<int> parents_ptr;
-  std::vector<int> children;
-  std::vector<int> pt_elem;
-  std::vector<double> pt_xh;      // (x, h) per point
-  // M2L lists
-  std::vector<int> m2l_tgt, m2l_ptr, m2l_src, m2l_tab;  // tab >= 0 reaction table, < 0: free table -(id+1)
-  std::vector<double> free_geo;   // (k, dx, dh) per free table
-  std::vector<int> reac_meta;     // (lt, ls, comp) per reaction table
-  std::vector<double> reac_geo;   // (dx, ht, hs)
-  // free near field
-  std::vector<int> near_tgt, near_ptr, near_src;
-  // reaction near field (CSR by element)
-  std::vector<int> rn_ptr, rn_src;
-  std::vector<unsigned> rn_mask;
-  // M2M / L2L operators F_j(d), d = child centre - parent centre; [layer][level][pos][4p+1]
-  std::vector<zd> ftab;
-  std::vector<int> tree_layer;
-  int n_layers = 0;
-  int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  DevBuf d_boxes, d_children, d_pt_elem, d_pt_xh;
-  DevBuf d_leaf_free, d_leaf_B, d_leaf_T, d_parents;
-  DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
-  DevBuf d_free_tab, d_reac_tab, d_ftab;
-  DevBuf d_near_tgt, d_near_ptr, d_near_src;
-  DevBuf d_rn_ptr, d_rn_src, d_rn_val;
-  DevBuf d_self, d_me, d_le, d_tree_layer;
-  int64_t bytes() const {
-    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
-                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_free_tab, &d_reac_tab,
-                           &d_ftab, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
-                           &d_self, &d_me, &d_le, &d_tree_layer};
-    int64_t b = 0;
-    for (auto* d : all) b += d->bytes;
-    return b;
-  }
-};
 
 void fmm_free(FmmPlan* f) { delete f; }
 int64_t fmm_bytes(const FmmPlan* f) { return f ? f->bytes() : 0; }
 void fmm_stats(const FmmPlan* f, int64_t* out) {
-  for (int i = 0; i < 8; ++i) out[i] = f ? f->stats[i] : 0;
+  for (int i = 0; i < 10; ++i) out[i] = f ? f->stats[i] : 0;
 }
 
 // =========================================================== setup kernels ==
@@ -917,18 +862,35 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   }
   LM_TRY(F->d_me.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
   LM_TRY(F->d_le.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
+  int64_t nf = 0, nr = 0, npp = 0;
+  for (int t : F->m2l_tab) (t < 0 ? nf : nr)++;
+  for (size_t t = 0; t < F->near_tgt.size(); ++t)
+    for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e)
+      npp += (int64_t)F->boxes[F->near_tgt[t]].npt * F->boxes[F->near_src[e]].npt;
   F->stats[0] = F->n_boxes;
-  F->stats[1] = (int64_t)F->m2l_src.size();
-  F->stats[2] = nfree;
-  F->stats[3] = nreac;
-  F->stats[4] = nrn;
-  F->stats[5] = F->lf;
-  F->stats[6] = F->lr;
-  F->stats[7] = (int64_t)F->near_src.size();
+  F->stats[1] = nf;
+  F->stats[2] = nr;
+  F->stats[3] = nfree;
+  F->stats[4] = nreac;
+  F->stats[5] = nrn;
+  F->stats[6] = F->lf;
+  F->stats[7] = F->lr;
+  F->stats[8] = (int64_t)F->near_src.size();
+  F->stats[9] = npp;
   return LM_OK;
 }
 
+// Stage timing: when ev != nullptr, ev[2*i], ev[2*i+1] bracket stage i on
+// stream s (0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near P2P, 6 reaction near + self).
+lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
+                           hipEvent_t* ev);
+
 lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s) {
+  return fmm_matvec_timed(g, precision, n_rhs, xv, yv, s, nullptr);
+}
+
+lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
+                           hipEvent_t* ev) {
   FmmPlan* F = g->fmm;
   LM_CHECK(F, LM_EINTERNAL, "no FMM plan");
   LM_CHECK(precision == LM_FP64, LM_EINVAL, "the FMM matvec supports LM_FP64 only in this build");
@@ -940,6 +902,9 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, voi
     double2* y = (double2*)yv + (int64_t)r * N;
     double2* me = F->d_me.as<double2>();
     double2* le = F->d_le.as<double2>();
+#define LM_STAGE(i, open)                                             \
+  if (ev && r == 0) LM_TRY_HIP(hipEventRecord(ev[2 * (i) + ((open) ? 0 : 1)], s))
+    LM_STAGE(0, 1);
     // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
     const std::vector<int>* leaves[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
     const DevBuf* dleaves[3] = {&F->d_leaf_free, &F->d_leaf_B, &F->d_leaf_T};
@@ -947,6 +912,8 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, voi
       if (!leaves[c]->empty())
         hipLaunchKernelGGL(k_p2m, dim3(leaves[c]->size()), dim3(WG), 0, s, p, dleaves[c]->as<int>(), boxes,
                            F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, me);
+    LM_STAGE(0, 0);
+    LM_STAGE(1, 1);
     // M2M, finest parents first
     for (int l = F->nlev - 2; l >= 0; --l) {
       const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
@@ -954,12 +921,16 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, voi
         hipLaunchKernelGGL(k_m2m, dim3(n), dim3(WG), 0, s, p, F->nlev, F->d_parents.as<int>() + F->parents_ptr[l],
                            boxes, F->d_children.as<int>(), tl, F->d_ftab.as<double2>(), me);
     }
+    LM_STAGE(1, 0);
     // M2L (every level at once); boxes without a list start from zero
     LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * P * sizeof(double2), s));
+    LM_STAGE(2, 1);
     if (!F->m2l_tgt.empty())
       hipLaunchKernelGGL(k_m2l, dim3(F->m2l_tgt.size()), dim3(WG), 0, s, p, F->d_m2l_tgt.as<int>(),
                          F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_tab.as<int>(),
                          F->d_free_tab.as<double2>(), F->d_reac_tab.as<double2>(), me, le);
+    LM_STAGE(2, 0);
+    LM_STAGE(3, 1);
     // L2L, coarse to fine
     for (int l = 1; l < F->nlev; ++l) {
       const int n = F->level_ptr[l + 1] - F->level_ptr[l];
@@ -967,19 +938,53 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, voi
         hipLaunchKernelGGL(k_l2l, dim3(n), dim3(WG), 0, s, p, F->nlev, F->level_ptr[l], boxes, tl,
                            F->d_ftab.as<double2>(), le);
     }
+    LM_STAGE(3, 0);
+    LM_STAGE(4, 1);
     // L2P: free trees write, side trees accumulate (each element once per launch)
     for (int c = 0; c < 3; ++c)
       if (!leaves[c]->empty())
         hipLaunchKernelGGL(k_l2p, dim3(leaves[c]->size()), dim3(WG), 0, s, p, c > 0 ? 1 : 0, dleaves[c]->as<int>(),
                            boxes, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, y);
+    LM_STAGE(4, 0);
+    LM_STAGE(5, 1);
     // near fields and self terms
     if (!F->near_tgt.empty())
       hipLaunchKernelGGL(k_p2p, dim3(F->near_tgt.size()), dim3(128), 0, s, F->d_near_tgt.as<int>(),
                          F->d_near_ptr.as<int>(), F->d_near_src.as<int>(), boxes, F->d_pt_elem.as<int>(),
                          F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, y);
+    LM_STAGE(5, 0);
+    LM_STAGE(6, 1);
     hipLaunchKernelGGL(k_near_self, dim3(div_up(N, 256)), dim3(256), 0, s, N, F->d_rn_ptr.as<int>(),
                        F->d_rn_src.as<int>(), F->d_rn_val.as<double2>(), F->d_self.as<double2>(), x, y);
+    LM_STAGE(6, 0);
+#undef LM_STAGE
     LM_TRY_HIP(hipGetLastError());
   }
   return LM_OK;
+}
+
+// Average per-stage durations (ms) over reps matvecs, measured with HIP events
+// on the stream the kernels run on; out[7] = whole matvec.
+lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, int reps, hipStream_t s,
+                          double* out) {
+  hipEvent_t ev[16];
+  for (int i = 0; i < 16; ++i) LM_TRY_HIP(hipEventCreate(&ev[i]));
+  for (int i = 0; i < 8; ++i) out[i] = 0.0;
+  lm_status st = LM_OK;
+  for (int r = 0; r < reps && st == LM_OK; ++r) {
+    LM_TRY_HIP(hipEventRecord(ev[14], s));
+    st = fmm_matvec_timed(g, precision, n_rhs, x, y, s, ev);
+    LM_TRY_HIP(hipEventRecord(ev[15], s));
+    LM_TRY_HIP(hipEventSynchronize(ev[15]));
+    for (int i = 0; i < 7; ++i) {
+      float ms = 0;
+      LM_TRY_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      out[i] += ms / reps;
+    }
+    float ms = 0;
+    LM_TRY_HIP(hipEventElapsedTime(&ms, ev[14], ev[15]));
+    out[7] += ms / reps;
+  }
+  for (int i = 0; i < 16; ++i) (void)hipEventDestroy(ev[i]);
+  return st;
 }

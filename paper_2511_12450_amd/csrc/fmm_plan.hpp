@@ -1,0 +1,61 @@
+// FMM plan shared by the matvec and the preconditioner.
+#pragma once
+#include <vector>
+
+#include "lm_internal.hpp"
+
+constexpr int MAXP = 31;  // 2p+1 <= 63 fits one 64-lane wavefront
+
+struct BoxDev {
+  double cx, ch, k;
+  int tree, level, parent, pos;
+  int pt0, npt, child0, nchild;
+};
+
+struct FmmPlan {
+  int p = 20, P = 41;
+  int nlev = 0, lf = 0, lr = 0;
+  double w_top = 0, x0 = 0;
+  int n_boxes = 0;
+  std::vector<BoxDev> boxes;
+  std::vector<int> level_ptr;     // boxes of level l: ids [level_ptr[l], level_ptr[l+1])
+  std::vector<int> leaf_free, leaf_B, leaf_T;  // leaf boxes by tree class
+  std::vector<int> parents_by_level;           // boxes with children, grouped by level
+  std::vector<int> parents_ptr;
+  std::vector<int> children;
+  std::vector<int> pt_elem;
+  std::vector<double> pt_xh;      // (x, h) per point
+  // M2L lists
+  std::vector<int> m2l_tgt, m2l_ptr, m2l_src, m2l_tab;  // tab >= 0 reaction table, < 0: free table -(id+1)
+  std::vector<double> free_geo;   // (k, dx, dh) per free table
+  std::vector<int> reac_meta;     // (lt, ls, comp) per reaction table
+  std::vector<double> reac_geo;   // (dx, ht, hs)
+  // free near field
+  std::vector<int> near_tgt, near_ptr, near_src;
+  // reaction near field (CSR by element)
+  std::vector<int> rn_ptr, rn_src;
+  std::vector<unsigned> rn_mask;
+  // M2M / L2L operators F_j(d), d = child centre - parent centre; [layer][level][pos][4p+1]
+  std::vector<zd> ftab;
+  std::vector<int> tree_layer;
+  int n_layers = 0;
+  int64_t stats[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+  DevBuf d_boxes, d_children, d_pt_elem, d_pt_xh;
+  DevBuf d_leaf_free, d_leaf_B, d_leaf_T, d_parents;
+  DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
+  DevBuf d_free_tab, d_reac_tab, d_ftab;
+  DevBuf d_near_tgt, d_near_ptr, d_near_src;
+  DevBuf d_rn_ptr, d_rn_src, d_rn_val;
+  DevBuf d_self, d_me, d_le, d_tree_layer;
+  int64_t bytes() const {
+    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
+                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_free_tab, &d_reac_tab,
+                           &d_ftab, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
+                           &d_self, &d_me, &d_le, &d_tree_layer};
+    int64_t b = 0;
+    for (auto* d : all) b += d->bytes;
+    return b;
+  }
+};
+

@@ -114,6 +114,8 @@ void fmm_free(FmmPlan* f);
 int64_t fmm_bytes(const FmmPlan* f);
 void fmm_stats(const FmmPlan* f, int64_t* out);
 lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, int reps, hipStream_t s,
+                          double* out);
 
 lm_status precond_build(lm_geom_s* g, hipStream_t s);
 void precond_free(Precond* p);

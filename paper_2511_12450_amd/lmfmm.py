@@ -54,6 +54,7 @@ _SIGS = {
     "lm_destroy_geometry": ([_vp], _ip),
     "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
+    "lm_matvec_stage_times": ([_vp, _ip, _ip, _vp, _vp, _ip, _vp, _dp], _ip),
     "lm_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
     "lm_gmres_solve": ([_vp, _ip, _ip, _dp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp], _ip),
     "lm_gmres_solve_rhs": ([_vp, _ip, _ip, _vp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp],
@@ -156,12 +157,12 @@ class Geometry:
         return cx, cy, ww, lay
 
     def fmm_stats(self):
-        """boxes, M2L entries, free classes, reaction tables, reaction near pairs,
-        free leaf level, reaction finest level, free near leaf pairs."""
-        out = (ctypes.c_int64 * 8)()
+        """Plan sizes of the fast method (see lm_fmm_stats)."""
+        out = (ctypes.c_int64 * 10)()
         _check(lib().lm_fmm_stats(self.h, out))
-        keys = ("boxes", "m2l_entries", "free_classes", "reaction_tables", "reaction_near_pairs",
-                "free_leaf_level", "reaction_finest_level", "free_near_leaf_pairs")
+        keys = ("boxes", "m2l_free_entries", "m2l_reaction_entries", "free_classes", "reaction_tables",
+                "reaction_near_pairs", "free_leaf_level", "reaction_finest_level", "free_near_leaf_pairs",
+                "free_near_pairs")
         return dict(zip(keys, list(out)))
 
     def close(self):
@@ -185,6 +186,14 @@ class Geometry:
             y = torch.empty_like(x)
         _check(lib().lm_matvec(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
         return y
+
+    def stage_times(self, x, y, reps=10, precision=LM_FP64):
+        """Average ms per FMM stage (P2M, M2M, M2L, L2L, L2P, near P2P,
+        reaction near + self, total) from HIP events inside the library."""
+        out = np.zeros(8)
+        _check(lib().lm_matvec_stage_times(self.h, precision, x.shape[0], _tptr(x), _tptr(y), reps, _stream(),
+                                           _dptr(out)))
+        return out
 
     def rhs(self, theta_rad):
         import torch
