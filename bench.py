@@ -27,9 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VALU_TFLOPS = 78.6
-STAGES = ("P2M", "M2M", "M2L", "L2L", "L2P", "near_P2P", "near_reaction_self")
-KERNEL_OF_STAGE = {"P2M": "k_p2m", "M2M": "k_m2m", "M2L": "k_m2l", "L2L": "k_l2l", "L2P": "k_l2p",
-                   "near_P2P": "k_p2p", "near_reaction_self": "k_near_self"}
+STAGES = ("P2M", "M2M", "M2L", "L2L", "L2P", "near", "unused")
+KERNEL_OF_STAGE = {"P2M": "k_p2m", "M2M": "k_m2m", "M2L": "k_m2l_apply+k_m2l_reduce", "L2L": "k_l2l",
+                   "L2P": "k_l2p", "near": "k_near_csr"}
 
 
 def _args():
@@ -151,9 +151,10 @@ def main():
             flops = 8.0 * P * P * n_e
             bytes_ = (16.0 * P * P * stats["reaction_tables"] + 16.0 * (4 * w.p + 1) * stats["free_classes"]
                       + 16.0 * P * n_e + 16.0 * P * stats["boxes"])
-        elif dom == "near_P2P":
-            flops = 8.0 * stats["free_near_pairs"]  # complex MAC per pair (H0 evaluation not counted)
-            bytes_ = 16.0 * 2 * N
+        elif dom == "near":
+            nnz = stats["free_near_pairs"] - N + stats["reaction_near_pairs"] + N
+            flops = 8.0 * nnz
+            bytes_ = 20.0 * nnz + 16.0 * 3 * N + 4.0 * N  # value + column index, x gather, y read/write, row ptr
         else:
             flops, bytes_ = float("nan"), float("nan")
         intensity = flops / bytes_

@@ -130,18 +130,6 @@ __global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, const i
   }
 }
 
-// Reaction near-field entries |Gamma_s| G^mask(c_t | c_s) by direct quadrature.
-__global__ void k_reac_near(MediumDev m, int n, const int* __restrict__ tgt, const int* __restrict__ src,
-                            const unsigned* __restrict__ mask, const double* __restrict__ cx,
-                            const double* __restrict__ cy, const double* __restrict__ w, const int* __restrict__ lay,
-                            double2* __restrict__ val) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int i = tgt[t], e = src[t];
-  const zd v = lmq::reaction_direct(m, lay[i], lay[e], fabs(cx[i] - cx[e]), cy[i], cy[e], mask[t]) * w[e];
-  val[t] = make_double2(v.re, v.im);
-}
-
 // ========================================================== matvec kernels ==
 
 // P2M: a_n = sum_s q_s J_n(k rho_s) e^{-i n theta_s}, q_s = |Gamma_s| x_s.
@@ -231,54 +219,6 @@ __global__ void __launch_bounds__(WG) k_m2m(int p, int nlev, const int* __restri
   if (threadIdx.x < (unsigned)P) me[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
 }
 
-// M2L for every target box with a list (all levels): b_m = sum over list.
-//   free entry  (tab < 0): b_m += (i/4) sum_n G_{n-m}(c_t - c_s) a_n
-//   reaction    (tab >= 0): b_m += sum_n Ttilde[n][m] a_n
-__global__ void __launch_bounds__(WG) k_m2l(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
-                                            const int* __restrict__ src, const int* __restrict__ tab,
-                                            const double2* __restrict__ free_tab,
-                                            const double2* __restrict__ reac_tab, const double2* __restrict__ me,
-                                            double2* __restrict__ le) {
-  const int b = tgts[blockIdx.x];
-  const int P = 2 * p + 1;
-  __shared__ double2 a[MAXPP];
-  __shared__ double2 g[4 * MAXP + 1];
-  const int mrow = (int)threadIdx.x;  // m + p
-  zd acc(0.0, 0.0);
-  for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
-    const int s = src[e], t = tab[e];
-    if (threadIdx.x < (unsigned)P) a[threadIdx.x] = me[(int64_t)s * P + threadIdx.x];
-    if (t < 0) {
-      const double2* gr = free_tab + (int64_t)(-t - 1) * (4 * p + 1);
-      for (int j = threadIdx.x; j <= 4 * p; j += WG) g[j] = gr[j];
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)P) {
-      if (t < 0) {
-        zd s2(0.0, 0.0);
-        for (int nn = 0; nn < P; ++nn) {
-          const double2 gv = g[nn - mrow + 2 * p];
-          const double2 av = a[nn];
-          s2.re += gv.x * av.x - gv.y * av.y;
-          s2.im += gv.x * av.y + gv.y * av.x;
-        }
-        acc.re -= 0.25 * s2.im;  // (i/4) * s2
-        acc.im += 0.25 * s2.re;
-      } else {
-        const double2* T = reac_tab + (int64_t)t * P * P + mrow;
-        for (int nn = 0; nn < P; ++nn) {
-          const double2 tv = T[(int64_t)nn * P];
-          const double2 av = a[nn];
-          acc.re += tv.x * av.x - tv.y * av.y;
-          acc.im += tv.x * av.y + tv.y * av.x;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)P) le[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
-}
-
 // L2L: b^c_n += sum_m F_{m-n}(c - C) b^C_m, for every box of one level with a parent.
 __global__ void __launch_bounds__(WG) k_l2l(int p, int nlev, int first, const BoxDev* __restrict__ boxes,
                                             const int* __restrict__ tree_layer, const double2* __restrict__ ftab,
@@ -344,81 +284,133 @@ __global__ void __launch_bounds__(WG) k_l2p(int p, int accumulate, const int* __
   }
 }
 
-// Free-space near field: y_t += sum_{s in neighbour leaves, s != t} (i/4) H0(k|z_t - z_s|) |Gamma_s| x_s.
-__global__ void __launch_bounds__(128) k_p2p(const int* __restrict__ tgts, const int* __restrict__ ptr,
-                                             const int* __restrict__ srcs, const BoxDev* __restrict__ boxes,
-                                             const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
-                                             const double* __restrict__ w, const double2* __restrict__ x,
-                                             double2* __restrict__ y) {
-  const int b = tgts[blockIdx.x];
-  const BoxDev B = boxes[b];
-  const double k = B.k;
-  __shared__ double sx[128], sh[128], qre[128], qim[128];
-  __shared__ int se[128];
-  for (int t0 = 0; t0 < B.npt; t0 += 128) {
-    const int t = t0 + threadIdx.x;
-    const bool act = t < B.npt;
-    double tx = 0, th = 0;
-    int te = -1;
-    if (act) {
-      const double2 xh = pt_xh[B.pt0 + t];
-      tx = xh.x;
-      th = xh.y;
-      te = pt_elem[B.pt0 + t];
-    }
-    zd acc(0.0, 0.0);
-    for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
-      const BoxDev S = boxes[srcs[e]];
-      for (int s0 = 0; s0 < S.npt; s0 += 128) {
-        const int s = s0 + threadIdx.x;
-        __syncthreads();
-        if (s < S.npt) {
-          const double2 xh = pt_xh[S.pt0 + s];
-          const int el = pt_elem[S.pt0 + s];
-          sx[threadIdx.x] = xh.x;
-          sh[threadIdx.x] = xh.y;
-          se[threadIdx.x] = el;
-          const double2 xv = x[el];
-          qre[threadIdx.x] = w[el] * xv.x;
-          qim[threadIdx.x] = w[el] * xv.y;
-        }
-        __syncthreads();
-        if (act) {
-          const int cnt = min(128, S.npt - s0);
-          for (int j = 0; j < cnt; ++j) {
-            if (se[j] == te) continue;
-            const double r = hypot(tx - sx[j], th - sh[j]);
-            const double jr = j0(k * r), yr = y0(k * r);
-            // (i/4)(J0 + i Y0) q
-            const double gre = -0.25 * yr, gim = 0.25 * jr;
-            acc.re += gre * qre[j] - gim * qim[j];
-            acc.im += gre * qim[j] + gim * qre[j];
-          }
-        }
-      }
-    }
-    if (act) {
-      const double2 o = y[te];
-      y[te] = make_double2(o.x + acc.re, o.y + acc.im);
-    }
+// Near-field matrix values: kind 0 free-space pair, 1 reaction pair (mask),
+// 2 self term.
+__global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tgt, const int* __restrict__ src,
+                              const unsigned* __restrict__ kind, const double* __restrict__ cx,
+                              const double* __restrict__ cy, const double* __restrict__ w,
+                              const int* __restrict__ lay, const double2* __restrict__ self,
+                              double2* __restrict__ val) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = tgt[t], e = src[t];
+  const unsigned kd = kind[t];
+  zd v(0.0, 0.0);
+  if (kd == 0u) {
+    const double kr = m.k[lay[i]] * hypot(cx[i] - cx[e], cy[i] - cy[e]);
+    v = zd(-0.25 * y0(kr), 0.25 * j0(kr)) * w[e];
+  } else if (kd == 0xFFFFFFFFu) {
+    const double2 sv = self[i];
+    v = zd(sv.x, sv.y);
+  } else {
+    v = lmq::reaction_direct(m, lay[i], lay[e], fabs(cx[i] - cx[e]), cy[i], cy[e], kd) * w[e];
   }
+  val[t] = make_double2(v.re, v.im);
 }
 
-// Reaction near field and self term: y_i += sum_j K_ij x_j + I^s_i x_i.
-__global__ void k_near_self(int N, const int* __restrict__ ptr, const int* __restrict__ src,
-                            const double2* __restrict__ val, const double2* __restrict__ self,
-                            const double2* __restrict__ x, double2* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double2 sv = self[i], xi = x[i];
-  double re = sv.x * xi.x - sv.y * xi.y, im = sv.x * xi.y + sv.y * xi.x;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+// y_i += sum_j Knear_ij x_j: one wavefront per row.
+__global__ void __launch_bounds__(256) k_near_csr(int N, const int* __restrict__ ptr, const int* __restrict__ src,
+                                                  const double2* __restrict__ val, const double2* __restrict__ x,
+                                                  double2* __restrict__ y) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  double re = 0.0, im = 0.0;
+  for (int e = ptr[row] + lane; e < ptr[row + 1]; e += 64) {
     const double2 v = val[e], xv = x[src[e]];
     re += v.x * xv.x - v.y * xv.y;
     im += v.x * xv.y + v.y * xv.x;
   }
-  const double2 o = y[i];
-  y[i] = make_double2(o.x + re, o.y + im);
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_down(re, off, 64);
+    im += __shfl_down(im, off, 64);
+  }
+  if (lane == 0) {
+    const double2 o = y[row];
+    y[row] = make_double2(o.x + re, o.y + im);
+  }
+}
+
+// M2L grouped by operator: one workgroup per operator (reaction table or
+// free-space class) keeps it in LDS and applies it to all its entries,
+// four source expansions at a time; results go to the entry's slot.
+constexpr int M2L_BATCH = 4;
+__global__ void __launch_bounds__(64) k_m2l_apply(int p, int nreac, const int* __restrict__ ptr,
+                                                  const int* __restrict__ slot, const int* __restrict__ src,
+                                                  const double2* __restrict__ free_tab,
+                                                  const double2* __restrict__ reac_tab,
+                                                  const double2* __restrict__ me, double2* __restrict__ out) {
+  extern __shared__ double2 lds[];
+  const int t = blockIdx.x;
+  const int P = 2 * p + 1;
+  const bool isfree = t >= nreac;
+  double2* T = lds;                                    // P*P (reaction) or 4p+1 (free)
+  double2* A = lds + (isfree ? (4 * p + 1) : P * P);   // [M2L_BATCH][P]
+  if (isfree) {
+    const double2* g = free_tab + (int64_t)(t - nreac) * (4 * p + 1);
+    for (int j = threadIdx.x; j <= 4 * p; j += 64) T[j] = g[j];
+  } else {
+    const double2* g = reac_tab + (int64_t)t * P * P;
+    for (int j = threadIdx.x; j < P * P; j += 64) T[j] = g[j];
+  }
+  const int e0 = ptr[t], e1 = ptr[t + 1];
+  for (int e = e0; e < e1; e += M2L_BATCH) {
+    const int ne = min(M2L_BATCH, e1 - e);
+    __syncthreads();
+    for (int j = threadIdx.x; j < ne * P; j += 64) {
+      const int q = j / P, n = j % P;
+      A[q * P + n] = me[(int64_t)src[e + q] * P + n];
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)P) {
+      const int mrow = threadIdx.x;
+      double re[M2L_BATCH], im[M2L_BATCH];
+#pragma unroll
+      for (int q = 0; q < M2L_BATCH; ++q) re[q] = im[q] = 0.0;
+      if (isfree) {
+        for (int n = 0; n < P; ++n) {
+          const double2 gv = T[n - mrow + 2 * p];
+#pragma unroll
+          for (int q = 0; q < M2L_BATCH; ++q) {
+            const double2 av = A[q * P + n];
+            re[q] += gv.x * av.x - gv.y * av.y;
+            im[q] += gv.x * av.y + gv.y * av.x;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < M2L_BATCH; ++q) {  // times i/4
+          const double r2 = -0.25 * im[q], i2 = 0.25 * re[q];
+          re[q] = r2;
+          im[q] = i2;
+        }
+      } else {
+        for (int n = 0; n < P; ++n) {
+          const double2 tv = T[n * P + mrow];
+#pragma unroll
+          for (int q = 0; q < M2L_BATCH; ++q) {
+            const double2 av = A[q * P + n];
+            re[q] += tv.x * av.x - tv.y * av.y;
+            im[q] += tv.x * av.y + tv.y * av.x;
+          }
+        }
+      }
+      for (int q = 0; q < ne; ++q) out[(int64_t)slot[e + q] * P + mrow] = make_double2(re[q], im[q]);
+    }
+  }
+}
+
+// LE of each target box = sum of its entries' slots.
+__global__ void __launch_bounds__(64) k_m2l_reduce(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
+                                                   const double2* __restrict__ out, double2* __restrict__ le) {
+  const int P = 2 * p + 1;
+  if (threadIdx.x >= (unsigned)P) return;
+  double re = 0.0, im = 0.0;
+  for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
+    const double2 v = out[(int64_t)e * P + threadIdx.x];
+    re += v.x;
+    im += v.y;
+  }
+  le[(int64_t)tgts[blockIdx.x] * P + threadIdx.x] = make_double2(re, im);
 }
 
 // ================================================================ host side ==
@@ -789,6 +781,71 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     for (int64_t i = 0; i < N; ++i) F->rn_ptr[i + 1] += F->rn_ptr[i];
   }
 
+  // ---- near-field matrix (CSR by element): free near, reaction near, self ----
+  std::vector<int> nm_tgt;
+  std::vector<unsigned> nm_kind;
+  {
+    std::vector<int> leaf_slot(N, -1);  // index into near_tgt of the element's free leaf
+    for (size_t t = 0; t < F->near_tgt.size(); ++t) {
+      const BoxDev& B = F->boxes[F->near_tgt[t]];
+      for (int i = 0; i < B.npt; ++i) leaf_slot[F->pt_elem[B.pt0 + i]] = (int)t;
+    }
+    F->nm_ptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t len = 1 + (F->rn_ptr[i + 1] - F->rn_ptr[i]);
+      const int t = leaf_slot[i];
+      for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e) len += F->boxes[F->near_src[e]].npt;
+      len -= 1;  // the element itself
+      F->nm_ptr[i + 1] = (int)len;
+    }
+    for (int64_t i = 0; i < N; ++i) F->nm_ptr[i + 1] += F->nm_ptr[i];
+    const int64_t nnz = F->nm_ptr[N];
+    LM_CHECK(nnz < ((int64_t)1 << 31), LM_ENOMEM, "near-field matrix too large");
+    F->nm_src.resize(nnz);
+    nm_tgt.resize(nnz);
+    nm_kind.resize(nnz);
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t q = F->nm_ptr[i];
+      F->nm_src[q] = (int)i;
+      nm_kind[q] = 0xFFFFFFFFu;
+      nm_tgt[q++] = (int)i;
+      for (int e = F->rn_ptr[i]; e < F->rn_ptr[i + 1]; ++e) {
+        F->nm_src[q] = F->rn_src[e];
+        nm_kind[q] = F->rn_mask[e];
+        nm_tgt[q++] = (int)i;
+      }
+      const int t = leaf_slot[i];
+      for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e) {
+        const BoxDev& C = F->boxes[F->near_src[e]];
+        for (int j = 0; j < C.npt; ++j) {
+          const int el = F->pt_elem[C.pt0 + j];
+          if (el == (int)i) continue;
+          F->nm_src[q] = el;
+          nm_kind[q] = 0u;
+          nm_tgt[q++] = (int)i;
+        }
+      }
+    }
+  }
+  // ---- M2L entries grouped by operator ----------------------------------------
+  {
+    F->n_reac_tab = (int)reac_id.size();
+    F->n_free_tab = (int)free_id.size();
+    const int ntab = F->n_reac_tab + F->n_free_tab;
+    F->tm_ptr.assign(ntab + 1, 0);
+    auto tabidx = [&](int t) { return t >= 0 ? t : F->n_reac_tab + (-t - 1); };
+    for (int t : F->m2l_tab) F->tm_ptr[tabidx(t) + 1]++;
+    for (int i = 0; i < ntab; ++i) F->tm_ptr[i + 1] += F->tm_ptr[i];
+    std::vector<int> fill(F->tm_ptr.begin(), F->tm_ptr.end() - 1);
+    F->tm_slot.resize(F->m2l_tab.size());
+    F->tm_src.resize(F->m2l_tab.size());
+    for (size_t e = 0; e < F->m2l_tab.size(); ++e) {
+      const int q = fill[tabidx(F->m2l_tab[e])]++;
+      F->tm_slot[q] = (int)e;
+      F->tm_src[q] = F->m2l_src[e];
+    }
+  }
+
   // ---- upload and device setup ---------------------------------------------------
   LM_TRY(up(F->d_boxes, F->boxes, s));
   LM_TRY(up(F->d_children, F->children, s));
@@ -844,22 +901,26 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
-  // reaction near-field entries
+  // near-field matrix values
   const int nrn = (int)F->rn_src.size();
-  LM_TRY(F->d_rn_val.alloc((size_t)std::max(nrn, 1) * sizeof(double2)));
-  if (nrn) {
-    std::vector<int> tgt(nrn);
-    for (int64_t i = 0; i < N; ++i)
-      for (int e = F->rn_ptr[i]; e < F->rn_ptr[i + 1]; ++e) tgt[e] = (int)i;
-    DevBuf dt, dm;
-    LM_TRY(up(dt, tgt, s));
-    LM_TRY(up(dm, F->rn_mask, s));
-    hipLaunchKernelGGL(k_reac_near, dim3(div_up(nrn, 64)), dim3(64), 0, s, m, nrn, dt.as<int>(), F->d_rn_src.as<int>(),
-                       dm.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(),
-                       g->d_layer.as<int>(), F->d_rn_val.as<double2>());
+  {
+    const int64_t nnz = F->nm_ptr[N];
+    LM_TRY(up(F->d_nm_ptr, F->nm_ptr, s));
+    LM_TRY(up(F->d_nm_src, F->nm_src, s));
+    DevBuf dt, dk;
+    LM_TRY(up(dt, nm_tgt, s));
+    LM_TRY(up(dk, nm_kind, s));
+    LM_TRY(F->d_nm_val.alloc(std::max<int64_t>(nnz, 1) * sizeof(double2)));
+    hipLaunchKernelGGL(k_near_values, dim3(div_up(nnz, 128)), dim3(128), 0, s, m, nnz, dt.as<int>(),
+                       F->d_nm_src.as<int>(), dk.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
+                       g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), F->d_nm_val.as<double2>());
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
+  LM_TRY(up(F->d_tm_ptr, F->tm_ptr, s));
+  LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
+  LM_TRY(up(F->d_tm_src, F->tm_src, s));
+  LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
   LM_TRY(F->d_me.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
   LM_TRY(F->d_le.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
   int64_t nf = 0, nr = 0, npp = 0;
@@ -881,7 +942,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
 }
 
 // Stage timing: when ev != nullptr, ev[2*i], ev[2*i+1] bracket stage i on
-// stream s (0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near P2P, 6 reaction near + self).
+// stream s (0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near-field matrix, 6 unused).
 lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
                            hipEvent_t* ev);
 
@@ -925,10 +986,15 @@ lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* x
     // M2L (every level at once); boxes without a list start from zero
     LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * P * sizeof(double2), s));
     LM_STAGE(2, 1);
-    if (!F->m2l_tgt.empty())
-      hipLaunchKernelGGL(k_m2l, dim3(F->m2l_tgt.size()), dim3(WG), 0, s, p, F->d_m2l_tgt.as<int>(),
-                         F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_tab.as<int>(),
-                         F->d_free_tab.as<double2>(), F->d_reac_tab.as<double2>(), me, le);
+    if (!F->m2l_tgt.empty()) {
+      const int ntab = F->n_reac_tab + F->n_free_tab;
+      const size_t lds = (size_t)(std::max(P * P, 4 * p + 1) + M2L_BATCH * P) * sizeof(double2);
+      hipLaunchKernelGGL(k_m2l_apply, dim3(ntab), dim3(64), lds, s, p, F->n_reac_tab, F->d_tm_ptr.as<int>(),
+                         F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), F->d_free_tab.as<double2>(),
+                         F->d_reac_tab.as<double2>(), me, F->d_m2l_out.as<double2>());
+      hipLaunchKernelGGL(k_m2l_reduce, dim3(F->m2l_tgt.size()), dim3(64), 0, s, p, F->d_m2l_tgt.as<int>(),
+                         F->d_m2l_ptr.as<int>(), F->d_m2l_out.as<double2>(), le);
+    }
     LM_STAGE(2, 0);
     LM_STAGE(3, 1);
     // L2L, coarse to fine
@@ -948,14 +1014,10 @@ lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* x
     LM_STAGE(4, 0);
     LM_STAGE(5, 1);
     // near fields and self terms
-    if (!F->near_tgt.empty())
-      hipLaunchKernelGGL(k_p2p, dim3(F->near_tgt.size()), dim3(128), 0, s, F->d_near_tgt.as<int>(),
-                         F->d_near_ptr.as<int>(), F->d_near_src.as<int>(), boxes, F->d_pt_elem.as<int>(),
-                         F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, y);
+    hipLaunchKernelGGL(k_near_csr, dim3(div_up(N, 4)), dim3(256), 0, s, N, F->d_nm_ptr.as<int>(),
+                       F->d_nm_src.as<int>(), F->d_nm_val.as<double2>(), x, y);
     LM_STAGE(5, 0);
     LM_STAGE(6, 1);
-    hipLaunchKernelGGL(k_near_self, dim3(div_up(N, 256)), dim3(256), 0, s, N, F->d_rn_ptr.as<int>(),
-                       F->d_rn_src.as<int>(), F->d_rn_val.as<double2>(), F->d_self.as<double2>(), x, y);
     LM_STAGE(6, 0);
 #undef LM_STAGE
     LM_TRY_HIP(hipGetLastError());

@@ -32,9 +32,15 @@ struct FmmPlan {
   std::vector<double> reac_geo;   // (dx, ht, hs)
   // free near field
   std::vector<int> near_tgt, near_ptr, near_src;
-  // reaction near field (CSR by element)
+  // reaction near field (pairs with their component masks)
   std::vector<int> rn_ptr, rn_src;
   std::vector<unsigned> rn_mask;
+  // near-field matrix (CSR by element, input numbering): free-space near
+  // pairs, reaction near pairs and the self term, values precomputed
+  std::vector<int> nm_ptr, nm_src;
+  // M2L entries grouped by operator (reaction tables, then free classes)
+  std::vector<int> tm_ptr, tm_slot, tm_src;
+  int n_reac_tab = 0, n_free_tab = 0;
   // M2M / L2L operators F_j(d), d = child centre - parent centre; [layer][level][pos][4p+1]
   std::vector<zd> ftab;
   std::vector<int> tree_layer;
@@ -48,11 +54,13 @@ struct FmmPlan {
   DevBuf d_near_tgt, d_near_ptr, d_near_src;
   DevBuf d_rn_ptr, d_rn_src, d_rn_val;
   DevBuf d_self, d_me, d_le, d_tree_layer;
+  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int64_t bytes() const {
     const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
                            &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_free_tab, &d_reac_tab,
                            &d_ftab, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
-                           &d_self, &d_me, &d_le, &d_tree_layer};
+                           &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
+                           &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

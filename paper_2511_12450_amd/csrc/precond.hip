@@ -145,23 +145,46 @@ __global__ void __launch_bounds__(256) k_pre_setup(MediumDev m, int first, const
   }
 }
 
-__global__ void __launch_bounds__(64) k_pre_apply(int N, int R, const int* __restrict__ jptr,
-                                                  const int* __restrict__ jidx, const int* __restrict__ nb,
-                                                  const int64_t* __restrict__ zoff, const double2* __restrict__ Z,
-                                                  const double2* __restrict__ x, double2* __restrict__ y) {
+// y_{B_r} = sum_j Z_B[j][r] x_{J_j}: x_J staged in LDS; lanes over r, the four
+// waves split the j range and combine through LDS.
+__global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __restrict__ jptr,
+                                                   const int* __restrict__ jidx, const int* __restrict__ nb,
+                                                   const int64_t* __restrict__ zoff, const double2* __restrict__ Z,
+                                                   const double2* __restrict__ x, double2* __restrict__ y) {
   const int leaf = blockIdx.x;
   const int j0_ = jptr[leaf], q = jptr[leaf + 1] - j0_, nB = nb[leaf];
   const int* J = jidx + j0_;
   const double2* Zl = Z + zoff[leaf];
-  for (int r = threadIdx.x; r < nB; r += blockDim.x) {
-    for (int rr = 0; rr < R; ++rr) {
-      const double2* xr = x + (int64_t)rr * N;
-      zd acc(0.0, 0.0);
-      for (int jj = 0; jj < q; ++jj) {
-        const double2 zv = Zl[(int64_t)jj * nB + r], xv = xr[J[jj]];
-        acc += zd(zv.x, zv.y) * zd(xv.x, xv.y);
+  __shared__ double2 xs[2048];
+  __shared__ double2 part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int chunk = (q + 3) / 4, ja = wv * chunk, jb = min(q, ja + chunk);
+  for (int rr = 0; rr < R; ++rr) {
+    const double2* xr = x + (int64_t)rr * N;
+    __syncthreads();
+    for (int j = threadIdx.x; j < q; j += 256) xs[j] = xr[J[j]];
+    __syncthreads();
+    for (int r0 = 0; r0 < nB; r0 += 64) {
+      const int r = r0 + lane;
+      double re = 0.0, im = 0.0;
+      if (r < nB) {
+        for (int jj = ja; jj < jb; ++jj) {
+          const double2 zv = Zl[(int64_t)jj * nB + r], xv = xs[jj];
+          re += zv.x * xv.x - zv.y * xv.y;
+          im += zv.x * xv.y + zv.y * xv.x;
+        }
       }
-      y[(int64_t)rr * N + J[r]] = make_double2(acc.re, acc.im);
+      part[wv][lane] = make_double2(re, im);
+      __syncthreads();
+      if (wv == 0 && r < nB) {
+        double2 t = part[0][lane];
+        for (int w2 = 1; w2 < 4; ++w2) {
+          t.x += part[w2][lane].x;
+          t.y += part[w2][lane].y;
+        }
+        y[(int64_t)rr * N + J[r]] = t;
+      }
+      __syncthreads();
     }
   }
 }
@@ -219,7 +242,7 @@ lm_status precond_build(lm_geom_s* g, hipStream_t s) {
 lm_status precond_apply(lm_geom_s* g, int n_rhs, const void* x, void* y, hipStream_t s) {
   Precond* P = g->pre;
   LM_CHECK(P, LM_EINVAL, "no preconditioner");
-  hipLaunchKernelGGL(k_pre_apply, dim3(P->nleaf), dim3(64), 0, s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+  hipLaunchKernelGGL(k_pre_apply, dim3(P->nleaf), dim3(256), 0, s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
                      P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
                      (const double2*)x, (double2*)y);
   LM_TRY_HIP(hipGetLastError());
