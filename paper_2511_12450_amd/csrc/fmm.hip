@@ -49,25 +49,51 @@ void fmm_stats(const FmmPlan* f, int64_t* out) {
 }
 
 // =========================================================== setup kernels ==
+//
+// Scaled expansions.  With s = k w_l / 2 for a box of level l in a tree of
+// wavenumber k and sig_n = s^|n| / |n|!, the library stores
+//   ME  at_n = a_n / sig_n   (|at_n| <~ |q| (rho/w)^|n|),
+//   LE  bt_m = b_m * sig_m   (|bt_m| <~ (w/R)^|m|),
+// and every translation operator carries the matching factors, so all stored
+// numbers stay within a few orders of magnitude of one and FP32 holds them.
+// Operators are stored column-major by input index: out_i = sum_j Op[j][i] in_j.
 
-// Hankel values G_j(D), j = -2p..2p, for each free-space M2L class.
-__global__ void k_free_tables(int n, int p, const double* __restrict__ geo, double2* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int J = 2 * p;
-  zd G[2 * (2 * MAXP) + 1];
-  zd hb[2 * MAXP + 1];
-  fm::g_seq(geo[3 * t], geo[3 * t + 1], geo[3 * t + 2], J, G, hb);
-  for (int j = 0; j <= 2 * J; ++j) out[(int64_t)t * (2 * J + 1) + j] = make_double2(G[j].re, G[j].im);
+__device__ __forceinline__ double sigma_of(const double* sig, int p, int layer, int nlev, int level, int n) {
+  return sig[(int64_t)(layer * nlev + level) * (p + 1) + (n < 0 ? -n : n)];
 }
 
-// Reaction M2L operator per class: one workgroup per table, nodes in chunks.
+// Free-space M2L operator per class: Op[n][m] = sig^t_m (i/4) G_{n-m}(c_t - c_s) sig^s_n.
+__global__ void __launch_bounds__(64) k_free_tables(int p, int nlev, const double* __restrict__ geo,
+                                                    const int* __restrict__ lvl, const double* __restrict__ sig,
+                                                    double2* __restrict__ out) {
+  const int t = blockIdx.x;
+  const int P = 2 * p + 1, J = 2 * p;
+  __shared__ double2 G[4 * MAXP + 1];
+  if (threadIdx.x == 0) {
+    zd g[4 * MAXP + 1];
+    zd hb[2 * MAXP + 1];
+    fm::g_seq(geo[3 * t], geo[3 * t + 1], geo[3 * t + 2], J, g, hb);
+    for (int j = 0; j <= 2 * J; ++j) G[j] = make_double2(g[j].re, g[j].im);
+  }
+  __syncthreads();
+  const int layer = lvl[2 * t], level = lvl[2 * t + 1];
+  for (int idx = threadIdx.x; idx < P * P; idx += 64) {
+    const int n = idx / P - p, mm = idx % P - p;
+    const double sc = 0.25 * sigma_of(sig, p, layer, nlev, level, mm) * sigma_of(sig, p, layer, nlev, level, n);
+    const double2 gv = G[n - mm + 2 * p];
+    out[(int64_t)t * P * P + idx] = make_double2(-gv.y * sc, gv.x * sc);  // (i/4) G
+  }
+}
+
+// Reaction M2L operator per class: one workgroup per table, nodes in chunks;
+// the scale factors of the target and source levels are applied on output.
 constexpr int TAB_CHUNK = 16;
-__global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, const int* __restrict__ meta,
-                                                     const double* __restrict__ geo, double2* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, int nlev, const int* __restrict__ meta,
+                                                     const double* __restrict__ geo, const double* __restrict__ sig,
+                                                     double2* __restrict__ out) {
   const int t = blockIdx.x;
   const int P = 2 * p + 1;
-  const int lt = meta[3 * t], ls = meta[3 * t + 1], comp = meta[3 * t + 2];
+  const int lt = meta[4 * t], ls = meta[4 * t + 1], comp = meta[4 * t + 2], level = meta[4 * t + 3];
   const double dx = geo[3 * t], ht = geo[3 * t + 1], hs = geo[3 * t + 2];
   __shared__ double2 A[TAB_CHUNK][MAXPP];
   __shared__ double2 B[TAB_CHUNK][MAXPP];
@@ -126,166 +152,14 @@ __global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, const i
   for (int e = 0; e < EPT; ++e) {
     const int idx = threadIdx.x + 256 * e;
     if (idx >= P * P) break;
-    out[(int64_t)t * P * P + idx] = make_double2(acc[e].re, acc[e].im);
+    const int n = idx / P - p, mm = idx % P - p;
+    const double sc = sigma_of(sig, p, lt, nlev, level, mm) * sigma_of(sig, p, ls, nlev, level, n);
+    out[(int64_t)t * P * P + idx] = make_double2(acc[e].re * sc, acc[e].im * sc);
   }
 }
 
-// ========================================================== matvec kernels ==
-
-// P2M: a_n = sum_s q_s J_n(k rho_s) e^{-i n theta_s}, q_s = |Gamma_s| x_s.
-__global__ void __launch_bounds__(WG) k_p2m(int p, const int* __restrict__ leaves, const BoxDev* __restrict__ boxes,
-                                            const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
-                                            const double* __restrict__ w, const double2* __restrict__ x,
-                                            double2* __restrict__ me) {
-  const int b = leaves[blockIdx.x];
-  const BoxDev B = boxes[b];
-  const int P = 2 * p + 1;
-  __shared__ double Jq_re[WG][MAXP + 1];
-  __shared__ double Jq_im[WG][MAXP + 1];
-  __shared__ double th[WG];
-  const int n = (int)threadIdx.x - p;
-  zd acc(0.0, 0.0);
-  for (int s0 = 0; s0 < B.npt; s0 += WG) {
-    const int s = s0 + threadIdx.x;
-    if (s < B.npt) {
-      const int pi = B.pt0 + s;
-      const double2 xh = pt_xh[pi];
-      const double dx = xh.x - B.cx, dh = xh.y - B.ch;
-      const int e = pt_elem[pi];
-      const double2 xv = x[e];
-      const double we = w[e];
-      double J[MAXP + 1];
-      fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
-      for (int j = 0; j <= p; ++j) {
-        Jq_re[threadIdx.x][j] = J[j] * we * xv.x;
-        Jq_im[threadIdx.x][j] = J[j] * we * xv.y;
-      }
-      th[threadIdx.x] = atan2(dh, dx);
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)P) {
-      const int cnt = min(WG, B.npt - s0);
-      const int an = n < 0 ? -n : n;
-      const double sg = (n < 0 && (an & 1)) ? -1.0 : 1.0;
-      for (int j = 0; j < cnt; ++j) {
-        double sn, cs;
-        sincos(-n * th[j], &sn, &cs);
-        const double re = Jq_re[j][an] * sg, im = Jq_im[j][an] * sg;
-        acc.re += re * cs - im * sn;
-        acc.im += re * sn + im * cs;
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)P) me[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
-}
-
-// Operator F_j(d) for the box's layer/level/position: ftab[((layer*nlev + level)*4 + pos)*(4p+1) + j + 2p]
-__device__ __forceinline__ const double2* ftab_row(const double2* ftab, int nlev, int p, int layer, int level, int pos) {
-  return ftab + ((int64_t)((layer * nlev + level) * 4 + pos)) * (4 * p + 1) + 2 * p;
-}
-
-// M2M: a^C_n = sum_children sum_m F_{m-n}(C - c) a^c_m = sum (-1)^{m-n} F_{m-n}(c - C) a_m.
-__global__ void __launch_bounds__(WG) k_m2m(int p, int nlev, const int* __restrict__ parents,
-                                            const BoxDev* __restrict__ boxes, const int* __restrict__ children,
-                                            const int* __restrict__ tree_layer, const double2* __restrict__ ftab,
-                                            double2* __restrict__ me) {
-  const int b = parents[blockIdx.x];
-  const BoxDev B = boxes[b];
-  const int P = 2 * p + 1;
-  __shared__ double2 a[MAXPP];
-  __shared__ double2 f[4 * MAXP + 1];
-  const int n = (int)threadIdx.x - p;
-  zd acc(0.0, 0.0);
-  for (int c = 0; c < B.nchild; ++c) {
-    const int cb = children[B.child0 + c];
-    const BoxDev C = boxes[cb];
-    if (threadIdx.x < (unsigned)P) a[threadIdx.x] = me[(int64_t)cb * P + threadIdx.x];
-    const double2* fr = ftab_row(ftab, nlev, p, tree_layer[C.tree], C.level, C.pos);
-    for (int j = threadIdx.x; j <= 4 * p; j += WG) f[j] = fr[j - 2 * p];
-    __syncthreads();
-    if (threadIdx.x < (unsigned)P) {
-      for (int mm = -p; mm <= p; ++mm) {
-        const int d = mm - n;
-        const double2 fv = f[d + 2 * p];
-        const double sg = (d & 1) ? -1.0 : 1.0;
-        const double2 av = a[mm + p];
-        acc.re += sg * (fv.x * av.x - fv.y * av.y);
-        acc.im += sg * (fv.x * av.y + fv.y * av.x);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)P) me[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
-}
-
-// L2L: b^c_n += sum_m F_{m-n}(c - C) b^C_m, for every box of one level with a parent.
-__global__ void __launch_bounds__(WG) k_l2l(int p, int nlev, int first, const BoxDev* __restrict__ boxes,
-                                            const int* __restrict__ tree_layer, const double2* __restrict__ ftab,
-                                            double2* __restrict__ le) {
-  const int b = first + blockIdx.x;
-  const BoxDev B = boxes[b];
-  const int P = 2 * p + 1;
-  __shared__ double2 a[MAXPP];
-  __shared__ double2 f[4 * MAXP + 1];
-  if (threadIdx.x < (unsigned)P) a[threadIdx.x] = le[(int64_t)B.parent * P + threadIdx.x];
-  const double2* fr = ftab_row(ftab, nlev, p, tree_layer[B.tree], B.level, B.pos);
-  for (int j = threadIdx.x; j <= 4 * p; j += WG) f[j] = fr[j - 2 * p];
-  __syncthreads();
-  if (threadIdx.x < (unsigned)P) {
-    const int n = (int)threadIdx.x - p;
-    const double2 old = le[(int64_t)b * P + threadIdx.x];
-    zd acc(old.x, old.y);
-    for (int mm = -p; mm <= p; ++mm) {
-      const double2 fv = f[mm - n + 2 * p];
-      const double2 av = a[mm + p];
-      acc.re += fv.x * av.x - fv.y * av.y;
-      acc.im += fv.x * av.y + fv.y * av.x;
-    }
-    le[(int64_t)b * P + threadIdx.x] = make_double2(acc.re, acc.im);
-  }
-}
-
-// L2P: y_e (=/+=) sum_m b_m J_m(k rho) e^{i m theta} for the points of each leaf.
-__global__ void __launch_bounds__(WG) k_l2p(int p, int accumulate, const int* __restrict__ leaves,
-                                            const BoxDev* __restrict__ boxes, const int* __restrict__ pt_elem,
-                                            const double2* __restrict__ pt_xh, const double2* __restrict__ le,
-                                            double2* __restrict__ y) {
-  const int b = leaves[blockIdx.x];
-  const BoxDev B = boxes[b];
-  const int P = 2 * p + 1;
-  __shared__ double2 L[MAXPP];
-  if (threadIdx.x < (unsigned)P) L[threadIdx.x] = le[(int64_t)b * P + threadIdx.x];
-  __syncthreads();
-  for (int s = threadIdx.x; s < B.npt; s += WG) {
-    const int pi = B.pt0 + s;
-    const double2 xh = pt_xh[pi];
-    const double dx = xh.x - B.cx, dh = xh.y - B.ch;
-    double J[MAXP + 1];
-    fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
-    const zd e1 = fm::cis(atan2(dh, dx));
-    double2 l0 = L[p];
-    zd acc(l0.x * J[0], l0.y * J[0]);
-    zd ep(1.0, 0.0);
-    for (int j = 1; j <= p; ++j) {
-      ep = ep * e1;
-      const double sg = (j & 1) ? -1.0 : 1.0;
-      const double2 lp = L[p + j], lm = L[p - j];
-      const zd cp = zd(lp.x, lp.y) * ep, cm = zd(lm.x, lm.y) * conj(ep);
-      acc += (cp + cm * sg) * J[j];
-    }
-    const int e = pt_elem[pi];
-    if (accumulate) {
-      const double2 o = y[e];
-      y[e] = make_double2(o.x + acc.re, o.y + acc.im);
-    } else {
-      y[e] = make_double2(acc.re, acc.im);
-    }
-  }
-}
-
-// Near-field matrix values: kind 0 free-space pair, 1 reaction pair (mask),
-// 2 self term.
+// Near-field matrix values: kind 0 free-space pair, all ones self term,
+// otherwise the component mask of a reaction pair.
 __global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tgt, const int* __restrict__ src,
                               const unsigned* __restrict__ kind, const double* __restrict__ cx,
                               const double* __restrict__ cy, const double* __restrict__ w,
@@ -308,51 +182,223 @@ __global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tg
   val[t] = make_double2(v.re, v.im);
 }
 
-// y_i += sum_j Knear_ij x_j: one wavefront per row.
-__global__ void __launch_bounds__(256) k_near_csr(int N, const int* __restrict__ ptr, const int* __restrict__ src,
-                                                  const double2* __restrict__ val, const double2* __restrict__ x,
-                                                  double2* __restrict__ y) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= N) return;
-  double re = 0.0, im = 0.0;
-  for (int e = ptr[row] + lane; e < ptr[row + 1]; e += 64) {
-    const double2 v = val[e], xv = x[src[e]];
-    re += v.x * xv.x - v.y * xv.y;
-    im += v.x * xv.y + v.y * xv.x;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    re += __shfl_down(re, off, 64);
-    im += __shfl_down(im, off, 64);
-  }
-  if (lane == 0) {
-    const double2 o = y[row];
-    y[row] = make_double2(o.x + re, o.y + im);
+__global__ void k_c128_to_c64_fmm(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+// ========================================================== matvec kernels ==
+// Templated on the storage/arithmetic type RT (double: LM_FP64, float:
+// LM_MIXED) with R right-hand sides per launch (R <= LM_RCHUNK).  Expansions
+// are stored [box][2p+1][R] and vectors [R][N].  A workgroup owns the (2p+1) R
+// outputs of one box; thread t holds outputs t, t + blockDim, ... (at most
+// MO of them) in registers, in fully unrolled loops so they stay in VGPRs.
+
+constexpr int LM_RCHUNK = 64;
+constexpr int MO = 16;          // (2p+1) R <= MO * 256 for p <= 31, R <= 64
+constexpr int PCH = 32;         // points per chunk in P2M / L2P
+
+template <typename RT> struct C2T;
+template <> struct C2T<double> { typedef double2 T; };
+template <> struct C2T<float> { typedef float2 T; };
+
+template <typename RT, typename V>
+__device__ __forceinline__ void cmac(RT& re, RT& im, V a, V b) {
+  re += a.x * b.x - a.y * b.y;
+  im += a.x * b.y + a.y * b.x;
+}
+
+template <typename V, typename RT>
+__device__ __forceinline__ V mk(RT re, RT im) {
+  V o;
+  o.x = re;
+  o.y = im;
+  return o;
+}
+
+// Bessel values J_j(k rho)/sig_j and e^{+-i j theta}, j = 0..p, for one point
+// into LDS rows (FP64 evaluation, stored in RT).
+template <typename RT>
+__device__ __forceinline__ void point_basis(double k, double dx, double dh, int p, const double* sg, double sign,
+                                            RT* js, typename C2T<RT>::T* cs) {
+  double J[MAXP + 1];
+  fm::bessel_j_seq(k * hypot(dx, dh), p, J);
+  const zd e1 = fm::cis(sign * atan2(dh, dx));
+  zd ep(1.0, 0.0);
+  for (int j = 0; j <= p; ++j) {
+    js[j] = (RT)(J[j] / sg[j]);
+    cs[j] = mk<typename C2T<RT>::T>((RT)ep.re, (RT)ep.im);
+    ep = ep * e1;
   }
 }
 
-// M2L grouped by operator: one workgroup per operator (reaction table or
-// free-space class) keeps it in LDS and applies it to all its entries,
-// four source expansions at a time; results go to the entry's slot.
+// P2M: at_n = sum_s q_s J_n(k rho_s) e^{-i n theta_s} / sig_n, q_s = |Gamma_s| x_s.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_p2m(int p, int R, int nlev, const int* __restrict__ leaves,
+                                             const BoxDev* __restrict__ boxes, const int* __restrict__ tree_layer,
+                                             const double* __restrict__ sig, const int* __restrict__ pt_elem,
+                                             const double2* __restrict__ pt_xh, const double* __restrict__ w,
+                                             const typename C2T<RT>::T* __restrict__ x, int N,
+                                             typename C2T<RT>::T* __restrict__ me) {
+  typedef typename C2T<RT>::T V;
+  const int b = leaves[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1, PR = P * R;
+  const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
+  __shared__ RT js[PCH][MAXP + 1];
+  __shared__ V cs[PCH][MAXP + 1];
+  extern __shared__ unsigned char dyn[];
+  V* qs = reinterpret_cast<V*>(dyn);  // [PCH][R]
+  RT are[MO], aim[MO];
+#pragma unroll
+  for (int i = 0; i < MO; ++i) are[i] = aim[i] = RT(0);
+  for (int s0 = 0; s0 < B.npt; s0 += PCH) {
+    const int cnt = min(PCH, B.npt - s0);
+    __syncthreads();
+    if (threadIdx.x < (unsigned)cnt) {
+      const double2 xh = pt_xh[B.pt0 + s0 + threadIdx.x];
+      point_basis<RT>(B.k, xh.x - B.cx, xh.y - B.ch, p, sg, -1.0, js[threadIdx.x], cs[threadIdx.x]);
+    }
+    for (int idx = threadIdx.x; idx < cnt * R; idx += blockDim.x) {
+      const int j = idx / R, r = idx - j * R;
+      const int e = pt_elem[B.pt0 + s0 + j];
+      const V xv = x[(int64_t)r * N + e];
+      const RT we = (RT)w[e];
+      qs[idx] = mk<V>(xv.x * we, xv.y * we);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MO; ++i) {
+      const int idx = threadIdx.x + i * blockDim.x;
+      if (idx < PR) {
+        const int n = idx / R - p, r = idx % R;
+        const int an = n < 0 ? -n : n;
+        const RT sn = (n < 0 && (an & 1)) ? RT(-1) : RT(1);
+        const RT cj = n < 0 ? RT(-1) : RT(1);  // e^{-i n th} = conj(e^{-i |n| th}) for n < 0
+        RT re = are[i], im = aim[i];
+        for (int j = 0; j < cnt; ++j) {
+          const V c = cs[j][an];
+          const RT jv = js[j][an] * sn;
+          const V q = qs[j * R + r];
+          const RT cy = c.y * cj;
+          re += jv * (c.x * q.x - cy * q.y);
+          im += jv * (c.x * q.y + cy * q.x);
+        }
+        are[i] = re;
+        aim[i] = im;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int idx = threadIdx.x + i * blockDim.x;
+    if (idx < PR) me[(int64_t)b * PR + idx] = mk<V>(are[i], aim[i]);
+  }
+}
+
+// acc[o][r] += sum_j Op[j][o] in[j][r] for this thread's outputs; Op is
+// column-major by input (global), in is [P][R] in LDS.
+template <typename RT>
+__device__ __forceinline__ void op_apply(int P, int R, const typename C2T<RT>::T* __restrict__ Op,
+                                         const typename C2T<RT>::T* in, RT* are, RT* aim) {
+  const int PR = P * R;
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int idx = threadIdx.x + i * blockDim.x;
+    if (idx < PR) {
+      const int o = idx / R, r = idx - o * R;
+      RT re = are[i], im = aim[i];
+      const typename C2T<RT>::T* op = Op + o;
+      for (int j = 0; j < P; ++j) cmac(re, im, op[(int64_t)j * P], in[j * R + r]);
+      are[i] = re;
+      aim[i] = im;
+    }
+  }
+}
+
+template <typename RT>
+__device__ __forceinline__ void acc_zero(RT* are, RT* aim) {
+#pragma unroll
+  for (int i = 0; i < MO; ++i) are[i] = aim[i] = RT(0);
+}
+
+template <typename RT>
+__device__ __forceinline__ void acc_store(int PR, const RT* are, const RT* aim, typename C2T<RT>::T* out) {
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int idx = threadIdx.x + i * blockDim.x;
+    if (idx < PR) out[idx] = mk<typename C2T<RT>::T>(are[i], aim[i]);
+  }
+}
+
+// M2M: parent at = sum over children of Op_child at_child.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_m2m(int p, int R, int nlev, const int* __restrict__ parents,
+                                             const BoxDev* __restrict__ boxes, const int* __restrict__ children,
+                                             const int* __restrict__ tree_layer,
+                                             const typename C2T<RT>::T* __restrict__ ops,
+                                             typename C2T<RT>::T* __restrict__ me) {
+  typedef typename C2T<RT>::T V;
+  const int b = parents[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1, PR = P * R;
+  extern __shared__ unsigned char dyn[];
+  V* a = reinterpret_cast<V*>(dyn);  // [P][R]
+  RT are[MO], aim[MO];
+  acc_zero(are, aim);
+  for (int c = 0; c < B.nchild; ++c) {
+    const int cb = children[B.child0 + c];
+    const BoxDev C = boxes[cb];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) a[idx] = me[(int64_t)cb * PR + idx];
+    __syncthreads();
+    const V* Op = ops + ((int64_t)((tree_layer[C.tree] * nlev + C.level) * 4 + C.pos)) * P * P;
+    op_apply<RT>(P, R, Op, a, are, aim);
+  }
+  acc_store(PR, are, aim, me + (int64_t)b * PR);
+}
+
+// M2L, target-major: each target box sums Op_entry at_source over its list.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __restrict__ tgts,
+                                                    const int* __restrict__ ptr, const int* __restrict__ src,
+                                                    const int* __restrict__ opi,
+                                                    const typename C2T<RT>::T* __restrict__ ops,
+                                                    const typename C2T<RT>::T* __restrict__ me,
+                                                    typename C2T<RT>::T* __restrict__ le) {
+  typedef typename C2T<RT>::T V;
+  const int P = 2 * p + 1, PR = P * R;
+  extern __shared__ unsigned char dyn[];
+  V* a = reinterpret_cast<V*>(dyn);  // [P][R]
+  RT are[MO], aim[MO];
+  acc_zero(are, aim);
+  for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
+    __syncthreads();
+    const int s = src[e];
+    for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) a[idx] = me[(int64_t)s * PR + idx];
+    __syncthreads();
+    op_apply<RT>(P, R, ops + (int64_t)opi[e] * P * P, a, are, aim);
+  }
+  acc_store(PR, are, aim, le + (int64_t)tgts[blockIdx.x] * PR);
+}
+
+// M2L, operator-major (one right-hand side): one workgroup per operator keeps
+// it in LDS and applies it to all its entries; results go to the entry slots.
 constexpr int M2L_BATCH = 4;
-__global__ void __launch_bounds__(64) k_m2l_apply(int p, int nreac, const int* __restrict__ ptr,
-                                                  const int* __restrict__ slot, const int* __restrict__ src,
-                                                  const double2* __restrict__ free_tab,
-                                                  const double2* __restrict__ reac_tab,
-                                                  const double2* __restrict__ me, double2* __restrict__ out) {
-  extern __shared__ double2 lds[];
+template <typename RT>
+__global__ void __launch_bounds__(64) k_m2l_apply(int p, const int* __restrict__ ptr, const int* __restrict__ slot,
+                                                  const int* __restrict__ src,
+                                                  const typename C2T<RT>::T* __restrict__ ops,
+                                                  const typename C2T<RT>::T* __restrict__ me,
+                                                  typename C2T<RT>::T* __restrict__ out) {
+  typedef typename C2T<RT>::T V;
+  extern __shared__ unsigned char dyn[];
+  V* T = reinterpret_cast<V*>(dyn);
   const int t = blockIdx.x;
   const int P = 2 * p + 1;
-  const bool isfree = t >= nreac;
-  double2* T = lds;                                    // P*P (reaction) or 4p+1 (free)
-  double2* A = lds + (isfree ? (4 * p + 1) : P * P);   // [M2L_BATCH][P]
-  if (isfree) {
-    const double2* g = free_tab + (int64_t)(t - nreac) * (4 * p + 1);
-    for (int j = threadIdx.x; j <= 4 * p; j += 64) T[j] = g[j];
-  } else {
-    const double2* g = reac_tab + (int64_t)t * P * P;
-    for (int j = threadIdx.x; j < P * P; j += 64) T[j] = g[j];
-  }
+  V* A = T + P * P;  // [M2L_BATCH][P]
+  const V* g = ops + (int64_t)t * P * P;
+  for (int j = threadIdx.x; j < P * P; j += 64) T[j] = g[j];
   const int e0 = ptr[t], e1 = ptr[t + 1];
   for (int e = e0; e < e1; e += M2L_BATCH) {
     const int ne = min(M2L_BATCH, e1 - e);
@@ -364,53 +410,139 @@ __global__ void __launch_bounds__(64) k_m2l_apply(int p, int nreac, const int* _
     __syncthreads();
     if (threadIdx.x < (unsigned)P) {
       const int mrow = threadIdx.x;
-      double re[M2L_BATCH], im[M2L_BATCH];
+      RT re[M2L_BATCH], im[M2L_BATCH];
 #pragma unroll
-      for (int q = 0; q < M2L_BATCH; ++q) re[q] = im[q] = 0.0;
-      if (isfree) {
-        for (int n = 0; n < P; ++n) {
-          const double2 gv = T[n - mrow + 2 * p];
+      for (int q = 0; q < M2L_BATCH; ++q) re[q] = im[q] = RT(0);
+      for (int n = 0; n < P; ++n) {
+        const V tv = T[n * P + mrow];
 #pragma unroll
-          for (int q = 0; q < M2L_BATCH; ++q) {
-            const double2 av = A[q * P + n];
-            re[q] += gv.x * av.x - gv.y * av.y;
-            im[q] += gv.x * av.y + gv.y * av.x;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < M2L_BATCH; ++q) {  // times i/4
-          const double r2 = -0.25 * im[q], i2 = 0.25 * re[q];
-          re[q] = r2;
-          im[q] = i2;
-        }
-      } else {
-        for (int n = 0; n < P; ++n) {
-          const double2 tv = T[n * P + mrow];
-#pragma unroll
-          for (int q = 0; q < M2L_BATCH; ++q) {
-            const double2 av = A[q * P + n];
-            re[q] += tv.x * av.x - tv.y * av.y;
-            im[q] += tv.x * av.y + tv.y * av.x;
-          }
-        }
+        for (int q = 0; q < M2L_BATCH; ++q) cmac(re[q], im[q], tv, A[q * P + n]);
       }
-      for (int q = 0; q < ne; ++q) out[(int64_t)slot[e + q] * P + mrow] = make_double2(re[q], im[q]);
+      for (int q = 0; q < ne; ++q) out[(int64_t)slot[e + q] * P + mrow] = mk<V>(re[q], im[q]);
     }
   }
 }
 
-// LE of each target box = sum of its entries' slots.
+template <typename RT>
 __global__ void __launch_bounds__(64) k_m2l_reduce(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
-                                                   const double2* __restrict__ out, double2* __restrict__ le) {
+                                                   const typename C2T<RT>::T* __restrict__ out,
+                                                   typename C2T<RT>::T* __restrict__ le) {
+  typedef typename C2T<RT>::T V;
   const int P = 2 * p + 1;
   if (threadIdx.x >= (unsigned)P) return;
-  double re = 0.0, im = 0.0;
+  RT re = 0, im = 0;
   for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
-    const double2 v = out[(int64_t)e * P + threadIdx.x];
+    const V v = out[(int64_t)e * P + threadIdx.x];
     re += v.x;
     im += v.y;
   }
-  le[(int64_t)tgts[blockIdx.x] * P + threadIdx.x] = make_double2(re, im);
+  le[(int64_t)tgts[blockIdx.x] * P + threadIdx.x] = mk<V>(re, im);
+}
+
+// L2L: child bt += Op parent bt, for every box of one level.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_l2l(int p, int R, int nlev, int first, const BoxDev* __restrict__ boxes,
+                                             const int* __restrict__ tree_layer,
+                                             const typename C2T<RT>::T* __restrict__ ops,
+                                             typename C2T<RT>::T* __restrict__ le) {
+  typedef typename C2T<RT>::T V;
+  const int b = first + blockIdx.x;
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1, PR = P * R;
+  extern __shared__ unsigned char dyn[];
+  V* a = reinterpret_cast<V*>(dyn);
+  for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) a[idx] = le[(int64_t)B.parent * PR + idx];
+  __syncthreads();
+  RT are[MO], aim[MO];
+  acc_zero(are, aim);
+  const V* Op = ops + ((int64_t)((tree_layer[B.tree] * nlev + B.level) * 4 + B.pos)) * P * P;
+  op_apply<RT>(P, R, Op, a, are, aim);
+  V* out = le + (int64_t)b * PR;
+#pragma unroll
+  for (int i = 0; i < MO; ++i) {
+    const int idx = threadIdx.x + i * blockDim.x;
+    if (idx < PR) {
+      const V o = out[idx];
+      out[idx] = mk<V>(o.x + are[i], o.y + aim[i]);
+    }
+  }
+}
+
+// L2P: y_e (=/+=) sum_m (bt_m / sig_m) J_m(k rho) e^{i m theta} for the points of each leaf.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumulate, const int* __restrict__ leaves,
+                                             const BoxDev* __restrict__ boxes, const int* __restrict__ tree_layer,
+                                             const double* __restrict__ sig, const int* __restrict__ pt_elem,
+                                             const double2* __restrict__ pt_xh,
+                                             const typename C2T<RT>::T* __restrict__ le, int N,
+                                             typename C2T<RT>::T* __restrict__ y) {
+  typedef typename C2T<RT>::T V;
+  const int b = leaves[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1, PR = P * R;
+  const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
+  __shared__ RT js[PCH][MAXP + 1];
+  __shared__ V cs[PCH][MAXP + 1];
+  extern __shared__ unsigned char dyn[];
+  V* L = reinterpret_cast<V*>(dyn);  // [P][R]
+  for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) L[idx] = le[(int64_t)b * PR + idx];
+  for (int s0 = 0; s0 < B.npt; s0 += PCH) {
+    const int cnt = min(PCH, B.npt - s0);
+    __syncthreads();
+    if (threadIdx.x < (unsigned)cnt) {
+      const double2 xh = pt_xh[B.pt0 + s0 + threadIdx.x];
+      point_basis<RT>(B.k, xh.x - B.cx, xh.y - B.ch, p, sg, 1.0, js[threadIdx.x], cs[threadIdx.x]);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cnt * R; idx += blockDim.x) {
+      const int j = idx / R, r = idx - j * R;
+      const V l0 = L[p * R + r];
+      RT re = js[j][0] * l0.x, im = js[j][0] * l0.y;
+      for (int m = 1; m <= p; ++m) {
+        const V c = cs[j][m];
+        const RT jv = js[j][m];
+        const RT jn = (m & 1) ? -jv : jv;  // J_{-m} = (-1)^m J_m
+        const V lp = L[(p + m) * R + r], ln = L[(p - m) * R + r];
+        // lp e^{i m th} J_m + ln e^{-i m th} J_{-m}
+        re += jv * (c.x * lp.x - c.y * lp.y) + jn * (c.x * ln.x + c.y * ln.y);
+        im += jv * (c.x * lp.y + c.y * lp.x) + jn * (c.x * ln.y - c.y * ln.x);
+      }
+      const int e = pt_elem[B.pt0 + s0 + j];
+      V* yp = y + (int64_t)r * N + e;
+      if (accumulate) {
+        const V o = *yp;
+        *yp = mk<V>(o.x + re, o.y + im);
+      } else {
+        *yp = mk<V>(re, im);
+      }
+    }
+  }
+}
+
+// y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __restrict__ ptr,
+                                                  const int* __restrict__ src,
+                                                  const typename C2T<RT>::T* __restrict__ val,
+                                                  const typename C2T<RT>::T* __restrict__ x,
+                                                  typename C2T<RT>::T* __restrict__ y) {
+  typedef typename C2T<RT>::T V;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  for (int r = 0; r < R; ++r) {
+    const V* xr = x + (int64_t)r * N;
+    RT re = 0, im = 0;
+    for (int e = ptr[row] + lane; e < ptr[row + 1]; e += 64) cmac(re, im, val[e], xr[src[e]]);
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_down(re, off, 64);
+      im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) {
+      const V o = y[(int64_t)r * N + row];
+      y[(int64_t)r * N + row] = mk<V>(o.x + re, o.y + im);
+    }
+  }
 }
 
 // ================================================================ host side ==
@@ -610,21 +742,47 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     else F->leaf_T.push_back(b);
   }
 
-  // ---- M2M / L2L operators F_j(child - parent) ---------------------------------
+  // ---- expansion scales and M2M / L2L operators -----------------------------------
+  // sig[layer][level][n] = s^n / n!, s = k w_level / 2.  Child c, parent C,
+  // d = c - C:  M2M  Op[m][n] = (-1)^{m-n} F_{m-n}(d) sig^c_m / sig^C_n,
+  //             L2L  Op[m][n] = sig^c_n F_{m-n}(d) / sig^C_m.
+  const int NL = L + 1;
+  F->sig.assign((size_t)NL * nlev * (p + 1), 0.0);
+  for (int l = 0; l <= L; ++l)
+    for (int lev = 0; lev < nlev; ++lev) {
+      const double sc = 0.5 * m.k[l] * wl(lev);
+      double v = 1.0;
+      for (int n = 0; n <= p; ++n) {
+        F->sig[(size_t)(l * nlev + lev) * (p + 1) + n] = v;
+        v *= sc / (n + 1);
+      }
+    }
+  auto sgv = [&](int l, int lev, int n) { return F->sig[(size_t)(l * nlev + lev) * (p + 1) + std::abs(n)]; };
+  const int P = F->P;
+  const size_t PP = (size_t)P * P;
+  F->n_tree_ops = NL * nlev * 4;
+  std::vector<double2> ops((size_t)2 * F->n_tree_ops * PP, make_double2(0.0, 0.0));
   {
     const int J = 2 * p;
-    F->ftab.assign((size_t)(L + 1) * nlev * 4 * (2 * J + 1), zd(0.0, 0.0));
-    std::vector<zd> buf(2 * J + 1);
+    std::vector<zd> fj(2 * J + 1);
     std::vector<double> jb(J + 1);
     for (int l = 0; l <= L; ++l)
       for (int lev = 1; lev < nlev; ++lev)
         for (int pos = 0; pos < 4; ++pos) {
-          const double d = 0.5 * wl(lev);
-          const double dx = (pos & 1) ? 0.5 * d : -0.5 * d;
-          const double dh = (pos & 2) ? 0.5 * d : -0.5 * d;
-          // child centre - parent centre = (+-w_lev/2, +-w_lev/2)
-          fm::f_seq(m.k[l], 2.0 * dx, 2.0 * dh, J, buf.data(), jb.data());
-          std::copy(buf.begin(), buf.end(), F->ftab.begin() + ((size_t)((l * nlev + lev) * 4 + pos)) * (2 * J + 1));
+          const double q = 0.25 * wl(lev - 1);  // child centre - parent centre = (+-q, +-q)
+          fm::f_seq(m.k[l], (pos & 1) ? q : -q, (pos & 2) ? q : -q, J, fj.data(), jb.data());
+          const size_t o = (size_t)((l * nlev + lev) * 4 + pos);
+          double2* M2 = ops.data() + o * PP;
+          double2* L2 = ops.data() + ((size_t)F->n_tree_ops + o) * PP;
+          for (int mi = -p; mi <= p; ++mi)
+            for (int ni = -p; ni <= p; ++ni) {
+              const zd f = fj[mi - ni + J];
+              const double sm = ((mi - ni) & 1) ? -1.0 : 1.0;
+              const double a = sm * sgv(l, lev, mi) / sgv(l, lev - 1, ni);
+              const double b = sgv(l, lev, ni) / sgv(l, lev - 1, mi);
+              M2[(size_t)(mi + p) * P + (ni + p)] = make_double2(f.re * a, f.im * a);
+              L2[(size_t)(mi + p) * P + (ni + p)] = make_double2(f.re * b, f.im * b);
+            }
         }
   }
 
@@ -640,6 +798,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     F->free_geo.push_back(m.k[layer]);
     F->free_geo.push_back(di * wl(lev));
     F->free_geo.push_back(dj * wl(lev));
+    F->free_lvl.push_back(layer);
+    F->free_lvl.push_back(lev);
     return id;
   };
   auto reac_tab = [&](int tt, int ts, int lev, int di, int jt, int js) {
@@ -651,6 +811,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     F->reac_meta.push_back(T[tt].layer);
     F->reac_meta.push_back(T[ts].layer);
     F->reac_meta.push_back(T[tt].side + 2 * T[ts].side);
+    F->reac_meta.push_back(lev);
     F->reac_geo.push_back(di * wl(lev));
     F->reac_geo.push_back((jt + 0.5) * wl(lev));
     F->reac_geo.push_back((js + 0.5) * wl(lev));
@@ -864,13 +1025,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_near_src, F->near_src, s));
   LM_TRY(up(F->d_rn_ptr, F->rn_ptr, s));
   LM_TRY(up(F->d_rn_src, F->rn_src, s));
-  {
-    std::vector<double2> ft(F->ftab.size());
-    for (size_t i = 0; i < ft.size(); ++i) ft[i] = make_double2(F->ftab[i].re, F->ftab[i].im);
-    LM_TRY(up(F->d_ftab, ft, s));
-    F->tree_layer = tree_layer;
-    LM_TRY(up(F->d_tree_layer, F->tree_layer, s));
-  }
+  F->tree_layer = tree_layer;
+  LM_TRY(up(F->d_tree_layer, F->tree_layer, s));
+  LM_TRY(up(F->d_sig, F->sig, s));
   {
     std::vector<double2> self(N);
     for (int64_t e = 0; e < N; ++e) {
@@ -879,27 +1036,43 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     }
     LM_TRY(up(F->d_self, self, s));
   }
-  // free-space Hankel tables
+  // operators: [M2M | L2L | reaction M2L | free-space M2L], P x P each
   const int nfree = (int)free_id.size(), nreac = (int)reac_id.size();
-  LM_TRY(F->d_free_tab.alloc((size_t)std::max(nfree, 1) * (4 * p + 1) * sizeof(double2)));
-  if (nfree) {
-    DevBuf geo;
-    LM_TRY(up(geo, F->free_geo, s));
-    hipLaunchKernelGGL(k_free_tables, dim3(div_up(nfree, 64)), dim3(64), 0, s, nfree, p, geo.as<double>(),
-                       F->d_free_tab.as<double2>());
-    LM_TRY_HIP(hipGetLastError());
-    LM_TRY_HIP(hipStreamSynchronize(s));
-  }
-  // reaction tables
-  LM_TRY(F->d_reac_tab.alloc((size_t)std::max(nreac, 1) * F->P * F->P * sizeof(double2)));
+  F->op_m2l = 2 * F->n_tree_ops;
+  const int64_t nops = (int64_t)F->op_m2l + nreac + nfree;
+  LM_TRY(F->d_ops64.alloc((size_t)nops * PP * sizeof(double2)));
+  LM_TRY_HIP(hipMemcpyAsync(F->d_ops64.p, ops.data(), ops.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  double2* m2l_ops = F->d_ops64.as<double2>() + (size_t)F->op_m2l * PP;
   if (nreac) {
     DevBuf meta, geo;
     LM_TRY(up(meta, F->reac_meta, s));
     LM_TRY(up(geo, F->reac_geo, s));
-    hipLaunchKernelGGL(k_reac_tables, dim3(nreac), dim3(256), 0, s, m, p, meta.as<int>(), geo.as<double>(),
-                       F->d_reac_tab.as<double2>());
+    hipLaunchKernelGGL(k_reac_tables, dim3(nreac), dim3(256), 0, s, m, p, nlev, meta.as<int>(), geo.as<double>(),
+                       F->d_sig.as<double>(), m2l_ops);
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  if (nfree) {
+    DevBuf geo, lvl;
+    LM_TRY(up(geo, F->free_geo, s));
+    LM_TRY(up(lvl, F->free_lvl, s));
+    hipLaunchKernelGGL(k_free_tables, dim3(nfree), dim3(64), 0, s, p, nlev, geo.as<double>(), lvl.as<int>(),
+                       F->d_sig.as<double>(), m2l_ops + (size_t)nreac * PP);
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  LM_TRY(F->d_ops32.alloc((size_t)nops * PP * sizeof(float2)));
+  hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nops * (int64_t)PP, 256)), dim3(256), 0, s,
+                     nops * (int64_t)PP, F->d_ops64.as<double2>(), F->d_ops32.as<float2>());
+  LM_TRY_HIP(hipGetLastError());
+  {
+    // per M2L entry: operator index into the M2L part
+    std::vector<int> opi(F->m2l_tab.size());
+    for (size_t e = 0; e < opi.size(); ++e) {
+      const int t = F->m2l_tab[e];
+      opi[e] = t >= 0 ? t : nreac + (-t - 1);
+    }
+    LM_TRY(up(F->d_m2l_op, opi, s));
   }
   // near-field matrix values
   const int nrn = (int)F->rn_src.size();
@@ -915,14 +1088,17 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
                        F->d_nm_src.as<int>(), dk.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
                        g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), F->d_nm_val.as<double2>());
     LM_TRY_HIP(hipGetLastError());
+    LM_TRY(F->d_nm_val32.alloc(std::max<int64_t>(nnz, 1) * sizeof(float2)));
+    hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nnz, 256)), dim3(256), 0, s, nnz, F->d_nm_val.as<double2>(),
+                       F->d_nm_val32.as<float2>());
+    LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
   LM_TRY(up(F->d_tm_ptr, F->tm_ptr, s));
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
   LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
-  LM_TRY(F->d_me.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
-  LM_TRY(F->d_le.alloc((size_t)F->n_boxes * F->P * sizeof(double2)));
+  LM_TRY(fmm_reserve(F, 1));
   int64_t nf = 0, nr = 0, npp = 0;
   for (int t : F->m2l_tab) (t < 0 ? nf : nr)++;
   for (size_t t = 0; t < F->near_tgt.size(); ++t)
@@ -941,88 +1117,130 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   return LM_OK;
 }
 
-// Stage timing: when ev != nullptr, ev[2*i], ev[2*i+1] bracket stage i on
-// stream s (0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near-field matrix, 6 unused).
-lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
-                           hipEvent_t* ev);
-
-lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s) {
-  return fmm_matvec_timed(g, precision, n_rhs, xv, yv, s, nullptr);
+// Expansion buffers for r right-hand sides per launch (grown on demand).
+lm_status fmm_reserve(FmmPlan* F, int r) {
+  r = std::min(std::max(r, 1), LM_RCHUNK);
+  if (r <= F->r_cap) return LM_OK;
+  const size_t bytes = (size_t)F->n_boxes * F->P * r * sizeof(double2);
+  LM_TRY(F->d_me.alloc(bytes));
+  LM_TRY(F->d_le.alloc(bytes));
+  F->r_cap = r;
+  return LM_OK;
 }
+
+namespace {
+
+// One matvec of R <= LM_RCHUNK right-hand sides in storage type RT.  When
+// ev != nullptr, ev[2 i], ev[2 i + 1] bracket stage i on stream s (0 P2M,
+// 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near-field matrix, 6 unused).
+template <typename RT>
+lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typename C2T<RT>::T* y, hipStream_t s,
+                       hipEvent_t* ev) {
+  typedef typename C2T<RT>::T V;
+  FmmPlan* F = g->fmm;
+  const int N = (int)g->N, p = F->p, P = F->P, PR = P * R, nlev = F->nlev;
+  const BoxDev* boxes = F->d_boxes.as<BoxDev>();
+  const int* tl = F->d_tree_layer.as<int>();
+  const double* sig = F->d_sig.as<double>();
+  const V* ops = sizeof(RT) == 8 ? (const V*)F->d_ops64.p : (const V*)F->d_ops32.p;
+  const V* nmv = sizeof(RT) == 8 ? (const V*)F->d_nm_val.p : (const V*)F->d_nm_val32.p;
+  const size_t PP = (size_t)P * P;
+  V* me = (V*)F->d_me.p;
+  V* le = (V*)F->d_le.p;
+  const int blk = std::min(256, 64 * (int)div_up(PR, 64));
+  const size_t lds_pr = (size_t)PR * sizeof(V);
+#define LM_STAGE(i, open) \
+  if (ev) LM_TRY_HIP(hipEventRecord(ev[2 * (i) + ((open) ? 0 : 1)], s))
+  LM_STAGE(0, 1);
+  // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
+  const std::vector<int>* leaves[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
+  const DevBuf* dleaves[3] = {&F->d_leaf_free, &F->d_leaf_B, &F->d_leaf_T};
+  for (int c = 0; c < 3; ++c)
+    if (!leaves[c]->empty())
+      hipLaunchKernelGGL(k_p2m<RT>, dim3(leaves[c]->size()), dim3(blk), (size_t)PCH * R * sizeof(V), s, p, R, nlev,
+                         dleaves[c]->as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
+                         g->d_w.as<double>(), x, N, me);
+  LM_STAGE(0, 0);
+  LM_STAGE(1, 1);
+  // M2M, finest parents first
+  for (int l = nlev - 2; l >= 0; --l) {
+    const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
+    if (n)
+      hipLaunchKernelGGL(k_m2m<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev,
+                         F->d_parents.as<int>() + F->parents_ptr[l], boxes, F->d_children.as<int>(), tl, ops, me);
+  }
+  LM_STAGE(1, 0);
+  // M2L (every level at once); boxes without a list start from zero
+  LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * PR * sizeof(V), s));
+  LM_STAGE(2, 1);
+  if (!F->m2l_tgt.empty()) {
+    const V* mops = ops + (size_t)F->op_m2l * PP;
+    const size_t lds = (PP + M2L_BATCH * P) * sizeof(V);
+    if (R == 1 && lds <= 65536) {
+      const int ntab = F->n_reac_tab + F->n_free_tab;
+      V* out = (V*)F->d_m2l_out.p;
+      hipLaunchKernelGGL(k_m2l_apply<RT>, dim3(ntab), dim3(64), lds, s, p, F->d_tm_ptr.as<int>(),
+                         F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), mops, me, out);
+      hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(64), 0, s, p, F->d_m2l_tgt.as<int>(),
+                         F->d_m2l_ptr.as<int>(), out, le);
+    } else {
+      hipLaunchKernelGGL(k_m2l_target<RT>, dim3(F->m2l_tgt.size()), dim3(blk), lds_pr, s, p, R,
+                         F->d_m2l_tgt.as<int>(), F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(),
+                         F->d_m2l_op.as<int>(), mops, me, le);
+    }
+  }
+  LM_STAGE(2, 0);
+  LM_STAGE(3, 1);
+  // L2L, coarse to fine
+  for (int l = 1; l < nlev; ++l) {
+    const int n = F->level_ptr[l + 1] - F->level_ptr[l];
+    if (n)
+      hipLaunchKernelGGL(k_l2l<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev, F->level_ptr[l], boxes, tl,
+                         ops + (size_t)F->n_tree_ops * PP, le);
+  }
+  LM_STAGE(3, 0);
+  LM_STAGE(4, 1);
+  // L2P: free trees write, side trees accumulate (each element once per launch)
+  for (int c = 0; c < 3; ++c)
+    if (!leaves[c]->empty())
+      hipLaunchKernelGGL(k_l2p<RT>, dim3(leaves[c]->size()), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0,
+                         dleaves[c]->as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le,
+                         N, y);
+  LM_STAGE(4, 0);
+  LM_STAGE(5, 1);
+  // near fields and self terms
+  hipLaunchKernelGGL(k_near_csr<RT>, dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
+                     F->d_nm_src.as<int>(), nmv, x, y);
+  LM_STAGE(5, 0);
+  LM_STAGE(6, 1);
+  LM_STAGE(6, 0);
+#undef LM_STAGE
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+}  // namespace
 
 lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
                            hipEvent_t* ev) {
   FmmPlan* F = g->fmm;
   LM_CHECK(F, LM_EINTERNAL, "no FMM plan");
-  LM_CHECK(precision == LM_FP64, LM_EINVAL, "the FMM matvec supports LM_FP64 only in this build");
-  const int N = (int)g->N, p = F->p, P = F->P;
-  const BoxDev* boxes = F->d_boxes.as<BoxDev>();
-  const int* tl = F->d_tree_layer.as<int>();
-  for (int r = 0; r < n_rhs; ++r) {
-    const double2* x = (const double2*)xv + (int64_t)r * N;
-    double2* y = (double2*)yv + (int64_t)r * N;
-    double2* me = F->d_me.as<double2>();
-    double2* le = F->d_le.as<double2>();
-#define LM_STAGE(i, open)                                             \
-  if (ev && r == 0) LM_TRY_HIP(hipEventRecord(ev[2 * (i) + ((open) ? 0 : 1)], s))
-    LM_STAGE(0, 1);
-    // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
-    const std::vector<int>* leaves[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
-    const DevBuf* dleaves[3] = {&F->d_leaf_free, &F->d_leaf_B, &F->d_leaf_T};
-    for (int c = 0; c < 3; ++c)
-      if (!leaves[c]->empty())
-        hipLaunchKernelGGL(k_p2m, dim3(leaves[c]->size()), dim3(WG), 0, s, p, dleaves[c]->as<int>(), boxes,
-                           F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), g->d_w.as<double>(), x, me);
-    LM_STAGE(0, 0);
-    LM_STAGE(1, 1);
-    // M2M, finest parents first
-    for (int l = F->nlev - 2; l >= 0; --l) {
-      const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
-      if (n)
-        hipLaunchKernelGGL(k_m2m, dim3(n), dim3(WG), 0, s, p, F->nlev, F->d_parents.as<int>() + F->parents_ptr[l],
-                           boxes, F->d_children.as<int>(), tl, F->d_ftab.as<double2>(), me);
+  const int64_t N = g->N;
+  LM_TRY(fmm_reserve(F, n_rhs));
+  for (int r0 = 0; r0 < n_rhs; r0 += LM_RCHUNK) {
+    const int R = std::min(LM_RCHUNK, n_rhs - r0);
+    hipEvent_t* e = r0 == 0 ? ev : nullptr;
+    if (precision == LM_FP64) {
+      LM_TRY(matvec_chunk<double>(g, R, (const double2*)xv + r0 * N, (double2*)yv + r0 * N, s, e));
+    } else {
+      LM_TRY(matvec_chunk<float>(g, R, (const float2*)xv + r0 * N, (float2*)yv + r0 * N, s, e));
     }
-    LM_STAGE(1, 0);
-    // M2L (every level at once); boxes without a list start from zero
-    LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * P * sizeof(double2), s));
-    LM_STAGE(2, 1);
-    if (!F->m2l_tgt.empty()) {
-      const int ntab = F->n_reac_tab + F->n_free_tab;
-      const size_t lds = (size_t)(std::max(P * P, 4 * p + 1) + M2L_BATCH * P) * sizeof(double2);
-      hipLaunchKernelGGL(k_m2l_apply, dim3(ntab), dim3(64), lds, s, p, F->n_reac_tab, F->d_tm_ptr.as<int>(),
-                         F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), F->d_free_tab.as<double2>(),
-                         F->d_reac_tab.as<double2>(), me, F->d_m2l_out.as<double2>());
-      hipLaunchKernelGGL(k_m2l_reduce, dim3(F->m2l_tgt.size()), dim3(64), 0, s, p, F->d_m2l_tgt.as<int>(),
-                         F->d_m2l_ptr.as<int>(), F->d_m2l_out.as<double2>(), le);
-    }
-    LM_STAGE(2, 0);
-    LM_STAGE(3, 1);
-    // L2L, coarse to fine
-    for (int l = 1; l < F->nlev; ++l) {
-      const int n = F->level_ptr[l + 1] - F->level_ptr[l];
-      if (n)
-        hipLaunchKernelGGL(k_l2l, dim3(n), dim3(WG), 0, s, p, F->nlev, F->level_ptr[l], boxes, tl,
-                           F->d_ftab.as<double2>(), le);
-    }
-    LM_STAGE(3, 0);
-    LM_STAGE(4, 1);
-    // L2P: free trees write, side trees accumulate (each element once per launch)
-    for (int c = 0; c < 3; ++c)
-      if (!leaves[c]->empty())
-        hipLaunchKernelGGL(k_l2p, dim3(leaves[c]->size()), dim3(WG), 0, s, p, c > 0 ? 1 : 0, dleaves[c]->as<int>(),
-                           boxes, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, y);
-    LM_STAGE(4, 0);
-    LM_STAGE(5, 1);
-    // near fields and self terms
-    hipLaunchKernelGGL(k_near_csr, dim3(div_up(N, 4)), dim3(256), 0, s, N, F->d_nm_ptr.as<int>(),
-                       F->d_nm_src.as<int>(), F->d_nm_val.as<double2>(), x, y);
-    LM_STAGE(5, 0);
-    LM_STAGE(6, 1);
-    LM_STAGE(6, 0);
-#undef LM_STAGE
-    LM_TRY_HIP(hipGetLastError());
   }
   return LM_OK;
+}
+
+lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s) {
+  return fmm_matvec_timed(g, precision, n_rhs, xv, yv, s, nullptr);
 }
 
 // Average per-stage durations (ms) over reps matvecs, measured with HIP events

@@ -28,7 +28,8 @@ struct FmmPlan {
   // M2L lists
   std::vector<int> m2l_tgt, m2l_ptr, m2l_src, m2l_tab;  // tab >= 0 reaction table, < 0: free table -(id+1)
   std::vector<double> free_geo;   // (k, dx, dh) per free table
-  std::vector<int> reac_meta;     // (lt, ls, comp) per reaction table
+  std::vector<int> free_lvl;      // (layer, level) per free table
+  std::vector<int> reac_meta;     // (lt, ls, comp, level) per reaction table
   std::vector<double> reac_geo;   // (dx, ht, hs)
   // free near field
   std::vector<int> near_tgt, near_ptr, near_src;
@@ -41,8 +42,10 @@ struct FmmPlan {
   // M2L entries grouped by operator (reaction tables, then free classes)
   std::vector<int> tm_ptr, tm_slot, tm_src;
   int n_reac_tab = 0, n_free_tab = 0;
-  // M2M / L2L operators F_j(d), d = child centre - parent centre; [layer][level][pos][4p+1]
-  std::vector<zd> ftab;
+  // expansion scales sig[layer][level][0..p]; translation operators, P x P
+  // each, column-major by input: [M2M: layer, level, pos][L2L: same][M2L]
+  std::vector<double> sig;
+  int n_tree_ops = 0, op_m2l = 0;
   std::vector<int> tree_layer;
   int n_layers = 0;
   int64_t stats[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -50,20 +53,23 @@ struct FmmPlan {
   DevBuf d_boxes, d_children, d_pt_elem, d_pt_xh;
   DevBuf d_leaf_free, d_leaf_B, d_leaf_T, d_parents;
   DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
-  DevBuf d_free_tab, d_reac_tab, d_ftab;
+  DevBuf d_sig, d_ops64, d_ops32, d_m2l_op;
   DevBuf d_near_tgt, d_near_ptr, d_near_src;
   DevBuf d_rn_ptr, d_rn_src, d_rn_val;
   DevBuf d_self, d_me, d_le, d_tree_layer;
-  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
+  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
+  int r_cap = 0;  // right-hand sides the expansion buffers hold
   int64_t bytes() const {
     const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
-                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_free_tab, &d_reac_tab,
-                           &d_ftab, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
+                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64, &d_ops32,
+                           &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
                            &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
-                           &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
+                           &d_nm_val32, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;
   }
 };
 
+// Grow the expansion buffers to hold r right-hand sides per launch.
+lm_status fmm_reserve(FmmPlan* F, int r);
