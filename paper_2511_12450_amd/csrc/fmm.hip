@@ -37,6 +37,12 @@
 #include "fmm_plan.hpp"
 
 namespace {
+// Top-level box width times the largest wavenumber.  Level 0 interacts all
+// pairs of non-adjacent boxes, so a wide top level keeps that quadratic list
+// short; the box radius k w / sqrt(2) = 5.7 stays well inside the range where
+// order p = 20 expansions converge to FP64 accuracy.
+constexpr double LM_TOP_KW = 8.0;
+constexpr int LM_PTS_ITEM = 64;  // points per P2M / L2P work item
 constexpr int WG = 64;
 constexpr int MAXPP = 2 * MAXP + 1;
 inline int64_t bkey(int i, int j) { return ((int64_t)i << 32) | (uint32_t)j; }
@@ -196,16 +202,18 @@ __global__ void k_c128_to_c64_fmm(int64_t n, const double2* __restrict__ a, floa
 
 constexpr int LM_RCHUNK = 64;
 constexpr int MO = 16;          // (2p+1) R <= MO * 256 for p <= 31, R <= 64
-constexpr int PCH = 32;         // points per chunk in P2M / L2P
 
 template <typename RT> struct C2T;
 template <> struct C2T<double> { typedef double2 T; };
 template <> struct C2T<float> { typedef float2 T; };
 
+// re + i im += a b as four chained FMAs.
 template <typename RT, typename V>
 __device__ __forceinline__ void cmac(RT& re, RT& im, V a, V b) {
-  re += a.x * b.x - a.y * b.y;
-  im += a.x * b.y + a.y * b.x;
+  re = fma(a.x, b.x, re);
+  re = fma(-a.y, b.y, re);
+  im = fma(a.x, b.y, im);
+  im = fma(a.y, b.x, im);
 }
 
 template <typename V, typename RT>
@@ -233,16 +241,21 @@ __device__ __forceinline__ void point_basis(double k, double dx, double dh, int 
 }
 
 // P2M: at_n = sum_s q_s J_n(k rho_s) e^{-i n theta_s} / sig_n, q_s = |Gamma_s| x_s.
-template <typename RT>
-__global__ void __launch_bounds__(256) k_p2m(int p, int R, int nlev, const int* __restrict__ leaves,
+// Points are taken PCH at a time (64 with one right-hand side, else 32).
+// One workgroup per work item (leaf box, first point, count <= LM_PTS_ITEM);
+// the partial expansions of a leaf's items are summed by k_p2m_reduce.
+template <typename RT, int PCH>
+__global__ void __launch_bounds__(256) k_p2m(int p, int R, int nlev, const int* __restrict__ items,
                                              const BoxDev* __restrict__ boxes, const int* __restrict__ tree_layer,
                                              const double* __restrict__ sig, const int* __restrict__ pt_elem,
                                              const double2* __restrict__ pt_xh, const double* __restrict__ w,
                                              const typename C2T<RT>::T* __restrict__ x, int N,
-                                             typename C2T<RT>::T* __restrict__ me) {
+                                             typename C2T<RT>::T* __restrict__ part) {
   typedef typename C2T<RT>::T V;
-  const int b = leaves[blockIdx.x];
-  const BoxDev B = boxes[b];
+  const int b = items[3 * blockIdx.x];
+  BoxDev B = boxes[b];
+  B.pt0 = items[3 * blockIdx.x + 1];
+  B.npt = items[3 * blockIdx.x + 2];
   const int P = 2 * p + 1, PR = P * R;
   const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
   __shared__ RT js[PCH][MAXP + 1];
@@ -292,7 +305,27 @@ __global__ void __launch_bounds__(256) k_p2m(int p, int R, int nlev, const int* 
 #pragma unroll
   for (int i = 0; i < MO; ++i) {
     const int idx = threadIdx.x + i * blockDim.x;
-    if (idx < PR) me[(int64_t)b * PR + idx] = mk<V>(are[i], aim[i]);
+    if (idx < PR) part[(int64_t)blockIdx.x * PR + idx] = mk<V>(are[i], aim[i]);
+  }
+}
+
+// me[leaf] = sum of the partial expansions of its work items.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_p2m_reduce(int PR, const int* __restrict__ leaves,
+                                                    const int* __restrict__ ptr,
+                                                    const typename C2T<RT>::T* __restrict__ part,
+                                                    typename C2T<RT>::T* __restrict__ me) {
+  typedef typename C2T<RT>::T V;
+  const int i0 = ptr[blockIdx.x], i1 = ptr[blockIdx.x + 1];
+  V* out = me + (int64_t)leaves[blockIdx.x] * PR;
+  for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) {
+    RT re = 0, im = 0;
+    for (int i = i0; i < i1; ++i) {
+      const V v = part[(int64_t)i * PR + idx];
+      re += v.x;
+      im += v.y;
+    }
+    out[idx] = mk<V>(re, im);
   }
 }
 
@@ -309,7 +342,15 @@ __device__ __forceinline__ void op_apply(int P, int R, const typename C2T<RT>::T
       const int o = idx / R, r = idx - o * R;
       RT re = are[i], im = aim[i];
       const typename C2T<RT>::T* op = Op + o;
-      for (int j = 0; j < P; ++j) cmac(re, im, op[(int64_t)j * P], in[j * R + r]);
+      int j = 0;
+      for (; j + 4 <= P; j += 4) {  // four operator loads in flight
+        typename C2T<RT>::T t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = op[(int64_t)(j + u) * P];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cmac(re, im, t[u], in[(j + u) * R + r]);
+      }
+      for (; j < P; ++j) cmac(re, im, op[(int64_t)j * P], in[j * R + r]);
       are[i] = re;
       aim[i] = im;
     }
@@ -382,61 +423,95 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
   acc_store(PR, are, aim, le + (int64_t)tgts[blockIdx.x] * PR);
 }
 
-// M2L, operator-major (one right-hand side): one workgroup per operator keeps
-// it in LDS and applies it to all its entries; results go to the entry slots.
-constexpr int M2L_BATCH = 4;
+// M2L, operator-major (one right-hand side): one wavefront per operator
+// streams its columns from HBM once per batch of M2L_EB entries (lane m holds
+// output row m); the source coefficients are wave-uniform, so they come
+// through scalar loads and every lane does M2L_EB complex FMAs per column
+// load.  Results go to per-entry slots, summed per target by k_m2l_reduce.
+// Operators with many entries are split into work items of at most
+// M2L_ITEM entries (item = operator, first entry, end), so no wavefront runs
+// much longer than the others.
+constexpr int M2L_EB = 8;
+constexpr int M2L_ITEM = 32;
 template <typename RT>
-__global__ void __launch_bounds__(64) k_m2l_apply(int p, const int* __restrict__ ptr, const int* __restrict__ slot,
+__global__ void __launch_bounds__(64) k_m2l_apply(int p, const int* __restrict__ items, const int* __restrict__ slot,
                                                   const int* __restrict__ src,
                                                   const typename C2T<RT>::T* __restrict__ ops,
                                                   const typename C2T<RT>::T* __restrict__ me,
                                                   typename C2T<RT>::T* __restrict__ out) {
   typedef typename C2T<RT>::T V;
-  extern __shared__ unsigned char dyn[];
-  V* T = reinterpret_cast<V*>(dyn);
-  const int t = blockIdx.x;
+  const int t = items[3 * blockIdx.x];
   const int P = 2 * p + 1;
-  V* A = T + P * P;  // [M2L_BATCH][P]
-  const V* g = ops + (int64_t)t * P * P;
-  for (int j = threadIdx.x; j < P * P; j += 64) T[j] = g[j];
-  const int e0 = ptr[t], e1 = ptr[t + 1];
-  for (int e = e0; e < e1; e += M2L_BATCH) {
-    const int ne = min(M2L_BATCH, e1 - e);
-    __syncthreads();
-    for (int j = threadIdx.x; j < ne * P; j += 64) {
-      const int q = j / P, n = j % P;
-      A[q * P + n] = me[(int64_t)src[e + q] * P + n];
+  const int m = threadIdx.x;
+  const bool act = m < P;
+  const V* T = ops + (int64_t)t * P * P + (act ? m : 0);
+  const int e0 = items[3 * blockIdx.x + 1], e1 = items[3 * blockIdx.x + 2];
+  for (int e = e0; e < e1; e += M2L_EB) {
+    const int ne = min(M2L_EB, e1 - e);
+    const V* a[M2L_EB];
+#pragma unroll
+    for (int q = 0; q < M2L_EB; ++q) a[q] = me + (int64_t)src[e + min(q, ne - 1)] * P;
+    RT re[M2L_EB], im[M2L_EB];
+#pragma unroll
+    for (int q = 0; q < M2L_EB; ++q) re[q] = im[q] = RT(0);
+    constexpr int U = sizeof(RT) == 8 ? 2 : 4;  // columns in flight per lane
+    int n = 0;
+    for (; n + U <= P; n += U) {
+      V tv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) tv[u] = T[(int64_t)(n + u) * P];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < M2L_EB; ++q) cmac(re[q], im[q], tv[u], a[q][n + u]);
     }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)P) {
-      const int mrow = threadIdx.x;
-      RT re[M2L_BATCH], im[M2L_BATCH];
+    for (; n < P; ++n) {
+      const V tv = T[(int64_t)n * P];
 #pragma unroll
-      for (int q = 0; q < M2L_BATCH; ++q) re[q] = im[q] = RT(0);
-      for (int n = 0; n < P; ++n) {
-        const V tv = T[n * P + mrow];
+      for (int q = 0; q < M2L_EB; ++q) cmac(re[q], im[q], tv, a[q][n]);
+    }
+    if (act) {
 #pragma unroll
-        for (int q = 0; q < M2L_BATCH; ++q) cmac(re[q], im[q], tv, A[q * P + n]);
-      }
-      for (int q = 0; q < ne; ++q) out[(int64_t)slot[e + q] * P + mrow] = mk<V>(re[q], im[q]);
+      for (int q = 0; q < M2L_EB; ++q)
+        if (q < ne) out[(int64_t)slot[e + q] * P + m] = mk<V>(re[q], im[q]);
     }
   }
 }
 
+// le[target] = sum of its entry slots: four wavefronts per target take every
+// fourth entry (two independent chains each), then combine through LDS.
 template <typename RT>
-__global__ void __launch_bounds__(64) k_m2l_reduce(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
-                                                   const typename C2T<RT>::T* __restrict__ out,
-                                                   typename C2T<RT>::T* __restrict__ le) {
+__global__ void __launch_bounds__(256) k_m2l_reduce(int p, const int* __restrict__ tgts, const int* __restrict__ ptr,
+                                                    const typename C2T<RT>::T* __restrict__ out,
+                                                    typename C2T<RT>::T* __restrict__ le) {
   typedef typename C2T<RT>::T V;
   const int P = 2 * p + 1;
-  if (threadIdx.x >= (unsigned)P) return;
-  RT re = 0, im = 0;
-  for (int e = ptr[blockIdx.x]; e < ptr[blockIdx.x + 1]; ++e) {
-    const V v = out[(int64_t)e * P + threadIdx.x];
-    re += v.x;
-    im += v.y;
+  const int m = threadIdx.x & 63, part = threadIdx.x >> 6;
+  __shared__ RT red[2][4][64];
+  RT r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+  if (m < P) {
+    const int e1 = ptr[blockIdx.x + 1];
+    int e = ptr[blockIdx.x] + part;
+    for (; e + 4 < e1; e += 8) {
+      const V a = out[(int64_t)e * P + m], b = out[(int64_t)(e + 4) * P + m];
+      r0 += a.x;
+      i0 += a.y;
+      r1 += b.x;
+      i1 += b.y;
+    }
+    if (e < e1) {
+      const V a = out[(int64_t)e * P + m];
+      r0 += a.x;
+      i0 += a.y;
+    }
   }
-  le[(int64_t)tgts[blockIdx.x] * P + threadIdx.x] = mk<V>(re, im);
+  red[0][part][m] = r0 + r1;
+  red[1][part][m] = i0 + i1;
+  __syncthreads();
+  if (part == 0 && m < P)
+    le[(int64_t)tgts[blockIdx.x] * P + m] =
+        mk<V>((red[0][0][m] + red[0][1][m]) + (red[0][2][m] + red[0][3][m]),
+              (red[1][0][m] + red[1][1][m]) + (red[1][2][m] + red[1][3][m]));
 }
 
 // L2L: child bt += Op parent bt, for every box of one level.
@@ -469,16 +544,18 @@ __global__ void __launch_bounds__(256) k_l2l(int p, int R, int nlev, int first, 
 }
 
 // L2P: y_e (=/+=) sum_m (bt_m / sig_m) J_m(k rho) e^{i m theta} for the points of each leaf.
-template <typename RT>
-__global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumulate, const int* __restrict__ leaves,
+template <typename RT, int PCH>
+__global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumulate, const int* __restrict__ items,
                                              const BoxDev* __restrict__ boxes, const int* __restrict__ tree_layer,
                                              const double* __restrict__ sig, const int* __restrict__ pt_elem,
                                              const double2* __restrict__ pt_xh,
                                              const typename C2T<RT>::T* __restrict__ le, int N,
                                              typename C2T<RT>::T* __restrict__ y) {
   typedef typename C2T<RT>::T V;
-  const int b = leaves[blockIdx.x];
-  const BoxDev B = boxes[b];
+  const int b = items[3 * blockIdx.x];
+  BoxDev B = boxes[b];
+  B.pt0 = items[3 * blockIdx.x + 1];
+  B.npt = items[3 * blockIdx.x + 2];
   const int P = 2 * p + 1, PR = P * R;
   const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
   __shared__ RT js[PCH][MAXP + 1];
@@ -591,7 +668,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   std::vector<double> wsort(g->w);
   std::nth_element(wsort.begin(), wsort.begin() + N / 2, wsort.end());
   const double hmed = wsort[N / 2];
-  F->w_top = 4.0 / m.kmax;
+  F->w_top = LM_TOP_KW / m.kmax;
   F->x0 = xmin - 1e-7 * (1.0 + std::fabs(xmin)) - 0.5 * hmed;
 
   // trees: free tree per layer (side B, or T for the bottom layer), side trees
@@ -740,6 +817,26 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     if (!t.reac) F->leaf_free.push_back(b);
     else if (t.side == SIDE_B) F->leaf_B.push_back(b);
     else F->leaf_T.push_back(b);
+  }
+  // point work items (leaf, first point, count) per tree class, and the
+  // item ranges of every leaf for the P2M reduction
+  {
+    const std::vector<int>* cls[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
+    F->p2m_ptr.push_back(0);
+    for (int c = 0; c < 3; ++c) {
+      F->item_ptr[c] = (int)F->pt_item.size() / 3;
+      for (int b : *cls[c]) {
+        const BoxDev& B = F->boxes[b];
+        for (int q = 0; q < B.npt; q += LM_PTS_ITEM) {
+          F->pt_item.push_back(b);
+          F->pt_item.push_back(B.pt0 + q);
+          F->pt_item.push_back(std::min(LM_PTS_ITEM, B.npt - q));
+        }
+        F->p2m_leaf.push_back(b);
+        F->p2m_ptr.push_back((int)F->pt_item.size() / 3);
+      }
+    }
+    F->item_ptr[3] = (int)F->pt_item.size() / 3;
   }
 
   // ---- expansion scales and M2M / L2L operators -----------------------------------
@@ -1005,6 +1102,12 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       F->tm_slot[q] = (int)e;
       F->tm_src[q] = F->m2l_src[e];
     }
+    for (int t = 0; t < ntab; ++t)
+      for (int e = F->tm_ptr[t]; e < F->tm_ptr[t + 1]; e += M2L_ITEM) {
+        F->tm_item.push_back(t);
+        F->tm_item.push_back(e);
+        F->tm_item.push_back(std::min(e + M2L_ITEM, F->tm_ptr[t + 1]));
+      }
   }
 
   // ---- upload and device setup ---------------------------------------------------
@@ -1012,9 +1115,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_children, F->children, s));
   LM_TRY(up(F->d_pt_elem, F->pt_elem, s));
   LM_TRY(up(F->d_pt_xh, F->pt_xh, s));
-  LM_TRY(up(F->d_leaf_free, F->leaf_free, s));
-  LM_TRY(up(F->d_leaf_B, F->leaf_B, s));
-  LM_TRY(up(F->d_leaf_T, F->leaf_T, s));
+  LM_TRY(up(F->d_pt_item, F->pt_item, s));
+  LM_TRY(up(F->d_p2m_leaf, F->p2m_leaf, s));
+  LM_TRY(up(F->d_p2m_ptr, F->p2m_ptr, s));
   LM_TRY(up(F->d_parents, F->parents_by_level, s));
   LM_TRY(up(F->d_m2l_tgt, F->m2l_tgt, s));
   LM_TRY(up(F->d_m2l_ptr, F->m2l_ptr, s));
@@ -1095,6 +1198,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
   LM_TRY(up(F->d_tm_ptr, F->tm_ptr, s));
+  LM_TRY(up(F->d_tm_item, F->tm_item, s));
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
   LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
@@ -1124,6 +1228,7 @@ lm_status fmm_reserve(FmmPlan* F, int r) {
   const size_t bytes = (size_t)F->n_boxes * F->P * r * sizeof(double2);
   LM_TRY(F->d_me.alloc(bytes));
   LM_TRY(F->d_le.alloc(bytes));
+  LM_TRY(F->d_p2m_part.alloc((size_t)std::max(F->item_ptr[3], 1) * F->P * r * sizeof(double2)));
   F->r_cap = r;
   return LM_OK;
 }
@@ -1153,13 +1258,20 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   if (ev) LM_TRY_HIP(hipEventRecord(ev[2 * (i) + ((open) ? 0 : 1)], s))
   LM_STAGE(0, 1);
   // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
-  const std::vector<int>* leaves[3] = {&F->leaf_free, &F->leaf_B, &F->leaf_T};
-  const DevBuf* dleaves[3] = {&F->d_leaf_free, &F->d_leaf_B, &F->d_leaf_T};
-  for (int c = 0; c < 3; ++c)
-    if (!leaves[c]->empty())
-      hipLaunchKernelGGL(k_p2m<RT>, dim3(leaves[c]->size()), dim3(blk), (size_t)PCH * R * sizeof(V), s, p, R, nlev,
-                         dleaves[c]->as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
-                         g->d_w.as<double>(), x, N, me);
+  const int n_items = F->item_ptr[3];
+  V* part = (V*)F->d_p2m_part.p;
+  if (n_items) {
+    if (R == 1)
+      hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
+                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
+                         g->d_w.as<double>(), x, N, part);
+    else
+      hipLaunchKernelGGL((k_p2m<RT, 32>), dim3(n_items), dim3(blk), (size_t)32 * R * sizeof(V), s, p, R, nlev,
+                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
+                         g->d_w.as<double>(), x, N, part);
+    hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_leaf.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
+                       F->d_p2m_ptr.as<int>(), part, me);
+  }
   LM_STAGE(0, 0);
   LM_STAGE(1, 1);
   // M2M, finest parents first
@@ -1175,13 +1287,11 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(2, 1);
   if (!F->m2l_tgt.empty()) {
     const V* mops = ops + (size_t)F->op_m2l * PP;
-    const size_t lds = (PP + M2L_BATCH * P) * sizeof(V);
-    if (R == 1 && lds <= 65536) {
-      const int ntab = F->n_reac_tab + F->n_free_tab;
+    if (R == 1) {
       V* out = (V*)F->d_m2l_out.p;
-      hipLaunchKernelGGL(k_m2l_apply<RT>, dim3(ntab), dim3(64), lds, s, p, F->d_tm_ptr.as<int>(),
+      hipLaunchKernelGGL(k_m2l_apply<RT>, dim3(F->tm_item.size() / 3), dim3(64), 0, s, p, F->d_tm_item.as<int>(),
                          F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), mops, me, out);
-      hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(64), 0, s, p, F->d_m2l_tgt.as<int>(),
+      hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, p, F->d_m2l_tgt.as<int>(),
                          F->d_m2l_ptr.as<int>(), out, le);
     } else {
       hipLaunchKernelGGL(k_m2l_target<RT>, dim3(F->m2l_tgt.size()), dim3(blk), lds_pr, s, p, R,
@@ -1201,11 +1311,17 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(3, 0);
   LM_STAGE(4, 1);
   // L2P: free trees write, side trees accumulate (each element once per launch)
-  for (int c = 0; c < 3; ++c)
-    if (!leaves[c]->empty())
-      hipLaunchKernelGGL(k_l2p<RT>, dim3(leaves[c]->size()), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0,
-                         dleaves[c]->as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le,
-                         N, y);
+  for (int c = 0; c < 3; ++c) {
+    const int i0 = F->item_ptr[c], ni = F->item_ptr[c + 1] - i0;
+    if (!ni) continue;
+    const int* it = F->d_pt_item.as<int>() + 3 * i0;
+    if (R == 1)
+      hipLaunchKernelGGL((k_l2p<RT, 64>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0, it, boxes, tl,
+                         sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);
+    else
+      hipLaunchKernelGGL((k_l2p<RT, 32>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0, it, boxes, tl,
+                         sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);
+  }
   LM_STAGE(4, 0);
   LM_STAGE(5, 1);
   // near fields and self terms

@@ -20,6 +20,9 @@ struct FmmPlan {
   std::vector<BoxDev> boxes;
   std::vector<int> level_ptr;     // boxes of level l: ids [level_ptr[l], level_ptr[l+1])
   std::vector<int> leaf_free, leaf_B, leaf_T;  // leaf boxes by tree class
+  std::vector<int> pt_item;       // (leaf, first point, count) work items, by class
+  int item_ptr[4] = {0, 0, 0, 0}; // items of class c: [item_ptr[c], item_ptr[c+1])
+  std::vector<int> p2m_leaf, p2m_ptr;  // every leaf and the range of its items
   std::vector<int> parents_by_level;           // boxes with children, grouped by level
   std::vector<int> parents_ptr;
   std::vector<int> children;
@@ -41,6 +44,7 @@ struct FmmPlan {
   std::vector<int> nm_ptr, nm_src;
   // M2L entries grouped by operator (reaction tables, then free classes)
   std::vector<int> tm_ptr, tm_slot, tm_src;
+  std::vector<int> tm_item;  // (operator, first entry, end) work items
   int n_reac_tab = 0, n_free_tab = 0;
   // expansion scales sig[layer][level][0..p]; translation operators, P x P
   // each, column-major by input: [M2M: layer, level, pos][L2L: same][M2L]
@@ -51,20 +55,20 @@ struct FmmPlan {
   int64_t stats[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   DevBuf d_boxes, d_children, d_pt_elem, d_pt_xh;
-  DevBuf d_leaf_free, d_leaf_B, d_leaf_T, d_parents;
+  DevBuf d_pt_item, d_p2m_leaf, d_p2m_ptr, d_p2m_part, d_parents;
   DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
   DevBuf d_sig, d_ops64, d_ops32, d_m2l_op;
   DevBuf d_near_tgt, d_near_ptr, d_near_src;
   DevBuf d_rn_ptr, d_rn_src, d_rn_val;
   DevBuf d_self, d_me, d_le, d_tree_layer;
-  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
+  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   int64_t bytes() const {
-    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_leaf_free, &d_leaf_B, &d_leaf_T,
+    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_pt_item, &d_p2m_leaf, &d_p2m_ptr, &d_p2m_part,
                            &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64, &d_ops32,
                            &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
                            &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
-                           &d_nm_val32, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
+                           &d_nm_val32, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;
