@@ -423,6 +423,100 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
   acc_store(PR, are, aim, le + (int64_t)tgts[blockIdx.x] * PR);
 }
 
+// M2L with matrix cores (FP32, several right-hand sides): one workgroup
+// (four wavefronts) per target box.  For each list entry the operator T
+// (P x P complex, column-major by input) and the source expansion a
+// (P x R complex) are staged in LDS, and the complex product is formed as the
+// real product of [[Re T, -Im T], [Im T, Re T]] (2P x 2P) with [Re a; Im a]
+// (2P x R) in 16x16x4 FP32 MFMA tiles (16 x 16 output tiles spread over the
+// four wavefronts, FP32 accumulation).
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int MF_TPW = 8;   // output tiles per wavefront: ceil(ceil(2P/16) ceil(R/16) / 4) <= 8
+constexpr int MF_ST = 8;    // staging loads in flight per lane
+// Work item = (target, first entry, end) with at most M2L_ITEM entries; each
+// item leaves a partial local expansion, summed per target by k_p2m_reduce.
+__global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __restrict__ items,
+                                                  const int* __restrict__ src, const int* __restrict__ opi,
+                                                  const float2* __restrict__ ops, const float2* __restrict__ me,
+                                                  float2* __restrict__ part) {
+  const int P = 2 * p + 1, PR = P * R, P2 = 2 * P, PP = P * P, NS = PP + PR;
+  const int MT = (P2 + 15) / 16, NT = (R + 15) / 16, KS = (P2 + 3) / 4, ntile = MT * NT;
+  extern __shared__ unsigned char dyn[];
+  float2* S = reinterpret_cast<float2*>(dyn);  // T [P][P] then a [P][R]
+  const float2* T = S;
+  const float2* A = S + PP;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  // per-tile operand coordinates (fixed for the whole launch)
+  int mrow[MF_TPW], jcol[MF_TPW];
+  bool ire[MF_TPW], ival[MF_TPW], jval[MF_TPW];
+#pragma unroll
+  for (int t = 0; t < MF_TPW; ++t) {
+    const int tile = wv + 4 * t;
+    const int i = 16 * (tile / NT) + l16, j = 16 * (tile % NT) + l16;
+    ival[t] = tile < ntile && i < P2;
+    ire[t] = i < P;
+    mrow[t] = ival[t] ? (ire[t] ? i : i - P) : 0;
+    jval[t] = tile < ntile && j < R;
+    jcol[t] = jval[t] ? j : 0;
+  }
+  v4f acc[MF_TPW];
+#pragma unroll
+  for (int t = 0; t < MF_TPW; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int e = items[3 * blockIdx.x + 1]; e < items[3 * blockIdx.x + 2]; ++e) {
+    const float2* Tg = ops + (int64_t)opi[e] * PP;
+    const float2* Ag = me + (int64_t)src[e] * PR;
+    __syncthreads();
+    for (int base = threadIdx.x; base < NS; base += 256 * MF_ST) {  // MF_ST loads in flight per lane
+      float2 v[MF_ST];
+#pragma unroll
+      for (int u = 0; u < MF_ST; ++u) {
+        const int idx = base + 256 * u;
+        if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
+      }
+#pragma unroll
+      for (int u = 0; u < MF_ST; ++u) {
+        const int idx = base + 256 * u;
+        if (idx < NS) S[idx] = v[u];
+      }
+    }
+    __syncthreads();
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + kq;
+      const bool kv = k < P2, kre = k < P;
+      const int n = kv ? (kre ? k : k - P) : 0;
+      const float2* Tn = T + n * P;
+      const float2* An = A + n * R;
+#pragma unroll
+      for (int t = 0; t < MF_TPW; ++t) {
+        if (wv + 4 * t < ntile) {  // wave-uniform
+          const float2 tv = Tn[mrow[t]];
+          const float2 sv = An[jcol[t]];
+          const float av = (kv && ival[t]) ? (ire[t] ? (kre ? tv.x : -tv.y) : (kre ? tv.y : tv.x)) : 0.f;
+          const float bv = (kv && jval[t]) ? (kre ? sv.x : sv.y) : 0.f;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* out = reinterpret_cast<float*>(part + (int64_t)blockIdx.x * PR);
+#pragma unroll
+  for (int t = 0; t < MF_TPW; ++t) {
+    const int tile = wv + 4 * t;
+    if (tile < ntile) {
+      const int j = 16 * (tile % NT) + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (tile / NT) + 4 * kq + v;
+        if (i < P2 && j < R) {
+          const bool ir = i < P;
+          out[2 * ((ir ? i : i - P) * R + j) + (ir ? 0 : 1)] = acc[t][v];
+        }
+      }
+    }
+  }
+}
+
 // M2L, operator-major (one right-hand side): one wavefront per operator
 // streams its columns from HBM once per batch of M2L_EB entries (lane m holds
 // output row m); the source coefficients are wave-uniform, so they come
@@ -596,7 +690,8 @@ __global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumul
   }
 }
 
-// y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row.
+// y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row;
+// right-hand sides in groups of four share each matrix value and index load.
 template <typename RT>
 __global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __restrict__ ptr,
                                                   const int* __restrict__ src,
@@ -607,17 +702,32 @@ __global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __res
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
-  for (int r = 0; r < R; ++r) {
-    const V* xr = x + (int64_t)r * N;
-    RT re = 0, im = 0;
-    for (int e = ptr[row] + lane; e < ptr[row + 1]; e += 64) cmac(re, im, val[e], xr[src[e]]);
-    for (int off = 32; off > 0; off >>= 1) {
-      re += __shfl_down(re, off, 64);
-      im += __shfl_down(im, off, 64);
+  const int e0 = ptr[row], e1 = ptr[row + 1];
+  for (int g = 0; g < R; g += 4) {
+    RT re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const V a = val[e];
+      const int c = src[e];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (g + u < R) cmac(re[u], im[u], a, x[(int64_t)(g + u) * N + c]);
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (g + u < R)
+        for (int off = 32; off > 0; off >>= 1) {
+          re[u] += __shfl_xor(re[u], off, 64);
+          im[u] += __shfl_xor(im[u], off, 64);
+        }
     if (lane == 0) {
-      const V o = y[(int64_t)r * N + row];
-      y[(int64_t)r * N + row] = mk<V>(o.x + re, o.y + im);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (g + u < R) {
+          V* yp = y + (int64_t)(g + u) * N + row;
+          const V o = *yp;
+          *yp = mk<V>(o.x + re[u], o.y + im[u]);
+        }
+      }
     }
   }
 }
@@ -1102,6 +1212,15 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       F->tm_slot[q] = (int)e;
       F->tm_src[q] = F->m2l_src[e];
     }
+    F->mf_ptr.push_back(0);
+    for (size_t t = 0; t < F->m2l_tgt.size(); ++t) {
+      for (int e = F->m2l_ptr[t]; e < F->m2l_ptr[t + 1]; e += M2L_ITEM) {
+        F->mf_item.push_back((int)t);
+        F->mf_item.push_back(e);
+        F->mf_item.push_back(std::min(e + M2L_ITEM, F->m2l_ptr[t + 1]));
+      }
+      F->mf_ptr.push_back((int)F->mf_item.size() / 3);
+    }
     for (int t = 0; t < ntab; ++t)
       for (int e = F->tm_ptr[t]; e < F->tm_ptr[t + 1]; e += M2L_ITEM) {
         F->tm_item.push_back(t);
@@ -1199,6 +1318,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   }
   LM_TRY(up(F->d_tm_ptr, F->tm_ptr, s));
   LM_TRY(up(F->d_tm_item, F->tm_item, s));
+  LM_TRY(up(F->d_mf_item, F->mf_item, s));
+  LM_TRY(up(F->d_mf_ptr, F->mf_ptr, s));
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
   LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
@@ -1229,6 +1350,7 @@ lm_status fmm_reserve(FmmPlan* F, int r) {
   LM_TRY(F->d_me.alloc(bytes));
   LM_TRY(F->d_le.alloc(bytes));
   LM_TRY(F->d_p2m_part.alloc((size_t)std::max(F->item_ptr[3], 1) * F->P * r * sizeof(double2)));
+  if (r > 1) LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
   F->r_cap = r;
   return LM_OK;
 }
@@ -1293,6 +1415,13 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
                          F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), mops, me, out);
       hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, p, F->d_m2l_tgt.as<int>(),
                          F->d_m2l_ptr.as<int>(), out, le);
+    } else if (sizeof(RT) == 4) {
+      float2* mpart = F->d_mf_part.as<float2>();
+      hipLaunchKernelGGL(k_m2l_mfma, dim3(F->mf_item.size() / 3), dim3(256), (PP + PR) * sizeof(float2), s, p, R,
+                         F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_op.as<int>(), (const float2*)mops,
+                         (const float2*)me, mpart);
+      hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
+                         F->d_mf_ptr.as<int>(), mpart, (float2*)le);
     } else {
       hipLaunchKernelGGL(k_m2l_target<RT>, dim3(F->m2l_tgt.size()), dim3(blk), lds_pr, s, p, R,
                          F->d_m2l_tgt.as<int>(), F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(),

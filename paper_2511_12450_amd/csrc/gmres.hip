@@ -15,58 +15,138 @@
 
 #include "lm_internal.hpp"
 
-// h[r][i] = sum_n conj(V[i][r][n]) w[r][n], i = 0..j  (grid: (j+1) x R)
-__global__ void __launch_bounds__(256) k_dots(int N, int R, const double2* __restrict__ V,
-                                              const double2* __restrict__ w, double2* __restrict__ h, int ldh) {
-  const int i = blockIdx.x, r = blockIdx.y;
-  const double2* v = V + ((int64_t)i * R + r) * N;
-  const double2* x = w + (int64_t)r * N;
-  double a = 0, b = 0;
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {
-    const double2 p = v[n], q = x[n];
-    a += p.x * q.x + p.y * q.y;
-    b += p.x * q.y - p.y * q.x;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-  }
-  __shared__ double red[2][4];
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = a;
-    red[1][threadIdx.x >> 6] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) h[(int64_t)r * ldh + i] = make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
-                                                             red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+// Gram-Schmidt passes stream the basis V[i][r][n] from HBM: every kernel is
+// element-parallel over n (grid (ceil(N / GS_SLICE), R)), keeps GS_UNROLL
+// basis loads in flight per lane and leaves one partial sum per wavefront;
+// a small second kernel adds the partials.
+constexpr int GS_UNROLL = 8;
+constexpr int GS_EPT = 4;                 // elements per thread in the dot kernel
+constexpr int GS_SLICE = 256 * GS_EPT;    // elements per workgroup in the dot kernel
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-// w[r] -= sum_{i<=j} V[i][r] h[r][i]
-__global__ void k_update(int N, int R, int j, const double2* __restrict__ V, double2* __restrict__ w,
-                         const double2* __restrict__ h, int ldh) {
+// part[(r ldh + i) nw + wave] = sum over the wave's elements of conj(V[i][r][n]) w[r][n]
+// Basis vectors [GS_IBLK z, GS_IBLK (z + 1)) for grid index z.
+constexpr int GS_IBLK = 64;
+__global__ void __launch_bounds__(256) k_dots_part(int N, int R, int cnt, const double2* __restrict__ V,
+                                                   const double2* __restrict__ w, double2* __restrict__ part,
+                                                   int ldh, int nw) {
+  const int r = blockIdx.y;
+  const int ib = blockIdx.z * GS_IBLK;
+  cnt = min(cnt, ib + GS_IBLK);
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t stride = (int64_t)R * N;
+  double2 x[GS_EPT];
+  int64_t off[GS_EPT];
+  bool ok[GS_EPT];
+#pragma unroll
+  for (int e = 0; e < GS_EPT; ++e) {
+    const int n = blockIdx.x * GS_SLICE + threadIdx.x + 256 * e;
+    ok[e] = n < N;
+    off[e] = (int64_t)r * N + (ok[e] ? n : 0);
+    x[e] = ok[e] ? w[off[e]] : make_double2(0.0, 0.0);
+  }
+  for (int i0 = ib; i0 < cnt; i0 += GS_UNROLL) {
+    double re[GS_UNROLL], im[GS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < GS_UNROLL; ++u) re[u] = im[u] = 0.0;
+#pragma unroll
+    for (int e = 0; e < GS_EPT; ++e) {
+      double2 a[GS_UNROLL];
+#pragma unroll
+      for (int u = 0; u < GS_UNROLL; ++u)
+        a[u] = (i0 + u < cnt) ? V[(int64_t)(i0 + u) * stride + off[e]] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < GS_UNROLL; ++u) {
+        const double2 b = ok[e] ? a[u] : make_double2(0.0, 0.0);
+        re[u] = fma(b.x, x[e].x, re[u]);
+        re[u] = fma(b.y, x[e].y, re[u]);
+        im[u] = fma(b.x, x[e].y, im[u]);
+        im[u] = fma(-b.y, x[e].x, im[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GS_UNROLL; ++u) {
+      re[u] = wave_sum(re[u]);
+      im[u] = wave_sum(im[u]);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int u = 0; u < GS_UNROLL; ++u)
+        if (i0 + u < cnt) part[((int64_t)r * ldh + i0 + u) * nw + wv] = make_double2(re[u], im[u]);
+    }
+  }
+}
+
+// h[r ldh + i] = sum_k part[(r ldh + i) nw + k]   (grid (cnt, R), one wavefront each)
+__global__ void __launch_bounds__(64) k_dots_final(int nw, const double2* __restrict__ part, int ldh,
+                                                   double2* __restrict__ h) {
+  const int64_t row = (int64_t)blockIdx.y * ldh + blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int k = threadIdx.x; k < nw; k += 64) {
+    const double2 v = part[row * nw + k];
+    re += v.x;
+    im += v.y;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (threadIdx.x == 0) h[row] = make_double2(re, im);
+}
+
+// w[r] -= sum_{i < cnt} V[i][r] h[r][i]; with nrm_part, also the wave partials of |w[r]|^2.
+__global__ void __launch_bounds__(256) k_update(int N, int R, int cnt, const double2* __restrict__ V,
+                                                double2* __restrict__ w, const double2* __restrict__ h, int ldh,
+                                                double* __restrict__ nrm_part, int nw) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
-  if (n >= N) return;
-  double2 acc = w[(int64_t)r * N + n];
-  for (int i = 0; i <= j; ++i) {
-    const double2 c = h[(int64_t)r * ldh + i];
-    const double2 v = V[((int64_t)i * R + r) * N + n];
-    acc.x -= c.x * v.x - c.y * v.y;
-    acc.y -= c.x * v.y + c.y * v.x;
+  const bool ok = n < N;
+  const int64_t o = (int64_t)r * N + (ok ? n : 0);
+  const int64_t stride = (int64_t)R * N;
+  const double2* hr = h + (int64_t)r * ldh;
+  double2 acc = ok ? w[o] : make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < cnt; i0 += GS_UNROLL) {
+    double2 v[GS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < GS_UNROLL; ++u) v[u] = (i0 + u < cnt) ? V[(int64_t)(i0 + u) * stride + o] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < GS_UNROLL; ++u) {
+      if (i0 + u < cnt) {
+        const double2 c = hr[i0 + u];
+        acc.x = fma(-c.x, v[u].x, acc.x);
+        acc.x = fma(c.y, v[u].y, acc.x);
+        acc.y = fma(-c.x, v[u].y, acc.y);
+        acc.y = fma(-c.y, v[u].x, acc.y);
+      }
+    }
   }
-  w[(int64_t)r * N + n] = acc;
+  if (ok) w[o] = acc;
+  if (nrm_part) {
+    const double q = wave_sum(ok ? acc.x * acc.x + acc.y * acc.y : 0.0);
+    if ((threadIdx.x & 63) == 0) nrm_part[(int64_t)r * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = q;
+  }
 }
 
-// nrm[r] = ||w_r||^2
-__global__ void __launch_bounds__(256) k_norm2(int N, const double2* __restrict__ w, double* __restrict__ nrm) {
-  const int r = blockIdx.x;
-  const double2* x = w + (int64_t)r * N;
-  double a = 0;
-  for (int n = threadIdx.x; n < N; n += blockDim.x) a += x[n].x * x[n].x + x[n].y * x[n].y;
-  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-  __shared__ double red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) nrm[r] = red[0] + red[1] + red[2] + red[3];
+// Wave partials of |w[r]|^2 (grid (ceil(N / 256), R)).
+__global__ void __launch_bounds__(256) k_norm_part(int N, const double2* __restrict__ w, double* __restrict__ part,
+                                                   int nw) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  double q = 0.0;
+  if (n < N) {
+    const double2 v = w[(int64_t)r * N + n];
+    q = v.x * v.x + v.y * v.y;
+  }
+  q = wave_sum(q);
+  if ((threadIdx.x & 63) == 0) part[(int64_t)r * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = q;
+}
+
+// nrm[r] = sum_k part[r nw + k]   (grid R, one wavefront each)
+__global__ void __launch_bounds__(64) k_norm_final(int nw, const double* __restrict__ part, double* __restrict__ nrm) {
+  double q = 0.0;
+  for (int k = threadIdx.x; k < nw; k += 64) q += part[(int64_t)blockIdx.x * nw + k];
+  q = wave_sum(q);
+  if (threadIdx.x == 0) nrm[blockIdx.x] = q;
 }
 
 // out[r] = in[r] * scale[r]
@@ -114,7 +194,7 @@ __global__ void k_c64_to_c128(int64_t n, const float2* __restrict__ a, double2* 
 namespace {
 
 struct Work {
-  DevBuf V, w, z, h, y, nrm, scale, x32, y32, mz;
+  DevBuf V, w, z, h, y, nrm, scale, x32, y32, mz, dpart, npart;
   std::vector<double2> hh;
 };
 
@@ -124,7 +204,7 @@ lm_status apply_KM(lm_geom_s* g, int precision, int R, const double2* x, double2
   const int64_t N = g->N, n = (int64_t)R * N;
   const double2* xin = x;
   if (use_pre) {
-    LM_TRY(precond_apply(g, R, x, wk.mz.p, s));
+    LM_TRY(precond_apply(g, precision, R, x, wk.mz.p, s));
     xin = wk.mz.as<double2>();
   }
   if (precision == LM_FP64) return geom_matvec(g, precision, R, xin, y, s);
@@ -158,16 +238,33 @@ lm_status gmres_run(lm_geom_s* g, int precision, int R, const void* g_dev, const
   }
   if (use_pre) LM_TRY(wk.mz.alloc(n * sizeof(double2)));
   double2* V = wk.V.as<double2>();
+  const int nw_d = 4 * (int)div_up(N, GS_SLICE), nw_u = 4 * (int)div_up(N, 256);
+  LM_TRY(wk.dpart.alloc((size_t)R * (m + 1) * nw_d * sizeof(double2)));
+  LM_TRY(wk.npart.alloc((size_t)R * nw_u * sizeof(double)));
+  const dim3 gD(div_up(N, GS_SLICE), R);
+  auto norm2 = [&](const double2* v) {
+    hipLaunchKernelGGL(k_norm_part, dim3(div_up(N, 256), R), dim3(256), 0, s, (int)N, v, wk.npart.as<double>(), nw_u);
+    hipLaunchKernelGGL(k_norm_final, dim3(R), dim3(64), 0, s, nw_u, wk.npart.as<double>(), wk.nrm.as<double>());
+  };
   double2* w = wk.w.as<double2>();
   double2* h1 = wk.h.as<double2>();
   double2* h2 = h1 + (size_t)R * (m + 1);
   const int ldh = m + 1;
   const dim3 gN(div_up(N, 256), R), b256(256);
+  auto gs_pass = [&](int cnt, double2* h, bool with_norm) {
+    hipLaunchKernelGGL(k_dots_part, dim3(gD.x, R, div_up(cnt, GS_IBLK)), b256, 0, s, (int)N, R, cnt, V, w,
+                       wk.dpart.as<double2>(), ldh, nw_d);
+    hipLaunchKernelGGL(k_dots_final, dim3(cnt, R), dim3(64), 0, s, nw_d, wk.dpart.as<double2>(), ldh, h);
+    hipLaunchKernelGGL(k_update, gN, b256, 0, s, (int)N, R, cnt, V, w, h, ldh,
+                       with_norm ? wk.npart.as<double>() : nullptr, nw_u);
+    if (with_norm)
+      hipLaunchKernelGGL(k_norm_final, dim3(R), dim3(64), 0, s, nw_u, wk.npart.as<double>(), wk.nrm.as<double>());
+  };
 
   LM_TRY_HIP(hipMemsetAsync(phi, 0, n * sizeof(double2), s));
   // ||g_r||
   std::vector<double> gnorm(R), nrm_h(R), scale_h(R);
-  hipLaunchKernelGGL(k_norm2, dim3(R), b256, 0, s, (int)N, gv, wk.nrm.as<double>());
+  norm2(gv);
   LM_TRY_HIP(hipMemcpyAsync(gnorm.data(), wk.nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
   LM_TRY_HIP(hipStreamSynchronize(s));
   for (auto& v : gnorm) v = std::sqrt(v);
@@ -194,7 +291,7 @@ lm_status gmres_run(lm_geom_s* g, int precision, int R, const void* g_dev, const
       LM_TRY(apply_KM(g, precision, R, wk.z.as<double2>(), w, use_pre, wk, s));  // z holds phi_hat (see below)
       hipLaunchKernelGGL(k_axpby, dim3(div_up(n, 256)), b256, 0, s, n, gv, -1.0, w, w);
     }
-    hipLaunchKernelGGL(k_norm2, dim3(R), b256, 0, s, (int)N, w, wk.nrm.as<double>());
+    norm2(w);
     LM_TRY_HIP(hipMemcpyAsync(nrm_h.data(), wk.nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
     LM_TRY_HIP(hipStreamSynchronize(s));
     std::vector<double> beta(R);
@@ -217,11 +314,8 @@ lm_status gmres_run(lm_geom_s* g, int precision, int R, const void* g_dev, const
       double2* Vj = V + (size_t)j * n;
       LM_TRY(apply_KM(g, precision, R, Vj, w, use_pre, wk, s));
       // CGS2
-      hipLaunchKernelGGL(k_dots, dim3(j + 1, R), b256, 0, s, (int)N, R, V, w, h1, ldh);
-      hipLaunchKernelGGL(k_update, gN, b256, 0, s, (int)N, R, j, V, w, h1, ldh);
-      hipLaunchKernelGGL(k_dots, dim3(j + 1, R), b256, 0, s, (int)N, R, V, w, h2, ldh);
-      hipLaunchKernelGGL(k_update, gN, b256, 0, s, (int)N, R, j, V, w, h2, ldh);
-      hipLaunchKernelGGL(k_norm2, dim3(R), b256, 0, s, (int)N, w, wk.nrm.as<double>());
+      gs_pass(j + 1, h1, false);
+      gs_pass(j + 1, h2, true);
       LM_TRY_HIP(hipGetLastError());
       LM_TRY_HIP(hipMemcpyAsync(hbuf.data(), h1, (size_t)2 * R * (m + 1) * sizeof(double2), hipMemcpyDeviceToHost, s));
       LM_TRY_HIP(hipMemcpyAsync(nrm_h.data(), wk.nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -302,14 +396,14 @@ lm_status gmres_run(lm_geom_s* g, int precision, int R, const void* g_dev, const
   }
   // phi = M z
   if (use_pre) {
-    LM_TRY(precond_apply(g, R, wk.z.p, phi, s));
+    LM_TRY(precond_apply(g, precision, R, wk.z.p, phi, s));
   } else {
     LM_TRY_HIP(hipMemcpyAsync(phi, wk.z.p, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   // true residual
   LM_TRY(apply_KM(g, precision, R, wk.z.as<double2>(), w, use_pre, wk, s));
   hipLaunchKernelGGL(k_axpby, dim3(div_up(n, 256)), b256, 0, s, n, gv, -1.0, w, w);
-  hipLaunchKernelGGL(k_norm2, dim3(R), b256, 0, s, (int)N, w, wk.nrm.as<double>());
+  norm2(w);
   LM_TRY_HIP(hipMemcpyAsync(nrm_h.data(), wk.nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
   LM_TRY_HIP(hipStreamSynchronize(s));
   bool ok = true;

@@ -120,6 +120,6 @@ lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x,
 lm_status precond_build(lm_geom_s* g, hipStream_t s);
 void precond_free(Precond* p);
 int64_t precond_bytes(const Precond* p);
-lm_status precond_apply(lm_geom_s* g, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
 
 inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }

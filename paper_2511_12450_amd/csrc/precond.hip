@@ -11,8 +11,9 @@
 // |Gamma_i|) and W = diag |Gamma|, so the rows of P_B^{-1} for B are
 // (1/|Gamma_r|) (A^{-1} e_r)^T.  Setup: one workgroup per leaf assembles A in
 // device scratch, factors it (LU, partial pivoting) and solves for the |B|
-// unit vectors.  Apply: y_{B_r} = sum_j Z_B[j][r] x_{J_j} (Z stored
-// column-major so the threads of a leaf read consecutive addresses).
+// unit vectors.  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
+// the lanes of a wavefront read consecutive addresses of one row); the
+// mixed form applies an FP32 copy of Z.
 #include <algorithm>
 
 #include "fmm_plan.hpp"
@@ -21,8 +22,10 @@ struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
   std::vector<int> jptr, jidx, nb;
   std::vector<int64_t> zoff;
-  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_tmp;
-  int64_t bytes() const { return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes; }
+  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_Z32, d_tmp;
+  int64_t bytes() const {
+    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes;
+  }
 };
 
 void precond_free(Precond* p) { delete p; }
@@ -141,52 +144,89 @@ __global__ void __launch_bounds__(256) k_pre_setup(MediumDev m, int first, const
     }
     const double s = 1.0 / w[J[r]];
     double2* Zl = Z + zoff[leaf];
-    for (int jj = 0; jj < q; ++jj) Zl[(int64_t)jj * nB + r] = make_double2(z[jj].x * s, z[jj].y * s);
+    for (int jj = 0; jj < q; ++jj) Zl[(int64_t)r * q + jj] = make_double2(z[jj].x * s, z[jj].y * s);
   }
 }
 
-// y_{B_r} = sum_j Z_B[j][r] x_{J_j}: x_J staged in LDS; lanes over r, the four
-// waves split the j range and combine through LDS.
+// y_{B_r} = sum_j Z_B[r][j] x_{J_j}: one workgroup per leaf; x_J of RG
+// right-hand sides at a time is staged in LDS (in the arithmetic type), each
+// wavefront takes rows r = wave, wave + 4, ... two at a time, lanes run along
+// the rows (coalesced Z loads), and a wavefront reduction finishes each row.
+template <typename ZT, typename RT, int RG>
 __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __restrict__ jptr,
                                                    const int* __restrict__ jidx, const int* __restrict__ nb,
-                                                   const int64_t* __restrict__ zoff, const double2* __restrict__ Z,
+                                                   const int64_t* __restrict__ zoff, const ZT* __restrict__ Z,
                                                    const double2* __restrict__ x, double2* __restrict__ y) {
+  typedef ZT V;
+  extern __shared__ unsigned char dyn[];
+  V* xs = reinterpret_cast<V*>(dyn);  // [RG][q]
   const int leaf = blockIdx.x;
   const int j0_ = jptr[leaf], q = jptr[leaf + 1] - j0_, nB = nb[leaf];
   const int* J = jidx + j0_;
-  const double2* Zl = Z + zoff[leaf];
-  __shared__ double2 xs[2048];
-  __shared__ double2 part[4][64];
+  const ZT* Zl = Z + zoff[leaf];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int chunk = (q + 3) / 4, ja = wv * chunk, jb = min(q, ja + chunk);
-  for (int rr = 0; rr < R; ++rr) {
-    const double2* xr = x + (int64_t)rr * N;
+  for (int g = 0; g < R; g += RG) {
+    const int ng = min(RG, R - g);
     __syncthreads();
-    for (int j = threadIdx.x; j < q; j += 256) xs[j] = xr[J[j]];
+    for (int idx = threadIdx.x; idx < ng * q; idx += 256) {
+      const int u = idx / q, j = idx - u * q;
+      const double2 v = x[(int64_t)(g + u) * N + J[j]];
+      V t;
+      t.x = (RT)v.x;
+      t.y = (RT)v.y;
+      xs[u * q + j] = t;
+    }
     __syncthreads();
-    for (int r0 = 0; r0 < nB; r0 += 64) {
-      const int r = r0 + lane;
-      double re = 0.0, im = 0.0;
-      if (r < nB) {
-        for (int jj = ja; jj < jb; ++jj) {
-          const double2 zv = Zl[(int64_t)jj * nB + r], xv = xs[jj];
-          re += zv.x * xv.x - zv.y * xv.y;
-          im += zv.x * xv.y + zv.y * xv.x;
+    for (int r = wv; r < nB; r += 8) {
+      const int r2 = r + 4;
+      const bool two = r2 < nB;
+      const ZT* z1 = Zl + (int64_t)r * q;
+      const ZT* z2 = Zl + (int64_t)(two ? r2 : r) * q;
+      RT a1[RG][2], a2[RG][2];
+#pragma unroll
+      for (int u = 0; u < RG; ++u) a1[u][0] = a1[u][1] = a2[u][0] = a2[u][1] = RT(0);
+#pragma unroll 4
+      for (int j = lane; j < q; j += 64) {
+        const ZT p1 = z1[j], p2 = z2[j];
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+          if (u < ng) {
+            const V xv = xs[u * q + j];
+            a1[u][0] = fma((RT)p1.x, xv.x, a1[u][0]);
+            a1[u][0] = fma(-(RT)p1.y, xv.y, a1[u][0]);
+            a1[u][1] = fma((RT)p1.x, xv.y, a1[u][1]);
+            a1[u][1] = fma((RT)p1.y, xv.x, a1[u][1]);
+            a2[u][0] = fma((RT)p2.x, xv.x, a2[u][0]);
+            a2[u][0] = fma(-(RT)p2.y, xv.y, a2[u][0]);
+            a2[u][1] = fma((RT)p2.x, xv.y, a2[u][1]);
+            a2[u][1] = fma((RT)p2.y, xv.x, a2[u][1]);
+          }
         }
       }
-      part[wv][lane] = make_double2(re, im);
-      __syncthreads();
-      if (wv == 0 && r < nB) {
-        double2 t = part[0][lane];
-        for (int w2 = 1; w2 < 4; ++w2) {
-          t.x += part[w2][lane].x;
-          t.y += part[w2][lane].y;
+#pragma unroll
+      for (int u = 0; u < RG; ++u)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          for (int off = 32; off > 0; off >>= 1) {
+            a1[u][c] += __shfl_xor(a1[u][c], off, 64);
+            a2[u][c] += __shfl_xor(a2[u][c], off, 64);
+          }
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+          if (u < ng) {
+            y[(int64_t)(g + u) * N + J[r]] = make_double2((double)a1[u][0], (double)a1[u][1]);
+            if (two) y[(int64_t)(g + u) * N + J[r2]] = make_double2((double)a2[u][0], (double)a2[u][1]);
+          }
         }
-        y[(int64_t)rr * N + J[r]] = t;
       }
-      __syncthreads();
     }
   }
+}
+
+__global__ void k_z_to_c64(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
 lm_status precond_build(lm_geom_s* g, hipStream_t s) {
@@ -235,16 +275,27 @@ lm_status precond_build(lm_geom_s* g, hipStream_t s) {
                        P->d_Z.as<double2>());
     LM_TRY_HIP(hipGetLastError());
   }
+  LM_TRY(P->d_Z32.alloc(std::max<int64_t>(z, 1) * sizeof(float2)));
+  hipLaunchKernelGGL(k_z_to_c64, dim3(div_up(std::max<int64_t>(z, 1), 256)), dim3(256), 0, s, z, P->d_Z.as<double2>(),
+                     P->d_Z32.as<float2>());
+  LM_TRY_HIP(hipGetLastError());
   LM_TRY_HIP(hipStreamSynchronize(s));
   return LM_OK;
 }
 
-lm_status precond_apply(lm_geom_s* g, int n_rhs, const void* x, void* y, hipStream_t s) {
+lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s) {
   Precond* P = g->pre;
   LM_CHECK(P, LM_EINVAL, "no preconditioner");
-  hipLaunchKernelGGL(k_pre_apply, dim3(P->nleaf), dim3(256), 0, s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                     P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
-                     (const double2*)x, (double2*)y);
+  if (precision == LM_FP64)
+    hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
+                       (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
+                       (const double2*)x, (double2*)y);
+  else
+    hipLaunchKernelGGL((k_pre_apply<float2, float, 4>), dim3(P->nleaf), dim3(256),
+                       (size_t)4 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
+                       (const double2*)x, (double2*)y);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
