@@ -183,6 +183,62 @@ lm_status lm_gmres_solve_rhs(lm_geom geom, int precision, int n_rhs, const void*
 lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, const double* obs_host,
                        void* out_dev, void* hip_stream);
 
+/* --------------------------------------------------------------- serving --
+ * Request-serving loop with continuous batching (one worker thread per
+ * server, on the device current at lm_server_create).  A request is a
+ * geometry (owned by the caller; it must outlive the request and must not be
+ * used by other calls while the server holds requests on it), n_rhs incidence
+ * angles (one GMRES solve each, as lm_gmres_solve with the server's
+ * precision) and optional far-field observation angles.  The worker advances
+ * every admitted solve one Arnoldi step per round; solves on the same
+ * geometry share one multi-right-hand-side launch per round, solves on
+ * different geometries run on separate streams.  Krylov bases stay in device
+ * memory.  Requests are admitted first-in first-out while the number of
+ * active right-hand sides stays <= max_active_rhs and the estimated device
+ * footprint of the admitted requests stays <= hbm_budget_bytes (basis,
+ * work vectors and the per-right-hand-side FMM workspace; the geometry itself
+ * is not counted).  Zero limits select 64 right-hand sides and 64 GiB.
+ * All server entry points are thread-safe. */
+typedef struct {
+  int64_t hbm_budget_bytes;
+  int max_active_rhs;
+  int precision; /* LM_FP64 or LM_MIXED, for every request of the server */
+} lm_server_opts;
+typedef struct {
+  lm_geom geom;
+  int n_rhs;
+  const double* theta_rad; /* host, n_rhs angles in (0, pi) */
+  lm_gmres_opts gmres;
+  int n_obs;               /* far-field angles (0: none) */
+  const double* obs_rad;   /* host, n_obs angles, none horizontal */
+} lm_request;
+typedef enum { LM_QUEUED = 0, LM_RUNNING = 1, LM_DONE = 2, LM_FAILED = 3, LM_CANCELLED = 4 } lm_state;
+lm_status lm_server_create(const lm_server_opts* opts, lm_server* out);
+/* Copies the request and queues it; never blocks.  LM_EINVAL for invalid
+ * numbers (NaN angles, bad options), LM_ENOMEM if the request can never be
+ * admitted under the server's limits. */
+lm_status lm_submit(lm_server server, const lm_request* request, uint64_t* request_id);
+/* State of a request; once LM_DONE, copies its reports (n_rhs), phi (host
+ * c128 [n_rhs][N]) and far field (host c128 [n_rhs][n_obs]) into the
+ * non-NULL outputs and returns the solve status (LM_OK or LM_NOT_CONVERGED).
+ * latency_s: seconds from submission to completion (or to now while
+ * pending).  Returns LM_ECANCELLED for a cancelled request, the failure
+ * status for a failed one, LM_ENOTFOUND for an unknown id. */
+lm_status lm_poll(lm_server server, uint64_t request_id, lm_state* state, lm_solve_report* reports_host,
+                  double* latency_s, void* phi_host, void* far_field_host);
+/* Cancels a queued or running request (running ones stop at the next round). */
+lm_status lm_cancel(lm_server server, uint64_t request_id);
+/* Frees a finished, failed or cancelled request's results. */
+lm_status lm_release(lm_server server, uint64_t request_id);
+/* The device footprint the server charges for a request of n_rhs solves on
+ * geom with these GMRES options (Krylov basis, work vectors, FMM workspace). */
+lm_status lm_request_footprint(lm_geom geom, int n_rhs, const lm_gmres_opts* gmres, int64_t* bytes);
+/* Host output of 6 int64: queued requests, active right-hand sides, admitted
+ * footprint bytes, rounds, fused K M launches, right-hand sides in them. */
+lm_status lm_server_stats(lm_server server, int64_t* out6);
+/* Cancels everything in flight, joins the worker and frees the server. */
+lm_status lm_server_destroy(lm_server server);
+
 #ifdef __cplusplus
 }
 #endif

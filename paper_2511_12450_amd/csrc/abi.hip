@@ -218,7 +218,7 @@ extern "C" lm_status lm_rhs(lm_geom g, int n_rhs, const double* theta, void* g_d
   return rhs_launch(g, n_rhs, theta, g_dev, (hipStream_t)hip_stream);
 }
 
-static lm_status check_gmres_opts(const lm_gmres_opts* o) {
+lm_status check_gmres_opts(const lm_gmres_opts* o) {
   LM_CHECK(o, LM_EINVAL, "gmres options are required");
   LM_CHECK(std::isfinite(o->tol) && o->tol > 0 && o->tol < 1, LM_EINVAL, "tol must be in (0, 1)");
   LM_CHECK(o->max_iter >= 1 && o->restart >= 1 && o->restart <= 1000, LM_EINVAL, "bad max_iter/restart");

@@ -1342,6 +1342,12 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   return LM_OK;
 }
 
+// Device bytes the FMM workspace needs per right-hand side of a launch.
+int64_t fmm_ws_per_rhs(const FmmPlan* F) {
+  if (!F) return 0;
+  return (int64_t)F->P * 16 * (2 * (int64_t)F->n_boxes + F->item_ptr[3]) + (int64_t)F->P * 8 * (F->mf_item.size() / 3);
+}
+
 // Expansion buffers for r right-hand sides per launch (grown on demand).
 lm_status fmm_reserve(FmmPlan* F, int r) {
   r = std::min(std::max(r, 1), LM_RCHUNK);

@@ -191,28 +191,39 @@ __global__ void k_c64_to_c128(int64_t n, const float2* __restrict__ a, double2* 
   if (i < n) b[i] = make_double2((double)a[i].x, (double)a[i].y);
 }
 
-namespace {
-
-struct Work {
-  DevBuf V, w, z, h, y, nrm, scale, x32, y32, mz, dpart, npart;
-  std::vector<double2> hh;
-};
-
-// y = K M x in FP64 storage; the matvec itself runs in the requested precision.
-lm_status apply_KM(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, Work& wk,
+// y = K M x in FP64 storage (M = the preconditioner when use_pre); the matvec
+// itself runs in the requested precision.  Work buffers grow on demand.
+lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, KmBufs& b,
                    hipStream_t s) {
   const int64_t N = g->N, n = (int64_t)R * N;
   const double2* xin = x;
   if (use_pre) {
-    LM_TRY(precond_apply(g, precision, R, x, wk.mz.p, s));
-    xin = wk.mz.as<double2>();
+    if (b.mz.bytes < (size_t)n * sizeof(double2)) LM_TRY(b.mz.alloc(n * sizeof(double2)));
+    LM_TRY(precond_apply(g, precision, R, x, b.mz.p, s));
+    xin = b.mz.as<double2>();
   }
   if (precision == LM_FP64) return geom_matvec(g, precision, R, xin, y, s);
-  hipLaunchKernelGGL(k_c128_to_c64, dim3(div_up(n, 256)), dim3(256), 0, s, n, xin, wk.x32.as<float2>());
-  LM_TRY(geom_matvec(g, precision, R, wk.x32.p, wk.y32.p, s));
-  hipLaunchKernelGGL(k_c64_to_c128, dim3(div_up(n, 256)), dim3(256), 0, s, n, wk.y32.as<float2>(), y);
+  if (b.x32.bytes < (size_t)n * sizeof(float2)) {
+    LM_TRY(b.x32.alloc(n * sizeof(float2)));
+    LM_TRY(b.y32.alloc(n * sizeof(float2)));
+  }
+  hipLaunchKernelGGL(k_c128_to_c64, dim3(div_up(n, 256)), dim3(256), 0, s, n, xin, b.x32.as<float2>());
+  LM_TRY(geom_matvec(g, precision, R, b.x32.p, b.y32.p, s));
+  hipLaunchKernelGGL(k_c64_to_c128, dim3(div_up(n, 256)), dim3(256), 0, s, n, b.y32.as<float2>(), y);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
+}
+
+namespace {
+
+struct Work {
+  DevBuf V, w, z, h, y, nrm, scale, dpart, npart;
+  KmBufs km;
+};
+
+lm_status apply_KM(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, Work& wk,
+                   hipStream_t s) {
+  return apply_km(g, precision, R, x, y, use_pre, wk.km, s);
 }
 
 }  // namespace
@@ -232,11 +243,6 @@ lm_status gmres_run(lm_geom_s* g, int precision, int R, const void* g_dev, const
   LM_TRY(wk.y.alloc((size_t)R * (m + 1) * sizeof(double2)));
   LM_TRY(wk.nrm.alloc(R * sizeof(double)));
   LM_TRY(wk.scale.alloc(R * sizeof(double)));
-  if (precision == LM_MIXED) {
-    LM_TRY(wk.x32.alloc(n * sizeof(float2)));
-    LM_TRY(wk.y32.alloc(n * sizeof(float2)));
-  }
-  if (use_pre) LM_TRY(wk.mz.alloc(n * sizeof(double2)));
   double2* V = wk.V.as<double2>();
   const int nw_d = 4 * (int)div_up(N, GS_SLICE), nw_u = 4 * (int)div_up(N, 256);
   LM_TRY(wk.dpart.alloc((size_t)R * (m + 1) * nw_d * sizeof(double2)));

@@ -106,6 +106,13 @@ lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, voi
 lm_status rhs_launch(lm_geom_s* g, int n_rhs, const double* theta_host, void* g_dev, hipStream_t s);
 lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_host,
                           void* out, hipStream_t s);
+struct KmBufs {
+  DevBuf x32, y32, mz;
+};
+lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, KmBufs& b,
+                   hipStream_t s);
+lm_status check_gmres_opts(const lm_gmres_opts* o);
+int64_t fmm_ws_per_rhs(const FmmPlan* f);
 lm_status gmres_run(lm_geom_s* g, int precision, int n_rhs, const void* g_dev, const lm_gmres_opts* o,
                     void* phi_dev, lm_solve_report* rep, hipStream_t s);
 

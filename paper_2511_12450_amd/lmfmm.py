@@ -40,6 +40,19 @@ class SolveReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_active_rhs", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_void_p), ("n_rhs", ctypes.c_int), ("theta_rad", ctypes.POINTER(ctypes.c_double)),
+                ("gmres", GmresOpts), ("n_obs", ctypes.c_int), ("obs_rad", ctypes.POINTER(ctypes.c_double))]
+
+
+LM_QUEUED, LM_RUNNING, LM_DONE, LM_FAILED, LM_CANCELLED = 0, 1, 2, 3, 4
+LM_ENOMEM, LM_ENOTFOUND, LM_ECANCELLED = -2, -4, -5
+
+
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
 _SIGS = {
     "lm_last_error": ([], ctypes.c_char_p),
@@ -60,6 +73,14 @@ _SIGS = {
     "lm_gmres_solve_rhs": ([_vp, _ip, _ip, _vp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp],
                            _ip),
     "lm_far_field": ([_vp, _ip, _vp, _ip, _dp, _vp, _vp], _ip),
+    "lm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)], _ip),
+    "lm_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _ip),
+    "lm_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport), _dp, _vp, _vp], _ip),
+    "lm_cancel": ([_vp, ctypes.c_uint64], _ip),
+    "lm_release": ([_vp, ctypes.c_uint64], _ip),
+    "lm_server_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
+    "lm_request_footprint": ([_vp, _ip, ctypes.POINTER(GmresOpts), ctypes.POINTER(ctypes.c_int64)], _ip),
+    "lm_server_destroy": ([_vp], _ip),
 }
 
 
@@ -236,3 +257,87 @@ def far_field_angles():
     top = np.radians(np.arange(5.0, 175.0 + 1e-9, 0.5))
     bot = np.radians(np.arange(185.0, 355.0 + 1e-9, 0.5))
     return np.concatenate([top, bot])
+
+
+def request_footprint(geom, n_rhs, tol=1e-6, max_iter=1000, restart=500, precond=1):
+    """Device bytes a server charges for a request (lm_request_footprint)."""
+    b = ctypes.c_int64()
+    _check(lib().lm_request_footprint(geom.h, int(n_rhs), ctypes.byref(GmresOpts(tol, max_iter, restart, precond)),
+                                      ctypes.byref(b)))
+    return b.value
+
+
+class Server:
+    """Continuous-batching GMRES server (lm_server_* in include/lmfmm.h).
+
+    submit() returns a request id at once; poll() reports the state and, once
+    done, the reports, phi (numpy c128 [n_rhs][N]) and far field (numpy c128
+    [n_rhs][n_obs])."""
+
+    def __init__(self, precision=LM_MIXED, max_active_rhs=64, hbm_budget_bytes=0):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_active_rhs), int(precision))
+        h = ctypes.c_void_p()
+        _check(lib().lm_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._req = {}
+
+    def submit(self, geom, theta_rad, tol=1e-6, max_iter=1000, restart=500, precond=1, obs_rad=None):
+        th = np.ascontiguousarray(np.atleast_1d(theta_rad), dtype=np.float64)
+        ob = np.zeros(0) if obs_rad is None else np.ascontiguousarray(np.atleast_1d(obs_rad), dtype=np.float64)
+        r = Request(geom.h, th.size, _dptr(th), GmresOpts(tol, max_iter, restart, precond), ob.size,
+                    _dptr(ob) if ob.size else None)
+        rid = ctypes.c_uint64()
+        _check(lib().lm_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
+        self._req[rid.value] = (geom.n, th.size, ob.size)
+        return rid.value
+
+    def poll(self, rid, results=False):
+        """(state, status, latency_s, reports, phi, far_field); the last three
+        are None unless the request is done and results=True."""
+        n, R, no = self._req[rid]
+        st = ctypes.c_int()
+        lat = np.zeros(1)
+        rep = (SolveReport * R)()
+        phi = np.empty((R, n), dtype=np.complex128) if results else None
+        ff = np.empty((R, no), dtype=np.complex128) if results and no else None
+        status = lib().lm_poll(self.h, rid, ctypes.byref(st), rep, _dptr(lat),
+                               None if phi is None else phi.ctypes.data_as(_vp),
+                               None if ff is None else ff.ctypes.data_as(_vp))
+        if st.value == LM_DONE:
+            return st.value, status, float(lat[0]), [(x.iterations, x.rel_residual) for x in rep], phi, ff
+        return st.value, status, float(lat[0]), None, None, None
+
+    def wait(self, rid, timeout=600.0, results=True):
+        import time
+        t0 = time.time()
+        while True:
+            out = self.poll(rid, results=results)
+            if out[0] in (LM_DONE, LM_FAILED, LM_CANCELLED):
+                return out
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"request {rid} not finished after {timeout} s")
+            time.sleep(0.002)
+
+    def cancel(self, rid):
+        _check(lib().lm_cancel(self.h, rid))
+
+    def release(self, rid):
+        _check(lib().lm_release(self.h, rid))
+        self._req.pop(rid, None)
+
+    def stats(self):
+        out = np.zeros(6, dtype=np.int64)
+        _check(lib().lm_server_stats(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return dict(zip(["queued", "active_rhs", "admitted_bytes", "rounds", "launches", "fused_rhs"],
+                        [int(v) for v in out]))
+
+    def close(self):
+        if self.h:
+            lib().lm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
