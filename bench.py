@@ -1,17 +1,26 @@
 """Benchmark: GMRES solves/sec (+ p50/p99 latency) of the layered-medium
-Nystrom solver on one MI355X.
+Nystrom solver on one MI355X, served FP32 form vs plain FP64 form.
 
-A step is one complete solve of the hot path for one incidence angle on a
-geometry whose operator data (trees, Sommerfeld M2L tables, near-field
-entries, preconditioner) are already resident in HBM: right-hand side ->
-preconditioned GMRES (layered FMM matvec inside) -> far-field pattern on 682
-angles.  Prints one JSON line.
+Workload (default): three layers (interfaces y = 0, -2; k = 5, 7, 4), 400
+scatterers (circles and 5-petal stars), N = 64,000 elements, FMM order
+p = 20, GMRES tol 1e-6 with the domain-decomposition preconditioner; the
+geometry's operator data (trees, Sommerfeld M2L tables, near-field matrix,
+preconditioner) are built once and stay resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+* plain FP64 form: one lm_gmres_solve per incidence angle (every step FP64),
+  then the far field on 682 angles; solves run one after another.
+* served FP32 form (the value): the request-serving loop in LM_MIXED
+  precision; a step is one batch of 64 incidence angles in [10, 170] deg
+  submitted at once as 16 requests of 4 angles (each request also asks for
+  the 682-angle far field); the server fuses them into multi-right-hand-side
+  launches.  solves/s = angles / wall time of the batch; latency = per
+  request, submission to completion.
 
-Workloads: three_layer (default: 3 layers, k = (5,7,4), 400 scatterers,
-N = 64,000, p = 20, GMRES tol 1e-6 with the domain-decomposition
-preconditioner) and plain_small (2 layers, N = 256, dense matrix).
+Both forms are checked against a tight FP64 reference (tol 1e-9, computed
+outside the timed region) on four of the angles: the far-field relative
+error of each form is reported (bar 1e-4).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
 import argparse
@@ -26,31 +35,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_VALU_TFLOPS = 78.6
 STAGES = ("P2M", "M2M", "M2L", "L2L", "L2P", "near", "unused")
-KERNEL_OF_STAGE = {"P2M": "k_p2m", "M2M": "k_m2m", "M2L": "k_m2l_apply+k_m2l_reduce", "L2L": "k_l2l",
-                   "L2P": "k_l2p", "near": "k_near_csr"}
 
 
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1, help="served batches of --angles incidence angles")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="three_layer")
+    ap.add_argument("--angles", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=16)
+    ap.add_argument("--plain-solves", type=int, default=4)
+    ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
 
-def _workload(name):
-    from paper_2511_12450_amd import workloads as wl
-
-    if name == "three_layer":
-        return wl.three_layer(), "fmm"
-    if name == "plain_small":
-        return wl.plain_small(), "dense"
-    raise SystemExit(f"unknown workload {name}")
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def cpu_baseline(w, iterations, budget_s):
@@ -85,9 +90,21 @@ def cpu_baseline(w, iterations, budget_s):
     n = el.n
     projected = n * row_s + (iterations + 1) * n * gemv_row_s
     return {"value": 1.0 / projected, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{done} rows of the dense matrix of {w.name} ({row_s:.2f} s/row on one core); "
-                       f"solve projected as {n} rows + {iterations + 1} dense matvecs = {projected:.3g} s "
-                       "(projected, not run)")}
+            "sample": (f"{done} rows of the dense FP64 matrix of {w.name} by direct Sommerfeld quadrature "
+                       f"({row_s:.2f} s/row on one core); one solve projected as {n} rows + "
+                       f"{iterations + 1} dense matvecs = {projected:.3g} s (projected, not run)")}
+
+
+def m2l_roofline(geo, stats, P, R, times):
+    """Roofline of the M2L launch of an R-right-hand-side FP32 matvec
+    (MFMA kernel): algorithmic flops = 8 P^2 R per list entry."""
+    n_e = stats["m2l_free_entries"] + stats["m2l_reaction_entries"]
+    t = float(times[2]) * 1e-3
+    flops = 8.0 * P * P * R * n_e
+    ach = flops / t / 1e12
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "kernel": "k_m2l_mfma (+ k_p2m_reduce)",
+            "kernel_avg_us": t * 1e6, "algorithmic_flops_per_launch": flops, "entries": n_e, "rhs_per_launch": R}
 
 
 def main():
@@ -99,110 +116,132 @@ def main():
     import torch
 
     from paper_2511_12450_amd import lmfmm
+    from paper_2511_12450_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    w, kind = _workload(a.workload)
-    th = np.radians(w.angles_deg[:1])
+    w = wl.three_layer()
     obs = lmfmm.far_field_angles()
     t0 = time.perf_counter()
-    method = lmfmm.LM_DENSE if kind == "dense" else lmfmm.LM_FMM
-    geo = lmfmm.Geometry.from_workload(w, method=method, p=w.p, precond=1 if kind == "fmm" else 0)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, p=w.p, precond=1)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    opts = dict(tol=w.tol, max_iter=2000, restart=500, precond=1 if kind == "fmm" else 0)
+    N, P = geo.n, 2 * w.p + 1
+    th_all = np.radians(np.linspace(10.0, 170.0, a.angles))
+    ref_idx = list(range(0, a.angles, max(1, a.angles // 4)))[:4]
+    gm = dict(tol=w.tol, max_iter=3000, restart=a.restart)
 
-    def step():
-        phi, rep, st = geo.solve(th, **opts)
+    # tight FP64 reference (untimed)
+    pr, rr, _ = geo.solve(th_all[ref_idx], tol=1e-9, max_iter=3000, restart=a.restart)
+    fref = geo.far_field(pr, obs).cpu().numpy()
+    del pr
+
+    # ---- plain FP64 form: single solves, one after another -----------------------
+    def plain(th):
+        phi, rep, st = geo.solve(np.array([th]), precision=lmfmm.LM_FP64, precond=1, **gm)
         ff = geo.far_field(phi, obs)
-        return phi, rep, st, ff
+        torch.cuda.synchronize()
+        return rep[0], st, ff.cpu().numpy()[0]
 
     for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    lat = []
-    t_start = time.perf_counter()
-    for _ in range(a.steps):
+        plain(th_all[ref_idx[0]])
+    lat_p, its_p, err_p = [], [], []
+    tp = time.perf_counter()
+    for i in range(a.plain_solves):
+        k = ref_idx[i % len(ref_idx)]
         t1 = time.perf_counter()
-        phi, rep, st, ff = step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t1)
-    elapsed = time.perf_counter() - t_start
-    iters = int(rep[0][0])
+        rep, st, ff = plain(th_all[k])
+        lat_p.append(time.perf_counter() - t1)
+        its_p.append(rep[0])
+        err_p.append(_rel(ff, fref[ref_idx.index(k)]))
+    plain_s = time.perf_counter() - tp
 
-    x = torch.from_numpy(np.exp(1j * np.linspace(0, 50, geo.n))[None, :].copy()).cuda()
+    # ---- served FP32 form: batches through the serving loop ----------------------
+    srv = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
+    per = max(1, a.angles // a.requests)
+    for _ in range(a.warmup):
+        srv.wait(srv.submit(geo, th_all[:per], obs_rad=obs, **gm), results=False)
+    km0, gs0, gsb0 = srv.phase_times()
+    st0 = srv.stats()
+    lat_s, its_s, err_s = [], [], []
+    tsrv = time.perf_counter()
+    for _ in range(a.steps):
+        ids = [(srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm), i) for i in range(0, a.angles, per)]
+        for rid, i0 in ids:
+            st, status, lat, rep, phi, ff = srv.wait(rid)
+            assert st == lmfmm.LM_DONE, (st, status)
+            lat_s.append(lat)
+            its_s += [r[0] for r in rep]
+            for r in range(len(rep)):
+                if i0 + r in ref_idx:
+                    err_s.append(_rel(ff[r], fref[ref_idx.index(i0 + r)]))
+            srv.release(rid)
+    served_s = time.perf_counter() - tsrv
+    km1, gs1, gsb1 = srv.phase_times()
+    st1 = srv.stats()
+    srv.close()
+    n_served = a.steps * a.angles
+
+    # ---- kernel rooflines (HIP events on the launch stream) ---------------------
+    stats = geo.fmm_stats()
+    R = min(64, a.angles)
+    x = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=R)).to(torch.complex64).cuda()
     y = torch.empty_like(x)
-    N = geo.n
-    P = 2 * w.p + 1
-    cfg = {"workload": w.name, "N": int(N), "layers": int(len(w.k)), "k": [float(v) for v in w.k],
-           "method": kind, "p": int(w.p), "angle_deg": float(w.angles_deg[0]), "gmres_tol": w.tol,
-           "gmres_iterations": iters, "converged": st == 0, "rel_residual": float(rep[0][1]),
-           "setup_s": setup_s, "device_bytes": int(geo.device_bytes)}
-    if kind == "fmm":
-        stats = geo.fmm_stats()
-        cfg["fmm"] = stats
-        times = geo.stage_times(x, y, reps=10)
-        cfg["matvec_ms"] = float(times[7])
-        cfg["stage_ms"] = {s_: float(t) for s_, t in zip(STAGES, times[:7])}
-        dom = STAGES[int(np.argmax(times[:7]))]
-        t_dom = float(times[STAGES.index(dom)]) * 1e-3
-        if dom == "M2L":
-            # each list entry: one (2p+1)^2 operator applied to one expansion
-            n_e = stats["m2l_free_entries"] + stats["m2l_reaction_entries"]
-            flops = 8.0 * P * P * n_e
-            bytes_ = (16.0 * P * P * stats["reaction_tables"] + 16.0 * (4 * w.p + 1) * stats["free_classes"]
-                      + 16.0 * P * n_e + 16.0 * P * stats["boxes"])
-        elif dom == "near":
-            nnz = stats["free_near_pairs"] - N + stats["reaction_near_pairs"] + N
-            flops = 8.0 * nnz
-            bytes_ = 20.0 * nnz + 16.0 * 3 * N + 4.0 * N  # value + column index, x gather, y read/write, row ptr
-        else:
-            flops, bytes_ = float("nan"), float("nan")
-        intensity = flops / bytes_
-        ridge = PEAK_FP64_VALU_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-        if intensity < ridge:
-            roof = {"bound": "hbm", "achieved": bytes_ / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-        else:
-            roof = {"bound": "alu", "achieved": flops / t_dom / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
-                    "unit": "TFLOP/s"}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
-        roof.update({"stage": dom, "kernel": KERNEL_OF_STAGE[dom], "kernel_avg_us": t_dom * 1e6,
-                     "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops})
-    else:
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for _ in range(5):
-            geo.matvec(x, y)
-        ev0.record()
-        for _ in range(200):
-            geo.matvec(x, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        t_dom = ev0.elapsed_time(ev1) / 1e3 / 200
-        bytes_ = 16.0 * N * N + 32.0 * N
-        roof = {"bound": "hbm", "achieved": bytes_ / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": bytes_ / t_dom / 1e9 / PEAK_HBM_GBS, "traffic": None, "kernel": "k_dense_gemv",
-                "kernel_avg_us": t_dom * 1e6, "algorithmic_bytes_per_launch": bytes_}
+    t_mix = geo.stage_times(x, y, reps=5, precision=lmfmm.LM_MIXED)
+    x1 = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=1)).cuda()
+    y1 = torch.empty_like(x1)
+    t_fp64 = geo.stage_times(x1, y1, reps=10, precision=lmfmm.LM_FP64)
+    rounds = st1["rounds"] - st0["rounds"]
+    gs_ms, km_ms = gs1 - gs0, km1 - km0
+    gs_roof = {"bound": "hbm", "achieved": (gsb1 - gsb0) / (gs_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+               "unit": "GB/s", "traffic": None, "kernel": "k_s_dots+k_s_dots_final+k_s_update x2 (CGS2 phase)",
+               "kernel_avg_us": 1e3 * gs_ms / max(rounds, 1),
+               "algorithmic_bytes_per_launch": (gsb1 - gsb0) / max(rounds, 1)}
+    gs_roof["frac"] = gs_roof["achieved"] / PEAK_HBM_GBS
+    m2l_roof = m2l_roofline(geo, stats, P, R, t_mix)
+    # the dominant kernel of the served step: CGS2 phase vs the M2L of its matvecs
+    m2l_total_ms = float(t_mix[2]) * rounds * (min(R, a.angles) / R)
+    roof, other = (gs_roof, m2l_roof) if gs_ms >= m2l_total_ms else (m2l_roof, gs_roof)
 
+    cfg = {"workload": w.name, "N": int(N), "layers": int(len(w.k)), "k": [float(v) for v in w.k], "p": int(w.p),
+           "gmres_tol": w.tol, "gmres_restart": a.restart, "preconditioner": "overlapping DD (Sec. 4.2)",
+           "served": {"angles_per_step": a.angles, "requests_per_step": len(range(0, a.angles, per)),
+                      "angles_per_request": per, "far_field_angles": int(obs.size),
+                      "iterations_min_max": [int(min(its_s)), int(max(its_s))], "rounds": int(rounds),
+                      "fused_rhs_per_launch": (st1["fused_rhs"] - st0["fused_rhs"]) /
+                                              max(1, st1["launches"] - st0["launches"]),
+                      "km_phase_ms": km_ms, "gs_phase_ms": gs_ms},
+           "setup_s": setup_s, "device_bytes": int(geo.device_bytes), "fmm": stats,
+           "matvec_fp32_R64_ms": float(t_mix[7]),
+           "matvec_fp32_R64_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_mix[:7])},
+           "matvec_fp64_R1_ms": float(t_fp64[7]),
+           "matvec_fp64_R1_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_fp64[:7])}}
     out = {
-        "metric": "GMRES solves/sec (plain FP64 single-solve form)",
-        "value": a.steps / elapsed,
+        "metric": "GMRES solves/sec + p50/p99 latency, served FP32 vs plain FP64, at rel err 1e-4",
+        "value": n_served / served_s,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * elapsed / a.steps,
-        "p50_s": float(np.percentile(lat, 50)),
-        "p99_s": float(np.percentile(lat, 99)),
+        "ms_per_step": 1e3 * served_s / a.steps,
+        "p50_s": float(np.percentile(lat_s, 50)),
+        "p99_s": float(np.percentile(lat_s, 99)),
+        "rel_err_far_field_max": float(max(err_s)),
+        "plain_fp64": {"value": a.plain_solves / plain_s, "unit": "solves/s", "solves": a.plain_solves,
+                       "p50_s": float(np.percentile(lat_p, 50)), "p99_s": float(np.percentile(lat_p, 99)),
+                       "iterations": [int(v) for v in its_p], "rel_err_far_field_max": float(max(err_p))},
+        "speedup_served_vs_plain": (n_served / served_s) / (a.plain_solves / plain_s),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
+        "precision_split": "f32 translations, near field and preconditioner apply; f64 Arnoldi, Givens, tables and self terms",
         "data": "synthetic",
         "config": cfg,
         "roofline": roof,
+        "roofline_other": other,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, iters, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, int(np.median(its_p)), a.cpu_seconds)
     print(json.dumps(out))
 
 

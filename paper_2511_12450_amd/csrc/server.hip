@@ -265,6 +265,8 @@ struct lm_server_s {
   int64_t used = 0;
   int active_rhs = 0;
   int64_t rounds = 0, launches = 0, fused_rhs = 0;
+  double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
+  hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
   // worker state
   std::vector<Column*> cols;
   std::map<std::pair<lm_geom_s*, int>, Group> groups;
@@ -379,6 +381,7 @@ lm_status round(lm_server_s* S) {
     if (!c->finished) cols.push_back(c);
   if (cols.empty()) return LM_OK;
   const int prec = S->o.precision;
+  LM_TRY_HIP(hipEventRecord(S->t0, S->s));
   // ---- 1. K M v for every column that needs it, fused per (geometry, precond)
   std::map<std::pair<lm_geom_s*, int>, std::vector<Column*>> byg;
   for (Column* c : cols) {
@@ -390,6 +393,7 @@ lm_status round(lm_server_s* S) {
   }
   LM_TRY_HIP(hipEventRecord(S->ev_main, S->s));
   std::vector<char> used_stream(SRV_STREAMS, 0);
+  int64_t n_launch = 0, n_fused = 0;
   for (auto& kv : byg) {
     lm_geom_s* g = kv.first.first;
     const bool pre = kv.first.second && g->pre;
@@ -413,14 +417,15 @@ lm_status round(lm_server_s* S) {
       c->w = Y + (size_t)k * N;
     }
     LM_TRY(apply_km(g, prec, R, X, Y, pre, G.km, st));
-    S->launches++;
-    S->fused_rhs += R;
+    n_launch++;
+    n_fused += R;
   }
   for (int i = 0; i < SRV_STREAMS; ++i)
     if (used_stream[i]) {
       LM_TRY_HIP(hipEventRecord(S->ev[i], S->gs[i]));
       LM_TRY_HIP(hipStreamWaitEvent(S->s, S->ev[i], 0));
     }
+  LM_TRY_HIP(hipEventRecord(S->t1, S->s));
   // ---- 2. residuals, norms and batched CGS2 ------------------------------------
   const int nc = (int)cols.size();
   int Nmax = 0, ldh = 1, cntmax = 0;
@@ -463,12 +468,30 @@ lm_status round(lm_server_s* S) {
   hipLaunchKernelGGL(k_s_norm_final, dim3(nc), dim3(64), 0, S->s, dd, S->d_npart.as<double>(), nwu,
                      S->d_nrm.as<double>());
   LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipEventRecord(S->t2, S->s));
+  double gsb = 0.0;
+  for (Column* c : cols) {  // bytes the CGS2 passes and the norm pass must move
+    const double n16 = 16.0 * c->N;
+    gsb += n16 + (c->phase == PH_ARNOLDI ? 2.0 * (2.0 * (c->j + 1) * n16 + 3.0 * n16) : 0.0);
+  }
   S->hh.resize((size_t)nc * hs);
   S->hnrm.resize(nc);
   if (cntmax > 0)
     LM_TRY_HIP(hipMemcpyAsync(S->hh.data(), S->d_h.p, (size_t)nc * hs * sizeof(double2), hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipMemcpyAsync(S->hnrm.data(), S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipStreamSynchronize(S->s));
+  {
+    float a = 0.f, b = 0.f;
+    LM_TRY_HIP(hipEventElapsedTime(&a, S->t0, S->t1));
+    LM_TRY_HIP(hipEventElapsedTime(&b, S->t1, S->t2));
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->km_ms += a;
+    S->gs_ms += b;
+    S->gs_bytes += gsb;
+    S->launches += n_launch;
+    S->fused_rhs += n_fused;
+    S->rounds++;
+  }
   // ---- 3. host updates ------------------------------------------------------------
   std::vector<ColDev> scal, comb;
   std::vector<double2> ys;
@@ -592,7 +615,6 @@ lm_status round(lm_server_s* S) {
     lm_status st = finish_column(S, c);
     if (st < 0) fail_request(S, c->req, st, lm_last_error());
   }
-  S->rounds++;
   return LM_OK;
 }
 
@@ -707,7 +729,9 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
   S->o = so;
   if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
   bool ok = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&S->ev_main, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&S->ev_main, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
+            hipEventCreate(&S->t2) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
     ok = hipStreamCreateWithFlags(&S->gs[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&S->ev[i], hipEventDisableTiming) == hipSuccess;
@@ -831,6 +855,15 @@ extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
   return LM_OK;
 }
 
+extern "C" lm_status lm_server_phase_times(lm_server S, double* out3) {
+  LM_CHECK(S && out3, LM_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out3[0] = S->km_ms;
+  out3[1] = S->gs_ms;
+  out3[2] = S->gs_bytes;
+  return LM_OK;
+}
+
 extern "C" lm_status lm_server_destroy(lm_server S) {
   if (!S) return LM_OK;
   {
@@ -851,6 +884,8 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
     if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
   }
   if (S->ev_main) (void)hipEventDestroy(S->ev_main);
+  for (hipEvent_t e : {S->t0, S->t1, S->t2})
+    if (e) (void)hipEventDestroy(e);
   if (S->s) (void)hipStreamDestroy(S->s);
   delete S;
   return LM_OK;

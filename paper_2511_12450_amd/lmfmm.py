@@ -79,6 +79,7 @@ _SIGS = {
     "lm_cancel": ([_vp, ctypes.c_uint64], _ip),
     "lm_release": ([_vp, ctypes.c_uint64], _ip),
     "lm_server_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
+    "lm_server_phase_times": ([_vp, _dp], _ip),
     "lm_request_footprint": ([_vp, _ip, ctypes.POINTER(GmresOpts), ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_server_destroy": ([_vp], _ip),
 }
@@ -330,6 +331,12 @@ class Server:
         _check(lib().lm_server_stats(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return dict(zip(["queued", "active_rhs", "admitted_bytes", "rounds", "launches", "fused_rhs"],
                         [int(v) for v in out]))
+
+    def phase_times(self):
+        """(K M phase ms, Gram-Schmidt phase ms, Gram-Schmidt algorithmic bytes)."""
+        out = np.zeros(3)
+        _check(lib().lm_server_phase_times(self.h, _dptr(out)))
+        return float(out[0]), float(out[1]), float(out[2])
 
     def close(self):
         if self.h:
