@@ -90,7 +90,9 @@ lm_status lm_destroy_layers(lm_layers layers);
  *           LM_AUTO picks DENSE for N <= 4096.
  *   p: expansion order (default 20); leaf_size: target points per leaf
  *   (default 48); precond: build the overlapping domain-decomposition
- *   preconditioner of Sec. 4.2 (default 1 for FMM, 0 for dense).
+ *   preconditioner of Sec. 4.2 (FMM only): 0 none, 1 subdomains = the
+ *   free-space leaf boxes, c >= 2 subdomains = boxes c-1 levels above the
+ *   leaves (larger blocks, fewer iterations); default (-1) = 2.
  * The handle keeps a reference to `layers`, which must outlive it.
  * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */
 typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;

@@ -124,7 +124,7 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void
 lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, int reps, hipStream_t s,
                           double* out);
 
-lm_status precond_build(lm_geom_s* g, hipStream_t s);
+lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s);
 void precond_free(Precond* p);
 int64_t precond_bytes(const Precond* p);
 lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);

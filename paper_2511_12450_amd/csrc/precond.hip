@@ -9,12 +9,20 @@
 //
 // P_B = A W with A complex symmetric (A_ij = (i/4) H_0(k r_ij), A_ii = I^s_i /
 // |Gamma_i|) and W = diag |Gamma|, so the rows of P_B^{-1} for B are
-// (1/|Gamma_r|) (A^{-1} e_r)^T.  Setup: one workgroup per leaf assembles A in
-// device scratch, factors it (LU, partial pivoting) and solves for the |B|
-// unit vectors.  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
+// (1/|Gamma_r|) (A^{-1} e_r)^T.  Setup, per subdomain: a kernel assembles A
+// in device memory, rocSOLVER factors it (LU with partial pivoting, FP64) and
+// solves for the |B| unit vectors, and a kernel stores the scaled rows.
+// Subdomains are the free-space tree's boxes at the leaf level, or `coarsen`
+// levels above it (bigger overlapping blocks: fewer GMRES iterations for a
+// larger setup and apply).  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
 // the lanes of a wavefront read consecutive addresses of one row); the
 // mixed form applies an FP32 copy of Z.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <algorithm>
+#include <map>
+#include <tuple>
 
 #include "fmm_plan.hpp"
 
@@ -22,9 +30,10 @@ struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
   std::vector<int> jptr, jidx, nb;
   std::vector<int64_t> zoff;
-  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_Z32, d_tmp;
+  std::vector<int> items;  // (subdomain, first row) work items of PA_ROWS rows for the MFMA apply
+  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_Z32, d_items;
   int64_t bytes() const {
-    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes;
+    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes + d_items.bytes;
   }
 };
 
@@ -33,119 +42,44 @@ int64_t precond_bytes(const Precond* p) { return p ? p->bytes() : 0; }
 
 static constexpr double kEulerGamma = 0.57721566490153286061;
 
-__global__ void __launch_bounds__(256) k_pre_setup(MediumDev m, int first, const int* __restrict__ jptr,
-                                                   const int* __restrict__ jidx, const int* __restrict__ nb,
-                                                   const int64_t* __restrict__ zoff, const double* __restrict__ cx,
-                                                   const double* __restrict__ cy, const double* __restrict__ w,
-                                                   const int* __restrict__ lay, double2* __restrict__ scratch,
-                                                   int64_t scratch_stride, double2* __restrict__ Z) {
-  const int leaf = first + blockIdx.x;
-  const int j0_ = jptr[leaf];
-  const int q = jptr[leaf + 1] - j0_;
-  const int nB = nb[leaf];
-  const int* J = jidx + j0_;
-  double2* A = scratch + (int64_t)blockIdx.x * scratch_stride;  // q*q row-major, then q*nB solutions
-  double2* X = A + (int64_t)q * q;
+// A (q x q, symmetric, so row- and column-major agree) for one subdomain.
+__global__ void k_pre_assemble(MediumDev m, int q, const int* __restrict__ J, const double* __restrict__ cx,
+                               const double* __restrict__ cy, const double* __restrict__ w,
+                               const int* __restrict__ lay, double2* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)q * q) return;
+  const int i = (int)(idx / q), jj = (int)(idx % q);
+  const int ei = J[i], ej = J[jj];
   const double k = m.k[lay[J[0]]];
-  __shared__ int perm[2048];
-  __shared__ double rbest[256];
-  __shared__ int ibest[256];
-  for (int idx = threadIdx.x; idx < q * q; idx += blockDim.x) {
-    const int i = idx / q, jj = idx % q;
-    const int ei = J[i], ej = J[jj];
-    double re, im;
-    if (i == jj) {
-      re = -(kEulerGamma + log(k * w[ei] / 4.0) - 1.0) / (2.0 * M_PI);
-      im = 0.25;
-    } else {
-      const double r = hypot(cx[ei] - cx[ej], cy[ei] - cy[ej]);
-      re = -0.25 * y0(k * r);
-      im = 0.25 * j0(k * r);
-    }
-    A[idx] = make_double2(re, im);
+  double re, im;
+  if (i == jj) {
+    re = -(kEulerGamma + log(k * w[ei] / 4.0) - 1.0) / (2.0 * M_PI);
+    im = 0.25;
+  } else {
+    const double r = hypot(cx[ei] - cx[ej], cy[ei] - cy[ej]);
+    re = -0.25 * y0(k * r);
+    im = 0.25 * j0(k * r);
   }
-  for (int i = threadIdx.x; i < q; i += blockDim.x) perm[i] = i;
-  __syncthreads();
-  for (int kk = 0; kk < q; ++kk) {
-    double best = -1.0;
-    int bi = kk;
-    for (int i = kk + threadIdx.x; i < q; i += blockDim.x) {
-      const double2 v = A[(int64_t)i * q + kk];
-      const double a = v.x * v.x + v.y * v.y;
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
-    }
-    rbest[threadIdx.x] = best;
-    ibest[threadIdx.x] = bi;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < (unsigned)off && rbest[threadIdx.x + off] > rbest[threadIdx.x]) {
-        rbest[threadIdx.x] = rbest[threadIdx.x + off];
-        ibest[threadIdx.x] = ibest[threadIdx.x + off];
-      }
-      __syncthreads();
-    }
-    const int piv = ibest[0];
-    if (piv != kk) {
-      for (int jj = threadIdx.x; jj < q; jj += blockDim.x) {
-        const double2 t = A[(int64_t)kk * q + jj];
-        A[(int64_t)kk * q + jj] = A[(int64_t)piv * q + jj];
-        A[(int64_t)piv * q + jj] = t;
-      }
-      if (threadIdx.x == 0) {
-        const int t = perm[kk];
-        perm[kk] = perm[piv];
-        perm[piv] = t;
-      }
-    }
-    __syncthreads();
-    const double2 pv = A[(int64_t)kk * q + kk];
-    const zd inv = 1.0 / zd(pv.x, pv.y);
-    for (int i = kk + 1 + threadIdx.x; i < q; i += blockDim.x) {
-      const double2 v = A[(int64_t)i * q + kk];
-      const zd l = zd(v.x, v.y) * inv;
-      A[(int64_t)i * q + kk] = make_double2(l.re, l.im);
-    }
-    __syncthreads();
-    const int rem = q - kk - 1;
-    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
-      const int i = kk + 1 + idx / rem, jj = kk + 1 + idx % rem;
-      const double2 l = A[(int64_t)i * q + kk], u = A[(int64_t)kk * q + jj];
-      double2 a = A[(int64_t)i * q + jj];
-      a.x -= l.x * u.x - l.y * u.y;
-      a.y -= l.x * u.y + l.y * u.x;
-      A[(int64_t)i * q + jj] = a;
-    }
-    __syncthreads();
-  }
-  // column r of A^{-1}: solve L U z = P e_r (one thread per right-hand side)
-  for (int r = threadIdx.x; r < nB; r += blockDim.x) {
-    double2* z = X + (int64_t)r * q;
-    for (int i = 0; i < q; ++i) {  // forward, unit lower
-      zd acc(perm[i] == r ? 1.0 : 0.0, 0.0);
-      for (int jj = 0; jj < i; ++jj) {
-        const double2 l = A[(int64_t)i * q + jj], v = z[jj];
-        acc -= zd(l.x, l.y) * zd(v.x, v.y);
-      }
-      z[i] = make_double2(acc.re, acc.im);
-    }
-    for (int i = q - 1; i >= 0; --i) {  // backward
-      const double2 zi = z[i];
-      zd acc(zi.x, zi.y);
-      for (int jj = i + 1; jj < q; ++jj) {
-        const double2 u = A[(int64_t)i * q + jj], v = z[jj];
-        acc -= zd(u.x, u.y) * zd(v.x, v.y);
-      }
-      const double2 d = A[(int64_t)i * q + i];
-      acc = acc / zd(d.x, d.y);
-      z[i] = make_double2(acc.re, acc.im);
-    }
-    const double s = 1.0 / w[J[r]];
-    double2* Zl = Z + zoff[leaf];
-    for (int jj = 0; jj < q; ++jj) Zl[(int64_t)r * q + jj] = make_double2(z[jj].x * s, z[jj].y * s);
-  }
+  A[idx] = make_double2(re, im);
+}
+
+// X = the first nB unit vectors (q x nB, column-major).
+__global__ void k_pre_unit(int q, int nB, double2* __restrict__ X) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)q * nB) return;
+  const int r = (int)(idx / q), j = (int)(idx % q);
+  X[idx] = make_double2(j == r ? 1.0 : 0.0, 0.0);
+}
+
+// Z_B[r][j] = X[j][r] / |Gamma_{J_r}|  (row r of P_B^{-1}).
+__global__ void k_pre_store(int q, int nB, const int* __restrict__ J, const double* __restrict__ w,
+                            const double2* __restrict__ X, double2* __restrict__ Z) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)q * nB) return;
+  const int r = (int)(idx / q);
+  const double sc = 1.0 / w[J[r]];
+  const double2 v = X[idx];
+  Z[idx] = make_double2(v.x * sc, v.y * sc);
 }
 
 // y_{B_r} = sum_j Z_B[r][j] x_{J_j}: one workgroup per leaf; x_J of RG
@@ -224,57 +158,192 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
   }
 }
 
+// Mixed-precision apply for several right-hand sides with matrix cores:
+// Y_B (rows x R) = Z_B (rows x q) X_J (q x R) per work item of PA_ROWS rows of
+// one subdomain, as the real product [[Re Z, -Im Z], [Im Z, Re Z]] [Re X; Im X]
+// in 16x16x4 FP32 MFMA tiles (FP32 accumulation).  K runs over the
+// neighbourhood in chunks of PA_KC complex columns staged in LDS (Z chunk
+// transposed to [j][r], X chunk converted from FP64 to FP32).
+typedef float pa_v4f __attribute__((ext_vector_type(4)));
+constexpr int PA_ROWS = 64, PA_KC = 32, PA_TPW = 8;
+__global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int* __restrict__ items,
+                                                        const int* __restrict__ jptr, const int* __restrict__ jidx,
+                                                        const int* __restrict__ nb, const int64_t* __restrict__ zoff,
+                                                        const float2* __restrict__ Z, const double2* __restrict__ x,
+                                                        double2* __restrict__ y) {
+  __shared__ float2 Zs[PA_KC][PA_ROWS];
+  __shared__ float2 Xs[PA_KC][64];
+  const int sd = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+  const int j0_ = jptr[sd], q = jptr[sd + 1] - j0_;
+  const int rows = min(PA_ROWS, nb[sd] - r0);
+  const int* J = jidx + j0_;
+  const float2* Zl = Z + zoff[sd] + (int64_t)r0 * q;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int R2 = 2 * rows, MT = (R2 + 15) / 16, NT = (R + 15) / 16, ntile = MT * NT;
+  int mrow[PA_TPW], jcol[PA_TPW];
+  bool ire[PA_TPW], ival[PA_TPW], jval[PA_TPW];
+#pragma unroll
+  for (int t = 0; t < PA_TPW; ++t) {
+    const int tile = wv + 4 * t;
+    const int i = 16 * (tile / NT) + l16, jj = 16 * (tile % NT) + l16;
+    ival[t] = tile < ntile && i < R2;
+    ire[t] = i < rows;
+    mrow[t] = ival[t] ? (ire[t] ? i : i - rows) : 0;
+    jval[t] = tile < ntile && jj < R;
+    jcol[t] = jval[t] ? jj : 0;
+  }
+  pa_v4f acc[PA_TPW];
+#pragma unroll
+  for (int t = 0; t < PA_TPW; ++t) acc[t] = pa_v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < q; c0 += PA_KC) {
+    const int kc = min(PA_KC, q - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 256) {
+      const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a Z row
+      Zs[jj][rr] = (rr < rows && jj < kc) ? Zl[(int64_t)rr * q + c0 + jj] : make_float2(0.f, 0.f);
+    }
+    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 256) {
+      const int jj = idx >> 6, rr = idx & 63;
+      float2 v = make_float2(0.f, 0.f);
+      if (jj < kc && rr < R) {
+        const double2 xv = x[(int64_t)rr * N + J[c0 + jj]];
+        v = make_float2((float)xv.x, (float)xv.y);
+      }
+      Xs[jj][rr] = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ks = 0; ks < 2 * PA_KC / 4; ++ks) {
+      const int k = 4 * ks + kq;
+      const bool kre = k < PA_KC;
+      const int n = kre ? k : k - PA_KC;
+#pragma unroll
+      for (int t = 0; t < PA_TPW; ++t) {
+        if (wv + 4 * t < ntile) {  // wave-uniform
+          const float2 zv = Zs[n][mrow[t]];
+          const float2 xv = Xs[n][jcol[t]];
+          const float av = ival[t] ? (ire[t] ? (kre ? zv.x : -zv.y) : (kre ? zv.y : zv.x)) : 0.f;
+          const float bv = jval[t] ? (kre ? xv.x : xv.y) : 0.f;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double* yd = reinterpret_cast<double*>(y);
+#pragma unroll
+  for (int t = 0; t < PA_TPW; ++t) {
+    const int tile = wv + 4 * t;
+    if (tile < ntile) {
+      const int jj = 16 * (tile % NT) + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (tile / NT) + 4 * kq + v;
+        if (i < R2 && jj < R) {
+          const bool ir = i < rows;
+          const int row = J[r0 + (ir ? i : i - rows)];
+          yd[2 * ((int64_t)jj * N + row) + (ir ? 0 : 1)] = (double)acc[t][v];
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_z_to_c64(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
-lm_status precond_build(lm_geom_s* g, hipStream_t s) {
+lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   FmmPlan* F = g->fmm;
   LM_CHECK(F, LM_EINTERNAL, "the preconditioner needs the FMM plan");
   auto* P = new (std::nothrow) Precond();
   LM_CHECK(P, LM_ENOMEM, "host allocation failed");
   g->pre = P;
-  // neighbourhoods from the free-space near lists (leaf itself first)
+  // subdomains: free-tree boxes at level lp; each owns the points of its
+  // leaves; neighbourhood = the subdomain and its (up to 8) level-lp neighbours
+  const int lp = std::max(0, F->lf - std::max(0, coarsen));
+  const double wl = F->w_top / (double)(1 << lp);
+  std::map<std::tuple<int, int, int>, std::vector<int>> pts;  // (tree, i, j) -> elements
+  for (int b : F->leaf_free) {
+    const BoxDev& B = F->boxes[b];
+    const int sh = B.level - lp;
+    const double wb = F->w_top / (double)(1 << B.level);
+    const int i = (int)std::lround((B.cx - F->x0) / wb - 0.5) >> sh;
+    const int j = (int)std::lround(B.ch / wb - 0.5) >> sh;
+    auto& v = pts[std::make_tuple(B.tree, i, j)];
+    for (int k = 0; k < B.npt; ++k) v.push_back(F->pt_elem[B.pt0 + k]);
+  }
+  (void)wl;
   P->jptr.push_back(0);
   int64_t z = 0;
-  for (size_t t = 0; t < F->near_tgt.size(); ++t) {
-    const int b = F->near_tgt[t];
-    const BoxDev& B = F->boxes[b];
-    for (int i = 0; i < B.npt; ++i) P->jidx.push_back(F->pt_elem[B.pt0 + i]);
-    for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e) {
-      const int c = F->near_src[e];
-      if (c == b) continue;
-      const BoxDev& C = F->boxes[c];
-      for (int i = 0; i < C.npt; ++i) P->jidx.push_back(F->pt_elem[C.pt0 + i]);
-    }
+  for (auto& kv : pts) {
+    const int t = std::get<0>(kv.first), i = std::get<1>(kv.first), j = std::get<2>(kv.first);
+    for (int e : kv.second) P->jidx.push_back(e);
+    for (int di = -1; di <= 1; ++di)
+      for (int dj = -1; dj <= 1; ++dj) {
+        if (!di && !dj) continue;
+        auto it = pts.find(std::make_tuple(t, i + di, j + dj));
+        if (it == pts.end()) continue;
+        for (int e : it->second) P->jidx.push_back(e);
+      }
     const int q = (int)P->jidx.size() - P->jptr.back();
+    const int nB = (int)kv.second.size();
     P->jptr.push_back((int)P->jidx.size());
-    P->nb.push_back(B.npt);
+    P->nb.push_back(nB);
     P->zoff.push_back(z);
-    z += (int64_t)q * B.npt;
+    z += (int64_t)q * nB;
     P->qmax = std::max(P->qmax, q);
-    P->bmax = std::max(P->bmax, B.npt);
+    P->bmax = std::max(P->bmax, nB);
   }
   P->nleaf = (int)P->nb.size();
-  LM_CHECK(P->qmax <= 2048, LM_EINVAL, "preconditioner neighbourhood too large (%d); use a smaller leaf_size", P->qmax);
+  for (int b = 0; b < P->nleaf; ++b)
+    for (int r = 0; r < P->nb[b]; r += PA_ROWS) {
+      P->items.push_back(b);
+      P->items.push_back(r);
+    }
+  LM_CHECK(P->qmax <= 4096, LM_EINVAL, "preconditioner neighbourhood too large (%d); use a finer level", P->qmax);
   LM_TRY(upload(P->d_jptr, P->jptr.data(), P->jptr.size() * sizeof(int), s));
   LM_TRY(upload(P->d_jidx, P->jidx.data(), P->jidx.size() * sizeof(int), s));
   LM_TRY(upload(P->d_nb, P->nb.data(), P->nb.size() * sizeof(int), s));
   LM_TRY(upload(P->d_zoff, P->zoff.data(), P->zoff.size() * sizeof(int64_t), s));
+  LM_TRY(upload(P->d_items, P->items.data(), P->items.size() * sizeof(int), s));
   LM_TRY(P->d_Z.alloc(std::max<int64_t>(z, 1) * sizeof(double2)));
-  const int64_t stride = (int64_t)P->qmax * P->qmax + (int64_t)P->qmax * P->bmax;
-  const int batch = (int)std::max<int64_t>(1, std::min<int64_t>(P->nleaf, ((int64_t)1 << 29) / (stride * 16)));
-  DevBuf scratch;
-  LM_TRY(scratch.alloc((size_t)batch * stride * sizeof(double2)));
-  for (int first = 0; first < P->nleaf; first += batch) {
-    const int n = std::min(batch, P->nleaf - first);
-    hipLaunchKernelGGL(k_pre_setup, dim3(n), dim3(256), 0, s, g->m, first, P->d_jptr.as<int>(), P->d_jidx.as<int>(),
-                       P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
-                       g->d_w.as<double>(), g->d_layer.as<int>(), scratch.as<double2>(), stride,
-                       P->d_Z.as<double2>());
+  DevBuf A, X, piv, info;
+  LM_TRY(A.alloc((size_t)P->qmax * P->qmax * sizeof(double2)));
+  LM_TRY(X.alloc((size_t)P->qmax * P->bmax * sizeof(double2)));
+  LM_TRY(piv.alloc((size_t)P->qmax * sizeof(rocblas_int)));
+  LM_TRY(info.alloc((size_t)P->nleaf * sizeof(rocblas_int)));
+  rocblas_handle h = nullptr;
+  LM_CHECK(rocblas_create_handle(&h) == rocblas_status_success, LM_EINTERNAL, "rocblas_create_handle failed");
+  struct HandleGuard {
+    rocblas_handle h;
+    ~HandleGuard() { rocblas_destroy_handle(h); }
+  } guard{h};
+  LM_CHECK(rocblas_set_stream(h, s) == rocblas_status_success, LM_EINTERNAL, "rocblas_set_stream failed");
+  auto* Ad = A.as<rocblas_double_complex>();
+  auto* Xd = X.as<rocblas_double_complex>();
+  for (int b = 0; b < P->nleaf; ++b) {
+    const int q = P->jptr[b + 1] - P->jptr[b], nB = P->nb[b];
+    const int* J = P->d_jidx.as<int>() + P->jptr[b];
+    hipLaunchKernelGGL(k_pre_assemble, dim3(div_up((int64_t)q * q, 256)), dim3(256), 0, s, g->m, q, J,
+                       g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
+                       A.as<double2>());
+    hipLaunchKernelGGL(k_pre_unit, dim3(div_up((int64_t)q * nB, 256)), dim3(256), 0, s, q, nB, X.as<double2>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_CHECK(rocsolver_zgetrf(h, q, q, Ad, q, piv.as<rocblas_int>(), info.as<rocblas_int>() + b) ==
+                 rocblas_status_success, LM_EINTERNAL, "rocsolver_zgetrf failed");
+    LM_CHECK(rocsolver_zgetrs(h, rocblas_operation_none, q, nB, Ad, q, piv.as<rocblas_int>(), Xd, q) ==
+                 rocblas_status_success, LM_EINTERNAL, "rocsolver_zgetrs failed");
+    hipLaunchKernelGGL(k_pre_store, dim3(div_up((int64_t)q * nB, 256)), dim3(256), 0, s, q, nB, J, g->d_w.as<double>(),
+                       X.as<double2>(), P->d_Z.as<double2>() + P->zoff[b]);
     LM_TRY_HIP(hipGetLastError());
   }
+  std::vector<rocblas_int> inf(P->nleaf);
+  LM_TRY_HIP(hipMemcpyAsync(inf.data(), info.p, inf.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  LM_TRY_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < P->nleaf; ++b)
+    LM_CHECK(inf[b] == 0, LM_EINTERNAL, "singular preconditioner block %d (pivot %d)", b, (int)inf[b]);
   LM_TRY(P->d_Z32.alloc(std::max<int64_t>(z, 1) * sizeof(float2)));
   hipLaunchKernelGGL(k_z_to_c64, dim3(div_up(std::max<int64_t>(z, 1), 256)), dim3(256), 0, s, z, P->d_Z.as<double2>(),
                      P->d_Z32.as<float2>());
@@ -286,16 +355,42 @@ lm_status precond_build(lm_geom_s* g, hipStream_t s) {
 lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s) {
   Precond* P = g->pre;
   LM_CHECK(P, LM_EINVAL, "no preconditioner");
-  if (precision == LM_FP64)
-    hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
-                       (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
-                       (const double2*)x, (double2*)y);
-  else
-    hipLaunchKernelGGL((k_pre_apply<float2, float, 4>), dim3(P->nleaf), dim3(256),
-                       (size_t)4 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
-                       (const double2*)x, (double2*)y);
+  if (precision == LM_MIXED && n_rhs > 1) {
+    for (int r0 = 0; r0 < n_rhs; r0 += 64) {
+      const int R = std::min(64, n_rhs - r0);
+      hipLaunchKernelGGL(k_pre_apply_mfma, dim3(P->items.size() / 2), dim3(256), 0, s, (int)g->N, R,
+                         P->d_items.as<int>(), P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(),
+                         P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(), (const double2*)x + (int64_t)r0 * g->N,
+                         (double2*)y + (int64_t)r0 * g->N);
+    }
+    LM_TRY_HIP(hipGetLastError());
+    return LM_OK;
+  }
+  // x_J of RG right-hand sides is staged in LDS: RG q sizeof <= 64 KiB
+  const bool big = P->qmax > 2048;
+  if (precision == LM_FP64) {
+    if (big)
+      hipLaunchKernelGGL((k_pre_apply<double2, double, 1>), dim3(P->nleaf), dim3(256),
+                         (size_t)P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
+                         (const double2*)x, (double2*)y);
+    else
+      hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
+                         (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
+                         (const double2*)x, (double2*)y);
+  } else {
+    if (big)
+      hipLaunchKernelGGL((k_pre_apply<float2, float, 2>), dim3(P->nleaf), dim3(256),
+                         (size_t)2 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
+                         (const double2*)x, (double2*)y);
+    else
+      hipLaunchKernelGGL((k_pre_apply<float2, float, 4>), dim3(P->nleaf), dim3(256),
+                         (size_t)4 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
+                         (const double2*)x, (double2*)y);
+  }
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }

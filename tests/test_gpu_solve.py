@@ -98,3 +98,17 @@ def test_not_converged_status():
     assert st == lmfmm.LM_NOT_CONVERGED
     assert rep[0][0] == 3 and rep[0][1] > 1e-12
     assert torch.isfinite(phi).all()
+
+
+def test_coarser_subdomains_fewer_iterations_same_solution():
+    w = wl.three_layer_mini(seed=3)
+    g1 = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=1)
+    g2 = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=2)
+    th = np.radians([45.0])
+    p1, r1, s1 = g1.solve(th, tol=1e-8, max_iter=800, restart=800)
+    p2, r2, s2 = g2.solve(th, tol=1e-8, max_iter=800, restart=800)
+    print("iterations with leaf / coarser subdomains:", r1[0][0], r2[0][0], flush=True)
+    assert s1 == lmfmm.LM_OK and s2 == lmfmm.LM_OK
+    assert r2[0][0] < r1[0][0]
+    obs = lmfmm.far_field_angles()[::7]
+    assert _rel(g2.far_field(p2, obs).cpu().numpy(), g1.far_field(p1, obs).cpu().numpy()) < 1e-6
