@@ -58,6 +58,25 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter record, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_three_layer_N64000.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for f, h in rec["source_sha256"].items():
+        if hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() != h:
+            return None
+    return rec
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(w, iterations, budget_s):
     """The oracle as it stands on one host core: rows of the dense Nystrom
     matrix by direct Sommerfeld quadrature, timed until budget_s has passed;
@@ -95,22 +114,10 @@ def cpu_baseline(w, iterations, budget_s):
                        f"{iterations + 1} dense matvecs = {projected:.3g} s (projected, not run)")}
 
 
-def m2l_roofline(geo, stats, P, R, times):
-    """Roofline of the M2L launch of an R-right-hand-side FP32 matvec
-    (MFMA kernel): algorithmic flops = 8 P^2 R per list entry."""
-    n_e = stats["m2l_free_entries"] + stats["m2l_reaction_entries"]
-    t = float(times[2]) * 1e-3
-    flops = 8.0 * P * P * R * n_e
-    ach = flops / t / 1e12
-    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "kernel": "k_m2l_mfma (+ k_p2m_reduce)",
-            "kernel_avg_us": t * 1e6, "algorithmic_flops_per_launch": flops, "entries": n_e, "rhs_per_launch": R}
-
-
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design only (DESIGN.md)",
+        print(json.dumps({"error": "lmfmm runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
@@ -126,6 +133,7 @@ def main():
     geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, p=w.p, precond=2)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    _log(f"geometry ready in {setup_s:.1f} s")
     N, P = geo.n, 2 * w.p + 1
     th_all = np.radians(np.linspace(10.0, 170.0, a.angles))
     ref_idx = list(range(0, a.angles, max(1, a.angles // 4)))[:4]
@@ -155,13 +163,16 @@ def main():
         its_p.append(rep[0])
         err_p.append(_rel(ff, fref[ref_idx.index(k)]))
     plain_s = time.perf_counter() - tp
+    _log(f"plain FP64: {a.plain_solves} solves in {plain_s:.2f} s")
 
     # ---- served FP32 form: batches through the serving loop ----------------------
     srv = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
     per = max(1, a.angles // a.requests)
-    for _ in range(a.warmup):
-        srv.wait(srv.submit(geo, th_all[:per], obs_rad=obs, **gm), results=False)
-    km0, gs0, gsb0 = srv.phase_times()
+    for _ in range(a.warmup):  # warm-up batches have the timed batch's shape
+        for rid in [srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm) for i in range(0, a.angles, per)]:
+            srv.wait(rid, results=False)
+            srv.release(rid)
+    ph0 = srv.phase_times()
     st0 = srv.stats()
     lat_s, its_s, err_s = [], [], []
     tsrv = time.perf_counter()
@@ -177,31 +188,44 @@ def main():
                     err_s.append(_rel(ff[r], fref[ref_idx.index(i0 + r)]))
             srv.release(rid)
     served_s = time.perf_counter() - tsrv
-    km1, gs1, gsb1 = srv.phase_times()
+    ph1 = srv.phase_times()
+    ph = {k: ph1[k] - ph0[k] for k in ph1}
     st1 = srv.stats()
     srv.close()
     n_served = a.steps * a.angles
+    _log(f"served FP32: {n_served} solves in {served_s:.2f} s")
 
-    # ---- kernel rooflines (HIP events on the launch stream) ---------------------
+    # ---- kernel rooflines (HIP events on the launch stream, inside the timed batch)
     stats = geo.fmm_stats()
+    rounds = st1["rounds"] - st0["rounds"]
+    m2l_avg_s = ph["m2l_ms"] * 1e-3 / max(ph["m2l_launches"], 1)
+    m2l_flops = ph["m2l_flops"] / max(ph["m2l_launches"], 1)
+    m2l_roof = {"bound": "mfma", "achieved": m2l_flops / m2l_avg_s / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "traffic": None, "kernel": "k_m2l_mfma (+ k_p2m_reduce)",
+                "kernel_avg_us": m2l_avg_s * 1e6, "launches": int(ph["m2l_launches"]),
+                "algorithmic_flops_per_launch": m2l_flops,
+                "entries": stats["m2l_free_entries"] + stats["m2l_reaction_entries"]}
+    m2l_roof["frac"] = m2l_roof["achieved"] / PEAK_FP32_MFMA_TFLOPS
+    gs_avg_s = ph["gs_ms"] * 1e-3 / max(rounds, 1)
+    gs_bytes = ph["gs_bytes"] / max(rounds, 1)
+    gs_roof = {"bound": "hbm", "achieved": gs_bytes / gs_avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "traffic": None, "kernel": "k_s_dots+k_s_update x2 (+ k_s_dots_final, k_s_resid, k_s_norm_final)",
+               "kernel_avg_us": gs_avg_s * 1e6, "launches": int(rounds), "algorithmic_bytes_per_launch": gs_bytes}
+    gs_roof["frac"] = gs_roof["achieved"] / PEAK_HBM_GBS
+    tr = _traffic()
+    if tr is not None:
+        m2l_roof["traffic"] = tr["k_m2l_mfma"]["hbm_bytes_per_launch"]
+        gs_roof["traffic"] = tr["cgs2_phase"]["hbm_bytes_per_round"]
+    # the dominant single kernel of the served step is the M2L; the CGS2 phase
+    # (several kernels) is reported beside it
+    roof, other = m2l_roof, gs_roof
+    x1 = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=1)).cuda()
+    y1 = torch.empty_like(x1)
+    t_fp64 = geo.stage_times(x1, y1, reps=10, precision=lmfmm.LM_FP64)
     R = min(64, a.angles)
     x = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=R)).to(torch.complex64).cuda()
     y = torch.empty_like(x)
     t_mix = geo.stage_times(x, y, reps=5, precision=lmfmm.LM_MIXED)
-    x1 = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=1)).cuda()
-    y1 = torch.empty_like(x1)
-    t_fp64 = geo.stage_times(x1, y1, reps=10, precision=lmfmm.LM_FP64)
-    rounds = st1["rounds"] - st0["rounds"]
-    gs_ms, km_ms = gs1 - gs0, km1 - km0
-    gs_roof = {"bound": "hbm", "achieved": (gsb1 - gsb0) / (gs_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
-               "unit": "GB/s", "traffic": None, "kernel": "k_s_dots+k_s_dots_final+k_s_update x2 (CGS2 phase)",
-               "kernel_avg_us": 1e3 * gs_ms / max(rounds, 1),
-               "algorithmic_bytes_per_launch": (gsb1 - gsb0) / max(rounds, 1)}
-    gs_roof["frac"] = gs_roof["achieved"] / PEAK_HBM_GBS
-    m2l_roof = m2l_roofline(geo, stats, P, R, t_mix)
-    # the dominant kernel of the served step: CGS2 phase vs the M2L of its matvecs
-    m2l_total_ms = float(t_mix[2]) * rounds * (min(R, a.angles) / R)
-    roof, other = (gs_roof, m2l_roof) if gs_ms >= m2l_total_ms else (m2l_roof, gs_roof)
 
     cfg = {"workload": w.name, "N": int(N), "layers": int(len(w.k)), "k": [float(v) for v in w.k], "p": int(w.p),
            "gmres_tol": w.tol, "gmres_restart": a.restart, "preconditioner": "overlapping DD (Sec. 4.2), subdomains one level above the FMM leaves",
@@ -210,7 +234,7 @@ def main():
                       "iterations_min_max": [int(min(its_s)), int(max(its_s))], "rounds": int(rounds),
                       "fused_rhs_per_launch": (st1["fused_rhs"] - st0["fused_rhs"]) /
                                               max(1, st1["launches"] - st0["launches"]),
-                      "km_phase_ms": km_ms, "gs_phase_ms": gs_ms},
+                      "km_phase_ms": ph["km_ms"], "gs_phase_ms": ph["gs_ms"], "m2l_ms": ph["m2l_ms"]},
            "setup_s": setup_s, "device_bytes": int(geo.device_bytes), "fmm": stats,
            "matvec_fp32_R64_ms": float(t_mix[7]),
            "matvec_fp32_R64_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_mix[:7])},

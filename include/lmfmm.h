@@ -238,14 +238,17 @@ lm_status lm_request_footprint(lm_geom geom, int n_rhs, const lm_gmres_opts* gmr
 /* Host output of 6 int64: queued requests, active right-hand sides, admitted
  * footprint bytes, rounds, fused K M launches, right-hand sides in them. */
 lm_status lm_server_stats(lm_server server, int64_t* out6);
-/* Host output of 3 doubles accumulated over the server's rounds, measured
- * with HIP events on the worker's stream: [0] ms in the fused K M phase
- * (gathers, preconditioner, matvecs; every geometry stream joined), [1] ms
- * in the Gram-Schmidt phase (two classical passes over each basis plus the
- * norms), [2] bytes that phase must move at minimum: per Arnoldi column with
- * j+1 basis vectors of N complex doubles, 2 x (2 (j+1) + 3) N x 16, plus
- * N x 16 for the norm. */
-lm_status lm_server_phase_times(lm_server server, double* out3);
+/* Host output of 6 doubles accumulated over the server's rounds, measured
+ * with HIP events on the streams the kernels run on: [0] ms in the fused
+ * K M phase (gathers, preconditioner, matvecs; every geometry stream
+ * joined), [1] ms in the Gram-Schmidt phase (two classical passes over each
+ * basis plus the norms), [2] bytes that phase must move at minimum: per
+ * Arnoldi column with j+1 basis vectors of N complex doubles,
+ * 2 x (2 (j+1) + 3) N x 16, plus N x 16 for the norm; [3] ms in the M2L
+ * launches of the fused FMM matvecs (first launch of each geometry stream
+ * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
+ * [5] the number of those launches. */
+lm_status lm_server_phase_times(lm_server server, double* out6);
 /* Cancels everything in flight, joins the worker and frees the server. */
 lm_status lm_server_destroy(lm_server server);
 

@@ -28,8 +28,8 @@ acoustic wave scattering in two-dimensional layered media"):
 * ``precond``    -- the overlapping domain-decomposition preconditioner
                     (Sec. 4.2), built densely.
 
-Readings of garbled or silent passages are listed in the design doc; the
-important ones are marked "reading" in the docstrings.
+Readings of garbled or silent passages are marked "reading" in the
+docstrings of the modules that depend on them.
 """
 
 from .medium import Medium, nonzero_components  # noqa: F401

@@ -7,7 +7,7 @@ generalized-reflection recursions Rellrecursionup / Rellrecursiondown, the
 generalized transmission generaltransmission, and the reaction densities of
 Cases I-III: densityinsourcelayer, disity1, disity2).
 
-Readings (listed in DESIGN.md):
+Readings:
 * the round-trip factor printed as exp(-2 k_{l,y} h_l) is read as
   exp(+2i k_{l,y} h_l), the form the paper prints inside Cases II and III;
 * the downward recursion starts from R~_{L,L+1} = 0 (the Remark after

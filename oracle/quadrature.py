@@ -4,7 +4,7 @@ Oracle (test infrastructure): see the package docstring.
 
 The paper gives the reaction components as Sommerfeld integrals
 (eq. fourreactions, uniform form eq. planewavekernel) but is silent on how
-they are evaluated (reading "O5" in the design doc).  Every reaction component has
+they are evaluated (reading: any convergent quadrature is admissible).  Every reaction component has
 the form
 
     I = (1/2pi) int_{-inf}^{inf} exp(i lam dx) F(lam) dlam,

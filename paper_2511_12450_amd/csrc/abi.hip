@@ -188,9 +188,10 @@ static lm_status check_prec(int precision) {
   return LM_OK;
 }
 
-lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s) {
+lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s,
+                      hipEvent_t* stage_ev) {
   if (g->method == LM_DENSE) return dense_matvec(g, precision, n_rhs, x, y, s);
-  return fmm_matvec(g, precision, n_rhs, x, y, s);
+  return fmm_matvec_timed(g, precision, n_rhs, x, y, s, stage_ev);
 }
 
 extern "C" lm_status lm_matvec(lm_geom g, int precision, int n_rhs, const void* x, void* y, void* hip_stream) {

@@ -202,13 +202,13 @@ lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2
     LM_TRY(precond_apply(g, precision, R, x, b.mz.p, s));
     xin = b.mz.as<double2>();
   }
-  if (precision == LM_FP64) return geom_matvec(g, precision, R, xin, y, s);
+  if (precision == LM_FP64) return geom_matvec(g, precision, R, xin, y, s, b.stage_ev);
   if (b.x32.bytes < (size_t)n * sizeof(float2)) {
     LM_TRY(b.x32.alloc(n * sizeof(float2)));
     LM_TRY(b.y32.alloc(n * sizeof(float2)));
   }
   hipLaunchKernelGGL(k_c128_to_c64, dim3(div_up(n, 256)), dim3(256), 0, s, n, xin, b.x32.as<float2>());
-  LM_TRY(geom_matvec(g, precision, R, b.x32.p, b.y32.p, s));
+  LM_TRY(geom_matvec(g, precision, R, b.x32.p, b.y32.p, s, b.stage_ev));
   hipLaunchKernelGGL(k_c64_to_c128, dim3(div_up(n, 256)), dim3(256), 0, s, n, b.y32.as<float2>(), y);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;

@@ -102,12 +102,14 @@ struct lm_geom_s {
 // ------------------------------------------------------------ entry points --
 lm_status dense_assemble(lm_geom_s* g, hipStream_t s);
 lm_status dense_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
-lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s,
+                      hipEvent_t* stage_ev = nullptr);
 lm_status rhs_launch(lm_geom_s* g, int n_rhs, const double* theta_host, void* g_dev, hipStream_t s);
 lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_host,
                           void* out, hipStream_t s);
 struct KmBufs {
   DevBuf x32, y32, mz;
+  hipEvent_t* stage_ev = nullptr;  // when set: 14 events bracketing the FMM stages (see fmm_matvec_timed)
 };
 lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, KmBufs& b,
                    hipStream_t s);
@@ -121,6 +123,8 @@ void fmm_free(FmmPlan* f);
 int64_t fmm_bytes(const FmmPlan* f);
 void fmm_stats(const FmmPlan* f, int64_t* out);
 lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s,
+                           hipEvent_t* ev);
 lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, int reps, hipStream_t s,
                           double* out);
 

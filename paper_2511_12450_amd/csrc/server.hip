@@ -266,7 +266,10 @@ struct lm_server_s {
   int active_rhs = 0;
   int64_t rounds = 0, launches = 0, fused_rhs = 0;
   double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
+  double m2l_ms = 0.0, m2l_flops = 0.0;              // M2L launches of the fused matvecs (HIP events)
+  int64_t m2l_launches = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+  hipEvent_t sev[SRV_STREAMS][14] = {};
   // worker state
   std::vector<Column*> cols;
   std::map<std::pair<lm_geom_s*, int>, Group> groups;
@@ -392,7 +395,9 @@ lm_status round(lm_server_s* S) {
     byg[{c->g, c->req->o.precond ? 1 : 0}].push_back(c);
   }
   LM_TRY_HIP(hipEventRecord(S->ev_main, S->s));
-  std::vector<char> used_stream(SRV_STREAMS, 0);
+  std::vector<char> used_stream(SRV_STREAMS, 0), stream_timed(SRV_STREAMS, 0);
+  std::vector<int> timed_streams;
+  double m2l_flops_round = 0.0;
   int64_t n_launch = 0, n_fused = 0;
   for (auto& kv : byg) {
     lm_geom_s* g = kv.first.first;
@@ -416,7 +421,18 @@ lm_status round(lm_server_s* S) {
       LM_TRY_HIP(hipMemcpyAsync(X + (size_t)k * N, in, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, st));
       c->w = Y + (size_t)k * N;
     }
+    const bool time_m2l = g->method == LM_FMM && !stream_timed[si];
+    G.km.stage_ev = time_m2l ? S->sev[si] : nullptr;
     LM_TRY(apply_km(g, prec, R, X, Y, pre, G.km, st));
+    G.km.stage_ev = nullptr;
+    if (time_m2l) {
+      stream_timed[si] = 1;
+      int64_t st10[10];
+      fmm_stats(g->fmm, st10);
+      const double P = 2.0 * g->p + 1.0;
+      m2l_flops_round += 8.0 * P * P * std::min(R, 64) * (double)(st10[1] + st10[2]);
+      timed_streams.push_back(si);
+    }
     n_launch++;
     n_fused += R;
   }
@@ -426,6 +442,7 @@ lm_status round(lm_server_s* S) {
       LM_TRY_HIP(hipStreamWaitEvent(S->s, S->ev[i], 0));
     }
   LM_TRY_HIP(hipEventRecord(S->t1, S->s));
+  float km_round = 0.f;
   // ---- 2. residuals, norms and batched CGS2 ------------------------------------
   const int nc = (int)cols.size();
   int Nmax = 0, ldh = 1, cntmax = 0;
@@ -448,7 +465,9 @@ lm_status round(lm_server_s* S) {
     d.N = c->N;
     d.cnt = c->phase == PH_ARNOLDI ? c->j + 1 : 0;
   }
-  LM_TRY(upload_desc(S, S->hdesc));
+  LM_TRY(upload_desc(S, S->hdesc));  // synchronises: the Gram-Schmidt timing starts after it
+  LM_TRY_HIP(hipEventElapsedTime(&km_round, S->t0, S->t1));
+  LM_TRY_HIP(hipEventRecord(S->t1, S->s));
   const ColDev* dd = S->d_desc.as<ColDev>();
   const int hs = 2 * ldh;
   if (cntmax > 0) {
@@ -481,12 +500,19 @@ lm_status round(lm_server_s* S) {
   LM_TRY_HIP(hipMemcpyAsync(S->hnrm.data(), S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipStreamSynchronize(S->s));
   {
-    float a = 0.f, b = 0.f;
-    LM_TRY_HIP(hipEventElapsedTime(&a, S->t0, S->t1));
+    float b = 0.f, m2l = 0.f;
     LM_TRY_HIP(hipEventElapsedTime(&b, S->t1, S->t2));
+    for (int si : timed_streams) {
+      float t = 0.f;
+      LM_TRY_HIP(hipEventElapsedTime(&t, S->sev[si][4], S->sev[si][5]));
+      m2l += t;
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    S->km_ms += a;
+    S->km_ms += km_round;
     S->gs_ms += b;
+    S->m2l_ms += m2l;
+    S->m2l_flops += m2l_flops_round;
+    S->m2l_launches += (int64_t)timed_streams.size();
     S->gs_bytes += gsb;
     S->launches += n_launch;
     S->fused_rhs += n_fused;
@@ -733,6 +759,8 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
             hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
             hipEventCreate(&S->t2) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
+    for (int e = 0; ok && e < 14; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
+  for (int i = 0; ok && i < SRV_STREAMS; ++i)
     ok = hipStreamCreateWithFlags(&S->gs[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&S->ev[i], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
@@ -855,12 +883,15 @@ extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
   return LM_OK;
 }
 
-extern "C" lm_status lm_server_phase_times(lm_server S, double* out3) {
-  LM_CHECK(S && out3, LM_EINVAL, "bad arguments");
+extern "C" lm_status lm_server_phase_times(lm_server S, double* out6) {
+  LM_CHECK(S && out6, LM_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> lk(S->mu);
-  out3[0] = S->km_ms;
-  out3[1] = S->gs_ms;
-  out3[2] = S->gs_bytes;
+  out6[0] = S->km_ms;
+  out6[1] = S->gs_ms;
+  out6[2] = S->gs_bytes;
+  out6[3] = S->m2l_ms;
+  out6[4] = S->m2l_flops;
+  out6[5] = (double)S->m2l_launches;
   return LM_OK;
 }
 
@@ -886,6 +917,9 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
   if (S->ev_main) (void)hipEventDestroy(S->ev_main);
   for (hipEvent_t e : {S->t0, S->t1, S->t2})
     if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < SRV_STREAMS; ++i)
+    for (int e = 0; e < 14; ++e)
+      if (S->sev[i][e]) (void)hipEventDestroy(S->sev[i][e]);
   if (S->s) (void)hipStreamDestroy(S->s);
   delete S;
   return LM_OK;

@@ -333,10 +333,11 @@ class Server:
                         [int(v) for v in out]))
 
     def phase_times(self):
-        """(K M phase ms, Gram-Schmidt phase ms, Gram-Schmidt algorithmic bytes)."""
-        out = np.zeros(3)
+        """dict: K M phase ms, Gram-Schmidt phase ms and algorithmic bytes,
+        M2L launch ms, flops and count (lm_server_phase_times)."""
+        out = np.zeros(6)
         _check(lib().lm_server_phase_times(self.h, _dptr(out)))
-        return float(out[0]), float(out[1]), float(out[2])
+        return dict(zip(["km_ms", "gs_ms", "gs_bytes", "m2l_ms", "m2l_flops", "m2l_launches"], [float(v) for v in out]))
 
     def close(self):
         if self.h:
