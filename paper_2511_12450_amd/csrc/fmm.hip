@@ -431,14 +431,16 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
 // (2P x R) in 16x16x4 FP32 MFMA tiles (16 x 16 output tiles spread over the
 // four wavefronts, FP32 accumulation).
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int MF_TPW = 8;   // output tiles per wavefront: ceil(ceil(2P/16) ceil(R/16) / 4) <= 8
 constexpr int MF_ST = 8;    // staging loads in flight per lane
 // Work item = (target, first entry, end) with at most M2L_ITEM entries; each
 // item leaves a partial local expansion, summed per target by k_p2m_reduce.
-__global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __restrict__ items,
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_m2l_mfma(int p, int R, const int* __restrict__ items,
                                                   const int* __restrict__ src, const int* __restrict__ opi,
                                                   const float2* __restrict__ ops, const float2* __restrict__ me,
-                                                  float2* __restrict__ part) {
+                                                  float2* __restrict__ part, const int* __restrict__ dtgt,
+                                                  int accumulate) {
+  constexpr int TPW = 32 / NW;  // output tiles per wavefront (at most 32 tiles: 2P <= 128, R <= 64)
   const int P = 2 * p + 1, PR = P * R, P2 = 2 * P, PP = P * P, NS = PP + PR;
   const int MT = (P2 + 15) / 16, NT = (R + 15) / 16, KS = (P2 + 3) / 4, ntile = MT * NT;
   extern __shared__ unsigned char dyn[];
@@ -447,12 +449,15 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __res
   const float2* A = S + PP;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  // per-tile operand coordinates (fixed for the whole launch)
-  int mrow[MF_TPW], jcol[MF_TPW];
-  bool ire[MF_TPW], ival[MF_TPW], jval[MF_TPW];
+  // per-tile operand coordinates (fixed for the whole launch); for NT in
+  // {1, 2, 4} every tile of a wavefront has the same column block, so its B
+  // operand is loaded once per k-step
+  const bool bshared = (NW % NT) == 0;
+  int mrow[TPW], jcol[TPW];
+  bool ire[TPW], ival[TPW], jval[TPW];
 #pragma unroll
-  for (int t = 0; t < MF_TPW; ++t) {
-    const int tile = wv + 4 * t;
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wv + NW * t;
     const int i = 16 * (tile / NT) + l16, j = 16 * (tile % NT) + l16;
     ival[t] = tile < ntile && i < P2;
     ire[t] = i < P;
@@ -460,23 +465,23 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __res
     jval[t] = tile < ntile && j < R;
     jcol[t] = jval[t] ? j : 0;
   }
-  v4f acc[MF_TPW];
+  v4f acc[TPW];
 #pragma unroll
-  for (int t = 0; t < MF_TPW; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TPW; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int e = items[3 * blockIdx.x + 1]; e < items[3 * blockIdx.x + 2]; ++e) {
     const float2* Tg = ops + (int64_t)opi[e] * PP;
     const float2* Ag = me + (int64_t)src[e] * PR;
     __syncthreads();
-    for (int base = threadIdx.x; base < NS; base += 256 * MF_ST) {  // MF_ST loads in flight per lane
+    for (int base = threadIdx.x; base < NS; base += 64 * NW * MF_ST) {  // MF_ST loads in flight per lane
       float2 v[MF_ST];
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 256 * u;
+        const int idx = base + 64 * NW * u;
         if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
       }
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 256 * u;
+        const int idx = base + 64 * NW * u;
         if (idx < NS) S[idx] = v[u];
       }
     }
@@ -487,22 +492,32 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __res
       const int n = kv ? (kre ? k : k - P) : 0;
       const float2* Tn = T + n * P;
       const float2* An = A + n * R;
+      float bs = 0.f;
+      if (bshared) {
+        const float2 sv = An[jcol[0]];
+        bs = (kv && jval[0]) ? (kre ? sv.x : sv.y) : 0.f;
+      }
 #pragma unroll
-      for (int t = 0; t < MF_TPW; ++t) {
-        if (wv + 4 * t < ntile) {  // wave-uniform
+      for (int t = 0; t < TPW; ++t) {
+        if (wv + NW * t < ntile) {  // wave-uniform
           const float2 tv = Tn[mrow[t]];
-          const float2 sv = An[jcol[t]];
           const float av = (kv && ival[t]) ? (ire[t] ? (kre ? tv.x : -tv.y) : (kre ? tv.y : tv.x)) : 0.f;
-          const float bv = (kv && jval[t]) ? (kre ? sv.x : sv.y) : 0.f;
+          float bv = bs;
+          if (!bshared) {
+            const float2 sv = An[jcol[t]];
+            bv = (kv && jval[t]) ? (kre ? sv.x : sv.y) : 0.f;
+          }
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
         }
       }
     }
   }
-  float* out = reinterpret_cast<float*>(part + (int64_t)blockIdx.x * PR);
+  // partial slot of this item, or (translations with one item per box) the
+  // output expansion itself, overwritten or accumulated
+  float* out = reinterpret_cast<float*>(part + (int64_t)(dtgt ? dtgt[blockIdx.x] : (int)blockIdx.x) * PR);
 #pragma unroll
-  for (int t = 0; t < MF_TPW; ++t) {
-    const int tile = wv + 4 * t;
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wv + NW * t;
     if (tile < ntile) {
       const int j = 16 * (tile % NT) + l16;
 #pragma unroll
@@ -510,7 +525,8 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(int p, int R, const int* __res
         const int i = 16 * (tile / NT) + 4 * kq + v;
         if (i < P2 && j < R) {
           const bool ir = i < P;
-          out[2 * ((ir ? i : i - P) * R + j) + (ir ? 0 : 1)] = acc[t][v];
+          float* o = out + 2 * ((ir ? i : i - P) * R + j) + (ir ? 0 : 1);
+          *o = accumulate ? *o + acc[t][v] : acc[t][v];
         }
       }
     }
@@ -691,8 +707,8 @@ __global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumul
 }
 
 // y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row;
-// right-hand sides in groups of four share each matrix value and index load.
-template <typename RT>
+// right-hand sides in groups of G share each matrix value and index load.
+template <typename RT, int G>
 __global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __restrict__ ptr,
                                                   const int* __restrict__ src,
                                                   const typename C2T<RT>::T* __restrict__ val,
@@ -703,17 +719,19 @@ __global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __res
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
   const int e0 = ptr[row], e1 = ptr[row + 1];
-  for (int g = 0; g < R; g += 4) {
-    RT re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+  for (int g = 0; g < R; g += G) {
+    RT re[G], im[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) re[u] = im[u] = RT(0);
     for (int e = e0 + lane; e < e1; e += 64) {
       const V a = val[e];
       const int c = src[e];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < G; ++u)
         if (g + u < R) cmac(re[u], im[u], a, x[(int64_t)(g + u) * N + c]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < G; ++u)
       if (g + u < R)
         for (int off = 32; off > 0; off >>= 1) {
           re[u] += __shfl_xor(re[u], off, 64);
@@ -721,7 +739,7 @@ __global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __res
         }
     if (lane == 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < G; ++u) {
         if (g + u < R) {
           V* yp = y + (int64_t)(g + u) * N + row;
           const V o = *yp;
@@ -1229,6 +1247,43 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       }
   }
 
+  // ---- translation items for the matrix-core M2M / L2L ------------------------------
+  // M2M: item k = parent parents_by_level[k], entries = its children with
+  // their M2M operators; L2L: one item per box of level >= 1 (in box order),
+  // entry = its parent with the L2L operator.  Operator indices count from the
+  // start of the operator array.
+  {
+    auto tr_op = [&](const BoxDev& c, int base) { return base + (tree_layer[c.tree] * nlev + c.level) * 4 + c.pos; };
+    for (int b : F->parents_by_level) {
+      const BoxDev& B = F->boxes[b];
+      F->tr_item.push_back(0);
+      F->tr_item.push_back((int)F->tr_src.size());
+      for (int c = 0; c < B.nchild; ++c) {
+        const int cb = F->children[B.child0 + c];
+        F->tr_src.push_back(cb);
+        F->tr_op.push_back(tr_op(F->boxes[cb], 0));
+      }
+      F->tr_item.push_back((int)F->tr_src.size());
+    }
+    F->l2l_item0 = (int)F->tr_item.size() / 3;
+    for (int b = F->level_ptr[1]; b < F->n_boxes; ++b) {
+      const BoxDev& B = F->boxes[b];
+      F->tr_item.push_back(0);
+      F->tr_item.push_back((int)F->tr_src.size());
+      F->tr_src.push_back(B.parent);
+      F->tr_op.push_back(tr_op(B, F->n_tree_ops));
+      F->tr_item.push_back((int)F->tr_src.size());
+    }
+  }
+  {
+    std::vector<int> ids(F->n_boxes);
+    for (int b = 0; b < F->n_boxes; ++b) ids[b] = b;
+    LM_TRY(up(F->d_box_id, ids, s));
+  }
+  LM_TRY(up(F->d_tr_item, F->tr_item, s));
+  LM_TRY(up(F->d_tr_src, F->tr_src, s));
+  LM_TRY(up(F->d_tr_op, F->tr_op, s));
+
   // ---- upload and device setup ---------------------------------------------------
   LM_TRY(up(F->d_boxes, F->boxes, s));
   LM_TRY(up(F->d_children, F->children, s));
@@ -1402,12 +1457,22 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   }
   LM_STAGE(0, 0);
   LM_STAGE(1, 1);
-  // M2M, finest parents first
+  // M2M, finest parents first (FP32 with several right-hand sides: matrix
+  // cores, one item per parent holding its children)
+  const bool tr_mfma = sizeof(RT) == 4 && R > 1;
+  const size_t lds_tr = (PP + PR) * sizeof(float2);
   for (int l = nlev - 2; l >= 0; --l) {
     const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
-    if (n)
+    if (!n) continue;
+    if (tr_mfma) {
+      const int i0 = F->parents_ptr[l];
+      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(n), dim3(512), lds_tr, s, p, R, F->d_tr_item.as<int>() + 3 * i0,
+                         F->d_tr_src.as<int>(), F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)me,
+                         (float2*)me, F->d_parents.as<int>() + i0, 0);
+    } else {
       hipLaunchKernelGGL(k_m2m<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev,
                          F->d_parents.as<int>() + F->parents_ptr[l], boxes, F->d_children.as<int>(), tl, ops, me);
+    }
   }
   LM_STAGE(1, 0);
   // M2L (every level at once); boxes without a list start from zero
@@ -1423,9 +1488,9 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
                          F->d_m2l_ptr.as<int>(), out, le);
     } else if (sizeof(RT) == 4) {
       float2* mpart = F->d_mf_part.as<float2>();
-      hipLaunchKernelGGL(k_m2l_mfma, dim3(F->mf_item.size() / 3), dim3(256), (PP + PR) * sizeof(float2), s, p, R,
+      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(F->mf_item.size() / 3), dim3(512), (PP + PR) * sizeof(float2), s, p, R,
                          F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_op.as<int>(), (const float2*)mops,
-                         (const float2*)me, mpart);
+                         (const float2*)me, mpart, (const int*)nullptr, 0);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
                          F->d_mf_ptr.as<int>(), mpart, (float2*)le);
     } else {
@@ -1436,12 +1501,19 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   }
   LM_STAGE(2, 0);
   LM_STAGE(3, 1);
-  // L2L, coarse to fine
+  // L2L, coarse to fine (matrix cores as for M2M: one item per child box)
   for (int l = 1; l < nlev; ++l) {
     const int n = F->level_ptr[l + 1] - F->level_ptr[l];
-    if (n)
+    if (!n) continue;
+    if (tr_mfma) {
+      const int i0 = F->l2l_item0 + F->level_ptr[l] - F->level_ptr[1];
+      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(n), dim3(512), lds_tr, s, p, R, F->d_tr_item.as<int>() + 3 * i0,
+                         F->d_tr_src.as<int>(), F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)le,
+                         (float2*)le, F->d_box_id.as<int>() + F->level_ptr[l], 1);
+    } else {
       hipLaunchKernelGGL(k_l2l<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev, F->level_ptr[l], boxes, tl,
                          ops + (size_t)F->n_tree_ops * PP, le);
+    }
   }
   LM_STAGE(3, 0);
   LM_STAGE(4, 1);
@@ -1460,8 +1532,12 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(4, 0);
   LM_STAGE(5, 1);
   // near fields and self terms
-  hipLaunchKernelGGL(k_near_csr<RT>, dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
-                     F->d_nm_src.as<int>(), nmv, x, y);
+  if (R >= 8)
+    hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
+                       F->d_nm_src.as<int>(), nmv, x, y);
+  else
+    hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
+                       F->d_nm_src.as<int>(), nmv, x, y);
   LM_STAGE(5, 0);
   LM_STAGE(6, 1);
   LM_STAGE(6, 0);

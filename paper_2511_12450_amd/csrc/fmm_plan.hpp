@@ -46,6 +46,8 @@ struct FmmPlan {
   std::vector<int> tm_ptr, tm_slot, tm_src;
   std::vector<int> tm_item;  // (operator, first entry, end) work items
   std::vector<int> mf_item, mf_ptr;  // (target slot, first entry, end) items, items per target
+  std::vector<int> tr_item, tr_src, tr_op;  // matrix-core M2M (per parent) and L2L (per box) items
+  int l2l_item0 = 0;
   int n_reac_tab = 0, n_free_tab = 0;
   // expansion scales sig[layer][level][0..p]; translation operators, P x P
   // each, column-major by input: [M2M: layer, level, pos][L2L: same][M2L]
@@ -62,6 +64,7 @@ struct FmmPlan {
   DevBuf d_near_tgt, d_near_ptr, d_near_src;
   DevBuf d_rn_ptr, d_rn_src, d_rn_val;
   DevBuf d_self, d_me, d_le, d_tree_layer;
+  DevBuf d_tr_item, d_tr_src, d_tr_op, d_box_id;
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   int64_t bytes() const {
@@ -69,7 +72,7 @@ struct FmmPlan {
                            &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64, &d_ops32,
                            &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
                            &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
-                           &d_nm_val32, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
+                           &d_nm_val32, &d_tr_item, &d_tr_src, &d_tr_op, &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

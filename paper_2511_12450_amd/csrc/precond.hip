@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
 // neighbourhood in chunks of PA_KC complex columns staged in LDS (Z chunk
 // transposed to [j][r], X chunk converted from FP64 to FP32).
 typedef float pa_v4f __attribute__((ext_vector_type(4)));
-constexpr int PA_ROWS = 64, PA_KC = 32, PA_TPW = 8;
-__global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int* __restrict__ items,
+constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_TPW = 32 / PA_NW;
+__global__ void __launch_bounds__(64 * PA_NW) k_pre_apply_mfma(int N, int R, const int* __restrict__ items,
                                                         const int* __restrict__ jptr, const int* __restrict__ jidx,
                                                         const int* __restrict__ nb, const int64_t* __restrict__ zoff,
                                                         const float2* __restrict__ Z, const double2* __restrict__ x,
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int*
   bool ire[PA_TPW], ival[PA_TPW], jval[PA_TPW];
 #pragma unroll
   for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + 4 * t;
+    const int tile = wv + PA_NW * t;
     const int i = 16 * (tile / NT) + l16, jj = 16 * (tile % NT) + l16;
     ival[t] = tile < ntile && i < R2;
     ire[t] = i < rows;
@@ -199,11 +199,11 @@ __global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int*
   for (int c0 = 0; c0 < q; c0 += PA_KC) {
     const int kc = min(PA_KC, q - c0);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 256) {
+    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 64 * PA_NW) {
       const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a Z row
       Zs[jj][rr] = (rr < rows && jj < kc) ? Zl[(int64_t)rr * q + c0 + jj] : make_float2(0.f, 0.f);
     }
-    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 256) {
+    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 64 * PA_NW) {
       const int jj = idx >> 6, rr = idx & 63;
       float2 v = make_float2(0.f, 0.f);
       if (jj < kc && rr < R) {
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int*
       const int n = kre ? k : k - PA_KC;
 #pragma unroll
       for (int t = 0; t < PA_TPW; ++t) {
-        if (wv + 4 * t < ntile) {  // wave-uniform
+        if (wv + PA_NW * t < ntile) {  // wave-uniform
           const float2 zv = Zs[n][mrow[t]];
           const float2 xv = Xs[n][jcol[t]];
           const float av = ival[t] ? (ire[t] ? (kre ? zv.x : -zv.y) : (kre ? zv.y : zv.x)) : 0.f;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_pre_apply_mfma(int N, int R, const int*
   double* yd = reinterpret_cast<double*>(y);
 #pragma unroll
   for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + 4 * t;
+    const int tile = wv + PA_NW * t;
     if (tile < ntile) {
       const int jj = 16 * (tile % NT) + l16;
 #pragma unroll
@@ -358,7 +358,7 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
   if (precision == LM_MIXED && n_rhs > 1) {
     for (int r0 = 0; r0 < n_rhs; r0 += 64) {
       const int R = std::min(64, n_rhs - r0);
-      hipLaunchKernelGGL(k_pre_apply_mfma, dim3(P->items.size() / 2), dim3(256), 0, s, (int)g->N, R,
+      hipLaunchKernelGGL(k_pre_apply_mfma, dim3(P->items.size() / 2), dim3(64 * PA_NW), 0, s, (int)g->N, R,
                          P->d_items.as<int>(), P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(),
                          P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(), (const double2*)x + (int64_t)r0 * g->N,
                          (double2*)y + (int64_t)r0 * g->N);
