@@ -209,7 +209,7 @@ def main():
     gs_avg_s = ph["gs_ms"] * 1e-3 / max(rounds, 1)
     gs_bytes = ph["gs_bytes"] / max(rounds, 1)
     gs_roof = {"bound": "hbm", "achieved": gs_bytes / gs_avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-               "traffic": None, "kernel": "k_s_dots+k_s_update x2 (+ k_s_dots_final, k_s_resid, k_s_norm_final)",
+               "traffic": None, "kernel": "k_s_dots2 + k_s_update2 (delayed CGS2; + k_s_dots2_final, k_s_resid, k_s_norm_final, k_s_norm_to)",
                "kernel_avg_us": gs_avg_s * 1e6, "launches": int(rounds), "algorithmic_bytes_per_launch": gs_bytes}
     gs_roof["frac"] = gs_roof["achieved"] / PEAK_HBM_GBS
     tr = _traffic()

@@ -241,10 +241,13 @@ lm_status lm_server_stats(lm_server server, int64_t* out6);
 /* Host output of 6 doubles accumulated over the server's rounds, measured
  * with HIP events on the streams the kernels run on: [0] ms in the fused
  * K M phase (gathers, preconditioner, matvecs; every geometry stream
- * joined), [1] ms in the Gram-Schmidt phase (two classical passes over each
- * basis plus the norms), [2] bytes that phase must move at minimum: per
- * Arnoldi column with j+1 basis vectors of N complex doubles,
- * 2 x (2 (j+1) + 3) N x 16, plus N x 16 for the norm; [3] ms in the M2L
+ * joined), [1] ms in the Gram-Schmidt phase (classical Gram-Schmidt with a
+ * delayed second pass: one dot pass and one update pass over each basis,
+ * plus the norms), [2] bytes that phase must move at minimum: per Arnoldi
+ * column at step j (basis V[0..j] of N complex doubles),
+ * (2 (j+1) + 6) N x 16 (dot pass: V[0..j] and the K M output; update pass:
+ * V[0..j-1], u and the K M output read, v_j and the next vector written),
+ * plus N x 16 per column for the norms; [3] ms in the M2L
  * launches of the fused FMM matvecs (first launch of each geometry stream
  * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
  * [5] the number of those launches. */

@@ -10,12 +10,19 @@
 //      incidence angles of different requests on the same geometry share the
 //      FMM passes); groups of different geometries go to different streams
 //      and overlap on the device;
-//   2. one batched two-pass classical Gram-Schmidt over every Arnoldi column
-//      (each with its own basis length), residual updates for columns that
-//      restart or finish, and one device-to-host copy of the new Hessenberg
-//      columns and norms;
-//   3. Givens rotations and convergence tests on the host, then batched
-//      basis-vector scaling and solution updates.
+//   2. Arnoldi orthogonalisation by classical Gram-Schmidt with a delayed
+//      second pass (each column with its own basis length): the vector u_j
+//      sent through K M is orthogonalised once; at the next step one read of
+//      the basis computes both V^H u_j (its re-orthogonalisation) and
+//      V^H K M u_j, the Hessenberg column of step j-1 is corrected, and one
+//      more read produces the re-orthogonalised v_j and the once-projected
+//      next vector.  Two passes over the basis per step instead of four,
+//      with the accuracy of two-pass CGS; the Hessenberg column (and the
+//      residual estimate) lags one step.  Residual updates for columns that
+//      restart or finish, and one device-to-host copy of the dot products
+//      and norms per round;
+//   3. Givens rotations and convergence tests on the host, then the batched
+//      update pass and solution updates.
 // Requests that arrive while others run are admitted at the next round as
 // soon as right-hand-side slots and the HBM budget allow; a request whose
 // footprint can never fit is rejected at submission.  Finished requests keep
@@ -54,7 +61,10 @@ struct ColDev {
   const double2* src; // copy / scale source
   double2* dst;       // copy / scale destination
   double2* z;         // solution accumulator
-  const double2* y;   // combination coefficients
+  const double2* y;   // combination / update coefficients
+  const double* nsrc; // squared norm to normalise by (device), or null
+  double* ndst;       // squared norm output (device), or null
+  double2 dr;         // complex scalar of the update pass
   double scale;
   int N, cnt;
 };
@@ -77,7 +87,7 @@ __device__ __forceinline__ double s_wave_sum(double v) {
 __global__ void __launch_bounds__(256) k_s_resid(const ColDev* __restrict__ d, double* __restrict__ part, int nw) {
   const ColDev c = d[blockIdx.y];
   const int n = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= c.N) return;  // whole workgroup beyond this column
+  if (blockIdx.x * 256 >= c.N || !c.w) return;  // beyond this column, or nothing to do
   double q = 0.0;
   if (n < c.N) {
     double2 v = c.w[n];
@@ -92,106 +102,20 @@ __global__ void __launch_bounds__(256) k_s_resid(const ColDev* __restrict__ d, d
   if ((threadIdx.x & 63) == 0) part[(int64_t)blockIdx.y * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = q;
 }
 
-// nrm[col] = sum of the column's wave partials (4 per 256 elements).
+// nrm[col] = sum of the column's wave partials (4 per 256 elements), or the
+// norm an earlier pass left at nsrc.
 __global__ void __launch_bounds__(64) k_s_norm_final(const ColDev* __restrict__ d, const double* __restrict__ part,
                                                      int nw, double* __restrict__ nrm) {
-  const int nwc = 4 * ((d[blockIdx.x].N + 255) / 256);
+  const ColDev c = d[blockIdx.x];
+  if (c.nsrc) {  // a norm computed by an earlier pass
+    if (threadIdx.x == 0) nrm[blockIdx.x] = *c.nsrc;
+    return;
+  }
+  const int nwc = 4 * ((c.N + 255) / 256);
   double q = 0.0;
   for (int k = threadIdx.x; k < nwc; k += 64) q += part[(int64_t)blockIdx.x * nw + k];
   q = s_wave_sum(q);
   if (threadIdx.x == 0) nrm[blockIdx.x] = q;
-}
-
-// Workgroup partials of conj(V[i]) . w for i in this workgroup's block of
-// basis vectors: part[(col ldh + i) nb + blockIdx.x].
-__global__ void __launch_bounds__(256) k_s_dots(const ColDev* __restrict__ d, double2* __restrict__ part, int ldh,
-                                                int nb) {
-  const ColDev c = d[blockIdx.y];
-  const int ib = blockIdx.z * SD_IBLK;
-  if (ib >= c.cnt || blockIdx.x * SD_SLICE >= c.N) return;  // uniform per workgroup
-  const int ie = min(c.cnt, ib + SD_IBLK);
-  constexpr int EPT = SD_SLICE / 256;
-  double2 x[EPT];
-  int idx[EPT];
-  bool ok[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int n = blockIdx.x * SD_SLICE + threadIdx.x + 256 * e;
-    ok[e] = n < c.N;
-    idx[e] = ok[e] ? n : 0;
-    x[e] = ok[e] ? c.w[idx[e]] : make_double2(0.0, 0.0);
-  }
-  __shared__ double red[2][4];
-  for (int i = ib; i < ie; ++i) {
-    const double2* v = c.V + (int64_t)i * c.N;
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const double2 a = ok[e] ? v[idx[e]] : make_double2(0.0, 0.0);
-      re = fma(a.x, x[e].x, re);
-      re = fma(a.y, x[e].y, re);
-      im = fma(a.x, x[e].y, im);
-      im = fma(-a.y, x[e].x, im);
-    }
-    re = s_wave_sum(re);
-    im = s_wave_sum(im);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      red[0][threadIdx.x >> 6] = re;
-      red[1][threadIdx.x >> 6] = im;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-      part[((int64_t)blockIdx.y * ldh + i) * nb + blockIdx.x] =
-          make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]), (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
-  }
-}
-
-// h[col hs + off + i] = sum of the column's workgroup partials  (grid (cntmax, ncols)).
-__global__ void __launch_bounds__(64) k_s_dots_final(const ColDev* __restrict__ d, const double2* __restrict__ part,
-                                                     int ldh, int nb, double2* __restrict__ h, int hs, int off) {
-  const ColDev c = d[blockIdx.y];
-  const int i = blockIdx.x;
-  if (i >= c.cnt) return;
-  const int nbc = (c.N + SD_SLICE - 1) / SD_SLICE;
-  double re = 0.0, im = 0.0;
-  for (int k = threadIdx.x; k < nbc; k += 64) {
-    const double2 v = part[((int64_t)blockIdx.y * ldh + i) * nb + k];
-    re += v.x;
-    im += v.y;
-  }
-  re = s_wave_sum(re);
-  im = s_wave_sum(im);
-  if (threadIdx.x == 0) h[(int64_t)blockIdx.y * hs + off + i] = make_double2(re, im);
-}
-
-// w -= sum_{i < cnt} V[i] h[i]
-__global__ void __launch_bounds__(256) k_s_update(const ColDev* __restrict__ d, const double2* __restrict__ h, int hs,
-                                                  int off) {
-  const ColDev c = d[blockIdx.y];
-  if (blockIdx.x * 256 >= c.N || c.cnt == 0) return;
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  const bool ok = n < c.N;
-  const int o = ok ? n : 0;
-  const double2* hc = h + (int64_t)blockIdx.y * hs + off;
-  double2 acc = ok ? c.w[o] : make_double2(0.0, 0.0);
-  constexpr int U = 8;
-  for (int i0 = 0; i0 < c.cnt; i0 += U) {
-    double2 v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = (i0 + u < c.cnt) ? c.V[(int64_t)(i0 + u) * c.N + o] : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (i0 + u < c.cnt) {
-        const double2 hv = hc[i0 + u];
-        acc.x = fma(-hv.x, v[u].x, acc.x);
-        acc.x = fma(hv.y, v[u].y, acc.x);
-        acc.y = fma(-hv.x, v[u].y, acc.y);
-        acc.y = fma(-hv.y, v[u].x, acc.y);
-      }
-    }
-  }
-  if (ok) c.w[o] = acc;
 }
 
 // z += sum_{i < cnt} V[i] y[i]
@@ -210,6 +134,162 @@ __global__ void __launch_bounds__(256) k_s_lincomb(const ColDev* __restrict__ d)
   c.z[n] = acc;
 }
 
+// Gathers the K M inputs of Arnoldi columns and normalises lagged basis
+// vectors: v = w * s with s = 1/sqrt(*nsrc) (then written back to w) or
+// s = scale; dst (the fused launch's input slot) may be null.
+__global__ void __launch_bounds__(256) k_s_gather(const ColDev* __restrict__ d) {
+  const ColDev c = d[blockIdx.y];
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= c.N) return;
+  const double s = c.nsrc ? 1.0 / sqrt(*c.nsrc) : c.scale;
+  double2 v = c.w[n];
+  v = make_double2(v.x * s, v.y * s);
+  if (c.nsrc) c.w[n] = v;
+  if (c.dst) c.dst[n] = v;
+}
+
+// Workgroup partials of conj(V[i]) . u and conj(V[i]) . z, u = V[cnt-1],
+// z = the K M output (or none), for the basis vectors of this workgroup.
+__global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, double2* __restrict__ pa,
+                                                 double2* __restrict__ pb, int ldh, int nb) {
+  const ColDev c = d[blockIdx.y];
+  const int ib = blockIdx.z * SD_IBLK;
+  if (ib >= c.cnt || blockIdx.x * SD_SLICE >= c.N) return;  // uniform per workgroup
+  const int ie = min(c.cnt, ib + SD_IBLK);
+  constexpr int EPT = SD_SLICE / 256;
+  const double2* u = c.V + (int64_t)(c.cnt - 1) * c.N;
+  double2 xu[EPT], xz[EPT];
+  int idx[EPT];
+  bool ok[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int n = blockIdx.x * SD_SLICE + threadIdx.x + 256 * e;
+    ok[e] = n < c.N;
+    idx[e] = ok[e] ? n : 0;
+    xu[e] = ok[e] ? u[idx[e]] : make_double2(0.0, 0.0);
+    xz[e] = (ok[e] && c.w) ? c.w[idx[e]] : make_double2(0.0, 0.0);
+  }
+  __shared__ double red[4][4];
+  for (int i = ib; i < ie; ++i) {
+    const double2* v = c.V + (int64_t)i * c.N;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const double2 a = ok[e] ? v[idx[e]] : make_double2(0.0, 0.0);
+      ar = fma(a.x, xu[e].x, ar);
+      ar = fma(a.y, xu[e].y, ar);
+      ai = fma(a.x, xu[e].y, ai);
+      ai = fma(-a.y, xu[e].x, ai);
+      br = fma(a.x, xz[e].x, br);
+      br = fma(a.y, xz[e].y, br);
+      bi = fma(a.x, xz[e].y, bi);
+      bi = fma(-a.y, xz[e].x, bi);
+    }
+    ar = s_wave_sum(ar);
+    ai = s_wave_sum(ai);
+    br = s_wave_sum(br);
+    bi = s_wave_sum(bi);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = ar;
+      red[1][threadIdx.x >> 6] = ai;
+      red[2][threadIdx.x >> 6] = br;
+      red[3][threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t o = ((int64_t)blockIdx.y * ldh + i) * nb + blockIdx.x;
+      pa[o] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                           (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+      pb[o] = make_double2((red[2][0] + red[2][1]) + (red[2][2] + red[2][3]),
+                           (red[3][0] + red[3][1]) + (red[3][2] + red[3][3]));
+    }
+  }
+}
+
+// h[col hs + i] = sum of a-partials, h[col hs + ldh + i] = sum of b-partials.
+__global__ void __launch_bounds__(64) k_s_dots2_final(const ColDev* __restrict__ d, const double2* __restrict__ pa,
+                                                      const double2* __restrict__ pb, int ldh, int nb,
+                                                      double2* __restrict__ h, int hs) {
+  const ColDev c = d[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= c.cnt) return;
+  const int nbc = (c.N + SD_SLICE - 1) / SD_SLICE;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  for (int k = threadIdx.x; k < nbc; k += 64) {
+    const int64_t o = ((int64_t)blockIdx.y * ldh + i) * nb + k;
+    ar += pa[o].x;
+    ai += pa[o].y;
+    br += pb[o].x;
+    bi += pb[o].y;
+  }
+  ar = s_wave_sum(ar);
+  ai = s_wave_sum(ai);
+  br = s_wave_sum(br);
+  bi = s_wave_sum(bi);
+  if (threadIdx.x == 0) {
+    h[(int64_t)blockIdx.y * hs + i] = make_double2(ar, ai);
+    h[(int64_t)blockIdx.y * hs + ldh + i] = make_double2(br, bi);
+  }
+}
+
+// One read of the basis V[0..cnt-1] (cnt = j) produces
+//   V[j]   <- (u - sum_i a_i V[i]) * scale                (re-orthogonalised v_j)
+//   V[j+1] <- z * scale - u * dr - sum_i e_i V[i]          (once-projected next vector)
+// with u = V[j], z = the K M output, a = y[0..j), e = y[j..2j); wave
+// partials of |V[j+1]|^2 into part.
+__global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d, double* __restrict__ part, int nw) {
+  const ColDev c = d[blockIdx.y];
+  if (blockIdx.x * 256 >= c.N) return;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const bool ok = n < c.N;
+  const int o = ok ? n : 0;
+  const int j = c.cnt;
+  double2* uj = c.V + (int64_t)j * c.N;
+  const double2 u = uj[o];
+  double2 q = u;
+  const double2 zv = c.w[o];
+  double2 w = make_double2(zv.x * c.scale - (u.x * c.dr.x - u.y * c.dr.y),
+                           zv.y * c.scale - (u.x * c.dr.y + u.y * c.dr.x));
+  constexpr int U = 8;
+  for (int i0 = 0; i0 < j; i0 += U) {
+    double2 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = (i0 + k < j) ? c.V[(int64_t)(i0 + k) * c.N + o] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (i0 + k < j) {
+        const double2 a = c.y[i0 + k], e = c.y[j + i0 + k];
+        q.x = fma(-a.x, v[k].x, q.x);
+        q.x = fma(a.y, v[k].y, q.x);
+        q.y = fma(-a.x, v[k].y, q.y);
+        q.y = fma(-a.y, v[k].x, q.y);
+        w.x = fma(-e.x, v[k].x, w.x);
+        w.x = fma(e.y, v[k].y, w.x);
+        w.y = fma(-e.x, v[k].y, w.y);
+        w.y = fma(-e.y, v[k].x, w.y);
+      }
+    }
+  }
+  if (ok) {
+    uj[o] = make_double2(q.x * c.scale, q.y * c.scale);
+    uj[c.N + o] = w;
+  }
+  const double qn = s_wave_sum(ok ? w.x * w.x + w.y * w.y : 0.0);
+  if ((threadIdx.x & 63) == 0) part[(int64_t)blockIdx.y * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = qn;
+}
+
+// *ndst = sum of the column's wave partials.
+__global__ void __launch_bounds__(64) k_s_norm_to(const ColDev* __restrict__ d, const double* __restrict__ part,
+                                                  int nw) {
+  const ColDev c = d[blockIdx.x];
+  const int nwc = 4 * ((c.N + 255) / 256);
+  double q = 0.0;
+  for (int k = threadIdx.x; k < nwc; k += 64) q += part[(int64_t)blockIdx.x * nw + k];
+  q = s_wave_sum(q);
+  if (threadIdx.x == 0) *c.ndst = q;
+}
+
 enum Phase { PH_INIT = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_FINAL = 3 };
 
 struct Request;
@@ -220,11 +300,12 @@ struct Column {
   lm_geom_s* g = nullptr;
   int N = 0, m = 0;
   Phase phase = PH_INIT;
-  DevBuf V, z, gv, y;
+  DevBuf V, z, gv, y, dn;  // dn: squared norm of the once-projected next vector
   int j = 0, its = 0, ncols = 0;
   double gnorm = 0.0, res = 1.0;
   bool converged = false, finished = false;
-  std::vector<C> H, cs, sn, e1;
+  bool km = false;        // needs K M this round
+  std::vector<C> H, Hraw, cs, sn, e1, cprev;  // rotated / raw Hessenberg, provisional column
   double2* w = nullptr;  // this round's vector (group output slice or gv)
 };
 
@@ -335,9 +416,12 @@ lm_status start_request(lm_server_s* S, Request* q) {
     LM_TRY(col->z.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->gv.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->y.alloc((size_t)(m + 1) * sizeof(double2)));
+    LM_TRY(col->dn.alloc(sizeof(double)));
     LM_TRY_HIP(hipMemsetAsync(col->z.p, 0, (size_t)N * sizeof(double2), S->s));
     LM_TRY(rhs_launch(q->g, 1, &q->theta[c], col->gv.p, S->s));
     col->H.assign((size_t)(m + 1) * m, 0.0);
+    col->Hraw.assign((size_t)(m + 1) * m, 0.0);
+    col->cprev.assign(m + 1, 0.0);
     col->cs.assign(m, 0.0);
     col->sn.assign(m, 0.0);
     col->e1.assign(m + 1, 0.0);
@@ -384,15 +468,61 @@ lm_status round(lm_server_s* S) {
     if (!c->finished) cols.push_back(c);
   if (cols.empty()) return LM_OK;
   const int prec = S->o.precision;
+  const int nc = (int)cols.size();
+  int Nmax = 0, ldh = 1, cntmax = 0;
+  for (Column* c : cols) {
+    Nmax = std::max(Nmax, c->N);
+    ldh = std::max(ldh, c->m + 1);
+    // an Arnoldi step needs K M u_j unless it can only finalise column j-1
+    // (restart length reached or the last allowed iteration)
+    c->km = c->phase == PH_RESTART || c->phase == PH_FINAL ||
+            (c->phase == PH_ARNOLDI && !(c->j >= 1 && (c->j == c->m || c->its + 1 >= c->req->o.max_iter)));
+    if (c->phase == PH_ARNOLDI) cntmax = std::max(cntmax, c->j + 1);
+  }
+  const int nwu = 4 * (int)div_up(Nmax, 256), nbd = (int)div_up(Nmax, SD_SLICE);
+  const int hs = 2 * ldh;
   LM_TRY_HIP(hipEventRecord(S->t0, S->s));
   // ---- 1. K M v for every column that needs it, fused per (geometry, precond)
   std::map<std::pair<lm_geom_s*, int>, std::vector<Column*>> byg;
   for (Column* c : cols) {
-    if (c->phase == PH_INIT) {
-      c->w = c->gv.as<double2>();
-      continue;
+    c->w = c->phase == PH_INIT ? c->gv.as<double2>() : nullptr;
+    if (c->km) byg[{c->g, c->req->o.precond ? 1 : 0}].push_back(c);
+  }
+  // gather the inputs (normalising lagged basis vectors on the way): one kernel
+  std::vector<ColDev> gath;
+  for (auto& kv : byg) {
+    Group& G = S->groups[kv.first];
+    const int R = (int)kv.second.size(), N = (int)kv.first.first->N;
+    LM_TRY(ensure(G.X, (size_t)R * N * sizeof(double2)));
+    LM_TRY(ensure(G.Y, (size_t)R * N * sizeof(double2)));
+    for (int k = 0; k < R; ++k) {
+      Column* c = kv.second[k];
+      ColDev d{};
+      d.N = N;
+      d.dst = G.X.as<double2>() + (size_t)k * N;
+      d.scale = 1.0;
+      if (c->phase == PH_ARNOLDI) {
+        d.w = c->V.as<double2>() + (size_t)c->j * N;
+        d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;
+      } else {
+        d.w = c->z.as<double2>();
+      }
+      gath.push_back(d);
+      c->w = G.Y.as<double2>() + (size_t)k * N;
     }
-    byg[{c->g, c->req->o.precond ? 1 : 0}].push_back(c);
+  }
+  for (Column* c : cols)  // finalise-only steps still normalise their lagged vector
+    if (c->phase == PH_ARNOLDI && !c->km && c->j >= 1) {
+      ColDev d{};
+      d.N = c->N;
+      d.w = c->V.as<double2>() + (size_t)c->j * c->N;
+      d.nsrc = c->dn.as<double>();
+      gath.push_back(d);
+    }
+  if (!gath.empty()) {
+    LM_TRY(upload_desc(S, gath));
+    hipLaunchKernelGGL(k_s_gather, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s, S->d_desc.as<ColDev>());
+    LM_TRY_HIP(hipGetLastError());
   }
   LM_TRY_HIP(hipEventRecord(S->ev_main, S->s));
   std::vector<char> used_stream(SRV_STREAMS, 0), stream_timed(SRV_STREAMS, 0);
@@ -402,8 +532,7 @@ lm_status round(lm_server_s* S) {
   for (auto& kv : byg) {
     lm_geom_s* g = kv.first.first;
     const bool pre = kv.first.second && g->pre;
-    std::vector<Column*>& gc = kv.second;
-    const int R = (int)gc.size(), N = (int)g->N;
+    const int R = (int)kv.second.size();
     auto it = S->stream_of.find(g);
     if (it == S->stream_of.end()) it = S->stream_of.emplace(g, (int)(S->stream_of.size() % SRV_STREAMS)).first;
     const int si = it->second;
@@ -411,19 +540,9 @@ lm_status round(lm_server_s* S) {
     if (!used_stream[si]) LM_TRY_HIP(hipStreamWaitEvent(st, S->ev_main, 0));
     used_stream[si] = 1;
     Group& G = S->groups[kv.first];
-    LM_TRY(ensure(G.X, (size_t)R * N * sizeof(double2)));
-    LM_TRY(ensure(G.Y, (size_t)R * N * sizeof(double2)));
-    double2* X = G.X.as<double2>();
-    double2* Y = G.Y.as<double2>();
-    for (int k = 0; k < R; ++k) {
-      Column* c = gc[k];
-      const double2* in = c->phase == PH_ARNOLDI ? c->V.as<double2>() + (size_t)c->j * N : c->z.as<double2>();
-      LM_TRY_HIP(hipMemcpyAsync(X + (size_t)k * N, in, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, st));
-      c->w = Y + (size_t)k * N;
-    }
     const bool time_m2l = g->method == LM_FMM && !stream_timed[si];
     G.km.stage_ev = time_m2l ? S->sev[si] : nullptr;
-    LM_TRY(apply_km(g, prec, R, X, Y, pre, G.km, st));
+    LM_TRY(apply_km(g, prec, R, G.X.as<double2>(), G.Y.as<double2>(), pre, G.km, st));
     G.km.stage_ev = nullptr;
     if (time_m2l) {
       stream_timed[si] = 1;
@@ -443,91 +562,63 @@ lm_status round(lm_server_s* S) {
     }
   LM_TRY_HIP(hipEventRecord(S->t1, S->s));
   float km_round = 0.f;
-  // ---- 2. residuals, norms and batched CGS2 ------------------------------------
-  const int nc = (int)cols.size();
-  int Nmax = 0, ldh = 1, cntmax = 0;
-  for (Column* c : cols) {
-    Nmax = std::max(Nmax, c->N);
-    ldh = std::max(ldh, c->m + 1);
-    if (c->phase == PH_ARNOLDI) cntmax = std::max(cntmax, c->j + 1);
-  }
-  const int nwu = 4 * (int)div_up(Nmax, 256), nbd = (int)div_up(Nmax, SD_SLICE);
+  // ---- 2. dot products of the delayed two-pass Gram-Schmidt, residuals, norms
   LM_TRY(ensure(S->d_npart, (size_t)nc * nwu * sizeof(double)));
   LM_TRY(ensure(S->d_nrm, (size_t)nc * sizeof(double)));
-  LM_TRY(ensure(S->d_h, (size_t)nc * 2 * ldh * sizeof(double2)));
+  LM_TRY(ensure(S->d_h, (size_t)nc * hs * sizeof(double2)));
   S->hdesc.assign(nc, ColDev{});
   for (int i = 0; i < nc; ++i) {
     Column* c = cols[i];
     ColDev& d = S->hdesc[i];
     d.V = c->V.as<double2>();
-    d.w = c->w;
-    d.g = (c->phase == PH_RESTART || c->phase == PH_FINAL) ? c->gv.as<double2>() : nullptr;
     d.N = c->N;
-    d.cnt = c->phase == PH_ARNOLDI ? c->j + 1 : 0;
+    if (c->phase == PH_ARNOLDI) {
+      d.cnt = c->j + 1;  // dots against V[0..j]; u = V[j]
+      d.w = c->km ? c->w : nullptr;
+      d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;  // norm of u before normalisation
+    } else {
+      d.w = c->w;
+      d.g = (c->phase == PH_RESTART || c->phase == PH_FINAL) ? c->gv.as<double2>() : nullptr;
+    }
   }
   LM_TRY(upload_desc(S, S->hdesc));  // synchronises: the Gram-Schmidt timing starts after it
   LM_TRY_HIP(hipEventElapsedTime(&km_round, S->t0, S->t1));
   LM_TRY_HIP(hipEventRecord(S->t1, S->s));
   const ColDev* dd = S->d_desc.as<ColDev>();
-  const int hs = 2 * ldh;
   if (cntmax > 0) {
-    LM_TRY(ensure(S->d_dpart, (size_t)nc * ldh * nbd * sizeof(double2)));
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_s_dots, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd,
-                         S->d_dpart.as<double2>(), ldh, nbd);
-      hipLaunchKernelGGL(k_s_dots_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, S->d_dpart.as<double2>(), ldh, nbd,
-                         S->d_h.as<double2>(), hs, pass * ldh);
-      hipLaunchKernelGGL(k_s_update, dim3(div_up(Nmax, 256), nc), dim3(256), 0, S->s, dd, S->d_h.as<double2>(), hs,
-                         pass * ldh);
-    }
+    LM_TRY(ensure(S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
+    double2* pa = S->d_dpart.as<double2>();
+    double2* pb = pa + (size_t)nc * ldh * nbd;
+    hipLaunchKernelGGL(k_s_dots2, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb, ldh, nbd);
+    hipLaunchKernelGGL(k_s_dots2_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, pa, pb, ldh, nbd,
+                       S->d_h.as<double2>(), hs);
   }
-  // norms: of the orthogonalised vector (Arnoldi), of g - K M z (restart,
-  // final) or of g (first round)
+  // norms: of g - K M z (restart, final) or g (first round); Arnoldi columns
+  // report the norm the previous update pass left
   hipLaunchKernelGGL(k_s_resid, dim3(div_up(Nmax, 256), nc), dim3(256), 0, S->s, dd, S->d_npart.as<double>(), nwu);
   hipLaunchKernelGGL(k_s_norm_final, dim3(nc), dim3(64), 0, S->s, dd, S->d_npart.as<double>(), nwu,
                      S->d_nrm.as<double>());
   LM_TRY_HIP(hipGetLastError());
-  LM_TRY_HIP(hipEventRecord(S->t2, S->s));
-  double gsb = 0.0;
-  for (Column* c : cols) {  // bytes the CGS2 passes and the norm pass must move
-    const double n16 = 16.0 * c->N;
-    gsb += n16 + (c->phase == PH_ARNOLDI ? 2.0 * (2.0 * (c->j + 1) * n16 + 3.0 * n16) : 0.0);
-  }
   S->hh.resize((size_t)nc * hs);
   S->hnrm.resize(nc);
   if (cntmax > 0)
     LM_TRY_HIP(hipMemcpyAsync(S->hh.data(), S->d_h.p, (size_t)nc * hs * sizeof(double2), hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipMemcpyAsync(S->hnrm.data(), S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
+  LM_TRY_HIP(hipEventRecord(S->t2, S->s));
   LM_TRY_HIP(hipStreamSynchronize(S->s));
-  {
-    float b = 0.f, m2l = 0.f;
-    LM_TRY_HIP(hipEventElapsedTime(&b, S->t1, S->t2));
-    for (int si : timed_streams) {
-      float t = 0.f;
-      LM_TRY_HIP(hipEventElapsedTime(&t, S->sev[si][4], S->sev[si][5]));
-      m2l += t;
-    }
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->km_ms += km_round;
-    S->gs_ms += b;
-    S->m2l_ms += m2l;
-    S->m2l_flops += m2l_flops_round;
-    S->m2l_launches += (int64_t)timed_streams.size();
-    S->gs_bytes += gsb;
-    S->launches += n_launch;
-    S->fused_rhs += n_fused;
-    S->rounds++;
-  }
+  float gs_a = 0.f;
+  LM_TRY_HIP(hipEventElapsedTime(&gs_a, S->t1, S->t2));
   // ---- 3. host updates ------------------------------------------------------------
-  std::vector<ColDev> scal, comb;
-  std::vector<double2> ys;
-  std::vector<int> comb_col;
+  std::vector<ColDev> scal, comb, upd;
+  std::vector<double2> ys, cf;
   std::vector<Column*> to_finish;
+  double gsb = 0.0;
   for (int i = 0; i < nc; ++i) {
     Column* c = cols[i];
     const double nrm = std::sqrt(S->hnrm[i]);
     const double tol = c->req->o.tol;
     const int N = c->N, m = c->m;
+    const double n16 = 16.0 * N;
     auto start_cycle = [&](const double2* r, double beta) {
       c->j = 0;
       std::fill(c->e1.begin(), c->e1.end(), C(0.0));
@@ -540,7 +631,26 @@ lm_status round(lm_server_s* S) {
       scal.push_back(d);
       c->phase = PH_ARNOLDI;
     };
+    auto end_cycle = [&](int cnt, bool conv) {  // y = H^{-1} e1 over cnt columns, z += V y
+      std::vector<C> yv(cnt);
+      for (int k = cnt - 1; k >= 0; --k) {
+        C acc = c->e1[k];
+        for (int l = k + 1; l < cnt; ++l) acc -= c->H[(size_t)l * (m + 1) + k] * yv[l];
+        yv[k] = acc / c->H[(size_t)k * (m + 1) + k];
+      }
+      ColDev d{};
+      d.V = c->V.as<double2>();
+      d.z = c->z.as<double2>();
+      d.N = N;
+      d.cnt = cnt;
+      d.scale = (double)ys.size();  // offset into the coefficient upload
+      for (int k = 0; k < cnt; ++k) ys.push_back(make_double2(yv[k].real(), yv[k].imag()));
+      comb.push_back(d);
+      c->converged = conv;
+      c->phase = (conv || c->its >= c->req->o.max_iter) ? PH_FINAL : PH_RESTART;
+    };
     if (c->phase == PH_INIT) {
+      gsb += n16;
       c->gnorm = nrm;
       if (nrm == 0.0) {
         c->res = 0.0;
@@ -550,92 +660,154 @@ lm_status round(lm_server_s* S) {
         c->res = 1.0;
         start_cycle(c->w, nrm);
       }
-    } else if (c->phase == PH_RESTART) {
+      continue;
+    }
+    if (c->phase == PH_RESTART || c->phase == PH_FINAL) {
+      gsb += 3.0 * n16;
       c->res = nrm / c->gnorm;
-      if (c->res <= tol) {
+      if (c->phase == PH_FINAL) {
+        to_finish.push_back(c);  // true residual; convergence was decided by the GMRES estimate
+      } else if (c->res <= tol) {
         c->converged = true;
         to_finish.push_back(c);
       } else {
         start_cycle(c->w, nrm);
       }
-    } else if (c->phase == PH_FINAL) {
-      c->res = nrm / c->gnorm;  // true residual; convergence was decided by the GMRES estimate
-      to_finish.push_back(c);
-    } else {  // Arnoldi: Givens on the new column
-      const int j = c->j;
-      const double2* h1 = &S->hh[(size_t)i * hs];
-      const double2* h2 = h1 + ldh;
-      C* Hc = &c->H[(size_t)j * (m + 1)];
-      for (int k = 0; k <= j; ++k) Hc[k] = C(h1[k].x + h2[k].x, h1[k].y + h2[k].y);
-      Hc[j + 1] = nrm;
-      for (int k = 0; k < j; ++k) {
+      continue;
+    }
+    // Arnoldi step j: a = V[0..j]^H u_j, b = V[0..j]^H K M u_j
+    const int j = c->j;
+    gsb += (c->km ? 2.0 * (j + 1) + 6.0 : (j + 2.0)) * n16;
+    const double2* ha = &S->hh[(size_t)i * hs];
+    const double2* hb = ha + ldh;
+    std::vector<C> aQ(j), bQ(j);
+    for (int k = 0; k < j; ++k) {
+      aQ[k] = C(ha[k].x, ha[k].y);
+      bQ[k] = C(hb[k].x, hb[k].y);
+    }
+    double aa = 0.0;
+    for (int k = 0; k < j; ++k) aa += std::norm(aQ[k]);
+    const double mu = ha[j].x;  // |u_j|^2 (u_j normalised this round)
+    const double rho = std::sqrt(std::max(mu - aa, 0.0));
+    if (j >= 1) {
+      // corrected Hessenberg column j-1 (from the provisional one and aQ)
+      const double bprev = nrm;  // |w| of the once-projected vector before normalisation
+      C* Hr = &c->Hraw[(size_t)(j - 1) * (m + 1)];
+      for (int k = 0; k < j; ++k) Hr[k] = c->cprev[k] + bprev * aQ[k];
+      Hr[j] = bprev * rho;
+      C* Hc = &c->H[(size_t)(j - 1) * (m + 1)];
+      for (int k = 0; k <= j; ++k) Hc[k] = Hr[k];
+      const int jj = j - 1;
+      for (int k = 0; k < jj; ++k) {
         const C a = Hc[k], b = Hc[k + 1];
         Hc[k] = std::conj(c->cs[k]) * a + std::conj(c->sn[k]) * b;
         Hc[k + 1] = -c->sn[k] * a + c->cs[k] * b;
       }
-      const C a = Hc[j], b = Hc[j + 1];
+      const C a = Hc[jj], b = Hc[jj + 1];
       const double rr = std::hypot(std::abs(a), std::abs(b));
-      c->cs[j] = rr > 0 ? a / rr : C(1.0);
-      c->sn[j] = rr > 0 ? b / rr : C(0.0);
-      Hc[j] = std::conj(c->cs[j]) * a + std::conj(c->sn[j]) * b;
-      Hc[j + 1] = 0.0;
-      c->e1[j + 1] = -c->sn[j] * c->e1[j];
-      c->e1[j] = std::conj(c->cs[j]) * c->e1[j];
+      c->cs[jj] = rr > 0 ? a / rr : C(1.0);
+      c->sn[jj] = rr > 0 ? b / rr : C(0.0);
+      Hc[jj] = std::conj(c->cs[jj]) * a + std::conj(c->sn[jj]) * b;
+      Hc[jj + 1] = 0.0;
+      c->e1[jj + 1] = -c->sn[jj] * c->e1[jj];
+      c->e1[jj] = std::conj(c->cs[jj]) * c->e1[jj];
       c->its++;
-      c->res = std::abs(c->e1[j + 1]) / c->gnorm;
-      const bool conv = c->res <= tol || nrm <= 1e-300;
-      if (conv || j + 1 == m || c->its >= c->req->o.max_iter) {
-        // y = H^{-1} e1, z += V y; then the true residual (final) or a restart
-        const int cnt = j + 1;
-        std::vector<C> yv(cnt);
-        for (int k = cnt - 1; k >= 0; --k) {
-          C acc = c->e1[k];
-          for (int l = k + 1; l < cnt; ++l) acc -= c->H[(size_t)l * (m + 1) + k] * yv[l];
-          yv[k] = acc / c->H[(size_t)k * (m + 1) + k];
-        }
-        comb_col.push_back(i);
-        for (int k = 0; k < cnt; ++k) ys.push_back(make_double2(yv[k].real(), yv[k].imag()));
-        ColDev d{};
-        d.V = c->V.as<double2>();
-        d.z = c->z.as<double2>();
-        d.N = N;
-        d.cnt = cnt;
-        comb.push_back(d);
-        c->converged = conv;
-        c->phase = (conv || c->its >= c->req->o.max_iter) ? PH_FINAL : PH_RESTART;
-      } else {
-        ColDev d{};
-        d.src = c->w;
-        d.dst = c->V.as<double2>() + (size_t)(j + 1) * N;
-        d.scale = 1.0 / nrm;
-        d.N = N;
-        scal.push_back(d);
-        c->j = j + 1;
+      c->res = std::abs(c->e1[jj + 1]) / c->gnorm;
+      const bool conv = c->res <= tol || std::abs(Hr[j]) <= 1e-300;
+      if (conv || j == m || c->its >= c->req->o.max_iter || !c->km) {
+        end_cycle(j, conv);
+        continue;
       }
     }
-  }
-  if (!comb.empty()) {
-    LM_TRY(ensure(S->d_y, ys.size() * sizeof(double2)));
-    LM_TRY_HIP(hipMemcpyAsync(S->d_y.p, ys.data(), ys.size() * sizeof(double2), hipMemcpyHostToDevice, S->s));
-    size_t off = 0;
-    for (auto& d : comb) {
-      d.y = S->d_y.as<double2>() + off;
-      off += d.cnt;
+    // continue: re-orthogonalise u_j into v_j and form the once-projected
+    // next vector from K M u_j (see the file comment)
+    const C gamma(hb[j].x, hb[j].y);
+    std::vector<C> Ha(j, C(0.0));
+    for (int l = 0; l < j; ++l)
+      for (int k = 0; k <= std::min(l + 1, j - 1); ++k) Ha[k] += c->Hraw[(size_t)l * (m + 1) + k] * aQ[l];
+    const C hj = j >= 1 ? c->Hraw[(size_t)(j - 1) * (m + 1) + j] * aQ[j - 1] : C(0.0);
+    C ab(0.0);
+    for (int k = 0; k < j; ++k) ab += std::conj(aQ[k]) * bQ[k];
+    const C cj = ((gamma - ab) / rho - hj) / rho;
+    const C dd2 = hj / rho + cj;
+    ColDev d{};
+    d.V = c->V.as<double2>();
+    d.w = c->w;
+    d.N = N;
+    d.cnt = j;
+    d.scale = 1.0 / rho;
+    d.dr = make_double2((dd2 / rho).real(), (dd2 / rho).imag());
+    d.ndst = c->dn.as<double>();
+    d.src = reinterpret_cast<const double2*>((size_t)cf.size());  // offset, fixed up after the upload
+    for (int k = 0; k < j; ++k) cf.push_back(make_double2(aQ[k].real(), aQ[k].imag()));
+    for (int k = 0; k < j; ++k) {
+      const C cq = (bQ[k] - Ha[k]) / rho;
+      c->cprev[k] = cq;
+      const C e = Ha[k] / rho + cq - aQ[k] * dd2 / rho;
+      cf.push_back(make_double2(e.real(), e.imag()));
     }
+    c->cprev[j] = cj;
+    upd.push_back(d);
+    c->j = j + 1;
   }
-  std::vector<ColDev> all(scal);
+  // coefficient uploads (update passes, then solution combinations)
+  const size_t ncf = cf.size();
+  std::vector<double2> coefs(cf);
+  coefs.insert(coefs.end(), ys.begin(), ys.end());
+  if (!coefs.empty()) {
+    LM_TRY(ensure(S->d_y, coefs.size() * sizeof(double2)));
+    LM_TRY_HIP(hipMemcpyAsync(S->d_y.p, coefs.data(), coefs.size() * sizeof(double2), hipMemcpyHostToDevice, S->s));
+  }
+  for (auto& d : upd) {
+    d.y = S->d_y.as<double2>() + (size_t)d.src;
+    d.src = nullptr;
+  }
+  for (auto& d : comb) {
+    d.y = S->d_y.as<double2>() + ncf + (size_t)d.scale;
+    d.scale = 0.0;
+  }
+  std::vector<ColDev> all(upd);
+  all.insert(all.end(), scal.begin(), scal.end());
   all.insert(all.end(), comb.begin(), comb.end());
+  float gs_b = 0.f;
   if (!all.empty()) {
     LM_TRY(upload_desc(S, all));
     int nm = 0;
     for (auto& d : all) nm = std::max(nm, d.N);
     const ColDev* da = S->d_desc.as<ColDev>();
+    LM_TRY_HIP(hipEventRecord(S->t1, S->s));
+    if (!upd.empty()) {
+      hipLaunchKernelGGL(k_s_update2, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
+                         S->d_npart.as<double>(), nwu);
+      hipLaunchKernelGGL(k_s_norm_to, dim3(upd.size()), dim3(64), 0, S->s, da, S->d_npart.as<double>(), nwu);
+    }
+    LM_TRY_HIP(hipEventRecord(S->t2, S->s));
     if (!scal.empty())
-      hipLaunchKernelGGL(k_s_copy, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s, da);
+      hipLaunchKernelGGL(k_s_copy, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s, da + upd.size());
     if (!comb.empty())
-      hipLaunchKernelGGL(k_s_lincomb, dim3(div_up(nm, 256), comb.size()), dim3(256), 0, S->s, da + scal.size());
+      hipLaunchKernelGGL(k_s_lincomb, dim3(div_up(nm, 256), comb.size()), dim3(256), 0, S->s,
+                         da + upd.size() + scal.size());
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(S->s));  // d_y / descriptors are reused next round
+    LM_TRY_HIP(hipEventElapsedTime(&gs_b, S->t1, S->t2));
+  }
+  {
+    float m2l = 0.f;
+    for (int si : timed_streams) {
+      float t = 0.f;
+      LM_TRY_HIP(hipEventElapsedTime(&t, S->sev[si][4], S->sev[si][5]));
+      m2l += t;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->km_ms += km_round;
+    S->gs_ms += gs_a + gs_b;
+    S->m2l_ms += m2l;
+    S->m2l_flops += m2l_flops_round;
+    S->m2l_launches += (int64_t)timed_streams.size();
+    S->gs_bytes += gsb;
+    S->launches += n_launch;
+    S->fused_rhs += n_fused;
+    S->rounds++;
   }
   for (Column* c : to_finish) {
     lm_status st = finish_column(S, c);
