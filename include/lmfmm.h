@@ -238,7 +238,7 @@ lm_status lm_request_footprint(lm_geom geom, int n_rhs, const lm_gmres_opts* gmr
 /* Host output of 6 int64: queued requests, active right-hand sides, admitted
  * footprint bytes, rounds, fused K M launches, right-hand sides in them. */
 lm_status lm_server_stats(lm_server server, int64_t* out6);
-/* Host output of 6 doubles accumulated over the server's rounds, measured
+/* Host output of 8 doubles accumulated over the server's rounds, measured
  * with HIP events on the streams the kernels run on: [0] ms in the fused
  * K M phase (gathers, preconditioner, matvecs; every geometry stream
  * joined), [1] ms in the Gram-Schmidt phase (classical Gram-Schmidt with a
@@ -250,8 +250,10 @@ lm_status lm_server_stats(lm_server server, int64_t* out6);
  * plus N x 16 per column for the norms; [3] ms in the M2L
  * launches of the fused FMM matvecs (first launch of each geometry stream
  * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
- * [5] the number of those launches. */
-lm_status lm_server_phase_times(lm_server server, double* out6);
+ * [5] the number of those launches, [6] host wall-clock ms of the rounds
+ * (everything but finishing columns), [7] host wall-clock ms spent finishing
+ * columns (phi = M z, far field, copies to host memory). */
+lm_status lm_server_phase_times(lm_server server, double* out8);
 /* Cancels everything in flight, joins the worker and frees the server. */
 lm_status lm_server_destroy(lm_server server);
 

@@ -30,6 +30,7 @@
 #include <map>
 #include <unordered_map>
 
+#include "block_mfma.hpp"
 #include "fmm_math.hpp"
 #include "lm_internal.hpp"
 #include "m2l_table.hpp"
@@ -186,6 +187,33 @@ __global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tg
     v = lmq::reaction_direct(m, lay[i], lay[e], fabs(cx[i] - cx[e]), cy[i], cy[e], kd) * w[e];
   }
   val[t] = make_double2(v.re, v.im);
+}
+
+// Free-space near field + self term as dense blocks, one workgroup per leaf:
+// Z_B[r][jj] = self term if J[jj] is the row's element, else the free-space
+// kernel (i/4) H_0(k |c_i - c_e|) |Gamma_e| (FP64, stored complex64).
+__global__ void k_near_block_values(MediumDev m, const int* __restrict__ jptr, const int* __restrict__ jidx,
+                                    const int* __restrict__ nb, const int64_t* __restrict__ zoff,
+                                    const double* __restrict__ cx, const double* __restrict__ cy,
+                                    const double* __restrict__ w, const int* __restrict__ lay,
+                                    const double2* __restrict__ self, float2* __restrict__ Z) {
+  const int b = blockIdx.x;
+  const int* J = jidx + jptr[b];
+  const int q = jptr[b + 1] - jptr[b], nB = nb[b];
+  float2* Zb = Z + zoff[b];
+  for (int64_t idx = threadIdx.x; idx < (int64_t)nB * q; idx += blockDim.x) {
+    const int r = (int)(idx / q), jj = (int)(idx % q);
+    const int i = J[r], e = J[jj];
+    zd v;
+    if (i == e) {
+      const double2 sv = self[i];
+      v = zd(sv.x, sv.y);
+    } else {
+      const double kr = m.k[lay[i]] * hypot(cx[i] - cx[e], cy[i] - cy[e]);
+      v = zd(-0.25 * y0(kr), 0.25 * j0(kr)) * w[e];
+    }
+    Zb[idx] = make_float2((float)v.re, (float)v.im);
+  }
 }
 
 __global__ void k_c128_to_c64_fmm(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
@@ -784,6 +812,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   const int p = g->p;
   LM_CHECK(p >= 4 && p <= MAXP, LM_EINVAL, "the FMM needs 4 <= p <= %d", MAXP);
   F->p = p;
+  F->n_el = N;
   F->P = 2 * p + 1;
   F->n_layers = L + 1;
 
@@ -1213,6 +1242,33 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       }
     }
   }
+  // ---- free-space near field + self terms as leaf blocks (matrix-core apply) ----
+  {
+    F->nb_jptr.push_back(0);
+    int64_t z = 0;
+    for (size_t t = 0; t < F->near_tgt.size(); ++t) {
+      const int b = F->near_tgt[t];
+      const BoxDev& B = F->boxes[b];
+      for (int i = 0; i < B.npt; ++i) F->nb_jidx.push_back(F->pt_elem[B.pt0 + i]);
+      for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e) {
+        const int c = F->near_src[e];
+        if (c == b) continue;
+        const BoxDev& Cb = F->boxes[c];
+        for (int i = 0; i < Cb.npt; ++i) F->nb_jidx.push_back(F->pt_elem[Cb.pt0 + i]);
+      }
+      const int q = (int)F->nb_jidx.size() - F->nb_jptr.back();
+      F->nb_jptr.push_back((int)F->nb_jidx.size());
+      F->nb_rows.push_back(B.npt);
+      F->nb_zoff.push_back(z);
+      for (int r = 0; r < B.npt; r += PA_ROWS) {
+        F->nb_item.push_back((int)t);
+        F->nb_item.push_back(r);
+      }
+      z += (int64_t)q * B.npt;
+    }
+    F->nb_nnz = z;
+  }
+
   // ---- M2L entries grouped by operator ----------------------------------------
   {
     F->n_reac_tab = (int)reac_id.size();
@@ -1371,6 +1427,38 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
+  {
+    LM_TRY(up(F->d_nb_jptr, F->nb_jptr, s));
+    LM_TRY(up(F->d_nb_jidx, F->nb_jidx, s));
+    LM_TRY(up(F->d_nb_rows, F->nb_rows, s));
+    LM_TRY(up(F->d_nb_zoff, F->nb_zoff, s));
+    LM_TRY(up(F->d_nb_item, F->nb_item, s));
+    LM_TRY(F->d_nb_Z32.alloc(std::max<int64_t>(F->nb_nnz, 1) * sizeof(float2)));
+    if (!F->nb_rows.empty())
+      hipLaunchKernelGGL(k_near_block_values, dim3(F->nb_rows.size()), dim3(256), 0, s, m, F->d_nb_jptr.as<int>(),
+                         F->d_nb_jidx.as<int>(), F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(),
+                         g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
+                         F->d_self.as<double2>(), F->d_nb_Z32.as<float2>());
+    // reaction near pairs alone, as CSR (the rest of the near field is in the blocks)
+    const int64_t nr = (int64_t)F->rn_src.size();
+    std::vector<int> rt(nr);
+    for (int64_t i = 0; i < N; ++i)
+      for (int e = F->rn_ptr[i]; e < F->rn_ptr[i + 1]; ++e) rt[e] = (int)i;
+    DevBuf dt, dk, v64;
+    LM_TRY(up(dt, rt, s));
+    LM_TRY(up(dk, F->rn_mask, s));
+    LM_TRY(v64.alloc(std::max<int64_t>(nr, 1) * sizeof(double2)));
+    LM_TRY(F->d_rn_val32.alloc(std::max<int64_t>(nr, 1) * sizeof(float2)));
+    if (nr) {
+      hipLaunchKernelGGL(k_near_values, dim3(div_up(nr, 128)), dim3(128), 0, s, m, nr, dt.as<int>(),
+                         F->d_rn_src.as<int>(), dk.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
+                         g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), v64.as<double2>());
+      hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nr, 256)), dim3(256), 0, s, nr, v64.as<double2>(),
+                         F->d_rn_val32.as<float2>());
+    }
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
   LM_TRY(up(F->d_tm_ptr, F->tm_ptr, s));
   LM_TRY(up(F->d_tm_item, F->tm_item, s));
   LM_TRY(up(F->d_mf_item, F->mf_item, s));
@@ -1411,7 +1499,10 @@ lm_status fmm_reserve(FmmPlan* F, int r) {
   LM_TRY(F->d_me.alloc(bytes));
   LM_TRY(F->d_le.alloc(bytes));
   LM_TRY(F->d_p2m_part.alloc((size_t)std::max(F->item_ptr[3], 1) * F->P * r * sizeof(double2)));
-  if (r > 1) LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
+  if (r > 1) {
+    LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
+    LM_TRY(F->d_xt.alloc((size_t)std::max<int64_t>(F->n_el, 1) * r * sizeof(float2)));
+  }
   F->r_cap = r;
   return LM_OK;
 }
@@ -1532,12 +1623,27 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(4, 0);
   LM_STAGE(5, 1);
   // near fields and self terms
-  if (R >= 8)
+  if (sizeof(RT) == 4 && R > 1) {
+    // FP32, several right-hand sides: free-space near field + self terms as
+    // leaf blocks on matrix cores, then the few reaction near pairs
+    if (!F->nb_item.empty()) {
+      hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
+                         (const float2*)x, F->d_xt.as<float2>());
+      hipLaunchKernelGGL((k_block_mfma<float2, true>), dim3(F->nb_item.size() / 2), dim3(64 * PA_NW), 0, s, N, R,
+                         F->d_nb_item.as<int>(), F->d_nb_jptr.as<int>(), F->d_nb_jidx.as<int>(),
+                         F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(), F->d_nb_Z32.as<float2>(),
+                         F->d_xt.as<float2>(), (float2*)y);
+    }
+    if (!F->rn_src.empty())
+      hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_rn_ptr.as<int>(),
+                         F->d_rn_src.as<int>(), F->d_rn_val32.as<float2>(), (const float2*)x, (float2*)y);
+  } else if (R >= 8) {
     hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
                        F->d_nm_src.as<int>(), nmv, x, y);
-  else
+  } else {
     hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
                        F->d_nm_src.as<int>(), nmv, x, y);
+  }
   LM_STAGE(5, 0);
   LM_STAGE(6, 1);
   LM_STAGE(6, 0);

@@ -17,6 +17,7 @@ struct FmmPlan {
   int nlev = 0, lf = 0, lr = 0;
   double w_top = 0, x0 = 0;
   int n_boxes = 0;
+  int64_t n_el = 0;               // boundary elements N
   std::vector<BoxDev> boxes;
   std::vector<int> level_ptr;     // boxes of level l: ids [level_ptr[l], level_ptr[l+1])
   std::vector<int> leaf_free, leaf_B, leaf_T;  // leaf boxes by tree class
@@ -47,6 +48,11 @@ struct FmmPlan {
   std::vector<int> tm_item;  // (operator, first entry, end) work items
   std::vector<int> mf_item, mf_ptr;  // (target slot, first entry, end) items, items per target
   std::vector<int> tr_item, tr_src, tr_op;  // matrix-core M2M (per parent) and L2L (per box) items
+  // free-space near field + self terms as leaf blocks: rows = the leaf's
+  // elements, columns = the leaf's and its neighbours' elements
+  std::vector<int> nb_jptr, nb_jidx, nb_rows, nb_item;
+  std::vector<int64_t> nb_zoff;
+  int64_t nb_nnz = 0;
   int l2l_item0 = 0;
   int n_reac_tab = 0, n_free_tab = 0;
   // expansion scales sig[layer][level][0..p]; translation operators, P x P
@@ -65,6 +71,7 @@ struct FmmPlan {
   DevBuf d_rn_ptr, d_rn_src, d_rn_val;
   DevBuf d_self, d_me, d_le, d_tree_layer;
   DevBuf d_tr_item, d_tr_src, d_tr_op, d_box_id;
+  DevBuf d_nb_jptr, d_nb_jidx, d_nb_rows, d_nb_item, d_nb_zoff, d_nb_Z32, d_rn_val32, d_xt;
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   int64_t bytes() const {
@@ -72,7 +79,7 @@ struct FmmPlan {
                            &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64, &d_ops32,
                            &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
                            &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
-                           &d_nm_val32, &d_tr_item, &d_tr_src, &d_tr_op, &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
+                           &d_nm_val32, &d_nb_jptr, &d_nb_jidx, &d_nb_rows, &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op, &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

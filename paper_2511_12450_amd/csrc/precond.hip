@@ -24,6 +24,7 @@
 #include <map>
 #include <tuple>
 
+#include "block_mfma.hpp"
 #include "fmm_plan.hpp"
 
 struct Precond {
@@ -32,8 +33,10 @@ struct Precond {
   std::vector<int64_t> zoff;
   std::vector<int> items;  // (subdomain, first row) work items of PA_ROWS rows for the MFMA apply
   DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_Z32, d_items;
+  DevBuf d_xt;  // transposed complex64 input of the matrix-core apply
   int64_t bytes() const {
-    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes + d_items.bytes;
+    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes + d_items.bytes +
+           d_xt.bytes;
   }
 };
 
@@ -158,97 +161,6 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
   }
 }
 
-// Mixed-precision apply for several right-hand sides with matrix cores:
-// Y_B (rows x R) = Z_B (rows x q) X_J (q x R) per work item of PA_ROWS rows of
-// one subdomain, as the real product [[Re Z, -Im Z], [Im Z, Re Z]] [Re X; Im X]
-// in 16x16x4 FP32 MFMA tiles (FP32 accumulation).  K runs over the
-// neighbourhood in chunks of PA_KC complex columns staged in LDS (Z chunk
-// transposed to [j][r], X chunk converted from FP64 to FP32).
-typedef float pa_v4f __attribute__((ext_vector_type(4)));
-constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_TPW = 32 / PA_NW;
-__global__ void __launch_bounds__(64 * PA_NW) k_pre_apply_mfma(int N, int R, const int* __restrict__ items,
-                                                        const int* __restrict__ jptr, const int* __restrict__ jidx,
-                                                        const int* __restrict__ nb, const int64_t* __restrict__ zoff,
-                                                        const float2* __restrict__ Z, const double2* __restrict__ x,
-                                                        double2* __restrict__ y) {
-  __shared__ float2 Zs[PA_KC][PA_ROWS];
-  __shared__ float2 Xs[PA_KC][64];
-  const int sd = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
-  const int j0_ = jptr[sd], q = jptr[sd + 1] - j0_;
-  const int rows = min(PA_ROWS, nb[sd] - r0);
-  const int* J = jidx + j0_;
-  const float2* Zl = Z + zoff[sd] + (int64_t)r0 * q;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int l16 = lane & 15, kq = lane >> 4;
-  const int R2 = 2 * rows, MT = (R2 + 15) / 16, NT = (R + 15) / 16, ntile = MT * NT;
-  int mrow[PA_TPW], jcol[PA_TPW];
-  bool ire[PA_TPW], ival[PA_TPW], jval[PA_TPW];
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + PA_NW * t;
-    const int i = 16 * (tile / NT) + l16, jj = 16 * (tile % NT) + l16;
-    ival[t] = tile < ntile && i < R2;
-    ire[t] = i < rows;
-    mrow[t] = ival[t] ? (ire[t] ? i : i - rows) : 0;
-    jval[t] = tile < ntile && jj < R;
-    jcol[t] = jval[t] ? jj : 0;
-  }
-  pa_v4f acc[PA_TPW];
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) acc[t] = pa_v4f{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < q; c0 += PA_KC) {
-    const int kc = min(PA_KC, q - c0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 64 * PA_NW) {
-      const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a Z row
-      Zs[jj][rr] = (rr < rows && jj < kc) ? Zl[(int64_t)rr * q + c0 + jj] : make_float2(0.f, 0.f);
-    }
-    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 64 * PA_NW) {
-      const int jj = idx >> 6, rr = idx & 63;
-      float2 v = make_float2(0.f, 0.f);
-      if (jj < kc && rr < R) {
-        const double2 xv = x[(int64_t)rr * N + J[c0 + jj]];
-        v = make_float2((float)xv.x, (float)xv.y);
-      }
-      Xs[jj][rr] = v;
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int ks = 0; ks < 2 * PA_KC / 4; ++ks) {
-      const int k = 4 * ks + kq;
-      const bool kre = k < PA_KC;
-      const int n = kre ? k : k - PA_KC;
-#pragma unroll
-      for (int t = 0; t < PA_TPW; ++t) {
-        if (wv + PA_NW * t < ntile) {  // wave-uniform
-          const float2 zv = Zs[n][mrow[t]];
-          const float2 xv = Xs[n][jcol[t]];
-          const float av = ival[t] ? (ire[t] ? (kre ? zv.x : -zv.y) : (kre ? zv.y : zv.x)) : 0.f;
-          const float bv = jval[t] ? (kre ? xv.x : xv.y) : 0.f;
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
-        }
-      }
-    }
-  }
-  double* yd = reinterpret_cast<double*>(y);
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + PA_NW * t;
-    if (tile < ntile) {
-      const int jj = 16 * (tile % NT) + l16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * (tile / NT) + 4 * kq + v;
-        if (i < R2 && jj < R) {
-          const bool ir = i < rows;
-          const int row = J[r0 + (ir ? i : i - rows)];
-          yd[2 * ((int64_t)jj * N + row) + (ir ? 0 : 1)] = (double)acc[t][v];
-        }
-      }
-    }
-  }
-}
-
 __global__ void k_z_to_c64(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -356,11 +268,15 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
   Precond* P = g->pre;
   LM_CHECK(P, LM_EINVAL, "no preconditioner");
   if (precision == LM_MIXED && n_rhs > 1) {
+    const size_t need = (size_t)g->N * std::min(n_rhs, 64) * sizeof(float2);
+    if (P->d_xt.bytes < need) LM_TRY(P->d_xt.alloc(need));
     for (int r0 = 0; r0 < n_rhs; r0 += 64) {
       const int R = std::min(64, n_rhs - r0);
-      hipLaunchKernelGGL(k_pre_apply_mfma, dim3(P->items.size() / 2), dim3(64 * PA_NW), 0, s, (int)g->N, R,
-                         P->d_items.as<int>(), P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(),
-                         P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(), (const double2*)x + (int64_t)r0 * g->N,
+      hipLaunchKernelGGL(k_to_nr<double2>, dim3(div_up(g->N, 32), div_up(R, 32)), dim3(32, 8), 0, s, (int)g->N, R,
+                         (const double2*)x + (int64_t)r0 * g->N, P->d_xt.as<float2>());
+      hipLaunchKernelGGL((k_block_mfma<double2, false>), dim3(P->items.size() / 2), dim3(64 * PA_NW), 0, s,
+                         (int)g->N, R, P->d_items.as<int>(), P->d_jptr.as<int>(), P->d_jidx.as<int>(),
+                         P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(), P->d_xt.as<float2>(),
                          (double2*)y + (int64_t)r0 * g->N);
     }
     LM_TRY_HIP(hipGetLastError());

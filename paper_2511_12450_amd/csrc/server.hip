@@ -348,6 +348,7 @@ struct lm_server_s {
   int64_t rounds = 0, launches = 0, fused_rhs = 0;
   double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
   double m2l_ms = 0.0, m2l_flops = 0.0;              // M2L launches of the fused matvecs (HIP events)
+  double round_ms = 0.0, finish_ms = 0.0;            // host wall time of rounds / of finishing columns
   int64_t m2l_launches = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
   hipEvent_t sev[SRV_STREAMS][14] = {};
@@ -463,6 +464,7 @@ lm_status finish_column(lm_server_s* S, Column* c) {
 // One round of the worker (see the file comment).  Returns an error only for
 // failures that are not attributable to a single request.
 lm_status round(lm_server_s* S) {
+  const double tr0 = now_s();
   std::vector<Column*> cols;
   for (Column* c : S->cols)
     if (!c->finished) cols.push_back(c);
@@ -722,9 +724,21 @@ lm_status round(lm_server_s* S) {
     // continue: re-orthogonalise u_j into v_j and form the once-projected
     // next vector from K M u_j (see the file comment)
     const C gamma(hb[j].x, hb[j].y);
+    // Ha = H[0..j-1, 0..j-1] aQ (upper Hessenberg), in plain real arithmetic
     std::vector<C> Ha(j, C(0.0));
-    for (int l = 0; l < j; ++l)
-      for (int k = 0; k <= std::min(l + 1, j - 1); ++k) Ha[k] += c->Hraw[(size_t)l * (m + 1) + k] * aQ[l];
+    {
+      std::vector<double> hr(2 * (size_t)j, 0.0);
+      for (int l = 0; l < j; ++l) {
+        const double ar = aQ[l].real(), ai = aQ[l].imag();
+        const double* H = reinterpret_cast<const double*>(&c->Hraw[(size_t)l * (m + 1)]);
+        const int kt = std::min(l + 1, j - 1);
+        for (int k = 0; k <= kt; ++k) {
+          hr[2 * k] += H[2 * k] * ar - H[2 * k + 1] * ai;
+          hr[2 * k + 1] += H[2 * k] * ai + H[2 * k + 1] * ar;
+        }
+      }
+      for (int k = 0; k < j; ++k) Ha[k] = C(hr[2 * k], hr[2 * k + 1]);
+    }
     const C hj = j >= 1 ? c->Hraw[(size_t)(j - 1) * (m + 1) + j] * aQ[j - 1] : C(0.0);
     C ab(0.0);
     for (int k = 0; k < j; ++k) ab += std::conj(aQ[k]) * bQ[k];
@@ -809,10 +823,15 @@ lm_status round(lm_server_s* S) {
     S->fused_rhs += n_fused;
     S->rounds++;
   }
+  const double tf0 = now_s();
   for (Column* c : to_finish) {
     lm_status st = finish_column(S, c);
     if (st < 0) fail_request(S, c->req, st, lm_last_error());
   }
+  const double tf1 = now_s();
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->round_ms += 1e3 * (tf0 - tr0);
+  S->finish_ms += 1e3 * (tf1 - tf0);
   return LM_OK;
 }
 
@@ -1055,15 +1074,17 @@ extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
   return LM_OK;
 }
 
-extern "C" lm_status lm_server_phase_times(lm_server S, double* out6) {
-  LM_CHECK(S && out6, LM_EINVAL, "bad arguments");
+extern "C" lm_status lm_server_phase_times(lm_server S, double* out8) {
+  LM_CHECK(S && out8, LM_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> lk(S->mu);
-  out6[0] = S->km_ms;
-  out6[1] = S->gs_ms;
-  out6[2] = S->gs_bytes;
-  out6[3] = S->m2l_ms;
-  out6[4] = S->m2l_flops;
-  out6[5] = (double)S->m2l_launches;
+  out8[0] = S->km_ms;
+  out8[1] = S->gs_ms;
+  out8[2] = S->gs_bytes;
+  out8[3] = S->m2l_ms;
+  out8[4] = S->m2l_flops;
+  out8[5] = (double)S->m2l_launches;
+  out8[6] = S->round_ms;
+  out8[7] = S->finish_ms;
   return LM_OK;
 }
 

@@ -335,9 +335,10 @@ class Server:
     def phase_times(self):
         """dict: K M phase ms, Gram-Schmidt phase ms and algorithmic bytes,
         M2L launch ms, flops and count (lm_server_phase_times)."""
-        out = np.zeros(6)
+        out = np.zeros(8)
         _check(lib().lm_server_phase_times(self.h, _dptr(out)))
-        return dict(zip(["km_ms", "gs_ms", "gs_bytes", "m2l_ms", "m2l_flops", "m2l_launches"], [float(v) for v in out]))
+        return dict(zip(["km_ms", "gs_ms", "gs_bytes", "m2l_ms", "m2l_flops", "m2l_launches", "round_ms", "finish_ms"],
+                        [float(v) for v in out]))
 
     def close(self):
         if self.h:
