@@ -8,94 +8,133 @@
 // Block-sparse products with matrix cores, for several right-hand sides:
 // Y_B (rows x R) (=|+=) Z_B (rows x q) X_J (q x R) per work item of PA_ROWS
 // rows of one block (a subdomain of the preconditioner, or a leaf box with
-// its neighbours for the near field), as the real product
-// [[Re Z, -Im Z], [Im Z, Re Z]] [Re X; Im X] in 16x16x4 FP32 MFMA tiles (FP32
-// accumulation).  Z_B is row-major, complex64; the input is the complex64
-// transpose xt [N][R] (k_to_nr), so a neighbourhood row of all right-hand
-// sides is one contiguous load; y is [R][N] in YT (complex128 or complex64).
-// K runs over the neighbourhood in chunks of PA_KC complex columns staged in
-// LDS (Z chunk transposed to [j][r]).
+// its neighbours for the near field), as a real product in 16x16x4 FP32 MFMA
+// tiles (FP32 accumulation) under the interleaved real embedding: real row
+// i = 2 r + rho (real / imaginary part of output row r), real column
+// k = 2 c + kappa, A[i][k] = Re Z[r][c] if rho == kappa, Im Z[r][c] if
+// rho = 1, kappa = 0, -Im Z[r][c] if rho = 0, kappa = 1, and
+// B[k][j] = Re / Im X[c][j] for kappa = 0 / 1.  A lane's rho and kappa are
+// fixed by its position in the MFMA layout, so each fragment is one LDS load
+// (and a sign flip for A).  Z_B is row-major, complex64; the input is the
+// complex64 transpose xt [N][R] (k_to_nr), so a neighbourhood row of all
+// right-hand sides is one contiguous load; y is [R][N] in YT (complex128 or
+// complex64).  K runs over the neighbourhood in chunks of PA_KC complex
+// columns staged in LDS (Z chunk transposed to [c][r]; row strides of 80
+// complex so that the two column halves of a fragment load fall in different
+// LDS banks).  Eight wavefronts in a 4 x 2 grid hold 2 x 2 output tiles each.
 typedef float pa_v4f __attribute__((ext_vector_type(4)));
-constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_TPW = 32 / PA_NW;
+constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80;
+// The product of one work item.  Op describes the item:
+//   rows, q                  output rows (<= PA_ROWS) and K length (complex)
+//   zrow(r)                  row r of the item's matrix (q complex64)
+//   brow(c)                  row c of the right operand (R complex64)
+//   store(r, j, re, im)      writes (or adds) output row r, right-hand side j
+template <class Op>
+__device__ __forceinline__ void block_mfma_body(const Op& op, int R) {
+  constexpr int TR = 2, TC = 2;
+  __shared__ float2 Zs[PA_KC][PA_LS];
+  __shared__ float2 Xs[PA_KC][PA_LS];
+  const int rows = op.rows, q = op.q;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int rho = l16 & 1, kap = kq & 1;
+  const unsigned sgn = (rho == 0 && kap == 1) ? 0x80000000u : 0u;
+  int aoff[TR], boff[TC];  // float offsets of this lane's fragments at k-step 0
+#pragma unroll
+  for (int t = 0; t < TR; ++t) aoff[t] = 2 * ((kq >> 1) * PA_LS + 8 * (wr * TR + t) + (l16 >> 1)) + (rho ^ kap);
+#pragma unroll
+  for (int c = 0; c < TC; ++c) boff[c] = 2 * ((kq >> 1) * PA_LS + 16 * (wc * TC + c) + l16) + kap;
+  const float* Zf = reinterpret_cast<const float*>(&Zs[0][0]);
+  const float* Xf = reinterpret_cast<const float*>(&Xs[0][0]);
+  pa_v4f acc[TR][TC];
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+#pragma unroll
+    for (int c = 0; c < TC; ++c) acc[t][c] = pa_v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < q; c0 += PA_KC) {
+    const int kc = min(PA_KC, q - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 64 * PA_NW) {
+      const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a matrix row
+      Zs[jj][rr] = (rr < rows && jj < kc) ? op.zrow(rr)[c0 + jj] : make_float2(0.f, 0.f);
+    }
+    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 64 * PA_NW) {
+      const int jj = idx >> 6, rr = idx & 63;
+      Xs[jj][rr] = (jj < kc && rr < R) ? op.brow(c0 + jj)[rr] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ks = 0; ks < PA_KC / 2; ++ks) {  // two complex columns per k-step
+      float av[TR], bv[TC];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) av[t] = __uint_as_float(__float_as_uint(Zf[aoff[t] + 4 * ks * PA_LS]) ^ sgn);
+#pragma unroll
+      for (int c = 0; c < TC; ++c) bv[c] = Xf[boff[c] + 4 * ks * PA_LS];
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[c], acc[t][c], 0, 0, 0);
+    }
+  }
+  // lane rows 4 kq + v of a tile are output rows 8 rt + 2 kq + v / 2, real
+  // part for even v
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int rt = wr * TR + t;
+#pragma unroll
+    for (int c = 0; c < TC; ++c) {
+      const int j = 16 * (wc * TC + c) + l16;
+      if (j < R) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = 8 * rt + 2 * kq + h;
+          if (r < rows) op.store(r, j, acc[t][c][2 * h], acc[t][c][2 * h + 1]);
+        }
+      }
+    }
+  }
+}
+
+// Near field / preconditioner blocks: item (block, first row); Z_B row-major
+// (nb rows x q), neighbourhood J (the block's own rows first), output
+// y[j][J[r]] of type YT, overwritten or (ACC) accumulated.
+template <typename YT, bool ACC>
+struct BlockOp {
+  int rows, q, N, R;
+  const float2* Zl;
+  const int* J;
+  int r0;
+  const float2* xt;
+  YT* y;
+  __device__ const float2* zrow(int r) const { return Zl + (int64_t)r * q; }
+  __device__ const float2* brow(int c) const { return xt + (int64_t)J[c] * R; }
+  __device__ void store(int r, int j, float re, float im) const {
+    typedef decltype(y->x) YS;
+    YT* o = y + (int64_t)j * N + J[r0 + r];
+    YT v;
+    if (ACC) {
+      v = *o;
+      v.x += (YS)re;
+      v.y += (YS)im;
+    } else {
+      v.x = (YS)re;
+      v.y = (YS)im;
+    }
+    *o = v;
+  }
+};
+
 template <typename YT, bool ACC>
 __global__ void __launch_bounds__(64 * PA_NW) k_block_mfma(int N, int R, const int* __restrict__ items,
                                                     const int* __restrict__ jptr, const int* __restrict__ jidx,
                                                     const int* __restrict__ nb, const int64_t* __restrict__ zoff,
                                                     const float2* __restrict__ Z, const float2* __restrict__ xt,
                                                     YT* __restrict__ y) {
-  __shared__ float2 Zs[PA_KC][PA_ROWS];
-  __shared__ float2 Xs[PA_KC][64];
   const int sd = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
-  const int j0_ = jptr[sd], q = jptr[sd + 1] - j0_;
-  const int rows = min(PA_ROWS, nb[sd] - r0);
-  const int* J = jidx + j0_;
-  const float2* Zl = Z + zoff[sd] + (int64_t)r0 * q;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int l16 = lane & 15, kq = lane >> 4;
-  const int R2 = 2 * rows, MT = (R2 + 15) / 16, NT = (R + 15) / 16, ntile = MT * NT;
-  int mrow[PA_TPW], jcol[PA_TPW];
-  bool ire[PA_TPW], ival[PA_TPW], jval[PA_TPW];
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + PA_NW * t;
-    const int i = 16 * (tile / NT) + l16, jj = 16 * (tile % NT) + l16;
-    ival[t] = tile < ntile && i < R2;
-    ire[t] = i < rows;
-    mrow[t] = ival[t] ? (ire[t] ? i : i - rows) : 0;
-    jval[t] = tile < ntile && jj < R;
-    jcol[t] = jval[t] ? jj : 0;
-  }
-  pa_v4f acc[PA_TPW];
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) acc[t] = pa_v4f{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < q; c0 += PA_KC) {
-    const int kc = min(PA_KC, q - c0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 64 * PA_NW) {
-      const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a Z row
-      Zs[jj][rr] = (rr < rows && jj < kc) ? Zl[(int64_t)rr * q + c0 + jj] : make_float2(0.f, 0.f);
-    }
-    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 64 * PA_NW) {
-      const int jj = idx >> 6, rr = idx & 63;
-      Xs[jj][rr] = (jj < kc && rr < R) ? xt[(int64_t)J[c0 + jj] * R + rr] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int ks = 0; ks < 2 * PA_KC / 4; ++ks) {
-      const int k = 4 * ks + kq;
-      const bool kre = k < PA_KC;
-      const int n = kre ? k : k - PA_KC;
-#pragma unroll
-      for (int t = 0; t < PA_TPW; ++t) {
-        if (wv + PA_NW * t < ntile) {  // wave-uniform
-          const float2 zv = Zs[n][mrow[t]];
-          const float2 xv = Xs[n][jcol[t]];
-          const float av = ival[t] ? (ire[t] ? (kre ? zv.x : -zv.y) : (kre ? zv.y : zv.x)) : 0.f;
-          const float bv = jval[t] ? (kre ? xv.x : xv.y) : 0.f;
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
-        }
-      }
-    }
-  }
-  typedef decltype(y->x) YS;
-  YS* yd = reinterpret_cast<YS*>(y);
-#pragma unroll
-  for (int t = 0; t < PA_TPW; ++t) {
-    const int tile = wv + PA_NW * t;
-    if (tile < ntile) {
-      const int jj = 16 * (tile % NT) + l16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * (tile / NT) + 4 * kq + v;
-        if (i < R2 && jj < R) {
-          const bool ir = i < rows;
-          const int row = J[r0 + (ir ? i : i - rows)];
-          YS* o = yd + 2 * ((int64_t)jj * N + row) + (ir ? 0 : 1);
-          *o = ACC ? (YS)(*o + (YS)acc[t][v]) : (YS)acc[t][v];
-        }
-      }
-    }
-  }
+  const int j0 = jptr[sd], q = jptr[sd + 1] - j0;
+  BlockOp<YT, ACC> op{min(PA_ROWS, nb[sd] - r0), q, N, R, Z + zoff[sd] + (int64_t)r0 * q, jidx + j0, r0, xt, y};
+  block_mfma_body(op, R);
 }
 
 // xt[n][r] = x[r][n] as complex64 (32 x 32 tiles through LDS; block (32, 8)).

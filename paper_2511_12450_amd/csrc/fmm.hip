@@ -46,6 +46,7 @@ constexpr double LM_TOP_KW = 8.0;
 constexpr int LM_PTS_ITEM = 64;  // points per P2M / L2P work item
 constexpr int WG = 64;
 constexpr int MAXPP = 2 * MAXP + 1;
+static_assert(LM_PTS_ITEM <= PA_ROWS && MAXPP <= PA_ROWS, "P2M / L2P items must fit one matrix-core block");
 inline int64_t bkey(int i, int j) { return ((int64_t)i << 32) | (uint32_t)j; }
 }  // namespace
 
@@ -451,114 +452,162 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
   acc_store(PR, are, aim, le + (int64_t)tgts[blockIdx.x] * PR);
 }
 
-// M2L with matrix cores (FP32, several right-hand sides): one workgroup
-// (four wavefronts) per target box.  For each list entry the operator T
-// (P x P complex, column-major by input) and the source expansion a
-// (P x R complex) are staged in LDS, and the complex product is formed as the
-// real product of [[Re T, -Im T], [Im T, Re T]] (2P x 2P) with [Re a; Im a]
-// (2P x R) in 16x16x4 FP32 MFMA tiles (16 x 16 output tiles spread over the
-// four wavefronts, FP32 accumulation).
+// Translations with matrix cores (FP32, several right-hand sides): M2L, and
+// M2M / L2L as items of one parent or child.  A work item (target, first
+// entry, end) sums Op_e a_src(e) over its entries; per entry the operator T
+// (P x P complex, [n][m] = column n of the input) and the source expansion a
+// (P x R complex, [n][j]) are copied to LDS as they lie in memory, and the
+// complex product is the real product of a 2P x 2P matrix with a 2P x R one
+// in 16x16x4 FP32 MFMA tiles (FP32 accumulation) under the interleaved real
+// embedding: real row i = 2m + rho (rho = 0 real part, 1 imaginary part of
+// output m), real column k = 2n + kappa, so
+//   A[i][k] = Re T[n][m]  if rho == kappa,   B[k][j] = Re a[n][j]  (kappa = 0)
+//             Im T[n][m]  if rho = 1, kappa = 0       Im a[n][j]  (kappa = 1)
+//            -Im T[n][m]  if rho = 0, kappa = 1.
+// Each lane's rho and kappa are fixed (row = lane % 16, k = lane / 16 in the
+// 16x16x4 layout), so a fragment is one LDS load of the right component and,
+// for A, one sign flip: no selects in the K loop.  K is padded to whole
+// unrolled steps with zero rows of a after the staged data (rows beyond P
+// read finite staged values times those zeros), and output rows beyond P are
+// clamped duplicates that are not stored.  Waves form a (MT/3) x 2 grid, each
+// holding 3 x TC output tiles.
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int MF_ST = 8;    // staging loads in flight per lane
-// Work item = (target, first entry, end) with at most M2L_ITEM entries; each
-// item leaves a partial local expansion, summed per target by k_p2m_reduce.
-template <int NW>
-__global__ void __launch_bounds__(64 * NW) k_m2l_mfma(int p, int R, const int* __restrict__ items,
-                                                  const int* __restrict__ src, const int* __restrict__ opi,
-                                                  const float2* __restrict__ ops, const float2* __restrict__ me,
-                                                  float2* __restrict__ part, const int* __restrict__ dtgt,
-                                                  int accumulate) {
-  constexpr int TPW = 32 / NW;  // output tiles per wavefront (at most 32 tiles: 2P <= 128, R <= 64)
-  const int P = 2 * p + 1, PR = P * R, P2 = 2 * P, PP = P * P, NS = PP + PR;
-  const int MT = (P2 + 15) / 16, NT = (R + 15) / 16, KS = (P2 + 3) / 4, ntile = MT * NT;
+constexpr int MF_ST = 8;  // staging loads in flight per lane
+constexpr int MF_UK = 3;  // k-steps per unrolled K iteration
+constexpr int MF_TR = 3;  // row tiles per wave
+__host__ __device__ inline int mf_ks(int P) { return ((P + 1) / 2 + MF_UK - 1) / MF_UK * MF_UK; }
+// float2 slots after the staged T and a that must read as zero
+__host__ __device__ inline int mf_zero_tail(int P, int R) {
+  const int KS = mf_ks(P), NT = (R + 15) / 16;
+  const int zb = (2 * KS - P) * R + 16 * NT;   // B rows n in [P, 2 KS) and column overrun
+  const int za = 2 * KS * P - P * P - P * R;   // A columns n in [P, 2 KS)
+  return zb > za ? zb : za;
+}
+inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_zero_tail(P, R)) * sizeof(float2); }
+template <int TC, int NWB>
+__global__ void __launch_bounds__(64 * NWB) k_m2l_mfma(int p, int R, const int* __restrict__ items,
+                                                   const int* __restrict__ src, const int* __restrict__ opi,
+                                                   const float2* __restrict__ ops, const float2* __restrict__ me,
+                                                   float2* __restrict__ part, const int* __restrict__ dtgt,
+                                                   int accumulate) {
+  const int P = 2 * p + 1, PP = P * P, PR = P * R, NS = PP + PR;
+  const int MT = (2 * P + 15) / 16, KS = mf_ks(P), NZ = mf_zero_tail(P, R);
   extern __shared__ unsigned char dyn[];
-  float2* S = reinterpret_cast<float2*>(dyn);  // T [P][P] then a [P][R]
-  const float2* T = S;
-  const float2* A = S + PP;
+  float2* S = reinterpret_cast<float2*>(dyn);  // T [n][m] (stride P), a [n][j] (stride R), zero tail
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  // per-tile operand coordinates (fixed for the whole launch); for NT in
-  // {1, 2, 4} every tile of a wavefront has the same column block, so its B
-  // operand is loaded once per k-step
-  const bool bshared = (NW % NT) == 0;
-  int mrow[TPW], jcol[TPW];
-  bool ire[TPW], ival[TPW], jval[TPW];
+  const int wr = wv >> 1, wc = wv & 1;
+  for (int idx = threadIdx.x; idx < NZ; idx += 64 * NWB) S[NS + idx] = make_float2(0.f, 0.f);
+  const int rho = l16 & 1, kap = kq & 1;
+  const unsigned sgn = (rho == 0 && kap == 1) ? 0x80000000u : 0u;
+  int aoff[MF_TR], boff[TC];  // float offsets of this lane's fragments at k-step 0
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wv + NW * t;
-    const int i = 16 * (tile / NT) + l16, j = 16 * (tile % NT) + l16;
-    ival[t] = tile < ntile && i < P2;
-    ire[t] = i < P;
-    mrow[t] = ival[t] ? (ire[t] ? i : i - P) : 0;
-    jval[t] = tile < ntile && j < R;
-    jcol[t] = jval[t] ? j : 0;
+  for (int t = 0; t < MF_TR; ++t) {
+    const int m = min(8 * (wr * MF_TR + t) + (l16 >> 1), P - 1);
+    aoff[t] = 2 * ((kq >> 1) * P + m) + (rho ^ kap);
   }
-  v4f acc[TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < TC; ++c) {
+    const int j = min(16 * (wc * TC + c) + l16, 16 * ((R + 15) / 16) - 1);
+    boff[c] = 2 * (PP + (kq >> 1) * R + j) + kap;
+  }
+  const float* Sf = reinterpret_cast<const float*>(S);
+  v4f acc[MF_TR][TC];
+#pragma unroll
+  for (int t = 0; t < MF_TR; ++t)
+#pragma unroll
+    for (int c = 0; c < TC; ++c) acc[t][c] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int e = items[3 * blockIdx.x + 1]; e < items[3 * blockIdx.x + 2]; ++e) {
     const float2* Tg = ops + (int64_t)opi[e] * PP;
     const float2* Ag = me + (int64_t)src[e] * PR;
     __syncthreads();
-    for (int base = threadIdx.x; base < NS; base += 64 * NW * MF_ST) {  // MF_ST loads in flight per lane
+    for (int base = threadIdx.x; base < NS; base += 64 * NWB * MF_ST) {
       float2 v[MF_ST];
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 64 * NW * u;
+        const int idx = base + 64 * NWB * u;
         if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
       }
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 64 * NW * u;
+        const int idx = base + 64 * NWB * u;
         if (idx < NS) S[idx] = v[u];
       }
     }
     __syncthreads();
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + kq;
-      const bool kv = k < P2, kre = k < P;
-      const int n = kv ? (kre ? k : k - P) : 0;
-      const float2* Tn = T + n * P;
-      const float2* An = A + n * R;
-      float bs = 0.f;
-      if (bshared) {
-        const float2 sv = An[jcol[0]];
-        bs = (kv && jval[0]) ? (kre ? sv.x : sv.y) : 0.f;
-      }
+    for (int ks = 0; ks < KS; ks += MF_UK) {
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        if (wv + NW * t < ntile) {  // wave-uniform
-          const float2 tv = Tn[mrow[t]];
-          const float av = (kv && ival[t]) ? (ire[t] ? (kre ? tv.x : -tv.y) : (kre ? tv.y : tv.x)) : 0.f;
-          float bv = bs;
-          if (!bshared) {
-            const float2 sv = An[jcol[t]];
-            bv = (kv && jval[t]) ? (kre ? sv.x : sv.y) : 0.f;
-          }
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
-        }
+      for (int u = 0; u < MF_UK; ++u) {
+        const int ka = 4 * (ks + u) * P, kb = 4 * (ks + u) * R;  // two complex columns per k-step
+        float av[MF_TR], bv[TC];
+#pragma unroll
+        for (int t = 0; t < MF_TR; ++t) av[t] = __uint_as_float(__float_as_uint(Sf[aoff[t] + ka]) ^ sgn);
+#pragma unroll
+        for (int c = 0; c < TC; ++c) bv[c] = Sf[boff[c] + kb];
+#pragma unroll
+        for (int t = 0; t < MF_TR; ++t)
+#pragma unroll
+          for (int c = 0; c < TC; ++c)
+            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[c], acc[t][c], 0, 0, 0);
       }
     }
   }
   // partial slot of this item, or (translations with one item per box) the
-  // output expansion itself, overwritten or accumulated
-  float* out = reinterpret_cast<float*>(part + (int64_t)(dtgt ? dtgt[blockIdx.x] : (int)blockIdx.x) * PR);
+  // output expansion itself, overwritten or accumulated; lane rows 4 kq + v of
+  // a tile are outputs m = 8 rt + 2 kq + v / 2, real part for even v
+  float2* out = part + (int64_t)(dtgt ? dtgt[blockIdx.x] : (int)blockIdx.x) * PR;
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wv + NW * t;
-    if (tile < ntile) {
-      const int j = 16 * (tile % NT) + l16;
+  for (int t = 0; t < MF_TR; ++t) {
+    const int rt = wr * MF_TR + t;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * (tile / NT) + 4 * kq + v;
-        if (i < P2 && j < R) {
-          const bool ir = i < P;
-          float* o = out + 2 * ((ir ? i : i - P) * R + j) + (ir ? 0 : 1);
-          *o = accumulate ? *o + acc[t][v] : acc[t][v];
+    for (int c = 0; c < TC; ++c) {
+      const int j = 16 * (wc * TC + c) + l16;
+      if (rt < MT && j < R) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int m = 8 * rt + 2 * kq + h;
+          if (m < P) {
+            float2* o = out + (int64_t)m * R + j;
+            const float2 r = make_float2(acc[t][c][2 * h], acc[t][c][2 * h + 1]);
+            *o = accumulate ? make_float2(o->x + r.x, o->y + r.y) : r;
+          }
         }
       }
     }
   }
+}
+
+// Launch of k_m2l_mfma for R in [1, 64] and 2P <= 144 (p <= 35).
+inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const int* src, const int* opi,
+                            const float2* ops, const float2* in, float2* out, const int* dtgt, int accumulate,
+                            hipStream_t s) {
+  const int P = 2 * p + 1, MT = (2 * P + 15) / 16;
+  const size_t lds = mf_lds_bytes(P, R);
+  const bool wide = R > 32, tall = MT > 2 * MF_TR;
+  if (!wide && !tall)
+    hipLaunchKernelGGL((k_m2l_mfma<1, 4>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in, out,
+                       dtgt, accumulate);
+  else if (wide && !tall)
+    hipLaunchKernelGGL((k_m2l_mfma<2, 4>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in, out,
+                       dtgt, accumulate);
+  else if (!wide)
+    hipLaunchKernelGGL((k_m2l_mfma<1, 6>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in, out,
+                       dtgt, accumulate);
+  else
+    hipLaunchKernelGGL((k_m2l_mfma<2, 6>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in, out,
+                       dtgt, accumulate);
+}
+
+// LDS limit of the four k_m2l_mfma instantiations (dynamic LDS above 64 KiB
+// must be allowed per kernel).
+inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
+  const void* fs[4] = {(const void*)k_m2l_mfma<1, 4>, (const void*)k_m2l_mfma<2, 4>, (const void*)k_m2l_mfma<1, 6>,
+                       (const void*)k_m2l_mfma<2, 6>};
+  for (const void* f : fs) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // M2L, operator-major (one right-hand side): one wavefront per operator
@@ -734,18 +783,106 @@ __global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumul
   }
 }
 
+// Point matrices of the P2M and L2P (complex64, evaluated in FP64) for the
+// matrix-core form, per work item (leaf, first point pos, count c) at offset
+// pos P: P2M [n][j] (P x c) = |Gamma_j| J_n(k rho_j) e^{-i n theta_j} / sig_|n|,
+// L2P [j][m] (c x P) = J_m(k rho_j) e^{i m theta_j} / sig_|m|, n, m = -p..p,
+// J_{-n} = (-1)^n J_n.  One thread per point.
+__global__ void __launch_bounds__(64) k_leaf_basis(int p, int nlev, const int* __restrict__ items,
+                                                   const BoxDev* __restrict__ boxes,
+                                                   const int* __restrict__ tree_layer, const double* __restrict__ sig,
+                                                   const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
+                                                   const double* __restrict__ w, float2* __restrict__ zp,
+                                                   float2* __restrict__ zl) {
+  const int b = items[3 * blockIdx.x], pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
+  const int j = threadIdx.x;
+  if (j >= cnt) return;
+  const BoxDev B = boxes[b];
+  const int P = 2 * p + 1;
+  const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
+  const double2 xh = pt_xh[pos + j];
+  const double dx = xh.x - B.cx, dh = xh.y - B.ch;
+  double J[MAXP + 1];
+  fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
+  const zd e1 = fm::cis(atan2(dh, dx));
+  const double we = w[pt_elem[pos + j]];
+  float2* P2 = zp + (int64_t)pos * P;
+  float2* L2 = zl + (int64_t)pos * P + (int64_t)j * P;
+  zd ep(1.0, 0.0);  // e^{i m theta}
+  for (int m = 0; m <= p; ++m) {
+    const double a = J[m] / sg[m], an = (m & 1) ? -a : a;  // J_m / sig_m, J_{-m} / sig_m
+    L2[p + m] = make_float2((float)(a * ep.re), (float)(a * ep.im));
+    L2[p - m] = make_float2((float)(an * ep.re), (float)(-an * ep.im));
+    P2[(int64_t)(p + m) * cnt + j] = make_float2((float)(we * a * ep.re), (float)(-we * a * ep.im));
+    P2[(int64_t)(p - m) * cnt + j] = make_float2((float)(we * an * ep.re), (float)(we * an * ep.im));
+    ep = ep * e1;
+  }
+}
+
+// P2M item on matrix cores: part[item] (P x R) = P2M matrix (P x c) times
+// the gathered input rows xt[e_j] (c x R).
+struct P2MOp {
+  int rows, q, R;
+  const float2* Z;
+  const int* elem;
+  const float2* xt;
+  float2* out;
+  __device__ const float2* zrow(int r) const { return Z + (int64_t)r * q; }
+  __device__ const float2* brow(int c) const { return xt + (int64_t)elem[c] * R; }
+  __device__ void store(int r, int j, float re, float im) const { out[(int64_t)r * R + j] = make_float2(re, im); }
+};
+__global__ void __launch_bounds__(64 * PA_NW) k_p2m_mfma(int p, int R, const int* __restrict__ items,
+                                                       const int* __restrict__ pt_elem, const float2* __restrict__ zp,
+                                                       const float2* __restrict__ xt, float2* __restrict__ part) {
+  const int pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
+  const int P = 2 * p + 1;
+  P2MOp op{P, cnt, R, zp + (int64_t)pos * P, pt_elem + pos, xt, part + (int64_t)blockIdx.x * P * R};
+  block_mfma_body(op, R);
+}
+
+// L2P item on matrix cores: y[j][e_r] (=|+=) L2P matrix (c x P) times the
+// leaf's local expansion le[leaf] (P x R).
+struct L2POp {
+  int rows, q, N, R, acc;
+  const float2* Z;
+  const float2* L;
+  const int* elem;
+  float2* y;
+  __device__ const float2* zrow(int r) const { return Z + (int64_t)r * q; }
+  __device__ const float2* brow(int c) const { return L + (int64_t)c * R; }
+  __device__ void store(int r, int j, float re, float im) const {
+    float2* o = y + (int64_t)j * N + elem[r];
+    if (acc) {
+      const float2 v = *o;
+      *o = make_float2(v.x + re, v.y + im);
+    } else {
+      *o = make_float2(re, im);
+    }
+  }
+};
+__global__ void __launch_bounds__(64 * PA_NW) k_l2p_mfma(int p, int R, int N, int accumulate,
+                                                       const int* __restrict__ items, const int* __restrict__ pt_elem,
+                                                       const float2* __restrict__ zl, const float2* __restrict__ le,
+                                                       float2* __restrict__ y) {
+  const int b = items[3 * blockIdx.x], pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
+  const int P = 2 * p + 1;
+  L2POp op{cnt, P, N, R, accumulate, zl + (int64_t)pos * P, le + (int64_t)b * P * R, pt_elem + pos, y};
+  block_mfma_body(op, R);
+}
+
 // y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row;
 // right-hand sides in groups of G share each matrix value and index load.
 template <typename RT, int G>
-__global__ void __launch_bounds__(256) k_near_csr(int N, int R, const int* __restrict__ ptr,
-                                                  const int* __restrict__ src,
+__global__ void __launch_bounds__(256) k_near_csr(int N, int nrow, const int* __restrict__ rows, int R,
+                                                  const int* __restrict__ ptr, const int* __restrict__ src,
                                                   const typename C2T<RT>::T* __restrict__ val,
                                                   const typename C2T<RT>::T* __restrict__ x,
                                                   typename C2T<RT>::T* __restrict__ y) {
   typedef typename C2T<RT>::T V;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ir = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= N) return;
+  if (ir >= nrow) return;
+  const int row = rows ? rows[ir] : ir;
   const int e0 = ptr[row], e1 = ptr[row + 1];
   for (int g = 0; g < R; g += G) {
     RT re[G], im[G];
@@ -1194,6 +1331,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       F->rn_mask.push_back(e.second);
     }
     for (int64_t i = 0; i < N; ++i) F->rn_ptr[i + 1] += F->rn_ptr[i];
+    for (int64_t i = 0; i < N; ++i)
+      if (F->rn_ptr[i + 1] > F->rn_ptr[i]) F->rn_rows.push_back((int)i);
   }
 
   // ---- near-field matrix (CSR by element): free near, reaction near, self ----
@@ -1357,6 +1496,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_near_ptr, F->near_ptr, s));
   LM_TRY(up(F->d_near_src, F->near_src, s));
   LM_TRY(up(F->d_rn_ptr, F->rn_ptr, s));
+  LM_TRY(up(F->d_rn_rows, F->rn_rows, s));
   LM_TRY(up(F->d_rn_src, F->rn_src, s));
   F->tree_layer = tree_layer;
   LM_TRY(up(F->d_tree_layer, F->tree_layer, s));
@@ -1466,7 +1606,24 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
   LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
+  // point matrices of the matrix-core P2M / L2P
+  {
+    const size_t npt = std::max<size_t>(F->pt_elem.size(), 1) * F->P * sizeof(float2);
+    LM_TRY(F->d_p2m_Z32.alloc(npt));
+    LM_TRY(F->d_l2p_Z32.alloc(npt));
+    if (F->item_ptr[3])
+      hipLaunchKernelGGL(k_leaf_basis, dim3(F->item_ptr[3]), dim3(64), 0, s, p, F->nlev, F->d_pt_item.as<int>(),
+                         F->d_boxes.as<BoxDev>(), F->d_tree_layer.as<int>(), F->d_sig.as<double>(),
+                         F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), g->d_w.as<double>(),
+                         F->d_p2m_Z32.as<float2>(), F->d_l2p_Z32.as<float2>());
+    LM_TRY_HIP(hipGetLastError());
+  }
   LM_TRY(fmm_reserve(F, 1));
+  {
+    size_t lds = 0;
+    for (int r = 1; r <= LM_RCHUNK; ++r) lds = std::max(lds, mf_lds_bytes(F->P, r));
+    LM_TRY_HIP(m2l_mfma_allow_lds(lds));
+  }
   int64_t nf = 0, nr = 0, npp = 0;
   for (int t : F->m2l_tab) (t < 0 ? nf : nr)++;
   for (size_t t = 0; t < F->near_tgt.size(); ++t)
@@ -1534,8 +1691,15 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
   const int n_items = F->item_ptr[3];
   V* part = (V*)F->d_p2m_part.p;
+  const bool pt_mfma = sizeof(RT) == 4 && R > 1;  // FP32 multi-RHS: point steps on matrix cores
+  if (pt_mfma)  // complex64 transpose of x, shared by the P2M and the near field
+    hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
+                       (const float2*)x, F->d_xt.as<float2>());
   if (n_items) {
-    if (R == 1)
+    if (pt_mfma)
+      hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
+                         F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(), F->d_xt.as<float2>(), (float2*)part);
+    else if (R == 1)
       hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
                          F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
                          g->d_w.as<double>(), x, N, part);
@@ -1551,15 +1715,13 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   // M2M, finest parents first (FP32 with several right-hand sides: matrix
   // cores, one item per parent holding its children)
   const bool tr_mfma = sizeof(RT) == 4 && R > 1;
-  const size_t lds_tr = (PP + PR) * sizeof(float2);
   for (int l = nlev - 2; l >= 0; --l) {
     const int n = F->parents_ptr[l + 1] - F->parents_ptr[l];
     if (!n) continue;
     if (tr_mfma) {
       const int i0 = F->parents_ptr[l];
-      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(n), dim3(512), lds_tr, s, p, R, F->d_tr_item.as<int>() + 3 * i0,
-                         F->d_tr_src.as<int>(), F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)me,
-                         (float2*)me, F->d_parents.as<int>() + i0, 0);
+      m2l_mfma_launch(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(), F->d_tr_op.as<int>(),
+                      (const float2*)ops, (const float2*)me, (float2*)me, F->d_parents.as<int>() + i0, 0, s);
     } else {
       hipLaunchKernelGGL(k_m2m<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev,
                          F->d_parents.as<int>() + F->parents_ptr[l], boxes, F->d_children.as<int>(), tl, ops, me);
@@ -1579,9 +1741,8 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
                          F->d_m2l_ptr.as<int>(), out, le);
     } else if (sizeof(RT) == 4) {
       float2* mpart = F->d_mf_part.as<float2>();
-      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(F->mf_item.size() / 3), dim3(512), (PP + PR) * sizeof(float2), s, p, R,
-                         F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(), F->d_m2l_op.as<int>(), (const float2*)mops,
-                         (const float2*)me, mpart, (const int*)nullptr, 0);
+      m2l_mfma_launch((int)(F->mf_item.size() / 3), p, R, F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(),
+                      F->d_m2l_op.as<int>(), (const float2*)mops, (const float2*)me, mpart, (const int*)nullptr, 0, s);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
                          F->d_mf_ptr.as<int>(), mpart, (float2*)le);
     } else {
@@ -1598,9 +1759,8 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     if (!n) continue;
     if (tr_mfma) {
       const int i0 = F->l2l_item0 + F->level_ptr[l] - F->level_ptr[1];
-      hipLaunchKernelGGL(k_m2l_mfma<8>, dim3(n), dim3(512), lds_tr, s, p, R, F->d_tr_item.as<int>() + 3 * i0,
-                         F->d_tr_src.as<int>(), F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)le,
-                         (float2*)le, F->d_box_id.as<int>() + F->level_ptr[l], 1);
+      m2l_mfma_launch(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(), F->d_tr_op.as<int>(),
+                      (const float2*)ops, (const float2*)le, (float2*)le, F->d_box_id.as<int>() + F->level_ptr[l], 1, s);
     } else {
       hipLaunchKernelGGL(k_l2l<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev, F->level_ptr[l], boxes, tl,
                          ops + (size_t)F->n_tree_ops * PP, le);
@@ -1613,7 +1773,10 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     const int i0 = F->item_ptr[c], ni = F->item_ptr[c + 1] - i0;
     if (!ni) continue;
     const int* it = F->d_pt_item.as<int>() + 3 * i0;
-    if (R == 1)
+    if (pt_mfma)
+      hipLaunchKernelGGL(k_l2p_mfma, dim3(ni), dim3(64 * PA_NW), 0, s, p, R, N, c > 0 ? 1 : 0, it,
+                         F->d_pt_elem.as<int>(), F->d_l2p_Z32.as<float2>(), (const float2*)le, (float2*)y);
+    else if (R == 1)
       hipLaunchKernelGGL((k_l2p<RT, 64>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0, it, boxes, tl,
                          sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);
     else
@@ -1627,22 +1790,21 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     // FP32, several right-hand sides: free-space near field + self terms as
     // leaf blocks on matrix cores, then the few reaction near pairs
     if (!F->nb_item.empty()) {
-      hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
-                         (const float2*)x, F->d_xt.as<float2>());
       hipLaunchKernelGGL((k_block_mfma<float2, true>), dim3(F->nb_item.size() / 2), dim3(64 * PA_NW), 0, s, N, R,
                          F->d_nb_item.as<int>(), F->d_nb_jptr.as<int>(), F->d_nb_jidx.as<int>(),
                          F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(), F->d_nb_Z32.as<float2>(),
                          F->d_xt.as<float2>(), (float2*)y);
     }
     if (!F->rn_src.empty())
-      hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_rn_ptr.as<int>(),
+      hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(F->rn_rows.size(), 4)), dim3(256), 0, s, N,
+                         (int)F->rn_rows.size(), F->d_rn_rows.as<int>(), R, F->d_rn_ptr.as<int>(),
                          F->d_rn_src.as<int>(), F->d_rn_val32.as<float2>(), (const float2*)x, (float2*)y);
   } else if (R >= 8) {
-    hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
-                       F->d_nm_src.as<int>(), nmv, x, y);
+    hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, N, (const int*)nullptr, R,
+                       F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
   } else {
-    hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, s, N, R, F->d_nm_ptr.as<int>(),
-                       F->d_nm_src.as<int>(), nmv, x, y);
+    hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, s, N, N, (const int*)nullptr, R,
+                       F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
   }
   LM_STAGE(5, 0);
   LM_STAGE(6, 1);

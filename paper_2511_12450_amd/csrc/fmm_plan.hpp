@@ -40,6 +40,7 @@ struct FmmPlan {
   // reaction near field (pairs with their component masks)
   std::vector<int> rn_ptr, rn_src;
   std::vector<unsigned> rn_mask;
+  std::vector<int> rn_rows;  // rows with reaction near pairs
   // near-field matrix (CSR by element, input numbering): free-space near
   // pairs, reaction near pairs and the self term, values precomputed
   std::vector<int> nm_ptr, nm_src;
@@ -68,18 +69,22 @@ struct FmmPlan {
   DevBuf d_m2l_tgt, d_m2l_ptr, d_m2l_src, d_m2l_tab;
   DevBuf d_sig, d_ops64, d_ops32, d_m2l_op;
   DevBuf d_near_tgt, d_near_ptr, d_near_src;
-  DevBuf d_rn_ptr, d_rn_src, d_rn_val;
+  DevBuf d_rn_ptr, d_rn_src, d_rn_val, d_rn_rows;
+  DevBuf d_p2m_Z32, d_l2p_Z32;  // point matrices of the matrix-core P2M / L2P
   DevBuf d_self, d_me, d_le, d_tree_layer;
   DevBuf d_tr_item, d_tr_src, d_tr_op, d_box_id;
   DevBuf d_nb_jptr, d_nb_jidx, d_nb_rows, d_nb_item, d_nb_zoff, d_nb_Z32, d_rn_val32, d_xt;
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   int64_t bytes() const {
-    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_pt_item, &d_p2m_leaf, &d_p2m_ptr, &d_p2m_part,
-                           &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64, &d_ops32,
-                           &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src, &d_rn_val,
-                           &d_self, &d_me, &d_le, &d_tree_layer, &d_nm_ptr, &d_nm_src, &d_nm_val,
-                           &d_nm_val32, &d_nb_jptr, &d_nb_jidx, &d_nb_rows, &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op, &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src, &d_m2l_out};
+    const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_pt_item, &d_p2m_leaf, &d_p2m_ptr,
+                           &d_p2m_part, &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64,
+                           &d_ops32, &d_m2l_op, &d_near_tgt, &d_near_ptr, &d_near_src, &d_rn_ptr, &d_rn_src,
+                           &d_rn_val, &d_rn_rows, &d_p2m_Z32, &d_l2p_Z32, &d_self, &d_me, &d_le, &d_tree_layer,
+                           &d_nm_ptr, &d_nm_src, &d_nm_val, &d_nm_val32, &d_nb_jptr, &d_nb_jidx, &d_nb_rows,
+                           &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op,
+                           &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
+                           &d_m2l_out};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;
