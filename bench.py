@@ -129,8 +129,8 @@ def main():
     w = wl.three_layer()
     obs = lmfmm.far_field_angles()
     t0 = time.perf_counter()
-    # preconditioner subdomains one level above the FMM leaves (precond=2)
-    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, p=w.p, precond=2)
+    # default preconditioner: the coarsest subdomain level that fits
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, p=w.p)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     _log(f"geometry ready in {setup_s:.1f} s")

@@ -92,7 +92,9 @@ lm_status lm_destroy_layers(lm_layers layers);
  *   (default 48); precond: build the overlapping domain-decomposition
  *   preconditioner of Sec. 4.2 (FMM only): 0 none, 1 subdomains = the
  *   free-space leaf boxes, c >= 2 subdomains = boxes c-1 levels above the
- *   leaves (larger blocks, fewer iterations); default (-1) = 2.
+ *   leaves (larger blocks, fewer iterations); default (-1) = the coarsest
+ *   level whose neighbourhoods hold at most 8192 elements and whose blocks
+ *   fit a quarter of the free device memory.
  * The handle keeps a reference to `layers`, which must outlive it.
  * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */
 typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;

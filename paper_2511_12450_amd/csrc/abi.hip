@@ -145,8 +145,7 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
     LM_TRY(dense_assemble(g.get(), s));
   } else {
     LM_TRY(fmm_build(g.get(), s));
-    const int want_pre = o.precond < 0 ? 2 : o.precond;
-    if (want_pre) LM_TRY(precond_build(g.get(), want_pre - 1, s));
+    if (o.precond) LM_TRY(precond_build(g.get(), o.precond < 0 ? -1 : o.precond - 1, s));
   }
   LM_TRY_HIP(hipStreamSynchronize(s));
   *out = g.release();

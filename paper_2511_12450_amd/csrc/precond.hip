@@ -14,7 +14,7 @@
 // solves for the |B| unit vectors, and a kernel stores the scaled rows.
 // Subdomains are the free-space tree's boxes at the leaf level, or `coarsen`
 // levels above it (bigger overlapping blocks: fewer GMRES iterations for a
-// larger setup and apply).  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
+// larger setup and apply); coarsen < 0 picks the coarsest level that fits.  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
 // the lanes of a wavefront read consecutive addresses of one row); the
 // mixed form applies an FP32 copy of Z.
 #include <rocblas/rocblas.h>
@@ -26,6 +26,8 @@
 
 #include "block_mfma.hpp"
 #include "fmm_plan.hpp"
+
+constexpr int PRE_QMAX = 8192;  // largest subdomain neighbourhood (LU workspace qmax^2 complex128)
 
 struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
@@ -174,39 +176,57 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   g->pre = P;
   // subdomains: free-tree boxes at level lp; each owns the points of its
   // leaves; neighbourhood = the subdomain and its (up to 8) level-lp neighbours
-  const int lp = std::max(0, F->lf - std::max(0, coarsen));
-  const double wl = F->w_top / (double)(1 << lp);
-  std::map<std::tuple<int, int, int>, std::vector<int>> pts;  // (tree, i, j) -> elements
-  for (int b : F->leaf_free) {
-    const BoxDev& B = F->boxes[b];
-    const int sh = B.level - lp;
-    const double wb = F->w_top / (double)(1 << B.level);
-    const int i = (int)std::lround((B.cx - F->x0) / wb - 0.5) >> sh;
-    const int j = (int)std::lround(B.ch / wb - 0.5) >> sh;
-    auto& v = pts[std::make_tuple(B.tree, i, j)];
-    for (int k = 0; k < B.npt; ++k) v.push_back(F->pt_elem[B.pt0 + k]);
-  }
-  (void)wl;
-  P->jptr.push_back(0);
-  int64_t z = 0;
-  for (auto& kv : pts) {
-    const int t = std::get<0>(kv.first), i = std::get<1>(kv.first), j = std::get<2>(kv.first);
-    for (int e : kv.second) P->jidx.push_back(e);
-    for (int di = -1; di <= 1; ++di)
-      for (int dj = -1; dj <= 1; ++dj) {
-        if (!di && !dj) continue;
-        auto it = pts.find(std::make_tuple(t, i + di, j + dj));
-        if (it == pts.end()) continue;
-        for (int e : it->second) P->jidx.push_back(e);
-      }
-    const int q = (int)P->jidx.size() - P->jptr.back();
-    const int nB = (int)kv.second.size();
-    P->jptr.push_back((int)P->jidx.size());
-    P->nb.push_back(nB);
-    P->zoff.push_back(z);
-    z += (int64_t)q * nB;
-    P->qmax = std::max(P->qmax, q);
-    P->bmax = std::max(P->bmax, nB);
+  auto plan = [&](int lp) {
+    P->jptr.assign(1, 0);
+    P->jidx.clear();
+    P->nb.clear();
+    P->zoff.clear();
+    P->qmax = P->bmax = 0;
+    std::map<std::tuple<int, int, int>, std::vector<int>> pts;  // (tree, i, j) -> elements
+    for (int b : F->leaf_free) {
+      const BoxDev& B = F->boxes[b];
+      const int sh = B.level - lp;
+      const double wb = F->w_top / (double)(1 << B.level);
+      const int i = (int)std::lround((B.cx - F->x0) / wb - 0.5) >> sh;
+      const int j = (int)std::lround(B.ch / wb - 0.5) >> sh;
+      auto& v = pts[std::make_tuple(B.tree, i, j)];
+      for (int k = 0; k < B.npt; ++k) v.push_back(F->pt_elem[B.pt0 + k]);
+    }
+    int64_t z = 0;
+    for (auto& kv : pts) {
+      const int t = std::get<0>(kv.first), i = std::get<1>(kv.first), j = std::get<2>(kv.first);
+      for (int e : kv.second) P->jidx.push_back(e);
+      for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (!di && !dj) continue;
+          auto it = pts.find(std::make_tuple(t, i + di, j + dj));
+          if (it == pts.end()) continue;
+          for (int e : it->second) P->jidx.push_back(e);
+        }
+      const int q = (int)P->jidx.size() - P->jptr.back();
+      const int nB = (int)kv.second.size();
+      P->jptr.push_back((int)P->jidx.size());
+      P->nb.push_back(nB);
+      P->zoff.push_back(z);
+      z += (int64_t)q * nB;
+      P->qmax = std::max(P->qmax, q);
+      P->bmax = std::max(P->bmax, nB);
+    }
+    return z;
+  };
+  int64_t z = 0;  // stored block entries
+  if (coarsen >= 0) {
+    z = plan(std::max(0, F->lf - coarsen));
+  } else {
+    // automatic: the coarsest level whose neighbourhoods fit PRE_QMAX and
+    // whose blocks (FP64 and FP32 copies) take at most a quarter of the free
+    // device memory; the leaf level otherwise
+    size_t fr = 0, tot = 0;
+    LM_TRY_HIP(hipMemGetInfo(&fr, &tot));
+    for (int lp = 0; lp <= F->lf; ++lp) {
+      z = plan(lp);
+      if (lp == F->lf || (P->qmax <= PRE_QMAX && (double)z * 24.0 <= 0.25 * (double)fr)) break;
+    }
   }
   P->nleaf = (int)P->nb.size();
   for (int b = 0; b < P->nleaf; ++b)
@@ -214,7 +234,14 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
       P->items.push_back(b);
       P->items.push_back(r);
     }
-  LM_CHECK(P->qmax <= 4096, LM_EINVAL, "preconditioner neighbourhood too large (%d); use a finer level", P->qmax);
+  LM_CHECK(P->qmax <= PRE_QMAX, LM_EINVAL, "preconditioner neighbourhood too large (%d > %d); use a finer level",
+           P->qmax, PRE_QMAX);
+  {  // the VALU apply stages x_J of one or two right-hand sides in LDS (up to 128 KiB)
+    const void* fs[4] = {(const void*)k_pre_apply<double2, double, 1>, (const void*)k_pre_apply<double2, double, 2>,
+                         (const void*)k_pre_apply<float2, float, 2>, (const void*)k_pre_apply<float2, float, 4>};
+    for (const void* f : fs)
+      LM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PRE_QMAX * 8));
+  }
   LM_TRY(upload(P->d_jptr, P->jptr.data(), P->jptr.size() * sizeof(int), s));
   LM_TRY(upload(P->d_jidx, P->jidx.data(), P->jidx.size() * sizeof(int), s));
   LM_TRY(upload(P->d_nb, P->nb.data(), P->nb.size() * sizeof(int), s));

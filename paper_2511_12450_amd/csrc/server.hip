@@ -361,6 +361,7 @@ struct lm_server_s {
   hipEvent_t ev_main = nullptr;
   hipEvent_t ev[SRV_STREAMS] = {};
   DevBuf d_desc, d_h, d_nrm, d_dpart, d_npart, d_y;
+  DevBuf d_fz, d_fphi, d_fff;  // finishing columns: z, phi = M z, far fields
   std::vector<ColDev> hdesc;
   std::vector<double2> hh;
   std::vector<double> hnrm;
@@ -433,32 +434,75 @@ lm_status start_request(lm_server_s* S, Request* q) {
   return LM_OK;
 }
 
-// phi = M z, far field, copy to host; marks the column finished.
-lm_status finish_column(lm_server_s* S, Column* c) {
-  Request* q = c->req;
-  const int N = c->N;
-  DevBuf phi, ff;
-  LM_TRY(phi.alloc((size_t)N * sizeof(double2)));
-  const bool pre = q->o.precond && c->g->pre;
-  if (pre) {
-    LM_TRY(precond_apply(c->g, S->o.precision, 1, c->z.p, phi.p, S->s));
-  } else {
-    LM_TRY_HIP(hipMemcpyAsync(phi.p, c->z.p, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, S->s));
+// phi = M z, far fields and copies to host memory for the columns that
+// finished this round; marks them finished.  Columns on one geometry share
+// one preconditioner launch (several right-hand sides), columns of one
+// request one far-field launch.  Returns the first failure; the columns of a
+// failed group are reported through *failed.
+lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<Request*>* failed) {
+  std::stable_sort(fin.begin(), fin.end(), [](const Column* a, const Column* b) {
+    if (a->g != b->g) return a->g < b->g;
+    const bool pa = a->req->o.precond != 0, pb = b->req->o.precond != 0;
+    if (pa != pb) return pa < pb;
+    if (a->req != b->req) return a->req->id < b->req->id;
+    return a->col < b->col;
+  });
+  lm_status first = LM_OK;
+  for (size_t i0 = 0; i0 < fin.size();) {
+    lm_geom_s* g = fin[i0]->g;
+    const bool pre = fin[i0]->req->o.precond && g->pre;
+    size_t i1 = i0;
+    while (i1 < fin.size() && fin[i1]->g == g && (fin[i1]->req->o.precond != 0) == (fin[i0]->req->o.precond != 0))
+      ++i1;
+    const int k = (int)(i1 - i0), N = fin[i0]->N;
+    const size_t vb = (size_t)N * sizeof(double2);
+    auto group = [&]() -> lm_status {
+      if (S->d_fz.bytes < k * vb) LM_TRY(S->d_fz.alloc(k * vb));
+      if (S->d_fphi.bytes < k * vb) LM_TRY(S->d_fphi.alloc(k * vb));
+      char* zb = (char*)S->d_fz.p;
+      char* pb = (char*)S->d_fphi.p;
+      for (int i = 0; i < k; ++i)
+        LM_TRY_HIP(hipMemcpyAsync((pre ? zb : pb) + i * vb, fin[i0 + i]->z.p, vb, hipMemcpyDeviceToDevice, S->s));
+      if (pre) LM_TRY(precond_apply(g, S->o.precision, k, zb, pb, S->s));
+      for (int i = 0; i < k; ++i) {
+        Column* c = fin[i0 + i];
+        LM_TRY_HIP(hipMemcpyAsync(c->req->phi.data() + (size_t)c->col * N, pb + i * vb, vb, hipMemcpyDeviceToHost,
+                                  S->s));
+      }
+      for (int a = 0; a < k;) {  // one far-field launch per request
+        Request* q = fin[i0 + a]->req;
+        int b = a;
+        while (b < k && fin[i0 + b]->req == q) ++b;
+        const int no = (int)q->obs.size();
+        if (no) {
+          const size_t fb = (size_t)(b - a) * no * sizeof(double2);
+          if (S->d_fff.bytes < fb) LM_TRY(S->d_fff.alloc(fb));
+          LM_TRY(farfield_launch(g, b - a, pb + a * vb, no, q->obs.data(), S->d_fff.p, S->s));
+          for (int i = a; i < b; ++i)
+            LM_TRY_HIP(hipMemcpyAsync(q->ff.data() + (size_t)fin[i0 + i]->col * no,
+                                      (const double2*)S->d_fff.p + (size_t)(i - a) * no, (size_t)no * sizeof(double2),
+                                      hipMemcpyDeviceToHost, S->s));
+        }
+        a = b;
+      }
+      LM_TRY_HIP(hipStreamSynchronize(S->s));
+      return LM_OK;
+    };
+    const lm_status st = group();
+    for (size_t i = i0; i < i1; ++i) {
+      Column* c = fin[i];
+      if (st < 0) {
+        if (failed && (failed->empty() || failed->back() != c->req)) failed->push_back(c->req);
+        continue;
+      }
+      c->req->rep[c->col].iterations = c->its;
+      c->req->rep[c->col].rel_residual = c->res;
+      c->finished = true;
+    }
+    if (st < 0 && first == LM_OK) first = st;
+    i0 = i1;
   }
-  LM_TRY_HIP(hipMemcpyAsync(q->phi.data() + (size_t)c->col * N, phi.p, (size_t)N * sizeof(double2),
-                            hipMemcpyDeviceToHost, S->s));
-  const int no = (int)q->obs.size();
-  if (no) {
-    LM_TRY(ff.alloc((size_t)no * sizeof(double2)));
-    LM_TRY(farfield_launch(c->g, 1, phi.p, no, q->obs.data(), ff.p, S->s));
-    LM_TRY_HIP(hipMemcpyAsync(q->ff.data() + (size_t)c->col * no, ff.p, (size_t)no * sizeof(double2),
-                              hipMemcpyDeviceToHost, S->s));
-  }
-  LM_TRY_HIP(hipStreamSynchronize(S->s));
-  q->rep[c->col].iterations = c->its;
-  q->rep[c->col].rel_residual = c->res;
-  c->finished = true;
-  return LM_OK;
+  return first;
 }
 
 // One round of the worker (see the file comment).  Returns an error only for
@@ -824,9 +868,13 @@ lm_status round(lm_server_s* S) {
     S->rounds++;
   }
   const double tf0 = now_s();
-  for (Column* c : to_finish) {
-    lm_status st = finish_column(S, c);
-    if (st < 0) fail_request(S, c->req, st, lm_last_error());
+  if (!to_finish.empty()) {
+    std::vector<Request*> failed;
+    const lm_status st = finish_columns(S, to_finish, &failed);
+    if (st < 0) {
+      const std::string msg = lm_last_error();
+      for (Request* q : failed) fail_request(S, q, st, msg);
+    }
   }
   const double tf1 = now_s();
   std::lock_guard<std::mutex> lk(S->mu);

@@ -112,3 +112,9 @@ def test_coarser_subdomains_fewer_iterations_same_solution():
     assert r2[0][0] < r1[0][0]
     obs = lmfmm.far_field_angles()[::7]
     assert _rel(g2.far_field(p2, obs).cpu().numpy(), g1.far_field(p1, obs).cpu().numpy()) < 1e-6
+    # the default picks the coarsest level that fits: no more iterations
+    g3 = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+    p3, r3, s3 = g3.solve(th, tol=1e-8, max_iter=800, restart=800)
+    print("iterations with the default subdomains:", r3[0][0], flush=True)
+    assert s3 == lmfmm.LM_OK and r3[0][0] <= r2[0][0]
+    assert _rel(g3.far_field(p3, obs).cpu().numpy(), g1.far_field(p1, obs).cpu().numpy()) < 1e-6
