@@ -197,7 +197,8 @@ lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, 
  * every admitted solve one Arnoldi step per round; solves on the same
  * geometry share one multi-right-hand-side launch per round, solves on
  * different geometries run on separate streams.  Krylov bases stay in device
- * memory.  Requests are admitted first-in first-out while the number of
+ * memory (complex64 under LM_MIXED, where the charged footprint below, which
+ * counts complex128 bases, is an upper bound).  Requests are admitted first-in first-out while the number of
  * active right-hand sides stays <= max_active_rhs and the estimated device
  * footprint of the admitted requests stays <= hbm_budget_bytes (basis,
  * work vectors and the per-right-hand-side FMM workspace; the geometry itself
@@ -246,10 +247,11 @@ lm_status lm_server_stats(lm_server server, int64_t* out6);
  * joined), [1] ms in the Gram-Schmidt phase (classical Gram-Schmidt with a
  * delayed second pass: one dot pass and one update pass over each basis,
  * plus the norms), [2] bytes that phase must move at minimum: per Arnoldi
- * column at step j (basis V[0..j] of N complex doubles),
- * (2 (j+1) + 6) N x 16 (dot pass: V[0..j] and the K M output; update pass:
- * V[0..j-1], u and the K M output read, v_j and the next vector written),
- * plus N x 16 per column for the norms; [3] ms in the M2L
+ * column at step j, with b = 16 bytes per basis element (LM_FP64) or 8
+ * (LM_MIXED: the Krylov basis is stored in complex64, every sum is
+ * accumulated in FP64), (2 j + 5) N b + 3 N x 16 (dot pass: V[0..j], u and
+ * the K M output; residual norm of the K M output; update pass: V[0..j-1],
+ * u and the K M output read, v_j and the next vector written); [3] ms in the M2L
  * launches of the fused FMM matvecs (first launch of each geometry stream
  * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
  * [5] the number of those launches, [6] host wall-clock ms of the rounds

@@ -53,13 +53,16 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Per-column operands of the batched kernels.
+// Per-column operands of the batched kernels.  The Krylov basis is stored
+// in BT (complex128, or complex64 for the mixed form: half the Gram-Schmidt
+// traffic; every dot product and update is still accumulated in FP64); all
+// other vectors are complex128.
 struct ColDev {
-  double2* V;         // basis [m+1][N]
-  double2* w;         // vector being orthogonalised / residual
+  void* V;            // basis [m+1][N] in BT
+  double2* w;         // K M output / residual vector
   const double2* g;   // right-hand side (residual form), or null
   const double2* src; // copy / scale source
-  double2* dst;       // copy / scale destination
+  double2* dst;       // gather destination (K M input slot), or null
   double2* z;         // solution accumulator
   const double2* y;   // combination / update coefficients
   const double* nsrc; // squared norm to normalise by (device), or null
@@ -67,15 +70,27 @@ struct ColDev {
   double2 dr;         // complex scalar of the update pass
   double scale;
   int N, cnt;
+  int vj;             // gather: basis vector to normalise, or -1 (gather w)
 };
 
-// dst = src * scale      (grid (ceil(Nmax / 256), ncols))
+__device__ __forceinline__ double2 bld(const double2* p) { return *p; }
+__device__ __forceinline__ double2 bld(const float2* p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ double2 bcv(double2 v) { return v; }
+__device__ __forceinline__ double2 bcv(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ void bst(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void bst(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+// V[0] = src * scale      (grid (ceil(Nmax / 256), ncols))
+template <typename BT>
 __global__ void __launch_bounds__(256) k_s_copy(const ColDev* __restrict__ d) {
   const ColDev c = d[blockIdx.y];
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= c.N) return;
   const double2 v = c.src[n];
-  c.dst[n] = make_double2(v.x * c.scale, v.y * c.scale);
+  bst((BT*)c.V + n, make_double2(v.x * c.scale, v.y * c.scale));
 }
 
 __device__ __forceinline__ double s_wave_sum(double v) {
@@ -119,13 +134,15 @@ __global__ void __launch_bounds__(64) k_s_norm_final(const ColDev* __restrict__ 
 }
 
 // z += sum_{i < cnt} V[i] y[i]
+template <typename BT>
 __global__ void __launch_bounds__(256) k_s_lincomb(const ColDev* __restrict__ d) {
   const ColDev c = d[blockIdx.y];
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= c.N) return;
+  const BT* V = (const BT*)c.V;
   double2 acc = c.z[n];
   for (int i = 0; i < c.cnt; ++i) {
-    const double2 a = c.y[i], v = c.V[(int64_t)i * c.N + n];
+    const double2 a = c.y[i], v = bld(V + (int64_t)i * c.N + n);
     acc.x = fma(a.x, v.x, acc.x);
     acc.x = fma(-a.y, v.y, acc.x);
     acc.y = fma(a.x, v.y, acc.y);
@@ -135,21 +152,30 @@ __global__ void __launch_bounds__(256) k_s_lincomb(const ColDev* __restrict__ d)
 }
 
 // Gathers the K M inputs of Arnoldi columns and normalises lagged basis
-// vectors: v = w * s with s = 1/sqrt(*nsrc) (then written back to w) or
-// s = scale; dst (the fused launch's input slot) may be null.
+// vectors: v = V[vj] * s with s = 1/sqrt(*nsrc) (written back to V[vj]), or
+// v = w * scale (vj < 0); dst (the fused launch's input slot) may be null.
+template <typename BT>
 __global__ void __launch_bounds__(256) k_s_gather(const ColDev* __restrict__ d) {
   const ColDev c = d[blockIdx.y];
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= c.N) return;
-  const double s = c.nsrc ? 1.0 / sqrt(*c.nsrc) : c.scale;
-  double2 v = c.w[n];
-  v = make_double2(v.x * s, v.y * s);
-  if (c.nsrc) c.w[n] = v;
+  double2 v;
+  if (c.vj >= 0) {
+    BT* vp = (BT*)c.V + (int64_t)c.vj * c.N + n;
+    const double s = c.nsrc ? 1.0 / sqrt(*c.nsrc) : c.scale;
+    v = bld(vp);
+    v = make_double2(v.x * s, v.y * s);
+    if (c.nsrc) bst(vp, v);
+  } else {
+    v = c.w[n];
+    v = make_double2(v.x * c.scale, v.y * c.scale);
+  }
   if (c.dst) c.dst[n] = v;
 }
 
 // Workgroup partials of conj(V[i]) . u and conj(V[i]) . z, u = V[cnt-1],
 // z = the K M output (or none), for the basis vectors of this workgroup.
+template <typename BT>
 __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, double2* __restrict__ pa,
                                                  double2* __restrict__ pb, int ldh, int nb) {
   const ColDev c = d[blockIdx.y];
@@ -157,8 +183,10 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
   if (ib >= c.cnt || blockIdx.x * SD_SLICE >= c.N) return;  // uniform per workgroup
   const int ie = min(c.cnt, ib + SD_IBLK);
   constexpr int EPT = SD_SLICE / 256;
-  const double2* u = c.V + (int64_t)(c.cnt - 1) * c.N;
-  double2 xu[EPT], xz[EPT];
+  const BT* V = (const BT*)c.V;
+  const BT* u = V + (int64_t)(c.cnt - 1) * c.N;
+  BT xb[EPT];  // u in the basis type
+  double2 xz[EPT];
   int idx[EPT];
   bool ok[EPT];
 #pragma unroll
@@ -166,44 +194,67 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
     const int n = blockIdx.x * SD_SLICE + threadIdx.x + 256 * e;
     ok[e] = n < c.N;
     idx[e] = ok[e] ? n : 0;
-    xu[e] = ok[e] ? u[idx[e]] : make_double2(0.0, 0.0);
+    xb[e] = u[idx[e]];
+    if (!ok[e]) xb[e].x = xb[e].y = 0;
     xz[e] = (ok[e] && c.w) ? c.w[idx[e]] : make_double2(0.0, 0.0);
   }
-  __shared__ double red[4][4];
-  for (int i = ib; i < ie; ++i) {
-    const double2* v = c.V + (int64_t)i * c.N;
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  // two basis vectors per iteration; the eight sums (re / im of V^H u and
+  // V^H z for each) are reduced over the wavefront by a transposing
+  // butterfly (after the xor-32, -16 and -8 steps lane l holds sum number
+  // l / 8 of its lane group, then three plain steps finish it), and the
+  // per-wave results of the whole block meet in LDS behind one barrier
+  __shared__ double red[SD_IBLK][4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int i = ib; i < ie; i += 2) {
+    const bool two = i + 1 < ie;
+    const BT* v0 = V + (int64_t)i * c.N;
+    const BT* v1 = V + (int64_t)(two ? i + 1 : i) * c.N;
+    BT b0[EPT], b1[EPT];  // raw loads (converted at use: fewer registers in flight)
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const double2 a = ok[e] ? v[idx[e]] : make_double2(0.0, 0.0);
-      ar = fma(a.x, xu[e].x, ar);
-      ar = fma(a.y, xu[e].y, ar);
-      ai = fma(a.x, xu[e].y, ai);
-      ai = fma(-a.y, xu[e].x, ai);
-      br = fma(a.x, xz[e].x, br);
-      br = fma(a.y, xz[e].y, br);
-      bi = fma(a.x, xz[e].y, bi);
-      bi = fma(-a.y, xz[e].x, bi);
+      b0[e] = v0[idx[e]];
+      b1[e] = v1[idx[e]];
     }
-    ar = s_wave_sum(ar);
-    ai = s_wave_sum(ai);
-    br = s_wave_sum(br);
-    bi = s_wave_sum(bi);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      red[0][threadIdx.x >> 6] = ar;
-      red[1][threadIdx.x >> 6] = ai;
-      red[2][threadIdx.x >> 6] = br;
-      red[3][threadIdx.x >> 6] = bi;
+    double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const double2 a0 = ok[e] ? bcv(b0[e]) : make_double2(0.0, 0.0);
+      const double2 a1 = (ok[e] && two) ? bcv(b1[e]) : make_double2(0.0, 0.0);
+      const double2 xu = bcv(xb[e]);
+      t[0] = fma(a0.x, xu.x, fma(a0.y, xu.y, t[0]));
+      t[1] = fma(a0.x, xu.y, fma(-a0.y, xu.x, t[1]));
+      t[2] = fma(a0.x, xz[e].x, fma(a0.y, xz[e].y, t[2]));
+      t[3] = fma(a0.x, xz[e].y, fma(-a0.y, xz[e].x, t[3]));
+      t[4] = fma(a1.x, xu.x, fma(a1.y, xu.y, t[4]));
+      t[5] = fma(a1.x, xu.y, fma(-a1.y, xu.x, t[5]));
+      t[6] = fma(a1.x, xz[e].x, fma(a1.y, xz[e].y, t[6]));
+      t[7] = fma(a1.x, xz[e].y, fma(-a1.y, xz[e].x, t[7]));
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int64_t o = ((int64_t)blockIdx.y * ldh + i) * nb + blockIdx.x;
-      pa[o] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
-                           (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
-      pb[o] = make_double2((red[2][0] + red[2][1]) + (red[2][2] + red[2][3]),
-                           (red[3][0] + red[3][1]) + (red[3][2] + red[3][3]));
+    // 8 -> 4 -> 2 -> 1 values per lane (lanes with the step's bit set keep the upper half)
+#pragma unroll
+    for (int h = 4, o = 32; h >= 1; h >>= 1, o >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const double send = up ? t[k] : t[k + h];
+        const double keep = up ? t[k + h] : t[k];
+        t[k] = keep + __shfl_xor(send, o, 64);
+      }
     }
+    double r = t[0];
+    r += __shfl_xor(r, 4, 64);
+    r += __shfl_xor(r, 2, 64);
+    r += __shfl_xor(r, 1, 64);
+    const int q = lane >> 3;  // sum number: vector q / 4, component q % 4
+    if ((lane & 7) == 0 && (q < 4 || two)) red[i - ib + (q >> 2)][wv][q & 3] = r;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ie - ib; t += 256) {
+    const double(*r)[4] = red[t];
+    const int64_t o = ((int64_t)blockIdx.y * ldh + ib + t) * nb + blockIdx.x;
+    pa[o] = make_double2((r[0][0] + r[1][0]) + (r[2][0] + r[3][0]), (r[0][1] + r[1][1]) + (r[2][1] + r[3][1]));
+    pb[o] = make_double2((r[0][2] + r[1][2]) + (r[2][2] + r[3][2]), (r[0][3] + r[1][3]) + (r[2][3] + r[3][3]));
   }
 }
 
@@ -238,6 +289,7 @@ __global__ void __launch_bounds__(64) k_s_dots2_final(const ColDev* __restrict__
 //   V[j+1] <- z * scale - u * dr - sum_i e_i V[i]          (once-projected next vector)
 // with u = V[j], z = the K M output, a = y[0..j), e = y[j..2j); wave
 // partials of |V[j+1]|^2 into part.
+template <typename BT>
 __global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d, double* __restrict__ part, int nw) {
   const ColDev c = d[blockIdx.y];
   if (blockIdx.x * 256 >= c.N) return;
@@ -245,8 +297,9 @@ __global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d,
   const bool ok = n < c.N;
   const int o = ok ? n : 0;
   const int j = c.cnt;
-  double2* uj = c.V + (int64_t)j * c.N;
-  const double2 u = uj[o];
+  BT* V = (BT*)c.V;
+  BT* uj = V + (int64_t)j * c.N;
+  const double2 u = bld(uj + o);
   double2 q = u;
   const double2 zv = c.w[o];
   double2 w = make_double2(zv.x * c.scale - (u.x * c.dr.x - u.y * c.dr.y),
@@ -255,7 +308,7 @@ __global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d,
   for (int i0 = 0; i0 < j; i0 += U) {
     double2 v[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) v[k] = (i0 + k < j) ? c.V[(int64_t)(i0 + k) * c.N + o] : make_double2(0.0, 0.0);
+    for (int k = 0; k < U; ++k) v[k] = (i0 + k < j) ? bld(V + (int64_t)(i0 + k) * c.N + o) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       if (i0 + k < j) {
@@ -272,8 +325,8 @@ __global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d,
     }
   }
   if (ok) {
-    uj[o] = make_double2(q.x * c.scale, q.y * c.scale);
-    uj[c.N + o] = w;
+    bst(uj + o, make_double2(q.x * c.scale, q.y * c.scale));
+    bst(uj + c.N + o, w);
   }
   const double qn = s_wave_sum(ok ? w.x * w.x + w.y * w.y : 0.0);
   if ((threadIdx.x & 63) == 0) part[(int64_t)blockIdx.y * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = qn;
@@ -396,6 +449,9 @@ lm_status upload_desc(lm_server_s* S, const std::vector<ColDev>& d) {
   return LM_OK;
 }
 
+// Bytes per element of a column's Krylov basis.
+size_t basis_bytes(const lm_server_s* S) { return S->o.precision == LM_MIXED ? sizeof(float2) : sizeof(double2); }
+
 lm_status ensure(DevBuf& b, size_t bytes) {
   if (b.bytes < bytes) LM_TRY(b.alloc(bytes));
   return LM_OK;
@@ -414,7 +470,7 @@ lm_status start_request(lm_server_s* S, Request* q) {
     col->g = q->g;
     col->N = N;
     col->m = m;
-    LM_TRY(col->V.alloc((size_t)(m + 1) * N * sizeof(double2)));
+    LM_TRY(col->V.alloc((size_t)(m + 1) * N * basis_bytes(S)));
     LM_TRY(col->z.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->gv.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->y.alloc((size_t)(m + 1) * sizeof(double2)));
@@ -514,6 +570,7 @@ lm_status round(lm_server_s* S) {
     if (!c->finished) cols.push_back(c);
   if (cols.empty()) return LM_OK;
   const int prec = S->o.precision;
+  const bool f32 = prec == LM_MIXED;  // complex64 Krylov basis
   const int nc = (int)cols.size();
   int Nmax = 0, ldh = 1, cntmax = 0;
   for (Column* c : cols) {
@@ -548,9 +605,11 @@ lm_status round(lm_server_s* S) {
       d.dst = G.X.as<double2>() + (size_t)k * N;
       d.scale = 1.0;
       if (c->phase == PH_ARNOLDI) {
-        d.w = c->V.as<double2>() + (size_t)c->j * N;
+        d.V = c->V.p;
+        d.vj = c->j;
         d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;
       } else {
+        d.vj = -1;
         d.w = c->z.as<double2>();
       }
       gath.push_back(d);
@@ -561,13 +620,19 @@ lm_status round(lm_server_s* S) {
     if (c->phase == PH_ARNOLDI && !c->km && c->j >= 1) {
       ColDev d{};
       d.N = c->N;
-      d.w = c->V.as<double2>() + (size_t)c->j * c->N;
+      d.V = c->V.p;
+      d.vj = c->j;
       d.nsrc = c->dn.as<double>();
       gath.push_back(d);
     }
   if (!gath.empty()) {
     LM_TRY(upload_desc(S, gath));
-    hipLaunchKernelGGL(k_s_gather, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s, S->d_desc.as<ColDev>());
+    if (f32)
+      hipLaunchKernelGGL(k_s_gather<float2>, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s,
+                         S->d_desc.as<ColDev>());
+    else
+      hipLaunchKernelGGL(k_s_gather<double2>, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s,
+                         S->d_desc.as<ColDev>());
     LM_TRY_HIP(hipGetLastError());
   }
   LM_TRY_HIP(hipEventRecord(S->ev_main, S->s));
@@ -616,7 +681,7 @@ lm_status round(lm_server_s* S) {
   for (int i = 0; i < nc; ++i) {
     Column* c = cols[i];
     ColDev& d = S->hdesc[i];
-    d.V = c->V.as<double2>();
+    d.V = c->V.p;
     d.N = c->N;
     if (c->phase == PH_ARNOLDI) {
       d.cnt = c->j + 1;  // dots against V[0..j]; u = V[j]
@@ -635,7 +700,12 @@ lm_status round(lm_server_s* S) {
     LM_TRY(ensure(S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
     double2* pa = S->d_dpart.as<double2>();
     double2* pb = pa + (size_t)nc * ldh * nbd;
-    hipLaunchKernelGGL(k_s_dots2, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb, ldh, nbd);
+    if (f32)
+      hipLaunchKernelGGL(k_s_dots2<float2>, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb,
+                         ldh, nbd);
+    else
+      hipLaunchKernelGGL(k_s_dots2<double2>, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb,
+                         ldh, nbd);
     hipLaunchKernelGGL(k_s_dots2_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, pa, pb, ldh, nbd,
                        S->d_h.as<double2>(), hs);
   }
@@ -659,6 +729,7 @@ lm_status round(lm_server_s* S) {
   std::vector<double2> ys, cf;
   std::vector<Column*> to_finish;
   double gsb = 0.0;
+  const double bb = (double)basis_bytes(S);
   for (int i = 0; i < nc; ++i) {
     Column* c = cols[i];
     const double nrm = std::sqrt(S->hnrm[i]);
@@ -671,7 +742,7 @@ lm_status round(lm_server_s* S) {
       c->e1[0] = beta;
       ColDev d{};
       d.src = r;
-      d.dst = c->V.as<double2>();
+      d.V = c->V.p;
       d.scale = 1.0 / beta;
       d.N = N;
       scal.push_back(d);
@@ -685,7 +756,7 @@ lm_status round(lm_server_s* S) {
         yv[k] = acc / c->H[(size_t)k * (m + 1) + k];
       }
       ColDev d{};
-      d.V = c->V.as<double2>();
+      d.V = c->V.p;
       d.z = c->z.as<double2>();
       d.N = N;
       d.cnt = cnt;
@@ -723,7 +794,9 @@ lm_status round(lm_server_s* S) {
     }
     // Arnoldi step j: a = V[0..j]^H u_j, b = V[0..j]^H K M u_j
     const int j = c->j;
-    gsb += (c->km ? 2.0 * (j + 1) + 6.0 : (j + 2.0)) * n16;
+    // basis vectors (bb bytes per element) and complex128 vectors moved by the
+    // dot, residual-norm and update kernels of this step
+    gsb += (c->km ? (2.0 * j + 5.0) * bb + 3.0 * 16.0 : (j + 2.0) * bb) * N;
     const double2* ha = &S->hh[(size_t)i * hs];
     const double2* hb = ha + ldh;
     std::vector<C> aQ(j), bQ(j);
@@ -789,7 +862,7 @@ lm_status round(lm_server_s* S) {
     const C cj = ((gamma - ab) / rho - hj) / rho;
     const C dd2 = hj / rho + cj;
     ColDev d{};
-    d.V = c->V.as<double2>();
+    d.V = c->V.p;
     d.w = c->w;
     d.N = N;
     d.cnt = j;
@@ -835,16 +908,30 @@ lm_status round(lm_server_s* S) {
     const ColDev* da = S->d_desc.as<ColDev>();
     LM_TRY_HIP(hipEventRecord(S->t1, S->s));
     if (!upd.empty()) {
-      hipLaunchKernelGGL(k_s_update2, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
-                         S->d_npart.as<double>(), nwu);
+      if (f32)
+        hipLaunchKernelGGL(k_s_update2<float2>, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
+                           S->d_npart.as<double>(), nwu);
+      else
+        hipLaunchKernelGGL(k_s_update2<double2>, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
+                           S->d_npart.as<double>(), nwu);
       hipLaunchKernelGGL(k_s_norm_to, dim3(upd.size()), dim3(64), 0, S->s, da, S->d_npart.as<double>(), nwu);
     }
     LM_TRY_HIP(hipEventRecord(S->t2, S->s));
-    if (!scal.empty())
-      hipLaunchKernelGGL(k_s_copy, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s, da + upd.size());
-    if (!comb.empty())
-      hipLaunchKernelGGL(k_s_lincomb, dim3(div_up(nm, 256), comb.size()), dim3(256), 0, S->s,
-                         da + upd.size() + scal.size());
+    if (!scal.empty()) {
+      if (f32)
+        hipLaunchKernelGGL(k_s_copy<float2>, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s, da + upd.size());
+      else
+        hipLaunchKernelGGL(k_s_copy<double2>, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s,
+                           da + upd.size());
+    }
+    if (!comb.empty()) {
+      if (f32)
+        hipLaunchKernelGGL(k_s_lincomb<float2>, dim3(div_up(nm, 256), comb.size()), dim3(256), 0, S->s,
+                           da + upd.size() + scal.size());
+      else
+        hipLaunchKernelGGL(k_s_lincomb<double2>, dim3(div_up(nm, 256), comb.size()), dim3(256), 0, S->s,
+                           da + upd.size() + scal.size());
+    }
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(S->s));  // d_y / descriptors are reused next round
     LM_TRY_HIP(hipEventElapsedTime(&gs_b, S->t1, S->t2));
