@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_VALU_TFLOPS = 78.6
-STAGES = ("P2M", "M2M", "M2L", "L2L", "L2P", "near", "unused")
+STAGES = ("P2M", "M2M", "M2L", "L2L", "L2P", "near", "M2L_sums")
 
 
 def _args():
@@ -201,7 +201,7 @@ def main():
     m2l_avg_s = ph["m2l_ms"] * 1e-3 / max(ph["m2l_launches"], 1)
     m2l_flops = ph["m2l_flops"] / max(ph["m2l_launches"], 1)
     m2l_roof = {"bound": "mfma", "achieved": m2l_flops / m2l_avg_s / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "traffic": None, "kernel": "k_m2l_mfma (+ k_p2m_reduce)",
+                "unit": "TFLOP/s", "traffic": None, "kernel": "k_m2l_mfma<2, 4, 0> (M2L lists)",
                 "kernel_avg_us": m2l_avg_s * 1e6, "launches": int(ph["m2l_launches"]),
                 "algorithmic_flops_per_launch": m2l_flops,
                 "entries": stats["m2l_free_entries"] + stats["m2l_reaction_entries"]}
@@ -214,7 +214,7 @@ def main():
     gs_roof["frac"] = gs_roof["achieved"] / PEAK_HBM_GBS
     tr = _traffic()
     if tr is not None:
-        m2l_roof["traffic"] = tr["k_m2l_mfma"]["hbm_bytes_per_launch"]
+        m2l_roof["traffic"] = tr["k_m2l_mfma_list"]["hbm_bytes_per_launch"]
         gs_roof["traffic"] = tr["cgs2_phase"]["hbm_bytes_per_round"]
     # the dominant single kernel of the served step is the M2L; the CGS2 phase
     # (several kernels) is reported beside it
@@ -228,7 +228,7 @@ def main():
     t_mix = geo.stage_times(x, y, reps=5, precision=lmfmm.LM_MIXED)
 
     cfg = {"workload": w.name, "N": int(N), "layers": int(len(w.k)), "k": [float(v) for v in w.k], "p": int(w.p),
-           "gmres_tol": w.tol, "gmres_restart": a.restart, "preconditioner": "overlapping DD (Sec. 4.2), subdomains one level above the FMM leaves",
+           "gmres_tol": w.tol, "gmres_restart": a.restart, "preconditioner": "overlapping DD (Sec. 4.2), default subdomain level (coarsest that fits)",
            "served": {"angles_per_step": a.angles, "requests_per_step": len(range(0, a.angles, per)),
                       "angles_per_request": per, "far_field_angles": int(obs.size),
                       "iterations_min_max": [int(min(its_s)), int(max(its_s))], "rounds": int(rounds),

@@ -134,9 +134,11 @@ lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, v
 /* Runs reps FMM matvecs (as lm_matvec) and returns in out8_host the average
  * duration in ms of each stage, measured with HIP events recorded on
  * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L (all
- * levels, free-space and reaction), [3] L2L, [4] L2P, [5] near-field matrix
- * (free-space near pairs, reaction near pairs and self terms), [6] unused
- * (0), [7] whole matvec.  Synchronises
+ * levels, free-space and reaction; the translation kernel alone), [3] L2L,
+ * [4] L2P, [5] near-field matrix (free-space near pairs, reaction near pairs
+ * and self terms), [6] the sums of the M2L partial results per target box
+ * (0 where the M2L writes its targets directly), [7] whole matvec.
+ * Synchronises
  * the stream.  LM_EINVAL for a dense geometry. */
 lm_status lm_matvec_stage_times(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, int reps,
                                 void* hip_stream, double* out8_host);

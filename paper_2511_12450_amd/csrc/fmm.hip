@@ -484,7 +484,10 @@ __host__ __device__ inline int mf_zero_tail(int P, int R) {
   return zb > za ? zb : za;
 }
 inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_zero_tail(P, R)) * sizeof(float2); }
-template <int TC, int NWB>
+// KIND only names the instantiation (MF_LIST: M2L lists, MF_TREE: M2M / L2L)
+// so that profiles tell the launches apart.
+enum { MF_LIST = 0, MF_TREE = 1 };
+template <int TC, int NWB, int KIND>
 __global__ void __launch_bounds__(64 * NWB) k_m2l_mfma(int p, int R, const int* __restrict__ items,
                                                    const int* __restrict__ src, const int* __restrict__ opi,
                                                    const float2* __restrict__ ops, const float2* __restrict__ me,
@@ -578,6 +581,7 @@ __global__ void __launch_bounds__(64 * NWB) k_m2l_mfma(int p, int R, const int* 
 }
 
 // Launch of k_m2l_mfma for R in [1, 64] and 2P <= 144 (p <= 35).
+template <int KIND>
 inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const int* src, const int* opi,
                             const float2* ops, const float2* in, float2* out, const int* dtgt, int accumulate,
                             hipStream_t s) {
@@ -585,24 +589,26 @@ inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const i
   const size_t lds = mf_lds_bytes(P, R);
   const bool wide = R > 32, tall = MT > 2 * MF_TR;
   if (!wide && !tall)
-    hipLaunchKernelGGL((k_m2l_mfma<1, 4>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in, out,
-                       dtgt, accumulate);
+    hipLaunchKernelGGL((k_m2l_mfma<1, 4, KIND>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in,
+                       out, dtgt, accumulate);
   else if (wide && !tall)
-    hipLaunchKernelGGL((k_m2l_mfma<2, 4>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in, out,
-                       dtgt, accumulate);
+    hipLaunchKernelGGL((k_m2l_mfma<2, 4, KIND>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in,
+                       out, dtgt, accumulate);
   else if (!wide)
-    hipLaunchKernelGGL((k_m2l_mfma<1, 6>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in, out,
-                       dtgt, accumulate);
+    hipLaunchKernelGGL((k_m2l_mfma<1, 6, KIND>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in,
+                       out, dtgt, accumulate);
   else
-    hipLaunchKernelGGL((k_m2l_mfma<2, 6>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in, out,
-                       dtgt, accumulate);
+    hipLaunchKernelGGL((k_m2l_mfma<2, 6, KIND>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in,
+                       out, dtgt, accumulate);
 }
 
-// LDS limit of the four k_m2l_mfma instantiations (dynamic LDS above 64 KiB
+// LDS limit of the k_m2l_mfma instantiations (dynamic LDS above 64 KiB
 // must be allowed per kernel).
 inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
-  const void* fs[4] = {(const void*)k_m2l_mfma<1, 4>, (const void*)k_m2l_mfma<2, 4>, (const void*)k_m2l_mfma<1, 6>,
-                       (const void*)k_m2l_mfma<2, 6>};
+  const void* fs[8] = {(const void*)k_m2l_mfma<1, 4, MF_LIST>, (const void*)k_m2l_mfma<2, 4, MF_LIST>,
+                       (const void*)k_m2l_mfma<1, 6, MF_LIST>, (const void*)k_m2l_mfma<2, 6, MF_LIST>,
+                       (const void*)k_m2l_mfma<1, 4, MF_TREE>, (const void*)k_m2l_mfma<2, 4, MF_TREE>,
+                       (const void*)k_m2l_mfma<1, 6, MF_TREE>, (const void*)k_m2l_mfma<2, 6, MF_TREE>};
   for (const void* f : fs) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -1720,8 +1726,9 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     if (!n) continue;
     if (tr_mfma) {
       const int i0 = F->parents_ptr[l];
-      m2l_mfma_launch(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(), F->d_tr_op.as<int>(),
-                      (const float2*)ops, (const float2*)me, (float2*)me, F->d_parents.as<int>() + i0, 0, s);
+      m2l_mfma_launch<MF_TREE>(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(),
+                               F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)me, (float2*)me,
+                               F->d_parents.as<int>() + i0, 0, s);
     } else {
       hipLaunchKernelGGL(k_m2m<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev,
                          F->d_parents.as<int>() + F->parents_ptr[l], boxes, F->d_children.as<int>(), tl, ops, me);
@@ -1737,21 +1744,34 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       V* out = (V*)F->d_m2l_out.p;
       hipLaunchKernelGGL(k_m2l_apply<RT>, dim3(F->tm_item.size() / 3), dim3(64), 0, s, p, F->d_tm_item.as<int>(),
                          F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), mops, me, out);
+      LM_STAGE(2, 0);
+      LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, p, F->d_m2l_tgt.as<int>(),
                          F->d_m2l_ptr.as<int>(), out, le);
+      LM_STAGE(6, 0);
     } else if (sizeof(RT) == 4) {
       float2* mpart = F->d_mf_part.as<float2>();
-      m2l_mfma_launch((int)(F->mf_item.size() / 3), p, R, F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(),
-                      F->d_m2l_op.as<int>(), (const float2*)mops, (const float2*)me, mpart, (const int*)nullptr, 0, s);
+      m2l_mfma_launch<MF_LIST>((int)(F->mf_item.size() / 3), p, R, F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(),
+                               F->d_m2l_op.as<int>(), (const float2*)mops, (const float2*)me, mpart,
+                               (const int*)nullptr, 0, s);
+      LM_STAGE(2, 0);
+      LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
                          F->d_mf_ptr.as<int>(), mpart, (float2*)le);
+      LM_STAGE(6, 0);
     } else {
       hipLaunchKernelGGL(k_m2l_target<RT>, dim3(F->m2l_tgt.size()), dim3(blk), lds_pr, s, p, R,
                          F->d_m2l_tgt.as<int>(), F->d_m2l_ptr.as<int>(), F->d_m2l_src.as<int>(),
                          F->d_m2l_op.as<int>(), mops, me, le);
+      LM_STAGE(2, 0);
+      LM_STAGE(6, 1);
+      LM_STAGE(6, 0);
     }
+  } else {
+    LM_STAGE(2, 0);
+    LM_STAGE(6, 1);
+    LM_STAGE(6, 0);
   }
-  LM_STAGE(2, 0);
   LM_STAGE(3, 1);
   // L2L, coarse to fine (matrix cores as for M2M: one item per child box)
   for (int l = 1; l < nlev; ++l) {
@@ -1759,8 +1779,9 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     if (!n) continue;
     if (tr_mfma) {
       const int i0 = F->l2l_item0 + F->level_ptr[l] - F->level_ptr[1];
-      m2l_mfma_launch(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(), F->d_tr_op.as<int>(),
-                      (const float2*)ops, (const float2*)le, (float2*)le, F->d_box_id.as<int>() + F->level_ptr[l], 1, s);
+      m2l_mfma_launch<MF_TREE>(n, p, R, F->d_tr_item.as<int>() + 3 * i0, F->d_tr_src.as<int>(),
+                               F->d_tr_op.as<int>(), (const float2*)ops, (const float2*)le, (float2*)le,
+                               F->d_box_id.as<int>() + F->level_ptr[l], 1, s);
     } else {
       hipLaunchKernelGGL(k_l2l<RT>, dim3(n), dim3(blk), lds_pr, s, p, R, nlev, F->level_ptr[l], boxes, tl,
                          ops + (size_t)F->n_tree_ops * PP, le);
@@ -1807,8 +1828,6 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
                        F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
   }
   LM_STAGE(5, 0);
-  LM_STAGE(6, 1);
-  LM_STAGE(6, 0);
 #undef LM_STAGE
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
