@@ -7,21 +7,19 @@
 
 // Block-sparse products with matrix cores, for several right-hand sides:
 // Y_B (rows x R) (=|+=) Z_B (rows x q) X_J (q x R) per work item of PA_ROWS
-// rows of one block (a subdomain of the preconditioner, or a leaf box with
-// its neighbours for the near field), as a real product in 16x16x4 FP32 MFMA
-// tiles (FP32 accumulation) under the interleaved real embedding: real row
-// i = 2 r + rho (real / imaginary part of output row r), real column
-// k = 2 c + kappa, A[i][k] = Re Z[r][c] if rho == kappa, Im Z[r][c] if
-// rho = 1, kappa = 0, -Im Z[r][c] if rho = 0, kappa = 1, and
-// B[k][j] = Re / Im X[c][j] for kappa = 0 / 1.  A lane's rho and kappa are
-// fixed by its position in the MFMA layout, so each fragment is one LDS load
-// (and a sign flip for A).  Z_B is row-major, complex64; the input is the
-// complex64 transpose xt [N][R] (k_to_nr), so a neighbourhood row of all
-// right-hand sides is one contiguous load; y is [R][N] in YT (complex128 or
-// complex64).  K runs over the neighbourhood in chunks of PA_KC complex
-// columns staged in LDS (Z chunk transposed to [c][r]; row strides of 80
-// complex so that the two column halves of a fragment load fall in different
-// LDS banks).  Eight wavefronts in a 4 x 2 grid hold 2 x 2 output tiles each.
+// rows of one block (a subdomain of the preconditioner, a leaf box with its
+// neighbours for the near field, a P2M or L2P point block), in 16x16x4 FP32
+// MFMA tiles (FP32 accumulation) by the three-multiplication form of the
+// complex product: T1 = Re Z Re X, T2 = Im Z Im X, T3 = (Re Z + Im Z)
+// (Re X + Im X), Y = (T1 - T2) + i (T3 - T1 - T2), three real products
+// instead of four.  A tile is 16 complex rows x 16 right-hand sides; a k-step
+// takes 4 complex columns (lane row = lane % 16, column = lane / 16), and one
+// 64-bit LDS load gives both parts of a fragment, so the third operand is
+// one add.  The input is the complex64 transpose xt [N][R] (k_to_nr), so a
+// neighbourhood row of all right-hand sides is one contiguous load; Z_B is
+// row-major complex64.  K runs over the neighbourhood in chunks of PA_KC
+// complex columns staged in LDS (Z chunk transposed to [c][r], row stride 80
+// complex).  Eight wavefronts in a 4 x 2 grid hold 1 x 2 tiles each.
 typedef float pa_v4f __attribute__((ext_vector_type(4)));
 constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80;
 // The product of one work item.  Op describes the item:
@@ -31,27 +29,22 @@ constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80;
 //   store(r, j, re, im)      writes (or adds) output row r, right-hand side j
 template <class Op>
 __device__ __forceinline__ void block_mfma_body(const Op& op, int R) {
-  constexpr int TR = 2, TC = 2;
+  constexpr int TC = 2;
   __shared__ float2 Zs[PA_KC][PA_LS];
   __shared__ float2 Xs[PA_KC][PA_LS];
   const int rows = op.rows, q = op.q;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int wr = wv >> 1, wc = wv & 1;
-  const int rho = l16 & 1, kap = kq & 1;
-  const unsigned sgn = (rho == 0 && kap == 1) ? 0x80000000u : 0u;
-  int aoff[TR], boff[TC];  // float offsets of this lane's fragments at k-step 0
+  const int rt = wv >> 1, wc = wv & 1;  // row tile, column-tile pair
+  const int aoff = kq * PA_LS + 16 * rt + l16;  // complex offsets of this lane's fragments at k-step 0
+  int boff[TC];
 #pragma unroll
-  for (int t = 0; t < TR; ++t) aoff[t] = 2 * ((kq >> 1) * PA_LS + 8 * (wr * TR + t) + (l16 >> 1)) + (rho ^ kap);
+  for (int c = 0; c < TC; ++c) boff[c] = kq * PA_LS + 16 * (wc * TC + c) + l16;
+  const float2* Zf = &Zs[0][0];
+  const float2* Xf = &Xs[0][0];
+  pa_v4f t1[TC], t2[TC], t3[TC];
 #pragma unroll
-  for (int c = 0; c < TC; ++c) boff[c] = 2 * ((kq >> 1) * PA_LS + 16 * (wc * TC + c) + l16) + kap;
-  const float* Zf = reinterpret_cast<const float*>(&Zs[0][0]);
-  const float* Xf = reinterpret_cast<const float*>(&Xs[0][0]);
-  pa_v4f acc[TR][TC];
-#pragma unroll
-  for (int t = 0; t < TR; ++t)
-#pragma unroll
-    for (int c = 0; c < TC; ++c) acc[t][c] = pa_v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < TC; ++c) t1[c] = t2[c] = t3[c] = pa_v4f{0.f, 0.f, 0.f, 0.f};
   for (int c0 = 0; c0 < q; c0 += PA_KC) {
     const int kc = min(PA_KC, q - c0);
     __syncthreads();
@@ -64,33 +57,29 @@ __device__ __forceinline__ void block_mfma_body(const Op& op, int R) {
       Xs[jj][rr] = (jj < kc && rr < R) ? op.brow(c0 + jj)[rr] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-#pragma unroll 4
-    for (int ks = 0; ks < PA_KC / 2; ++ks) {  // two complex columns per k-step
-      float av[TR], bv[TC];
+#pragma unroll 2
+    for (int ks = 0; ks < PA_KC / 4; ++ks) {
+      const float2 av = Zf[aoff + 4 * ks * PA_LS];
+      const float as = av.x + av.y;
 #pragma unroll
-      for (int t = 0; t < TR; ++t) av[t] = __uint_as_float(__float_as_uint(Zf[aoff[t] + 4 * ks * PA_LS]) ^ sgn);
-#pragma unroll
-      for (int c = 0; c < TC; ++c) bv[c] = Xf[boff[c] + 4 * ks * PA_LS];
-#pragma unroll
-      for (int t = 0; t < TR; ++t)
-#pragma unroll
-        for (int c = 0; c < TC; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[c], acc[t][c], 0, 0, 0);
+      for (int c = 0; c < TC; ++c) {
+        const float2 bv = Xf[boff[c] + 4 * ks * PA_LS];
+        t1[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, t1[c], 0, 0, 0);
+        t2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, t2[c], 0, 0, 0);
+        t3[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bv.x + bv.y, t3[c], 0, 0, 0);
+      }
     }
   }
-  // lane rows 4 kq + v of a tile are output rows 8 rt + 2 kq + v / 2, real
-  // part for even v
+  // lane rows 4 kq + v of a tile are output rows 16 rt + 4 kq + v
 #pragma unroll
-  for (int t = 0; t < TR; ++t) {
-    const int rt = wr * TR + t;
+  for (int c = 0; c < TC; ++c) {
+    const int j = 16 * (wc * TC + c) + l16;
+    if (j < R) {
 #pragma unroll
-    for (int c = 0; c < TC; ++c) {
-      const int j = 16 * (wc * TC + c) + l16;
-      if (j < R) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = 8 * rt + 2 * kq + h;
-          if (r < rows) op.store(r, j, acc[t][c][2 * h], acc[t][c][2 * h + 1]);
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + 4 * kq + v;
+        const float a = t1[c][v], b = t2[c][v];
+        if (r < rows) op.store(r, j, a - b, t3[c][v] - a - b);
       }
     }
   }

@@ -456,159 +456,141 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
 // M2M / L2L as items of one parent or child.  A work item (target, first
 // entry, end) sums Op_e a_src(e) over its entries; per entry the operator T
 // (P x P complex, [n][m] = column n of the input) and the source expansion a
-// (P x R complex, [n][j]) are copied to LDS as they lie in memory, and the
-// complex product is the real product of a 2P x 2P matrix with a 2P x R one
-// in 16x16x4 FP32 MFMA tiles (FP32 accumulation) under the interleaved real
-// embedding: real row i = 2m + rho (rho = 0 real part, 1 imaginary part of
-// output m), real column k = 2n + kappa, so
-//   A[i][k] = Re T[n][m]  if rho == kappa,   B[k][j] = Re a[n][j]  (kappa = 0)
-//             Im T[n][m]  if rho = 1, kappa = 0       Im a[n][j]  (kappa = 1)
-//            -Im T[n][m]  if rho = 0, kappa = 1.
-// Each lane's rho and kappa are fixed (row = lane % 16, k = lane / 16 in the
-// 16x16x4 layout), so a fragment is one LDS load of the right component and,
-// for A, one sign flip: no selects in the K loop.  K is padded to whole
-// unrolled steps with zero rows of a after the staged data (rows beyond P
-// read finite staged values times those zeros), and output rows beyond P are
-// clamped duplicates that are not stored.  Waves form a (MT/3) x 2 grid, each
-// holding 3 x TC output tiles.
+// (P x R complex, [n][j]) are copied to LDS as they lie in memory (flat,
+// coalesced, MF_ST loads in flight per lane), and the complex product is
+// formed in 16x16x4 FP32 MFMA tiles (FP32 accumulation) by the
+// three-multiplication form T1 = Re T Re a, T2 = Im T Im a,
+// T3 = (Re T + Im T)(Re a + Im a), T a = (T1 - T2) + i (T3 - T1 - T2): a tile
+// is 16 output coefficients x 16 right-hand sides, a k-step 4 input
+// coefficients (A[i][k] = T[n][m] with m = lane % 16, n = lane / 16), each
+// fragment one 64-bit LDS load.  K is padded to whole k-steps by zero rows
+// of a placed after the staged data (rows beyond P read finite staged values
+// times those zeros); output rows beyond P are clamped duplicates that are
+// not stored.  Each wavefront holds 3 row tiles (48 coefficients) of one
+// column tile; WC column tiles and WR row groups form the workgroup.
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int MF_ST = 8;  // staging loads in flight per lane
-constexpr int MF_UK = 3;  // k-steps per unrolled K iteration
 constexpr int MF_TR = 3;  // row tiles per wave
-__host__ __device__ inline int mf_ks(int P) { return ((P + 1) / 2 + MF_UK - 1) / MF_UK * MF_UK; }
-// float2 slots after the staged T and a that must read as zero
+__host__ __device__ inline int mf_ks(int P) { return (P + 3) / 4; }
+// complex slots after the staged T and a that must read as zero
 __host__ __device__ inline int mf_zero_tail(int P, int R) {
   const int KS = mf_ks(P), NT = (R + 15) / 16;
-  const int zb = (2 * KS - P) * R + 16 * NT;   // B rows n in [P, 2 KS) and column overrun
-  const int za = 2 * KS * P - P * P - P * R;   // A columns n in [P, 2 KS)
+  const int zb = (4 * KS - P) * R + 16 * NT;  // B rows n in [P, 4 KS) and column overrun
+  const int za = 4 * KS * P - P * P - P * R;  // A columns n in [P, 4 KS)
   return zb > za ? zb : za;
 }
 inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_zero_tail(P, R)) * sizeof(float2); }
 // KIND only names the instantiation (MF_LIST: M2L lists, MF_TREE: M2M / L2L)
 // so that profiles tell the launches apart.
 enum { MF_LIST = 0, MF_TREE = 1 };
-template <int TC, int NWB, int KIND>
-__global__ void __launch_bounds__(64 * NWB) k_m2l_mfma(int p, int R, const int* __restrict__ items,
-                                                   const int* __restrict__ src, const int* __restrict__ opi,
-                                                   const float2* __restrict__ ops, const float2* __restrict__ me,
-                                                   float2* __restrict__ part, const int* __restrict__ dtgt,
-                                                   int accumulate) {
+template <int WC, int WR, int KIND>
+__global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const int* __restrict__ items,
+                                                      const int* __restrict__ src, const int* __restrict__ opi,
+                                                      const float2* __restrict__ ops, const float2* __restrict__ me,
+                                                      float2* __restrict__ part, const int* __restrict__ dtgt,
+                                                      int accumulate) {
+  constexpr int NTH = 64 * WC * WR;
   const int P = 2 * p + 1, PP = P * P, PR = P * R, NS = PP + PR;
-  const int MT = (2 * P + 15) / 16, KS = mf_ks(P), NZ = mf_zero_tail(P, R);
+  const int MT = (P + 15) / 16, NT = (R + 15) / 16, KS = mf_ks(P), NZ = mf_zero_tail(P, R);
   extern __shared__ unsigned char dyn[];
   float2* S = reinterpret_cast<float2*>(dyn);  // T [n][m] (stride P), a [n][j] (stride R), zero tail
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int wr = wv >> 1, wc = wv & 1;
-  for (int idx = threadIdx.x; idx < NZ; idx += 64 * NWB) S[NS + idx] = make_float2(0.f, 0.f);
-  const int rho = l16 & 1, kap = kq & 1;
-  const unsigned sgn = (rho == 0 && kap == 1) ? 0x80000000u : 0u;
-  int aoff[MF_TR], boff[TC];  // float offsets of this lane's fragments at k-step 0
+  const int wr = wv / WC, ct = wv % WC;
+  for (int idx = threadIdx.x; idx < NZ; idx += NTH) S[NS + idx] = make_float2(0.f, 0.f);
+  int aoff[MF_TR];  // complex offsets of this lane's fragments at k-step 0
 #pragma unroll
-  for (int t = 0; t < MF_TR; ++t) {
-    const int m = min(8 * (wr * MF_TR + t) + (l16 >> 1), P - 1);
-    aoff[t] = 2 * ((kq >> 1) * P + m) + (rho ^ kap);
-  }
+  for (int t = 0; t < MF_TR; ++t) aoff[t] = kq * P + min(16 * (wr * MF_TR + t) + l16, P - 1);
+  const int boff = PP + kq * R + min(16 * ct + l16, 16 * NT - 1);
+  v4f t1[MF_TR], t2[MF_TR], t3[MF_TR];
 #pragma unroll
-  for (int c = 0; c < TC; ++c) {
-    const int j = min(16 * (wc * TC + c) + l16, 16 * ((R + 15) / 16) - 1);
-    boff[c] = 2 * (PP + (kq >> 1) * R + j) + kap;
-  }
-  const float* Sf = reinterpret_cast<const float*>(S);
-  v4f acc[MF_TR][TC];
-#pragma unroll
-  for (int t = 0; t < MF_TR; ++t)
-#pragma unroll
-    for (int c = 0; c < TC; ++c) acc[t][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < MF_TR; ++t) t1[t] = t2[t] = t3[t] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int e = items[3 * blockIdx.x + 1]; e < items[3 * blockIdx.x + 2]; ++e) {
     const float2* Tg = ops + (int64_t)opi[e] * PP;
     const float2* Ag = me + (int64_t)src[e] * PR;
     __syncthreads();
-    for (int base = threadIdx.x; base < NS; base += 64 * NWB * MF_ST) {
+    for (int base = threadIdx.x; base < NS; base += NTH * MF_ST) {
       float2 v[MF_ST];
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 64 * NWB * u;
+        const int idx = base + NTH * u;
         if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
       }
 #pragma unroll
       for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + 64 * NWB * u;
+        const int idx = base + NTH * u;
         if (idx < NS) S[idx] = v[u];
       }
     }
     __syncthreads();
-    for (int ks = 0; ks < KS; ks += MF_UK) {
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ++ks) {
+      const float2 bv = S[boff + 4 * ks * R];
+      const float bs = bv.x + bv.y;
 #pragma unroll
-      for (int u = 0; u < MF_UK; ++u) {
-        const int ka = 4 * (ks + u) * P, kb = 4 * (ks + u) * R;  // two complex columns per k-step
-        float av[MF_TR], bv[TC];
-#pragma unroll
-        for (int t = 0; t < MF_TR; ++t) av[t] = __uint_as_float(__float_as_uint(Sf[aoff[t] + ka]) ^ sgn);
-#pragma unroll
-        for (int c = 0; c < TC; ++c) bv[c] = Sf[boff[c] + kb];
-#pragma unroll
-        for (int t = 0; t < MF_TR; ++t)
-#pragma unroll
-          for (int c = 0; c < TC; ++c)
-            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[c], acc[t][c], 0, 0, 0);
+      for (int t = 0; t < MF_TR; ++t) {
+        const float2 av = S[aoff[t] + 4 * ks * P];
+        t1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, t1[t], 0, 0, 0);
+        t2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, t2[t], 0, 0, 0);
+        t3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bs, t3[t], 0, 0, 0);
       }
     }
   }
   // partial slot of this item, or (translations with one item per box) the
-  // output expansion itself, overwritten or accumulated; lane rows 4 kq + v of
-  // a tile are outputs m = 8 rt + 2 kq + v / 2, real part for even v
+  // output expansion itself, overwritten or accumulated; lane rows 4 kq + v
+  // of a tile are coefficients m = 16 rt + 4 kq + v
   float2* out = part + (int64_t)(dtgt ? dtgt[blockIdx.x] : (int)blockIdx.x) * PR;
+  const int j = 16 * ct + l16;
 #pragma unroll
   for (int t = 0; t < MF_TR; ++t) {
     const int rt = wr * MF_TR + t;
+    if (rt < MT && j < R) {
 #pragma unroll
-    for (int c = 0; c < TC; ++c) {
-      const int j = 16 * (wc * TC + c) + l16;
-      if (rt < MT && j < R) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int m = 8 * rt + 2 * kq + h;
-          if (m < P) {
-            float2* o = out + (int64_t)m * R + j;
-            const float2 r = make_float2(acc[t][c][2 * h], acc[t][c][2 * h + 1]);
-            *o = accumulate ? make_float2(o->x + r.x, o->y + r.y) : r;
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + 4 * kq + v;
+        if (m < P) {
+          float2* o = out + (int64_t)m * R + j;
+          const float a = t1[t][v], b = t2[t][v];
+          const float2 r = make_float2(a - b, t3[t][v] - a - b);
+          *o = accumulate ? make_float2(o->x + r.x, o->y + r.y) : r;
         }
       }
     }
   }
 }
 
-// Launch of k_m2l_mfma for R in [1, 64] and 2P <= 144 (p <= 35).
+// Launch of k_m2l_mfma for R in [1, 64] and P <= 96 (p <= 47): one wavefront
+// per column tile of 16 right-hand sides, one or two row groups of 48.
 template <int KIND>
 inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const int* src, const int* opi,
                             const float2* ops, const float2* in, float2* out, const int* dtgt, int accumulate,
                             hipStream_t s) {
-  const int P = 2 * p + 1, MT = (2 * P + 15) / 16;
+  const int P = 2 * p + 1, MT = (P + 15) / 16, NT = (R + 15) / 16;
   const size_t lds = mf_lds_bytes(P, R);
-  const bool wide = R > 32, tall = MT > 2 * MF_TR;
-  if (!wide && !tall)
-    hipLaunchKernelGGL((k_m2l_mfma<1, 4, KIND>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in,
-                       out, dtgt, accumulate);
-  else if (wide && !tall)
-    hipLaunchKernelGGL((k_m2l_mfma<2, 4, KIND>), dim3(n_items), dim3(256), lds, s, p, R, items, src, opi, ops, in,
-                       out, dtgt, accumulate);
-  else if (!wide)
-    hipLaunchKernelGGL((k_m2l_mfma<1, 6, KIND>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in,
-                       out, dtgt, accumulate);
-  else
-    hipLaunchKernelGGL((k_m2l_mfma<2, 6, KIND>), dim3(n_items), dim3(384), lds, s, p, R, items, src, opi, ops, in,
-                       out, dtgt, accumulate);
+  const bool two = MT > MF_TR;
+#define LM_MF(WC, WR)                                                                                           \
+  hipLaunchKernelGGL((k_m2l_mfma<WC, WR, KIND>), dim3(n_items), dim3(64 * (WC) * (WR)), lds, s, p, R, items, src, \
+                     opi, ops, in, out, dtgt, accumulate)
+  if (NT > 2) {
+    if (two) LM_MF(4, 2); else LM_MF(4, 1);
+  } else if (NT == 2) {
+    if (two) LM_MF(2, 2); else LM_MF(2, 1);
+  } else {
+    if (two) LM_MF(1, 2); else LM_MF(1, 1);
+  }
+#undef LM_MF
 }
 
 // LDS limit of the k_m2l_mfma instantiations (dynamic LDS above 64 KiB
 // must be allowed per kernel).
 inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
-  const void* fs[8] = {(const void*)k_m2l_mfma<1, 4, MF_LIST>, (const void*)k_m2l_mfma<2, 4, MF_LIST>,
-                       (const void*)k_m2l_mfma<1, 6, MF_LIST>, (const void*)k_m2l_mfma<2, 6, MF_LIST>,
-                       (const void*)k_m2l_mfma<1, 4, MF_TREE>, (const void*)k_m2l_mfma<2, 4, MF_TREE>,
-                       (const void*)k_m2l_mfma<1, 6, MF_TREE>, (const void*)k_m2l_mfma<2, 6, MF_TREE>};
+  const void* fs[12] = {
+      (const void*)k_m2l_mfma<4, 1, MF_LIST>, (const void*)k_m2l_mfma<4, 2, MF_LIST>,
+      (const void*)k_m2l_mfma<2, 1, MF_LIST>, (const void*)k_m2l_mfma<2, 2, MF_LIST>,
+      (const void*)k_m2l_mfma<1, 1, MF_LIST>, (const void*)k_m2l_mfma<1, 2, MF_LIST>,
+      (const void*)k_m2l_mfma<4, 1, MF_TREE>, (const void*)k_m2l_mfma<4, 2, MF_TREE>,
+      (const void*)k_m2l_mfma<2, 1, MF_TREE>, (const void*)k_m2l_mfma<2, 2, MF_TREE>,
+      (const void*)k_m2l_mfma<1, 1, MF_TREE>, (const void*)k_m2l_mfma<1, 2, MF_TREE>};
   for (const void* f : fs) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
