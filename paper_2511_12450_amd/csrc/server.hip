@@ -71,6 +71,7 @@ struct ColDev {
   double scale;
   int N, cnt;
   int vj;             // gather: basis vector to normalise, or -1 (gather w)
+  int ld;             // basis stride (elements; a multiple of 64, so pairs are 16-byte aligned)
 };
 
 __device__ __forceinline__ double2 bld(const double2* p) { return *p; }
@@ -82,6 +83,23 @@ __device__ __forceinline__ double2 bcv(double2 v) { return v; }
 __device__ __forceinline__ double2 bcv(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ __forceinline__ void bst(double2* p, double2 v) { *p = v; }
 __device__ __forceinline__ void bst(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+// two consecutive basis elements from an even position (one 16-byte load for complex64)
+__device__ __forceinline__ void bld2(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ __forceinline__ void bld2(const float2* p, double2& a, double2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_double2((double)v.x, (double)v.y);
+  b = make_double2((double)v.z, (double)v.w);
+}
+__device__ __forceinline__ void bst2(double2* p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
+}
+__device__ __forceinline__ void bst2(float2* p, double2 a, double2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+}
 
 // V[0] = src * scale      (grid (ceil(Nmax / 256), ncols))
 template <typename BT>
@@ -142,7 +160,7 @@ __global__ void __launch_bounds__(256) k_s_lincomb(const ColDev* __restrict__ d)
   const BT* V = (const BT*)c.V;
   double2 acc = c.z[n];
   for (int i = 0; i < c.cnt; ++i) {
-    const double2 a = c.y[i], v = bld(V + (int64_t)i * c.N + n);
+    const double2 a = c.y[i], v = bld(V + (int64_t)i * c.ld + n);
     acc.x = fma(a.x, v.x, acc.x);
     acc.x = fma(-a.y, v.y, acc.x);
     acc.y = fma(a.x, v.y, acc.y);
@@ -161,7 +179,7 @@ __global__ void __launch_bounds__(256) k_s_gather(const ColDev* __restrict__ d) 
   if (n >= c.N) return;
   double2 v;
   if (c.vj >= 0) {
-    BT* vp = (BT*)c.V + (int64_t)c.vj * c.N + n;
+    BT* vp = (BT*)c.V + (int64_t)c.vj * c.ld + n;
     const double s = c.nsrc ? 1.0 / sqrt(*c.nsrc) : c.scale;
     v = bld(vp);
     v = make_double2(v.x * s, v.y * s);
@@ -175,6 +193,7 @@ __global__ void __launch_bounds__(256) k_s_gather(const ColDev* __restrict__ d) 
 
 // Workgroup partials of conj(V[i]) . u and conj(V[i]) . z, u = V[cnt-1],
 // z = the K M output (or none), for the basis vectors of this workgroup.
+// Each thread takes EPT / 2 pairs of consecutive elements of a SD_SLICE slice.
 template <typename BT>
 __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, double2* __restrict__ pa,
                                                  double2* __restrict__ pb, int ldh, int nb) {
@@ -182,21 +201,24 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
   const int ib = blockIdx.z * SD_IBLK;
   if (ib >= c.cnt || blockIdx.x * SD_SLICE >= c.N) return;  // uniform per workgroup
   const int ie = min(c.cnt, ib + SD_IBLK);
-  constexpr int EPT = SD_SLICE / 256;
+  constexpr int EP = SD_SLICE / 512;  // pairs per thread
   const BT* V = (const BT*)c.V;
-  const BT* u = V + (int64_t)(c.cnt - 1) * c.N;
-  BT xb[EPT];  // u in the basis type
-  double2 xz[EPT];
-  int idx[EPT];
-  bool ok[EPT];
+  const BT* u = V + (int64_t)(c.cnt - 1) * c.ld;
+  double2 xu[2 * EP], xz[2 * EP];
+  int idx[EP];
+  bool ok[2 * EP];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int n = blockIdx.x * SD_SLICE + threadIdx.x + 256 * e;
-    ok[e] = n < c.N;
-    idx[e] = ok[e] ? n : 0;
-    xb[e] = u[idx[e]];
-    if (!ok[e]) xb[e].x = xb[e].y = 0;
-    xz[e] = (ok[e] && c.w) ? c.w[idx[e]] : make_double2(0.0, 0.0);
+  for (int e = 0; e < EP; ++e) {
+    const int n = blockIdx.x * SD_SLICE + 2 * (threadIdx.x + 256 * e);
+    ok[2 * e] = n < c.N;
+    ok[2 * e + 1] = n + 1 < c.N;
+    idx[e] = ok[2 * e] ? n : 0;
+    bld2(u + idx[e], xu[2 * e], xu[2 * e + 1]);
+    xz[2 * e] = (ok[2 * e] && c.w) ? c.w[idx[e]] : make_double2(0.0, 0.0);
+    xz[2 * e + 1] = (ok[2 * e + 1] && c.w) ? c.w[idx[e] + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (!ok[2 * e + h]) xu[2 * e + h] = make_double2(0.0, 0.0);
   }
   // two basis vectors per iteration; the eight sums (re / im of V^H u and
   // V^H z for each) are reduced over the wavefront by a transposing
@@ -208,28 +230,28 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
 #pragma unroll 1
   for (int i = ib; i < ie; i += 2) {
     const bool two = i + 1 < ie;
-    const BT* v0 = V + (int64_t)i * c.N;
-    const BT* v1 = V + (int64_t)(two ? i + 1 : i) * c.N;
-    BT b0[EPT], b1[EPT];  // raw loads (converted at use: fewer registers in flight)
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      b0[e] = v0[idx[e]];
-      b1[e] = v1[idx[e]];
-    }
+    const BT* v0 = V + (int64_t)i * c.ld;
+    const BT* v1 = V + (int64_t)(two ? i + 1 : i) * c.ld;
     double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const double2 a0 = ok[e] ? bcv(b0[e]) : make_double2(0.0, 0.0);
-      const double2 a1 = (ok[e] && two) ? bcv(b1[e]) : make_double2(0.0, 0.0);
-      const double2 xu = bcv(xb[e]);
-      t[0] = fma(a0.x, xu.x, fma(a0.y, xu.y, t[0]));
-      t[1] = fma(a0.x, xu.y, fma(-a0.y, xu.x, t[1]));
-      t[2] = fma(a0.x, xz[e].x, fma(a0.y, xz[e].y, t[2]));
-      t[3] = fma(a0.x, xz[e].y, fma(-a0.y, xz[e].x, t[3]));
-      t[4] = fma(a1.x, xu.x, fma(a1.y, xu.y, t[4]));
-      t[5] = fma(a1.x, xu.y, fma(-a1.y, xu.x, t[5]));
-      t[6] = fma(a1.x, xz[e].x, fma(a1.y, xz[e].y, t[6]));
-      t[7] = fma(a1.x, xz[e].y, fma(-a1.y, xz[e].x, t[7]));
+    for (int e = 0; e < EP; ++e) {
+      double2 a0[2], a1[2];
+      bld2(v0 + idx[e], a0[0], a0[1]);
+      bld2(v1 + idx[e], a1[0], a1[1]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * e + h;
+        const double2 p0 = ok[k] ? a0[h] : make_double2(0.0, 0.0);
+        const double2 p1 = (ok[k] && two) ? a1[h] : make_double2(0.0, 0.0);
+        t[0] = fma(p0.x, xu[k].x, fma(p0.y, xu[k].y, t[0]));
+        t[1] = fma(p0.x, xu[k].y, fma(-p0.y, xu[k].x, t[1]));
+        t[2] = fma(p0.x, xz[k].x, fma(p0.y, xz[k].y, t[2]));
+        t[3] = fma(p0.x, xz[k].y, fma(-p0.y, xz[k].x, t[3]));
+        t[4] = fma(p1.x, xu[k].x, fma(p1.y, xu[k].y, t[4]));
+        t[5] = fma(p1.x, xu[k].y, fma(-p1.y, xu[k].x, t[5]));
+        t[6] = fma(p1.x, xz[k].x, fma(p1.y, xz[k].y, t[6]));
+        t[7] = fma(p1.x, xz[k].y, fma(-p1.y, xz[k].x, t[7]));
+      }
     }
     // 8 -> 4 -> 2 -> 1 values per lane (lanes with the step's bit set keep the upper half)
 #pragma unroll
@@ -288,55 +310,72 @@ __global__ void __launch_bounds__(64) k_s_dots2_final(const ColDev* __restrict__
 //   V[j]   <- (u - sum_i a_i V[i]) * scale                (re-orthogonalised v_j)
 //   V[j+1] <- z * scale - u * dr - sum_i e_i V[i]          (once-projected next vector)
 // with u = V[j], z = the K M output, a = y[0..j), e = y[j..2j); wave
-// partials of |V[j+1]|^2 into part.
+// partials of |V[j+1]|^2 into part.  Each thread takes two consecutive
+// elements (SU_ELEM per workgroup); the element past N of an odd N is basis
+// padding and is left out of the norm.
+constexpr int SU_ELEM = 512;
 template <typename BT>
 __global__ void __launch_bounds__(256) k_s_update2(const ColDev* __restrict__ d, double* __restrict__ part, int nw) {
   const ColDev c = d[blockIdx.y];
-  if (blockIdx.x * 256 >= c.N) return;
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  const bool ok = n < c.N;
-  const int o = ok ? n : 0;
+  if (blockIdx.x * SU_ELEM >= c.N) return;
+  const int n = 2 * (blockIdx.x * 256 + threadIdx.x);
+  const bool ok0 = n < c.N, ok1 = n + 1 < c.N;
+  const int o = ok0 ? n : 0;
   const int j = c.cnt;
   BT* V = (BT*)c.V;
-  BT* uj = V + (int64_t)j * c.N;
-  const double2 u = bld(uj + o);
-  double2 q = u;
-  const double2 zv = c.w[o];
-  double2 w = make_double2(zv.x * c.scale - (u.x * c.dr.x - u.y * c.dr.y),
-                           zv.y * c.scale - (u.x * c.dr.y + u.y * c.dr.x));
-  constexpr int U = 8;
-  for (int i0 = 0; i0 < j; i0 += U) {
-    double2 v[U];
+  BT* uj = V + (int64_t)j * c.ld;
+  double2 u[2], q[2], w[2];
+  bld2(uj + o, u[0], u[1]);
+  const double2 zv[2] = {c.w[o], ok1 ? c.w[o + 1] : make_double2(0.0, 0.0)};
 #pragma unroll
-    for (int k = 0; k < U; ++k) v[k] = (i0 + k < j) ? bld(V + (int64_t)(i0 + k) * c.N + o) : make_double2(0.0, 0.0);
+  for (int h = 0; h < 2; ++h) {
+    q[h] = u[h];
+    w[h] = make_double2(zv[h].x * c.scale - (u[h].x * c.dr.x - u[h].y * c.dr.y),
+                        zv[h].y * c.scale - (u[h].x * c.dr.y + u[h].y * c.dr.x));
+  }
+  constexpr int U = 4;
+  for (int i0 = 0; i0 < j; i0 += U) {
+    double2 v[U][2];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (i0 + k < j) {
+        bld2(V + (int64_t)(i0 + k) * c.ld + o, v[k][0], v[k][1]);
+      } else {
+        v[k][0] = v[k][1] = make_double2(0.0, 0.0);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       if (i0 + k < j) {
         const double2 a = c.y[i0 + k], e = c.y[j + i0 + k];
-        q.x = fma(-a.x, v[k].x, q.x);
-        q.x = fma(a.y, v[k].y, q.x);
-        q.y = fma(-a.x, v[k].y, q.y);
-        q.y = fma(-a.y, v[k].x, q.y);
-        w.x = fma(-e.x, v[k].x, w.x);
-        w.x = fma(e.y, v[k].y, w.x);
-        w.y = fma(-e.x, v[k].y, w.y);
-        w.y = fma(-e.y, v[k].x, w.y);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          q[h].x = fma(-a.x, v[k][h].x, q[h].x);
+          q[h].x = fma(a.y, v[k][h].y, q[h].x);
+          q[h].y = fma(-a.x, v[k][h].y, q[h].y);
+          q[h].y = fma(-a.y, v[k][h].x, q[h].y);
+          w[h].x = fma(-e.x, v[k][h].x, w[h].x);
+          w[h].x = fma(e.y, v[k][h].y, w[h].x);
+          w[h].y = fma(-e.x, v[k][h].y, w[h].y);
+          w[h].y = fma(-e.y, v[k][h].x, w[h].y);
+        }
       }
     }
   }
-  if (ok) {
-    bst(uj + o, make_double2(q.x * c.scale, q.y * c.scale));
-    bst(uj + c.N + o, w);
+  if (ok0) {
+    bst2(uj + o, make_double2(q[0].x * c.scale, q[0].y * c.scale), make_double2(q[1].x * c.scale, q[1].y * c.scale));
+    bst2(uj + c.ld + o, w[0], w[1]);
   }
-  const double qn = s_wave_sum(ok ? w.x * w.x + w.y * w.y : 0.0);
+  const double qn = s_wave_sum((ok0 ? w[0].x * w[0].x + w[0].y * w[0].y : 0.0) +
+                               (ok1 ? w[1].x * w[1].x + w[1].y * w[1].y : 0.0));
   if ((threadIdx.x & 63) == 0) part[(int64_t)blockIdx.y * nw + blockIdx.x * 4 + (threadIdx.x >> 6)] = qn;
 }
 
-// *ndst = sum of the column's wave partials.
+// *ndst = sum of the column's wave partials (4 per SU_ELEM elements).
 __global__ void __launch_bounds__(64) k_s_norm_to(const ColDev* __restrict__ d, const double* __restrict__ part,
                                                   int nw) {
   const ColDev c = d[blockIdx.x];
-  const int nwc = 4 * ((c.N + 255) / 256);
+  const int nwc = 4 * ((c.N + SU_ELEM - 1) / SU_ELEM);
   double q = 0.0;
   for (int k = threadIdx.x; k < nwc; k += 64) q += part[(int64_t)blockIdx.x * nw + k];
   q = s_wave_sum(q);
@@ -352,6 +391,7 @@ struct Column {
   int col = 0;
   lm_geom_s* g = nullptr;
   int N = 0, m = 0;
+  int ldv = 0;  // basis stride: N rounded up to a multiple of 64
   Phase phase = PH_INIT;
   DevBuf V, z, gv, y, dn;  // dn: squared norm of the once-projected next vector
   int j = 0, its = 0, ncols = 0;
@@ -425,7 +465,8 @@ namespace {
 int64_t footprint(const lm_geom_s* g, const lm_gmres_opts& o, int R) {
   const int64_t N = g->N;
   const int m = std::max(1, std::min(o.restart, o.max_iter));
-  const int64_t per = (int64_t)(m + 1 + 2 + 3) * N * 16 + (int64_t)(m + 1) * 16 + 2 * N * 8 +
+  const int64_t ld = (N + 63) / 64 * 64;  // basis stride
+  const int64_t per = (int64_t)(m + 1) * ld * 16 + (int64_t)(2 + 3) * N * 16 + (int64_t)(m + 1) * 16 + 2 * N * 8 +
                       (g->fmm ? fmm_ws_per_rhs(g->fmm) : 0);
   return per * R;
 }
@@ -470,7 +511,8 @@ lm_status start_request(lm_server_s* S, Request* q) {
     col->g = q->g;
     col->N = N;
     col->m = m;
-    LM_TRY(col->V.alloc((size_t)(m + 1) * N * basis_bytes(S)));
+    col->ldv = (N + 63) / 64 * 64;
+    LM_TRY(col->V.alloc((size_t)(m + 1) * col->ldv * basis_bytes(S)));
     LM_TRY(col->z.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->gv.alloc((size_t)N * sizeof(double2)));
     LM_TRY(col->y.alloc((size_t)(m + 1) * sizeof(double2)));
@@ -492,8 +534,8 @@ lm_status start_request(lm_server_s* S, Request* q) {
 
 // phi = M z, far fields and copies to host memory for the columns that
 // finished this round; marks them finished.  Columns on one geometry share
-// one preconditioner launch (several right-hand sides), columns of one
-// request one far-field launch.  Returns the first failure; the columns of a
+// one preconditioner launch (several right-hand sides), columns of requests
+// with the same observation angles one far-field launch.  Returns the first failure; the columns of a
 // failed group are reported through *failed.
 lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<Request*>* failed) {
   std::stable_sort(fin.begin(), fin.end(), [](const Column* a, const Column* b) {
@@ -525,17 +567,17 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
         LM_TRY_HIP(hipMemcpyAsync(c->req->phi.data() + (size_t)c->col * N, pb + i * vb, vb, hipMemcpyDeviceToHost,
                                   S->s));
       }
-      for (int a = 0; a < k;) {  // one far-field launch per request
-        Request* q = fin[i0 + a]->req;
+      for (int a = 0; a < k;) {  // one far-field launch per run of requests with the same angles
+        const std::vector<double>& obs = fin[i0 + a]->req->obs;
         int b = a;
-        while (b < k && fin[i0 + b]->req == q) ++b;
-        const int no = (int)q->obs.size();
+        while (b < k && fin[i0 + b]->req->obs == obs) ++b;
+        const int no = (int)obs.size();
         if (no) {
           const size_t fb = (size_t)(b - a) * no * sizeof(double2);
           if (S->d_fff.bytes < fb) LM_TRY(S->d_fff.alloc(fb));
-          LM_TRY(farfield_launch(g, b - a, pb + a * vb, no, q->obs.data(), S->d_fff.p, S->s));
+          LM_TRY(farfield_launch(g, b - a, pb + a * vb, no, obs.data(), S->d_fff.p, S->s));
           for (int i = a; i < b; ++i)
-            LM_TRY_HIP(hipMemcpyAsync(q->ff.data() + (size_t)fin[i0 + i]->col * no,
+            LM_TRY_HIP(hipMemcpyAsync(fin[i0 + i]->req->ff.data() + (size_t)fin[i0 + i]->col * no,
                                       (const double2*)S->d_fff.p + (size_t)(i - a) * no, (size_t)no * sizeof(double2),
                                       hipMemcpyDeviceToHost, S->s));
         }
@@ -606,6 +648,7 @@ lm_status round(lm_server_s* S) {
       d.scale = 1.0;
       if (c->phase == PH_ARNOLDI) {
         d.V = c->V.p;
+        d.ld = c->ldv;
         d.vj = c->j;
         d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;
       } else {
@@ -621,6 +664,7 @@ lm_status round(lm_server_s* S) {
       ColDev d{};
       d.N = c->N;
       d.V = c->V.p;
+      d.ld = c->ldv;
       d.vj = c->j;
       d.nsrc = c->dn.as<double>();
       gath.push_back(d);
@@ -682,6 +726,7 @@ lm_status round(lm_server_s* S) {
     Column* c = cols[i];
     ColDev& d = S->hdesc[i];
     d.V = c->V.p;
+    d.ld = c->ldv;
     d.N = c->N;
     if (c->phase == PH_ARNOLDI) {
       d.cnt = c->j + 1;  // dots against V[0..j]; u = V[j]
@@ -743,6 +788,7 @@ lm_status round(lm_server_s* S) {
       ColDev d{};
       d.src = r;
       d.V = c->V.p;
+      d.ld = c->ldv;
       d.scale = 1.0 / beta;
       d.N = N;
       scal.push_back(d);
@@ -757,6 +803,7 @@ lm_status round(lm_server_s* S) {
       }
       ColDev d{};
       d.V = c->V.p;
+      d.ld = c->ldv;
       d.z = c->z.as<double2>();
       d.N = N;
       d.cnt = cnt;
@@ -863,6 +910,7 @@ lm_status round(lm_server_s* S) {
     const C dd2 = hj / rho + cj;
     ColDev d{};
     d.V = c->V.p;
+    d.ld = c->ldv;
     d.w = c->w;
     d.N = N;
     d.cnt = j;
@@ -909,10 +957,10 @@ lm_status round(lm_server_s* S) {
     LM_TRY_HIP(hipEventRecord(S->t1, S->s));
     if (!upd.empty()) {
       if (f32)
-        hipLaunchKernelGGL(k_s_update2<float2>, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
+        hipLaunchKernelGGL(k_s_update2<float2>, dim3(div_up(nm, SU_ELEM), upd.size()), dim3(256), 0, S->s, da,
                            S->d_npart.as<double>(), nwu);
       else
-        hipLaunchKernelGGL(k_s_update2<double2>, dim3(div_up(nm, 256), upd.size()), dim3(256), 0, S->s, da,
+        hipLaunchKernelGGL(k_s_update2<double2>, dim3(div_up(nm, SU_ELEM), upd.size()), dim3(256), 0, S->s, da,
                            S->d_npart.as<double>(), nwu);
       hipLaunchKernelGGL(k_s_norm_to, dim3(upd.size()), dim3(64), 0, S->s, da, S->d_npart.as<double>(), nwu);
     }
