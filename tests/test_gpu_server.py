@@ -200,3 +200,61 @@ def test_not_converged_reported(geoms):
         assert np.all(np.isfinite(phi))
     finally:
         srv.close()
+
+
+def test_batched_finish_matches_direct_solves(geoms):
+    """Columns finishing in the same round share one preconditioner launch;
+    requests with the same observation angles share one far-field launch."""
+    mini, g_mini, small, g_small = geoms
+    obs2 = lmfmm.far_field_angles()[5::23]
+    thA, thB, thC = np.radians([35.0, 65.0]), np.radians([95.0, 125.0]), np.radians([150.0])
+    ref = {}
+    for th in np.concatenate([thA, thB, thC]):
+        phi, rep, st = g_mini.solve(np.array([th]), tol=1e-10, max_iter=800, restart=400, precond=1)
+        assert st == lmfmm.LM_OK
+        ref[float(th)] = phi
+    for prec, tol, bar in ((lmfmm.LM_FP64, 1e-9, 1e-6), (lmfmm.LM_MIXED, 1e-6, 1e-4)):
+        srv = lmfmm.Server(precision=prec)
+        try:
+            ids = [srv.submit(g_mini, thA, tol=tol, max_iter=800, restart=400, obs_rad=OBS),
+                   srv.submit(g_mini, thB, tol=tol, max_iter=800, restart=400, obs_rad=OBS),
+                   srv.submit(g_mini, thC, tol=tol, max_iter=800, restart=400, obs_rad=obs2)]
+            for rid, th, ob in zip(ids, (thA, thB, thC), (OBS, OBS, obs2)):
+                st, status, lat, rep, phi, ff = srv.wait(rid)
+                assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK, (prec, st, status)
+                for r, t in enumerate(th):
+                    want = g_mini.far_field(ref[float(t)], ob).cpu().numpy()[0]
+                    err = _rel(ff[r], want)
+                    print(f"precision {prec} angle {np.degrees(t):.0f}: its {rep[r][0]}, far field vs direct {err:.2e}",
+                          flush=True)
+                    assert err < bar
+            print("rounds", srv.stats()["rounds"], flush=True)
+        finally:
+            srv.close()
+
+
+def test_odd_n_basis_padding():
+    """N odd: the last element pair of every basis vector ends in padding."""
+    w0 = wl.plain_small()
+    polys = [wl.circle((float(p[:, 0].mean()), float(p[:, 1].mean())), 0.3, n)
+             for p, n in zip(w0.polygons, (63, 64, 64, 64))]
+    w = wl.Workload("odd_N255", w0.d, w0.k, w0.eta, polys, np.array([40.0]))
+    assert w.n_elements % 2 == 1
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_DENSE)
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    th = np.radians([40.0, 140.0])
+    K = matrix(med, el)
+    for prec, tol, bar in ((lmfmm.LM_FP64, 1e-10, 1e-6), (lmfmm.LM_MIXED, 1e-6, 1e-4)):
+        srv = lmfmm.Server(precision=prec)
+        try:
+            rid = srv.submit(geo, th, tol=tol, max_iter=300, restart=300, precond=0, obs_rad=OBS)
+            st, status, lat, rep, phi, ff = srv.wait(rid)
+            assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK
+            for r, t in enumerate(th):
+                want = far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), OBS)
+                err = _rel(ff[r], want)
+                print(f"N={el.n} precision {prec}: far field vs oracle {err:.2e}", flush=True)
+                assert err < bar
+        finally:
+            srv.close()
