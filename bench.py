@@ -50,6 +50,10 @@ def _args():
     ap.add_argument("--plain-solves", type=int, default=4)
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stream-requests", type=int, default=550,
+                    help="requests of the open-loop Poisson stream (0: skip); the first 50 are warm-up")
+    ap.add_argument("--stream-rho", type=float, default=0.5, help="arrival rate as a fraction of the served capacity")
+    ap.add_argument("--stream-max-angles", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -195,6 +199,51 @@ def main():
     n_served = a.steps * a.angles
     _log(f"served FP32: {n_served} solves in {served_s:.2f} s")
 
+    # ---- served FP32 form under an open-loop stream: Poisson arrivals at
+    # rho x the capacity just measured, 1..max angles per request drawn from the
+    # batch's angle grid; latency per request from submit to done
+    stream = None
+    if a.stream_requests > 0:
+        rng = np.random.default_rng(7)
+        cap = n_served / served_s
+        n_ang = rng.integers(1, a.stream_max_angles + 1, size=a.stream_requests)
+        rate = a.stream_rho * cap / float(np.mean(n_ang))  # requests per second
+        t_arr = np.cumsum(rng.exponential(1.0 / rate, size=a.stream_requests))
+        picks = [np.sort(rng.choice(a.angles, size=int(k), replace=False)) for k in n_ang]
+        srv2 = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
+        pend, lat_q, err_q, its_q = {}, {}, [], []
+        i, t0s = 0, time.perf_counter()
+        while i < len(t_arr) or pend:
+            now = time.perf_counter() - t0s
+            while i < len(t_arr) and t_arr[i] <= now:
+                pend[srv2.submit(geo, th_all[picks[i]], obs_rad=obs, **gm)] = i
+                i += 1
+            for rid in list(pend):
+                out_q = srv2.poll(rid, results=True)
+                if out_q[0] in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
+                    assert out_q[0] == lmfmm.LM_DONE, out_q[:2]
+                    k = pend.pop(rid)
+                    lat_q[k] = out_q[2]
+                    its_q += [r_[0] for r_ in out_q[3]]
+                    for r_, ai in enumerate(picks[k]):
+                        if ai in ref_idx:
+                            err_q.append(_rel(out_q[5][r_], fref[ref_idx.index(ai)]))
+                    srv2.release(rid)
+            time.sleep(0.0005)
+        span = time.perf_counter() - t0s
+        srv2.close()
+        keep = [lat_q[k] for k in range(50, a.stream_requests)] if a.stream_requests > 100 else list(lat_q.values())
+        stream = {"requests": a.stream_requests, "warmup_requests_excluded": 50 if a.stream_requests > 100 else 0,
+                  "rho": a.stream_rho, "arrival_rate_solves_s": float(rate * np.mean(n_ang)),
+                  "angles_per_request": [1, a.stream_max_angles], "solves": int(np.sum(n_ang)),
+                  "solves_per_s": float(np.sum(n_ang) / span),
+                  "p50_s": float(np.percentile(keep, 50)), "p99_s": float(np.percentile(keep, 99)),
+                  "iterations_min_max": [int(min(its_q)), int(max(its_q))],
+                  "rel_err_far_field_max": float(max(err_q)) if err_q else None,
+                  "checked_solves": len(err_q)}
+        _log(f"stream: {a.stream_requests} requests in {span:.1f} s, p50 {stream['p50_s']:.3f} s, "
+             f"p99 {stream['p99_s']:.3f} s")
+
     # ---- kernel rooflines (HIP events on the launch stream, inside the timed batch)
     stats = geo.fmm_stats()
     rounds = st1["rounds"] - st0["rounds"]
@@ -248,9 +297,14 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": 1e3 * served_s / a.steps,
-        "p50_s": float(np.percentile(lat_s, 50)),
-        "p99_s": float(np.percentile(lat_s, 99)),
-        "rel_err_far_field_max": float(max(err_s)),
+        # per-request latency over the open-loop stream (requests 50.. of 550),
+        # else over the timed batch
+        "p50_s": stream["p50_s"] if stream else float(np.percentile(lat_s, 50)),
+        "p99_s": stream["p99_s"] if stream else float(np.percentile(lat_s, 99)),
+        "batch_p50_s": float(np.percentile(lat_s, 50)),
+        "batch_p99_s": float(np.percentile(lat_s, 99)),
+        "rel_err_far_field_max": float(max(err_s + (stream["rel_err_far_field_max"] and [stream["rel_err_far_field_max"]] or []))) if stream else float(max(err_s)),
+        "stream": stream,
         "plain_fp64": {"value": a.plain_solves / plain_s, "unit": "solves/s", "solves": a.plain_solves,
                        "p50_s": float(np.percentile(lat_p, 50)), "p99_s": float(np.percentile(lat_p, 99)),
                        "iterations": [int(v) for v in its_p], "rel_err_far_field_max": float(max(err_p))},
