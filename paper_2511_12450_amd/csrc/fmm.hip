@@ -858,10 +858,11 @@ __global__ void __launch_bounds__(64 * PA_NW) k_l2p_mfma(int p, int R, int N, in
   block_mfma_body(op, R);
 }
 
-// y_i += sum_j Knear_ij x_j for every right-hand side: one wavefront per row;
-// right-hand sides in groups of G share each matrix value and index load.
+// y_i (+)= sum_j Knear_ij x_j for every right-hand side (acc: add, else
+// overwrite): one wavefront per row; right-hand sides in groups of G share
+// each matrix value and index load.
 template <typename RT, int G>
-__global__ void __launch_bounds__(256) k_near_csr(int N, int nrow, const int* __restrict__ rows, int R,
+__global__ void __launch_bounds__(256) k_near_csr(int N, int nrow, const int* __restrict__ rows, int R, int acc,
                                                   const int* __restrict__ ptr, const int* __restrict__ src,
                                                   const typename C2T<RT>::T* __restrict__ val,
                                                   const typename C2T<RT>::T* __restrict__ x,
@@ -895,8 +896,12 @@ __global__ void __launch_bounds__(256) k_near_csr(int N, int nrow, const int* __
       for (int u = 0; u < G; ++u) {
         if (g + u < R) {
           V* yp = y + (int64_t)(g + u) * N + row;
-          const V o = *yp;
-          *yp = mk<V>(o.x + re[u], o.y + im[u]);
+          if (acc) {
+            const V o = *yp;
+            *yp = mk<V>(o.x + re[u], o.y + im[u]);
+          } else {
+            *yp = mk<V>(re[u], im[u]);
+          }
         }
       }
     }
@@ -931,6 +936,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   FmmPlan* F = new (std::nothrow) FmmPlan();
   LM_CHECK(F, LM_ENOMEM, "host allocation failed");
   g->fmm = F;
+  LM_TRY_HIP(hipStreamCreateWithFlags(&F->s_near, hipStreamNonBlocking));
+  LM_TRY_HIP(hipEventCreateWithFlags(&F->ev_fork, hipEventDisableTiming));
+  LM_TRY_HIP(hipEventCreateWithFlags(&F->ev_join, hipEventDisableTiming));
   const MediumDev& m = g->m;
   const int L = m.L;
   const int64_t N = g->N;
@@ -1683,6 +1691,39 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   if (pt_mfma)  // complex64 transpose of x, shared by the P2M and the near field
     hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
                        (const float2*)x, F->d_xt.as<float2>());
+  // The near field and self terms only need x: they run on the plan's side
+  // stream, overlapped with P2M .. L2L, and write y first; every L2P launch
+  // then accumulates after the join.
+  LM_TRY_HIP(hipEventRecord(F->ev_fork, s));
+  LM_TRY_HIP(hipStreamWaitEvent(F->s_near, F->ev_fork, 0));
+  {
+    hipStream_t sn = F->s_near;
+    if (ev) LM_TRY_HIP(hipEventRecord(ev[10], sn));
+    if (pt_mfma) {
+      // FP32, several right-hand sides: free-space near field + self terms as
+      // leaf blocks on matrix cores (every element is a row of one leaf
+      // block), then the few reaction near pairs
+      if (F->nb_item.empty())
+        LM_TRY_HIP(hipMemsetAsync(y, 0, (size_t)R * N * sizeof(float2), sn));
+      else
+        hipLaunchKernelGGL((k_block_mfma<float2, false>), dim3(F->nb_item.size() / 2), dim3(64 * PA_NW), 0, sn, N,
+                           R, F->d_nb_item.as<int>(), F->d_nb_jptr.as<int>(), F->d_nb_jidx.as<int>(),
+                           F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(), F->d_nb_Z32.as<float2>(),
+                           F->d_xt.as<float2>(), (float2*)y);
+      if (!F->rn_src.empty())
+        hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(F->rn_rows.size(), 4)), dim3(256), 0, sn, N,
+                           (int)F->rn_rows.size(), F->d_rn_rows.as<int>(), R, 1, F->d_rn_ptr.as<int>(),
+                           F->d_rn_src.as<int>(), F->d_rn_val32.as<float2>(), (const float2*)x, (float2*)y);
+    } else if (R >= 8) {  // CSR with the self term in every row
+      hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, sn, N, N, (const int*)nullptr, R, 0,
+                         F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
+    } else {
+      hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, sn, N, N, (const int*)nullptr, R, 0,
+                         F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
+    }
+    if (ev) LM_TRY_HIP(hipEventRecord(ev[11], sn));
+    LM_TRY_HIP(hipEventRecord(F->ev_join, sn));
+  }
   if (n_items) {
     if (pt_mfma)
       hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
@@ -1770,46 +1811,24 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     }
   }
   LM_STAGE(3, 0);
+  LM_TRY_HIP(hipStreamWaitEvent(s, F->ev_join, 0));  // y holds the near field
   LM_STAGE(4, 1);
-  // L2P: free trees write, side trees accumulate (each element once per launch)
+  // L2P: every tree class accumulates (each element once per launch)
   for (int c = 0; c < 3; ++c) {
     const int i0 = F->item_ptr[c], ni = F->item_ptr[c + 1] - i0;
     if (!ni) continue;
     const int* it = F->d_pt_item.as<int>() + 3 * i0;
     if (pt_mfma)
-      hipLaunchKernelGGL(k_l2p_mfma, dim3(ni), dim3(64 * PA_NW), 0, s, p, R, N, c > 0 ? 1 : 0, it,
+      hipLaunchKernelGGL(k_l2p_mfma, dim3(ni), dim3(64 * PA_NW), 0, s, p, R, N, 1, it,
                          F->d_pt_elem.as<int>(), F->d_l2p_Z32.as<float2>(), (const float2*)le, (float2*)y);
     else if (R == 1)
-      hipLaunchKernelGGL((k_l2p<RT, 64>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0, it, boxes, tl,
+      hipLaunchKernelGGL((k_l2p<RT, 64>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, 1, it, boxes, tl,
                          sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);
     else
-      hipLaunchKernelGGL((k_l2p<RT, 32>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, c > 0 ? 1 : 0, it, boxes, tl,
+      hipLaunchKernelGGL((k_l2p<RT, 32>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, 1, it, boxes, tl,
                          sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);
   }
   LM_STAGE(4, 0);
-  LM_STAGE(5, 1);
-  // near fields and self terms
-  if (sizeof(RT) == 4 && R > 1) {
-    // FP32, several right-hand sides: free-space near field + self terms as
-    // leaf blocks on matrix cores, then the few reaction near pairs
-    if (!F->nb_item.empty()) {
-      hipLaunchKernelGGL((k_block_mfma<float2, true>), dim3(F->nb_item.size() / 2), dim3(64 * PA_NW), 0, s, N, R,
-                         F->d_nb_item.as<int>(), F->d_nb_jptr.as<int>(), F->d_nb_jidx.as<int>(),
-                         F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(), F->d_nb_Z32.as<float2>(),
-                         F->d_xt.as<float2>(), (float2*)y);
-    }
-    if (!F->rn_src.empty())
-      hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(F->rn_rows.size(), 4)), dim3(256), 0, s, N,
-                         (int)F->rn_rows.size(), F->d_rn_rows.as<int>(), R, F->d_rn_ptr.as<int>(),
-                         F->d_rn_src.as<int>(), F->d_rn_val32.as<float2>(), (const float2*)x, (float2*)y);
-  } else if (R >= 8) {
-    hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, s, N, N, (const int*)nullptr, R,
-                       F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
-  } else {
-    hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, s, N, N, (const int*)nullptr, R,
-                       F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
-  }
-  LM_STAGE(5, 0);
 #undef LM_STAGE
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;

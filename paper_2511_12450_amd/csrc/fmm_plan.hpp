@@ -76,6 +76,17 @@ struct FmmPlan {
   DevBuf d_nb_jptr, d_nb_jidx, d_nb_rows, d_nb_item, d_nb_zoff, d_nb_Z32, d_rn_val32, d_xt;
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
+  // side stream of the near field (default priority) and its fork / join events
+  hipStream_t s_near = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  FmmPlan() = default;
+  FmmPlan(const FmmPlan&) = delete;
+  FmmPlan& operator=(const FmmPlan&) = delete;
+  ~FmmPlan() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (s_near) (void)hipStreamDestroy(s_near);
+  }
   int64_t bytes() const {
     const DevBuf* all[] = {&d_boxes, &d_children, &d_pt_elem, &d_pt_xh, &d_pt_item, &d_p2m_leaf, &d_p2m_ptr,
                            &d_p2m_part, &d_parents, &d_m2l_tgt, &d_m2l_ptr, &d_m2l_src, &d_m2l_tab, &d_sig, &d_ops64,
