@@ -28,12 +28,14 @@
 // footprint can never fit is rejected at submission.  Finished requests keep
 // phi and the far field in host memory until released.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -424,6 +426,91 @@ struct Group {
   KmBufs km;
 };
 
+// One column's host update of a round: descriptors and coefficients with
+// offsets local to this column (rebased when the columns are merged).
+struct HostStep {
+  std::vector<ColDev> scal, comb, upd;
+  std::vector<double2> ys, cf;
+  std::vector<Column*> to_finish;
+  double gsb = 0.0;
+  void clear() {
+    scal.clear();
+    comb.clear();
+    upd.clear();
+    ys.clear();
+    cf.clear();
+    to_finish.clear();
+    gsb = 0.0;
+  }
+};
+
+// A few persistent host threads for per-column work: run(n, f) calls f(i)
+// for i in [0, n) on the pool and the calling thread and returns when all
+// are done.
+class HostPool {
+ public:
+  explicit HostPool(int n) : nt_(std::max(1, n)) {
+    for (int t = 1; t < nt_; ++t) th_.emplace_back([this] { loop(); });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    if (nt_ == 1 || n < 4) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      f_ = &f;
+      n_ = n;
+      next_.store(0);
+      busy_ = nt_ - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [this] { return busy_ == 0; });
+  }
+
+ private:
+  void work() {
+    for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*f_)(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        if (stop_) return;
+      }
+      work();
+      {
+        std::lock_guard<std::mutex> lk(m_);
+        if (--busy_ == 0) done_.notify_one();
+      }
+    }
+  }
+  int nt_;
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* f_ = nullptr;
+  int n_ = 0, busy_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 }  // namespace
 
 struct lm_server_s {
@@ -455,6 +542,8 @@ struct lm_server_s {
   hipEvent_t ev[SRV_STREAMS] = {};
   DevBuf d_desc, d_h, d_nrm, d_dpart, d_npart, d_y;
   DevBuf d_fz, d_fphi, d_fff;  // finishing columns: z, phi = M z, far fields
+  std::unique_ptr<HostPool> pool;  // per-column host updates
+  std::vector<HostStep> steps;
   std::vector<ColDev> hdesc;
   std::vector<double2> hh;
   std::vector<double> hnrm;
@@ -770,12 +859,14 @@ lm_status round(lm_server_s* S) {
   float gs_a = 0.f;
   LM_TRY_HIP(hipEventElapsedTime(&gs_a, S->t1, S->t2));
   // ---- 3. host updates ------------------------------------------------------------
-  std::vector<ColDev> scal, comb, upd;
-  std::vector<double2> ys, cf;
-  std::vector<Column*> to_finish;
-  double gsb = 0.0;
+  // Per column, independent of the others (its Hessenberg correction is
+  // O(j^2)): spread over the host pool, each column's descriptors and
+  // coefficients into its own HostStep, merged in column order afterwards.
   const double bb = (double)basis_bytes(S);
-  for (int i = 0; i < nc; ++i) {
+  S->steps.resize(nc);
+  auto host_step = [&](int i) {
+    HostStep& o = S->steps[i];
+    o.clear();
     Column* c = cols[i];
     const double nrm = std::sqrt(S->hnrm[i]);
     const double tol = c->req->o.tol;
@@ -791,7 +882,7 @@ lm_status round(lm_server_s* S) {
       d.ld = c->ldv;
       d.scale = 1.0 / beta;
       d.N = N;
-      scal.push_back(d);
+      o.scal.push_back(d);
       c->phase = PH_ARNOLDI;
     };
     auto end_cycle = [&](int cnt, bool conv) {  // y = H^{-1} e1 over cnt columns, z += V y
@@ -807,43 +898,43 @@ lm_status round(lm_server_s* S) {
       d.z = c->z.as<double2>();
       d.N = N;
       d.cnt = cnt;
-      d.scale = (double)ys.size();  // offset into the coefficient upload
-      for (int k = 0; k < cnt; ++k) ys.push_back(make_double2(yv[k].real(), yv[k].imag()));
-      comb.push_back(d);
+      d.scale = (double)o.ys.size();  // offset into the coefficient upload
+      for (int k = 0; k < cnt; ++k) o.ys.push_back(make_double2(yv[k].real(), yv[k].imag()));
+      o.comb.push_back(d);
       c->converged = conv;
       c->phase = (conv || c->its >= c->req->o.max_iter) ? PH_FINAL : PH_RESTART;
     };
     if (c->phase == PH_INIT) {
-      gsb += n16;
+      o.gsb += n16;
       c->gnorm = nrm;
       if (nrm == 0.0) {
         c->res = 0.0;
         c->converged = true;
-        to_finish.push_back(c);
+        o.to_finish.push_back(c);
       } else {
         c->res = 1.0;
         start_cycle(c->w, nrm);
       }
-      continue;
+      return;
     }
     if (c->phase == PH_RESTART || c->phase == PH_FINAL) {
-      gsb += 3.0 * n16;
+      o.gsb += 3.0 * n16;
       c->res = nrm / c->gnorm;
       if (c->phase == PH_FINAL) {
-        to_finish.push_back(c);  // true residual; convergence was decided by the GMRES estimate
+        o.to_finish.push_back(c);  // true residual; convergence was decided by the GMRES estimate
       } else if (c->res <= tol) {
         c->converged = true;
-        to_finish.push_back(c);
+        o.to_finish.push_back(c);
       } else {
         start_cycle(c->w, nrm);
       }
-      continue;
+      return;
     }
     // Arnoldi step j: a = V[0..j]^H u_j, b = V[0..j]^H K M u_j
     const int j = c->j;
     // basis vectors (bb bytes per element) and complex128 vectors moved by the
     // dot, residual-norm and update kernels of this step
-    gsb += (c->km ? (2.0 * j + 5.0) * bb + 3.0 * 16.0 : (j + 2.0) * bb) * N;
+    o.gsb += (c->km ? (2.0 * j + 5.0) * bb + 3.0 * 16.0 : (j + 2.0) * bb) * N;
     const double2* ha = &S->hh[(size_t)i * hs];
     const double2* hb = ha + ldh;
     std::vector<C> aQ(j), bQ(j);
@@ -882,7 +973,7 @@ lm_status round(lm_server_s* S) {
       const bool conv = c->res <= tol || std::abs(Hr[j]) <= 1e-300;
       if (conv || j == m || c->its >= c->req->o.max_iter || !c->km) {
         end_cycle(j, conv);
-        continue;
+        return;
       }
     }
     // continue: re-orthogonalise u_j into v_j and form the once-projected
@@ -917,17 +1008,39 @@ lm_status round(lm_server_s* S) {
     d.scale = 1.0 / rho;
     d.dr = make_double2((dd2 / rho).real(), (dd2 / rho).imag());
     d.ndst = c->dn.as<double>();
-    d.src = reinterpret_cast<const double2*>((size_t)cf.size());  // offset, fixed up after the upload
-    for (int k = 0; k < j; ++k) cf.push_back(make_double2(aQ[k].real(), aQ[k].imag()));
+    d.src = reinterpret_cast<const double2*>((size_t)o.cf.size());  // offset, fixed up after the upload
+    for (int k = 0; k < j; ++k) o.cf.push_back(make_double2(aQ[k].real(), aQ[k].imag()));
     for (int k = 0; k < j; ++k) {
       const C cq = (bQ[k] - Ha[k]) / rho;
       c->cprev[k] = cq;
       const C e = Ha[k] / rho + cq - aQ[k] * dd2 / rho;
-      cf.push_back(make_double2(e.real(), e.imag()));
+      o.cf.push_back(make_double2(e.real(), e.imag()));
     }
     c->cprev[j] = cj;
-    upd.push_back(d);
+    o.upd.push_back(d);
     c->j = j + 1;
+  };
+  S->pool->run(nc, host_step);
+  std::vector<ColDev> scal, comb, upd;
+  std::vector<double2> ys, cf;
+  std::vector<Column*> to_finish;
+  double gsb = 0.0;
+  for (int i = 0; i < nc; ++i) {
+    HostStep& o = S->steps[i];
+    const size_t bys = ys.size(), bcf = cf.size();
+    for (ColDev d : o.comb) {
+      d.scale += (double)bys;
+      comb.push_back(d);
+    }
+    for (ColDev d : o.upd) {
+      d.src = reinterpret_cast<const double2*>(reinterpret_cast<size_t>(d.src) + bcf);
+      upd.push_back(d);
+    }
+    scal.insert(scal.end(), o.scal.begin(), o.scal.end());
+    ys.insert(ys.end(), o.ys.begin(), o.ys.end());
+    cf.insert(cf.end(), o.cf.begin(), o.cf.end());
+    to_finish.insert(to_finish.end(), o.to_finish.begin(), o.to_finish.end());
+    gsb += o.gsb;
   }
   // coefficient uploads (update passes, then solution combinations)
   const size_t ncf = cf.size();
@@ -1142,7 +1255,15 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
     delete S;
     return LM_EHIP;
   }
-  S->th = std::thread(worker, S);
+  try {  // host threads for the per-column updates: at most 8, never more than the cores
+    const int hc = (int)std::thread::hardware_concurrency();
+    S->pool.reset(new HostPool(std::min(8, std::max(1, hc))));
+    S->th = std::thread(worker, S);
+  } catch (const std::exception& e) {
+    lm_set_error("host thread creation failed: %s", e.what());
+    delete S;
+    return LM_EINTERNAL;
+  }
   *out = S;
   return LM_OK;
 }
