@@ -204,7 +204,10 @@ lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, 
  * active right-hand sides stays <= max_active_rhs and the estimated device
  * footprint of the admitted requests stays <= hbm_budget_bytes (basis,
  * work vectors and the per-right-hand-side FMM workspace; the geometry itself
- * is not counted).  Zero limits select 64 right-hand sides and 64 GiB.
+ * is not counted).  Zero limits select 64 right-hand sides and 64 GiB.  The
+ * device buffers of up to max_active_rhs finished solves are kept for reuse
+ * by later solves with the same N and restart length (outside that budget;
+ * released when an allocation fails and at lm_server_destroy).
  * All server entry points are thread-safe. */
 typedef struct {
   int64_t hbm_budget_bytes;

@@ -402,6 +402,14 @@ struct Column {
   bool km = false;        // needs K M this round
   std::vector<C> H, Hraw, cs, sn, e1, cprev;  // rotated / raw Hessenberg, provisional column
   double2* w = nullptr;  // this round's vector (group output slice or gv)
+  void reset() {  // solver state of a fresh column (device buffers are kept)
+    phase = PH_INIT;
+    j = its = ncols = 0;
+    gnorm = 0.0;
+    res = 1.0;
+    converged = finished = km = false;
+    w = nullptr;
+  }
 };
 
 struct Request {
@@ -534,6 +542,7 @@ struct lm_server_s {
   hipEvent_t sev[SRV_STREAMS][14] = {};
   // worker state
   std::vector<Column*> cols;
+  std::vector<Column*> spare;  // finished columns that keep their device buffers
   std::map<std::pair<lm_geom_s*, int>, Group> groups;
   std::map<lm_geom_s*, int> stream_of;
   hipStream_t s = nullptr;
@@ -588,24 +597,48 @@ lm_status ensure(DevBuf& b, size_t bytes) {
 }
 
 // Allocate the columns of an admitted request and compute its right-hand sides.
+void drop_spares(lm_server_s* S) {
+  for (Column* c : S->spare) delete c;
+  S->spare.clear();
+}
+
 lm_status start_request(lm_server_s* S, Request* q) {
   const int m = std::max(1, std::min(q->o.restart, q->o.max_iter));
   const int N = (int)q->g->N;
   for (int c = 0; c < q->R; ++c) {
-    Column* col = new (std::nothrow) Column();
+    // a spare column of the same shape keeps its device buffers
+    Column* col = nullptr;
+    for (auto it = S->spare.begin(); it != S->spare.end(); ++it)
+      if ((*it)->N == N && (*it)->m == m) {
+        col = *it;
+        S->spare.erase(it);
+        break;
+      }
+    const bool fresh = col == nullptr;
+    if (fresh) col = new (std::nothrow) Column();
     LM_CHECK(col, LM_ENOMEM, "host allocation failed");
     S->cols.push_back(col);
+    col->reset();
     col->req = q;
     col->col = c;
     col->g = q->g;
     col->N = N;
     col->m = m;
     col->ldv = (N + 63) / 64 * 64;
-    LM_TRY(col->V.alloc((size_t)(m + 1) * col->ldv * basis_bytes(S)));
-    LM_TRY(col->z.alloc((size_t)N * sizeof(double2)));
-    LM_TRY(col->gv.alloc((size_t)N * sizeof(double2)));
-    LM_TRY(col->y.alloc((size_t)(m + 1) * sizeof(double2)));
-    LM_TRY(col->dn.alloc(sizeof(double)));
+    if (fresh) {
+      auto alloc = [&]() -> lm_status {
+        LM_TRY(col->V.alloc((size_t)(m + 1) * col->ldv * basis_bytes(S)));
+        LM_TRY(col->z.alloc((size_t)N * sizeof(double2)));
+        LM_TRY(col->gv.alloc((size_t)N * sizeof(double2)));
+        LM_TRY(col->y.alloc((size_t)(m + 1) * sizeof(double2)));
+        LM_TRY(col->dn.alloc(sizeof(double)));
+        return LM_OK;
+      };
+      if (alloc() < 0) {  // give the spare columns' memory back and try once more
+        drop_spares(S);
+        LM_TRY(alloc());
+      }
+    }
     LM_TRY_HIP(hipMemsetAsync(col->z.p, 0, (size_t)N * sizeof(double2), S->s));
     LM_TRY(rhs_launch(q->g, 1, &q->theta[c], col->gv.p, S->s));
     col->H.assign((size_t)(m + 1) * m, 0.0);
@@ -1131,11 +1164,20 @@ lm_status round(lm_server_s* S) {
   return LM_OK;
 }
 
+// Removes the request's columns; up to max_active_rhs of them stay as spares
+// with their device buffers for the next admission of the same shape.
 void release_columns(lm_server_s* S, Request* q) {
   auto& v = S->cols;
   for (auto it = v.begin(); it != v.end();) {
     if ((*it)->req == q) {
-      delete *it;
+      Column* c = *it;
+      const bool whole = c->V.p && c->z.p && c->gv.p && c->y.p && c->dn.p;  // a failed start leaves holes
+      if (whole && (int)S->spare.size() < S->o.max_active_rhs) {
+        (*it)->req = nullptr;
+        S->spare.push_back(*it);
+      } else {
+        delete *it;
+      }
       it = v.erase(it);
     } else {
       ++it;
@@ -1223,6 +1265,7 @@ void worker(lm_server_s* S) {
     }
   }
   for (Request* q : running) release_columns(S, q);
+  drop_spares(S);
 }
 
 }  // namespace
