@@ -14,9 +14,10 @@
 // solves for the |B| unit vectors, and a kernel stores the scaled rows.
 // Subdomains are the free-space tree's boxes at the leaf level, or `coarsen`
 // levels above it (bigger overlapping blocks: fewer GMRES iterations for a
-// larger setup and apply); coarsen < 0 picks the coarsest level that fits.  Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so
-// the lanes of a wavefront read consecutive addresses of one row); the
-// mixed form applies an FP32 copy of Z.
+// larger setup and apply); coarsen < 0 picks the coarsest level that fits.
+// Apply: y_{B_r} = sum_j Z_B[r][j] x_{J_j} (Z row-major, so the lanes of a
+// wavefront read consecutive addresses of one row); the FP32 form applies a
+// binary16 copy of Z on matrix cores (see k_pre_h16).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -24,7 +25,6 @@
 #include <map>
 #include <tuple>
 
-#include "block_mfma.hpp"
 #include "fmm_plan.hpp"
 
 constexpr int PRE_QMAX = 8192;  // largest subdomain neighbourhood (LU workspace qmax^2 complex128)
@@ -32,13 +32,13 @@ constexpr int PRE_QMAX = 8192;  // largest subdomain neighbourhood (LU workspace
 struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
   std::vector<int> jptr, jidx, nb;
-  std::vector<int64_t> zoff;
-  std::vector<int> items;  // (subdomain, first row) work items of PA_ROWS rows for the MFMA apply
-  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_Z, d_Z32, d_items;
-  DevBuf d_xt;  // transposed complex64 input of the matrix-core apply
+  std::vector<int64_t> zoff, rowoff, zhoff;  // zhoff: binary16 blocks (row stride q rounded up to 4)
+  std::vector<int> items;  // (subdomain, first row) work items of PH_ROWS rows for the FP32-form apply
+  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_zhoff, d_rowoff, d_Z, d_Zh, d_rsc, d_items;
+  DevBuf d_xh, d_xl, d_cmax;  // split half-precision input of the FP32-form apply, column maxima
   int64_t bytes() const {
-    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_Z.bytes + d_Z32.bytes + d_items.bytes +
-           d_xt.bytes;
+    return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_zhoff.bytes + d_rowoff.bytes + d_Z.bytes + d_Zh.bytes +
+           d_rsc.bytes + d_items.bytes + d_xh.bytes + d_xl.bytes + d_cmax.bytes;
   }
 };
 
@@ -86,6 +86,10 @@ __global__ void k_pre_store(int q, int nB, const int* __restrict__ J, const doub
   const double2 v = X[idx];
   Z[idx] = make_double2(v.x * sc, v.y * sc);
 }
+
+// y_{B_r} = sum_j Z_B[r][j] x_{J_j}: one workgroup per leaf; x_J of RG
+// right-hand sides at a time is staged in LDS (in the arithmetic type), each
+// wavefront takes rows r = wave, wave + 4, ... two at a time, lanes run along
 
 // y_{B_r} = sum_j Z_B[r][j] x_{J_j}: one workgroup per leaf; x_J of RG
 // right-hand sides at a time is staged in LDS (in the arithmetic type), each
@@ -163,9 +167,233 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
   }
 }
 
-__global__ void k_z_to_c64(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+// ---- FP32-form apply on half-precision matrix cores ------------------------------
+// The preconditioner only sets the iteration count, provided that every
+// application in a solve is the same fixed complex-linear operator.  The FP32
+// form therefore stores the rows of P_B^{-1} once in binary16 (each row
+// scaled by a power of two so that its largest part is below 1, the scale
+// kept in FP32) and applies them with v_mfma_f32_16x16x16f16 (FP32
+// accumulation) to an input split into two binary16 parts x = x_hi + x_lo
+// (each right-hand side scaled by a power of two first): the operator is
+// fixed, and the input is represented to about 2^-22 of its largest element,
+// as in FP32.  The complex product uses the interleaved real embedding (four
+// real products, so the operator stays complex-linear): real row 2r + rho,
+// real column 2c + kappa, A = Re Z for rho == kappa, -Im Z for (0, 1), Im Z
+// for (1, 0); a lane holds the four k of two complex columns, i.e. one
+// 8-byte pair (Z[r][c], Z[r][c+1]) with the imaginary sign flipped (rho = 0)
+// or the halves swapped (rho = 1).
+typedef _Float16 ph4 __attribute__((ext_vector_type(4)));
+typedef float pf4 __attribute__((ext_vector_type(4)));
+constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZS = 136, PH_XS = 80;  // rows per item; LDS strides
+constexpr int PH_XLD = 64;  // row stride of the split input (right-hand sides)
+
+__device__ __forceinline__ uint32_t h16_pack(float re, float im) {
+  const _Float16 a = (_Float16)re, b = (_Float16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+__device__ __forceinline__ float h16_lo(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu)); }
+__device__ __forceinline__ float h16_hi(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); }
+
+// Row r (global index) of the stored blocks: scale 2^e with max |Re|, |Im| < 2^e,
+// binary16 entries of the scaled row at rzh[r], zero up to the next multiple of 4.
+__global__ void __launch_bounds__(256) k_z_to_h16(const int64_t* __restrict__ rz, const int64_t* __restrict__ rzh,
+                                                  const int* __restrict__ rq, const double2* __restrict__ Z,
+                                                  uint32_t* __restrict__ Zh, float* __restrict__ rsc) {
+  const int r = blockIdx.x;
+  const int64_t o = rz[r], oh = rzh[r];
+  const int q = rq[r], qp = (q + 3) & ~3;
+  double m = 0.0;
+  for (int c = threadIdx.x; c < q; c += 256) m = fmax(m, fmax(fabs(Z[o + c].x), fabs(Z[o + c].y)));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  __shared__ double wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+  int e = 0;
+  if (m > 0.0) (void)frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+  const double sc = ldexp(1.0, -e);
+  for (int c = threadIdx.x; c < qp; c += 256)
+    Zh[oh + c] = c < q ? h16_pack((float)(Z[o + c].x * sc), (float)(Z[o + c].y * sc)) : 0u;
+  if (threadIdx.x == 0) rsc[r] = (float)ldexp(1.0, e);
+}
+
+// cmax[j] = max |Re|, |Im| of right-hand side j (as FP32 bits; cmax zeroed before).
+__global__ void __launch_bounds__(256) k_h16_colmax(int N, const double2* __restrict__ x, unsigned* __restrict__ cmax) {
+  const int j = blockIdx.y;
+  float m = 0.f;
+  for (int n = blockIdx.x * 2048 + threadIdx.x; n < min(N, (int)(blockIdx.x + 1) * 2048); n += 256) {
+    const double2 v = x[(int64_t)j * N + n];
+    m = fmaxf(m, fmaxf((float)fabs(v.x), (float)fabs(v.y)));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(cmax + j, __float_as_uint(m));
+}
+
+// v where keep, else zeros (component selects: no select between addresses)
+__device__ __forceinline__ uint4 ph_keep(bool keep, uint4 v) {
+  const uint32_t m = keep ? 0xffffffffu : 0u;
+  return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+}
+
+__device__ __forceinline__ int h16_col_exp(unsigned bits) {
+  const float m = __uint_as_float(bits);
+  int e = 0;
+  if (m > 0.f) (void)frexpf(m, &e);
+  return e;
+}
+
+// xh[n][j] + xl[n][j] = 2^-e_j x[j][n] (binary16 pairs, row stride PH_XLD, 32 x 32
+// tiles through LDS).
+__global__ void __launch_bounds__(256) k_h16_split(int N, int R, const double2* __restrict__ x,
+                                                   const unsigned* __restrict__ cmax, uint32_t* __restrict__ xh,
+                                                   uint32_t* __restrict__ xl) {
+  __shared__ uint2 tile[32][33];
+  const int n0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int j = j0 + k, n = n0 + threadIdx.x;
+    if (j < R && n < N) {
+      const float sc = ldexpf(1.f, -h16_col_exp(cmax[j]));
+      const double2 v = x[(int64_t)j * N + n];
+      const float re = (float)v.x * sc, im = (float)v.y * sc;
+      const uint32_t hi = h16_pack(re, im);
+      tile[k][threadIdx.x] = make_uint2(hi, h16_pack(re - h16_lo(hi), im - h16_hi(hi)));
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int n = n0 + k, j = j0 + threadIdx.x;
+    if (n < N && j < R) {
+      const uint2 t = tile[threadIdx.x][k];
+      xh[(int64_t)n * PH_XLD + j] = t.x;
+      xl[(int64_t)n * PH_XLD + j] = t.y;
+    }
+  }
+}
+
+// y_{B_r}[j] = sum_c Z_B[r][c] x_{J_c}[j] for a (subdomain, PH_ROWS rows)
+// item: 8 wavefronts in a 4 x 2 grid, each 4 x 2 tiles of 16 real rows
+// (8 complex) x 16 right-hand sides; K in chunks of PH_KC complex columns,
+// 8 per k-step.  The next chunk's binary16 data is loaded into registers
+// while the current one is multiplied, so one barrier pair per chunk is all
+// the staging costs.
+__global__ void __launch_bounds__(512) k_pre_h16(int N, int R, const int* __restrict__ items,
+                                                 const int* __restrict__ jptr, const int* __restrict__ jidx,
+                                                 const int* __restrict__ nb, const int64_t* __restrict__ zoff,
+                                                 const int64_t* __restrict__ rowoff, const uint32_t* __restrict__ Zh,
+                                                 const float* __restrict__ rsc, const uint32_t* __restrict__ xh,
+                                                 const uint32_t* __restrict__ xl, const unsigned* __restrict__ cmax,
+                                                 double2* __restrict__ y) {
+  constexpr int TR = PH_ROWS / 32, UZ = PH_ROWS * PH_KC / 2048, UX = PH_KC * 64 / 2048;  // 16-byte loads per thread
+  __shared__ uint2 Zs[PH_KC / 2][PH_ZS];  // [column pair][row]
+  __shared__ uint2 Xh[PH_KC / 2][PH_XS];  // [column pair][right-hand side]
+  __shared__ uint2 Xl[PH_KC / 2][PH_XS];
+  const int sd = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+  const int j0 = jptr[sd], q = jptr[sd + 1] - j0, qp = (q + 3) & ~3;
+  const int rows = min(PH_ROWS, nb[sd] - r0);
+  const int* J = jidx + j0;
+  const uint32_t* Zl = Zh + zoff[sd] + (int64_t)r0 * qp;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  const bool rho = (l16 & 1) != 0;
+  pf4 acc[TR][2];
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[t][c] = pf4{0.f, 0.f, 0.f, 0.f};
+  uint4 zr[UZ], hr[UX], lr[UX];
+// Next chunk into registers: 4 consecutive columns of a Z row (rows padded to a
+// multiple of 4), 4 consecutive right-hand sides of an input row.
+#define PH_FETCH(c0)                                                                                                   \
+  do {                                                                                                                 \
+_Pragma("unroll")                                                                                                      \
+    for (int u = 0; u < UZ; ++u) {                                                                                     \
+      const int idx = threadIdx.x + 512 * u, rr = idx / (PH_KC / 4), cq = 4 * (idx % (PH_KC / 4));                     \
+      const bool okz = rr < rows && c0 + cq < qp;                                                                      \
+      const uint4 tz = *reinterpret_cast<const uint4*>(Zl + (okz ? (int64_t)rr * qp + c0 + cq : 0));                   \
+      zr[u] = ph_keep(okz, tz);                                                                                        \
+    }                                                                                                                  \
+_Pragma("unroll")                                                                                                      \
+    for (int u = 0; u < UX; ++u) {                                                                                     \
+      const int idx = threadIdx.x + 512 * u, cc = idx >> 4, jq = 4 * (idx & 15);                                       \
+      const bool ok = c0 + cc < q && jq < R;                                                                           \
+      const int64_t o = ok ? (int64_t)J[c0 + cc] * PH_XLD + jq : 0;                                                    \
+      const uint4 th = *reinterpret_cast<const uint4*>(xh + o), tl = *reinterpret_cast<const uint4*>(xl + o);          \
+      hr[u] = ph_keep(ok, th);                                                                                         \
+      lr[u] = ph_keep(ok, tl);                                                                                         \
+    }                                                                                                                  \
+  } while (0)
+  if (q > 0) PH_FETCH(0);
+  for (int c0 = 0; c0 < q; c0 += PH_KC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UZ; ++u) {
+      const int idx = threadIdx.x + 512 * u, rr = idx / (PH_KC / 4), cq = 4 * (idx % (PH_KC / 4));
+      Zs[cq >> 1][rr] = make_uint2(zr[u].x, zr[u].y);
+      Zs[(cq >> 1) + 1][rr] = make_uint2(zr[u].z, zr[u].w);
+    }
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int idx = threadIdx.x + 512 * u, cc = idx >> 4, jq = 4 * (idx & 15);
+      uint32_t* ph = reinterpret_cast<uint32_t*>(&Xh[cc >> 1][jq]) + (cc & 1);
+      uint32_t* pl = reinterpret_cast<uint32_t*>(&Xl[cc >> 1][jq]) + (cc & 1);
+      ph[0] = hr[u].x;
+      ph[2] = hr[u].y;
+      ph[4] = hr[u].z;
+      ph[6] = hr[u].w;
+      pl[0] = lr[u].x;
+      pl[2] = lr[u].y;
+      pl[4] = lr[u].z;
+      pl[6] = lr[u].w;
+    }
+    __syncthreads();
+    if (c0 + PH_KC < q) PH_FETCH(c0 + PH_KC);
+#pragma unroll
+    for (int ks = 0; ks < PH_KC / 8; ++ks) {
+      const int pr = 4 * ks + kq;  // column pair of this lane's four k
+      ph4 bh[2], bl[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        bh[c] = __builtin_bit_cast(ph4, Xh[pr][16 * (2 * wc + c) + l16]);
+        bl[c] = __builtin_bit_cast(ph4, Xl[pr][16 * (2 * wc + c) + l16]);
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        uint2 z = Zs[pr][8 * (TR * wr + t) + (l16 >> 1)];
+        if (rho) {
+          z.x = (z.x >> 16) | (z.x << 16);
+          z.y = (z.y >> 16) | (z.y << 16);
+        } else {
+          z.x ^= 0x80000000u;
+          z.y ^= 0x80000000u;
+        }
+        const ph4 a = __builtin_bit_cast(ph4, z);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bh[c], acc[t][c], 0, 0, 0);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bl[c], acc[t][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+#undef PH_FETCH
+  // lane rows 4 kq + v of a tile: complex row 8 rt + 2 kq + v / 2, real part for even v
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int j = 16 * (2 * wc + c) + l16;
+    if (j >= R) continue;
+    const double cs = ldexp(1.0, h16_col_exp(cmax[j]));
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = 8 * (TR * wr + t) + 2 * kq + h;
+        if (r < rows) {
+          const double sc = cs * (double)rsc[rowoff[sd] + r0 + r];
+          y[(int64_t)j * N + J[r0 + r]] = make_double2(acc[t][c][2 * h] * sc, acc[t][c][2 * h + 1] * sc);
+        }
+      }
+  }
 }
 
 lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
@@ -230,15 +458,14 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   }
   P->nleaf = (int)P->nb.size();
   for (int b = 0; b < P->nleaf; ++b)
-    for (int r = 0; r < P->nb[b]; r += PA_ROWS) {
+    for (int r = 0; r < P->nb[b]; r += PH_ROWS) {
       P->items.push_back(b);
       P->items.push_back(r);
     }
   LM_CHECK(P->qmax <= PRE_QMAX, LM_EINVAL, "preconditioner neighbourhood too large (%d > %d); use a finer level",
            P->qmax, PRE_QMAX);
   {  // the VALU apply stages x_J of one or two right-hand sides in LDS (up to 128 KiB)
-    const void* fs[4] = {(const void*)k_pre_apply<double2, double, 1>, (const void*)k_pre_apply<double2, double, 2>,
-                         (const void*)k_pre_apply<float2, float, 2>, (const void*)k_pre_apply<float2, float, 4>};
+    const void* fs[2] = {(const void*)k_pre_apply<double2, double, 1>, (const void*)k_pre_apply<double2, double, 2>};
     for (const void* f : fs)
       LM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PRE_QMAX * 8));
   }
@@ -283,57 +510,78 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   LM_TRY_HIP(hipStreamSynchronize(s));
   for (int b = 0; b < P->nleaf; ++b)
     LM_CHECK(inf[b] == 0, LM_EINTERNAL, "singular preconditioner block %d (pivot %d)", b, (int)inf[b]);
-  LM_TRY(P->d_Z32.alloc(std::max<int64_t>(z, 1) * sizeof(float2)));
-  hipLaunchKernelGGL(k_z_to_c64, dim3(div_up(std::max<int64_t>(z, 1), 256)), dim3(256), 0, s, z, P->d_Z.as<double2>(),
-                     P->d_Z32.as<float2>());
-  LM_TRY_HIP(hipGetLastError());
-  LM_TRY_HIP(hipStreamSynchronize(s));
+  // binary16 rows with power-of-two row scales for the FP32-form apply
+  {
+    std::vector<int64_t> rz, rzh;
+    std::vector<int> rq;
+    P->rowoff.assign(1, 0);
+    P->zhoff.clear();
+    int64_t zh = 0;
+    for (int b = 0; b < P->nleaf; ++b) {
+      const int q = P->jptr[b + 1] - P->jptr[b], qp = (q + 3) & ~3;
+      P->zhoff.push_back(zh);
+      for (int r = 0; r < P->nb[b]; ++r) {
+        rz.push_back(P->zoff[b] + (int64_t)r * q);
+        rzh.push_back(zh + (int64_t)r * qp);
+        rq.push_back(q);
+      }
+      zh += (int64_t)P->nb[b] * qp;
+      P->rowoff.push_back(P->rowoff.back() + P->nb[b]);
+    }
+    DevBuf d_rz, d_rzh, d_rq;
+    LM_TRY(upload(d_rz, rz.data(), rz.size() * sizeof(int64_t), s));
+    LM_TRY(upload(d_rzh, rzh.data(), rzh.size() * sizeof(int64_t), s));
+    LM_TRY(upload(d_rq, rq.data(), rq.size() * sizeof(int), s));
+    LM_TRY(upload(P->d_rowoff, P->rowoff.data(), P->rowoff.size() * sizeof(int64_t), s));
+    LM_TRY(upload(P->d_zhoff, P->zhoff.data(), P->zhoff.size() * sizeof(int64_t), s));
+    LM_TRY(P->d_Zh.alloc(std::max<int64_t>(zh, 4) * sizeof(uint32_t)));
+    LM_TRY(P->d_rsc.alloc(std::max<size_t>(rz.size(), 1) * sizeof(float)));
+    if (!rz.empty())
+      hipLaunchKernelGGL(k_z_to_h16, dim3(rz.size()), dim3(256), 0, s, d_rz.as<int64_t>(), d_rzh.as<int64_t>(),
+                         d_rq.as<int>(), P->d_Z.as<double2>(), P->d_Zh.as<uint32_t>(), P->d_rsc.as<float>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
   return LM_OK;
 }
 
 lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s) {
   Precond* P = g->pre;
   LM_CHECK(P, LM_EINVAL, "no preconditioner");
-  if (precision == LM_MIXED && n_rhs > 1) {
-    const size_t need = (size_t)g->N * std::min(n_rhs, 64) * sizeof(float2);
-    if (P->d_xt.bytes < need) LM_TRY(P->d_xt.alloc(need));
+  if (precision == LM_MIXED) {  // half-precision matrix cores, chunks of 64 right-hand sides
+    const int N = (int)g->N, Rc = std::min(n_rhs, 64);
+    const size_t need = (size_t)N * PH_XLD * sizeof(uint32_t);
+    if (P->d_xh.bytes < need) LM_TRY(P->d_xh.alloc(need));
+    if (P->d_xl.bytes < need) LM_TRY(P->d_xl.alloc(need));
+    if (!P->d_cmax.p) LM_TRY(P->d_cmax.alloc(64 * sizeof(unsigned)));
     for (int r0 = 0; r0 < n_rhs; r0 += 64) {
       const int R = std::min(64, n_rhs - r0);
-      hipLaunchKernelGGL(k_to_nr<double2>, dim3(div_up(g->N, 32), div_up(R, 32)), dim3(32, 8), 0, s, (int)g->N, R,
-                         (const double2*)x + (int64_t)r0 * g->N, P->d_xt.as<float2>());
-      hipLaunchKernelGGL((k_block_mfma<double2, false>), dim3(P->items.size() / 2), dim3(64 * PA_NW), 0, s,
-                         (int)g->N, R, P->d_items.as<int>(), P->d_jptr.as<int>(), P->d_jidx.as<int>(),
-                         P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(), P->d_xt.as<float2>(),
-                         (double2*)y + (int64_t)r0 * g->N);
+      const double2* xr = (const double2*)x + (int64_t)r0 * N;
+      LM_TRY_HIP(hipMemsetAsync(P->d_cmax.p, 0, (size_t)R * sizeof(unsigned), s));
+      hipLaunchKernelGGL(k_h16_colmax, dim3(div_up(N, 2048), R), dim3(256), 0, s, N, xr, P->d_cmax.as<unsigned>());
+      hipLaunchKernelGGL(k_h16_split, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R, xr,
+                         P->d_cmax.as<unsigned>(), P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>());
+      hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 2), dim3(512), 0, s, N, R, P->d_items.as<int>(),
+                         P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zhoff.as<int64_t>(),
+                         P->d_rowoff.as<int64_t>(), P->d_Zh.as<uint32_t>(), P->d_rsc.as<float>(),
+                         P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>(), P->d_cmax.as<unsigned>(),
+                         (double2*)y + (int64_t)r0 * N);
     }
     LM_TRY_HIP(hipGetLastError());
     return LM_OK;
   }
-  // x_J of RG right-hand sides is staged in LDS: RG q sizeof <= 64 KiB
+  // FP64: x_J of RG right-hand sides is staged in LDS: RG q sizeof <= 128 KiB
   const bool big = P->qmax > 2048;
-  if (precision == LM_FP64) {
-    if (big)
-      hipLaunchKernelGGL((k_pre_apply<double2, double, 1>), dim3(P->nleaf), dim3(256),
-                         (size_t)P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
-                         (const double2*)x, (double2*)y);
-    else
-      hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
-                         (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
-                         (const double2*)x, (double2*)y);
-  } else {
-    if (big)
-      hipLaunchKernelGGL((k_pre_apply<float2, float, 2>), dim3(P->nleaf), dim3(256),
-                         (size_t)2 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
-                         (const double2*)x, (double2*)y);
-    else
-      hipLaunchKernelGGL((k_pre_apply<float2, float, 4>), dim3(P->nleaf), dim3(256),
-                         (size_t)4 * P->qmax * sizeof(float2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
-                         P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z32.as<float2>(),
-                         (const double2*)x, (double2*)y);
-  }
+  if (big)
+    hipLaunchKernelGGL((k_pre_apply<double2, double, 1>), dim3(P->nleaf), dim3(256),
+                       (size_t)P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
+                       (const double2*)x, (double2*)y);
+  else
+    hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
+                       (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
+                       P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
+                       (const double2*)x, (double2*)y);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
