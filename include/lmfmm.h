@@ -131,6 +131,16 @@ lm_status lm_fmm_stats(lm_geom geom, int64_t* out10);
 lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev,
                     void* hip_stream);
 
+/* y = M x for n_rhs vectors: M = P^{-1} = sum_B S_B Q_B P_B^{-1} R_B, the
+ * overlapping domain-decomposition preconditioner of Sec. 4.2 (built by
+ * lm_geometry_create with precond != 0), the operator GMRES applies on the
+ * right (solve K M z = g, phi = M z).  LM_FP64 applies the FP64 rows;
+ * LM_MIXED the binary16 copy on matrix cores, a fixed complex-linear operator
+ * within about 1e-3 of the FP64 one (it only changes iteration counts).
+ * x_dev, y_dev: device [n_rhs][N] complex128 for both precisions; x and y
+ * must not overlap.  LM_EINVAL when the geometry has no preconditioner. */
+lm_status lm_precond_apply(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, void* hip_stream);
+
 /* Runs reps FMM matvecs (as lm_matvec) and returns in out8_host the average
  * duration in ms of each stage, measured with HIP events recorded on
  * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L (all

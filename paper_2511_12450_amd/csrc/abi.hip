@@ -201,6 +201,15 @@ extern "C" lm_status lm_matvec(lm_geom g, int precision, int n_rhs, const void* 
   return geom_matvec(g, precision, n_rhs, x, y, (hipStream_t)hip_stream);
 }
 
+extern "C" lm_status lm_precond_apply(lm_geom g, int precision, int n_rhs, const void* x, void* y, void* hip_stream) {
+  LM_CHECK(g, LM_EINVAL, "geom is NULL");
+  LM_TRY(check_prec(precision));
+  LM_CHECK(n_rhs >= 1, LM_EINVAL, "n_rhs must be >= 1");
+  LM_CHECK(x && y && x != y, LM_EINVAL, "x and y must be distinct device pointers");
+  LM_CHECK(g->pre, LM_EINVAL, "the geometry has no preconditioner");
+  return precond_apply(g, precision, n_rhs, x, y, (hipStream_t)hip_stream);
+}
+
 extern "C" lm_status lm_matvec_stage_times(lm_geom g, int precision, int n_rhs, const void* x, void* y, int reps,
                                            void* hip_stream, double* out8) {
   LM_CHECK(g && out8 && reps >= 1, LM_EINVAL, "bad arguments");

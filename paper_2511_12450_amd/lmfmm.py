@@ -67,6 +67,7 @@ _SIGS = {
     "lm_destroy_geometry": ([_vp], _ip),
     "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
+    "lm_precond_apply": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
     "lm_matvec_stage_times": ([_vp, _ip, _ip, _vp, _vp, _ip, _vp, _dp], _ip),
     "lm_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
     "lm_gmres_solve": ([_vp, _ip, _ip, _dp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp], _ip),
@@ -207,6 +208,16 @@ class Geometry:
         if y is None:
             y = torch.empty_like(x)
         _check(lib().lm_matvec(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
+        return y
+
+    def precond_apply(self, x, y=None, precision=LM_FP64):
+        """y = M x (lm_precond_apply); x: complex128 [n_rhs][N] on the device."""
+        import torch
+        x = x.reshape(-1, self.n)
+        assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().lm_precond_apply(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
         return y
 
     def stage_times(self, x, y, reps=10, precision=LM_FP64):

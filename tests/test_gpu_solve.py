@@ -118,3 +118,27 @@ def test_coarser_subdomains_fewer_iterations_same_solution():
     print("iterations with the default subdomains:", r3[0][0], flush=True)
     assert s3 == lmfmm.LM_OK and r3[0][0] <= r2[0][0]
     assert _rel(g3.far_field(p3, obs).cpu().numpy(), g1.far_field(p1, obs).cpu().numpy()) < 1e-6
+
+
+def test_fp32_preconditioner_is_one_fixed_complex_linear_operator():
+    """The FP32 form applies the preconditioner rows in binary16 on matrix
+    cores; GMRES with right preconditioning needs the same complex-linear
+    operator at every application, which is what this checks (it need only
+    be close to the FP64 operator)."""
+    w = wl.three_layer_mini(seed=3)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+    x = torch.from_numpy(wl.random_vector(geo.n, seed=11, n_rhs=3)).cuda()
+    y64 = geo.precond_apply(x, precision=lmfmm.LM_FP64).cpu().numpy()
+    y32 = geo.precond_apply(x, precision=lmfmm.LM_MIXED).cpu().numpy()
+    for r in range(3):
+        d = _rel(y32[r], y64[r])
+        print(f"rhs {r}: binary16 vs FP64 operator rel diff {d:.2e}", flush=True)
+        assert d < 2e-3
+        one = geo.precond_apply(x[r:r + 1].contiguous(), precision=lmfmm.LM_MIXED).cpu().numpy()[0]
+        assert np.array_equal(one, y32[r])  # alone = in a batch, bit for bit
+    a, b = 0.3 - 1.7j, -2.1 + 0.4j
+    z = (a * x[0] + b * x[1])[None].contiguous()
+    yz = geo.precond_apply(z, precision=lmfmm.LM_MIXED).cpu().numpy()[0]
+    lin = _rel(yz, a * y32[0] + b * y32[1])
+    print(f"complex linearity rel diff {lin:.2e}", flush=True)
+    assert lin < 1e-5
