@@ -313,7 +313,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "precision_split": "f32 translations, near field and preconditioner apply; f64 Arnoldi, Givens, tables and self terms",
+        "precision_split": ("f32 translations and near field (matrix cores, f32 accumulation); binary16 preconditioner "
+                            "products on a split input (fixed operator, f32 accumulation); complex64 Krylov basis "
+                            "storage; f64 Arnoldi and Givens arithmetic, spectral tables and self terms"),
         "data": "synthetic",
         "config": cfg,
         "roofline": roof,
