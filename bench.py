@@ -250,7 +250,7 @@ def main():
     m2l_avg_s = ph["m2l_ms"] * 1e-3 / max(ph["m2l_launches"], 1)
     m2l_flops = ph["m2l_flops"] / max(ph["m2l_launches"], 1)
     m2l_roof = {"bound": "mfma", "achieved": m2l_flops / m2l_avg_s / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "traffic": None, "kernel": "k_m2l_mfma<4, 1, 0> (M2L lists)",
+                "unit": "TFLOP/s", "traffic": None, "kernel": "k_m2l_mfma<4, 1, 0, true> (M2L lists)",
                 "kernel_avg_us": m2l_avg_s * 1e6, "launches": int(ph["m2l_launches"]),
                 "algorithmic_flops_per_launch": m2l_flops,
                 "entries": stats["m2l_free_entries"] + stats["m2l_reaction_entries"]}

@@ -469,7 +469,8 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
 // not stored.  Each wavefront holds 3 row tiles (48 coefficients) of one
 // column tile; WC column tiles and WR row groups form the workgroup.
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int MF_ST = 8;  // staging loads in flight per lane
+constexpr int MF_ST = 8;   // staging loads in flight per lane
+constexpr int MF_PF = 18;  // prefetch registers per lane (an entry of p = 20, R = 64 on 256 threads)
 constexpr int MF_TR = 3;  // row tiles per wave
 __host__ __device__ inline int mf_ks(int P) { return (P + 3) / 4; }
 // complex slots after the staged T and a that must read as zero
@@ -483,7 +484,7 @@ inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_ze
 // KIND only names the instantiation (MF_LIST: M2L lists, MF_TREE: M2M / L2L)
 // so that profiles tell the launches apart.
 enum { MF_LIST = 0, MF_TREE = 1 };
-template <int WC, int WR, int KIND>
+template <int WC, int WR, int KIND, bool PRE>
 __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const int* __restrict__ items,
                                                       const int* __restrict__ src, const int* __restrict__ opi,
                                                       const float2* __restrict__ ops, const float2* __restrict__ me,
@@ -505,24 +506,50 @@ __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const i
   v4f t1[MF_TR], t2[MF_TR], t3[MF_TR];
 #pragma unroll
   for (int t = 0; t < MF_TR; ++t) t1[t] = t2[t] = t3[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int e = items[3 * blockIdx.x + 1]; e < items[3 * blockIdx.x + 2]; ++e) {
-    const float2* Tg = ops + (int64_t)opi[e] * PP;
-    const float2* Ag = me + (int64_t)src[e] * PR;
+  const int e0 = items[3 * blockIdx.x + 1], e1 = items[3 * blockIdx.x + 2];
+  // PRE (one entry fits MF_PF values per thread): the next entry is loaded
+  // into registers while the current one is multiplied
+  constexpr bool pre = PRE;
+  float2 pf[PRE ? MF_PF : 1];
+#define LM_MF_FETCH(e)                                                          \
+  do {                                                                          \
+    const float2* Tg_ = ops + (int64_t)opi[e] * PP;                             \
+    const float2* Ag_ = me + (int64_t)src[e] * PR;                              \
+    _Pragma("unroll") for (int u = 0; u < (PRE ? MF_PF : 1); ++u) {             \
+      const int idx = threadIdx.x + NTH * u;                                    \
+      const int ii = idx < NS ? idx : 0;                                        \
+      pf[u] = *(ii < PP ? Tg_ + ii : Ag_ + (ii - PP));                          \
+    }                                                                           \
+  } while (0)
+  if (pre && e0 < e1) LM_MF_FETCH(e0);
+  for (int e = e0; e < e1; ++e) {
     __syncthreads();
-    for (int base = threadIdx.x; base < NS; base += NTH * MF_ST) {
-      float2 v[MF_ST];
+    if (pre) {
 #pragma unroll
-      for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + NTH * u;
-        if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
+      for (int u = 0; u < (PRE ? MF_PF : 1); ++u) {
+        const int idx = threadIdx.x + NTH * u;
+        if (idx < NS) S[idx] = pf[u];
       }
+      __syncthreads();
+      if (e + 1 < e1) LM_MF_FETCH(e + 1);
+    } else {
+      const float2* Tg = ops + (int64_t)opi[e] * PP;
+      const float2* Ag = me + (int64_t)src[e] * PR;
+      for (int base = threadIdx.x; base < NS; base += NTH * MF_ST) {
+        float2 v[MF_ST];
 #pragma unroll
-      for (int u = 0; u < MF_ST; ++u) {
-        const int idx = base + NTH * u;
-        if (idx < NS) S[idx] = v[u];
+        for (int u = 0; u < MF_ST; ++u) {
+          const int idx = base + NTH * u;
+          if (idx < NS) v[u] = idx < PP ? Tg[idx] : Ag[idx - PP];
+        }
+#pragma unroll
+        for (int u = 0; u < MF_ST; ++u) {
+          const int idx = base + NTH * u;
+          if (idx < NS) S[idx] = v[u];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll 1
     for (int ks = 0; ks < KS; ++ks) {
       const float2 bv = S[boff + 4 * ks * R];
@@ -536,6 +563,7 @@ __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const i
       }
     }
   }
+#undef LM_MF_FETCH
   // partial slot of this item, or (translations with one item per box) the
   // output expansion itself, overwritten or accumulated; lane rows 4 kq + v
   // of a tile are coefficients m = 16 rt + 4 kq + v
@@ -568,9 +596,16 @@ inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const i
   const int P = 2 * p + 1, MT = (P + 15) / 16, NT = (R + 15) / 16;
   const size_t lds = mf_lds_bytes(P, R);
   const bool two = MT > MF_TR;
-#define LM_MF(WC, WR)                                                                                           \
-  hipLaunchKernelGGL((k_m2l_mfma<WC, WR, KIND>), dim3(n_items), dim3(64 * (WC) * (WR)), lds, s, p, R, items, src, \
-                     opi, ops, in, out, dtgt, accumulate)
+  const int NS = P * P + P * R;
+#define LM_MF(WC, WR)                                                                                               \
+  do {                                                                                                              \
+    if (NS <= MF_PF * 64 * (WC) * (WR))                                                                             \
+      hipLaunchKernelGGL((k_m2l_mfma<WC, WR, KIND, true>), dim3(n_items), dim3(64 * (WC) * (WR)), lds, s, p, R,    \
+                         items, src, opi, ops, in, out, dtgt, accumulate);                                          \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_m2l_mfma<WC, WR, KIND, false>), dim3(n_items), dim3(64 * (WC) * (WR)), lds, s, p, R,   \
+                         items, src, opi, ops, in, out, dtgt, accumulate);                                          \
+  } while (0)
   if (NT > 2) {
     if (two) LM_MF(4, 2); else LM_MF(4, 1);
   } else if (NT == 2) {
@@ -584,13 +619,12 @@ inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const i
 // LDS limit of the k_m2l_mfma instantiations (dynamic LDS above 64 KiB
 // must be allowed per kernel).
 inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
-  const void* fs[12] = {
-      (const void*)k_m2l_mfma<4, 1, MF_LIST>, (const void*)k_m2l_mfma<4, 2, MF_LIST>,
-      (const void*)k_m2l_mfma<2, 1, MF_LIST>, (const void*)k_m2l_mfma<2, 2, MF_LIST>,
-      (const void*)k_m2l_mfma<1, 1, MF_LIST>, (const void*)k_m2l_mfma<1, 2, MF_LIST>,
-      (const void*)k_m2l_mfma<4, 1, MF_TREE>, (const void*)k_m2l_mfma<4, 2, MF_TREE>,
-      (const void*)k_m2l_mfma<2, 1, MF_TREE>, (const void*)k_m2l_mfma<2, 2, MF_TREE>,
-      (const void*)k_m2l_mfma<1, 1, MF_TREE>, (const void*)k_m2l_mfma<1, 2, MF_TREE>};
+#define LM_MF4(KIND, PRE)                                                                        \
+  (const void*)k_m2l_mfma<4, 1, KIND, PRE>, (const void*)k_m2l_mfma<4, 2, KIND, PRE>,            \
+      (const void*)k_m2l_mfma<2, 1, KIND, PRE>, (const void*)k_m2l_mfma<2, 2, KIND, PRE>,        \
+      (const void*)k_m2l_mfma<1, 1, KIND, PRE>, (const void*)k_m2l_mfma<1, 2, KIND, PRE>
+  const void* fs[24] = {LM_MF4(MF_LIST, true), LM_MF4(MF_LIST, false), LM_MF4(MF_TREE, true), LM_MF4(MF_TREE, false)};
+#undef LM_MF4
   for (const void* f : fs) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
