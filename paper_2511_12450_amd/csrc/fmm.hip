@@ -1375,16 +1375,16 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       for (int i = 0; i < B.npt; ++i) leaf_slot[F->pt_elem[B.pt0 + i]] = (int)t;
     }
     F->nm_ptr.assign(N + 1, 0);
+    int64_t nnz = 0;
     for (int64_t i = 0; i < N; ++i) {
       int64_t len = 1 + (F->rn_ptr[i + 1] - F->rn_ptr[i]);
       const int t = leaf_slot[i];
       for (int e = F->near_ptr[t]; e < F->near_ptr[t + 1]; ++e) len += F->boxes[F->near_src[e]].npt;
       len -= 1;  // the element itself
-      F->nm_ptr[i + 1] = (int)len;
+      nnz += len;
+      LM_CHECK(nnz < ((int64_t)1 << 31), LM_ENOMEM, "near-field matrix too large");
+      F->nm_ptr[i + 1] = (int)nnz;
     }
-    for (int64_t i = 0; i < N; ++i) F->nm_ptr[i + 1] += F->nm_ptr[i];
-    const int64_t nnz = F->nm_ptr[N];
-    LM_CHECK(nnz < ((int64_t)1 << 31), LM_ENOMEM, "near-field matrix too large");
     F->nm_src.resize(nnz);
     nm_tgt.resize(nnz);
     nm_kind.resize(nnz);
@@ -1425,6 +1425,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
         const BoxDev& Cb = F->boxes[c];
         for (int i = 0; i < Cb.npt; ++i) F->nb_jidx.push_back(F->pt_elem[Cb.pt0 + i]);
       }
+      LM_CHECK(F->nb_jidx.size() < ((size_t)1 << 31), LM_ENOMEM, "near-field blocks too large");
       const int q = (int)F->nb_jidx.size() - F->nb_jptr.back();
       F->nb_jptr.push_back((int)F->nb_jidx.size());
       F->nb_rows.push_back(B.npt);
