@@ -95,6 +95,11 @@ lm_status lm_destroy_layers(lm_layers layers);
  *   leaves (larger blocks, fewer iterations); default (-1) = the coarsest
  *   level whose neighbourhoods hold at most 8192 elements and whose blocks
  *   fit a quarter of the free device memory.
+ *   top_fft: the interactions of the coarsest level (boxes of width 8 / k_max
+ *   that meet every non-adjacent box of their tree and of every side tree)
+ *   as a convolution along x, done by FFT: 0 (default) when the direct list
+ *   would hold more than twice the frequency-domain products, 1 always,
+ *   -1 never.  Same operator either way, up to rounding.
  * The handle keeps a reference to `layers`, which must outlive it.
  * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */
 typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;
@@ -103,6 +108,7 @@ typedef struct {
   int p;
   int leaf_size;
   int precond;
+  int top_fft;
 } lm_geom_opts;
 lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* node_offsets_host,
                              const double* nodes_xy_host, const lm_geom_opts* opts, void* hip_stream,
@@ -141,17 +147,19 @@ lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, v
  * must not overlap.  LM_EINVAL when the geometry has no preconditioner. */
 lm_status lm_precond_apply(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, void* hip_stream);
 
-/* Runs reps FMM matvecs (as lm_matvec) and returns in out8_host the average
+/* Runs reps FMM matvecs (as lm_matvec) and returns in out9_host the average
  * duration in ms of each stage, measured with HIP events recorded on
- * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L (all
- * levels, free-space and reaction; the translation kernel alone), [3] L2L,
- * [4] L2P, [5] near-field matrix (free-space near pairs, reaction near pairs
- * and self terms), [6] the sums of the M2L partial results per target box
- * (0 where the M2L writes its targets directly), [7] whole matvec.
- * Synchronises
- * the stream.  LM_EINVAL for a dense geometry. */
+ * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L lists
+ * (every level below the coarsest when the level-0 convolution is on, every
+ * level otherwise; free-space and reaction; the translation kernel alone),
+ * [3] L2L, [4] L2P, [5] near-field matrix (free-space near pairs, reaction
+ * near pairs and self terms), [6] the sums of the M2L partial results per
+ * target box (0 where the M2L writes its targets directly), [7] whole
+ * matvec, [8] the level-0 convolution (forward transforms, frequency-domain
+ * products, inverse transforms; 0 when it is off).  Synchronises the
+ * stream.  LM_EINVAL for a dense geometry. */
 lm_status lm_matvec_stage_times(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, int reps,
-                                void* hip_stream, double* out8_host);
+                                void* hip_stream, double* out9_host);
 
 /* ------------------------------------------------------------------- rhs --
  * g = -u^inc - u^b on Gamma_0 and -u^b elsewhere (eq. homogeneousscattering)

@@ -108,13 +108,15 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   g->layers = layers;
   g->m = layers->m;
   g->N = N;
-  lm_geom_opts o = {LM_AUTO, 20, 48, -1};
+  lm_geom_opts o = {LM_AUTO, 20, 48, -1, 0};
   if (opts) o = *opts;
   LM_CHECK(o.method >= LM_AUTO && o.method <= LM_FMM, LM_EINVAL, "bad method");
   g->method = o.method == LM_AUTO ? (N <= 4096 ? LM_DENSE : LM_FMM) : o.method;
   g->p = o.p > 0 ? o.p : 20;
   LM_CHECK(g->p <= 40, LM_EINVAL, "p must be <= 40");
   g->leaf_size = o.leaf_size > 0 ? o.leaf_size : 48;
+  LM_CHECK(o.top_fft >= -1 && o.top_fft <= 1, LM_EINVAL, "top_fft must be -1, 0 or 1");
+  g->top_fft = o.top_fft;
 
   // elements (Sec. 3.3): chord midpoints, chord lengths, layer of the midpoint
   g->cx.resize(N);
@@ -211,12 +213,12 @@ extern "C" lm_status lm_precond_apply(lm_geom g, int precision, int n_rhs, const
 }
 
 extern "C" lm_status lm_matvec_stage_times(lm_geom g, int precision, int n_rhs, const void* x, void* y, int reps,
-                                           void* hip_stream, double* out8) {
-  LM_CHECK(g && out8 && reps >= 1, LM_EINVAL, "bad arguments");
+                                           void* hip_stream, double* out9) {
+  LM_CHECK(g && out9 && reps >= 1, LM_EINVAL, "bad arguments");
   LM_TRY(check_prec(precision));
   LM_CHECK(n_rhs >= 1 && x && y && x != y, LM_EINVAL, "x and y must be distinct device pointers");
   LM_CHECK(g->method == LM_FMM, LM_EINVAL, "stage timing is defined for the FMM method");
-  return fmm_stage_times(g, precision, n_rhs, x, y, reps, (hipStream_t)hip_stream, out8);
+  return fmm_stage_times(g, precision, n_rhs, x, y, reps, (hipStream_t)hip_stream, out9);
 }
 
 extern "C" lm_status lm_rhs(lm_geom g, int n_rhs, const double* theta, void* g_dev, void* hip_stream) {

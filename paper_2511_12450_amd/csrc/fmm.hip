@@ -452,6 +452,126 @@ __global__ void __launch_bounds__(256) k_m2l_target(int p, int R, const int* __r
   acc_store(PR, are, aim, le + (int64_t)tgts[blockIdx.x] * PR);
 }
 
+// ---- level-0 convolution along x (see the plan) ---------------------------
+// A workgroup transforms CH = 2^lgc columns of one row, of length L = 2^lgL,
+// held in LDS as buf[k][c].  Radix-2, decimation in time: inputs are stored
+// at bit-reversed positions, then log2 L butterfly passes; tw[t] =
+// exp(-2 pi i t / L) for t < L / 2 (conjugated for the inverse).
+__device__ __forceinline__ int top_brev(int k, int lgL) { return (int)(__brev((unsigned)k) >> (32 - lgL)); }
+
+template <typename V, bool INV>
+__device__ void top_fft_lds(V* buf, int lgL, int lgc, const V* __restrict__ tw) {
+  const int L = 1 << lgL, nb = (L >> 1) << lgc;
+  for (int lh = 0; lh < lgL; ++lh) {
+    __syncthreads();
+    const int half = 1 << lh;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int c = b & ((1 << lgc) - 1), bf = b >> lgc;
+      const int j = bf & (half - 1), grp = bf >> lh;
+      const int i0 = ((grp << (lh + 1)) + j) << lgc | c, i1 = i0 + (half << lgc);
+      V w = tw[j << (lgL - 1 - lh)];
+      if (INV) w.y = -w.y;
+      const V a = buf[i0], x = buf[i1];
+      V t;
+      t.x = w.x * x.x - w.y * x.y;
+      t.y = w.x * x.y + w.y * x.x;
+      buf[i0] = mk<V>(a.x + t.x, a.y + t.y);
+      buf[i1] = mk<V>(a.x - t.x, a.y - t.y);
+    }
+  }
+  __syncthreads();
+}
+
+// Forward transform of the level-0 expansions of row blockIdx.y, columns
+// [CH blockIdx.x, +CH) of the P x R block: mh[row][f][c].
+template <typename V>
+__global__ void __launch_bounds__(256) k_top_fwd(int lgL, int lgc, int nx, int PR, const int* __restrict__ grid,
+                                                 const V* __restrict__ me, const V* __restrict__ tw,
+                                                 V* __restrict__ mh) {
+  extern __shared__ unsigned char dyn[];
+  V* buf = reinterpret_cast<V*>(dyn);
+  const int L = 1 << lgL, CH = 1 << lgc, r = blockIdx.y, c0 = blockIdx.x * CH;
+  for (int idx = threadIdx.x; idx < (L << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    V v = mk<V>(0, 0);
+    if (k < nx && c0 + c < PR) {
+      const int b = grid[(int64_t)r * nx + k];
+      if (b >= 0) v = me[(int64_t)b * PR + c0 + c];
+    }
+    buf[(top_brev(k, lgL) << lgc) | c] = v;
+  }
+  top_fft_lds<V, false>(buf, lgL, lgc, tw);
+  for (int idx = threadIdx.x; idx < (L << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    if (c0 + c < PR) mh[((int64_t)r * L + k) * PR + c0 + c] = buf[idx];
+  }
+}
+
+// Inverse transform of row blockIdx.y of lh[row][f][c], scaled by 1/L, into
+// the local expansions of that row's level-0 boxes (written, not added: a
+// level-0 box has no other M2L source).
+template <typename V>
+__global__ void __launch_bounds__(256) k_top_inv(int lgL, int lgc, int nx, int PR, const int* __restrict__ grid,
+                                                 const V* __restrict__ lh, const V* __restrict__ tw,
+                                                 V* __restrict__ le) {
+  extern __shared__ unsigned char dyn[];
+  V* buf = reinterpret_cast<V*>(dyn);
+  const int L = 1 << lgL, CH = 1 << lgc, r = blockIdx.y, c0 = blockIdx.x * CH;
+  for (int idx = threadIdx.x; idx < (L << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    V v = mk<V>(0, 0);
+    if (c0 + c < PR) v = lh[((int64_t)r * L + k) * PR + c0 + c];
+    buf[(top_brev(k, lgL) << lgc) | c] = v;
+  }
+  top_fft_lds<V, true>(buf, lgL, lgc, tw);
+  const double sc = 1.0 / L;
+  for (int idx = threadIdx.x; idx < (nx << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    const int b = grid[(int64_t)r * nx + k];
+    if (b >= 0 && c0 + c < PR) {
+      const V v = buf[idx];
+      le[(int64_t)b * PR + c0 + c] = mk<V>(v.x * sc, v.y * sc);
+    }
+  }
+}
+
+// Transformed operator sequences (setup, FP64): class blockIdx.y, operator
+// entries [CH blockIdx.x, +CH) of P x P.  Offset di in [-(nx-1), nx-1] sits at
+// position di mod L; the adjacent offsets of a near class are zero.
+__global__ void __launch_bounds__(256) k_top_tables(int lgL, int lgc, int nx, int PP, const double2* __restrict__ tab,
+                                                    const int* __restrict__ near, const double2* __restrict__ tw,
+                                                    double2* __restrict__ out64, float2* __restrict__ out32) {
+  extern __shared__ unsigned char dyn[];
+  double2* buf = reinterpret_cast<double2*>(dyn);
+  const int L = 1 << lgL, CH = 1 << lgc, cls = blockIdx.y, c0 = blockIdx.x * CH, D = 2 * nx - 1;
+  const bool nr = near[cls] != 0;
+  for (int idx = threadIdx.x; idx < (L << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    const int di = k < nx ? k : (k > L - nx ? k - L : L);
+    double2 v = make_double2(0.0, 0.0);
+    if (di < L && c0 + c < PP && !(nr && di >= -1 && di <= 1))
+      v = tab[((int64_t)cls * D + di + nx - 1) * PP + c0 + c];
+    buf[(top_brev(k, lgL) << lgc) | c] = v;
+  }
+  top_fft_lds<double2, false>(buf, lgL, lgc, tw);
+  for (int idx = threadIdx.x; idx < (L << lgc); idx += blockDim.x) {
+    const int k = idx >> lgc, c = idx & (CH - 1);
+    if (c0 + c < PP) {
+      const int64_t o = ((int64_t)cls * L + k) * PP + c0 + c;
+      out64[o] = buf[idx];
+      out32[o] = make_float2((float)buf[idx].x, (float)buf[idx].y);
+    }
+  }
+}
+
+// Columns per workgroup of the level-0 transforms: the largest power of two
+// <= 64 whose L x CH block fits 32 KiB of LDS.
+inline int top_lgc(int lgL, size_t elem) {
+  int lgc = 6;
+  while (lgc > 0 && ((size_t)1 << (lgL + lgc)) * elem > 32768) --lgc;
+  return lgc;
+}
+
 // Translations with matrix cores (FP32, several right-hand sides): M2L, and
 // M2M / L2L as items of one parent or child.  A work item (target, first
 // entry, end) sums Op_e a_src(e) over its entries; per entry the operator T
@@ -481,9 +601,10 @@ __host__ __device__ inline int mf_zero_tail(int P, int R) {
   return zb > za ? zb : za;
 }
 inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_zero_tail(P, R)) * sizeof(float2); }
-// KIND only names the instantiation (MF_LIST: M2L lists, MF_TREE: M2M / L2L)
+// KIND only names the instantiation (MF_LIST: M2L lists, MF_TREE: M2M / L2L,
+// MF_TOP: the frequency-domain products of the level-0 convolution)
 // so that profiles tell the launches apart.
-enum { MF_LIST = 0, MF_TREE = 1 };
+enum { MF_LIST = 0, MF_TREE = 1, MF_TOP = 2 };
 template <int WC, int WR, int KIND, bool PRE>
 __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const int* __restrict__ items,
                                                       const int* __restrict__ src, const int* __restrict__ opi,
@@ -623,7 +744,8 @@ inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
   (const void*)k_m2l_mfma<4, 1, KIND, PRE>, (const void*)k_m2l_mfma<4, 2, KIND, PRE>,            \
       (const void*)k_m2l_mfma<2, 1, KIND, PRE>, (const void*)k_m2l_mfma<2, 2, KIND, PRE>,        \
       (const void*)k_m2l_mfma<1, 1, KIND, PRE>, (const void*)k_m2l_mfma<1, 2, KIND, PRE>
-  const void* fs[24] = {LM_MF4(MF_LIST, true), LM_MF4(MF_LIST, false), LM_MF4(MF_TREE, true), LM_MF4(MF_TREE, false)};
+  const void* fs[36] = {LM_MF4(MF_LIST, true), LM_MF4(MF_LIST, false), LM_MF4(MF_TREE, true),
+                        LM_MF4(MF_TREE, false), LM_MF4(MF_TOP, true),   LM_MF4(MF_TOP, false)};
 #undef LM_MF4
   for (const void* f : fs) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1243,10 +1365,142 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     const double w = wl(B.level);
     return std::make_pair((int)std::lround((B.cx - F->x0) / w - 0.5), (int)std::lround(B.ch / w - 0.5));
   };
+  // ---- level 0 as a convolution along x ---------------------------------------
+  // A level-0 box meets every non-adjacent level-0 box of its free tree and
+  // every level-0 box of every side tree (no coarser level exists).  Its
+  // operator depends on the rows (tree, j) of target and source and on the
+  // column offset it - is alone, so per pair of rows that part of the M2L is
+  // a Toeplitz product along the columns: transform the level-0 expansions
+  // of each row (length top_L >= 2 nx - 1, zero padded, so the circular
+  // convolution is the linear one on columns 0..nx-1), multiply per
+  // frequency by the transformed operator sequence of each row pair, and
+  // transform back.
+  std::vector<double> top_free_geo, top_reac_geo;
+  std::vector<int> top_free_lvl, top_reac_meta, top_cls_near;
+  {
+    std::map<std::pair<int, int>, int> row_of;  // (tree, j) -> row
+    int nx = 0;
+    int64_t nreac0 = 0, direct = 0;
+    for (size_t ti = 0; ti < T.size(); ++ti) {
+      for (int64_t kk : T[ti].keys[0]) {
+        nx = std::max(nx, (int)(kk >> 32) + 1);
+        row_of.emplace(std::make_pair((int)ti, (int)(uint32_t)kk), 0);
+      }
+      const int64_t n0 = (int64_t)T[ti].keys[0].size();
+      if (T[ti].reac) nreac0 += n0;
+      else direct += n0 * n0;
+    }
+    direct += nreac0 * nreac0;
+    std::vector<std::pair<int, int>> rows;
+    for (auto& kv : row_of) {
+      kv.second = (int)rows.size();
+      rows.push_back(kv.first);
+    }
+    int L = 2;
+    while (L < 2 * nx - 1) L <<= 1;
+    // row pairs of every target row, with their operator class
+    std::map<std::tuple<int, int, int>, int> free_cls;       // (layer, dj, 0)
+    std::map<std::tuple<int, int, int, int>, int> reac_cls;  // (tt, ts, jt, js)
+    std::vector<std::vector<std::pair<int, int>>> pr(rows.size());  // (source row, class: free < 0)
+    int64_t npairs = 0;
+    for (size_t rt = 0; rt < rows.size(); ++rt) {
+      const int tt = rows[rt].first, jt = rows[rt].second;
+      for (size_t rs = 0; rs < rows.size(); ++rs) {
+        const int ts = rows[rs].first, js = rows[rs].second;
+        if (T[tt].reac != T[ts].reac || (!T[tt].reac && ts != tt)) continue;
+        int c;
+        if (T[tt].reac) {
+          auto q = reac_cls.emplace(std::make_tuple(tt, ts, jt, js), (int)reac_cls.size()).first;
+          c = q->second;
+        } else {
+          auto q = free_cls.emplace(std::make_tuple(T[tt].layer, jt - js, 0), (int)free_cls.size()).first;
+          c = -1 - q->second;
+        }
+        pr[rt].push_back({(int)rs, c});
+      }
+      npairs += (int64_t)pr[rt].size();
+    }
+    const size_t ncls = reac_cls.size() + free_cls.size();
+    F->top_on = nx > 0 && L <= 2048 && rows.size() < 65536 && ncls < 65536 &&
+                (g->top_fft > 0 || (g->top_fft == 0 && direct > 2 * npairs * L));
+    if (F->top_on) {
+      const int nrc = (int)reac_cls.size(), nfc = (int)free_cls.size(), D = 2 * nx - 1;
+      F->top_rows = (int)rows.size();
+      F->top_nx = nx;
+      F->top_L = L;
+      F->top_ncls = nrc + nfc;
+      F->top_direct = direct;
+      F->top_grid.assign((size_t)rows.size() * nx, -1);
+      for (size_t ti = 0; ti < T.size(); ++ti)
+        for (int64_t kk : T[ti].keys[0]) {
+          const int r = row_of.at({(int)ti, (int)(uint32_t)kk});
+          F->top_grid[(size_t)r * nx + (int)(kk >> 32)] = T[ti].idx[0].at(kk);
+        }
+      // tables of every class at every offset di = -(nx-1) .. nx-1 (class
+      // c, offset di at c * D + di + nx - 1; reaction classes first).  The
+      // offsets of adjacent boxes (|di| <= 1 in a near class) are not
+      // interactions: they get a harmless geometry and are masked out.
+      top_cls_near.assign(F->top_ncls, 0);
+      top_reac_meta.resize((size_t)nrc * D * 4);
+      top_reac_geo.resize((size_t)nrc * D * 3);
+      top_free_geo.resize((size_t)nfc * D * 3);
+      top_free_lvl.resize((size_t)nfc * D * 2);
+      const double w0 = wl(0);
+      for (auto& kv : reac_cls) {
+        const int c = kv.second;
+        const int tt = std::get<0>(kv.first), ts = std::get<1>(kv.first);
+        const int jt = std::get<2>(kv.first), js = std::get<3>(kv.first);
+        const bool near = jt == 0 && js == 0;
+        top_cls_near[c] = near;
+        for (int di = -(nx - 1); di <= nx - 1; ++di) {
+          const size_t t = (size_t)c * D + di + nx - 1;
+          const int dd = near && std::abs(di) <= 1 ? 2 : di;
+          top_reac_meta[4 * t] = T[tt].layer;
+          top_reac_meta[4 * t + 1] = T[ts].layer;
+          top_reac_meta[4 * t + 2] = T[tt].side + 2 * T[ts].side;
+          top_reac_meta[4 * t + 3] = 0;
+          top_reac_geo[3 * t] = dd * w0;
+          top_reac_geo[3 * t + 1] = (jt + 0.5) * w0;
+          top_reac_geo[3 * t + 2] = (js + 0.5) * w0;
+        }
+      }
+      for (auto& kv : free_cls) {
+        const int c = kv.second;
+        const int layer = std::get<0>(kv.first), dj = std::get<1>(kv.first);
+        const bool near = std::abs(dj) <= 1;
+        top_cls_near[nrc + c] = near;
+        for (int di = -(nx - 1); di <= nx - 1; ++di) {
+          const size_t t = (size_t)c * D + di + nx - 1;
+          const int dd = near && std::abs(di) <= 1 ? 2 : di;
+          top_free_geo[3 * t] = m.k[layer];
+          top_free_geo[3 * t + 1] = dd * w0;
+          top_free_geo[3 * t + 2] = dj * w0;
+          top_free_lvl[2 * t] = layer;
+          top_free_lvl[2 * t + 1] = 0;
+        }
+      }
+      // frequency-domain items: target (row, frequency) sums, over the row
+      // pairs of its row, the transformed operator of the pair's class times
+      // the transformed source row at the same frequency
+      F->top_ptr.push_back(0);
+      for (size_t rt = 0; rt < rows.size(); ++rt)
+        for (int f = 0; f < L; ++f) {
+          const int e0 = (int)F->top_src.size();
+          for (auto& q : pr[rt]) {
+            const int c = q.second >= 0 ? q.second : nrc + (-1 - q.second);
+            F->top_src.push_back(q.first * L + f);
+            F->top_op.push_back(c * L + f);
+          }
+          F->top_item.insert(F->top_item.end(), {(int)(rt * L + f), e0, (int)F->top_src.size()});
+          F->top_ptr.push_back((int)F->top_src.size());
+        }
+    }
+  }
   for (int b = 0; b < F->n_boxes; ++b) {
     const BoxDev& B = F->boxes[b];
     const TreeB& tb = T[B.tree];
     const int lev = B.level;
+    if (lev == 0 && F->top_on) continue;  // the level-0 convolution covers it
     auto [it, jt] = ij(b);
     std::vector<std::pair<int, int>> lst;  // (source, tab)
     if (!tb.reac) {
@@ -1578,6 +1832,62 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     }
     LM_TRY(up(F->d_m2l_op, opi, s));
   }
+  if (F->top_on) {
+    // level-0 convolution: operator tables at every offset (temporary),
+    // their transforms along the offset (FP64 and FP32), the index arrays
+    const int nx = F->top_nx, L = F->top_L, D = 2 * nx - 1;
+    const int nrc = (int)(top_reac_meta.size() / (4 * (size_t)D)), nfc = (int)(top_free_lvl.size() / (2 * (size_t)D));
+    int lgL = 0;
+    while ((1 << lgL) < L) ++lgL;
+    std::vector<double2> tw(L / 2);
+    std::vector<float2> tw32(L / 2);
+    for (int t = 0; t < L / 2; ++t) {
+      const double a = -2.0 * M_PI * t / L;
+      tw[t] = make_double2(std::cos(a), std::sin(a));
+      tw32[t] = make_float2((float)tw[t].x, (float)tw[t].y);
+    }
+    LM_TRY(up(F->d_top_tw64, tw, s));
+    LM_TRY(up(F->d_top_tw32, tw32, s));
+    DevBuf tab, near;
+    LM_TRY(tab.alloc((size_t)F->top_ncls * D * PP * sizeof(double2)));
+    if (nrc) {
+      DevBuf meta, geo;
+      LM_TRY(up(meta, top_reac_meta, s));
+      LM_TRY(up(geo, top_reac_geo, s));
+      hipLaunchKernelGGL(k_reac_tables, dim3(nrc * D), dim3(256), 0, s, m, p, nlev, meta.as<int>(), geo.as<double>(),
+                         F->d_sig.as<double>(), tab.as<double2>());
+      LM_TRY_HIP(hipGetLastError());
+      LM_TRY_HIP(hipStreamSynchronize(s));
+    }
+    if (nfc) {
+      DevBuf geo, lvl;
+      LM_TRY(up(geo, top_free_geo, s));
+      LM_TRY(up(lvl, top_free_lvl, s));
+      hipLaunchKernelGGL(k_free_tables, dim3(nfc * D), dim3(64), 0, s, p, nlev, geo.as<double>(), lvl.as<int>(),
+                         F->d_sig.as<double>(), tab.as<double2>() + (size_t)nrc * D * PP);
+      LM_TRY_HIP(hipGetLastError());
+      LM_TRY_HIP(hipStreamSynchronize(s));
+    }
+    LM_TRY(up(near, top_cls_near, s));
+    LM_TRY(F->d_top_T64.alloc((size_t)F->top_ncls * L * PP * sizeof(double2)));
+    LM_TRY(F->d_top_T32.alloc((size_t)F->top_ncls * L * PP * sizeof(float2)));
+    const int lgc = top_lgc(lgL, sizeof(double2));
+    hipLaunchKernelGGL(k_top_tables, dim3(div_up((int64_t)PP, 1 << lgc), F->top_ncls), dim3(256),
+                       ((size_t)L << lgc) * sizeof(double2), s, lgL, lgc, nx, (int)PP, tab.as<double2>(),
+                       near.as<int>(), F->d_top_tw64.as<double2>(), F->d_top_T64.as<double2>(),
+                       F->d_top_T32.as<float2>());
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+    std::vector<int> id((size_t)F->top_rows * L);
+    for (size_t i = 0; i < id.size(); ++i) id[i] = (int)i;
+    LM_TRY(up(F->d_top_id, id, s));
+    LM_TRY(up(F->d_top_grid, F->top_grid, s));
+    LM_TRY(up(F->d_top_item, F->top_item, s));
+    LM_TRY(up(F->d_top_ptr, F->top_ptr, s));
+    LM_TRY(up(F->d_top_src, F->top_src, s));
+    LM_TRY(up(F->d_top_op, F->top_op, s));
+    LM_TRY_HIP(hipStreamSynchronize(s));  // host staging vectors end with this scope
+  }
   // near-field matrix values
   const int nrn = (int)F->rn_src.size();
   {
@@ -1687,6 +1997,11 @@ lm_status fmm_reserve(FmmPlan* F, int r) {
   LM_TRY(F->d_me.alloc(bytes));
   LM_TRY(F->d_le.alloc(bytes));
   LM_TRY(F->d_p2m_part.alloc((size_t)std::max(F->item_ptr[3], 1) * F->P * r * sizeof(double2)));
+  if (F->top_on) {
+    const size_t tb = (size_t)F->top_rows * F->top_L * F->P * r * sizeof(double2);
+    LM_TRY(F->d_top_mh.alloc(tb));
+    LM_TRY(F->d_top_lh.alloc(tb));
+  }
   if (r > 1) {
     LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
     LM_TRY(F->d_xt.alloc((size_t)std::max<int64_t>(F->n_el, 1) * r * sizeof(float2)));
@@ -1699,7 +2014,8 @@ namespace {
 
 // One matvec of R <= LM_RCHUNK right-hand sides in storage type RT.  When
 // ev != nullptr, ev[2 i], ev[2 i + 1] bracket stage i on stream s (0 P2M,
-// 1 M2M, 2 M2L, 3 L2L, 4 L2P, 5 near-field matrix, 6 unused).
+// 1 M2M, 2 M2L lists, 3 L2L, 4 L2P, 5 near field (side stream), 6 M2L
+// partial sums, 7 level-0 convolution).
 template <typename RT>
 lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typename C2T<RT>::T* y, hipStream_t s,
                        hipEvent_t* ev) {
@@ -1795,6 +2111,35 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(1, 0);
   // M2L (every level at once); boxes without a list start from zero
   LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * PR * sizeof(V), s));
+  // level 0 as a convolution along x (stage 7): transform the level-0
+  // expansions of every row, one product per row pair and frequency,
+  // transform back into the level-0 local expansions
+  LM_STAGE(7, 1);
+  if (F->top_on) {
+    const int L = F->top_L, nx = F->top_nx, nrow = F->top_rows;
+    int lgL = 0;
+    while ((1 << lgL) < L) ++lgL;
+    const int lgc = top_lgc(lgL, sizeof(V));
+    const dim3 tg((unsigned)div_up(PR, 1 << lgc), (unsigned)nrow);
+    const size_t tlds = ((size_t)L << lgc) * sizeof(V);
+    V* mh = (V*)F->d_top_mh.p;
+    V* lh = (V*)F->d_top_lh.p;
+    const V* tw = sizeof(RT) == 8 ? (const V*)F->d_top_tw64.p : (const V*)F->d_top_tw32.p;
+    const V* tops = sizeof(RT) == 8 ? (const V*)F->d_top_T64.p : (const V*)F->d_top_T32.p;
+    hipLaunchKernelGGL(k_top_fwd<V>, tg, dim3(256), tlds, s, lgL, lgc, nx, PR, F->d_top_grid.as<int>(),
+                       (const V*)me, tw, mh);
+    if (sizeof(RT) == 4 && R > 1)
+      m2l_mfma_launch<MF_TOP>(nrow * L, p, R, F->d_top_item.as<int>(), F->d_top_src.as<int>(),
+                              F->d_top_op.as<int>(), (const float2*)tops, (const float2*)mh, (float2*)lh,
+                              (const int*)nullptr, 0, s);
+    else
+      hipLaunchKernelGGL(k_m2l_target<RT>, dim3(nrow * L), dim3(blk), lds_pr, s, p, R, F->d_top_id.as<int>(),
+                         F->d_top_ptr.as<int>(), F->d_top_src.as<int>(), F->d_top_op.as<int>(), tops,
+                         (const V*)mh, lh);
+    hipLaunchKernelGGL(k_top_inv<V>, tg, dim3(256), tlds, s, lgL, lgc, nx, PR, F->d_top_grid.as<int>(),
+                       (const V*)lh, tw, le);
+  }
+  LM_STAGE(7, 0);
   LM_STAGE(2, 1);
   if (!F->m2l_tgt.empty()) {
     const V* mops = ops + (size_t)F->op_m2l * PP;
@@ -1894,27 +2239,28 @@ lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, voi
 }
 
 // Average per-stage durations (ms) over reps matvecs, measured with HIP events
-// on the stream the kernels run on; out[7] = whole matvec.
+// on the stream the kernels run on; out[0..6] = stages 0..6, out[7] = whole
+// matvec, out[8] = stage 7 (level-0 convolution).
 lm_status fmm_stage_times(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, int reps, hipStream_t s,
                           double* out) {
-  hipEvent_t ev[16];
-  for (int i = 0; i < 16; ++i) LM_TRY_HIP(hipEventCreate(&ev[i]));
-  for (int i = 0; i < 8; ++i) out[i] = 0.0;
+  hipEvent_t ev[18];
+  for (int i = 0; i < 18; ++i) LM_TRY_HIP(hipEventCreate(&ev[i]));
+  for (int i = 0; i < 9; ++i) out[i] = 0.0;
   lm_status st = LM_OK;
   for (int r = 0; r < reps && st == LM_OK; ++r) {
-    LM_TRY_HIP(hipEventRecord(ev[14], s));
+    LM_TRY_HIP(hipEventRecord(ev[16], s));
     st = fmm_matvec_timed(g, precision, n_rhs, x, y, s, ev);
-    LM_TRY_HIP(hipEventRecord(ev[15], s));
-    LM_TRY_HIP(hipEventSynchronize(ev[15]));
-    for (int i = 0; i < 7; ++i) {
+    LM_TRY_HIP(hipEventRecord(ev[17], s));
+    LM_TRY_HIP(hipEventSynchronize(ev[17]));
+    for (int i = 0; i < 8; ++i) {
       float ms = 0;
       LM_TRY_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
-      out[i] += ms / reps;
+      out[i == 7 ? 8 : i] += ms / reps;
     }
     float ms = 0;
-    LM_TRY_HIP(hipEventElapsedTime(&ms, ev[14], ev[15]));
+    LM_TRY_HIP(hipEventElapsedTime(&ms, ev[16], ev[17]));
     out[7] += ms / reps;
   }
-  for (int i = 0; i < 16; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 18; ++i) (void)hipEventDestroy(ev[i]);
   return st;
 }

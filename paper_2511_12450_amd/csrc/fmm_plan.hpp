@@ -55,6 +55,15 @@ struct FmmPlan {
   std::vector<int64_t> nb_zoff;
   int64_t nb_nnz = 0;
   int l2l_item0 = 0;
+  // level 0 by FFT along x: rows (tree, j) of level-0 boxes over top_nx
+  // columns, transforms of length top_L (a power of two >= 2 top_nx - 1);
+  // operator classes (one Toeplitz operator sequence per class) and the
+  // frequency-domain M2L items (row * top_L + frequency, first entry, end)
+  bool top_on = false;
+  int top_rows = 0, top_nx = 0, top_L = 0, top_ncls = 0;
+  int64_t top_direct = 0;  // level-0 list entries the transform replaces
+  std::vector<int> top_grid;  // [row][top_nx] -> level-0 box or -1
+  std::vector<int> top_item, top_ptr, top_src, top_op;
   int n_reac_tab = 0, n_free_tab = 0;
   // expansion scales sig[layer][level][0..p]; translation operators, P x P
   // each, column-major by input: [M2M: layer, level, pos][L2L: same][M2L]
@@ -75,6 +84,8 @@ struct FmmPlan {
   DevBuf d_tr_item, d_tr_src, d_tr_op, d_box_id;
   DevBuf d_nb_jptr, d_nb_jidx, d_nb_rows, d_nb_item, d_nb_zoff, d_nb_Z32, d_rn_val32, d_xt;
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
+  DevBuf d_top_grid, d_top_item, d_top_ptr, d_top_src, d_top_op, d_top_id, d_top_tw64, d_top_tw32;
+  DevBuf d_top_T64, d_top_T32, d_top_mh, d_top_lh;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   // side stream of the near field (default priority) and its fork / join events
   hipStream_t s_near = nullptr;
@@ -95,7 +106,8 @@ struct FmmPlan {
                            &d_nm_ptr, &d_nm_src, &d_nm_val, &d_nm_val32, &d_nb_jptr, &d_nb_jidx, &d_nb_rows,
                            &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op,
                            &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
-                           &d_m2l_out};
+                           &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
+                           &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

@@ -84,6 +84,7 @@ struct lm_geom_s {
   int method = LM_DENSE;
   int p = 20;
   int leaf_size = 48;
+  int top_fft = 0;  // level-0 M2L by FFT: 0 when it pays, 1 always, -1 never
   // host element data, input numbering
   std::vector<double> cx, cy, w;
   std::vector<int32_t> layer;
@@ -109,7 +110,7 @@ lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, c
                           void* out, hipStream_t s);
 struct KmBufs {
   DevBuf x32, y32, mz;
-  hipEvent_t* stage_ev = nullptr;  // when set: 14 events bracketing the FMM stages (see fmm_matvec_timed)
+  hipEvent_t* stage_ev = nullptr;  // when set: 16 events bracketing the FMM stages (see fmm_matvec_timed)
 };
 lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, KmBufs& b,
                    hipStream_t s);

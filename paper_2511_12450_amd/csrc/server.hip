@@ -539,7 +539,7 @@ struct lm_server_s {
   double round_ms = 0.0, finish_ms = 0.0;            // host wall time of rounds / of finishing columns
   int64_t m2l_launches = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
-  hipEvent_t sev[SRV_STREAMS][14] = {};
+  hipEvent_t sev[SRV_STREAMS][16] = {};
   // worker state
   std::vector<Column*> cols;
   std::vector<Column*> spare;  // finished columns that keep their device buffers
@@ -1289,7 +1289,7 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
             hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
             hipEventCreate(&S->t2) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
-    for (int e = 0; ok && e < 14; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
+    for (int e = 0; ok && e < 16; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
     ok = hipStreamCreateWithFlags(&S->gs[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&S->ev[i], hipEventDisableTiming) == hipSuccess;
@@ -1458,7 +1458,7 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
   for (hipEvent_t e : {S->t0, S->t1, S->t2})
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < SRV_STREAMS; ++i)
-    for (int e = 0; e < 14; ++e)
+    for (int e = 0; e < 16; ++e)
       if (S->sev[i][e]) (void)hipEventDestroy(S->sev[i][e]);
   if (S->s) (void)hipStreamDestroy(S->s);
   delete S;

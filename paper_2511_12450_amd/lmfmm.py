@@ -28,7 +28,8 @@ class LmError(RuntimeError):
 
 
 class GeomOpts(ctypes.Structure):
-    _fields_ = [("method", ctypes.c_int), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int), ("precond", ctypes.c_int)]
+    _fields_ = [("method", ctypes.c_int), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int), ("precond", ctypes.c_int),
+                ("top_fft", ctypes.c_int)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -151,10 +152,10 @@ class Layers:
 class Geometry:
     """Elements of closed node polygons (Sec. 3.3) plus the operator data."""
 
-    def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1):
+    def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1, top_fft=0):
         off = np.ascontiguousarray(node_offsets, dtype=np.int64)
         xy = np.ascontiguousarray(nodes_xy, dtype=np.float64)
-        o = GeomOpts(method, p, leaf_size, precond)
+        o = GeomOpts(method, p, leaf_size, precond, top_fft)
         h = ctypes.c_void_p()
         _check(lib().lm_create_geometry(layers.h, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                         _dptr(xy), ctypes.byref(o), _stream(), ctypes.byref(h)))
@@ -221,9 +222,10 @@ class Geometry:
         return y
 
     def stage_times(self, x, y, reps=10, precision=LM_FP64):
-        """Average ms per FMM stage (P2M, M2M, M2L, L2L, L2P, near P2P,
-        reaction near + self, total) from HIP events inside the library."""
-        out = np.zeros(8)
+        """Average ms per FMM stage from HIP events inside the library: P2M,
+        M2M, M2L lists, L2L, L2P, near field, M2L partial sums, whole matvec,
+        level-0 convolution (lm_matvec_stage_times)."""
+        out = np.zeros(9)
         _check(lib().lm_matvec_stage_times(self.h, precision, x.shape[0], _tptr(x), _tptr(y), reps, _stream(),
                                            _dptr(out)))
         return out

@@ -1,0 +1,74 @@
+"""Writes the stored expected values for the full-size sampled-row parity
+tests: rows of the layered-medium Nystrom matrix (Sec. 3.3, the discrete
+system with the layered Green's function of Sec. 2) applied to seeded
+random vectors, for the 64,000-element three-layer workload and the
+1,000,000-element five-layer workload.
+
+Only the oracle and the seeded input generators are used.  Each row costs
+one pass of the oracle's direct Sommerfeld quadrature over every source
+(about 15 s at N = 64,000 and a few minutes at N = 1,000,000), so rows run
+in parallel worker processes.
+
+usage: python tests/golden/make_fullsize_rows.py [three_layer|five_layer] [workers]
+"""
+
+import multiprocessing as mp
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.medium import Medium  # noqa: E402
+from oracle.nystrom import Elements, matrix_rows  # noqa: E402
+from paper_2511_12450_amd import workloads as wl  # noqa: E402
+
+# name -> (workload, vector seed, right-hand sides, rows near an interface, other rows, row seed)
+CASES = {
+    "three_layer": (wl.three_layer, 21, 64, 4, 4, 31),
+    "five_layer": (wl.five_layer, 22, 8, 3, 3, 32),
+}
+
+_G = {}
+
+
+def sample_rows(med, el, n_near, n_any, seed):
+    """Rows drawn half among elements within 0.05 of an interface, half anywhere."""
+    rng = np.random.default_rng(seed)
+    near = np.nonzero(np.min(np.abs(el.cy[:, None] + med.d[None, :]), axis=1) < 0.05)[0]
+    return np.unique(np.concatenate([rng.choice(near, n_near, replace=False), rng.choice(el.n, n_any, replace=False)]))
+
+
+def _row(i):
+    med, el, X = _G["med"], _G["el"], _G["X"]
+    return matrix_rows(med, el, [i])[0] @ X.T
+
+
+def main():
+    name = sys.argv[1]
+    workers = int(sys.argv[2]) if len(sys.argv) > 2 else 1  # up to 35 GB per worker at N = 1,000,000
+    gen, vseed, nrhs, n_near, n_any, rseed = CASES[name]
+    w = gen()
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    X = wl.random_vector(el.n, seed=vseed, n_rhs=nrhs)
+    rows = sample_rows(med, el, n_near, n_any, rseed)
+    _G.update(med=med, el=el, X=X)
+    with mp.get_context("fork").Pool(workers) as pool:
+        Y = np.array(pool.map(_row, list(rows)))
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"fullsize_rows_{name}.txt")
+    with open(out, "w") as f:
+        f.write(f"# Oracle rows of the layered Nystrom matrix times seeded vectors: workload {w.name} (N={el.n}),\n")
+        f.write(f"# x = workloads.random_vector(N, seed={vseed}, n_rhs={nrhs}); rows drawn by sample_rows(seed={rseed}).\n")
+        f.write("# Written by tests/golden/make_fullsize_rows.py from the oracle alone.\n")
+        f.write("# columns: row rhs re im\n")
+        for a, i in enumerate(rows):
+            for r in range(nrhs):
+                f.write(f"{int(i)} {r} {float(Y[a, r].real)!r} {float(Y[a, r].imag)!r}\n")
+    print("wrote", out, "rows", rows.tolist(), flush=True)
+
+
+if __name__ == "__main__":
+    main()

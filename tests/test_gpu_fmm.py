@@ -33,10 +33,11 @@ def _straddle():
                        polys, np.array([40.0]))
 
 
-def test_fmm_matvec_straddling_eta():
+@pytest.mark.parametrize("top_fft", [-1, 1])
+def test_fmm_matvec_straddling_eta(top_fft):
     w = _straddle()
-    print("case: straddle3 fmm", flush=True)
-    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0)
+    print(f"case: straddle3 fmm top_fft={top_fft}", flush=True)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=top_fft)
     st = geo.fmm_stats()
     print(st, flush=True)
     med = Medium(w.d, w.k, w.eta)
@@ -108,3 +109,43 @@ def test_fmm_tiny():
     x = wl.random_vector(4, seed=1)[0]
     y = geo.matvec(torch.from_numpy(x[None]).cuda()).cpu().numpy()[0]
     assert _rel(y, K @ x) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [lmfmm.LM_FP64, lmfmm.LM_MIXED])
+def test_level0_convolution_equals_direct_lists(mini, precision):
+    """The coarsest level by FFT along x (top_fft=1) against the same
+    interactions as explicit M2L list entries (top_fft=-1): same operator up
+    to rounding, for one and several right-hand sides, and against the
+    oracle's sampled rows."""
+    w, _, med, el = mini
+    on = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=1)
+    off = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=-1)
+    s_on, s_off = on.fmm_stats(), off.fmm_stats()
+    print("lists with / without the level-0 convolution", s_on, s_off, flush=True)
+    assert s_on["m2l_free_entries"] + s_on["m2l_reaction_entries"] < \
+        s_off["m2l_free_entries"] + s_off["m2l_reaction_entries"]
+    dt = torch.complex128 if precision == lmfmm.LM_FP64 else torch.complex64
+    bar = 1e-11 if precision == lmfmm.LM_FP64 else 1e-5
+    for R in (1, 5):
+        x = torch.from_numpy(wl.random_vector(el.n, seed=20 + R, n_rhs=R)).to(dt).cuda()
+        a = on.matvec(x, precision=precision).cpu().numpy()
+        b = off.matvec(x, precision=precision).cpu().numpy()
+        err = _rel(a, b)
+        print(f"precision {precision} R={R}: level-0 convolution vs lists rel diff {err:.2e}", flush=True)
+        assert err < bar
+    y = torch.empty_like(x)
+    st_on = on.stage_times(x, y, reps=2, precision=precision)
+    st_off = off.stage_times(x, y, reps=2, precision=precision)
+    print("stage ms on", np.round(st_on, 3).tolist(), "off", np.round(st_off, 3).tolist(), flush=True)
+    assert st_on[8] > 0  # (off: the events bracket no kernel)
+    xr = wl.random_vector(el.n, seed=9, n_rhs=1)[0]
+    yr = on.matvec(torch.from_numpy(xr[None]).to(dt).cuda(), precision=precision).cpu().numpy()[0]
+    rng = np.random.default_rng(0)
+    near = np.nonzero(np.min(np.abs(el.cy[:, None] + med.d[None, :]), axis=1) < 0.05)[0]
+    rows = np.unique(np.concatenate([rng.choice(near, 12, replace=False), rng.choice(el.n, 12, replace=False)]))
+    xo = xr.astype(np.complex64).astype(np.complex128) if precision == lmfmm.LM_MIXED else xr
+    err = _rel(yr[rows].astype(np.complex128), matrix_rows(med, el, rows) @ xo)
+    print(f"precision {precision}: level-0 convolution sampled-row rel err {err:.2e}", flush=True)
+    assert err < (1e-6 if precision == lmfmm.LM_FP64 else 1e-4)
+    on.close()
+    off.close()
