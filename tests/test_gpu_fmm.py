@@ -149,3 +149,38 @@ def test_level0_convolution_equals_direct_lists(mini, precision):
     assert err < (1e-6 if precision == lmfmm.LM_FP64 else 1e-4)
     on.close()
     off.close()
+
+
+def test_level0_convolution_wide_sparse_rows():
+    """A wide medium with few scatterers: level-0 rows with empty columns,
+    rows holding one box, a scatterer across an eta != 1 interface.  The
+    convolution against the lists and both against the full oracle matrix."""
+    polys = [wl.circle((-5.6, 0.9), 0.18, 40), wl.star((-3.1, -0.6), 0.2, 48, 0.3), wl.circle((-0.4, -1.25), 0.22, 48),
+             wl.ellipse((1.7, 0.05), 0.3, 0.15, 0.4, 48), wl.circle((4.9, -2.3), 0.15, 32), wl.star((5.8, 1.6), 0.16, 40, 1.1)]
+    w = wl.Workload("wide6", np.array([0.0, 1.2]), np.array([6.0, 8.0, 5.0]), np.array([1.0, 1.5, 1.0]), polys,
+                    np.array([60.0]))
+    print("case: wide6 level-0 convolution", flush=True)
+    on = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=1)
+    off = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=-1)
+    s_on, s_off = on.fmm_stats(), off.fmm_stats()
+    print(s_on, s_off, flush=True)
+    assert s_on["m2l_reaction_entries"] < s_off["m2l_reaction_entries"]
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    K = matrix(med, el)
+    x = wl.random_vector(el.n, seed=13, n_rhs=3)
+    xt = torch.from_numpy(x).cuda()
+    y_on = on.matvec(xt).cpu().numpy()
+    y_off = off.matvec(xt).cpu().numpy()
+    y32 = on.matvec(xt.to(torch.complex64), precision=lmfmm.LM_MIXED).cpu().numpy()
+    ref = (K @ x.T).T
+    e_lists, e_on, e_off = _rel(y_on, y_off), _rel(y_on, ref), _rel(y_off, ref)
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    e32 = _rel(y32.astype(np.complex128), (K @ x32.T).T)
+    print(f"wide6: convolution vs lists {e_lists:.2e}, vs oracle {e_on:.2e} (lists {e_off:.2e}), FP32 {e32:.2e}",
+          flush=True)
+    assert e_lists < 1e-11
+    assert e_on < 1e-6 and e_off < 1e-6
+    assert e32 < 1e-4
+    on.close()
+    off.close()
