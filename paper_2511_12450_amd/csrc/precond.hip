@@ -33,12 +33,18 @@ struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
   std::vector<int> jptr, jidx, nb;
   std::vector<int64_t> zoff, rowoff, zhoff;  // zhoff: binary16 blocks (row stride q rounded up to 4)
-  std::vector<int> items;  // (subdomain, first row) work items of PH_ROWS rows for the FP32-form apply
-  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_zhoff, d_rowoff, d_Z, d_Zh, d_rsc, d_items;
+  // FP32-form apply: work items (subdomain, first row, first column, column
+  // end, partial slot or -1) of PH_ROWS rows and at most PH_KSEG columns (the
+  // columns of a row block split evenly); row blocks whose columns span
+  // several items sum their partial slots in order (subdomain, first row,
+  // first slot, count)
+  std::vector<int> items, sums;
+  int nslot = 0;
+  DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_zhoff, d_rowoff, d_Z, d_Zh, d_rsc, d_items, d_sums, d_part;
   DevBuf d_xh, d_xl, d_cmax;  // split half-precision input of the FP32-form apply, column maxima
   int64_t bytes() const {
     return d_jptr.bytes + d_jidx.bytes + d_nb.bytes + d_zoff.bytes + d_zhoff.bytes + d_rowoff.bytes + d_Z.bytes + d_Zh.bytes +
-           d_rsc.bytes + d_items.bytes + d_xh.bytes + d_xl.bytes + d_cmax.bytes;
+           d_rsc.bytes + d_items.bytes + d_xh.bytes + d_xl.bytes + d_cmax.bytes + d_sums.bytes + d_part.bytes;
   }
 };
 
@@ -186,6 +192,7 @@ typedef _Float16 ph4 __attribute__((ext_vector_type(4)));
 typedef float pf4 __attribute__((ext_vector_type(4)));
 constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZS = 136, PH_XS = 80;  // rows per item; LDS strides
 constexpr int PH_XLD = 64;  // row stride of the split input (right-hand sides)
+constexpr int PH_KSEG = 1024;  // most columns per work item (a multiple of PH_KC)
 
 __device__ __forceinline__ uint32_t h16_pack(float re, float im) {
   const _Float16 a = (_Float16)re, b = (_Float16)im;
@@ -270,24 +277,28 @@ __global__ void __launch_bounds__(256) k_h16_split(int N, int R, const double2* 
   }
 }
 
-// y_{B_r}[j] = sum_c Z_B[r][c] x_{J_c}[j] for a (subdomain, PH_ROWS rows)
-// item: 8 wavefronts in a 4 x 2 grid, each 4 x 2 tiles of 16 real rows
-// (8 complex) x 16 right-hand sides; K in chunks of PH_KC complex columns,
-// 8 per k-step.  The next chunk's binary16 data is loaded into registers
-// while the current one is multiplied, so one barrier pair per chunk is all
-// the staging costs.
+// y_{B_r}[j] = sum_c Z_B[r][c] x_{J_c}[j] for a (subdomain, PH_ROWS rows,
+// PH_KSEG columns) item: 8 wavefronts in a 4 x 2 grid, each 4 x 2 tiles of 16
+// real rows (8 complex) x 16 right-hand sides; K in chunks of PH_KC complex
+// columns, 8 per k-step.  The next chunk's binary16 data is loaded into
+// registers while the current one is multiplied, so one barrier pair per
+// chunk is all the staging costs.  Splitting long rows over several items
+// keeps every CU busy until the end (neighbourhoods differ by 2-3x in size);
+// such items leave their FP32 sums in a partial slot (k_pre_h16_sum adds
+// the slots of a row block in order, so the operator stays fixed).
 __global__ void __launch_bounds__(512) k_pre_h16(int N, int R, const int* __restrict__ items,
                                                  const int* __restrict__ jptr, const int* __restrict__ jidx,
                                                  const int* __restrict__ nb, const int64_t* __restrict__ zoff,
                                                  const int64_t* __restrict__ rowoff, const uint32_t* __restrict__ Zh,
                                                  const float* __restrict__ rsc, const uint32_t* __restrict__ xh,
                                                  const uint32_t* __restrict__ xl, const unsigned* __restrict__ cmax,
-                                                 double2* __restrict__ y) {
+                                                 double2* __restrict__ y, float2* __restrict__ part) {
   constexpr int TR = PH_ROWS / 32, UZ = PH_ROWS * PH_KC / 2048, UX = PH_KC * 64 / 2048;  // 16-byte loads per thread
   __shared__ uint2 Zs[PH_KC / 2][PH_ZS];  // [column pair][row]
   __shared__ uint2 Xh[PH_KC / 2][PH_XS];  // [column pair][right-hand side]
   __shared__ uint2 Xl[PH_KC / 2][PH_XS];
-  const int sd = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+  const int* it = items + 5 * blockIdx.x;
+  const int sd = it[0], r0 = it[1], cb = it[2], ce = it[3], slot = it[4];
   const int j0 = jptr[sd], q = jptr[sd + 1] - j0, qp = (q + 3) & ~3;
   const int rows = min(PH_ROWS, nb[sd] - r0);
   const int* J = jidx + j0;
@@ -323,8 +334,8 @@ _Pragma("unroll")                                                               
       lr[u] = ph_keep(ok, tl);                                                                                         \
     }                                                                                                                  \
   } while (0)
-  if (q > 0) PH_FETCH(0);
-  for (int c0 = 0; c0 < q; c0 += PH_KC) {
+  if (cb < ce) PH_FETCH(cb);
+  for (int c0 = cb; c0 < ce; c0 += PH_KC) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < UZ; ++u) {
@@ -347,7 +358,7 @@ _Pragma("unroll")                                                               
       pl[6] = lr[u].w;
     }
     __syncthreads();
-    if (c0 + PH_KC < q) PH_FETCH(c0 + PH_KC);
+    if (c0 + PH_KC < ce) PH_FETCH(c0 + PH_KC);
 #pragma unroll
     for (int ks = 0; ks < PH_KC / 8; ++ks) {
       const int pr = 4 * ks + kq;  // column pair of this lane's four k
@@ -378,6 +389,22 @@ _Pragma("unroll")                                                               
   }
 #undef PH_FETCH
   // lane rows 4 kq + v of a tile: complex row 8 rt + 2 kq + v / 2, real part for even v
+  if (slot >= 0) {  // partial sums of this column range
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = 16 * (2 * wc + c) + l16;
+      if (j >= R) continue;
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = 8 * (TR * wr + t) + 2 * kq + h;
+          if (r < rows)
+            part[((int64_t)slot * PH_ROWS + r) * PH_XLD + j] = make_float2(acc[t][c][2 * h], acc[t][c][2 * h + 1]);
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int j = 16 * (2 * wc + c) + l16;
@@ -393,6 +420,31 @@ _Pragma("unroll")                                                               
           y[(int64_t)j * N + J[r0 + r]] = make_double2(acc[t][c][2 * h] * sc, acc[t][c][2 * h + 1] * sc);
         }
       }
+  }
+}
+
+// Row blocks split over several items: y = scales x (sum of the partial
+// slots, in slot order).
+__global__ void __launch_bounds__(256) k_pre_h16_sum(int N, int R, const int* __restrict__ sums,
+                                                     const int* __restrict__ jptr, const int* __restrict__ jidx,
+                                                     const int* __restrict__ nb, const int64_t* __restrict__ rowoff,
+                                                     const float* __restrict__ rsc, const unsigned* __restrict__ cmax,
+                                                     const float2* __restrict__ part, double2* __restrict__ y) {
+  const int sd = sums[4 * blockIdx.x], r0 = sums[4 * blockIdx.x + 1];
+  const int slot0 = sums[4 * blockIdx.x + 2], ns = sums[4 * blockIdx.x + 3];
+  const int rows = min(PH_ROWS, nb[sd] - r0);
+  const int* J = jidx + jptr[sd];
+  for (int idx = threadIdx.x; idx < rows * PH_XLD; idx += blockDim.x) {
+    const int r = idx / PH_XLD, j = idx % PH_XLD;
+    if (j >= R) continue;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      const float2 v = part[((int64_t)(slot0 + k) * PH_ROWS + r) * PH_XLD + j];
+      re += v.x;
+      im += v.y;
+    }
+    const double sc = ldexp(1.0, h16_col_exp(cmax[j])) * (double)rsc[rowoff[sd] + r0 + r];
+    y[(int64_t)j * N + J[r0 + r]] = make_double2(re * sc, im * sc);
   }
 }
 
@@ -457,11 +509,15 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
     }
   }
   P->nleaf = (int)P->nb.size();
-  for (int b = 0; b < P->nleaf; ++b)
+  for (int b = 0; b < P->nleaf; ++b) {
+    const int q = P->jptr[b + 1] - P->jptr[b], nseg = std::max(1, (q + PH_KSEG - 1) / PH_KSEG);
+    const int len = ((q + nseg - 1) / nseg + PH_KC - 1) / PH_KC * PH_KC;  // <= PH_KSEG
     for (int r = 0; r < P->nb[b]; r += PH_ROWS) {
-      P->items.push_back(b);
-      P->items.push_back(r);
+      if (nseg > 1) P->sums.insert(P->sums.end(), {b, r, P->nslot, nseg});
+      for (int k = 0; k < nseg; ++k)
+        P->items.insert(P->items.end(), {b, r, k * len, std::min(q, (k + 1) * len), nseg > 1 ? P->nslot++ : -1});
     }
+  }
   LM_CHECK(P->qmax <= PRE_QMAX, LM_EINVAL, "preconditioner neighbourhood too large (%d > %d); use a finer level",
            P->qmax, PRE_QMAX);
   {  // the VALU apply stages x_J of one or two right-hand sides in LDS (up to 128 KiB)
@@ -474,6 +530,8 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   LM_TRY(upload(P->d_nb, P->nb.data(), P->nb.size() * sizeof(int), s));
   LM_TRY(upload(P->d_zoff, P->zoff.data(), P->zoff.size() * sizeof(int64_t), s));
   LM_TRY(upload(P->d_items, P->items.data(), P->items.size() * sizeof(int), s));
+  LM_TRY(upload(P->d_sums, P->sums.data(), P->sums.size() * sizeof(int), s));
+  LM_TRY(P->d_part.alloc((size_t)P->nslot * PH_ROWS * PH_XLD * sizeof(float2)));
   LM_TRY(P->d_Z.alloc(std::max<int64_t>(z, 1) * sizeof(double2)));
   DevBuf A, X, piv, info;
   LM_TRY(A.alloc((size_t)P->qmax * P->qmax * sizeof(double2)));
@@ -561,11 +619,16 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
       hipLaunchKernelGGL(k_h16_colmax, dim3(div_up(N, 2048), R), dim3(256), 0, s, N, xr, P->d_cmax.as<unsigned>());
       hipLaunchKernelGGL(k_h16_split, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R, xr,
                          P->d_cmax.as<unsigned>(), P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>());
-      hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 2), dim3(512), 0, s, N, R, P->d_items.as<int>(),
+      hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 5), dim3(512), 0, s, N, R, P->d_items.as<int>(),
                          P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zhoff.as<int64_t>(),
                          P->d_rowoff.as<int64_t>(), P->d_Zh.as<uint32_t>(), P->d_rsc.as<float>(),
                          P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>(), P->d_cmax.as<unsigned>(),
-                         (double2*)y + (int64_t)r0 * N);
+                         (double2*)y + (int64_t)r0 * N, P->d_part.as<float2>());
+      if (!P->sums.empty())
+        hipLaunchKernelGGL(k_pre_h16_sum, dim3(P->sums.size() / 4), dim3(256), 0, s, N, R, P->d_sums.as<int>(),
+                           P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_rowoff.as<int64_t>(),
+                           P->d_rsc.as<float>(), P->d_cmax.as<unsigned>(), P->d_part.as<float2>(),
+                           (double2*)y + (int64_t)r0 * N);
     }
     LM_TRY_HIP(hipGetLastError());
     return LM_OK;
