@@ -34,10 +34,9 @@ struct Precond {
   std::vector<int> jptr, jidx, nb;
   std::vector<int64_t> zoff, rowoff, zhoff;  // zhoff: binary16 blocks (row stride q rounded up to 4)
   // FP32-form apply: work items (subdomain, first row, first column, column
-  // end, partial slot or -1) of PH_ROWS rows and at most PH_KSEG columns (the
-  // columns of a row block split evenly); row blocks whose columns span
-  // several items sum their partial slots in order (subdomain, first row,
-  // first slot, count)
+  // end, partial slot) of PH_ROWS rows and at most PH_KSEG columns (the
+  // columns of a row block split evenly); per row block (subdomain, first
+  // row, first slot, count) the slots are summed in order
   std::vector<int> items, sums;
   int nslot = 0;
   DevBuf d_jptr, d_jidx, d_nb, d_zoff, d_zhoff, d_rowoff, d_Z, d_Zh, d_rsc, d_items, d_sums, d_part;
@@ -284,15 +283,14 @@ __global__ void __launch_bounds__(256) k_h16_split(int N, int R, const double2* 
 // registers while the current one is multiplied, so one barrier pair per
 // chunk is all the staging costs.  Splitting long rows over several items
 // keeps every CU busy until the end (neighbourhoods differ by 2-3x in size);
-// such items leave their FP32 sums in a partial slot (k_pre_h16_sum adds
-// the slots of a row block in order, so the operator stays fixed).
-__global__ void __launch_bounds__(512) k_pre_h16(int N, int R, const int* __restrict__ items,
-                                                 const int* __restrict__ jptr, const int* __restrict__ jidx,
-                                                 const int* __restrict__ nb, const int64_t* __restrict__ zoff,
-                                                 const int64_t* __restrict__ rowoff, const uint32_t* __restrict__ Zh,
-                                                 const float* __restrict__ rsc, const uint32_t* __restrict__ xh,
-                                                 const uint32_t* __restrict__ xl, const unsigned* __restrict__ cmax,
-                                                 double2* __restrict__ y, float2* __restrict__ part) {
+// every item leaves its FP32 sums in a partial slot and k_pre_h16_sum adds
+// the slots of a row block in order (so the operator stays fixed), scales
+// them and writes y along the rows.
+__global__ void __launch_bounds__(512) k_pre_h16(int R, const int* __restrict__ items, const int* __restrict__ jptr,
+                                                 const int* __restrict__ jidx, const int* __restrict__ nb,
+                                                 const int64_t* __restrict__ zoff, const uint32_t* __restrict__ Zh,
+                                                 const uint32_t* __restrict__ xh, const uint32_t* __restrict__ xl,
+                                                 float2* __restrict__ part) {
   constexpr int TR = PH_ROWS / 32, UZ = PH_ROWS * PH_KC / 2048, UX = PH_KC * 64 / 2048;  // 16-byte loads per thread
   __shared__ uint2 Zs[PH_KC / 2][PH_ZS];  // [column pair][row]
   __shared__ uint2 Xh[PH_KC / 2][PH_XS];  // [column pair][right-hand side]
@@ -388,63 +386,59 @@ _Pragma("unroll")                                                               
     }
   }
 #undef PH_FETCH
-  // lane rows 4 kq + v of a tile: complex row 8 rt + 2 kq + v / 2, real part for even v
-  if (slot >= 0) {  // partial sums of this column range
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int j = 16 * (2 * wc + c) + l16;
-      if (j >= R) continue;
-#pragma unroll
-      for (int t = 0; t < TR; ++t)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = 8 * (TR * wr + t) + 2 * kq + h;
-          if (r < rows)
-            part[((int64_t)slot * PH_ROWS + r) * PH_XLD + j] = make_float2(acc[t][c][2 * h], acc[t][c][2 * h + 1]);
-        }
-    }
-    return;
-  }
+  // FP32 sums of this column range into its partial slot (lane rows 4 kq + v
+  // of a tile: complex row 8 rt + 2 kq + v / 2, real part for even v)
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int j = 16 * (2 * wc + c) + l16;
     if (j >= R) continue;
-    const double cs = ldexp(1.0, h16_col_exp(cmax[j]));
 #pragma unroll
     for (int t = 0; t < TR; ++t)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int r = 8 * (TR * wr + t) + 2 * kq + h;
-        if (r < rows) {
-          const double sc = cs * (double)rsc[rowoff[sd] + r0 + r];
-          y[(int64_t)j * N + J[r0 + r]] = make_double2(acc[t][c][2 * h] * sc, acc[t][c][2 * h + 1] * sc);
-        }
+        if (r < rows)
+          part[((int64_t)slot * PH_ROWS + r) * PH_XLD + j] = make_float2(acc[t][c][2 * h], acc[t][c][2 * h + 1]);
       }
   }
 }
 
-// Row blocks split over several items: y = scales x (sum of the partial
-// slots, in slot order).
+// Every row block: y = scales x (sum of its partial slots, in slot order).  Slots are read along the right-hand sides and y is
+// written along the rows (through an LDS transpose, 16 right-hand sides at a
+// time), so both sides stay coalesced.
 __global__ void __launch_bounds__(256) k_pre_h16_sum(int N, int R, const int* __restrict__ sums,
                                                      const int* __restrict__ jptr, const int* __restrict__ jidx,
                                                      const int* __restrict__ nb, const int64_t* __restrict__ rowoff,
                                                      const float* __restrict__ rsc, const unsigned* __restrict__ cmax,
                                                      const float2* __restrict__ part, double2* __restrict__ y) {
+  __shared__ double2 T[16][PH_ROWS + 1];
   const int sd = sums[4 * blockIdx.x], r0 = sums[4 * blockIdx.x + 1];
   const int slot0 = sums[4 * blockIdx.x + 2], ns = sums[4 * blockIdx.x + 3];
   const int rows = min(PH_ROWS, nb[sd] - r0);
   const int* J = jidx + jptr[sd];
-  for (int idx = threadIdx.x; idx < rows * PH_XLD; idx += blockDim.x) {
-    const int r = idx / PH_XLD, j = idx % PH_XLD;
-    if (j >= R) continue;
-    double re = 0.0, im = 0.0;
-    for (int k = 0; k < ns; ++k) {
-      const float2 v = part[((int64_t)(slot0 + k) * PH_ROWS + r) * PH_XLD + j];
-      re += v.x;
-      im += v.y;
+  const float* rs = rsc + rowoff[sd] + r0;
+  for (int jh = 0; jh < R; jh += 16) {
+    for (int idx = threadIdx.x; idx < rows * 16; idx += blockDim.x) {
+      const int r = idx >> 4, jj = idx & 15;
+      double re = 0.0, im = 0.0;
+      if (jh + jj < R)
+        for (int k = 0; k < ns; ++k) {
+          const float2 v = part[((int64_t)(slot0 + k) * PH_ROWS + r) * PH_XLD + jh + jj];
+          re += v.x;
+          im += v.y;
+        }
+      T[jj][r] = make_double2(re, im);
     }
-    const double sc = ldexp(1.0, h16_col_exp(cmax[j])) * (double)rsc[rowoff[sd] + r0 + r];
-    y[(int64_t)j * N + J[r0 + r]] = make_double2(re * sc, im * sc);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * 16; idx += blockDim.x) {
+      const int jj = idx / rows, r = idx - jj * rows, j = jh + jj;
+      if (j < R) {
+        const double sc = ldexp(1.0, h16_col_exp(cmax[j])) * (double)rs[r];
+        const double2 v = T[jj][r];
+        y[(int64_t)j * N + J[r0 + r]] = make_double2(v.x * sc, v.y * sc);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -513,9 +507,8 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
     const int q = P->jptr[b + 1] - P->jptr[b], nseg = std::max(1, (q + PH_KSEG - 1) / PH_KSEG);
     const int len = ((q + nseg - 1) / nseg + PH_KC - 1) / PH_KC * PH_KC;  // <= PH_KSEG
     for (int r = 0; r < P->nb[b]; r += PH_ROWS) {
-      if (nseg > 1) P->sums.insert(P->sums.end(), {b, r, P->nslot, nseg});
-      for (int k = 0; k < nseg; ++k)
-        P->items.insert(P->items.end(), {b, r, k * len, std::min(q, (k + 1) * len), nseg > 1 ? P->nslot++ : -1});
+      P->sums.insert(P->sums.end(), {b, r, P->nslot, nseg});
+      for (int k = 0; k < nseg; ++k) P->items.insert(P->items.end(), {b, r, k * len, std::min(q, (k + 1) * len), P->nslot++});
     }
   }
   LM_CHECK(P->qmax <= PRE_QMAX, LM_EINVAL, "preconditioner neighbourhood too large (%d > %d); use a finer level",
@@ -619,11 +612,10 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
       hipLaunchKernelGGL(k_h16_colmax, dim3(div_up(N, 2048), R), dim3(256), 0, s, N, xr, P->d_cmax.as<unsigned>());
       hipLaunchKernelGGL(k_h16_split, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R, xr,
                          P->d_cmax.as<unsigned>(), P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>());
-      hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 5), dim3(512), 0, s, N, R, P->d_items.as<int>(),
+      hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 5), dim3(512), 0, s, R, P->d_items.as<int>(),
                          P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zhoff.as<int64_t>(),
-                         P->d_rowoff.as<int64_t>(), P->d_Zh.as<uint32_t>(), P->d_rsc.as<float>(),
-                         P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>(), P->d_cmax.as<unsigned>(),
-                         (double2*)y + (int64_t)r0 * N, P->d_part.as<float2>());
+                         P->d_Zh.as<uint32_t>(), P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>(),
+                         P->d_part.as<float2>());
       if (!P->sums.empty())
         hipLaunchKernelGGL(k_pre_h16_sum, dim3(P->sums.size() / 4), dim3(256), 0, s, N, R, P->d_sums.as<int>(),
                            P->d_jptr.as<int>(), P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_rowoff.as<int64_t>(),
