@@ -6,15 +6,19 @@ random vectors, for the 64,000-element three-layer workload and the
 
 Only the oracle and the seeded input generators are used.  Each row costs
 one pass of the oracle's direct Sommerfeld quadrature over every source
-(about 15 s at N = 64,000 and a few minutes at N = 1,000,000), so rows run
+(about 15 s at N = 64,000 and about 12 minutes at N = 1,000,000), so rows run
 in parallel worker processes.
 
 usage: python tests/golden/make_fullsize_rows.py [three_layer|five_layer] [workers]
+
+Rows already computed by an interrupted run are taken from a scratch file in
+the system temporary directory.
 """
 
 import multiprocessing as mp
 import os
 import sys
+import tempfile
 
 import numpy as np
 
@@ -28,7 +32,7 @@ from paper_2511_12450_amd import workloads as wl  # noqa: E402
 # name -> (workload, vector seed, right-hand sides, rows near an interface, other rows, row seed)
 CASES = {
     "three_layer": (wl.three_layer, 21, 64, 4, 4, 31),
-    "five_layer": (wl.five_layer, 22, 8, 3, 3, 32),
+    "five_layer": (wl.five_layer, 22, 8, 2, 2, 32),
 }
 
 _G = {}
@@ -56,8 +60,21 @@ def main():
     X = wl.random_vector(el.n, seed=vseed, n_rhs=nrhs)
     rows = sample_rows(med, el, n_near, n_any, rseed)
     _G.update(med=med, el=el, X=X)
+    # finished rows are kept in a scratch file of the system temporary
+    # directory, so an interrupted run resumes where it stopped
+    scratch = os.path.join(tempfile.gettempdir(), f"fullsize_rows_{name}_{vseed}_{nrhs}_{rseed}.npz")
+    done = {}
+    if os.path.exists(scratch):
+        z = np.load(scratch)
+        done = {int(i): y for i, y in zip(z["rows"], z["Y"])}
+    todo = [int(i) for i in rows if int(i) not in done]
     with mp.get_context("fork").Pool(workers) as pool:
-        Y = np.array(pool.map(_row, list(rows)))
+        for i, y in zip(todo, pool.imap(_row, todo)):
+            done[i] = y
+            print("row", i, "done", flush=True)
+            ks = sorted(done)
+            np.savez(scratch, rows=np.array(ks), Y=np.array([done[k] for k in ks]))
+    Y = np.array([done[int(i)] for i in rows])
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"fullsize_rows_{name}.txt")
     with open(out, "w") as f:
         f.write(f"# Oracle rows of the layered Nystrom matrix times seeded vectors: workload {w.name} (N={el.n}),\n")
