@@ -98,7 +98,8 @@ lm_status lm_destroy_layers(lm_layers layers);
  *   top_fft: the interactions of the coarsest level (boxes of width 8 / k_max
  *   that meet every non-adjacent box of their tree and of every side tree)
  *   as a convolution along x, done by FFT: 0 (default) when the direct list
- *   would hold more than twice the frequency-domain products, 1 always,
+ *   would hold more than twice the frequency-domain products and the
+ *   transformed operators fit a quarter of the free device memory, 1 always,
  *   -1 never.  Same operator either way, up to rounding.
  * The handle keeps a reference to `layers`, which must outlive it.
  * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */

@@ -1421,8 +1421,14 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       npairs += (int64_t)pr[rt].size();
     }
     const size_t ncls = reac_cls.size() + free_cls.size();
+    // device bytes: transformed sequences (FP64 + complex64) and, during
+    // setup, the tables at every offset
+    const double PPd = (double)(2 * p + 1) * (2 * p + 1);
+    const double top_bytes = (double)ncls * PPd * (24.0 * L + 16.0 * (2 * nx - 1));
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
     F->top_on = nx > 0 && L <= 2048 && rows.size() < 65536 && ncls < 65536 &&
-                (g->top_fft > 0 || (g->top_fft == 0 && direct > 2 * npairs * L));
+                (g->top_fft > 0 || (g->top_fft == 0 && direct > 2 * npairs * L && top_bytes <= 0.25 * (double)fr));
     if (F->top_on) {
       const int nrc = (int)reac_cls.size(), nfc = (int)free_cls.size(), D = 2 * nx - 1;
       F->top_rows = (int)rows.size();
