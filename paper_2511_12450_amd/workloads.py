@@ -202,25 +202,32 @@ def five_layer(seed=5, n_scat=4000, n_nodes=250, box=((-30.0, 30.0), (-12.0, 6.0
 def stream_geometry(g):
     """One geometry of the serving pool (seed 4+g): 2-4 layers, thickness
     U[1,3], k ~ U[1,10], N ~ U[4000, 250000] in scatterers of 160 nodes,
-    R ~ U[0.1,0.2], 10% straddlers, box for ~0.3 area fraction."""
-    rng = np.random.default_rng(4 + g)
-    n_layers = int(rng.integers(2, 5))
-    th = rng.uniform(1.0, 3.0, size=n_layers - 2)
-    d = np.concatenate([[0.0], np.cumsum(th)]) if n_layers > 2 else np.array([0.0])
-    k = rng.uniform(1.0, 10.0, size=n_layers)
-    N = int(rng.uniform(4000, 250000))
-    n_scat = max(1, N // 160)
-    area = n_scat * np.pi * (0.15 * 1.2) ** 2 / 0.3
-    side = np.sqrt(area)
-    ymid = -0.5 * d[-1]
-    box = ((-side, side), (ymid - side / 4, ymid + side / 4))
+    R ~ U[0.1,0.2], 10% straddlers, box for ~0.3 area fraction (enlarged by
+    25% steps, same draws, when the placement does not fit)."""
 
     def radius(rng_, kind):
         R = rng_.uniform(0.1, 0.2)
         return R, (1.2 * R if kind == "star" else R)
 
-    placed = _place(rng, n_scat, box, radius, 0.03, d, straddle_frac=0.1, iface_clear=0.02,
-                    kinds=("circle", "star"))
+    for attempt in range(8):
+        rng = np.random.default_rng(4 + g)
+        n_layers = int(rng.integers(2, 5))
+        th = rng.uniform(1.0, 3.0, size=n_layers - 2)
+        d = np.concatenate([[0.0], np.cumsum(th)]) if n_layers > 2 else np.array([0.0])
+        k = rng.uniform(1.0, 10.0, size=n_layers)
+        N = int(rng.uniform(4000, 250000))
+        n_scat = max(1, N // 160)
+        area = n_scat * np.pi * (0.15 * 1.2) ** 2 / 0.3
+        side = np.sqrt(area) * 1.25 ** attempt
+        ymid = -0.5 * d[-1]
+        box = ((-side, side), (ymid - side / 4, ymid + side / 4))
+        try:
+            placed = _place(rng, n_scat, box, radius, 0.03, d, straddle_frac=0.1, iface_clear=0.02,
+                            kinds=("circle", "star"), max_tries=200000)
+            break
+        except RuntimeError:
+            if attempt == 7:
+                raise
     polys = _shapes(rng, placed, 160)
     return Workload(f"stream_g{g}_N{n_scat * 160}", d, k, np.ones(n_layers), polys,
                     np.array([90.0]), p=20, tol=1e-6)
