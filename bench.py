@@ -55,6 +55,11 @@ def _args():
     ap.add_argument("--stream-rho", type=float, default=0.5, help="arrival rate as a fraction of the served capacity")
     ap.add_argument("--stream-max-angles", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pool-geometries", type=int, default=0,
+                    help="also serve an open-loop stream over this many pool geometries (2-4 layers, "
+                         "N in [4,000, 250,000], 1-16 angles per request); 0: skip")
+    ap.add_argument("--pool-requests", type=int, default=60)
+    ap.add_argument("--pool-rate", type=float, default=0.35, help="requests per second of the pool stream")
     return ap.parse_args()
 
 
@@ -244,6 +249,54 @@ def main():
         _log(f"stream: {a.stream_requests} requests in {span:.1f} s, p50 {stream['p50_s']:.3f} s, "
              f"p99 {stream['p99_s']:.3f} s")
 
+    # ---- optional: a stream over several pool geometries (different media and
+    # sizes, 1-16 angles per request, admission by HBM footprint)
+    pool = None
+    if a.pool_geometries > 0:
+        ws = [wl.stream_geometry(g) for g in range(a.pool_geometries)]
+        t0p = time.perf_counter()
+        pgeos = [lmfmm.Geometry.from_workload(w_, method=lmfmm.LM_FMM, p=w_.p) for w_ in ws]
+        _log(f"pool: {len(ws)} geometries (N {min(w_.n_elements for w_ in ws)}..{max(w_.n_elements for w_ in ws)}) "
+             f"ready in {time.perf_counter() - t0p:.1f} s")
+        rng = np.random.default_rng(11)
+        nq = a.pool_requests
+        gi = rng.integers(0, len(pgeos), size=nq)
+        na = rng.integers(1, 17, size=nq)
+        th_q = [np.radians(rng.uniform(10.0, 170.0, size=int(k))) for k in na]
+        t_arr = np.cumsum(rng.exponential(1.0 / a.pool_rate, size=nq))
+        srv3 = lmfmm.Server(precision=lmfmm.LM_MIXED, hbm_budget_bytes=int(160e9))
+        pend, lat_g, its_g = {}, {}, []
+        i, t0s = 0, time.perf_counter()
+        while i < nq or pend:
+            now = time.perf_counter() - t0s
+            while i < nq and t_arr[i] <= now:
+                pend[srv3.submit(pgeos[gi[i]], th_q[i], obs_rad=obs, **gm)] = i
+                i += 1
+            for rid in list(pend):
+                out_q = srv3.poll(rid, results=True)
+                if out_q[0] in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
+                    assert out_q[0] == lmfmm.LM_DONE, out_q[:2]
+                    k = pend.pop(rid)
+                    lat_g[k] = out_q[2]
+                    its_g += [r_[0] for r_ in out_q[3]]
+                    srv3.release(rid)
+                    if len(lat_g) % 25 == 0:
+                        _log(f"pool: {len(lat_g)} of {nq} requests done")
+            time.sleep(0.0005)
+        span = time.perf_counter() - t0s
+        srv3.close()
+        for g_ in pgeos:
+            g_.close()
+        keep = [lat_g[k] for k in range(nq // 10, nq)]
+        pool = {"geometries": [w_.name for w_ in ws], "layers": [int(len(w_.k)) for w_ in ws],
+                "requests": nq, "warmup_requests_excluded": nq // 10, "arrival_rate_requests_s": a.pool_rate,
+                "angles_per_request": [1, 16], "solves": int(np.sum(na)),
+                "solves_per_s": float(np.sum(na) / span), "span_s": span,
+                "p50_s": float(np.percentile(keep, 50)), "p99_s": float(np.percentile(keep, 99)),
+                "iterations_min_max": [int(min(its_g)), int(max(its_g))]}
+        _log(f"pool: {nq} requests, {int(np.sum(na))} solves in {span:.1f} s, p50 {pool['p50_s']:.3f} s, "
+             f"p99 {pool['p99_s']:.3f} s")
+
     # ---- kernel rooflines (HIP events on the launch stream, inside the timed batch)
     stats = geo.fmm_stats()
     rounds = st1["rounds"] - st0["rounds"]
@@ -305,6 +358,7 @@ def main():
         "batch_p99_s": float(np.percentile(lat_s, 99)),
         "rel_err_far_field_max": float(max(err_s + (stream["rel_err_far_field_max"] and [stream["rel_err_far_field_max"]] or []))) if stream else float(max(err_s)),
         "stream": stream,
+        "pool_stream": pool,
         "plain_fp64": {"value": a.plain_solves / plain_s, "unit": "solves/s", "solves": a.plain_solves,
                        "p50_s": float(np.percentile(lat_p, 50)), "p99_s": float(np.percentile(lat_p, 99)),
                        "iterations": [int(v) for v in its_p], "rel_err_far_field_max": float(max(err_p))},
