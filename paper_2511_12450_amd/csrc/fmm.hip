@@ -708,6 +708,81 @@ __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const i
   }
 }
 
+// M2L with few right-hand sides (FP32, 2 <= R <= 8), operator-major: the
+// list kernel would stage a P x P operator for every entry's P x R block.
+// Here a work item (operator, <= M2L_ITEM of its entries) stages the operator
+// once and multiplies it by the source blocks of G = 64 / R entries at a
+// time, laid side by side as the CB = G R columns of B ([n][c], c = g R + j),
+// with the same tiles and three-product form as k_m2l_mfma (WR row groups of
+// 3 tiles, 4 column tiles).  Entry g's P x R result goes to its slot (its
+// list position), summed per target by k_p2m_reduce.
+constexpr int OM_RMAX = 8;  // right-hand sides up to which the M2L runs operator-major
+template <int WR>
+__global__ void __launch_bounds__(256 * WR) k_m2l_om(int p, int R, const int* __restrict__ items,
+                                                     const int* __restrict__ slot, const int* __restrict__ src,
+                                                     const float2* __restrict__ ops, const float2* __restrict__ me,
+                                                     float2* __restrict__ out) {
+  constexpr int NTH = 256 * WR;
+  const int P = 2 * p + 1, PP = P * P, PR = P * R, G = 64 / R, CB = G * R;
+  const int MT = (P + 15) / 16, NT = (CB + 15) / 16, KS = mf_ks(P), NZ = mf_zero_tail(P, CB);
+  extern __shared__ unsigned char dyn[];
+  float2* S = reinterpret_cast<float2*>(dyn);  // T [n][m] (stride P), B [n][c] (stride CB), zero tail
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int wr = wv >> 2, ct = wv & 3;
+  const int t = items[3 * blockIdx.x], e0 = items[3 * blockIdx.x + 1], e1 = items[3 * blockIdx.x + 2];
+  const float2* Tg = ops + (int64_t)t * PP;
+  for (int idx = threadIdx.x; idx < PP; idx += NTH) S[idx] = Tg[idx];
+  for (int idx = threadIdx.x; idx < NZ; idx += NTH) S[PP + P * CB + idx] = make_float2(0.f, 0.f);
+  int aoff[MF_TR];
+#pragma unroll
+  for (int u = 0; u < MF_TR; ++u) aoff[u] = kq * P + min(16 * (wr * MF_TR + u) + l16, P - 1);
+  const int col = 16 * ct + l16;
+  const int boff = PP + kq * CB + min(col, 16 * NT - 1);
+  for (int eg = e0; eg < e1; eg += G) {
+    const int ng = min(G, e1 - eg);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < P * CB; idx += NTH) {
+      const int n = idx / CB, c = idx - n * CB, g = c / R, j = c - g * R;
+      S[PP + idx] = g < ng ? me[(int64_t)src[eg + g] * PR + n * R + j] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    v4f t1[MF_TR], t2[MF_TR], t3[MF_TR];
+#pragma unroll
+    for (int u = 0; u < MF_TR; ++u) t1[u] = t2[u] = t3[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ++ks) {
+      const float2 bv = S[boff + 4 * ks * CB];
+      const float bs = bv.x + bv.y;
+#pragma unroll
+      for (int u = 0; u < MF_TR; ++u) {
+        const float2 av = S[aoff[u] + 4 * ks * P];
+        t1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, t1[u], 0, 0, 0);
+        t2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, t2[u], 0, 0, 0);
+        t3[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bs, t3[u], 0, 0, 0);
+      }
+    }
+    const int g = col / R, j = col - g * R;
+    if (col < CB && g < ng) {
+      float2* o = out + (int64_t)slot[eg + g] * PR + j;
+#pragma unroll
+      for (int u = 0; u < MF_TR; ++u) {
+        const int rt = wr * MF_TR + u;
+        if (rt < MT) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = 16 * rt + 4 * kq + v;
+            if (m < P) {
+              const float a = t1[u][v], b = t2[u][v];
+              o[(int64_t)m * R] = make_float2(a - b, t3[u][v] - a - b);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Launch of k_m2l_mfma for R in [1, 64] and P <= 96 (p <= 47): one wavefront
 // per column tile of 16 right-hand sides, one or two row groups of 48.
 template <int KIND>
@@ -737,15 +812,16 @@ inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const i
 #undef LM_MF
 }
 
-// LDS limit of the k_m2l_mfma instantiations (dynamic LDS above 64 KiB
-// must be allowed per kernel).
+// LDS limit of the k_m2l_mfma and k_m2l_om instantiations (dynamic LDS
+// above 64 KiB must be allowed per kernel).
 inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
 #define LM_MF4(KIND, PRE)                                                                        \
   (const void*)k_m2l_mfma<4, 1, KIND, PRE>, (const void*)k_m2l_mfma<4, 2, KIND, PRE>,            \
       (const void*)k_m2l_mfma<2, 1, KIND, PRE>, (const void*)k_m2l_mfma<2, 2, KIND, PRE>,        \
       (const void*)k_m2l_mfma<1, 1, KIND, PRE>, (const void*)k_m2l_mfma<1, 2, KIND, PRE>
-  const void* fs[36] = {LM_MF4(MF_LIST, true), LM_MF4(MF_LIST, false), LM_MF4(MF_TREE, true),
-                        LM_MF4(MF_TREE, false), LM_MF4(MF_TOP, true),   LM_MF4(MF_TOP, false)};
+  const void* fs[38] = {LM_MF4(MF_LIST, true), LM_MF4(MF_LIST, false), LM_MF4(MF_TREE, true),
+                        LM_MF4(MF_TREE, false), LM_MF4(MF_TOP, true),   LM_MF4(MF_TOP, false),
+                        (const void*)k_m2l_om<1>,  (const void*)k_m2l_om<2>};
 #undef LM_MF4
   for (const void* f : fs) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -2009,6 +2085,8 @@ lm_status fmm_reserve(FmmPlan* F, int r) {
     LM_TRY(F->d_top_lh.alloc(tb));
   }
   if (r > 1) {
+    LM_TRY(F->d_om_slot.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * std::min(r, OM_RMAX) *
+                              sizeof(float2)));
     LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
     LM_TRY(F->d_xt.alloc((size_t)std::max<int64_t>(F->n_el, 1) * r * sizeof(float2)));
   }
@@ -2157,6 +2235,23 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_m2l_reduce<RT>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, p, F->d_m2l_tgt.as<int>(),
                          F->d_m2l_ptr.as<int>(), out, le);
+      LM_STAGE(6, 0);
+    } else if (sizeof(RT) == 4 && R <= OM_RMAX) {
+      // few right-hand sides: operator-major, one operator staged per item
+      float2* slots = F->d_om_slot.as<float2>();
+      const size_t lds = mf_lds_bytes(P, (64 / R) * R);
+      if ((P + 15) / 16 > MF_TR)
+        hipLaunchKernelGGL(k_m2l_om<2>, dim3(F->tm_item.size() / 3), dim3(512), lds, s, p, R,
+                           F->d_tm_item.as<int>(), F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(),
+                           (const float2*)mops, (const float2*)me, slots);
+      else
+        hipLaunchKernelGGL(k_m2l_om<1>, dim3(F->tm_item.size() / 3), dim3(256), lds, s, p, R,
+                           F->d_tm_item.as<int>(), F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(),
+                           (const float2*)mops, (const float2*)me, slots);
+      LM_STAGE(2, 0);
+      LM_STAGE(6, 1);
+      hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
+                         F->d_m2l_ptr.as<int>(), slots, (float2*)le);
       LM_STAGE(6, 0);
     } else if (sizeof(RT) == 4) {
       float2* mpart = F->d_mf_part.as<float2>();

@@ -86,6 +86,7 @@ struct FmmPlan {
   DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   DevBuf d_top_grid, d_top_item, d_top_ptr, d_top_src, d_top_op, d_top_id, d_top_tw64, d_top_tw32;
   DevBuf d_top_T64, d_top_T32, d_top_mh, d_top_lh;
+  DevBuf d_om_slot;  // per-entry M2L results of the few-right-hand-side (operator-major) launch
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   // side stream of the near field (default priority) and its fork / join events
   hipStream_t s_near = nullptr;
@@ -107,7 +108,8 @@ struct FmmPlan {
                            &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op,
                            &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
                            &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
-                           &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh};
+                           &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh,
+                           &d_om_slot};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

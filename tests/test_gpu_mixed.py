@@ -96,6 +96,24 @@ def test_multi_rhs_equals_single(mini, n_rhs):
         assert err < 1e-4
 
 
+@pytest.mark.parametrize("n_rhs", [2, 7, 16])
+def test_fp32_few_rhs_matches_many(mini, n_rhs):
+    """FP32 launches of few right-hand sides (up to 8: operator-major M2L;
+    16: target-major) against the same vectors inside a 64-wide launch and
+    against FP64."""
+    w, geo, med, el = mini
+    x = torch.from_numpy(wl.random_vector(el.n, seed=40, n_rhs=64)).cuda()
+    y64 = geo.matvec(x).cpu().numpy()
+    x32 = x.to(torch.complex64)
+    wide = geo.matvec(x32, precision=lmfmm.LM_MIXED).cpu().numpy()
+    few = geo.matvec(x32[:n_rhs].contiguous(), precision=lmfmm.LM_MIXED).cpu().numpy()
+    e_wide = _rel(few.astype(np.complex128), wide[:n_rhs].astype(np.complex128))
+    e_64 = _rel(few.astype(np.complex128), y64[:n_rhs])
+    print(f"R={n_rhs}: FP32 few vs wide launch {e_wide:.2e}, vs FP64 {e_64:.2e}", flush=True)
+    assert e_wide < 1e-5
+    assert e_64 < 1e-4
+
+
 def test_fp32_solve_far_field_vs_oracle(straddle):
     w, geo, med, el, K = straddle
     th = np.radians(w.angles_deg)
