@@ -341,12 +341,13 @@ __global__ void __launch_bounds__(256) k_p2m(int p, int R, int nlev, const int* 
 // me[leaf] = sum of the partial expansions of its work items.
 template <typename RT>
 __global__ void __launch_bounds__(256) k_p2m_reduce(int PR, const int* __restrict__ leaves,
-                                                    const int* __restrict__ ptr,
+                                                    const int* __restrict__ ptr, const int* __restrict__ sel,
                                                     const typename C2T<RT>::T* __restrict__ part,
                                                     typename C2T<RT>::T* __restrict__ me) {
   typedef typename C2T<RT>::T V;
-  const int i0 = ptr[blockIdx.x], i1 = ptr[blockIdx.x + 1];
-  V* out = me + (int64_t)leaves[blockIdx.x] * PR;
+  const int k = sel ? sel[blockIdx.x] : (int)blockIdx.x;  // sel: a subset of the outputs
+  const int i0 = ptr[k], i1 = ptr[k + 1];
+  V* out = me + (int64_t)leaves[k] * PR;
   for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) {
     RT re = 0, im = 0;
     for (int i = i0; i < i1; ++i) {
@@ -1051,12 +1052,16 @@ struct P2MOp {
   __device__ const float2* brow(int c) const { return xt + (int64_t)elem[c] * R; }
   __device__ void store(int r, int j, float re, float im) const { out[(int64_t)r * R + j] = make_float2(re, im); }
 };
+// The only item of a leaf writes the leaf's expansion itself (dst >= 0);
+// the items of larger leaves write partials, summed by k_p2m_reduce.
 __global__ void __launch_bounds__(64 * PA_NW) k_p2m_mfma(int p, int R, const int* __restrict__ items,
-                                                       const int* __restrict__ pt_elem, const float2* __restrict__ zp,
-                                                       const float2* __restrict__ xt, float2* __restrict__ part) {
-  const int pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
+                                                       const int* __restrict__ dst, const int* __restrict__ pt_elem,
+                                                       const float2* __restrict__ zp, const float2* __restrict__ xt,
+                                                       float2* __restrict__ part, float2* __restrict__ me) {
+  const int pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2], d = dst[blockIdx.x];
   const int P = 2 * p + 1;
-  P2MOp op{P, cnt, R, zp + (int64_t)pos * P, pt_elem + pos, xt, part + (int64_t)blockIdx.x * P * R};
+  float2* out = d >= 0 ? me + (int64_t)d * P * R : part + (int64_t)blockIdx.x * P * R;
+  P2MOp op{P, cnt, R, zp + (int64_t)pos * P, pt_elem + pos, xt, out};
   block_mfma_body(op, R);
 }
 
@@ -1356,6 +1361,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
         }
         F->p2m_leaf.push_back(b);
         F->p2m_ptr.push_back((int)F->pt_item.size() / 3);
+        const int i0 = F->p2m_ptr[F->p2m_ptr.size() - 2], i1 = F->p2m_ptr.back();
+        for (int i = i0; i < i1; ++i) F->p2m_dst.push_back(i1 - i0 == 1 ? b : -1);
+        if (i1 - i0 > 1) F->p2m_msel.push_back((int)F->p2m_leaf.size() - 1);
       }
     }
     F->item_ptr[3] = (int)F->pt_item.size() / 3;
@@ -1854,6 +1862,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_pt_item, F->pt_item, s));
   LM_TRY(up(F->d_p2m_leaf, F->p2m_leaf, s));
   LM_TRY(up(F->d_p2m_ptr, F->p2m_ptr, s));
+  LM_TRY(up(F->d_p2m_dst, F->p2m_dst, s));
+  LM_TRY(up(F->d_p2m_msel, F->p2m_msel, s));
   LM_TRY(up(F->d_parents, F->parents_by_level, s));
   LM_TRY(up(F->d_m2l_tgt, F->m2l_tgt, s));
   LM_TRY(up(F->d_m2l_ptr, F->m2l_ptr, s));
@@ -2162,7 +2172,8 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   if (n_items) {
     if (pt_mfma)
       hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
-                         F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(), F->d_xt.as<float2>(), (float2*)part);
+                         F->d_p2m_dst.as<int>(), F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(),
+                         F->d_xt.as<float2>(), (float2*)part, (float2*)me);
     else if (R == 1)
       hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
                          F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
@@ -2171,8 +2182,12 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       hipLaunchKernelGGL((k_p2m<RT, 32>), dim3(n_items), dim3(blk), (size_t)32 * R * sizeof(V), s, p, R, nlev,
                          F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
                          g->d_w.as<double>(), x, N, part);
-    hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_leaf.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
-                       F->d_p2m_ptr.as<int>(), part, me);
+    if (!pt_mfma)
+      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_leaf.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
+                         F->d_p2m_ptr.as<int>(), (const int*)nullptr, part, me);
+    else if (!F->p2m_msel.empty())  // leaves of one item were written directly
+      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_msel.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
+                         F->d_p2m_ptr.as<int>(), F->d_p2m_msel.as<int>(), part, me);
   }
   LM_STAGE(0, 0);
   LM_STAGE(1, 1);
@@ -2251,7 +2266,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       LM_STAGE(2, 0);
       LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
-                         F->d_m2l_ptr.as<int>(), slots, (float2*)le);
+                         F->d_m2l_ptr.as<int>(), (const int*)nullptr, slots, (float2*)le);
       LM_STAGE(6, 0);
     } else if (sizeof(RT) == 4) {
       float2* mpart = F->d_mf_part.as<float2>();
@@ -2261,7 +2276,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       LM_STAGE(2, 0);
       LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),
-                         F->d_mf_ptr.as<int>(), mpart, (float2*)le);
+                         F->d_mf_ptr.as<int>(), (const int*)nullptr, mpart, (float2*)le);
       LM_STAGE(6, 0);
     } else {
       hipLaunchKernelGGL(k_m2l_target<RT>, dim3(F->m2l_tgt.size()), dim3(blk), lds_pr, s, p, R,

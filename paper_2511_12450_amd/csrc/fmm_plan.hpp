@@ -24,6 +24,8 @@ struct FmmPlan {
   std::vector<int> pt_item;       // (leaf, first point, count) work items, by class
   int item_ptr[4] = {0, 0, 0, 0}; // items of class c: [item_ptr[c], item_ptr[c+1])
   std::vector<int> p2m_leaf, p2m_ptr;  // every leaf and the range of its items
+  std::vector<int> p2m_dst;   // per item: its leaf when the leaf has one item (written directly), else -1
+  std::vector<int> p2m_msel;  // positions (in p2m_leaf) of the leaves with several items
   std::vector<int> parents_by_level;           // boxes with children, grouped by level
   std::vector<int> parents_ptr;
   std::vector<int> children;
@@ -87,6 +89,7 @@ struct FmmPlan {
   DevBuf d_top_grid, d_top_item, d_top_ptr, d_top_src, d_top_op, d_top_id, d_top_tw64, d_top_tw32;
   DevBuf d_top_T64, d_top_T32, d_top_mh, d_top_lh;
   DevBuf d_om_slot;  // per-entry M2L results of the few-right-hand-side (operator-major) launch
+  DevBuf d_p2m_dst, d_p2m_msel;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   // side stream of the near field (default priority) and its fork / join events
   hipStream_t s_near = nullptr;
@@ -109,7 +112,7 @@ struct FmmPlan {
                            &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
                            &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
                            &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh,
-                           &d_om_slot};
+                           &d_om_slot, &d_p2m_dst, &d_p2m_msel};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;
