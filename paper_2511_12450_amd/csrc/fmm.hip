@@ -373,12 +373,12 @@ __device__ __forceinline__ void op_apply(int P, int R, const typename C2T<RT>::T
       RT re = are[i], im = aim[i];
       const typename C2T<RT>::T* op = Op + o;
       int j = 0;
-      for (; j + 4 <= P; j += 4) {  // four operator loads in flight
-        typename C2T<RT>::T t[4];
+      for (; j + 8 <= P; j += 8) {  // eight operator loads in flight
+        typename C2T<RT>::T t[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = op[(int64_t)(j + u) * P];
+        for (int u = 0; u < 8; ++u) t[u] = op[(int64_t)(j + u) * P];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cmac(re, im, t[u], in[(j + u) * R + r]);
+        for (int u = 0; u < 8; ++u) cmac(re, im, t[u], in[(j + u) * R + r]);
       }
       for (; j < P; ++j) cmac(re, im, op[(int64_t)j * P], in[j * R + r]);
       are[i] = re;
