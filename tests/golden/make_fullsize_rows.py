@@ -6,7 +6,7 @@ random vectors, for the 64,000-element three-layer workload and the
 
 Only the oracle and the seeded input generators are used.  Each row costs
 one pass of the oracle's direct Sommerfeld quadrature over every source
-(about 15 s at N = 64,000 and about 12 minutes at N = 1,000,000), so rows run
+(about 15 s at N = 64,000 and 20-30 minutes at N = 1,000,000), so rows run
 in parallel worker processes.
 
 usage: python tests/golden/make_fullsize_rows.py [three_layer|five_layer] [workers]
@@ -29,10 +29,12 @@ from oracle.medium import Medium  # noqa: E402
 from oracle.nystrom import Elements, matrix_rows  # noqa: E402
 from paper_2511_12450_amd import workloads as wl  # noqa: E402
 
-# name -> (workload, vector seed, right-hand sides, rows near an interface, other rows, row seed)
+# name -> (workload, vector seed, right-hand sides, rows near an interface, other rows, row seed,
+#          rows kept: the first ones of the sorted draw; a row of the 1,000,000-element
+#          workload takes 20-30 minutes of the oracle)
 CASES = {
-    "three_layer": (wl.three_layer, 21, 64, 4, 4, 31),
-    "five_layer": (wl.five_layer, 22, 8, 2, 2, 32),
+    "three_layer": (wl.three_layer, 21, 64, 4, 4, 31, 8),
+    "five_layer": (wl.five_layer, 22, 8, 2, 2, 32, 2),
 }
 
 _G = {}
@@ -53,12 +55,12 @@ def _row(i):
 def main():
     name = sys.argv[1]
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else 1  # up to 35 GB per worker at N = 1,000,000
-    gen, vseed, nrhs, n_near, n_any, rseed = CASES[name]
+    gen, vseed, nrhs, n_near, n_any, rseed, keep = CASES[name]
     w = gen()
     med = Medium(w.d, w.k, w.eta)
     el = Elements(med, w.polygons)
     X = wl.random_vector(el.n, seed=vseed, n_rhs=nrhs)
-    rows = sample_rows(med, el, n_near, n_any, rseed)
+    rows = sample_rows(med, el, n_near, n_any, rseed)[:keep]
     _G.update(med=med, el=el, X=X)
     # finished rows are kept in a scratch file of the system temporary
     # directory, so an interrupted run resumes where it stopped
@@ -78,7 +80,8 @@ def main():
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"fullsize_rows_{name}.txt")
     with open(out, "w") as f:
         f.write(f"# Oracle rows of the layered Nystrom matrix times seeded vectors: workload {w.name} (N={el.n}),\n")
-        f.write(f"# x = workloads.random_vector(N, seed={vseed}, n_rhs={nrhs}); rows drawn by sample_rows(seed={rseed}).\n")
+        f.write(f"# x = workloads.random_vector(N, seed={vseed}, n_rhs={nrhs}); rows drawn by sample_rows({n_near}, {n_any}, "
+                f"seed={rseed}), first {len(rows)} kept.\n")
         f.write("# Written by tests/golden/make_fullsize_rows.py from the oracle alone.\n")
         f.write("# columns: row rhs re im\n")
         for a, i in enumerate(rows):
