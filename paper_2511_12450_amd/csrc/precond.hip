@@ -225,12 +225,16 @@ __global__ void __launch_bounds__(256) k_z_to_h16(const int64_t* __restrict__ rz
 
 // cmax[j] = max |Re|, |Im| of right-hand side j (as FP32 bits; cmax zeroed before).
 __global__ void __launch_bounds__(256) k_h16_colmax(int N, const double2* __restrict__ x, unsigned* __restrict__ cmax) {
-  const int j = blockIdx.y;
-  float m = 0.f;
-  for (int n = blockIdx.x * 2048 + threadIdx.x; n < min(N, (int)(blockIdx.x + 1) * 2048); n += 256) {
-    const double2 v = x[(int64_t)j * N + n];
-    m = fmaxf(m, fmaxf((float)fabs(v.x), (float)fabs(v.y)));
+  const int j = blockIdx.y, n0 = blockIdx.x * 2048 + threadIdx.x;
+  double2 v[8];  // all eight loads in flight before the maxima
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (n0 + 256 * u < N) v[u] = x[(int64_t)j * N + n0 + 256 * u];
+    else v[u] = make_double2(0.0, 0.0);
   }
+  float m = 0.f;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) m = fmaxf(m, fmaxf((float)fabs(v[u].x), (float)fabs(v[u].y)));
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(cmax + j, __float_as_uint(m));
 }
