@@ -121,8 +121,10 @@ lm_status lm_geometry_info(lm_geom geom, int64_t* n_elements, int64_t* device_by
 lm_status lm_geometry_elements(lm_geom geom, double* cx, double* cy, double* w, int32_t* layer);
 lm_status lm_destroy_geometry(lm_geom geom);
 /* Size of the fast-method plan (all zero for LM_DENSE), host output of 10
- * int64: boxes, free-space M2L entries, reaction M2L entries, free-space M2L
- * classes, reaction M2L operators (Sommerfeld tables), reaction near-field
+ * int64: boxes, free-space M2L list entries, reaction M2L list entries (the
+ * lists leave out the coarsest level when its convolution is on),
+ * free-space M2L classes, reaction M2L operators (Sommerfeld tables of the
+ * lists), reaction near-field
  * element pairs, free-space leaf level, reaction finest level, free-space
  * near-field leaf pairs, free-space near-field element pairs. */
 lm_status lm_fmm_stats(lm_geom geom, int64_t* out10);
