@@ -184,3 +184,21 @@ def test_level0_convolution_wide_sparse_rows():
     assert e32 < 1e-4
     on.close()
     off.close()
+
+
+def test_level0_convolution_over_launch_chunks(mini):
+    """More right-hand sides than one launch holds (70 = 64 + 6): the level-0
+    convolution's frequency buffers are reused by the second chunk."""
+    w, _, med, el = mini
+    on = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=1)
+    off = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=-1)
+    x = torch.from_numpy(wl.random_vector(el.n, seed=71, n_rhs=70)).cuda()
+    for precision, dt, bar in ((lmfmm.LM_FP64, torch.complex128, 1e-11), (lmfmm.LM_MIXED, torch.complex64, 1e-5)):
+        xx = x.to(dt)
+        a = on.matvec(xx, precision=precision).cpu().numpy().astype(np.complex128)
+        b = off.matvec(xx, precision=precision).cpu().numpy().astype(np.complex128)
+        errs = [_rel(a[r], b[r]) for r in (0, 63, 64, 69)]
+        print(f"precision {precision}, R=70: convolution vs lists per rhs", [f"{e:.1e}" for e in errs], flush=True)
+        assert max(errs) < bar
+    on.close()
+    off.close()
