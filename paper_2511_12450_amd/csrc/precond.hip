@@ -100,6 +100,7 @@ __global__ void k_pre_store(int q, int nB, const int* __restrict__ J, const doub
 // right-hand sides at a time is staged in LDS (in the arithmetic type), each
 // wavefront takes rows r = wave, wave + 4, ... two at a time, lanes run along
 // the rows (coalesced Z loads), and a wavefront reduction finishes each row.
+constexpr int PA_ROWS_FP64 = 64;  // rows per workgroup of the FP64 apply
 template <typename ZT, typename RT, int RG>
 __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __restrict__ jptr,
                                                    const int* __restrict__ jidx, const int* __restrict__ nb,
@@ -110,6 +111,10 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
   V* xs = reinterpret_cast<V*>(dyn);  // [RG][q]
   const int leaf = blockIdx.x;
   const int j0_ = jptr[leaf], q = jptr[leaf + 1] - j0_, nB = nb[leaf];
+  // rows [r_lo, r_hi) of the subdomain: PA_ROWS per workgroup, so that every
+  // CU has work (a subdomain per workgroup would leave most of them idle)
+  const int r_lo = blockIdx.y * PA_ROWS_FP64, r_hi = min(nB, r_lo + PA_ROWS_FP64);
+  if (r_lo >= nB) return;
   const int* J = jidx + j0_;
   const ZT* Zl = Z + zoff[leaf];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -125,9 +130,9 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
       xs[u * q + j] = t;
     }
     __syncthreads();
-    for (int r = wv; r < nB; r += 8) {
+    for (int r = r_lo + wv; r < r_hi; r += 8) {
       const int r2 = r + 4;
-      const bool two = r2 < nB;
+      const bool two = r2 < r_hi;
       const ZT* z1 = Zl + (int64_t)r * q;
       const ZT* z2 = Zl + (int64_t)(two ? r2 : r) * q;
       RT a1[RG][2], a2[RG][2];
@@ -632,12 +637,12 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
   // FP64: x_J of RG right-hand sides is staged in LDS: RG q sizeof <= 128 KiB
   const bool big = P->qmax > 2048;
   if (big)
-    hipLaunchKernelGGL((k_pre_apply<double2, double, 1>), dim3(P->nleaf), dim3(256),
+    hipLaunchKernelGGL((k_pre_apply<double2, double, 1>), dim3(P->nleaf, div_up(P->bmax, PA_ROWS_FP64)), dim3(256),
                        (size_t)P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
                        P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
                        (const double2*)x, (double2*)y);
   else
-    hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf), dim3(256),
+    hipLaunchKernelGGL((k_pre_apply<double2, double, 2>), dim3(P->nleaf, div_up(P->bmax, PA_ROWS_FP64)), dim3(256),
                        (size_t)2 * P->qmax * sizeof(double2), s, (int)g->N, n_rhs, P->d_jptr.as<int>(),
                        P->d_jidx.as<int>(), P->d_nb.as<int>(), P->d_zoff.as<int64_t>(), P->d_Z.as<double2>(),
                        (const double2*)x, (double2*)y);
