@@ -87,10 +87,11 @@ def test_fmm_vs_dense_full_vector(mini):
     assert err < 1e-6
 
 
-def test_fmm_homogeneous_medium():
+@pytest.mark.parametrize("top_fft", [-1, 1])
+def test_fmm_homogeneous_medium(top_fft):
     w = _straddle()
     w = wl.Workload("homog", w.d, np.array([3.0, 3.0, 3.0]), np.ones(3), w.polygons, w.angles_deg)
-    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0, top_fft=top_fft)
     med = Medium(w.d, w.k, w.eta)
     el = Elements(med, w.polygons)
     K = matrix(med, el)
@@ -99,10 +100,11 @@ def test_fmm_homogeneous_medium():
     assert _rel(y, K @ x) < 1e-6
 
 
-def test_fmm_tiny():
+@pytest.mark.parametrize("top_fft", [-1, 1])
+def test_fmm_tiny(top_fft):
     lay = lmfmm.Layers([0.0], [2.0, 3.0])
     tri = np.array([[0.0, 0.01], [0.3, -0.02], [0.1, 0.2], [-0.2, 0.1]])
-    geo = lmfmm.Geometry(lay, np.array([0, 4]), tri, method=lmfmm.LM_FMM, precond=0)
+    geo = lmfmm.Geometry(lay, np.array([0, 4]), tri, method=lmfmm.LM_FMM, precond=0, top_fft=top_fft)
     med = Medium([0.0], [2.0, 3.0])
     el = Elements(med, [tri])
     K = matrix(med, el)
