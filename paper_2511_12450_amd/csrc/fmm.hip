@@ -2136,9 +2136,30 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   if (pt_mfma)  // complex64 transpose of x, shared by the P2M and the near field
     hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
                        (const float2*)x, F->d_xt.as<float2>());
+  if (n_items) {
+    if (pt_mfma)
+      hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
+                         F->d_p2m_dst.as<int>(), F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(),
+                         F->d_xt.as<float2>(), (float2*)part, (float2*)me);
+    else if (R == 1)
+      hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
+                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
+                         g->d_w.as<double>(), x, N, part);
+    else
+      hipLaunchKernelGGL((k_p2m<RT, 32>), dim3(n_items), dim3(blk), (size_t)32 * R * sizeof(V), s, p, R, nlev,
+                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
+                         g->d_w.as<double>(), x, N, part);
+    if (!pt_mfma)
+      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_leaf.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
+                         F->d_p2m_ptr.as<int>(), (const int*)nullptr, part, me);
+    else if (!F->p2m_msel.empty())  // leaves of one item were written directly
+      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_msel.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
+                         F->d_p2m_ptr.as<int>(), F->d_p2m_msel.as<int>(), part, me);
+  }
   // The near field and self terms only need x: they run on the plan's side
-  // stream, overlapped with P2M .. L2L, and write y first; every L2P launch
-  // then accumulates after the join.
+  // stream, after the P2M (which heads the critical path) and overlapped with
+  // M2M .. L2L, and write y first; every L2P launch then accumulates after
+  // the join.
   LM_TRY_HIP(hipEventRecord(F->ev_fork, s));
   LM_TRY_HIP(hipStreamWaitEvent(F->s_near, F->ev_fork, 0));
   {
@@ -2168,26 +2189,6 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     }
     if (ev) LM_TRY_HIP(hipEventRecord(ev[11], sn));
     LM_TRY_HIP(hipEventRecord(F->ev_join, sn));
-  }
-  if (n_items) {
-    if (pt_mfma)
-      hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
-                         F->d_p2m_dst.as<int>(), F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(),
-                         F->d_xt.as<float2>(), (float2*)part, (float2*)me);
-    else if (R == 1)
-      hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
-                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
-                         g->d_w.as<double>(), x, N, part);
-    else
-      hipLaunchKernelGGL((k_p2m<RT, 32>), dim3(n_items), dim3(blk), (size_t)32 * R * sizeof(V), s, p, R, nlev,
-                         F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
-                         g->d_w.as<double>(), x, N, part);
-    if (!pt_mfma)
-      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_leaf.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
-                         F->d_p2m_ptr.as<int>(), (const int*)nullptr, part, me);
-    else if (!F->p2m_msel.empty())  // leaves of one item were written directly
-      hipLaunchKernelGGL(k_p2m_reduce<RT>, dim3(F->p2m_msel.size()), dim3(blk), 0, s, PR, F->d_p2m_leaf.as<int>(),
-                         F->d_p2m_ptr.as<int>(), F->d_p2m_msel.as<int>(), part, me);
   }
   LM_STAGE(0, 0);
   LM_STAGE(1, 1);
