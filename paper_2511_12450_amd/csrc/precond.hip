@@ -197,6 +197,8 @@ typedef float pf4 __attribute__((ext_vector_type(4)));
 constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZS = 136, PH_XS = 80;  // rows per item; LDS strides
 constexpr int PH_XLD = 64;  // row stride of the split input (right-hand sides)
 constexpr int PH_KSEG = 1024;  // most columns per work item (a multiple of PH_KC)
+constexpr int PH_MAXSEG = 8;    // column ranges of a row block: PRE_QMAX / PH_KSEG
+static_assert(PH_MAXSEG * PH_KSEG >= PRE_QMAX, "slots per row block");
 
 __device__ __forceinline__ uint32_t h16_pack(float re, float im) {
   const _Float16 a = (_Float16)re, b = (_Float16)im;
@@ -430,12 +432,20 @@ __global__ void __launch_bounds__(256) k_pre_h16_sum(int N, int R, const int* __
     for (int idx = threadIdx.x; idx < rows * 16; idx += blockDim.x) {
       const int r = idx >> 4, jj = idx & 15;
       double re = 0.0, im = 0.0;
-      if (jh + jj < R)
-        for (int k = 0; k < ns; ++k) {
-          const float2 v = part[((int64_t)(slot0 + k) * PH_ROWS + r) * PH_XLD + jh + jj];
-          re += v.x;
-          im += v.y;
-        }
+      if (jh + jj < R) {
+        // a row block has at most PH_MAXSEG slots; all loads of a pass are
+        // issued before the sums (added in slot order)
+        float2 v[PH_MAXSEG];
+#pragma unroll
+        for (int k = 0; k < PH_MAXSEG; ++k)  // clamped addresses (ns >= 1); extra slots are dropped below
+          v[k] = part[((int64_t)(slot0 + min(k, ns - 1)) * PH_ROWS + r) * PH_XLD + jh + jj];
+#pragma unroll
+        for (int k = 0; k < PH_MAXSEG; ++k)
+          if (k < ns) {
+            re += v[k].x;
+            im += v[k].y;
+          }
+      }
       T[jj][r] = make_double2(re, im);
     }
     __syncthreads();
