@@ -350,7 +350,18 @@ __global__ void __launch_bounds__(256) k_p2m_reduce(int PR, const int* __restric
   V* out = me + (int64_t)leaves[k] * PR;
   for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) {
     RT re = 0, im = 0;
-    for (int i = i0; i < i1; ++i) {
+    int i = i0;
+    for (; i + 4 <= i1; i += 4) {  // four partial loads in flight, summed in order
+      V v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)(i + u) * PR + idx];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        re += v[u].x;
+        im += v[u].y;
+      }
+    }
+    for (; i < i1; ++i) {
       const V v = part[(int64_t)i * PR + idx];
       re += v.x;
       im += v.y;
