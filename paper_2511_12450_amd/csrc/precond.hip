@@ -230,20 +230,27 @@ __global__ void __launch_bounds__(256) k_z_to_h16(const int64_t* __restrict__ rz
   if (threadIdx.x == 0) rsc[r] = (float)ldexp(1.0, e);
 }
 
-// cmax[j] = max |Re|, |Im| of right-hand side j (as FP32 bits; cmax zeroed before).
+// cmax[j] = max |Re|, |Im| of right-hand side j (as FP32 bits; cmax zeroed before):
+// H16_CM elements per workgroup, one atomic per workgroup.
+constexpr int H16_CM = 8192;
 __global__ void __launch_bounds__(256) k_h16_colmax(int N, const double2* __restrict__ x, unsigned* __restrict__ cmax) {
-  const int j = blockIdx.y, n0 = blockIdx.x * 2048 + threadIdx.x;
-  double2 v[8];  // all eight loads in flight before the maxima
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    if (n0 + 256 * u < N) v[u] = x[(int64_t)j * N + n0 + 256 * u];
-    else v[u] = make_double2(0.0, 0.0);
-  }
+  const int j = blockIdx.y;
   float m = 0.f;
+  for (int n0 = blockIdx.x * H16_CM + threadIdx.x; n0 < min(N, (int)(blockIdx.x + 1) * H16_CM); n0 += 2048) {
+    double2 v[8];  // eight loads in flight before the maxima
 #pragma unroll
-  for (int u = 0; u < 8; ++u) m = fmaxf(m, fmaxf((float)fabs(v[u].x), (float)fabs(v[u].y)));
+    for (int u = 0; u < 8; ++u) {
+      if (n0 + 256 * u < N) v[u] = x[(int64_t)j * N + n0 + 256 * u];
+      else v[u] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmaxf(m, fmaxf((float)fabs(v[u].x), (float)fabs(v[u].y)));
+  }
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(cmax + j, __float_as_uint(m));
+  __shared__ float wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(cmax + j, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
 }
 
 // v where keep, else zeros (component selects: no select between addresses)
@@ -628,7 +635,7 @@ lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, v
       const int R = std::min(64, n_rhs - r0);
       const double2* xr = (const double2*)x + (int64_t)r0 * N;
       LM_TRY_HIP(hipMemsetAsync(P->d_cmax.p, 0, (size_t)R * sizeof(unsigned), s));
-      hipLaunchKernelGGL(k_h16_colmax, dim3(div_up(N, 2048), R), dim3(256), 0, s, N, xr, P->d_cmax.as<unsigned>());
+      hipLaunchKernelGGL(k_h16_colmax, dim3(div_up(N, H16_CM), R), dim3(256), 0, s, N, xr, P->d_cmax.as<unsigned>());
       hipLaunchKernelGGL(k_h16_split, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R, xr,
                          P->d_cmax.as<unsigned>(), P->d_xh.as<uint32_t>(), P->d_xl.as<uint32_t>());
       hipLaunchKernelGGL(k_pre_h16, dim3(P->items.size() / 5), dim3(512), 0, s, R, P->d_items.as<int>(),
