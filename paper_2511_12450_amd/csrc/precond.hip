@@ -100,7 +100,7 @@ __global__ void k_pre_store(int q, int nB, const int* __restrict__ J, const doub
 // right-hand sides at a time is staged in LDS (in the arithmetic type), each
 // wavefront takes rows r = wave, wave + 4, ... two at a time, lanes run along
 // the rows (coalesced Z loads), and a wavefront reduction finishes each row.
-constexpr int PA_ROWS_FP64 = 64;  // rows per workgroup of the FP64 apply
+constexpr int PA_ROWS_FP64 = 32;  // rows per workgroup of the FP64 apply
 template <typename ZT, typename RT, int RG>
 __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __restrict__ jptr,
                                                    const int* __restrict__ jidx, const int* __restrict__ nb,
