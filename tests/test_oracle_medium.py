@@ -9,7 +9,7 @@ recursions of Sec. 3.1 fails here.
 import numpy as np
 import pytest
 
-from oracle.incident import background, background_amplitudes, incident
+from oracle.incident import background, background_amplitudes, boundary_data, incident
 from oracle.medium import Medium, nonzero_components
 
 MEDIA = [
@@ -189,3 +189,81 @@ def test_background_field_transmission_conditions(mi, theta_deg):
     y0 = 0.5 - med.d[0]
     assert np.allclose(background(med, th, [x], [y0])[0], A[0] * np.exp(1j * (kx * x + ky[0] * y0)))
     assert np.allclose(incident(med, th, [x], [y0])[0], np.exp(1j * (kx * x - k0y * y0)))
+
+
+def _d_dy(f, y, h, sgn):
+    """One-sided fourth-order derivative of f at y from samples y + sgn j h,
+    j = 0..4 (all on one side of an interface)."""
+    c = np.array([-25.0, 48.0, -36.0, 16.0, -3.0]) / 12.0
+    return sum(c[j] * f(y + sgn * j * h) for j in range(5)) / (sgn * h)
+
+
+@pytest.mark.parametrize("mi", range(len(MEDIA)))
+@pytest.mark.parametrize("theta_deg", [20.0, 75.0, 90.0, 135.0])
+def test_field_helpers_in_every_layer(mi, theta_deg):
+    """incident(), background() and boundary_data() themselves, in every layer
+    (Sec. 2.2, eqs. incidentwave, TLhelmholtztotallayer2, homogeneousscattering):
+
+    * at interior points of every layer, u^inc + u^b equals the field of the
+      amplitudes obtained by solving all interface conditions at once
+      (independent of the recursions), and u^inc vanishes below layer 0;
+    * just above and just below every interface (+-1e-9), u^inc + u^b and
+      eta d/dy(u^inc + u^b) agree, the derivatives taken by one-sided finite
+      differences of the helpers' values inside each layer;
+    * background(dy=True) equals the finite-difference derivative of
+      background() inside each layer;
+    * boundary_data = -(u^inc + u^b)."""
+    med = MEDIA[mi]
+    th = np.radians(theta_deg)
+    kx = med.k[0] * np.cos(th)
+    up, dn = _stack_solve_from_above(med, kx)
+    ky = med.ky(np.array([kx], dtype=complex))[:, 0]
+    xs = np.array([-1.3, 0.37, 2.9])
+
+    def total(x, y):
+        return incident(med, th, x, y) + background(med, th, x, y)
+
+    # interior points of every layer (the outer layers sampled 0.2 and 1.1 away)
+    tops = [None] + [-med.d[l] for l in range(med.L)]
+    bots = [-med.d[l] for l in range(med.L)] + [None]
+    for l in range(med.L + 1):
+        if tops[l] is None:
+            ys = [bots[l] + 0.2, bots[l] + 1.1]
+        elif bots[l] is None:
+            ys = [tops[l] - 0.2, tops[l] - 1.1]
+        else:
+            h = tops[l] - bots[l]
+            ys = [bots[l] + 0.25 * h, bots[l] + 0.7 * h]
+        for y in ys:
+            yy = np.full(xs.shape, y)
+            assert np.all(med.layer_of(yy) == l)
+            ref = up[l] * np.exp(1j * (kx * xs + ky[l] * y)) + dn[l] * np.exp(1j * (kx * xs - ky[l] * y))
+            got = total(xs, yy)
+            assert np.allclose(got, ref, rtol=1e-11, atol=1e-12), (l, y)
+            inc = incident(med, th, xs, yy)
+            if l == 0:
+                assert np.allclose(inc, np.exp(1j * (kx * xs - med.k[0] * np.sin(th) * y)), rtol=1e-14)
+            else:
+                assert np.all(inc == 0), (l, y)
+            assert np.allclose(boundary_data(med, th, xs, yy), -got, rtol=1e-14, atol=0)
+            hh = 1e-3
+            for sgn in (1.0, -1.0):
+                fd = _d_dy(lambda t: background(med, th, xs, np.full(xs.shape, t)), y, hh, sgn)
+                _, dub = background(med, th, xs, yy, dy=True)
+                assert np.allclose(dub, fd, rtol=1e-7, atol=1e-8 * med.k.max()), (l, y)
+
+    # across every interface, from the helpers' values on each side
+    eps, hh = 1e-9, 1e-3
+    for m in range(med.L):
+        yi = -med.d[m]
+        ya, yb = yi + eps, yi - eps
+        assert np.all(med.layer_of(np.full(xs.shape, ya)) == m)
+        assert np.all(med.layer_of(np.full(xs.shape, yb)) == m + 1)
+        ua, ub_ = total(xs, np.full(xs.shape, ya)), total(xs, np.full(xs.shape, yb))
+        assert np.allclose(ua, ub_, rtol=1e-7, atol=1e-8), m
+        da = _d_dy(lambda t: total(xs, np.full(xs.shape, t)), ya, hh, 1.0)
+        db = _d_dy(lambda t: total(xs, np.full(xs.shape, t)), yb, hh, -1.0)
+        scale = med.k.max() * max(1.0, np.abs(ua).max())
+        assert np.allclose(med.eta[m] * da, med.eta[m + 1] * db, rtol=0, atol=1e-6 * scale * med.eta.max()), m
+        if m == 0:
+            assert np.all(incident(med, th, xs, np.full(xs.shape, yb)) == 0)
