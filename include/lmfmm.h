@@ -150,6 +150,22 @@ lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, v
  * must not overlap.  LM_EINVAL when the geometry has no preconditioner. */
 lm_status lm_precond_apply(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev, void* hip_stream);
 
+/* The subdomains of the preconditioner (Sec. 4.2: a box B of a layer's
+ * free-space tree, its own elements and the elements of B and its neighbour
+ * boxes) as integer lists, host outputs.
+ * info4_host (required): 4 int64 = number of subdomains S, tree level of the
+ *   subdomain boxes (0 = the coarsest), total length of the neighbourhood
+ *   lists, leaf level of the free-space trees.
+ * jptr_host (S+1 int32), nb_host (S int32), jidx_host (info4[2] int32), each
+ *   written when non-NULL (call once with NULLs to size them): the
+ *   neighbourhood of subdomain b is jidx[jptr[b] .. jptr[b+1]) (element
+ *   indices in input numbering); its first nb[b] entries are the elements of
+ *   B itself, the rows of P_B^{-1} the preconditioner keeps, the rest those of
+ *   the neighbour boxes.  Subdomains are ordered by (layer, column, row).
+ * Errors: LM_EINVAL when the geometry has no preconditioner. */
+lm_status lm_precond_subdomains(lm_geom geom, int64_t* info4_host, int32_t* jptr_host, int32_t* nb_host,
+                                int32_t* jidx_host);
+
 /* Runs reps FMM matvecs (as lm_matvec) and returns in out9_host the average
  * duration in ms of each stage, measured with HIP events recorded on
  * hip_stream around the stage's kernels: [0] P2M, [1] M2M, [2] M2L lists

@@ -212,6 +212,11 @@ extern "C" lm_status lm_precond_apply(lm_geom g, int precision, int n_rhs, const
   return precond_apply(g, precision, n_rhs, x, y, (hipStream_t)hip_stream);
 }
 
+extern "C" lm_status lm_precond_subdomains(lm_geom g, int64_t* info4, int32_t* jptr, int32_t* nb, int32_t* jidx) {
+  LM_CHECK(g && info4, LM_EINVAL, "bad arguments");
+  return precond_subdomains(g, info4, jptr, nb, jidx);
+}
+
 extern "C" lm_status lm_matvec_stage_times(lm_geom g, int precision, int n_rhs, const void* x, void* y, int reps,
                                            void* hip_stream, double* out9) {
   LM_CHECK(g && out9 && reps >= 1, LM_EINVAL, "bad arguments");

@@ -133,5 +133,6 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s);
 void precond_free(Precond* p);
 int64_t precond_bytes(const Precond* p);
 lm_status precond_apply(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, hipStream_t s);
+lm_status precond_subdomains(const lm_geom_s* g, int64_t* info4, int32_t* jptr, int32_t* nb, int32_t* jidx);
 
 inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }

@@ -31,6 +31,7 @@ constexpr int PRE_QMAX = 8192;  // largest subdomain neighbourhood (LU workspace
 
 struct Precond {
   int nleaf = 0, qmax = 0, bmax = 0;
+  int level = 0, leaf_level = 0;  // tree level of the subdomain boxes; leaf level of the free-space trees
   std::vector<int> jptr, jidx, nb;
   std::vector<int64_t> zoff, rowoff, zhoff;  // zhoff: binary16 blocks (row stride q rounded up to 4)
   // FP32-form apply: work items (subdomain, first row, first column, column
@@ -477,6 +478,8 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
   // subdomains: free-tree boxes at level lp; each owns the points of its
   // leaves; neighbourhood = the subdomain and its (up to 8) level-lp neighbours
   auto plan = [&](int lp) {
+    P->level = lp;
+    P->leaf_level = F->lf;
     P->jptr.assign(1, 0);
     P->jidx.clear();
     P->nb.clear();
@@ -619,6 +622,19 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
   }
+  return LM_OK;
+}
+
+lm_status precond_subdomains(const lm_geom_s* g, int64_t* info4, int32_t* jptr, int32_t* nb, int32_t* jidx) {
+  const Precond* P = g->pre;
+  LM_CHECK(P, LM_EINVAL, "the geometry has no preconditioner");
+  info4[0] = P->nleaf;
+  info4[1] = P->level;
+  info4[2] = (int64_t)P->jidx.size();
+  info4[3] = P->leaf_level;
+  if (jptr) std::copy(P->jptr.begin(), P->jptr.end(), jptr);
+  if (nb) std::copy(P->nb.begin(), P->nb.end(), nb);
+  if (jidx) std::copy(P->jidx.begin(), P->jidx.end(), jidx);
   return LM_OK;
 }
 

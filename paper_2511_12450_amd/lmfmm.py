@@ -69,6 +69,8 @@ _SIGS = {
     "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
     "lm_precond_apply": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
+    "lm_precond_subdomains": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _ip),
     "lm_matvec_stage_times": ([_vp, _ip, _ip, _vp, _vp, _ip, _vp, _dp], _ip),
     "lm_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
     "lm_gmres_solve": ([_vp, _ip, _ip, _dp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp], _ip),
@@ -220,6 +222,22 @@ class Geometry:
             y = torch.empty_like(x)
         _check(lib().lm_precond_apply(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
         return y
+
+    def precond_subdomains(self):
+        """(level, leaf level, [(own elements, neighbourhood elements)]) of
+        the preconditioner (lm_precond_subdomains)."""
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        info = np.zeros(4, dtype=np.int64)
+        _check(lib().lm_precond_subdomains(self.h, info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None, None,
+                                           None))
+        S, lev, nj, lf = (int(v) for v in info)
+        jptr = np.zeros(S + 1, dtype=np.int32)
+        nb = np.zeros(S, dtype=np.int32)
+        jidx = np.zeros(max(nj, 1), dtype=np.int32)
+        _check(lib().lm_precond_subdomains(self.h, info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           jptr.ctypes.data_as(i32), nb.ctypes.data_as(i32), jidx.ctypes.data_as(i32)))
+        subs = [(jidx[jptr[b]:jptr[b] + nb[b]].copy(), jidx[jptr[b]:jptr[b + 1]].copy()) for b in range(S)]
+        return lev, lf, subs
 
     def stage_times(self, x, y, reps=10, precision=LM_FP64):
         """Average ms per FMM stage from HIP events inside the library: P2M,
