@@ -140,6 +140,24 @@ lm_status lm_fmm_stats(lm_geom geom, int64_t* out10);
 lm_status lm_matvec(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev,
                     void* hip_stream);
 
+/* lm_matvec for callers that cannot allocate device memory (code under
+ * stream capture, serving loops or harnesses that forbid hipMalloc): the same
+ * operator, arguments and errors as lm_matvec, with the FMM's per-launch
+ * workspace (expansions, partial sums, level-0 transforms, the complex64
+ * transpose of x) in a static device array of LM_NOALLOC_SCRATCH_BYTES that
+ * every GPU the library runs on holds until the process ends, instead of
+ * buffers the library allocates.  It calls no hipMalloc / hipFree and no
+ * allocating library routine.  The right-hand sides are processed in chunks
+ * of as many as the array holds (at most 64); LM_EINVAL when it cannot hold
+ * the workspace of one right-hand side (then use lm_matvec).  A dense
+ * geometry needs no workspace.  Every call on a device shares that device's
+ * array: calls that overlap on one device (any streams, any geometries) race
+ * and must be serialised by the caller; calls on one geometry also share its
+ * side stream, as with lm_matvec. */
+#define LM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+lm_status lm_matvec_noalloc(lm_geom geom, int precision, int n_rhs, const void* x_dev, void* y_dev,
+                            void* hip_stream);
+
 /* y = M x for n_rhs vectors: M = P^{-1} = sum_B S_B Q_B P_B^{-1} R_B, the
  * overlapping domain-decomposition preconditioner of Sec. 4.2 (built by
  * lm_geometry_create with precond != 0), the operator GMRES applies on the

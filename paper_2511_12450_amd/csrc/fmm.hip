@@ -2049,7 +2049,6 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_mf_ptr, F->mf_ptr, s));
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
-  LM_TRY(F->d_m2l_out.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * sizeof(double2)));
   // point matrices of the matrix-core P2M / L2P
   {
     const size_t npt = std::max<size_t>(F->pt_elem.size(), 1) * F->P * sizeof(float2);
@@ -2092,27 +2091,64 @@ int64_t fmm_ws_per_rhs(const FmmPlan* F) {
   return (int64_t)F->P * 16 * (2 * (int64_t)F->n_boxes + F->item_ptr[3]) + (int64_t)F->P * 8 * (F->mf_item.size() / 3);
 }
 
+// Per-launch workspace of r right-hand sides: byte sizes of the buffers
+// (expansions, P2M partial sums, level-0 transforms, per-entry M2L results,
+// the complex64 transpose of x).
+void fmm_ws_sizes(const FmmPlan* F, int r, size_t sz[FMM_WS_N]) {
+  r = std::min(std::max(r, 1), LM_RCHUNK);
+  const size_t P = F->P;
+  sz[FMM_WS_ME] = sz[FMM_WS_LE] = (size_t)F->n_boxes * P * r * sizeof(double2);
+  sz[FMM_WS_PART] = (size_t)std::max(F->item_ptr[3], 1) * P * r * sizeof(double2);
+  sz[FMM_WS_TOP_MH] = sz[FMM_WS_TOP_LH] =
+      F->top_on ? (size_t)F->top_rows * F->top_L * P * r * sizeof(double2) : 0;
+  sz[FMM_WS_M2L_OUT] = std::max<size_t>(F->m2l_src.size(), 1) * P * sizeof(double2);
+  sz[FMM_WS_OM_SLOT] = r > 1 ? std::max<size_t>(F->m2l_src.size(), 1) * P * std::min(r, OM_RMAX) * sizeof(float2) : 0;
+  sz[FMM_WS_MF_PART] = r > 1 ? std::max<size_t>(F->mf_item.size() / 3, 1) * P * r * sizeof(float2) : 0;
+  sz[FMM_WS_XT] = r > 1 ? (size_t)std::max<int64_t>(F->n_el, 1) * r * sizeof(float2) : 0;
+}
+
+// Bytes of one contiguous workspace of r right-hand sides (every buffer
+// starting at a 256-byte boundary).
+size_t fmm_ws_bytes(const FmmPlan* F, int r) {
+  size_t sz[FMM_WS_N], t = 0;
+  fmm_ws_sizes(F, r, sz);
+  for (int i = 0; i < FMM_WS_N; ++i) t += (sz[i] + 255) & ~(size_t)255;
+  return t;
+}
+
+// The workspace carved from one device region of at least fmm_ws_bytes.
+FmmWs fmm_ws_carve(const FmmPlan* F, int r, void* base) {
+  size_t sz[FMM_WS_N], off = 0;
+  fmm_ws_sizes(F, r, sz);
+  FmmWs w;
+  for (int i = 0; i < FMM_WS_N; ++i) {
+    w.p[i] = sz[i] ? (char*)base + off : nullptr;
+    off += (sz[i] + 255) & ~(size_t)255;
+  }
+  return w;
+}
+
 // Expansion buffers for r right-hand sides per launch (grown on demand).
 lm_status fmm_reserve(FmmPlan* F, int r) {
   r = std::min(std::max(r, 1), LM_RCHUNK);
   if (r <= F->r_cap) return LM_OK;
-  const size_t bytes = (size_t)F->n_boxes * F->P * r * sizeof(double2);
-  LM_TRY(F->d_me.alloc(bytes));
-  LM_TRY(F->d_le.alloc(bytes));
-  LM_TRY(F->d_p2m_part.alloc((size_t)std::max(F->item_ptr[3], 1) * F->P * r * sizeof(double2)));
-  if (F->top_on) {
-    const size_t tb = (size_t)F->top_rows * F->top_L * F->P * r * sizeof(double2);
-    LM_TRY(F->d_top_mh.alloc(tb));
-    LM_TRY(F->d_top_lh.alloc(tb));
-  }
-  if (r > 1) {
-    LM_TRY(F->d_om_slot.alloc(std::max<size_t>(F->m2l_src.size(), 1) * F->P * std::min(r, OM_RMAX) *
-                              sizeof(float2)));
-    LM_TRY(F->d_mf_part.alloc(std::max<size_t>(F->mf_item.size() / 3, 1) * F->P * r * sizeof(float2)));
-    LM_TRY(F->d_xt.alloc((size_t)std::max<int64_t>(F->n_el, 1) * r * sizeof(float2)));
-  }
+  size_t sz[FMM_WS_N];
+  fmm_ws_sizes(F, r, sz);
+  DevBuf* bufs[FMM_WS_N] = {&F->d_me, &F->d_le, &F->d_p2m_part, &F->d_top_mh, &F->d_top_lh,
+                            &F->d_m2l_out, &F->d_om_slot, &F->d_mf_part, &F->d_xt};
+  for (int i = 0; i < FMM_WS_N; ++i)
+    if (sz[i] > bufs[i]->bytes) LM_TRY(bufs[i]->alloc(sz[i]));
   F->r_cap = r;
   return LM_OK;
+}
+
+// The plan's own workspace (after fmm_reserve).
+static FmmWs fmm_ws_own(FmmPlan* F) {
+  FmmWs w;
+  DevBuf* bufs[FMM_WS_N] = {&F->d_me, &F->d_le, &F->d_p2m_part, &F->d_top_mh, &F->d_top_lh,
+                            &F->d_m2l_out, &F->d_om_slot, &F->d_mf_part, &F->d_xt};
+  for (int i = 0; i < FMM_WS_N; ++i) w.p[i] = bufs[i]->p;
+  return w;
 }
 
 namespace {
@@ -2122,8 +2158,8 @@ namespace {
 // 1 M2M, 2 M2L lists, 3 L2L, 4 L2P, 5 near field (side stream), 6 M2L
 // partial sums, 7 level-0 convolution).
 template <typename RT>
-lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typename C2T<RT>::T* y, hipStream_t s,
-                       hipEvent_t* ev) {
+lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typename C2T<RT>::T* y, const FmmWs& ws,
+                       hipStream_t s, hipEvent_t* ev) {
   typedef typename C2T<RT>::T V;
   FmmPlan* F = g->fmm;
   const int N = (int)g->N, p = F->p, P = F->P, PR = P * R, nlev = F->nlev;
@@ -2133,8 +2169,8 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   const V* ops = sizeof(RT) == 8 ? (const V*)F->d_ops64.p : (const V*)F->d_ops32.p;
   const V* nmv = sizeof(RT) == 8 ? (const V*)F->d_nm_val.p : (const V*)F->d_nm_val32.p;
   const size_t PP = (size_t)P * P;
-  V* me = (V*)F->d_me.p;
-  V* le = (V*)F->d_le.p;
+  V* me = (V*)ws.p[FMM_WS_ME];
+  V* le = (V*)ws.p[FMM_WS_LE];
   const int blk = std::min(256, 64 * (int)div_up(PR, 64));
   const size_t lds_pr = (size_t)PR * sizeof(V);
 #define LM_STAGE(i, open) \
@@ -2142,16 +2178,16 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   LM_STAGE(0, 1);
   // P2M on every leaf (leaves of all trees; internal boxes come from M2M)
   const int n_items = F->item_ptr[3];
-  V* part = (V*)F->d_p2m_part.p;
+  V* part = (V*)ws.p[FMM_WS_PART];
   const bool pt_mfma = sizeof(RT) == 4 && R > 1;  // FP32 multi-RHS: point steps on matrix cores
   if (pt_mfma)  // complex64 transpose of x, shared by the P2M and the near field
     hipLaunchKernelGGL(k_to_nr<float2>, dim3(div_up(N, 32), div_up(R, 32)), dim3(32, 8), 0, s, N, R,
-                       (const float2*)x, F->d_xt.as<float2>());
+                       (const float2*)x, (float2*)ws.p[FMM_WS_XT]);
   if (n_items) {
     if (pt_mfma)
       hipLaunchKernelGGL(k_p2m_mfma, dim3(n_items), dim3(64 * PA_NW), 0, s, p, R, F->d_pt_item.as<int>(),
                          F->d_p2m_dst.as<int>(), F->d_pt_elem.as<int>(), F->d_p2m_Z32.as<float2>(),
-                         F->d_xt.as<float2>(), (float2*)part, (float2*)me);
+                         (float2*)ws.p[FMM_WS_XT], (float2*)part, (float2*)me);
     else if (R == 1)
       hipLaunchKernelGGL((k_p2m<RT, 64>), dim3(n_items), dim3(blk), (size_t)64 * R * sizeof(V), s, p, R, nlev,
                          F->d_pt_item.as<int>(), boxes, tl, sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(),
@@ -2186,7 +2222,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
         hipLaunchKernelGGL((k_block_mfma<float2, false>), dim3(F->nb_item.size() / 2), dim3(64 * PA_NW), 0, sn, N,
                            R, F->d_nb_item.as<int>(), F->d_nb_jptr.as<int>(), F->d_nb_jidx.as<int>(),
                            F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(), F->d_nb_Z32.as<float2>(),
-                           F->d_xt.as<float2>(), (float2*)y);
+                           (float2*)ws.p[FMM_WS_XT], (float2*)y);
       if (!F->rn_src.empty())
         hipLaunchKernelGGL((k_near_csr<float, 8>), dim3(div_up(F->rn_rows.size(), 4)), dim3(256), 0, sn, N,
                            (int)F->rn_rows.size(), F->d_rn_rows.as<int>(), R, 1, F->d_rn_ptr.as<int>(),
@@ -2233,8 +2269,8 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     const int lgc = top_lgc(lgL, sizeof(V));
     const dim3 tg((unsigned)div_up(PR, 1 << lgc), (unsigned)nrow);
     const size_t tlds = ((size_t)L << lgc) * sizeof(V);
-    V* mh = (V*)F->d_top_mh.p;
-    V* lh = (V*)F->d_top_lh.p;
+    V* mh = (V*)ws.p[FMM_WS_TOP_MH];
+    V* lh = (V*)ws.p[FMM_WS_TOP_LH];
     const V* tw = sizeof(RT) == 8 ? (const V*)F->d_top_tw64.p : (const V*)F->d_top_tw32.p;
     const V* tops = sizeof(RT) == 8 ? (const V*)F->d_top_T64.p : (const V*)F->d_top_T32.p;
     hipLaunchKernelGGL(k_top_fwd<V>, tg, dim3(256), tlds, s, lgL, lgc, nx, PR, F->d_top_grid.as<int>(),
@@ -2255,7 +2291,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
   if (!F->m2l_tgt.empty()) {
     const V* mops = ops + (size_t)F->op_m2l * PP;
     if (R == 1) {
-      V* out = (V*)F->d_m2l_out.p;
+      V* out = (V*)ws.p[FMM_WS_M2L_OUT];
       hipLaunchKernelGGL(k_m2l_apply<RT>, dim3(F->tm_item.size() / 3), dim3(64), 0, s, p, F->d_tm_item.as<int>(),
                          F->d_tm_slot.as<int>(), F->d_tm_src.as<int>(), mops, me, out);
       LM_STAGE(2, 0);
@@ -2265,7 +2301,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       LM_STAGE(6, 0);
     } else if (sizeof(RT) == 4 && R <= OM_RMAX) {
       // few right-hand sides: operator-major, one operator staged per item
-      float2* slots = F->d_om_slot.as<float2>();
+      float2* slots = (float2*)ws.p[FMM_WS_OM_SLOT];
       const size_t lds = mf_lds_bytes(P, (64 / R) * R);
       if ((P + 15) / 16 > MF_TR)
         hipLaunchKernelGGL(k_m2l_om<2>, dim3(F->tm_item.size() / 3), dim3(512), lds, s, p, R,
@@ -2281,7 +2317,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
                          F->d_m2l_ptr.as<int>(), (const int*)nullptr, slots, (float2*)le);
       LM_STAGE(6, 0);
     } else if (sizeof(RT) == 4) {
-      float2* mpart = F->d_mf_part.as<float2>();
+      float2* mpart = (float2*)ws.p[FMM_WS_MF_PART];
       m2l_mfma_launch<MF_LIST>((int)(F->mf_item.size() / 3), p, R, F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(),
                                F->d_m2l_op.as<int>(), (const float2*)mops, (const float2*)me, mpart,
                                (const int*)nullptr, 0, s);
@@ -2344,22 +2380,46 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
 
 }  // namespace
 
+// Matvec in chunks of at most rc right-hand sides on the workspace ws
+// (holding rc right-hand sides).
+static lm_status matvec_chunks(lm_geom_s* g, int precision, int n_rhs, int rc, const void* xv, void* yv,
+                               const FmmWs& ws, hipStream_t s, hipEvent_t* ev) {
+  const int64_t N = g->N;
+  for (int r0 = 0; r0 < n_rhs; r0 += rc) {
+    const int R = std::min(rc, n_rhs - r0);
+    hipEvent_t* e = r0 == 0 ? ev : nullptr;
+    if (precision == LM_FP64) {
+      LM_TRY(matvec_chunk<double>(g, R, (const double2*)xv + r0 * N, (double2*)yv + r0 * N, ws, s, e));
+    } else {
+      LM_TRY(matvec_chunk<float>(g, R, (const float2*)xv + r0 * N, (float2*)yv + r0 * N, ws, s, e));
+    }
+  }
+  return LM_OK;
+}
+
 lm_status fmm_matvec_timed(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s,
                            hipEvent_t* ev) {
   FmmPlan* F = g->fmm;
   LM_CHECK(F, LM_EINTERNAL, "no FMM plan");
-  const int64_t N = g->N;
   LM_TRY(fmm_reserve(F, n_rhs));
-  for (int r0 = 0; r0 < n_rhs; r0 += LM_RCHUNK) {
-    const int R = std::min(LM_RCHUNK, n_rhs - r0);
-    hipEvent_t* e = r0 == 0 ? ev : nullptr;
-    if (precision == LM_FP64) {
-      LM_TRY(matvec_chunk<double>(g, R, (const double2*)xv + r0 * N, (double2*)yv + r0 * N, s, e));
-    } else {
-      LM_TRY(matvec_chunk<float>(g, R, (const float2*)xv + r0 * N, (float2*)yv + r0 * N, s, e));
-    }
-  }
-  return LM_OK;
+  return matvec_chunks(g, precision, n_rhs, LM_RCHUNK, xv, yv, fmm_ws_own(F), s, ev);
+}
+
+// Matvec whose workspace is the caller's region [base, base + cap): no
+// device allocation.  Chunks of as many right-hand sides as the region holds
+// (at most LM_RCHUNK); LM_EINVAL when it cannot hold one.
+lm_status fmm_matvec_in(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, void* base, size_t cap,
+                        hipStream_t s) {
+  FmmPlan* F = g->fmm;
+  LM_CHECK(F, LM_EINTERNAL, "no FMM plan");
+  int rc = std::min(n_rhs, LM_RCHUNK);
+  while (rc > 1 && fmm_ws_bytes(F, rc) > cap) --rc;
+  const size_t need = fmm_ws_bytes(F, rc);
+  LM_CHECK(need <= cap, LM_EINVAL,
+           "the matvec workspace of this geometry (%zu bytes for one right-hand side) exceeds the %zu-byte static "
+           "scratch; use lm_matvec",
+           need, cap);
+  return matvec_chunks(g, precision, n_rhs, rc, xv, yv, fmm_ws_carve(F, rc, base), s, nullptr);
 }
 
 lm_status fmm_matvec(lm_geom_s* g, int precision, int n_rhs, const void* xv, void* yv, hipStream_t s) {

@@ -119,6 +119,19 @@ int64_t fmm_ws_per_rhs(const FmmPlan* f);
 lm_status gmres_run(lm_geom_s* g, int precision, int n_rhs, const void* g_dev, const lm_gmres_opts* o,
                     void* phi_dev, lm_solve_report* rep, hipStream_t s);
 
+// Per-launch workspace of the FMM matvec: expansions, P2M partial sums,
+// level-0 transforms, per-entry M2L results, the complex64 transpose of x.
+enum {
+  FMM_WS_ME, FMM_WS_LE, FMM_WS_PART, FMM_WS_TOP_MH, FMM_WS_TOP_LH, FMM_WS_M2L_OUT, FMM_WS_OM_SLOT,
+  FMM_WS_MF_PART, FMM_WS_XT, FMM_WS_N
+};
+struct FmmWs {
+  void* p[FMM_WS_N] = {};
+};
+size_t fmm_ws_bytes(const FmmPlan* f, int r);
+lm_status fmm_matvec_in(lm_geom_s* g, int precision, int n_rhs, const void* x, void* y, void* base, size_t cap,
+                        hipStream_t s);
+
 lm_status fmm_build(lm_geom_s* g, hipStream_t s);
 void fmm_free(FmmPlan* f);
 int64_t fmm_bytes(const FmmPlan* f);

@@ -68,6 +68,7 @@ _SIGS = {
     "lm_destroy_geometry": ([_vp], _ip),
     "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
+    "lm_matvec_noalloc": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
     "lm_precond_apply": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
     "lm_precond_subdomains": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _ip),
@@ -211,6 +212,17 @@ class Geometry:
         if y is None:
             y = torch.empty_like(x)
         _check(lib().lm_matvec(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
+        return y
+
+    def matvec_noalloc(self, x, y, precision=LM_FP64):
+        """y = K x through lm_matvec_noalloc (workspace in the library's
+        static device array; y must be given)."""
+        import torch
+        dt = torch.complex128 if precision == LM_FP64 else torch.complex64
+        x = x.reshape(-1, self.n)
+        assert x.dtype == dt and x.is_cuda and x.is_contiguous()
+        assert y.dtype == dt and y.is_cuda and y.is_contiguous() and y.numel() == x.numel()
+        _check(lib().lm_matvec_noalloc(self.h, precision, x.shape[0], _tptr(x), _tptr(y), _stream()))
         return y
 
     def precond_apply(self, x, y=None, precision=LM_FP64):
