@@ -14,11 +14,15 @@ preconditioner) are built once and stay resident in HBM.
   submitted at once as 16 requests of 4 angles (each request also asks for
   the 682-angle far field); the server fuses them into multi-right-hand-side
   launches.  solves/s = angles / wall time of the batch; latency = per
-  request, submission to completion.
+  request, submission to completion.  The same batch is also served with the
+  preconditioner applied from its FP64 rows instead of the binary16 copy.
+* latency under load: an open-loop Poisson stream on the same geometry, and
+  a stream over a pool of seeded geometries of 2-4 layers (different media
+  and sizes, 1-16 angles per request, admission by HBM footprint).
 
-Both forms are checked against a tight FP64 reference (tol 1e-9, computed
-outside the timed region) on four of the angles: the far-field relative
-error of each form is reported (bar 1e-4).
+Every solve of every form is checked against a tight FP64 reference (all 64
+angles solved together at tol 1e-9, outside the timed region): the far-field
+relative error per angle is reported (bar 1e-4).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -47,19 +51,22 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--angles", type=int, default=64)
     ap.add_argument("--requests", type=int, default=16)
-    ap.add_argument("--plain-solves", type=int, default=4)
+    ap.add_argument("--plain-solves", type=int, default=16)
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stream-requests", type=int, default=550,
                     help="requests of the open-loop Poisson stream (0: skip); the first 50 are warm-up")
     ap.add_argument("--stream-rho", type=float, default=0.5, help="arrival rate as a fraction of the served capacity")
     ap.add_argument("--stream-max-angles", type=int, default=4)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--pool-geometries", type=int, default=0,
-                    help="also serve an open-loop stream over this many pool geometries (2-4 layers, "
-                         "N in [4,000, 250,000], 1-16 angles per request); 0: skip")
-    ap.add_argument("--pool-requests", type=int, default=60)
-    ap.add_argument("--pool-rate", type=float, default=0.35, help="requests per second of the pool stream")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--pool-geometries", type=int, default=6,
+                    help="serve open-loop streams over this many pool geometries (2-4 layers, N in "
+                         "[4,000, 250,000], 1-16 angles per request); 0: skip")
+    ap.add_argument("--pool-requests", type=int, default=30, help="requests per pool stream")
+    ap.add_argument("--pool-rho", type=str, default="0.5,0.9",
+                    help="arrival rates of the pool streams as fractions of the pool's served capacity")
+    ap.add_argument("--pool-budget-gb", type=float, default=0.0,
+                    help="also run the first pool stream under this HBM budget (restart 100); 0: skip")
     return ap.parse_args()
 
 
@@ -86,41 +93,97 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, iterations, budget_s):
-    """The oracle as it stands on one host core: rows of the dense Nystrom
-    matrix by direct Sommerfeld quadrature, timed until budget_s has passed;
-    the full solve is projected as N rows of assembly plus (iterations + 1)
-    dense matvecs."""
+def _oracle_rows(args):
+    """Worker: rows of the dense oracle matrix until budget_s has passed."""
+    name, rows, budget_s = args
     from threadpoolctl import threadpool_limits
 
-    from oracle.medium import Medium
-    from oracle.nystrom import Elements, matrix_rows
+    from oracle.nystrom import matrix_rows
 
-    med = Medium(w.d, w.k, w.eta)
-    el = Elements(med, w.polygons)
-    rng = np.random.default_rng(0)
-    rows = rng.permutation(el.n)
+    med, el = _ORACLE[name]
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         done = 0
         K = None
-        while done == 0 or time.perf_counter() - t0 < budget_s:
+        while done < len(rows) and (done == 0 or time.perf_counter() - t0 < budget_s):
             K = matrix_rows(med, el, [int(rows[done])])
             done += 1
-            if done >= el.n:
-                break
         row_s = (time.perf_counter() - t0) / done
         x = np.ones(el.n, dtype=complex)
         t1 = time.perf_counter()
-        for _ in range(20):
+        for _ in range(10):
             K @ x
-        gemv_row_s = (time.perf_counter() - t1) / 20
-    n = el.n
-    projected = n * row_s + (iterations + 1) * n * gemv_row_s
-    return {"value": 1.0 / projected, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{done} rows of the dense FP64 matrix of {w.name} by direct Sommerfeld quadrature "
-                       f"({row_s:.2f} s/row on one core); one solve projected as {n} rows + "
-                       f"{iterations + 1} dense matvecs = {projected:.3g} s (projected, not run)")}
+        gemv_row_s = (time.perf_counter() - t1) / 10
+    return done, row_s, gemv_row_s
+
+
+_ORACLE = {}
+
+
+def cpu_baseline_time(w, budget_s):
+    """The oracle as it stands, timed on the host cores before the GPU is
+    touched: one worker process per core (one BLAS thread each, at most 16,
+    the host share of one GPU) computes rows of the dense Nystrom matrix by
+    direct Sommerfeld quadrature for budget_s seconds."""
+    import multiprocessing as mp
+
+    from oracle.medium import Medium
+    from oracle.nystrom import Elements
+
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    _ORACLE[w.name] = (med, el)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    rows = np.random.default_rng(0).permutation(el.n)
+    chunks = [(w.name, rows[i::cores][:1000], budget_s) for i in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_rows, chunks)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    return {"n": el.n, "cores": cores, "rows": done, "wall_s": wall, "rows_per_s": done / wall,
+            "gemv_row_s": float(np.median([r[2] for r in res])), "row_s_per_core": float(np.median([r[1] for r in res]))}
+
+
+def cpu_baseline(w, t, iterations):
+    """One solve projected from the timed sample: N rows of assembly at the
+    measured rate of all workers plus (iterations + 1) dense matvecs spread
+    over the same cores."""
+    n = t["n"]
+    projected = n / t["rows_per_s"] + (iterations + 1) * n * t["gemv_row_s"] / t["cores"]
+    return {"value": 1.0 / projected, "unit": "solves/s", "cores": t["cores"], "kind": "oracle",
+            "sample": (f"{t['rows']} rows of the dense FP64 matrix of {w.name} by direct Sommerfeld quadrature in "
+                       f"{t['wall_s']:.1f} s on {t['cores']} worker processes ({t['row_s_per_core']:.2f} s/row per "
+                       f"core); one solve projected as {n} rows + {iterations + 1} dense matvecs = "
+                       f"{projected:.3g} s (projected, not run)")}
+
+
+def _pool_stream(lmfmm, srv, pgeos, gi, th_q, t_arr, obs, gm_of, fref_of=None):
+    """Open-loop stream: request i arrives at t_arr[i]; returns per-request
+    latency, iterations, far-field errors (when references are given) and
+    the span."""
+    pend, lat, its, errs = {}, {}, [], []
+    i, t0 = 0, time.perf_counter()
+    nq = len(t_arr)
+    while i < nq or pend:
+        now = time.perf_counter() - t0
+        while i < nq and t_arr[i] <= now:
+            pend[srv.submit(pgeos[gi[i]], th_q[i], obs_rad=obs, **gm_of(gi[i]))] = i
+            i += 1
+        for rid in list(pend):
+            out_q = srv.poll(rid, results=True)
+            if out_q[0] in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
+                assert out_q[0] == lmfmm.LM_DONE, out_q[:2]
+                k = pend.pop(rid)
+                lat[k] = out_q[2]
+                its += [r_[0] for r_ in out_q[3]]
+                if fref_of is not None:
+                    errs += fref_of(k, out_q[5])
+                srv.release(rid)
+                if len(lat) % 20 == 0:
+                    _log(f"  {len(lat)} of {nq} requests done")
+        time.sleep(0.0005)
+    return lat, its, errs, time.perf_counter() - t0
 
 
 def main():
@@ -129,13 +192,19 @@ def main():
         print(json.dumps({"error": "lmfmm runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    from paper_2511_12450_amd import workloads as wl
+
+    w = wl.three_layer()
+    # the oracle's sample runs on the host cores before the GPU is touched
+    cpu_t = None if a.no_cpu_baseline else cpu_baseline_time(w, a.cpu_seconds)
+    if cpu_t:
+        _log(f"oracle: {cpu_t['rows']} rows in {cpu_t['wall_s']:.1f} s on {cpu_t['cores']} cores")
+
     import torch
 
     from paper_2511_12450_amd import lmfmm
-    from paper_2511_12450_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    w = wl.three_layer()
     obs = lmfmm.far_field_angles()
     t0 = time.perf_counter()
     # default preconditioner: the coarsest subdomain level that fits
@@ -143,15 +212,18 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     _log(f"geometry ready in {setup_s:.1f} s")
-    N, P = geo.n, 2 * w.p + 1
+    N = geo.n
     th_all = np.radians(np.linspace(10.0, 170.0, a.angles))
-    ref_idx = list(range(0, a.angles, max(1, a.angles // 4)))[:4]
     gm = dict(tol=w.tol, max_iter=3000, restart=a.restart)
 
-    # tight FP64 reference (untimed)
-    pr, rr, _ = geo.solve(th_all[ref_idx], tol=1e-9, max_iter=3000, restart=a.restart)
-    fref = geo.far_field(pr, obs).cpu().numpy()
-    del pr
+    # tight FP64 reference of every angle, solved together (untimed)
+    tr0 = time.perf_counter()
+    fref = np.zeros((a.angles, obs.size), dtype=complex)
+    for c0 in range(0, a.angles, 64):
+        pr, rr, _ = geo.solve(th_all[c0:c0 + 64], tol=1e-9, max_iter=3000, restart=a.restart)
+        fref[c0:c0 + 64] = geo.far_field(pr, obs).cpu().numpy()
+        del pr
+    _log(f"FP64 reference of {a.angles} angles (tol 1e-9) in {time.perf_counter() - tr0:.1f} s")
 
     # ---- plain FP64 form: single solves, one after another -----------------------
     def plain(th):
@@ -160,49 +232,55 @@ def main():
         torch.cuda.synchronize()
         return rep[0], st, ff.cpu().numpy()[0]
 
+    plain_idx = [int(v) for v in np.linspace(0, a.angles - 1, a.plain_solves).round()]
     for _ in range(a.warmup):
-        plain(th_all[ref_idx[0]])
+        plain(th_all[plain_idx[0]])
     lat_p, its_p, err_p = [], [], []
     tp = time.perf_counter()
-    for i in range(a.plain_solves):
-        k = ref_idx[i % len(ref_idx)]
+    for k in plain_idx:
         t1 = time.perf_counter()
         rep, st, ff = plain(th_all[k])
         lat_p.append(time.perf_counter() - t1)
         its_p.append(rep[0])
-        err_p.append(_rel(ff, fref[ref_idx.index(k)]))
+        err_p.append(_rel(ff, fref[k]))
     plain_s = time.perf_counter() - tp
     _log(f"plain FP64: {a.plain_solves} solves in {plain_s:.2f} s")
 
     # ---- served FP32 form: batches through the serving loop ----------------------
-    srv = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
     per = max(1, a.angles // a.requests)
-    for _ in range(a.warmup):  # warm-up batches have the timed batch's shape
-        for rid in [srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm) for i in range(0, a.angles, per)]:
-            srv.wait(rid, results=False)
-            srv.release(rid)
-    ph0 = srv.phase_times()
-    st0 = srv.stats()
-    lat_s, its_s, err_s = [], [], []
-    tsrv = time.perf_counter()
-    for _ in range(a.steps):
-        ids = [(srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm), i) for i in range(0, a.angles, per)]
-        for rid, i0 in ids:
-            st, status, lat, rep, phi, ff = srv.wait(rid)
-            assert st == lmfmm.LM_DONE, (st, status)
-            lat_s.append(lat)
-            its_s += [r[0] for r in rep]
-            for r in range(len(rep)):
-                if i0 + r in ref_idx:
-                    err_s.append(_rel(ff[r], fref[ref_idx.index(i0 + r)]))
-            srv.release(rid)
-    served_s = time.perf_counter() - tsrv
-    ph1 = srv.phase_times()
-    ph = {k: ph1[k] - ph0[k] for k in ph1}
-    st1 = srv.stats()
+
+    def served(srv, steps, warmup):
+        for _ in range(warmup):  # warm-up batches have the timed batch's shape
+            for rid in [srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm) for i in range(0, a.angles, per)]:
+                srv.wait(rid, results=False)
+                srv.release(rid)
+        ph0, st0 = srv.phase_times(), srv.stats()
+        lat, its, err = [], [], np.zeros(a.angles)
+        t_0 = time.perf_counter()
+        for _ in range(steps):
+            ids = [(srv.submit(geo, th_all[i:i + per], obs_rad=obs, **gm), i) for i in range(0, a.angles, per)]
+            for rid, i0 in ids:
+                st, status, lt, rep, phi, ff = srv.wait(rid)
+                assert st == lmfmm.LM_DONE, (st, status)
+                lat.append(lt)
+                its += [r[0] for r in rep]
+                for r in range(len(rep)):
+                    err[i0 + r] = max(err[i0 + r], _rel(ff[r], fref[i0 + r]))
+                srv.release(rid)
+        span = time.perf_counter() - t_0
+        ph1, st1 = srv.phase_times(), srv.stats()
+        return span, lat, its, err, {k: ph1[k] - ph0[k] for k in ph1}, st0, st1
+
+    srv = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
+    served_s, lat_s, its_s, err_s, ph, st0, st1 = served(srv, a.steps, a.warmup)
     srv.close()
     n_served = a.steps * a.angles
     _log(f"served FP32: {n_served} solves in {served_s:.2f} s")
+    # the same batch with the preconditioner applied from its FP64 rows
+    srv = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles), precond_fp64=True)
+    served64_s, _, its_s64, err_s64, ph64, _, _ = served(srv, 1, 0)
+    srv.close()
+    _log(f"served FP32 with the FP64 preconditioner: {a.angles} solves in {served64_s:.2f} s")
 
     # ---- served FP32 form under an open-loop stream: Poisson arrivals at
     # rho x the capacity just measured, 1..max angles per request drawn from the
@@ -216,26 +294,12 @@ def main():
         t_arr = np.cumsum(rng.exponential(1.0 / rate, size=a.stream_requests))
         picks = [np.sort(rng.choice(a.angles, size=int(k), replace=False)) for k in n_ang]
         srv2 = lmfmm.Server(precision=lmfmm.LM_MIXED, max_active_rhs=max(64, a.angles))
-        pend, lat_q, err_q, its_q = {}, {}, [], []
-        i, t0s = 0, time.perf_counter()
-        while i < len(t_arr) or pend:
-            now = time.perf_counter() - t0s
-            while i < len(t_arr) and t_arr[i] <= now:
-                pend[srv2.submit(geo, th_all[picks[i]], obs_rad=obs, **gm)] = i
-                i += 1
-            for rid in list(pend):
-                out_q = srv2.poll(rid, results=True)
-                if out_q[0] in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
-                    assert out_q[0] == lmfmm.LM_DONE, out_q[:2]
-                    k = pend.pop(rid)
-                    lat_q[k] = out_q[2]
-                    its_q += [r_[0] for r_ in out_q[3]]
-                    for r_, ai in enumerate(picks[k]):
-                        if ai in ref_idx:
-                            err_q.append(_rel(out_q[5][r_], fref[ref_idx.index(ai)]))
-                    srv2.release(rid)
-            time.sleep(0.0005)
-        span = time.perf_counter() - t0s
+
+        def ref_err(k, ff):
+            return [_rel(ff[r_], fref[ai]) for r_, ai in enumerate(picks[k])]
+
+        lat_q, its_q, err_q, span = _pool_stream(lmfmm, srv2, [geo], np.zeros(a.stream_requests, dtype=int),
+                                                 [th_all[p_] for p_ in picks], t_arr, obs, lambda g_: gm, ref_err)
         srv2.close()
         keep = [lat_q[k] for k in range(50, a.stream_requests)] if a.stream_requests > 100 else list(lat_q.values())
         stream = {"requests": a.stream_requests, "warmup_requests_excluded": 50 if a.stream_requests > 100 else 0,
@@ -244,58 +308,64 @@ def main():
                   "solves_per_s": float(np.sum(n_ang) / span),
                   "p50_s": float(np.percentile(keep, 50)), "p99_s": float(np.percentile(keep, 99)),
                   "iterations_min_max": [int(min(its_q)), int(max(its_q))],
-                  "rel_err_far_field_max": float(max(err_q)) if err_q else None,
-                  "checked_solves": len(err_q)}
+                  "rel_err_far_field_max": float(max(err_q)), "checked_solves": len(err_q)}
         _log(f"stream: {a.stream_requests} requests in {span:.1f} s, p50 {stream['p50_s']:.3f} s, "
              f"p99 {stream['p99_s']:.3f} s")
 
-    # ---- optional: a stream over several pool geometries (different media and
-    # sizes, 1-16 angles per request, admission by HBM footprint)
+    # ---- streams over a pool of geometries (different media and sizes, 1-16
+    # angles per request, admission by HBM footprint): the pool's served
+    # capacity from a closed batch, then Poisson streams at fractions of it
     pool = None
     if a.pool_geometries > 0:
         ws = [wl.stream_geometry(g) for g in range(a.pool_geometries)]
         t0p = time.perf_counter()
         pgeos = [lmfmm.Geometry.from_workload(w_, method=lmfmm.LM_FMM, p=w_.p) for w_ in ws]
+        pool_setup = time.perf_counter() - t0p
         _log(f"pool: {len(ws)} geometries (N {min(w_.n_elements for w_ in ws)}..{max(w_.n_elements for w_ in ws)}) "
-             f"ready in {time.perf_counter() - t0p:.1f} s")
+             f"ready in {pool_setup:.1f} s")
+        budget = int(0.8 * torch.cuda.mem_get_info()[0])
         rng = np.random.default_rng(11)
-        nq = a.pool_requests
-        gi = rng.integers(0, len(pgeos), size=nq)
-        na = rng.integers(1, 17, size=nq)
-        th_q = [np.radians(rng.uniform(10.0, 170.0, size=int(k))) for k in na]
-        t_arr = np.cumsum(rng.exponential(1.0 / a.pool_rate, size=nq))
-        srv3 = lmfmm.Server(precision=lmfmm.LM_MIXED, hbm_budget_bytes=int(160e9))
-        pend, lat_g, its_g = {}, {}, []
-        i, t0s = 0, time.perf_counter()
-        while i < nq or pend:
-            now = time.perf_counter() - t0s
-            while i < nq and t_arr[i] <= now:
-                pend[srv3.submit(pgeos[gi[i]], th_q[i], obs_rad=obs, **gm)] = i
-                i += 1
-            for rid in list(pend):
-                out_q = srv3.poll(rid, results=True)
-                if out_q[0] in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
-                    assert out_q[0] == lmfmm.LM_DONE, out_q[:2]
-                    k = pend.pop(rid)
-                    lat_g[k] = out_q[2]
-                    its_g += [r_[0] for r_ in out_q[3]]
-                    srv3.release(rid)
-                    if len(lat_g) % 25 == 0:
-                        _log(f"pool: {len(lat_g)} of {nq} requests done")
-            time.sleep(0.0005)
-        span = time.perf_counter() - t0s
-        srv3.close()
+        gmp = lambda g_: gm  # noqa: E731
+        # closed batch: one request of 8 angles per geometry, all at once
+        srvc = lmfmm.Server(precision=lmfmm.LM_MIXED, hbm_budget_bytes=budget)
+        thc = [np.radians(np.linspace(20.0, 160.0, 8)) for _ in pgeos]
+        latc, itsc, _, spanc = _pool_stream(lmfmm, srvc, pgeos, list(range(len(pgeos))), thc,
+                                            np.zeros(len(pgeos)), obs, gmp)
+        srvc.close()
+        cap_pool = 8 * len(pgeos) / spanc
+        _log(f"pool: closed batch of {8 * len(pgeos)} solves in {spanc:.1f} s ({cap_pool:.1f} solves/s)")
+        runs = []
+        rhos = [float(v) for v in a.pool_rho.split(",") if v]
+        plan = [(r_, budget, a.restart) for r_ in rhos]
+        if a.pool_budget_gb > 0:
+            plan.append((rhos[0], int(a.pool_budget_gb * 2 ** 30), 100))
+        for rho, bud, rst in plan:
+            nq = a.pool_requests
+            gi = rng.integers(0, len(pgeos), size=nq)
+            na = rng.integers(1, 17, size=nq)
+            th_q = [np.radians(rng.uniform(10.0, 170.0, size=int(k))) for k in na]
+            rate = rho * cap_pool / float(np.mean(na))
+            t_arr = np.cumsum(rng.exponential(1.0 / rate, size=nq))
+            gmr = dict(gm, restart=rst)
+            srv3 = lmfmm.Server(precision=lmfmm.LM_MIXED, hbm_budget_bytes=bud)
+            lat_g, its_g, _, span = _pool_stream(lmfmm, srv3, pgeos, gi, th_q, t_arr, obs, lambda g_: gmr)
+            mem = srv3.memory()
+            srv3.close()
+            keep = [lat_g[k] for k in range(nq // 10, nq)]
+            runs.append({"rho": rho, "hbm_budget_bytes": bud, "gmres_restart": rst, "requests": nq,
+                         "warmup_requests_excluded": nq // 10, "arrival_rate_solves_s": float(rate * np.mean(na)),
+                         "solves": int(np.sum(na)), "solves_per_s": float(np.sum(na) / span), "span_s": span,
+                         "p50_s": float(np.percentile(keep, 50)), "p99_s": float(np.percentile(keep, 99)),
+                         "iterations_min_max": [int(min(its_g)), int(max(its_g))],
+                         "server_bytes_at_end": mem["held"]})
+            _log(f"pool rho {rho}: {nq} requests, {int(np.sum(na))} solves in {span:.1f} s, "
+                 f"p50 {runs[-1]['p50_s']:.3f} s, p99 {runs[-1]['p99_s']:.3f} s")
         for g_ in pgeos:
             g_.close()
-        keep = [lat_g[k] for k in range(nq // 10, nq)]
         pool = {"geometries": [w_.name for w_ in ws], "layers": [int(len(w_.k)) for w_ in ws],
-                "requests": nq, "warmup_requests_excluded": nq // 10, "arrival_rate_requests_s": a.pool_rate,
-                "angles_per_request": [1, 16], "solves": int(np.sum(na)),
-                "solves_per_s": float(np.sum(na) / span), "span_s": span,
-                "p50_s": float(np.percentile(keep, 50)), "p99_s": float(np.percentile(keep, 99)),
-                "iterations_min_max": [int(min(its_g)), int(max(its_g))]}
-        _log(f"pool: {nq} requests, {int(np.sum(na))} solves in {span:.1f} s, p50 {pool['p50_s']:.3f} s, "
-             f"p99 {pool['p99_s']:.3f} s")
+                "N": [int(w_.n_elements) for w_ in ws], "setup_s": pool_setup, "angles_per_request": [1, 16],
+                "capacity_solves_s": cap_pool, "capacity_batch": f"{len(pgeos)} requests of 8 angles, one per geometry",
+                "runs": runs}
 
     # ---- kernel rooflines (HIP events on the launch stream, inside the timed batch)
     stats = geo.fmm_stats()
@@ -328,6 +398,20 @@ def main():
     x = torch.from_numpy(wl.random_vector(N, seed=1, n_rhs=R)).to(torch.complex64).cuda()
     y = torch.empty_like(x)
     t_mix = geo.stage_times(x, y, reps=5, precision=lmfmm.LM_MIXED)
+    # near field (the P2P step): leaf blocks on matrix cores at R = 64 (FP32),
+    # the FP64 CSR at R = 1; stage 5, HIP events on the near-field stream
+    pairs = stats["free_near_pairs"] + stats["reaction_near_pairs"]
+    p2p = [{"bound": "mfma", "kernel": "k_block_mfma (free-space near field + self terms, leaf blocks) + "
+                                       "k_near_csr (reaction near pairs), FP32, R = 64",
+            "near_pairs": pairs, "algorithmic_flops_per_launch": 8.0 * R * pairs, "kernel_avg_us": 1e3 * t_mix[5],
+            "achieved": 8.0 * R * pairs / (1e-3 * t_mix[5]) / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s"},
+           {"bound": "hbm", "kernel": "k_near_csr<double, 4> (near field + self terms, CSR), FP64, R = 1",
+            "near_pairs": pairs, "algorithmic_bytes_per_launch": 20.0 * pairs + 32.0 * N,
+            "kernel_avg_us": 1e3 * t_fp64[5],
+            "achieved": (20.0 * pairs + 32.0 * N) / (1e-3 * t_fp64[5]) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}]
+    for e in p2p:
+        e["frac"] = e["achieved"] / e["peak"]
 
     cfg = {"workload": w.name, "N": int(N), "layers": int(len(w.k)), "k": [float(v) for v in w.k], "p": int(w.p),
            "gmres_tol": w.tol, "gmres_restart": a.restart, "preconditioner": "overlapping DD (Sec. 4.2), default subdomain level (coarsest that fits)",
@@ -336,12 +420,14 @@ def main():
                       "iterations_min_max": [int(min(its_s)), int(max(its_s))], "rounds": int(rounds),
                       "fused_rhs_per_launch": (st1["fused_rhs"] - st0["fused_rhs"]) /
                                               max(1, st1["launches"] - st0["launches"]),
-                      "km_phase_ms": ph["km_ms"], "gs_phase_ms": ph["gs_ms"], "m2l_ms": ph["m2l_ms"]},
+                      "km_phase_ms": ph["km_ms"], "gs_phase_ms": ph["gs_ms"], "m2l_ms": ph["m2l_ms"],
+                      "round_host_ms": ph["round_ms"], "finish_host_ms": ph["finish_ms"]},
            "setup_s": setup_s, "device_bytes": int(geo.device_bytes), "fmm": stats,
            "matvec_fp32_R64_ms": float(t_mix[7]),
            "matvec_fp32_R64_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_mix) if s_ != "total"},
            "matvec_fp64_R1_ms": float(t_fp64[7]),
            "matvec_fp64_R1_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_fp64) if s_ != "total"}}
+    errs_all = list(err_s) + (([stream["rel_err_far_field_max"]]) if stream else [])
     out = {
         "metric": "GMRES solves/sec + p50/p99 latency, served FP32 vs plain FP64, at rel err 1e-4",
         "value": n_served / served_s,
@@ -356,9 +442,14 @@ def main():
         "p99_s": stream["p99_s"] if stream else float(np.percentile(lat_s, 99)),
         "batch_p50_s": float(np.percentile(lat_s, 50)),
         "batch_p99_s": float(np.percentile(lat_s, 99)),
-        "rel_err_far_field_max": float(max(err_s + (stream["rel_err_far_field_max"] and [stream["rel_err_far_field_max"]] or []))) if stream else float(max(err_s)),
+        "rel_err_far_field_max": float(max(errs_all)),
+        "rel_err_far_field_per_angle": [float(f"{v:.3g}") for v in err_s],
         "stream": stream,
         "pool_stream": pool,
+        "served_fp64_preconditioner": {"value": a.angles / served64_s, "unit": "solves/s", "solves": a.angles,
+                                       "iterations_min_max": [int(min(its_s64)), int(max(its_s64))],
+                                       "rel_err_far_field_max": float(max(err_s64)),
+                                       "km_phase_ms": ph64["km_ms"]},
         "plain_fp64": {"value": a.plain_solves / plain_s, "unit": "solves/s", "solves": a.plain_solves,
                        "p50_s": float(np.percentile(lat_p, 50)), "p99_s": float(np.percentile(lat_p, 99)),
                        "iterations": [int(v) for v in its_p], "rel_err_far_field_max": float(max(err_p))},
@@ -368,15 +459,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "precision_split": ("f32 translations and near field (matrix cores, f32 accumulation); binary16 preconditioner "
-                            "products on a split input (fixed operator, f32 accumulation); complex64 Krylov basis "
-                            "storage; f64 Arnoldi and Givens arithmetic, spectral tables and self terms"),
+                            "products on a split input (fixed operator, f32 accumulation; served_fp64_preconditioner "
+                            "is the same form with the FP64 preconditioner rows); complex64 Krylov basis storage; f64 "
+                            "Arnoldi and Givens arithmetic, spectral tables and self terms"),
         "data": "synthetic",
         "config": cfg,
         "roofline": roof,
         "roofline_other": other,
+        "roofline_p2p": p2p,
     }
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, int(np.median(its_p)), a.cpu_seconds)
+    if cpu_t:
+        out["cpu_baseline"] = cpu_baseline(w, cpu_t, int(np.median(its_p)))
     print(json.dumps(out))
 
 

@@ -261,13 +261,19 @@ lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, 
  * work vectors and the per-right-hand-side FMM workspace; the geometry itself
  * is not counted).  Zero limits select 64 right-hand sides and 64 GiB.  The
  * device buffers of up to max_active_rhs finished solves are kept for reuse
- * by later solves with the same N and restart length (outside that budget;
- * released when an allocation fails and at lm_server_destroy).
+ * by later solves with the same N and restart length; they count against the
+ * same budget and are freed (those no admitted request can reuse first) when
+ * an admission needs the room, when an allocation fails and at
+ * lm_server_destroy.  The buffers of the fused launches of a geometry are
+ * freed once none of its solves is admitted, so the device memory the server
+ * holds (lm_server_memory) stays within the budget.
  * All server entry points are thread-safe. */
 typedef struct {
   int64_t hbm_budget_bytes;
   int max_active_rhs;
   int precision; /* LM_FP64 or LM_MIXED, for every request of the server */
+  int precond_fp64; /* nonzero: an LM_MIXED server applies the preconditioner
+                       with its FP64 rows instead of the binary16 copy */
 } lm_server_opts;
 typedef struct {
   lm_geom geom;
@@ -301,6 +307,11 @@ lm_status lm_request_footprint(lm_geom geom, int n_rhs, const lm_gmres_opts* gmr
 /* Host output of 6 int64: queued requests, active right-hand sides, admitted
  * footprint bytes, rounds, fused K M launches, right-hand sides in them. */
 lm_status lm_server_stats(lm_server server, int64_t* out6);
+/* Host output of 3 int64: device bytes the server's own buffers hold now
+ * (Krylov bases and work vectors of admitted and spare solves, fused-launch
+ * buffers, round buffers; not the geometries), the part held by spare
+ * solves, and the admitted footprint (as lm_server_stats). */
+lm_status lm_server_memory(lm_server server, int64_t* out3);
 /* Host output of 8 doubles accumulated over the server's rounds, measured
  * with HIP events on the streams the kernels run on: [0] ms in the fused
  * K M phase (gathers, preconditioner, matvecs; every geometry stream

@@ -199,7 +199,7 @@ lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2
   const double2* xin = x;
   if (use_pre) {
     if (b.mz.bytes < (size_t)n * sizeof(double2)) LM_TRY(b.mz.alloc(n * sizeof(double2)));
-    LM_TRY(precond_apply(g, precision, R, x, b.mz.p, s));
+    LM_TRY(precond_apply(g, b.pre_precision < 0 ? precision : b.pre_precision, R, x, b.mz.p, s));
     xin = b.mz.as<double2>();
   }
   if (precision == LM_FP64) return geom_matvec(g, precision, R, xin, y, s, b.stage_ev);

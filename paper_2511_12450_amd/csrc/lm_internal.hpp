@@ -111,6 +111,7 @@ lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, c
 struct KmBufs {
   DevBuf x32, y32, mz;
   hipEvent_t* stage_ev = nullptr;  // when set: 16 events bracketing the FMM stages (see fmm_matvec_timed)
+  int pre_precision = -1;          // precision of the preconditioner apply (-1: the matvec's)
 };
 lm_status apply_km(lm_geom_s* g, int precision, int R, const double2* x, double2* y, bool use_pre, KmBufs& b,
                    hipStream_t s);

@@ -532,6 +532,7 @@ struct lm_server_s {
   std::map<uint64_t, Request*> reqs;
   uint64_t next_id = 1;
   int64_t used = 0;
+  int64_t held = 0, held_spare = 0;  // device bytes of the server's own buffers (all / spare columns), worker-updated
   int active_rhs = 0;
   int64_t rounds = 0, launches = 0, fused_rhs = 0;
   double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
@@ -588,6 +589,10 @@ lm_status upload_desc(lm_server_s* S, const std::vector<ColDev>& d) {
   return LM_OK;
 }
 
+// Precision of the preconditioner apply: the server's, or the FP64 rows when
+// asked for.
+int pre_precision(const lm_server_s* S) { return S->o.precond_fp64 ? LM_FP64 : S->o.precision; }
+
 // Bytes per element of a column's Krylov basis.
 size_t basis_bytes(const lm_server_s* S) { return S->o.precision == LM_MIXED ? sizeof(float2) : sizeof(double2); }
 
@@ -600,6 +605,62 @@ lm_status ensure(DevBuf& b, size_t bytes) {
 void drop_spares(lm_server_s* S) {
   for (Column* c : S->spare) delete c;
   S->spare.clear();
+}
+
+int64_t col_bytes(const Column* c) { return (int64_t)(c->V.bytes + c->z.bytes + c->gv.bytes + c->y.bytes + c->dn.bytes); }
+
+// Frees spare columns until they hold at most `allow` bytes: first those no
+// admitted request can reuse (another N or restart length), oldest first.
+void trim_spares(lm_server_s* S, int64_t allow, const std::vector<Request*>& admit) {
+  int64_t sb = 0;
+  for (Column* c : S->spare) sb += col_bytes(c);
+  auto reusable = [&](const Column* c) {
+    for (const Request* q : admit)
+      if (q->g->N == c->N && std::max(1, std::min(q->o.restart, q->o.max_iter)) == c->m) return true;
+    return false;
+  };
+  for (int pass = 0; pass < 2 && sb > allow; ++pass)
+    for (auto it = S->spare.begin(); it != S->spare.end() && sb > allow;) {
+      if (pass == 0 && reusable(*it)) {
+        ++it;
+        continue;
+      }
+      sb -= col_bytes(*it);
+      delete *it;
+      it = S->spare.erase(it);
+    }
+}
+
+// Frees the fused-launch buffers of (geometry, preconditioner) groups that no
+// admitted column uses any more, and the round and finishing buffers when
+// nothing runs; then records the device bytes the server holds.
+void settle_memory(lm_server_s* S, bool idle) {
+  for (auto it = S->groups.begin(); it != S->groups.end();) {
+    bool live = false;
+    for (const Column* c : S->cols)
+      if (c->g == it->first.first && c->req && (c->req->o.precond ? 1 : 0) == it->first.second) {
+        live = true;
+        break;
+      }
+    it = live ? std::next(it) : S->groups.erase(it);
+  }
+  if (idle)  // nothing admitted: the round and finishing buffers are regrown on demand
+    for (DevBuf* b : {&S->d_desc, &S->d_h, &S->d_nrm, &S->d_dpart, &S->d_npart, &S->d_y, &S->d_fz, &S->d_fphi,
+                      &S->d_fff})
+      b->release();
+  int64_t h = 0, hs = 0;
+  for (const Column* c : S->cols) h += col_bytes(c);
+  for (const Column* c : S->spare) hs += col_bytes(c);
+  for (const auto& kv : S->groups) {
+    const Group& G = kv.second;
+    h += (int64_t)(G.X.bytes + G.Y.bytes + G.km.x32.bytes + G.km.y32.bytes + G.km.mz.bytes);
+  }
+  for (const DevBuf* b : {&S->d_desc, &S->d_h, &S->d_nrm, &S->d_dpart, &S->d_npart, &S->d_y, &S->d_fz, &S->d_fphi,
+                          &S->d_fff})
+    h += (int64_t)b->bytes;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->held = h + hs;
+  S->held_spare = hs;
 }
 
 lm_status start_request(lm_server_s* S, Request* q) {
@@ -683,7 +744,7 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
       char* pb = (char*)S->d_fphi.p;
       for (int i = 0; i < k; ++i)
         LM_TRY_HIP(hipMemcpyAsync((pre ? zb : pb) + i * vb, fin[i0 + i]->z.p, vb, hipMemcpyDeviceToDevice, S->s));
-      if (pre) LM_TRY(precond_apply(g, S->o.precision, k, zb, pb, S->s));
+      if (pre) LM_TRY(precond_apply(g, pre_precision(S), k, zb, pb, S->s));
       for (int i = 0; i < k; ++i) {
         Column* c = fin[i0 + i];
         LM_TRY_HIP(hipMemcpyAsync(c->req->phi.data() + (size_t)c->col * N, pb + i * vb, vb, hipMemcpyDeviceToHost,
@@ -819,6 +880,7 @@ lm_status round(lm_server_s* S) {
     Group& G = S->groups[kv.first];
     const bool time_m2l = g->method == LM_FMM && !stream_timed[si];
     G.km.stage_ev = time_m2l ? S->sev[si] : nullptr;
+    G.km.pre_precision = pre_precision(S);
     LM_TRY(apply_km(g, prec, R, G.X.as<double2>(), G.Y.as<double2>(), pre, G.km, st));
     G.km.stage_ev = nullptr;
     if (time_m2l) {
@@ -1190,6 +1252,7 @@ void worker(lm_server_s* S) {
   std::vector<Request*> running;
   while (true) {
     std::vector<Request*> admit;
+    int64_t allow = 0;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       // drop cancelled requests (queued ones are dropped at cancel time)
@@ -1222,11 +1285,15 @@ void worker(lm_server_s* S) {
         S->active_rhs += q->R;
         admit.push_back(q);
       }
+      allow = S->o.hbm_budget_bytes - S->used;
       if (running.empty() && admit.empty()) {
         S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
         continue;
       }
     }
+    // spare columns count against the budget: free what the admitted
+    // requests' footprints leave no room for
+    if (!admit.empty()) trim_spares(S, allow, admit);
     for (Request* q : admit) {
       lm_status st = start_request(S, q);
       if (st < 0) {
@@ -1263,6 +1330,7 @@ void worker(lm_server_s* S) {
         ++it;
       }
     }
+    settle_memory(S, running.empty());
   }
   for (Request* q : running) release_columns(S, q);
   drop_spares(S);
@@ -1418,6 +1486,15 @@ extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
   out6[3] = S->rounds;
   out6[4] = S->launches;
   out6[5] = S->fused_rhs;
+  return LM_OK;
+}
+
+extern "C" lm_status lm_server_memory(lm_server S, int64_t* out3) {
+  LM_CHECK(S && out3, LM_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out3[0] = S->held;
+  out3[1] = S->held_spare;
+  out3[2] = S->used;
   return LM_OK;
 }
 

@@ -42,7 +42,8 @@ class SolveReport(ctypes.Structure):
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_active_rhs", ctypes.c_int), ("precision", ctypes.c_int)]
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_active_rhs", ctypes.c_int), ("precision", ctypes.c_int),
+                ("precond_fp64", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -85,6 +86,7 @@ _SIGS = {
     "lm_release": ([_vp, ctypes.c_uint64], _ip),
     "lm_server_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_server_phase_times": ([_vp, _dp], _ip),
+    "lm_server_memory": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_request_footprint": ([_vp, _ip, ctypes.POINTER(GmresOpts), ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_server_destroy": ([_vp], _ip),
 }
@@ -318,8 +320,8 @@ class Server:
     done, the reports, phi (numpy c128 [n_rhs][N]) and far field (numpy c128
     [n_rhs][n_obs])."""
 
-    def __init__(self, precision=LM_MIXED, max_active_rhs=64, hbm_budget_bytes=0):
-        o = ServerOpts(int(hbm_budget_bytes), int(max_active_rhs), int(precision))
+    def __init__(self, precision=LM_MIXED, max_active_rhs=64, hbm_budget_bytes=0, precond_fp64=False):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_active_rhs), int(precision), int(bool(precond_fp64)))
         h = ctypes.c_void_p()
         _check(lib().lm_server_create(ctypes.byref(o), ctypes.byref(h)))
         self.h = h
@@ -374,6 +376,13 @@ class Server:
         _check(lib().lm_server_stats(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return dict(zip(["queued", "active_rhs", "admitted_bytes", "rounds", "launches", "fused_rhs"],
                         [int(v) for v in out]))
+
+    def memory(self):
+        """dict: device bytes the server holds, of which spare solves, and the
+        admitted footprint (lm_server_memory)."""
+        out = np.zeros(3, dtype=np.int64)
+        _check(lib().lm_server_memory(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return dict(zip(["held", "spare", "admitted"], [int(v) for v in out]))
 
     def phase_times(self):
         """dict: K M phase ms, Gram-Schmidt phase ms and algorithmic bytes,

@@ -18,12 +18,9 @@ from oracle.medium import Medium
 from oracle.nystrom import Elements, matrix, matrix_rows
 from paper_2511_12450_amd import lmfmm
 from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _straddle():
@@ -45,10 +42,7 @@ def test_fmm_matvec_straddling_eta(top_fft):
     K = matrix(med, el)
     x = wl.random_vector(el.n, seed=4, n_rhs=2)
     y = geo.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
-    for r in range(2):
-        err = _rel(y[r], K @ x[r])
-        print("straddle3 rel err", err, flush=True)
-        assert err < 1e-6
+    check(y, (K @ x.T).T, 1e-6, f"straddle3 fmm top_fft={top_fft}")
 
 
 @pytest.fixture(scope="module")
@@ -71,9 +65,7 @@ def test_fmm_matvec_sampled_rows(mini):
     near = np.nonzero(np.min(np.abs(el.cy[:, None] + med.d[None, :]), axis=1) < 0.05)[0]
     rows = np.unique(np.concatenate([rng.choice(near, 12, replace=False), rng.choice(el.n, 12, replace=False)]))
     ref = matrix_rows(med, el, rows) @ x
-    err = _rel(y[rows], ref)
-    print("mini sampled-row rel err", err, flush=True)
-    assert err < 1e-6
+    check(y[rows], ref, 1e-6, "mini sampled rows", idx=rows)
 
 
 def test_fmm_vs_dense_full_vector(mini):
@@ -82,9 +74,7 @@ def test_fmm_vs_dense_full_vector(mini):
     x = torch.from_numpy(wl.random_vector(el.n, seed=10, n_rhs=1)).cuda()
     yf = geo.matvec(x).cpu().numpy()[0]
     yd = dense.matvec(x).cpu().numpy()[0]
-    err = _rel(yf, yd)
-    print("mini fmm vs dense rel err", err, flush=True)
-    assert err < 1e-6
+    check(yf, yd, 1e-6, "mini fmm vs dense full vector")
 
 
 @pytest.mark.parametrize("top_fft", [-1, 1])
@@ -97,7 +87,7 @@ def test_fmm_homogeneous_medium(top_fft):
     K = matrix(med, el)
     x = wl.random_vector(el.n, seed=6, n_rhs=1)[0]
     y = geo.matvec(torch.from_numpy(x[None]).cuda()).cpu().numpy()[0]
-    assert _rel(y, K @ x) < 1e-6
+    check(y, K @ x, 1e-6, f"homogeneous fmm top_fft={top_fft}")
 
 
 @pytest.mark.parametrize("top_fft", [-1, 1])
@@ -110,7 +100,7 @@ def test_fmm_tiny(top_fft):
     K = matrix(med, el)
     x = wl.random_vector(4, seed=1)[0]
     y = geo.matvec(torch.from_numpy(x[None]).cuda()).cpu().numpy()[0]
-    assert _rel(y, K @ x) < 1e-6
+    check(y, K @ x, 1e-6, f"tiny fmm top_fft={top_fft}")
 
 
 @pytest.mark.parametrize("precision", [lmfmm.LM_FP64, lmfmm.LM_MIXED])
@@ -132,9 +122,7 @@ def test_level0_convolution_equals_direct_lists(mini, precision):
         x = torch.from_numpy(wl.random_vector(el.n, seed=20 + R, n_rhs=R)).to(dt).cuda()
         a = on.matvec(x, precision=precision).cpu().numpy()
         b = off.matvec(x, precision=precision).cpu().numpy()
-        err = _rel(a, b)
-        print(f"precision {precision} R={R}: level-0 convolution vs lists rel diff {err:.2e}", flush=True)
-        assert err < bar
+        check(a, b, bar, f"precision {precision} R={R}: level-0 convolution vs lists")
     y = torch.empty_like(x)
     st_on = on.stage_times(x, y, reps=2, precision=precision)
     st_off = off.stage_times(x, y, reps=2, precision=precision)
@@ -146,9 +134,9 @@ def test_level0_convolution_equals_direct_lists(mini, precision):
     near = np.nonzero(np.min(np.abs(el.cy[:, None] + med.d[None, :]), axis=1) < 0.05)[0]
     rows = np.unique(np.concatenate([rng.choice(near, 12, replace=False), rng.choice(el.n, 12, replace=False)]))
     xo = xr.astype(np.complex64).astype(np.complex128) if precision == lmfmm.LM_MIXED else xr
-    err = _rel(yr[rows].astype(np.complex128), matrix_rows(med, el, rows) @ xo)
-    print(f"precision {precision}: level-0 convolution sampled-row rel err {err:.2e}", flush=True)
-    assert err < (1e-6 if precision == lmfmm.LM_FP64 else 1e-4)
+    check(yr[rows].astype(np.complex128), matrix_rows(med, el, rows) @ xo,
+          1e-6 if precision == lmfmm.LM_FP64 else 1e-4, f"precision {precision}: level-0 convolution sampled rows",
+          idx=rows)
     on.close()
     off.close()
 
@@ -176,14 +164,11 @@ def test_level0_convolution_wide_sparse_rows():
     y_off = off.matvec(xt).cpu().numpy()
     y32 = on.matvec(xt.to(torch.complex64), precision=lmfmm.LM_MIXED).cpu().numpy()
     ref = (K @ x.T).T
-    e_lists, e_on, e_off = _rel(y_on, y_off), _rel(y_on, ref), _rel(y_off, ref)
+    check(y_on, y_off, 1e-11, "wide6 convolution vs lists")
+    check(y_on, ref, 1e-6, "wide6 convolution vs oracle")
+    check(y_off, ref, 1e-6, "wide6 lists vs oracle")
     x32 = x.astype(np.complex64).astype(np.complex128)
-    e32 = _rel(y32.astype(np.complex128), (K @ x32.T).T)
-    print(f"wide6: convolution vs lists {e_lists:.2e}, vs oracle {e_on:.2e} (lists {e_off:.2e}), FP32 {e32:.2e}",
-          flush=True)
-    assert e_lists < 1e-11
-    assert e_on < 1e-6 and e_off < 1e-6
-    assert e32 < 1e-4
+    check(y32.astype(np.complex128), (K @ x32.T).T, 1e-4, "wide6 FP32 form vs oracle")
     on.close()
     off.close()
 
@@ -199,8 +184,6 @@ def test_level0_convolution_over_launch_chunks(mini):
         xx = x.to(dt)
         a = on.matvec(xx, precision=precision).cpu().numpy().astype(np.complex128)
         b = off.matvec(xx, precision=precision).cpu().numpy().astype(np.complex128)
-        errs = [_rel(a[r], b[r]) for r in (0, 63, 64, 69)]
-        print(f"precision {precision}, R=70: convolution vs lists per rhs", [f"{e:.1e}" for e in errs], flush=True)
-        assert max(errs) < bar
+        check(a, b, bar, f"precision {precision}, R=70: convolution vs lists")
     on.close()
     off.close()

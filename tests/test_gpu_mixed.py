@@ -19,12 +19,9 @@ from oracle.nystrom import Elements, matrix, matrix_rows
 from oracle.solve import lu_solve
 from paper_2511_12450_amd import lmfmm
 from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _straddle():
@@ -58,10 +55,8 @@ def test_fp32_matvec_vs_oracle(straddle):
     w, geo, med, el, K = straddle
     x = wl.random_vector(el.n, seed=4, n_rhs=3)
     y = geo.matvec(torch.from_numpy(x).to(torch.complex64).cuda(), precision=lmfmm.LM_MIXED).cpu().numpy()
-    for r in range(3):
-        err = _rel(y[r].astype(np.complex128), K @ x[r].astype(np.complex64).astype(np.complex128))
-        print("straddle3 FP32 matvec rel err", err, flush=True)
-        assert err < 1e-4
+    ref = (K @ x.astype(np.complex64).astype(np.complex128).T).T
+    check(y.astype(np.complex128), ref, 1e-4, "straddle3 FP32 matvec")
 
 
 def test_fp32_matvec_sampled_rows(mini):
@@ -72,9 +67,7 @@ def test_fp32_matvec_sampled_rows(mini):
     near = np.nonzero(np.min(np.abs(el.cy[:, None] + med.d[None, :]), axis=1) < 0.05)[0]
     rows = np.unique(np.concatenate([rng.choice(near, 10, replace=False), rng.choice(el.n, 10, replace=False)]))
     ref = matrix_rows(med, el, rows) @ x.astype(np.complex128)
-    err = _rel(y[rows].astype(np.complex128), ref)
-    print("mini FP32 sampled-row rel err", err, flush=True)
-    assert err < 1e-4
+    check(y[rows].astype(np.complex128), ref, 1e-4, "mini FP32 sampled rows", idx=rows)
 
 
 @pytest.mark.parametrize("n_rhs", [5, 70])
@@ -83,17 +76,11 @@ def test_multi_rhs_equals_single(mini, n_rhs):
     x = torch.from_numpy(wl.random_vector(el.n, seed=20 + n_rhs, n_rhs=n_rhs)).cuda()
     yb = geo.matvec(x).cpu().numpy()
     picks = [0, n_rhs // 2, n_rhs - 1]
-    for r in picks:
-        ys = geo.matvec(x[r:r + 1].contiguous()).cpu().numpy()[0]
-        err = _rel(yb[r], ys)
-        print(f"R={n_rhs} rhs {r}: batched vs single rel diff {err:.2e}", flush=True)
-        assert err < 1e-12
+    ys = np.array([geo.matvec(x[r:r + 1].contiguous()).cpu().numpy()[0] for r in picks])
+    check(yb[picks], ys, 1e-12, f"R={n_rhs}: batched vs single")
     x32 = x.to(torch.complex64)
     y32 = geo.matvec(x32, precision=lmfmm.LM_MIXED).cpu().numpy()
-    for r in picks:
-        err = _rel(y32[r].astype(np.complex128), yb[r])
-        print(f"R={n_rhs} rhs {r}: FP32 vs FP64 rel diff {err:.2e}", flush=True)
-        assert err < 1e-4
+    check(y32[picks].astype(np.complex128), yb[picks], 1e-4, f"R={n_rhs}: FP32 vs FP64")
 
 
 @pytest.mark.parametrize("n_rhs", [2, 7, 16])
@@ -107,11 +94,8 @@ def test_fp32_few_rhs_matches_many(mini, n_rhs):
     x32 = x.to(torch.complex64)
     wide = geo.matvec(x32, precision=lmfmm.LM_MIXED).cpu().numpy()
     few = geo.matvec(x32[:n_rhs].contiguous(), precision=lmfmm.LM_MIXED).cpu().numpy()
-    e_wide = _rel(few.astype(np.complex128), wide[:n_rhs].astype(np.complex128))
-    e_64 = _rel(few.astype(np.complex128), y64[:n_rhs])
-    print(f"R={n_rhs}: FP32 few vs wide launch {e_wide:.2e}, vs FP64 {e_64:.2e}", flush=True)
-    assert e_wide < 1e-5
-    assert e_64 < 1e-4
+    check(few.astype(np.complex128), wide[:n_rhs].astype(np.complex128), 1e-5, f"R={n_rhs}: FP32 few vs wide launch")
+    check(few.astype(np.complex128), y64[:n_rhs], 1e-4, f"R={n_rhs}: FP32 few vs FP64")
 
 
 def test_fp32_solve_far_field_vs_oracle(straddle):
@@ -122,11 +106,8 @@ def test_fp32_solve_far_field_vs_oracle(straddle):
     assert st == lmfmm.LM_OK
     obs = lmfmm.far_field_angles()[::13]
     ff = geo.far_field(phi, obs).cpu().numpy()
-    for r, t in enumerate(th):
-        ref = lu_solve(K, boundary_data(med, t, el.cx, el.cy))
-        err = _rel(ff[r], far_field(med, el, ref, obs))
-        print("angle", w.angles_deg[r], "mixed far-field rel err", err, flush=True)
-        assert err < 1e-4
+    ref = np.array([far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), obs) for t in th])
+    check(ff, ref, 1e-4, "straddle3 mixed solve far field")
 
 
 def test_fp32_dense_solve_far_field_vs_oracle():
@@ -140,6 +121,4 @@ def test_fp32_dense_solve_far_field_vs_oracle():
     obs = lmfmm.far_field_angles()[::7]
     ff = geo.far_field(phi, obs).cpu().numpy()[0]
     ref = lu_solve(matrix(med, el), boundary_data(med, th[0], el.cx, el.cy))
-    err = _rel(ff, far_field(med, el, ref, obs))
-    print("plain_small mixed far-field rel err", err, flush=True)
-    assert err < 1e-4
+    check(ff, far_field(med, el, ref, obs), 1e-4, "plain_small mixed dense solve far field")

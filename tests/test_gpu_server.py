@@ -23,12 +23,9 @@ from oracle.nystrom import Elements, matrix
 from oracle.solve import lu_solve
 from paper_2511_12450_amd import lmfmm
 from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -56,11 +53,8 @@ def test_server_fp64_matches_direct_solve_and_oracle(geoms):
         med = Medium(small.d, small.k, small.eta)
         el = Elements(med, small.polygons)
         K = matrix(med, el)
-        for r, t in enumerate(th):
-            ref = far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), OBS)
-            err = _rel(ff[r], ref)
-            print("server FP64 far field vs oracle", err, flush=True)
-            assert err < 1e-6
+        ref = np.array([far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), OBS) for t in th])
+        check(ff, ref, 1e-6, "server FP64 far field vs oracle")
         # same as the direct solver on the FMM geometry
         th2 = np.radians([60.0])
         rid2 = srv.submit(g_mini, th2, tol=1e-8, max_iter=800, restart=400, precond=1, obs_rad=OBS)
@@ -70,7 +64,7 @@ def test_server_fp64_matches_direct_solve_and_oracle(geoms):
         ff_d = g_mini.far_field(phi_d, OBS).cpu().numpy()
         print("server its", rep, "direct its", rep_d, flush=True)
         assert abs(rep[0][0] - rep_d[0][0]) <= 2
-        assert _rel(ff_s[0], ff_d[0]) < 1e-6
+        check(ff_s, ff_d, 1e-6, "server vs direct solve far field")
         srv.release(rid)
         srv.release(rid2)
     finally:
@@ -102,11 +96,8 @@ def test_alone_equals_in_mix_and_fusion(geoms):
             assert st == lmfmm.LM_DONE and s == lmfmm.LM_OK, (rid, st, s)
             assert np.all(np.isfinite(ff))
             its += sum(r[0] for r in rep)
-        for r in range(2):
-            d = _rel(ffA2[r], ffA[r])
-            print(f"angle {np.degrees(thA[r]):.0f}: alone its {repA[r][0]}, in mix its {rep2[r][0]}, "
-                  f"far-field rel diff {d:.2e}", flush=True)
-            assert d < 1e-4
+        print(f"alone its {[r[0] for r in repA]}, in mix its {[r[0] for r in rep2]}", flush=True)
+        check(ffA2, ffA, 1e-4, "far field alone vs in the mix")
         stt = srv.stats()
         mix_rounds = stt["rounds"] - alone_stats["rounds"]
         mix_launches = stt["launches"] - alone_stats["launches"]
@@ -189,6 +180,62 @@ def test_admission_by_hbm_budget(geoms):
         srv.close()
 
 
+def test_memory_stays_within_budget():
+    """A stream over three geometries of different sizes under a budget that
+    holds about two requests: the device memory the server holds (bases and
+    work vectors of admitted and spare solves, fused-launch buffers, round
+    buffers) never exceeds the budget, spare solves of other shapes are freed
+    when an admission needs the room, and the fused-launch buffers of an idle
+    geometry are released."""
+    ws = [wl.three_layer_mini(seed=s, n_scat=n) for s, n in ((3, 25), (4, 18), (5, 12))]
+    print("case: memory budget, N =", [w.n_elements for w in ws], flush=True)
+    gs = [lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=1) for w in ws]
+    opts = dict(tol=1e-6, max_iter=600, restart=40)
+    rng = np.random.default_rng(5)
+    reqs = [(int(rng.integers(0, 3)), np.radians(rng.uniform(10, 170, size=int(rng.integers(1, 4)))))
+            for _ in range(10)]
+    big = max(lmfmm.request_footprint(gs[g], th.size, **opts) for g, th in reqs)
+    budget = int(2.2 * big)
+    srv = lmfmm.Server(precision=lmfmm.LM_MIXED, hbm_budget_bytes=budget)
+    try:
+        ids = []
+        peak = 0
+        for g, th in reqs:
+            ids.append((srv.submit(gs[g], th, obs_rad=OBS, **opts), g, th))
+            time.sleep(0.01)
+            peak = max(peak, srv.memory()["held"])
+        pending = list(ids)
+        t0 = time.time()
+        while pending:
+            m = srv.memory()
+            peak = max(peak, m["held"])
+            assert m["held"] <= budget, (m, budget)
+            for item in list(pending):
+                st = srv.poll(item[0])[0]
+                if st in (lmfmm.LM_DONE, lmfmm.LM_FAILED, lmfmm.LM_CANCELLED):
+                    pending.remove(item)
+            assert time.time() - t0 < 120, "requests did not finish"
+            time.sleep(0.002)
+        for rid, g, th in ids:
+            st, status, lat, rep, phi, ff = srv.wait(rid)
+            assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK, (st, status)
+            assert np.all(np.isfinite(ff))
+        time.sleep(0.05)
+        m = srv.memory()
+        print(f"budget {budget}, peak held {peak}, at rest {m}", flush=True)
+        assert peak <= budget
+        assert m["admitted"] == 0 and m["held"] == m["spare"] <= budget
+        # the last request's results against its geometry's direct solve
+        rid, g, th = ids[-1]
+        st, status, lat, rep, phi, ff = srv.wait(rid)
+        pd, rd, sd = gs[g].solve(th, tol=1e-9, max_iter=800, restart=400, precond=1)
+        check(ff, gs[g].far_field(pd, OBS).cpu().numpy(), 1e-4, "budgeted stream vs direct solve")
+    finally:
+        srv.close()
+        for g in gs:
+            g.close()
+
+
 def test_not_converged_reported(geoms):
     mini, g_mini, small, g_small = geoms
     srv = lmfmm.Server(precision=lmfmm.LM_FP64)
@@ -222,12 +269,9 @@ def test_batched_finish_matches_direct_solves(geoms):
             for rid, th, ob in zip(ids, (thA, thB, thC), (OBS, OBS, obs2)):
                 st, status, lat, rep, phi, ff = srv.wait(rid)
                 assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK, (prec, st, status)
-                for r, t in enumerate(th):
-                    want = g_mini.far_field(ref[float(t)], ob).cpu().numpy()[0]
-                    err = _rel(ff[r], want)
-                    print(f"precision {prec} angle {np.degrees(t):.0f}: its {rep[r][0]}, far field vs direct {err:.2e}",
-                          flush=True)
-                    assert err < bar
+                want = np.array([g_mini.far_field(ref[float(t)], ob).cpu().numpy()[0] for t in th])
+                print(f"precision {prec}: its {[r[0] for r in rep]}", flush=True)
+                check(ff, want, bar, f"precision {prec}: batched finish far field vs direct")
             print("rounds", srv.stats()["rounds"], flush=True)
         finally:
             srv.close()
@@ -251,10 +295,7 @@ def test_odd_n_basis_padding():
             rid = srv.submit(geo, th, tol=tol, max_iter=300, restart=300, precond=0, obs_rad=OBS)
             st, status, lat, rep, phi, ff = srv.wait(rid)
             assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK
-            for r, t in enumerate(th):
-                want = far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), OBS)
-                err = _rel(ff[r], want)
-                print(f"N={el.n} precision {prec}: far field vs oracle {err:.2e}", flush=True)
-                assert err < bar
+            want = np.array([far_field(med, el, lu_solve(K, boundary_data(med, t, el.cx, el.cy)), OBS) for t in th])
+            check(ff, want, bar, f"N={el.n} precision {prec}: far field vs oracle")
         finally:
             srv.close()

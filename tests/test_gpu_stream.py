@@ -23,14 +23,11 @@ torch = pytest.importorskip("torch")
 
 from paper_2511_12450_amd import lmfmm
 from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
 
 OBS = lmfmm.far_field_angles()[::11]
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def test_stream_of_mixed_geometries():
@@ -68,7 +65,6 @@ def test_stream_of_mixed_geometries():
         lat = np.array([done[q][2] for q in range(n_req)])
         print(f"stream: {n_req} requests, {int(n_ang.sum())} solves in {time.time() - t0:.2f} s, "
               f"latency p50 {np.percentile(lat, 50):.3f} s, p99 {np.percentile(lat, 99):.3f} s", flush=True)
-        worst = 0.0
         for q in range(n_req):
             st, status, _, rep, phi, ff = done[q]
             assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK, (q, st, status, rep)
@@ -76,10 +72,7 @@ def test_stream_of_mixed_geometries():
             ref_phi, _, rst = g.solve(angles[q], tol=1e-8, max_iter=2000, restart=500, precision=lmfmm.LM_FP64)
             assert rst == lmfmm.LM_OK
             ref = g.far_field(ref_phi, OBS).cpu().numpy()
-            for r in range(n_ang[q]):
-                worst = max(worst, _rel(ff[r], ref[r]))
-        print(f"stream: worst far-field rel err against FP64 direct solves {worst:.2e}", flush=True)
-        assert worst < 1e-4
+            check(ff, ref, 1e-4, f"stream request {q} ({n_ang[q]} angles) far field vs FP64 direct solves")
         # the request with most angles, alone on a fresh server
         q = int(np.argmax(n_ang))
         srv1 = lmfmm.Server(precision=lmfmm.LM_MIXED)
@@ -89,9 +82,7 @@ def test_stream_of_mixed_geometries():
             assert st == lmfmm.LM_DONE and status == lmfmm.LM_OK
         finally:
             srv1.close()
-        diff = _rel(phi1, done[q][4])
-        print(f"stream: request {q} ({n_ang[q]} angles) alone vs in the mix: rel diff {diff:.2e}", flush=True)
-        assert diff < 1e-6
+        check(phi1, done[q][4], 1e-6, f"stream: request {q} ({n_ang[q]} angles) phi alone vs in the mix")
     finally:
         srv.close()
         for g in geos:
