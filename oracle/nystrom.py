@@ -60,8 +60,12 @@ def self_term(k, w):
     return (0.25j - (EULER_GAMMA + np.log(k * w / 4.0) - 1.0) / (2.0 * np.pi)) * w
 
 
-def matrix_rows(med, el, rows, green=None):
-    """Rows of the unscaled dense matrix K (complex128, shape (len(rows), N))."""
+def matrix_rows(med, el, rows, green=None, chunk=None):
+    """Rows of the unscaled dense matrix K (complex128, shape (len(rows), N)).
+
+    chunk: evaluate the sources of a layer in blocks of at most this many
+    (bounds the memory of the vectorised quadrature at large N; every entry
+    is computed the same way)."""
     G = LayeredGreen(med) if green is None else green
     out = np.zeros((len(rows), el.n), dtype=complex)
     layers = range(med.L + 1)
@@ -70,14 +74,15 @@ def matrix_rows(med, el, rows, green=None):
         l = int(el.layer[i])
         x, y = el.cx[i], el.cy[i]
         for lp in layers:
-            idx = src_idx[lp]
-            if idx.size == 0:
-                continue
-            vals = G.reaction(l, lp, x, y, el.cx[idx], el.cy[idx])
-            if lp == l:
-                off = idx != i
-                vals[off] += free_space(med.k[l], x, y, el.cx[idx[off]], el.cy[idx[off]])
-            out[r, idx] = vals * el.w[idx]
+            idx_all = src_idx[lp]
+            step = idx_all.size if chunk is None else int(chunk)
+            for c0 in range(0, idx_all.size, max(step, 1)):
+                idx = idx_all[c0:c0 + step]
+                vals = G.reaction(l, lp, x, y, el.cx[idx], el.cy[idx])
+                if lp == l:
+                    off = idx != i
+                    vals[off] += free_space(med.k[l], x, y, el.cx[idx[off]], el.cy[idx[off]])
+                out[r, idx] = vals * el.w[idx]
         out[r, i] += self_term(med.k[l], el.w[i])
     return out
 

@@ -7,7 +7,8 @@ random vectors, for the 64,000-element three-layer workload and the
 Only the oracle and the seeded input generators are used.  Each row costs
 one pass of the oracle's direct Sommerfeld quadrature over every source
 (about 15 s at N = 64,000 and 20-30 minutes at N = 1,000,000), so rows run
-in parallel worker processes.
+in parallel worker processes; sources are evaluated in blocks of CHUNK to
+bound the memory of a worker.
 
 usage: python tests/golden/make_fullsize_rows.py [three_layer|five_layer] [workers]
 
@@ -34,10 +35,11 @@ from paper_2511_12450_amd import workloads as wl  # noqa: E402
 #          workload takes 20-30 minutes of the oracle)
 CASES = {
     "three_layer": (wl.three_layer, 21, 64, 4, 4, 31, 8),
-    "five_layer": (wl.five_layer, 22, 8, 2, 2, 32, 2),
+    "five_layer": (wl.five_layer, 22, 8, 4, 4, 32, 8),
 }
 
 _G = {}
+CHUNK = 20000  # sources per block of the oracle's vectorised quadrature (memory)
 
 
 def sample_rows(med, el, n_near, n_any, seed):
@@ -49,12 +51,12 @@ def sample_rows(med, el, n_near, n_any, seed):
 
 def _row(i):
     med, el, X = _G["med"], _G["el"], _G["X"]
-    return matrix_rows(med, el, [i])[0] @ X.T
+    return matrix_rows(med, el, [i], chunk=CHUNK)[0] @ X.T
 
 
 def main():
     name = sys.argv[1]
-    workers = int(sys.argv[2]) if len(sys.argv) > 2 else 1  # up to 35 GB per worker at N = 1,000,000
+    workers = int(sys.argv[2]) if len(sys.argv) > 2 else 1
     gen, vseed, nrhs, n_near, n_any, rseed, keep = CASES[name]
     w = gen()
     med = Medium(w.d, w.k, w.eta)
