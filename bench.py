@@ -65,6 +65,10 @@ def _args():
     ap.add_argument("--pool-requests", type=int, default=30, help="requests per pool stream")
     ap.add_argument("--pool-rho", type=str, default="0.5,0.9",
                     help="arrival rates of the pool streams as fractions of the pool's served capacity")
+    ap.add_argument("--replica", type=str, default="",
+                    help="run a paper replica instead of the benchmark: 'example1' (Sec. 5, Table 5.1)")
+    ap.add_argument("--replica-n", type=str, default="960,1920,3840,7680,15360",
+                    help="example1: nodes per unit length of the L-shape (N = 12.5 x this)")
     ap.add_argument("--pool-budget-gb", type=float, default=0.0,
                     help="also run the first pool stream under this HBM budget (restart 100); 0: skip")
     return ap.parse_args()
@@ -186,8 +190,71 @@ def _pool_stream(lmfmm, srv, pgeos, gi, th_q, t_arr, obs, gm_of, fref_of=None):
     return lat, its, errs, time.perf_counter() - t0
 
 
+# Table 5.1 of the paper (Example 1; CPU time, hardware not reported): N,
+# GMRES iterations without / with the preconditioner, time in s without /
+# with it, L-infinity error of the preconditioned solve.
+PAPER_TABLE_5_1 = [(12000, 140, 60, 739.71, 573.37, 2.282e-2), (24000, 163, 68, 918.03, 650.14, 1.151e-2),
+                   (48000, 190, 77, 1142.87, 783.46, 5.782e-3), (96000, 278, 86, 2110.27, 1014.66, 2.897e-3),
+                   (192000, 331, 99, 3535.53, 1501.94, 1.450e-3)]
+
+
+def replica_example1(a):
+    """Example 1 of Sec. 5: the L-shaped scatterer across four of five
+    layers (eta = 1..5, k = 3.2, 2.5, 5.1, 8.6, 6.9), manufactured solution
+    G(. | s) of a unit point source at s = (0, 0.375) inside it; FP64 GMRES
+    at tol 1e-8 with and without the preconditioner; error of the far-field
+    pattern (682 angles) against the exact one, per N."""
+    import torch
+
+    from paper_2511_12450_amd import lmfmm
+    from paper_2511_12450_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    obs = lmfmm.far_field_angles()
+    src = np.array([[0.0, 0.375]])
+    rows = []
+    for n in [int(v) for v in a.replica_n.split(",") if v]:
+        w = wl.paper_example1(n_per_side_unit=n)
+        t0 = time.perf_counter()
+        geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        g = geo.point_source_rhs(src)
+        exact = lmfmm.point_far_field(geo.layers, src, obs).cpu().numpy()[0]
+        row = {"N": int(geo.n), "setup_s": setup}
+        for pc, key in ((1, "preconditioned"), (0, "plain")):
+            t1 = time.perf_counter()
+            phi, rep, st = geo.solve_rhs(g, tol=1e-8, max_iter=5000, restart=1000, precond=pc)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t1
+            ff = geo.far_field(phi, obs).cpu().numpy()[0]
+            row[key] = {"iterations": int(rep[0][0]), "solve_s": ts, "status": int(st),
+                        "far_field_err_l2": _rel(ff, exact),
+                        "far_field_err_linf": float(np.abs(ff - exact).max() / np.abs(exact).max())}
+        _log(f"example1 N={geo.n}: its {row['preconditioned']['iterations']} / {row['plain']['iterations']}, "
+             f"far-field err {row['preconditioned']['far_field_err_linf']:.3e}, setup {setup:.1f} s")
+        rows.append(row)
+        geo.close()
+        torch.cuda.empty_cache()
+    for i in range(1, len(rows)):
+        p0, p1 = rows[i - 1]["preconditioned"], rows[i]["preconditioned"]
+        rows[i]["ratio_linf"] = p0["far_field_err_linf"] / p1["far_field_err_linf"]
+        rows[i]["ratio_l2"] = p0["far_field_err_l2"] / p1["far_field_err_l2"]
+    print(json.dumps({"replica": "example1", "workload": "L-shape across 4 of 5 layers, eta 1..5, point source "
+                      "(0, 0.375), FP64, GMRES tol 1e-8", "rows": rows,
+                      "paper_table_5_1": [dict(zip(("N", "its", "its_preconditioned", "time_s",
+                                                    "time_s_preconditioned", "linf_error"), r))
+                                          for r in PAPER_TABLE_5_1],
+                      "paper_hardware": "not reported (CPU time)"}))
+
+
 def main():
     a = _args()
+    if a.replica:
+        if a.replica != "example1":
+            sys.exit(f"unknown replica {a.replica}")
+        replica_example1(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "lmfmm runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus": a.gpus}))

@@ -244,6 +244,30 @@ lm_status lm_gmres_solve_rhs(lm_geom geom, int precision, int n_rhs, const void*
 lm_status lm_far_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_obs, const double* obs_host,
                        void* out_dev, void* hip_stream);
 
+/* --------------------------------------------------------- point sources --
+ * The layered Green's function G(r | s) (Sec. 3.1, eq. layeredGreensfun:
+ * the free-space part when r and s share a layer plus the reaction
+ * components of eq. fourreactions) is the field at r of a unit point source
+ * at s.  It satisfies every transmission condition and radiates, so with s
+ * inside a scatterer its boundary values are the data of an exterior problem
+ * whose solution is G(. | s) (the manufactured solution of Sec. 5, Example 1),
+ * and with s outside every scatterer -G(. | s) on the boundary is the data of
+ * a point-source incident field.
+ *
+ * lm_point_source_rhs: g[r][i] = G(c_i | s_r) at the collocation points for
+ * n_src sources src_xy_host[2 r], src_xy_host[2 r + 1] (host; a source's layer
+ * follows the element rule, ties to the upper layer); the reaction part by
+ * direct Sommerfeld quadrature in FP64.  g_dev: device c128 [n_src][N].
+ * Errors: LM_EINVAL for a non-finite source or one that coincides with a
+ * collocation point. */
+lm_status lm_point_source_rhs(lm_geom geom, int n_src, const double* src_xy_host, void* g_dev, void* hip_stream);
+/* Far-field patterns of unit point sources (the far field of G(. | s_r), in
+ * the convention of lm_far_field: u ~ e^{i k R}/sqrt(R) u_inf, top layer for
+ * 0 < t < pi, bottom layer for pi < t < 2 pi).  out_dev: device c128
+ * [n_src][n_obs]. */
+lm_status lm_point_far_field(lm_layers layers, int n_src, const double* src_xy_host, int n_obs,
+                             const double* obs_host, void* out_dev, void* hip_stream);
+
 /* --------------------------------------------------------------- serving --
  * Request-serving loop with continuous batching (one worker thread per
  * server, on the device current at lm_server_create).  A request is a

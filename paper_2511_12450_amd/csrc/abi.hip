@@ -78,15 +78,6 @@ int64_t lm_geom_s::device_bytes() const {
   return b;
 }
 
-// Layer of a height y: l with -d_l < y < -d_{l-1}; within 1e-12 of an
-// interface the point belongs to the upper layer.
-static int layer_of(const MediumDev& m, double y) {
-  int l = 0;
-  for (int j = 0; j < m.L; ++j)
-    if (y < -m.d[j] - 1e-12) l = j + 1;
-  return l;
-}
-
 extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* off,
                                         const double* nodes, const lm_geom_opts* opts, void* hip_stream,
                                         lm_geom* out) {

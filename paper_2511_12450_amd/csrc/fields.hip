@@ -158,3 +158,32 @@ lm_status farfield_launch(lm_geom_s* g, int R, const void* phi, int n_obs, const
   LM_TRY_HIP(hipStreamSynchronize(s));
   return LM_OK;
 }
+
+// Far-field patterns of unit point sources: the same sum with one term per
+// source (weight 1, density 1): source r is "element" r and the density of
+// right-hand side r is the r-th unit vector.
+lm_status point_far_field_launch(const MediumDev& m, int R, const double* src_xy_host, int n_obs,
+                                 const double* obs_host, void* out, hipStream_t s) {
+  std::vector<double> x(R), y(R), w(R, 1.0);
+  std::vector<int32_t> lay(R);
+  std::vector<double2> eye((size_t)R * R, make_double2(0.0, 0.0));
+  for (int r = 0; r < R; ++r) {
+    x[r] = src_xy_host[2 * r];
+    y[r] = src_xy_host[2 * r + 1];
+    lay[r] = layer_of(m, y[r]);
+    eye[(size_t)r * R + r] = make_double2(1.0, 0.0);
+  }
+  DevBuf ob, dx, dy, dw, dl, dphi;
+  LM_TRY(upload(ob, obs_host, n_obs * sizeof(double), s));
+  LM_TRY(upload(dx, x.data(), R * sizeof(double), s));
+  LM_TRY(upload(dy, y.data(), R * sizeof(double), s));
+  LM_TRY(upload(dw, w.data(), R * sizeof(double), s));
+  LM_TRY(upload(dl, lay.data(), R * sizeof(int32_t), s));
+  LM_TRY(upload(dphi, eye.data(), eye.size() * sizeof(double2), s));
+  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, m, R, R, ob.as<double>(),
+                     dx.as<double>(), dy.as<double>(), dw.as<double>(), dl.as<int>(), dphi.as<double2>(),
+                     (double2*)out, n_obs);
+  LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+  return LM_OK;
+}

@@ -73,6 +73,15 @@ struct lm_layers_s {
   MediumDev m;
 };
 
+// Layer of a height y: l with -d_l < y < -d_{l-1}; within 1e-12 of an
+// interface the point belongs to the upper layer.
+inline int layer_of(const MediumDev& m, double y) {
+  int l = 0;
+  for (int j = 0; j < m.L; ++j)
+    if (y < -m.d[j] - 1e-12) l = j + 1;
+  return l;
+}
+
 // ----------------------------------------------------------------- geometry --
 struct FmmPlan;   // fmm.hip
 struct Precond;   // precond.hip
@@ -108,6 +117,8 @@ lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, voi
 lm_status rhs_launch(lm_geom_s* g, int n_rhs, const double* theta_host, void* g_dev, hipStream_t s);
 lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_host,
                           void* out, hipStream_t s);
+lm_status point_far_field_launch(const MediumDev& m, int n_src, const double* src_xy_host, int n_obs,
+                                 const double* obs_host, void* out, hipStream_t s);
 struct KmBufs {
   DevBuf x32, y32, mz;
   hipEvent_t* stage_ev = nullptr;  // when set: 16 events bracketing the FMM stages (see fmm_matvec_timed)

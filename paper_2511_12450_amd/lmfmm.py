@@ -79,6 +79,8 @@ _SIGS = {
     "lm_gmres_solve_rhs": ([_vp, _ip, _ip, _vp, ctypes.POINTER(GmresOpts), _vp, ctypes.POINTER(SolveReport), _vp],
                            _ip),
     "lm_far_field": ([_vp, _ip, _vp, _ip, _dp, _vp, _vp], _ip),
+    "lm_point_source_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
+    "lm_point_far_field": ([_vp, _ip, _dp, _ip, _dp, _vp, _vp], _ip),
     "lm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)], _ip),
     "lm_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _ip),
     "lm_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport), _dp, _vp, _vp], _ip),
@@ -289,6 +291,15 @@ class Geometry:
                                              rep, _stream()))
         return phi, [(r.iterations, r.rel_residual) for r in rep], st
 
+    def point_source_rhs(self, src_xy):
+        """G(c_i | s_r) at the collocation points for point sources s_r
+        (lm_point_source_rhs); src_xy: (n_src, 2)."""
+        import torch
+        sxy = np.ascontiguousarray(np.atleast_2d(src_xy), dtype=np.float64)
+        g = torch.empty((sxy.shape[0], self.n), dtype=torch.complex128, device="cuda")
+        _check(lib().lm_point_source_rhs(self.h, sxy.shape[0], _dptr(sxy), _tptr(g), _stream()))
+        return g
+
     def far_field(self, phi, obs_rad):
         import torch
         phi = phi.reshape(-1, self.n).contiguous()
@@ -296,6 +307,17 @@ class Geometry:
         out = torch.empty((phi.shape[0], ob.size), dtype=torch.complex128, device="cuda")
         _check(lib().lm_far_field(self.h, phi.shape[0], _tptr(phi), ob.size, _dptr(ob), _tptr(out), _stream()))
         return out
+
+
+def point_far_field(layers, src_xy, obs_rad):
+    """Far-field patterns of unit point sources (lm_point_far_field), device
+    complex128 [n_src][n_obs]."""
+    import torch
+    sxy = np.ascontiguousarray(np.atleast_2d(src_xy), dtype=np.float64)
+    ob = np.ascontiguousarray(np.atleast_1d(obs_rad), dtype=np.float64)
+    out = torch.empty((sxy.shape[0], ob.size), dtype=torch.complex128, device="cuda")
+    _check(lib().lm_point_far_field(layers.h, sxy.shape[0], _dptr(sxy), ob.size, _dptr(ob), _tptr(out), _stream()))
+    return out
 
 
 def far_field_angles():

@@ -1,0 +1,98 @@
+"""The paper's Example 1 (Sec. 5, Table 5.1) through the C-ABI: an L-shaped
+scatterer crossing four of the five layers of a medium with eta = 1..5, and
+the manufactured exterior solution u^s = G(. | s) of a unit point source at
+s = (0, 0.375) inside the scatterer.
+
+* lm_point_source_rhs (boundary values of G(. | s)) and lm_point_far_field
+  (far-field pattern of G(. | s)) against the oracle, entry by entry;
+* the solved far field converges to the exact one at first order in the
+  element length (the paper's Table 5.1 shows error ratios of about 2 per
+  doubling of N); the paper measures errors at points it does not name, the
+  far-field pattern on 682 angles is used here;
+* the preconditioner of Sec. 4.2 reduces the iteration count.
+"""
+
+import types
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.farfield import far_field
+from oracle.green import LayeredGreen
+from oracle.medium import Medium
+from oracle.nystrom import Elements
+from paper_2511_12450_amd import lmfmm
+from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
+
+pytestmark = pytest.mark.gpu
+
+SRC = np.array([[0.0, 0.375]])
+
+
+def _oracle_point_values(med, el, s):
+    """G(c_i | s) from the oracle, through eta-weighted reciprocity
+    eta_l G_{l l'}(r, r') = eta_{l'} G_{l' l}(r', r): one oracle call per
+    layer with the source point as the target."""
+    G = LayeredGreen(med)
+    ls = int(med.layer_of(np.array([s[1]]))[0])
+    out = np.zeros(el.n, dtype=complex)
+    for l in range(med.L + 1):
+        idx = np.nonzero(el.layer == l)[0]
+        if idx.size:
+            # eta_l G_{l ls}(c, s) = eta_ls G_{ls l}(s, c)
+            out[idx] = med.eta[ls] / med.eta[l] * G.green(s[0], s[1], el.cx[idx], el.cy[idx], l=ls, lp=l)
+    return out
+
+
+def test_point_source_values_and_far_field_vs_oracle():
+    w = wl.paper_example1(n_per_side_unit=24)
+    print(f"case: example1 point source, N={w.n_elements}", flush=True)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0)
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    srcs = np.array([[0.0, 0.375], [-0.2, -1.7], [1.9, -2.2]])  # layers 0, 2, 3 (inside the L)
+    g = geo.point_source_rhs(srcs).cpu().numpy()
+    ref = np.array([_oracle_point_values(med, el, s) for s in srcs])
+    check(g, ref, 1e-10, "point-source boundary values vs oracle")
+    obs = lmfmm.far_field_angles()[::9]
+    ff = lmfmm.point_far_field(geo.layers, srcs, obs).cpu().numpy()
+    fref = []
+    for s in srcs:
+        pt = types.SimpleNamespace(cx=s[:1], cy=s[1:], w=np.ones(1), layer=med.layer_of(s[1:]), n=1)
+        fref.append(far_field(med, pt, np.ones(1), obs))
+    check(ff, np.array(fref), 1e-12, "point-source far field vs oracle")
+
+
+def test_example1_first_order_and_preconditioner():
+    obs = lmfmm.far_field_angles()
+    errs, its = [], []
+    lay = None
+    for n in (120, 240, 480, 960):
+        w = wl.paper_example1(n_per_side_unit=n)
+        geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+        lay = geo.layers
+        g = geo.point_source_rhs(SRC)
+        exact = lmfmm.point_far_field(lay, SRC, obs).cpu().numpy()[0]
+        row = []
+        for pc in (1, 0):
+            phi, rep, st = geo.solve_rhs(g, tol=1e-10, max_iter=3000, restart=1000, precond=pc)
+            assert st == lmfmm.LM_OK, (n, pc, rep)
+            row.append(rep[0][0])
+            if pc == 1:
+                ff = geo.far_field(phi, obs).cpu().numpy()[0]
+                e2 = float(np.linalg.norm(ff - exact) / np.linalg.norm(exact))
+                einf = float(np.abs(ff - exact).max() / np.abs(exact).max())
+                errs.append((e2, einf))
+        its.append(row)
+        print(f"example1 N={geo.n}: iterations with / without the preconditioner {row}, "
+              f"far-field error L2 {errs[-1][0]:.3e} Linf {errs[-1][1]:.3e}", flush=True)
+        geo.close()
+    e = np.array(errs)
+    ratios = e[:-1] / e[1:]
+    print("error ratios per doubling (L2, Linf):", np.round(ratios, 2).tolist(), flush=True)
+    assert np.all(ratios[-2:] > 1.6) and np.all(ratios[-2:] < 2.6)
+    for with_pc, without in its:
+        assert with_pc < without
