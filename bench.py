@@ -66,7 +66,8 @@ def _args():
     ap.add_argument("--pool-rho", type=str, default="0.5,0.9",
                     help="arrival rates of the pool streams as fractions of the pool's served capacity")
     ap.add_argument("--replica", type=str, default="",
-                    help="run a paper replica instead of the benchmark: 'example1' (Sec. 5, Table 5.1)")
+                    help="run a paper replica instead of the benchmark: 'example1', 'example2' or 'example3' "
+                         "(Sec. 5, Tables 5.1-5.3)")
     ap.add_argument("--replica-n", type=str, default="960,1920,3840,7680,15360",
                     help="example1: nodes per unit length of the L-shape (N = 12.5 x this)")
     ap.add_argument("--pool-budget-gb", type=float, default=0.0,
@@ -248,12 +249,69 @@ def replica_example1(a):
                       "paper_hardware": "not reported (CPU time)"}))
 
 
+# Tables 5.2 and 5.3 of the paper (Examples 2 and 3; CPU time, hardware not
+# reported): N, iterations without / with the preconditioner, time in s
+# without / with it.
+PAPER_TABLE_5_2 = [(12000, 93, 59, 1628.33, 1362.33), (24000, 104, 66, 1822.82, 1520.70),
+                   (48000, 115, 72, 2429.23, 1685.44), (96000, 132, 81, 3042.68, 2058.86),
+                   (192000, 162, 93, 3807.98, 2827.82)]
+PAPER_TABLE_5_3 = [(12000, 125, 71, 1638.88, 1553.62), (24000, 138, 79, 1742.52, 1639.49),
+                   (48000, 156, 88, 2031.50, 1831.76), (96000, 173, 101, 2708.44, 2649.50),
+                   (192000, 192, 112, 3782.74, 3056.38)]
+
+
+def replica_plane_wave(a, which):
+    """Examples 2 and 3 of Sec. 5 (plane-wave incidence, no closed-form
+    solution): FP64 GMRES at tol 1e-8 with and without the preconditioner
+    per N, and the self-convergence of the far-field pattern (682 angles):
+    the difference to the next finer N, whose ratio per doubling is about 2
+    at first order."""
+    import torch
+
+    from paper_2511_12450_amd import lmfmm
+    from paper_2511_12450_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    gen, table = (wl.paper_example2, PAPER_TABLE_5_2) if which == "example2" else (wl.paper_example3, PAPER_TABLE_5_3)
+    obs = lmfmm.far_field_angles()
+    rows, ffs = [], []
+    for n_el in [int(12.5 * int(v)) for v in a.replica_n.split(",") if v]:
+        w = gen(n_el)
+        t0 = time.perf_counter()
+        geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+        torch.cuda.synchronize()
+        row = {"N": int(geo.n), "setup_s": time.perf_counter() - t0}
+        th = np.radians(w.angles_deg)
+        for pc, key in ((1, "preconditioned"), (0, "plain")):
+            t1 = time.perf_counter()
+            phi, rep, st = geo.solve(th, tol=1e-8, max_iter=5000, restart=1000, precond=pc)
+            torch.cuda.synchronize()
+            row[key] = {"iterations": int(rep[0][0]), "solve_s": time.perf_counter() - t1, "status": int(st)}
+            if pc == 1:
+                ffs.append(geo.far_field(phi, obs).cpu().numpy()[0])
+        _log(f"{which} N={geo.n}: its {row['preconditioned']['iterations']} / {row['plain']['iterations']}")
+        rows.append(row)
+        geo.close()
+        torch.cuda.empty_cache()
+    for i in range(len(rows) - 1):
+        rows[i]["far_field_diff_to_next"] = _rel(ffs[i], ffs[i + 1])
+    for i in range(1, len(rows) - 1):
+        rows[i]["diff_ratio"] = rows[i - 1]["far_field_diff_to_next"] / rows[i]["far_field_diff_to_next"]
+    print(json.dumps({"replica": which, "workload": gen.__doc__.split(":")[0].strip(), "rows": rows,
+                      "paper_table": [dict(zip(("N", "its", "its_preconditioned", "time_s", "time_s_preconditioned"),
+                                               r)) for r in table],
+                      "paper_hardware": "not reported (CPU time)"}))
+
+
 def main():
     a = _args()
     if a.replica:
-        if a.replica != "example1":
+        if a.replica == "example1":
+            replica_example1(a)
+        elif a.replica in ("example2", "example3"):
+            replica_plane_wave(a, a.replica)
+        else:
             sys.exit(f"unknown replica {a.replica}")
-        replica_example1(a)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "lmfmm runs on one GPU; sharding across GPUs is not implemented",

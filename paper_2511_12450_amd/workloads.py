@@ -248,6 +248,33 @@ def paper_example1(n_per_side_unit=40):
                     np.array([1.0, 2.0, 3.0, 4.0, 5.0]), [P], np.array([90.0]), extra={"source": (0.0, 0.375)})
 
 
+def paper_example2(n_elements=12000):
+    """Example 2 geometry (Sec. 5): six layers, interfaces y = 0, -1, -2, -3,
+    -4, eta = (1.1, 2.3, 3.4, 4.6, 5.0, 6.6), k = (1.2, 2.3, 4.5, 6.1, 7.7,
+    10.0); two "peanuts" of eq. scattererpara (a = 0.5, b = 1, petal number 2,
+    theta0 = pi/4) centred at (0, -1) and (2, -3), n_elements / 2 nodes each;
+    incident wave e^{i(-3 sqrt(2)/5)(x + y)}: k_0 = 1.2 travelling along
+    (-1, -1)/sqrt(2), i.e. theta = 135 deg."""
+    m = n_elements // 2
+    polys = [flower((0.0, -1.0), 0.5, 1.0, 2, np.pi / 4, m), flower((2.0, -3.0), 0.5, 1.0, 2, np.pi / 4, m)]
+    return Workload("paper_example2", np.array([0.0, 1.0, 2.0, 3.0, 4.0]),
+                    np.array([1.2, 2.3, 4.5, 6.1, 7.7, 10.0]), np.array([1.1, 2.3, 3.4, 4.6, 5.0, 6.6]), polys,
+                    np.array([135.0]))
+
+
+def paper_example3(n_elements=12000):
+    """Example 3 geometry (Sec. 5): six layers, interfaces y = 0, -1, -2, -3,
+    -4, eta = (1, 2, 3, 4, 5, 6), k = (2, 3, 6, 5, 8, 10); five 5-petal
+    flowers of eq. scattererpara (a = 0.2, b = 0.7, theta0 = 0) centred at
+    (-1.5, 0), (1.5, 0), (0, -2), (-1.5, -4) and, as printed, (1.5, 4),
+    n_elements / 5 nodes each; incident wave e^{-2iy}: theta = 90 deg."""
+    m = n_elements // 5
+    cs = [(-1.5, 0.0), (1.5, 0.0), (0.0, -2.0), (-1.5, -4.0), (1.5, 4.0)]
+    polys = [flower(c, 0.2, 0.7, 5, 0.0, m) for c in cs]
+    return Workload("paper_example3", np.array([0.0, 1.0, 2.0, 3.0, 4.0]), np.array([2.0, 3.0, 6.0, 5.0, 8.0, 10.0]),
+                    np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0]), polys, np.array([90.0]))
+
+
 def random_vector(n, seed, n_rhs=1):
     """Seeded complex Gaussian vectors, shape (n_rhs, n)."""
     rng = np.random.default_rng(seed)

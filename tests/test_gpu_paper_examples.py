@@ -1,4 +1,4 @@
-"""The paper's Example 1 (Sec. 5, Table 5.1) through the C-ABI: an L-shaped
+"""The paper's Examples 1-3 (Sec. 5, Tables 5.1-5.3) through the C-ABI.  Example 1: an L-shaped
 scatterer crossing four of the five layers of a medium with eta = 1..5, and
 the manufactured exterior solution u^s = G(. | s) of a unit point source at
 s = (0, 0.375) inside the scatterer.
@@ -96,3 +96,32 @@ def test_example1_first_order_and_preconditioner():
     assert np.all(ratios[-2:] > 1.6) and np.all(ratios[-2:] < 2.6)
     for with_pc, without in its:
         assert with_pc < without
+
+
+@pytest.mark.parametrize("which", ["example2", "example3"])
+def test_examples_2_and_3_self_convergence(which):
+    """Examples 2 and 3 (six eta != 1 layers, plane-wave incidence, no closed
+    form): the far-field pattern's difference to the next finer N halves per
+    doubling (first order), and the preconditioner reduces the iterations."""
+    gen = wl.paper_example2 if which == "example2" else wl.paper_example3
+    obs = lmfmm.far_field_angles()
+    ffs, its = [], []
+    for n_el in (3000, 6000, 12000, 24000):
+        w = gen(n_el)
+        geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM)
+        th = np.radians(w.angles_deg)
+        row = []
+        for pc in (1, 0):
+            phi, rep, st = geo.solve(th, tol=1e-10, max_iter=3000, restart=1000, precond=pc)
+            assert st == lmfmm.LM_OK, (which, n_el, pc, rep)
+            row.append(rep[0][0])
+            if pc == 1:
+                ffs.append(geo.far_field(phi, obs).cpu().numpy()[0])
+        its.append(row)
+        geo.close()
+    d = [float(np.linalg.norm(ffs[i] - ffs[i + 1]) / np.linalg.norm(ffs[i + 1])) for i in range(3)]
+    ratios = [d[i] / d[i + 1] for i in range(2)]
+    print(f"{which}: iterations (with, without) {its}, far-field differences {np.round(d, 8).tolist()}, "
+          f"ratios {np.round(ratios, 2).tolist()}", flush=True)
+    assert all(1.6 < r < 2.6 for r in ratios)
+    assert all(a < b for a, b in its)
