@@ -268,6 +268,27 @@ lm_status lm_point_source_rhs(lm_geom geom, int n_src, const double* src_xy_host
 lm_status lm_point_far_field(lm_layers layers, int n_src, const double* src_xy_host, int n_obs,
                              const double* obs_host, void* out_dev, void* hip_stream);
 
+/* ------------------------------------------------------- off the boundary --
+ * Scattered field at receivers off the boundary (eq. integralrep, unscaled
+ * form): u^s(p) = sum_e |Gamma_e| phi_e G(p | c_e) with the layered Green's
+ * function, for n_rhs densities phi_dev (device c128 [n_rhs][N], e.g. from
+ * lm_gmres_solve) at n_pts receivers pts_xy_host (host, (x, y) pairs).
+ * Free-space part by a direct sum over the elements of the receiver's layer
+ * (O(N) per receiver); reaction part by the spectral form of the components:
+ * source spectra sum_e |Gamma_e| phi_e e^{-+i lam x_e} e^{i k_{l',y} h_s(e)} on
+ * the nodes of the Sommerfeld contour, then one pass over the nodes per
+ * receiver.  The number of nodes grows like (extent of sources and receivers)
+ * / (distance of the receiver to the interface its arriving waves come from),
+ * receivers being grouped by that distance in powers of two.  FP64.
+ * out_dev: device c128 [n_rhs][n_pts].  Errors: LM_EINVAL for a receiver
+ * within 1e-4 of an interface or non-finite coordinates. */
+lm_status lm_field(lm_geom geom, int n_rhs, const void* phi_dev, int n_pts, const double* pts_xy_host,
+                   void* out_dev, void* hip_stream);
+/* G(p | s_r) at n_pts receivers for n_src unit point sources (the same
+ * evaluation with one term per source).  out_dev: device c128 [n_src][n_pts]. */
+lm_status lm_point_field(lm_layers layers, int n_src, const double* src_xy_host, int n_pts,
+                         const double* pts_xy_host, void* out_dev, void* hip_stream);
+
 /* --------------------------------------------------------------- serving --
  * Request-serving loop with continuous batching (one worker thread per
  * server, on the device current at lm_server_create).  A request is a

@@ -81,6 +81,8 @@ _SIGS = {
     "lm_far_field": ([_vp, _ip, _vp, _ip, _dp, _vp, _vp], _ip),
     "lm_point_source_rhs": ([_vp, _ip, _dp, _vp, _vp], _ip),
     "lm_point_far_field": ([_vp, _ip, _dp, _ip, _dp, _vp, _vp], _ip),
+    "lm_field": ([_vp, _ip, _vp, _ip, _dp, _vp, _vp], _ip),
+    "lm_point_field": ([_vp, _ip, _dp, _ip, _dp, _vp, _vp], _ip),
     "lm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)], _ip),
     "lm_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _ip),
     "lm_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport), _dp, _vp, _vp], _ip),
@@ -300,6 +302,16 @@ class Geometry:
         _check(lib().lm_point_source_rhs(self.h, sxy.shape[0], _dptr(sxy), _tptr(g), _stream()))
         return g
 
+    def field(self, phi, pts_xy):
+        """Scattered field of densities phi at receivers pts_xy (n, 2)
+        (lm_field): device complex128 [n_rhs][n_pts]."""
+        import torch
+        phi = phi.reshape(-1, self.n).contiguous()
+        p = np.ascontiguousarray(np.atleast_2d(pts_xy), dtype=np.float64)
+        out = torch.empty((phi.shape[0], p.shape[0]), dtype=torch.complex128, device="cuda")
+        _check(lib().lm_field(self.h, phi.shape[0], _tptr(phi), p.shape[0], _dptr(p), _tptr(out), _stream()))
+        return out
+
     def far_field(self, phi, obs_rad):
         import torch
         phi = phi.reshape(-1, self.n).contiguous()
@@ -317,6 +329,17 @@ def point_far_field(layers, src_xy, obs_rad):
     ob = np.ascontiguousarray(np.atleast_1d(obs_rad), dtype=np.float64)
     out = torch.empty((sxy.shape[0], ob.size), dtype=torch.complex128, device="cuda")
     _check(lib().lm_point_far_field(layers.h, sxy.shape[0], _dptr(sxy), ob.size, _dptr(ob), _tptr(out), _stream()))
+    return out
+
+
+def point_field(layers, src_xy, pts_xy):
+    """G(p | s) of unit point sources at receivers (lm_point_field), device
+    complex128 [n_src][n_pts]."""
+    import torch
+    sxy = np.ascontiguousarray(np.atleast_2d(src_xy), dtype=np.float64)
+    p = np.ascontiguousarray(np.atleast_2d(pts_xy), dtype=np.float64)
+    out = torch.empty((sxy.shape[0], p.shape[0]), dtype=torch.complex128, device="cuda")
+    _check(lib().lm_point_field(layers.h, sxy.shape[0], _dptr(sxy), p.shape[0], _dptr(p), _tptr(out), _stream()))
     return out
 
 
