@@ -17,7 +17,7 @@ import numpy as np
 from scipy.special import hankel1
 
 from .medium import nonzero_components
-from .quadrature import bin_index, node_set, sommerfeld
+from .quadrature import bin_index, node_set, sommerfeld, sommerfeld_dx
 
 
 def free_space(k, x, y, xs, ys, dy=False):
@@ -30,6 +30,17 @@ def free_space(k, x, y, xs, ys, dy=False):
         return g
     dg = -0.25j * k * hankel1(1, k * rho) * ry / rho
     return g, dg
+
+
+def free_space_grad(k, x, y, xs, ys):
+    """(i/4) H_0^(1)(k |r - r'|) and its gradient in the target r:
+    -(i/4) k H_1^(1)(k rho) (r - r') / rho."""
+    rx = np.asarray(x) - np.asarray(xs)
+    ry = np.asarray(y) - np.asarray(ys)
+    rho = np.hypot(rx, ry)
+    g = 0.25j * hankel1(0, k * rho)
+    d = -0.25j * k * hankel1(1, k * rho) / rho
+    return g, d * rx, d * ry
 
 
 class _SigmaCache:
@@ -109,6 +120,69 @@ class LayeredGreen:
         if dy:
             return out, dout
         return out
+
+    def reaction_component_grad(self, comp, l, lp, x, y, xs, ys):
+        """One reaction component and its gradient in the target (x, y).
+        d/dx acts on e^{i lam (x - x')} through the sign of x - x' and the
+        X-derivative of the folded integral; d/dy on e^{i Theta} through
+        dTheta/dy = k_{l,y} dA/dy (dA/dy = +-1)."""
+        med = self.med
+        xs = np.atleast_1d(np.asarray(xs, dtype=float))
+        ys = np.atleast_1d(np.asarray(ys, dtype=float))
+        A, B = med.theta_coeffs(comp, l, lp, y, ys)
+        A = np.broadcast_to(np.asarray(A, dtype=float), ys.shape)
+        B = np.broadcast_to(np.asarray(B, dtype=float), ys.shape)
+        dAdy = med.theta_coeffs(comp, l, lp, y + 1.0, ys)[0] - A
+        D = np.maximum(A + B, 0.0)
+        X = np.abs(x - xs)
+        sgn = np.sign(x - xs)
+        g = np.zeros(xs.shape, dtype=complex)
+        gx = np.zeros(xs.shape, dtype=complex)
+        gy = np.zeros(xs.shape, dtype=complex)
+        ib_x, ib_d = bin_index(X), bin_index(D)
+        keys = ib_x.astype(np.int64) * 1000 + (ib_d.astype(np.int64) + 500)
+        for key in np.unique(keys):
+            sel = np.nonzero(keys == key)[0]
+            ix, idd = int(ib_x[sel[0]]), int(ib_d[sel[0]])
+            nodes, groups = self.cache.get(l, lp, ix, idd)
+            if all(gg is None or not np.any(gg[2][comp]) for gg in groups):
+                continue
+            facs, dfacs = [], []
+            for gg in groups:
+                if gg is None:
+                    facs.append(None)
+                    dfacs.append(None)
+                    continue
+                kyl, kylp, sig = gg
+                ph = np.exp(1j * (kyl[None, :] * A[sel, None] + kylp[None, :] * B[sel, None]))
+                f = ph * sig[comp][None, :]
+                facs.append(f)
+                dfacs.append(f * (1j * kyl[None, :]) * dAdy[sel, None])
+            g[sel] = sommerfeld(X[sel], facs[0], facs[1], facs[2], nodes)
+            gx[sel] = sgn[sel] * sommerfeld_dx(X[sel], facs[0], facs[1], facs[2], nodes)
+            gy[sel] = sommerfeld(X[sel], dfacs[0], dfacs[1], dfacs[2], nodes)
+        return g, gx, gy
+
+    def green_grad(self, x, y, xs, ys, l, lp):
+        """G_{l l'}(r | r') and its gradient in the target r, for one target
+        and an array of sources in layer l'."""
+        med = self.med
+        xs = np.atleast_1d(np.asarray(xs, dtype=float))
+        ys = np.atleast_1d(np.asarray(ys, dtype=float))
+        g = np.zeros(xs.shape, dtype=complex)
+        gx = np.zeros(xs.shape, dtype=complex)
+        gy = np.zeros(xs.shape, dtype=complex)
+        for c in nonzero_components(l, lp, med.L):
+            a, b, cc = self.reaction_component_grad(c, l, lp, x, y, xs, ys)
+            g += a
+            gx += b
+            gy += cc
+        if l == lp:
+            a, b, cc = free_space_grad(med.k[l], x, y, xs, ys)
+            g += a
+            gx += b
+            gy += cc
+        return g, gx, gy
 
     def reaction(self, l, lp, x, y, xs, ys, dy=False):
         """G^r_{l l'}: sum of the non-zero components (Remark: 4L^2 of them)."""

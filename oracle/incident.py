@@ -60,3 +60,22 @@ def background(med, theta, x, y, dy=False):
 def boundary_data(med, theta, x, y):
     """g at collocation points (eq. homogeneousscattering)."""
     return -incident(med, theta, x, y) - background(med, theta, x, y)
+
+
+def boundary_data_bc(med, theta, x, y, nx, ny, beta=None):
+    """Data of the sound-hard (beta None) or impedance condition
+    (d_n + i beta) u = 0 with u = u^inc + u^b + u^s: the right side
+    -(d_n + i beta)(u^inc + u^b) at points with normals (nx, ny)."""
+    x = np.asarray(x, dtype=float)
+    y = np.asarray(y, dtype=float)
+    kx = med.k[0] * np.cos(theta)
+    k0y = med.k[0] * np.sin(theta)
+    ui = incident(med, theta, x, y)
+    ub, dub = background(med, theta, x, y, dy=True)
+    u = ui + ub
+    ux = 1j * kx * u
+    uy = -1j * k0y * ui + dub
+    g = -(np.asarray(nx) * ux + np.asarray(ny) * uy)
+    if beta is not None:
+        g = g - 1j * beta * u
+    return g

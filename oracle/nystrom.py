@@ -28,15 +28,18 @@ so a test can check both give the same phi.
 import numpy as np
 
 from .green import LayeredGreen, free_space
+from .medium import nonzero_components
 
 EULER_GAMMA = 0.57721566490153286061
 
 
 class Elements:
-    """Chord elements of closed polygons (one polygon per scatterer)."""
+    """Chord elements of closed polygons (one polygon per scatterer), with the
+    unit normal of every chord pointing out of its polygon (the sign of the
+    polygon's signed area decides the orientation)."""
 
     def __init__(self, med, polygons):
-        cx, cy, w, sid = [], [], [], []
+        cx, cy, w, sid, nx, ny = [], [], [], [], [], []
         for j, P in enumerate(polygons):
             P = np.asarray(P, dtype=float)
             if P.ndim != 2 or P.shape[1] != 2 or P.shape[0] < 3:
@@ -44,8 +47,15 @@ class Elements:
             Q = np.roll(P, -1, axis=0)
             cx.append(0.5 * (P[:, 0] + Q[:, 0]))
             cy.append(0.5 * (P[:, 1] + Q[:, 1]))
-            w.append(np.hypot(Q[:, 0] - P[:, 0], Q[:, 1] - P[:, 1]))
+            ln = np.hypot(Q[:, 0] - P[:, 0], Q[:, 1] - P[:, 1])
+            w.append(ln)
             sid.append(np.full(P.shape[0], j))
+            area2 = np.sum(P[:, 0] * Q[:, 1] - Q[:, 0] * P[:, 1])  # twice the signed area
+            o = 1.0 if area2 > 0 else -1.0  # counter-clockwise: the right-hand normal points out
+            nx.append(o * (Q[:, 1] - P[:, 1]) / ln)
+            ny.append(-o * (Q[:, 0] - P[:, 0]) / ln)
+        self.nx = np.concatenate(nx)
+        self.ny = np.concatenate(ny)
         self.cx = np.concatenate(cx)
         self.cy = np.concatenate(cy)
         self.w = np.concatenate(w)
@@ -85,6 +95,47 @@ def matrix_rows(med, el, rows, green=None, chunk=None):
                 out[r, idx] = vals * el.w[idx]
         out[r, i] += self_term(med.k[l], el.w[i])
     return out
+
+
+def matrix_bc(med, el, beta=None, green=None):
+    """Matrix of a sound-hard (beta None) or impedance scatterer.
+
+    Reading (the paper names Neumann and Robin conditions in Sec. 2.1 and
+    treats only the Dirichlet one): the same single-layer representation
+    u^s = S phi, with the exterior limit of its normal derivative
+    d_n S phi = (-1/2 + K') phi (n pointing out of the scatterer) and the
+    condition (d_n + i beta) u = 0 on the boundary; collocated at the chord
+    midpoints with the rectangle rule:
+
+        A_ie = |Gamma_e| n_i . grad_r G(c_i | c_e) [+ i beta K_ie],   e != i,
+        A_ii = -1/2 + |Gamma_i| n_i . grad_r G^r(c_i | c_i) [+ i beta K_ii];
+
+    the free-space part of the self term of K' vanishes on a straight element
+    ((c - r') . n = 0 along it)."""
+    G = LayeredGreen(med) if green is None else green
+    A = np.zeros((el.n, el.n), dtype=complex)
+    for i in range(el.n):
+        l = int(el.layer[i])
+        for lp in range(med.L + 1):
+            idx = np.nonzero(el.layer == lp)[0]
+            if idx.size == 0:
+                continue
+            g, gx, gy = G.green_grad(el.cx[i], el.cy[i], el.cx[idx], el.cy[idx], l, lp)
+            if lp == l:
+                # the self pair keeps only its reaction part
+                j = np.nonzero(idx == i)[0]
+                rg = [G.reaction_component_grad(c, l, l, el.cx[i], el.cy[i], el.cx[i:i + 1], el.cy[i:i + 1])
+                      for c in nonzero_components(l, l, med.L)]
+                g[j] = sum(r[0] for r in rg) if rg else 0.0
+                gx[j] = sum(r[1] for r in rg) if rg else 0.0
+                gy[j] = sum(r[2] for r in rg) if rg else 0.0
+            A[i, idx] = (el.nx[i] * gx + el.ny[i] * gy) * el.w[idx]
+            if beta is not None:
+                A[i, idx] += 1j * beta * g * el.w[idx]
+        A[i, i] -= 0.5
+        if beta is not None:
+            A[i, i] += 1j * beta * self_term(med.k[l], el.w[i])
+    return A
 
 
 def matrix(med, el, green=None):

@@ -133,3 +133,16 @@ def sommerfeld(X, fac_c, fac_p, fac_m, nodes):
         out = out + (np.exp(1j * lam_p[None, :] * X) * fac_p) @ w_p
         out = out + (np.exp(-1j * lam_m[None, :] * X) * fac_m) @ w_m
     return out / (2.0 * np.pi)
+
+
+def sommerfeld_dx(X, fac_c, fac_p, fac_m, nodes):
+    """d/dX of ``sommerfeld``: the lam-integrand gains i lam on the e^{+i lam X}
+    branch and -i lam on the e^{-i lam X} branch (so 2 cos(lam X) becomes
+    -2 lam sin(lam X) on the shared nodes)."""
+    lam_c, w_c, lam_p, w_p, lam_m, w_m = nodes
+    X = np.asarray(X, dtype=float)[:, None]
+    out = ((-2.0 * lam_c[None, :] * np.sin(lam_c[None, :] * X)) * fac_c) @ w_c
+    if lam_p.size:
+        out = out + (1j * lam_p[None, :] * np.exp(1j * lam_p[None, :] * X) * fac_p) @ w_p
+        out = out + (-1j * lam_m[None, :] * np.exp(-1j * lam_m[None, :] * X) * fac_m) @ w_m
+    return out / (2.0 * np.pi)
