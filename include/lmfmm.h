@@ -104,12 +104,22 @@ lm_status lm_destroy_layers(lm_layers layers);
  * The handle keeps a reference to `layers`, which must outlive it.
  * Errors: LM_EINVAL (bad offsets, NaN, degenerate chord), LM_ENOMEM, LM_EHIP. */
 typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;
+/* Boundary condition of the scatterers (Sec. 2.1 names all three; the paper
+ * develops the Dirichlet one).  Neumann and Robin use the same single-layer
+ * representation u^s = S phi and the exterior limit of its normal derivative,
+ * (-1/2 + K' + i beta S) phi = -(d_n + i beta)(u^inc + u^b) for the condition
+ * (d_n + i beta) u = 0 (n out of the scatterer; beta = robin_beta, 0 for
+ * Neumann); collocated at the chord midpoints with the rectangle rule.  They
+ * need the dense method (LM_EINVAL with LM_FMM). */
+typedef enum { LM_BC_DIRICHLET = 0, LM_BC_NEUMANN = 1, LM_BC_ROBIN = 2 } lm_bc;
 typedef struct {
   int method;
   int p;
   int leaf_size;
   int precond;
   int top_fft;
+  int bc;            /* lm_bc */
+  double robin_beta; /* impedance beta of LM_BC_ROBIN */
 } lm_geom_opts;
 lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* node_offsets_host,
                              const double* nodes_xy_host, const lm_geom_opts* opts, void* hip_stream,
@@ -119,6 +129,9 @@ lm_status lm_geometry_info(lm_geom geom, int64_t* n_elements, int64_t* device_by
 /* Element data in input numbering (host outputs, any may be NULL):
  * cx, cy, w: double[N]; layer: int32[N]. */
 lm_status lm_geometry_elements(lm_geom geom, double* cx, double* cy, double* w, int32_t* layer);
+/* Unit normals of the elements pointing out of their polygon (the sign of the
+ * polygon's signed area gives its orientation), host outputs double[N]. */
+lm_status lm_geometry_normals(lm_geom geom, double* nx, double* ny);
 lm_status lm_destroy_geometry(lm_geom geom);
 /* Size of the fast-method plan (all zero for LM_DENSE), host output of 10
  * int64: boxes, free-space M2L list entries, reaction M2L list entries (the
@@ -199,7 +212,9 @@ lm_status lm_matvec_stage_times(lm_geom geom, int precision, int n_rhs, const vo
                                 void* hip_stream, double* out9_host);
 
 /* ------------------------------------------------------------------- rhs --
- * g = -u^inc - u^b on Gamma_0 and -u^b elsewhere (eq. homogeneousscattering)
+ * Dirichlet scatterers: g = -u^inc - u^b on Gamma_0 and -u^b elsewhere
+ * (eq. homogeneousscattering); Neumann / Robin scatterers:
+ * g = -(d_n + i beta)(u^inc + u^b) at the collocation points
  * for plane waves travelling along (cos t, -sin t), t = theta_host[r] in
  * radians, 0 < t < pi.  g_dev: device c128 [n_rhs][N]. */
 lm_status lm_rhs(lm_geom geom, int n_rhs, const double* theta_host, void* g_dev, void* hip_stream);

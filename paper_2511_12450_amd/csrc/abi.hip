@@ -72,7 +72,7 @@ lm_geom_s::~lm_geom_s() {
 }
 
 int64_t lm_geom_s::device_bytes() const {
-  int64_t b = d_cx.bytes + d_cy.bytes + d_w.bytes + d_layer.bytes + d_K.bytes + d_K32.bytes;
+  int64_t b = d_cx.bytes + d_cy.bytes + d_w.bytes + d_layer.bytes + d_nx.bytes + d_ny.bytes + d_K.bytes + d_K32.bytes;
   if (fmm) b += fmm_bytes(fmm);
   if (pre) b += precond_bytes(pre);
   return b;
@@ -99,8 +99,12 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   g->layers = layers;
   g->m = layers->m;
   g->N = N;
-  lm_geom_opts o = {LM_AUTO, 20, 48, -1, 0};
+  lm_geom_opts o = {LM_AUTO, 20, 48, -1, 0, LM_BC_DIRICHLET, 0.0};
   if (opts) o = *opts;
+  LM_CHECK(o.bc >= LM_BC_DIRICHLET && o.bc <= LM_BC_ROBIN, LM_EINVAL, "bad boundary condition");
+  LM_CHECK(std::isfinite(o.robin_beta), LM_EINVAL, "non-finite robin_beta");
+  g->bc = o.bc;
+  g->robin_beta = o.bc == LM_BC_ROBIN ? o.robin_beta : 0.0;
   LM_CHECK(o.method >= LM_AUTO && o.method <= LM_FMM, LM_EINVAL, "bad method");
   g->method = o.method == LM_AUTO ? (N <= 4096 ? LM_DENSE : LM_FMM) : o.method;
   g->p = o.p > 0 ? o.p : 20;
@@ -113,9 +117,17 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   g->cx.resize(N);
   g->cy.resize(N);
   g->w.resize(N);
+  g->nx.resize(N);
+  g->ny.resize(N);
   g->layer.resize(N);
   for (int j = 0; j < n_scatterers; ++j) {
     const int64_t a = off[j], n = off[j + 1] - off[j];
+    double area2 = 0.0;  // twice the signed area: > 0 for counter-clockwise nodes
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t p0 = a + i, p1 = a + (i + 1) % n;
+      area2 += nodes[2 * p0] * nodes[2 * p1 + 1] - nodes[2 * p1] * nodes[2 * p0 + 1];
+    }
+    const double o = area2 > 0 ? 1.0 : -1.0;
     for (int64_t i = 0; i < n; ++i) {
       const int64_t p0 = a + i, p1 = a + (i + 1) % n;
       const double x0 = nodes[2 * p0], y0 = nodes[2 * p0 + 1];
@@ -125,6 +137,8 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
       g->cx[p0] = 0.5 * (x0 + x1);
       g->cy[p0] = 0.5 * (y0 + y1);
       g->w[p0] = len;
+      g->nx[p0] = o * (y1 - y0) / len;
+      g->ny[p0] = -o * (x1 - x0) / len;
       g->layer[p0] = layer_of(g->m, g->cy[p0]);
     }
   }
@@ -132,7 +146,11 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   LM_TRY(upload(g->d_cy, g->cy.data(), N * sizeof(double), s));
   LM_TRY(upload(g->d_w, g->w.data(), N * sizeof(double), s));
   LM_TRY(upload(g->d_layer, g->layer.data(), N * sizeof(int32_t), s));
+  LM_TRY(upload(g->d_nx, g->nx.data(), N * sizeof(double), s));
+  LM_TRY(upload(g->d_ny, g->ny.data(), N * sizeof(double), s));
 
+  LM_CHECK(g->bc == LM_BC_DIRICHLET || g->method == LM_DENSE, LM_EINVAL,
+           "Neumann and Robin conditions need the dense method");
   if (g->method == LM_DENSE) {
     LM_CHECK(N <= 32768, LM_EINVAL, "dense method limited to N <= 32768");
     LM_TRY(dense_assemble(g.get(), s));
@@ -160,6 +178,14 @@ extern "C" lm_status lm_geometry_elements(lm_geom g, double* cx, double* cy, dou
   if (cy) std::memcpy(cy, g->cy.data(), n * sizeof(double));
   if (w) std::memcpy(w, g->w.data(), n * sizeof(double));
   if (layer) std::memcpy(layer, g->layer.data(), n * sizeof(int32_t));
+  return LM_OK;
+}
+
+extern "C" lm_status lm_geometry_normals(lm_geom g, double* nx, double* ny) {
+  LM_CHECK(g, LM_EINVAL, "geom is NULL");
+  const size_t n = (size_t)g->N;
+  if (nx) std::memcpy(nx, g->nx.data(), n * sizeof(double));
+  if (ny) std::memcpy(ny, g->ny.data(), n * sizeof(double));
   return LM_OK;
 }
 

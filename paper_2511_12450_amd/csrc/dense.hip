@@ -1,4 +1,5 @@
 // Dense plain path: assemble K by direct Sommerfeld quadrature, then y = K x.
+// (Dirichlet scatterers below; sound-hard and impedance ones further down.)
 //
 // Sec. 3.3, eq. matrixelmemts (unscaled rows):
 //   K_ie = |Gamma_e| [ delta_{l_i l_e} (i/4) H_0(k |c_i - c_e|) + G^r(c_i | c_e) ]  (e != i)
@@ -34,6 +35,45 @@ __global__ void __launch_bounds__(256) k_dense_assemble(MediumDev m, int N, cons
   K[idx] = make_double2(v.re, v.im);
 }
 
+// Sound-hard / impedance scatterers (single-layer representation, exterior
+// normal-derivative limit):
+//   A_ie = |Gamma_e| n_i . grad G(c_i | c_e) + i beta K_ie  (e != i),
+//   A_ii = -1/2 + |Gamma_i| n_i . grad G^r(c_i | c_i) + i beta K_ii;
+// grad G^f(c_i | c_e) = -(i/4) k H_1(k r) (c_i - c_e) / r, and the free-space
+// part of the self term of K' is zero on a straight element.
+__global__ void __launch_bounds__(256) k_dense_assemble_bc(MediumDev m, int N, const double* __restrict__ cx,
+                                                           const double* __restrict__ cy,
+                                                           const double* __restrict__ w,
+                                                           const double* __restrict__ nx,
+                                                           const double* __restrict__ ny,
+                                                           const int* __restrict__ lay, double beta,
+                                                           double2* __restrict__ K) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx / N), e = (int)(idx % N);
+  const int li = lay[i], le = lay[e];
+  const double dx = cx[i] - cx[e], dy = cy[i] - cy[e];
+  zd g, gx, gy;
+  lmq::reaction_direct_grad(m, li, le, dx, cy[i], cy[e], g, gx, gy);
+  zd dn = gx * nx[i] + gy * ny[i];
+  if (i == e) {
+    g = g * w[i] + self_term(m.k[li], w[i]);
+    dn = dn * w[i] + zd(-0.5, 0.0);
+  } else {
+    if (li == le) {
+      const double r = sqrt(dx * dx + dy * dy), kr = m.k[li] * r;
+      g += zd(-0.25 * y0(kr), 0.25 * j0(kr));
+      // -(i/4) k H_1(k r) / r, H_1 = J_1 + i Y_1
+      const zd d = zd(0.25 * y1(kr), -0.25 * j1(kr)) * (m.k[li] / r);
+      dn += d * (dx * nx[i] + dy * ny[i]);
+    }
+    g = g * w[e];
+    dn = dn * w[e];
+  }
+  const zd v = dn + zd(0.0, beta) * g;
+  K[idx] = make_double2(v.re, v.im);
+}
+
 __global__ void k_to_c64(const double2* __restrict__ a, float2* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -42,8 +82,13 @@ __global__ void k_to_c64(const double2* __restrict__ a, float2* __restrict__ b, 
 lm_status dense_assemble(lm_geom_s* g, hipStream_t s) {
   const int64_t N = g->N, NN = N * N;
   LM_TRY(g->d_K.alloc(NN * sizeof(double2)));
-  hipLaunchKernelGGL(k_dense_assemble, dim3(div_up(NN, 256)), dim3(256), 0, s, g->m, (int)N, g->d_cx.as<double>(),
-                     g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(), g->d_K.as<double2>());
+  if (g->bc == LM_BC_DIRICHLET)
+    hipLaunchKernelGGL(k_dense_assemble, dim3(div_up(NN, 256)), dim3(256), 0, s, g->m, (int)N, g->d_cx.as<double>(),
+                       g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(), g->d_K.as<double2>());
+  else
+    hipLaunchKernelGGL(k_dense_assemble_bc, dim3(div_up(NN, 256)), dim3(256), 0, s, g->m, (int)N,
+                       g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_nx.as<double>(),
+                       g->d_ny.as<double>(), g->d_layer.as<int>(), g->robin_beta, g->d_K.as<double2>());
   LM_TRY_HIP(hipGetLastError());
   LM_TRY(g->d_K32.alloc(NN * sizeof(float2)));
   hipLaunchKernelGGL(k_to_c64, dim3(div_up(NN, 256)), dim3(256), 0, s, g->d_K.as<double2>(), g->d_K32.as<float2>(), NN);

@@ -47,6 +47,35 @@ __global__ void k_rhs(int N, int R, const BgAmp* __restrict__ amp, const double*
   g[(int64_t)r * N + i] = make_double2(u.re, u.im);
 }
 
+// Sound-hard / impedance scatterers: g = -(d_n + i beta)(u^inc + u^b), with
+// d/dx = i kx and d/dy = +-i k_{l,y} on the up / down-going terms.
+__global__ void k_rhs_bc(int N, int R, const BgAmp* __restrict__ amp, const double* __restrict__ cx,
+                         const double* __restrict__ cy, const double* __restrict__ nx, const double* __restrict__ ny,
+                         const int* __restrict__ lay, const double* __restrict__ theta, const MediumDev m, double beta,
+                         double2* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const BgAmp& a = amp[r];
+  const int l = lay[i];
+  const double x = cx[i], y = cy[i];
+  const zd ex = zexp(zd(0.0, a.kx * x));
+  const zd up = a.A[l] * zexp(zd(0.0, y) * a.ky[l]), dn = a.B[l] * zexp(zd(0.0, -y) * a.ky[l]);
+  zd u = up + dn;
+  zd uy = (up - dn) * (zd(0.0, 1.0) * a.ky[l]);
+  if (l == 0) {
+    const double k0y = m.k[0] * sin(theta[r]);
+    const zd ui = zexp(zd(0.0, -k0y * y));
+    u += ui;
+    uy += ui * zd(0.0, -k0y);
+  }
+  u = u * ex;
+  uy = uy * ex;
+  const zd ux = u * zd(0.0, a.kx);
+  const zd v = -(ux * nx[i] + uy * ny[i] + u * zd(0.0, beta));
+  g[(int64_t)r * N + i] = make_double2(v.re, v.im);
+}
+
 lm_status rhs_launch(lm_geom_s* g, int R, const double* theta_host, void* g_dev, hipStream_t s) {
   DevBuf th, amp;
   LM_TRY(upload(th, theta_host, R * sizeof(double), s));
@@ -54,8 +83,13 @@ lm_status rhs_launch(lm_geom_s* g, int R, const double* theta_host, void* g_dev,
   hipLaunchKernelGGL(k_background, dim3(div_up(R, 64)), dim3(64), 0, s, g->m, R, th.as<double>(), amp.as<BgAmp>());
   LM_TRY_HIP(hipGetLastError());
   const int N = (int)g->N;
-  hipLaunchKernelGGL(k_rhs, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(), g->d_cx.as<double>(),
-                     g->d_cy.as<double>(), g->d_layer.as<int>(), th.as<double>(), g->m, (double2*)g_dev);
+  if (g->bc == LM_BC_DIRICHLET)
+    hipLaunchKernelGGL(k_rhs, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(), g->d_cx.as<double>(),
+                       g->d_cy.as<double>(), g->d_layer.as<int>(), th.as<double>(), g->m, (double2*)g_dev);
+  else
+    hipLaunchKernelGGL(k_rhs_bc, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(),
+                       g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_nx.as<double>(), g->d_ny.as<double>(),
+                       g->d_layer.as<int>(), th.as<double>(), g->m, g->robin_beta, (double2*)g_dev);
   LM_TRY_HIP(hipGetLastError());
   LM_TRY_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
   return LM_OK;

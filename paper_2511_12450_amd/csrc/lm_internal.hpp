@@ -94,11 +94,13 @@ struct lm_geom_s {
   int p = 20;
   int leaf_size = 48;
   int top_fft = 0;  // level-0 M2L by FFT: 0 when it pays, 1 always, -1 never
+  int bc = LM_BC_DIRICHLET;  // boundary condition of the scatterers
+  double robin_beta = 0.0;   // impedance of the Robin condition
   // host element data, input numbering
-  std::vector<double> cx, cy, w;
+  std::vector<double> cx, cy, w, nx, ny;  // nx, ny: unit normal out of the element's polygon
   std::vector<int32_t> layer;
   // device element data, input numbering
-  DevBuf d_cx, d_cy, d_w, d_layer;
+  DevBuf d_cx, d_cy, d_w, d_layer, d_nx, d_ny;
   // dense path
   DevBuf d_K;          // complex128 row-major [N][N]
   DevBuf d_K32;        // complex64 copy for the mixed form

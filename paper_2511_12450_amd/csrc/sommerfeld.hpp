@@ -154,4 +154,119 @@ LM_HD zd reaction_direct(const MediumDev& m, int lt, int ls, double X, double yt
   return acc * (1.0 / (2.0 * M_PI));
 }
 
+// F(lam) as above and its target y-derivative factor: component c gains
+// i k_{lt,y} dh_t/dy, dh_t/dy = +1 on the bottom side (h = y + d) and -1 on
+// the top side (h = -d - y).
+LM_HD void integrand_dy(const MediumDev& m, int lt, int ls, const PairSides& p, zd lam, zd& f, zd& fy) {
+  StackAt st;
+  stack_at(m, lam, st);
+  zd S[4];
+  side_densities(m, st, lt, ls, p.mask, S);
+  f = zd(0.0, 0.0);
+  fy = zd(0.0, 0.0);
+  for (int c = 0; c < 4; ++c) {
+    if (!((p.mask >> c) & 1u)) continue;
+    const zd v = S[c] * zexp(zd(0.0, 1.0) * (st.ky[lt] * p.ht[c] + st.ky[ls] * p.hs[c]));
+    f += v;
+    const double sy = (c & 1) == SIDE_B ? 1.0 : -1.0;
+    fy += v * (zd(0.0, sy) * st.ky[lt]);
+  }
+}
+
+// G^r(r | r') and its gradient in the target r (signed horizontal offset
+// dx = x - x'): the same contour as reaction_direct; d/dx acts on the
+// oscillating factor of the folded integral (e^{+i lam X} gains i lam,
+// e^{-i lam X} gains -i lam; times the sign of dx), d/dy on the target factor.
+LM_HD void reaction_direct_grad(const MediumDev& m, int lt, int ls, double dx, double yt, double ys, zd& g, zd& gx,
+                                zd& gy) {
+  g = gx = gy = zd(0.0, 0.0);
+  PairSides p = pair_sides(m, lt, ls, yt, ys, 0xFu);
+  if (!p.mask) return;
+  const double X = fabs(dx), sx = dx < 0.0 ? -1.0 : 1.0;
+  const double T = m.kmax + 1.5;
+  const double Xs = fmax(X, 1e-300);
+  const double Dm = fmax(p.Dmin, 1e-12);
+  zd f, fy;
+  {
+    const double a = fmin(0.5, 3.0 / Xs);
+    const double wmax = fmin(fmin(0.3, 0.5 * a), 8.0 / Xs);
+    const int np = (int)ceil(T / wmax);
+    const double h = T / np;
+    for (int q = 0; q < np; ++q) {
+      const double c0 = (q + 0.5) * h;
+      for (int j = 0; j < 20; ++j) {
+        double t = c0 + 0.5 * h * glx(j), u = t / T;
+        zd lam(t, -a * 4.0 * u * (1.0 - u));
+        zd dl(1.0, -a * (4.0 / T) * (1.0 - 2.0 * u));
+        zd e = zexp(zd(0.0, 1.0) * lam * X), ei = 1.0 / e;
+        zd w = dl * (0.5 * h * glw(j));
+        integrand_dy(m, lt, ls, p, lam, f, fy);
+        g += w * (e + ei) * f;
+        gx += w * (zd(0.0, 1.0) * lam * (e - ei)) * f;
+        gy += w * (e + ei) * fy;
+      }
+    }
+  }
+  if (Dm >= X / 3.0) {
+    const double end = T + 36.0 / Dm;
+    double x0 = T;
+    while (x0 < end) {
+      double w = fmin(fmin(8.0 / Xs, 2.5 / Dm), 0.3 + 0.3 * (x0 - T));
+      double x1 = fmin(end, x0 + w);
+      double hh = 0.5 * (x1 - x0), mid = 0.5 * (x1 + x0);
+      for (int j = 0; j < 20; ++j) {
+        double lr = mid + hh * glx(j);
+        integrand_dy(m, lt, ls, p, zd(lr, 0.0), f, fy);
+        double cs = 2.0 * cos(lr * X), sn = -2.0 * lr * sin(lr * X);
+        g += f * (hh * glw(j) * cs);
+        gx += f * (hh * glw(j) * sn);
+        gy += fy * (hh * glw(j) * cs);
+      }
+      x0 = x1;
+    }
+  } else {
+    const double L1 = T + 1.5;
+    double x0 = T;
+    while (x0 < L1) {
+      double x1 = fmin(L1, x0 + fmin(0.3, 8.0 / Xs));
+      double hh = 0.5 * (x1 - x0), mid = 0.5 * (x1 + x0);
+      for (int j = 0; j < 20; ++j) {
+        double lr = mid + hh * glx(j);
+        integrand_dy(m, lt, ls, p, zd(lr, 0.0), f, fy);
+        double cs = 2.0 * cos(lr * X), sn = -2.0 * lr * sin(lr * X);
+        g += f * (hh * glw(j) * cs);
+        gx += f * (hh * glw(j) * sn);
+        gy += fy * (hh * glw(j) * cs);
+      }
+      x0 = x1;
+    }
+    const double z = hypot(X, Dm);
+    const double psi = atan2(X, Dm);
+    zd ep(cos(psi), sin(psi));
+    const double S = 50.0 / z;
+    double s0 = 0.0;
+    while (s0 < S) {
+      double s1 = fmin(S, s0 + fmin(2.5 / z, 0.4 + 0.4 * s0));
+      double hh = 0.5 * (s1 - s0), mid = 0.5 * (s1 + s0);
+      for (int j = 0; j < 20; ++j) {
+        double s = mid + hh * glx(j);
+        zd lp = L1 + ep * s, lm = L1 + conj(ep) * s;
+        zd fp, fpy, fm, fmy;
+        integrand_dy(m, lt, ls, p, lp, fp, fpy);
+        integrand_dy(m, lt, ls, p, lm, fm, fmy);
+        const zd xp = zexp(zd(0.0, X) * lp), xm = zexp(zd(0.0, -X) * lm);
+        const zd wp = ep * (hh * glw(j)), wm = conj(ep) * (hh * glw(j));
+        g += fp * xp * wp + fm * xm * wm;
+        gx += (zd(0.0, 1.0) * lp) * fp * xp * wp + (zd(0.0, -1.0) * lm) * fm * xm * wm;
+        gy += fpy * xp * wp + fmy * xm * wm;
+      }
+      s0 = s1;
+    }
+  }
+  const double inv = 1.0 / (2.0 * M_PI);
+  g = g * inv;
+  gx = gx * (sx * inv);
+  gy = gy * inv;
+}
+
 }  // namespace lmq

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblmfmm.so")
 LM_OK, LM_NOT_CONVERGED = 0, 1
 LM_FP64, LM_MIXED = 0, 1
 LM_AUTO, LM_DENSE, LM_FMM = 0, 1, 2
+LM_BC_DIRICHLET, LM_BC_NEUMANN, LM_BC_ROBIN = 0, 1, 2
 
 _lib = None
 
@@ -29,7 +30,7 @@ class LmError(RuntimeError):
 
 class GeomOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int), ("precond", ctypes.c_int),
-                ("top_fft", ctypes.c_int)]
+                ("top_fft", ctypes.c_int), ("bc", ctypes.c_int), ("robin_beta", ctypes.c_double)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -66,6 +67,7 @@ _SIGS = {
     "lm_geometry_info": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_int)], _ip),
     "lm_geometry_elements": ([_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)], _ip),
+    "lm_geometry_normals": ([_vp, _dp, _dp], _ip),
     "lm_destroy_geometry": ([_vp], _ip),
     "lm_fmm_stats": ([_vp, ctypes.POINTER(ctypes.c_int64)], _ip),
     "lm_matvec": ([_vp, _ip, _ip, _vp, _vp, _vp], _ip),
@@ -161,10 +163,11 @@ class Layers:
 class Geometry:
     """Elements of closed node polygons (Sec. 3.3) plus the operator data."""
 
-    def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1, top_fft=0):
+    def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1, top_fft=0,
+                 bc=LM_BC_DIRICHLET, robin_beta=0.0):
         off = np.ascontiguousarray(node_offsets, dtype=np.int64)
         xy = np.ascontiguousarray(nodes_xy, dtype=np.float64)
-        o = GeomOpts(method, p, leaf_size, precond, top_fft)
+        o = GeomOpts(method, p, leaf_size, precond, top_fft, bc, robin_beta)
         h = ctypes.c_void_p()
         _check(lib().lm_create_geometry(layers.h, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                         _dptr(xy), ctypes.byref(o), _stream(), ctypes.byref(h)))
@@ -188,6 +191,12 @@ class Geometry:
         _check(lib().lm_geometry_elements(self.h, _dptr(cx), _dptr(cy), _dptr(ww),
                                           lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return cx, cy, ww, lay
+
+    def normals(self):
+        """Outward unit normals of the elements (lm_geometry_normals)."""
+        nx, ny = np.empty(self.n), np.empty(self.n)
+        _check(lib().lm_geometry_normals(self.h, _dptr(nx), _dptr(ny)))
+        return nx, ny
 
     def fmm_stats(self):
         """Plan sizes of the fast method (see lm_fmm_stats)."""
