@@ -62,3 +62,17 @@ def test_three_layer_row_recomputed():
     y = matrix_rows(med, el, [row])[0] @ X[:4].T
     ref = stored[:4, 2] + 1j * stored[:4, 3]
     assert np.allclose(y, ref, rtol=1e-12, atol=0.0)
+
+
+def test_mini_far_fields_file():
+    """The stored far fields of the 64-angle mini workload: every angle and
+    observation direction the writer produces, finite."""
+    spec = importlib.util.spec_from_file_location("make_mini_far_fields", os.path.join(GOLDEN, "make_mini_far_fields.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    a = np.loadtxt(os.path.join(GOLDEN, "mini_far_fields.txt"))
+    n_obs = mod.obs_angles().size
+    assert a.shape == (64 * n_obs, 4)
+    assert np.array_equal(a[:, 0].astype(int), np.repeat(np.arange(64), n_obs))
+    assert np.array_equal(a[:, 1].astype(int), np.tile(np.arange(n_obs), 64))
+    assert np.all(np.isfinite(a[:, 2:])) and np.abs(a[:, 2:]).max() > 0
