@@ -25,7 +25,9 @@
 //      update pass and solution updates.
 // Requests that arrive while others run are admitted at the next round as
 // soon as right-hand-side slots and the HBM budget allow; a request whose
-// footprint can never fit is rejected at submission.  Finished requests keep
+// footprint can never fit is rejected at submission.  Admission, cancel,
+// failure and release are the host-only scheduler of sched.hpp, driven here
+// by the device work below.  Finished requests keep
 // phi and the far field in host memory until released.
 #include <algorithm>
 #include <atomic>
@@ -43,6 +45,7 @@
 #include <vector>
 
 #include "lm_internal.hpp"
+#include "sched.hpp"
 
 namespace {
 
@@ -419,7 +422,7 @@ struct Request {
   std::vector<double> theta, obs;
   lm_gmres_opts o{};
   lm_state state = LM_QUEUED;
-  lm_status status = LM_OK;
+  lm_status status = LM_OK, fail_status = LM_OK;  // fail_status: a failure pending until the worker lets go
   std::string err;
   std::vector<lm_solve_report> rep;
   std::vector<double2> phi, ff;
@@ -524,16 +527,9 @@ class HostPool {
 struct lm_server_s {
   lm_server_opts o{};
   int device = 0;
-  std::mutex mu;
-  std::condition_variable cv;
+  lmsched::Book<Request> B;  // requests, queue, admission counters and the lock over them
   std::thread th;
-  bool stop = false;
-  std::deque<Request*> queue;
-  std::map<uint64_t, Request*> reqs;
-  uint64_t next_id = 1;
-  int64_t used = 0;
   int64_t held = 0, held_spare = 0;  // device bytes of the server's own buffers (all / spare columns), worker-updated
-  int active_rhs = 0;
   int64_t rounds = 0, launches = 0, fused_rhs = 0;
   double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
   double m2l_ms = 0.0, m2l_flops = 0.0;              // M2L launches of the fused matvecs (HIP events)
@@ -568,16 +564,6 @@ int64_t footprint(const lm_geom_s* g, const lm_gmres_opts& o, int R) {
   const int64_t per = (int64_t)(m + 1) * ld * 16 + (int64_t)(2 + 3) * N * 16 + (int64_t)(m + 1) * 16 + 2 * N * 8 +
                       (g->fmm ? fmm_ws_per_rhs(g->fmm) : 0);
   return per * R;
-}
-
-void fail_request(lm_server_s* S, Request* q, lm_status st, const std::string& msg) {
-  std::lock_guard<std::mutex> lk(S->mu);
-  if (q->state == LM_QUEUED || q->state == LM_RUNNING) {
-    q->state = LM_FAILED;
-    q->status = st;
-    q->err = msg;
-    q->t_done = now_s();
-  }
 }
 
 lm_status upload_desc(lm_server_s* S, const std::vector<ColDev>& d) {
@@ -658,7 +644,7 @@ void settle_memory(lm_server_s* S, bool idle) {
   for (const DevBuf* b : {&S->d_desc, &S->d_h, &S->d_nrm, &S->d_dpart, &S->d_npart, &S->d_y, &S->d_fz, &S->d_fphi,
                           &S->d_fff})
     h += (int64_t)b->bytes;
-  std::lock_guard<std::mutex> lk(S->mu);
+  std::lock_guard<std::mutex> lk(S->B.mu);
   S->held = h + hs;
   S->held_spare = hs;
 }
@@ -788,7 +774,7 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
 
 // One round of the worker (see the file comment).  Returns an error only for
 // failures that are not attributable to a single request.
-lm_status round(lm_server_s* S) {
+lm_status run_round(lm_server_s* S) {
   const double tr0 = now_s();
   std::vector<Column*> cols;
   for (Column* c : S->cols)
@@ -1199,7 +1185,7 @@ lm_status round(lm_server_s* S) {
       LM_TRY_HIP(hipEventElapsedTime(&t, S->sev[si][4], S->sev[si][5]));
       m2l += t;
     }
-    std::lock_guard<std::mutex> lk(S->mu);
+    std::lock_guard<std::mutex> lk(S->B.mu);
     S->km_ms += km_round;
     S->gs_ms += gs_a + gs_b;
     S->m2l_ms += m2l;
@@ -1216,11 +1202,11 @@ lm_status round(lm_server_s* S) {
     const lm_status st = finish_columns(S, to_finish, &failed);
     if (st < 0) {
       const std::string msg = lm_last_error();
-      for (Request* q : failed) fail_request(S, q, st, msg);
+      for (Request* q : failed) S->B.mark_failed(q, st, msg);
     }
   }
   const double tf1 = now_s();
-  std::lock_guard<std::mutex> lk(S->mu);
+  std::lock_guard<std::mutex> lk(S->B.mu);
   S->round_ms += 1e3 * (tf0 - tr0);
   S->finish_ms += 1e3 * (tf1 - tf0);
   return LM_OK;
@@ -1247,92 +1233,35 @@ void release_columns(lm_server_s* S, Request* q) {
   }
 }
 
+// The device side of the worker loop (lmsched::run_worker drives it).
+struct GpuDev {
+  lm_server_s* S;
+  lm_status start(Request* q) { return start_request(S, q); }
+  void release(Request* q) { release_columns(S, q); }
+  bool has_work() const { return !S->cols.empty(); }
+  lm_status round() { return run_round(S); }
+  bool finished(Request* q, bool* conv) {
+    bool all = true;
+    *conv = true;
+    for (const Column* c : S->cols)
+      if (c->req == q) {
+        all = all && c->finished;
+        *conv = *conv && c->converged;
+      }
+    return all;
+  }
+  // spare columns count against the budget: free what the admitted requests'
+  // footprints leave no room for
+  void trim(int64_t allow, const std::vector<Request*>& admit) { trim_spares(S, allow, admit); }
+  void settle(bool idle) { settle_memory(S, idle); }
+  double now() const { return now_s(); }
+  std::string last_error() const { return lm_last_error(); }
+};
+
 void worker(lm_server_s* S) {
   (void)hipSetDevice(S->device);
-  std::vector<Request*> running;
-  while (true) {
-    std::vector<Request*> admit;
-    int64_t allow = 0;
-    {
-      std::unique_lock<std::mutex> lk(S->mu);
-      // drop cancelled requests (queued ones are dropped at cancel time)
-      for (auto it = running.begin(); it != running.end();) {
-        Request* q = *it;
-        if (q->cancel || q->state == LM_FAILED) {
-          if (q->state == LM_RUNNING) {
-            q->state = LM_CANCELLED;
-            q->status = LM_ECANCELLED;
-            q->t_done = now_s();
-          }
-          S->used -= q->bytes;
-          S->active_rhs -= q->R;
-          lk.unlock();
-          release_columns(S, q);
-          lk.lock();
-          it = running.erase(it);
-        } else {
-          ++it;
-        }
-      }
-      if (S->stop) break;
-      // admission: FIFO while right-hand-side slots and the HBM budget allow
-      while (!S->queue.empty()) {
-        Request* q = S->queue.front();
-        if (S->active_rhs + q->R > S->o.max_active_rhs || S->used + q->bytes > S->o.hbm_budget_bytes) break;
-        S->queue.pop_front();
-        q->state = LM_RUNNING;
-        S->used += q->bytes;
-        S->active_rhs += q->R;
-        admit.push_back(q);
-      }
-      allow = S->o.hbm_budget_bytes - S->used;
-      if (running.empty() && admit.empty()) {
-        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-        continue;
-      }
-    }
-    // spare columns count against the budget: free what the admitted
-    // requests' footprints leave no room for
-    if (!admit.empty()) trim_spares(S, allow, admit);
-    for (Request* q : admit) {
-      lm_status st = start_request(S, q);
-      if (st < 0) {
-        fail_request(S, q, st, lm_last_error());
-        release_columns(S, q);
-      }
-      running.push_back(q);
-    }
-    lm_status st = S->cols.empty() ? LM_OK : round(S);
-    if (st < 0) {
-      const std::string msg = lm_last_error();
-      for (Request* q : running) fail_request(S, q, st, msg);
-    }
-    // completed requests
-    for (auto it = running.begin(); it != running.end();) {
-      Request* q = *it;
-      bool all = true;
-      bool conv = true;
-      for (Column* c : S->cols)
-        if (c->req == q) {
-          all = all && c->finished;
-          conv = conv && c->converged;
-        }
-      if (all && q->state == LM_RUNNING) {
-        release_columns(S, q);
-        std::lock_guard<std::mutex> lk(S->mu);
-        q->state = LM_DONE;
-        q->status = conv ? LM_OK : LM_NOT_CONVERGED;
-        q->t_done = now_s();
-        S->used -= q->bytes;
-        S->active_rhs -= q->R;
-        it = running.erase(it);
-      } else {
-        ++it;
-      }
-    }
-    settle_memory(S, running.empty());
-  }
-  for (Request* q : running) release_columns(S, q);
+  GpuDev D{S};
+  lmsched::run_worker(S->B, D);
   drop_spares(S);
 }
 
@@ -1351,6 +1280,8 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
   auto* S = new (std::nothrow) lm_server_s();
   LM_CHECK(S, LM_ENOMEM, "host allocation failed");
   S->o = so;
+  S->B.max_rhs = so.max_active_rhs;
+  S->B.budget = so.hbm_budget_bytes;
   if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
   bool ok = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&S->ev_main, hipEventDisableTiming) == hipSuccess &&
@@ -1401,29 +1332,17 @@ extern "C" lm_status lm_submit(lm_server S, const lm_request* r, uint64_t* id) {
   q->bytes = footprint(q->g, q->o, q->R);
   q->phi.assign((size_t)q->R * q->g->N, make_double2(0.0, 0.0));
   q->ff.assign((size_t)q->R * r->n_obs, make_double2(0.0, 0.0));
-  if (q->R > S->o.max_active_rhs || q->bytes > S->o.hbm_budget_bytes) {
-    const int64_t b = q->bytes;
-    delete q;
-    LM_CHECK(false, LM_ENOMEM, "request can never be admitted (%d right-hand sides, %lld bytes)", r->n_rhs,
-             (long long)b);
-  }
-  std::lock_guard<std::mutex> lk(S->mu);
-  q->id = S->next_id++;
-  q->t_submit = now_s();
-  S->reqs[q->id] = q;
-  S->queue.push_back(q);
-  *id = q->id;
-  S->cv.notify_all();
-  return LM_OK;
+  if (q->R > S->o.max_active_rhs || q->bytes > S->o.hbm_budget_bytes)
+    lm_set_error("request can never be admitted (%d right-hand sides, %lld bytes)", r->n_rhs, (long long)q->bytes);
+  return S->B.submit(q, now_s(), id);  // deletes q when it can never be admitted
 }
 
 extern "C" lm_status lm_poll(lm_server S, uint64_t id, lm_state* state, lm_solve_report* reports, double* latency_s,
                              void* phi_host, void* far_field_host) {
   LM_CHECK(S && state, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
-  auto it = S->reqs.find(id);
-  LM_CHECK(it != S->reqs.end(), LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
-  Request* q = it->second;
+  std::lock_guard<std::mutex> lk(S->B.mu);
+  Request* q = S->B.find(id);
+  LM_CHECK(q, LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
   *state = q->state;
   if (latency_s) *latency_s = q->t_done > 0 ? q->t_done - q->t_submit : now_s() - q->t_submit;
   if (q->state == LM_DONE) {
@@ -1442,32 +1361,17 @@ extern "C" lm_status lm_poll(lm_server S, uint64_t id, lm_state* state, lm_solve
 
 extern "C" lm_status lm_cancel(lm_server S, uint64_t id) {
   LM_CHECK(S, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
-  auto it = S->reqs.find(id);
-  LM_CHECK(it != S->reqs.end(), LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
-  Request* q = it->second;
-  if (q->state == LM_QUEUED) {
-    S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), q), S->queue.end());
-    q->state = LM_CANCELLED;
-    q->status = LM_ECANCELLED;
-    q->t_done = now_s();
-  } else if (q->state == LM_RUNNING) {
-    q->cancel = true;
-  }
-  return LM_OK;
+  const lm_status st = S->B.cancel(id, now_s());
+  LM_CHECK(st != LM_ENOTFOUND, LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
+  return st;
 }
 
 extern "C" lm_status lm_release(lm_server S, uint64_t id) {
   LM_CHECK(S, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
-  auto it = S->reqs.find(id);
-  LM_CHECK(it != S->reqs.end(), LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
-  Request* q = it->second;
-  LM_CHECK(q->state == LM_DONE || q->state == LM_FAILED || q->state == LM_CANCELLED, LM_EINVAL,
-           "request %llu is still queued or running", (unsigned long long)id);
-  delete q;
-  S->reqs.erase(it);
-  return LM_OK;
+  const lm_status st = S->B.release(id);
+  LM_CHECK(st != LM_ENOTFOUND, LM_ENOTFOUND, "unknown request id %llu", (unsigned long long)id);
+  LM_CHECK(st != LM_EINVAL, LM_EINVAL, "request %llu is still queued or running", (unsigned long long)id);
+  return st;
 }
 
 extern "C" lm_status lm_request_footprint(lm_geom g, int n_rhs, const lm_gmres_opts* o, int64_t* bytes) {
@@ -1479,10 +1383,10 @@ extern "C" lm_status lm_request_footprint(lm_geom g, int n_rhs, const lm_gmres_o
 
 extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
   LM_CHECK(S && out6, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
-  out6[0] = (int64_t)S->queue.size();
-  out6[1] = S->active_rhs;
-  out6[2] = S->used;
+  std::lock_guard<std::mutex> lk(S->B.mu);
+  out6[0] = (int64_t)S->B.queue.size();
+  out6[1] = S->B.active;
+  out6[2] = S->B.used;
   out6[3] = S->rounds;
   out6[4] = S->launches;
   out6[5] = S->fused_rhs;
@@ -1491,16 +1395,16 @@ extern "C" lm_status lm_server_stats(lm_server S, int64_t* out6) {
 
 extern "C" lm_status lm_server_memory(lm_server S, int64_t* out3) {
   LM_CHECK(S && out3, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
+  std::lock_guard<std::mutex> lk(S->B.mu);
   out3[0] = S->held;
   out3[1] = S->held_spare;
-  out3[2] = S->used;
+  out3[2] = S->B.used;
   return LM_OK;
 }
 
 extern "C" lm_status lm_server_phase_times(lm_server S, double* out8) {
   LM_CHECK(S && out8, LM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(S->mu);
+  std::lock_guard<std::mutex> lk(S->B.mu);
   out8[0] = S->km_ms;
   out8[1] = S->gs_ms;
   out8[2] = S->gs_bytes;
@@ -1514,15 +1418,9 @@ extern "C" lm_status lm_server_phase_times(lm_server S, double* out8) {
 
 extern "C" lm_status lm_server_destroy(lm_server S) {
   if (!S) return LM_OK;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->stop = true;
-    for (auto& kv : S->reqs)
-      if (kv.second->state == LM_RUNNING) kv.second->cancel = true;
-    S->cv.notify_all();
-  }
+  S->B.request_stop();
   if (S->th.joinable()) S->th.join();
-  for (auto& kv : S->reqs) delete kv.second;
+  S->B.clear();
   for (Column* c : S->cols) delete c;
   S->cols.clear();
   S->groups.clear();
