@@ -602,7 +602,8 @@ inline int top_lgc(int lgL, size_t elem) {
 // column tile; WC column tiles and WR row groups form the workgroup.
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int MF_ST = 8;   // staging loads in flight per lane
-constexpr int MF_PF = 18;  // prefetch registers per lane (an entry of p = 20, R = 64 on 256 threads)
+constexpr int MF_PT = 7;   // prefetch registers per lane for the operator (P^2 <= 7 x threads: p = 20 on 256)
+constexpr int MF_PA = 11;  // and for the source block (P R <= 11 x threads: p = 20, R = 64 on 256)
 constexpr int MF_TR = 3;  // row tiles per wave
 __host__ __device__ inline int mf_ks(int P) { return (P + 3) / 4; }
 // complex slots after the staged T and a that must read as zero
@@ -618,7 +619,7 @@ inline size_t mf_lds_bytes(int P, int R) { return (size_t)(P * P + P * R + mf_ze
 // so that profiles tell the launches apart.
 enum { MF_LIST = 0, MF_TREE = 1, MF_TOP = 2 };
 template <int WC, int WR, int KIND, bool PRE>
-__global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const int* __restrict__ items,
+__global__ void __launch_bounds__(64 * WC * WR) __attribute__((amdgpu_waves_per_eu(PRE ? 4 : 1))) k_m2l_mfma(int p, int R, const int* __restrict__ items,
                                                       const int* __restrict__ src, const int* __restrict__ opi,
                                                       const float2* __restrict__ ops, const float2* __restrict__ me,
                                                       float2* __restrict__ part, const int* __restrict__ dtgt,
@@ -640,29 +641,36 @@ __global__ void __launch_bounds__(64 * WC * WR) k_m2l_mfma(int p, int R, const i
 #pragma unroll
   for (int t = 0; t < MF_TR; ++t) t1[t] = t2[t] = t3[t] = v4f{0.f, 0.f, 0.f, 0.f};
   const int e0 = items[3 * blockIdx.x + 1], e1 = items[3 * blockIdx.x + 2];
-  // PRE (one entry fits MF_PF values per thread): the next entry is loaded
-  // into registers while the current one is multiplied
-  constexpr bool pre = PRE;
-  float2 pf[PRE ? MF_PF : 1];
+  // PRE (an entry's operator fits MF_PT and its source block MF_PA values per
+  // thread): the next entry is loaded into registers while the current one is
+  // multiplied.  Every load has a uniform base (operator or source block plus
+  // NTH u) and the thread index as offset, so the loop keeps no per-load
+  // addresses; lanes past the end re-read the last element.
+  const int tid = threadIdx.x;
+  float2 pt[PRE ? MF_PT : 1], pa[PRE ? MF_PA : 1];
 #define LM_MF_FETCH(e)                                                          \
   do {                                                                          \
     const float2* Tg_ = ops + (int64_t)opi[e] * PP;                             \
     const float2* Ag_ = me + (int64_t)src[e] * PR;                              \
-    _Pragma("unroll") for (int u = 0; u < (PRE ? MF_PF : 1); ++u) {             \
-      const int idx = threadIdx.x + NTH * u;                                    \
-      const int ii = idx < NS ? idx : 0;                                        \
-      pf[u] = *(ii < PP ? Tg_ + ii : Ag_ + (ii - PP));                          \
+    _Pragma("unroll") for (int u = 0; u < (PRE ? MF_PT : 1); ++u) {             \
+      const int o = NTH * u;                                                    \
+      if (o < PP) pt[u] = Tg_[o + min(tid, PP - 1 - o)];                        \
+    }                                                                           \
+    _Pragma("unroll") for (int u = 0; u < (PRE ? MF_PA : 1); ++u) {             \
+      const int o = NTH * u;                                                    \
+      if (o < PR) pa[u] = Ag_[o + min(tid, PR - 1 - o)];                        \
     }                                                                           \
   } while (0)
-  if (pre && e0 < e1) LM_MF_FETCH(e0);
+  if (PRE && e0 < e1) LM_MF_FETCH(e0);
   for (int e = e0; e < e1; ++e) {
     __syncthreads();
-    if (pre) {
+    if (PRE) {
 #pragma unroll
-      for (int u = 0; u < (PRE ? MF_PF : 1); ++u) {
-        const int idx = threadIdx.x + NTH * u;
-        if (idx < NS) S[idx] = pf[u];
-      }
+      for (int u = 0; u < (PRE ? MF_PT : 1); ++u)
+        if (NTH * u + tid < PP) S[NTH * u + tid] = pt[u];
+#pragma unroll
+      for (int u = 0; u < (PRE ? MF_PA : 1); ++u)
+        if (NTH * u + tid < PR) S[PP + NTH * u + tid] = pa[u];
       __syncthreads();
       if (e + 1 < e1) LM_MF_FETCH(e + 1);
     } else {
@@ -804,10 +812,10 @@ inline void m2l_mfma_launch(int n_items, int p, int R, const int* items, const i
   const int P = 2 * p + 1, MT = (P + 15) / 16, NT = (R + 15) / 16;
   const size_t lds = mf_lds_bytes(P, R);
   const bool two = MT > MF_TR;
-  const int NS = P * P + P * R;
+  const int PP = P * P, PR = P * R;
 #define LM_MF(WC, WR)                                                                                               \
   do {                                                                                                              \
-    if (NS <= MF_PF * 64 * (WC) * (WR))                                                                             \
+    if (PP <= MF_PT * 64 * (WC) * (WR) && PR <= MF_PA * 64 * (WC) * (WR))                                           \
       hipLaunchKernelGGL((k_m2l_mfma<WC, WR, KIND, true>), dim3(n_items), dim3(64 * (WC) * (WR)), lds, s, p, R,    \
                          items, src, opi, ops, in, out, dtgt, accumulate);                                          \
     else                                                                                                            \
@@ -852,6 +860,7 @@ inline hipError_t m2l_mfma_allow_lds(size_t bytes) {
 // much longer than the others.
 constexpr int M2L_EB = 8;
 constexpr int M2L_ITEM = 32;
+constexpr int M2L_MF_ITEM = 32;  // entries per item of the matrix-core M2L lists
 template <typename RT>
 __global__ void __launch_bounds__(64) k_m2l_apply(int p, const int* __restrict__ items, const int* __restrict__ slot,
                                                   const int* __restrict__ src,
@@ -1792,6 +1801,22 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       z += (int64_t)q * B.npt;
     }
     F->nb_nnz = z;
+    // items write disjoint rows: launch the largest (rows x columns) first
+    const int nit = (int)F->nb_item.size() / 2;
+    std::vector<int64_t> work(nit);
+    std::vector<int> ord(nit);
+    for (int i = 0; i < nit; ++i) {
+      const int t = F->nb_item[2 * i], r = F->nb_item[2 * i + 1];
+      work[i] = (int64_t)std::min(PA_ROWS, F->nb_rows[t] - r) * (F->nb_jptr[t + 1] - F->nb_jptr[t]);
+      ord[i] = i;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<int> sorted(F->nb_item.size());
+    for (int i = 0; i < nit; ++i) {
+      sorted[2 * i] = F->nb_item[2 * ord[i]];
+      sorted[2 * i + 1] = F->nb_item[2 * ord[i] + 1];
+    }
+    F->nb_item.swap(sorted);
   }
 
   // ---- M2L entries grouped by operator ----------------------------------------
@@ -1811,21 +1836,44 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       F->tm_slot[q] = (int)e;
       F->tm_src[q] = F->m2l_src[e];
     }
+    // matrix-core M2L items: slots in target order; launched longest first so
+    // that the short items fill in behind the long ones
+    std::vector<int> it;
     F->mf_ptr.push_back(0);
     for (size_t t = 0; t < F->m2l_tgt.size(); ++t) {
-      for (int e = F->m2l_ptr[t]; e < F->m2l_ptr[t + 1]; e += M2L_ITEM) {
-        F->mf_item.push_back((int)t);
-        F->mf_item.push_back(e);
-        F->mf_item.push_back(std::min(e + M2L_ITEM, F->m2l_ptr[t + 1]));
+      for (int e = F->m2l_ptr[t]; e < F->m2l_ptr[t + 1]; e += M2L_MF_ITEM) {
+        it.push_back((int)t);
+        it.push_back(e);
+        it.push_back(std::min(e + M2L_MF_ITEM, F->m2l_ptr[t + 1]));
       }
-      F->mf_ptr.push_back((int)F->mf_item.size() / 3);
+      F->mf_ptr.push_back((int)it.size() / 3);
     }
+    const int nit = (int)it.size() / 3;
+    F->mf_slot.resize(nit);
+    for (int i = 0; i < nit; ++i) F->mf_slot[i] = i;
+    std::stable_sort(F->mf_slot.begin(), F->mf_slot.end(),
+                     [&](int a, int b) { return it[3 * a + 2] - it[3 * a + 1] > it[3 * b + 2] - it[3 * b + 1]; });
+    F->mf_item.resize(it.size());
+    for (int i = 0; i < nit; ++i)
+      for (int c = 0; c < 3; ++c) F->mf_item[3 * i + c] = it[3 * F->mf_slot[i] + c];
     for (int t = 0; t < ntab; ++t)
       for (int e = F->tm_ptr[t]; e < F->tm_ptr[t + 1]; e += M2L_ITEM) {
         F->tm_item.push_back(t);
         F->tm_item.push_back(e);
         F->tm_item.push_back(std::min(e + M2L_ITEM, F->tm_ptr[t + 1]));
       }
+    {  // operator-major items write per-entry slots: launch the longest first
+      const int n = (int)F->tm_item.size() / 3;
+      std::vector<int> ord(n);
+      for (int i = 0; i < n; ++i) ord[i] = i;
+      const std::vector<int>& ti = F->tm_item;
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int a, int b) { return ti[3 * a + 2] - ti[3 * a + 1] > ti[3 * b + 2] - ti[3 * b + 1]; });
+      std::vector<int> sorted(ti.size());
+      for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) sorted[3 * i + c] = ti[3 * ord[i] + c];
+      F->tm_item.swap(sorted);
+    }
   }
 
   // ---- translation items for the matrix-core M2M / L2L ------------------------------
@@ -2047,6 +2095,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_tm_item, F->tm_item, s));
   LM_TRY(up(F->d_mf_item, F->mf_item, s));
   LM_TRY(up(F->d_mf_ptr, F->mf_ptr, s));
+  LM_TRY(up(F->d_mf_slot, F->mf_slot, s));
   LM_TRY(up(F->d_tm_slot, F->tm_slot, s));
   LM_TRY(up(F->d_tm_src, F->tm_src, s));
   // point matrices of the matrix-core P2M / L2P
@@ -2320,7 +2369,7 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
       float2* mpart = (float2*)ws.p[FMM_WS_MF_PART];
       m2l_mfma_launch<MF_LIST>((int)(F->mf_item.size() / 3), p, R, F->d_mf_item.as<int>(), F->d_m2l_src.as<int>(),
                                F->d_m2l_op.as<int>(), (const float2*)mops, (const float2*)me, mpart,
-                               (const int*)nullptr, 0, s);
+                               F->d_mf_slot.as<int>(), 0, s);
       LM_STAGE(2, 0);
       LM_STAGE(6, 1);
       hipLaunchKernelGGL(k_p2m_reduce<float>, dim3(F->m2l_tgt.size()), dim3(256), 0, s, PR, F->d_m2l_tgt.as<int>(),

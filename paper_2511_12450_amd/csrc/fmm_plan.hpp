@@ -49,7 +49,9 @@ struct FmmPlan {
   // M2L entries grouped by operator (reaction tables, then free classes)
   std::vector<int> tm_ptr, tm_slot, tm_src;
   std::vector<int> tm_item;  // (operator, first entry, end) work items
-  std::vector<int> mf_item, mf_ptr;  // (target slot, first entry, end) items, items per target
+  // (target, first entry, end) items of the matrix-core M2L, longest first;
+  // mf_slot: each item's partial slot (slots in target order, mf_ptr: slots per target)
+  std::vector<int> mf_item, mf_slot, mf_ptr;
   std::vector<int> tr_item, tr_src, tr_op;  // matrix-core M2M (per parent) and L2L (per box) items
   // free-space near field + self terms as leaf blocks: rows = the leaf's
   // elements, columns = the leaf's and its neighbours' elements
@@ -85,7 +87,7 @@ struct FmmPlan {
   DevBuf d_self, d_me, d_le, d_tree_layer;
   DevBuf d_tr_item, d_tr_src, d_tr_op, d_box_id;
   DevBuf d_nb_jptr, d_nb_jidx, d_nb_rows, d_nb_item, d_nb_zoff, d_nb_Z32, d_rn_val32, d_xt;
-  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
+  DevBuf d_nm_ptr, d_nm_src, d_nm_val, d_nm_val32, d_mf_item, d_mf_slot, d_mf_ptr, d_mf_part, d_tm_item, d_tm_ptr, d_tm_slot, d_tm_src, d_m2l_out;
   DevBuf d_top_grid, d_top_item, d_top_ptr, d_top_src, d_top_op, d_top_id, d_top_tw64, d_top_tw32;
   DevBuf d_top_T64, d_top_T32, d_top_mh, d_top_lh;
   DevBuf d_om_slot;  // per-entry M2L results of the few-right-hand-side (operator-major) launch
@@ -109,7 +111,7 @@ struct FmmPlan {
                            &d_rn_val, &d_rn_rows, &d_p2m_Z32, &d_l2p_Z32, &d_self, &d_me, &d_le, &d_tree_layer,
                            &d_nm_ptr, &d_nm_src, &d_nm_val, &d_nm_val32, &d_nb_jptr, &d_nb_jidx, &d_nb_rows,
                            &d_nb_item, &d_nb_zoff, &d_nb_Z32, &d_rn_val32, &d_xt, &d_tr_item, &d_tr_src, &d_tr_op,
-                           &d_box_id, &d_mf_item, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
+                           &d_box_id, &d_mf_item, &d_mf_slot, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
                            &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
                            &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh,
                            &d_om_slot, &d_p2m_dst, &d_p2m_msel};

@@ -540,6 +540,21 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
       for (int k = 0; k < nseg; ++k) P->items.insert(P->items.end(), {b, r, k * len, std::min(q, (k + 1) * len), P->nslot++});
     }
   }
+  {  // every item has its own slot: launch the largest (rows x columns) first
+    const int nit = (int)P->items.size() / 5;
+    std::vector<int64_t> work(nit);
+    std::vector<int> ord(nit);
+    for (int i = 0; i < nit; ++i) {
+      const int* it = &P->items[5 * i];
+      work[i] = (int64_t)std::min(PH_ROWS, P->nb[it[0]] - it[1]) * (it[3] - it[2]);
+      ord[i] = i;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<int> sorted(P->items.size());
+    for (int i = 0; i < nit; ++i)
+      for (int c = 0; c < 5; ++c) sorted[5 * i + c] = P->items[5 * ord[i] + c];
+    P->items.swap(sorted);
+  }
   LM_CHECK(P->qmax <= PRE_QMAX, LM_EINVAL, "preconditioner neighbourhood too large (%d > %d); use a finer level",
            P->qmax, PRE_QMAX);
   {  // the VALU apply stages x_J of one or two right-hand sides in LDS (up to 128 KiB)
