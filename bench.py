@@ -564,7 +564,9 @@ def main():
                       "fused_rhs_per_launch": (st1["fused_rhs"] - st0["fused_rhs"]) /
                                               max(1, st1["launches"] - st0["launches"]),
                       "km_phase_ms": ph["km_ms"], "gs_phase_ms": ph["gs_ms"], "m2l_ms": ph["m2l_ms"],
-                      "round_host_ms": ph["round_ms"], "finish_host_ms": ph["finish_ms"]},
+                      "round_host_ms": ph["round_ms"], "finish_host_ms": ph["finish_ms"],
+                      "round_queue_ms": ph["launch_ms"], "round_wait_ms": ph["wait_ms"],
+                      "round_step_ms": ph["step_ms"]},
            "setup_s": setup_s, "device_bytes": int(geo.device_bytes), "fmm": stats,
            "matvec_fp32_R64_ms": float(t_mix[7]),
            "matvec_fp32_R64_stage_ms": {s_: float(t) for s_, t in zip(STAGES, t_mix) if s_ != "total"},

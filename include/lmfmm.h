@@ -372,7 +372,7 @@ lm_status lm_server_stats(lm_server server, int64_t* out6);
  * buffers, round buffers; not the geometries), the part held by spare
  * solves, and the admitted footprint (as lm_server_stats). */
 lm_status lm_server_memory(lm_server server, int64_t* out3);
-/* Host output of 8 doubles accumulated over the server's rounds, measured
+/* Host output of 11 doubles accumulated over the server's rounds, measured
  * with HIP events on the streams the kernels run on: [0] ms in the fused
  * K M phase (gathers, preconditioner, matvecs; every geometry stream
  * joined), [1] ms in the Gram-Schmidt phase (classical Gram-Schmidt with a
@@ -387,8 +387,12 @@ lm_status lm_server_memory(lm_server server, int64_t* out3);
  * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
  * [5] the number of those launches, [6] host wall-clock ms of the rounds
  * (everything but finishing columns), [7] host wall-clock ms spent finishing
- * columns (phi = M z, far field, copies to host memory). */
-lm_status lm_server_phase_times(lm_server server, double* out8);
+ * columns (phi = M z, far field, copies to host memory); the rounds' host
+ * time split: [8] ms queueing a round's copies and kernels, [9] ms blocked
+ * in the round's one wait (for the dot products and norms), [10] ms of the
+ * host step after it (Hessenberg columns, rotations, coefficients) up to the
+ * queued update pass. */
+lm_status lm_server_phase_times(lm_server server, double* out11);
 /* Cancels everything in flight, joins the worker and frees the server. */
 lm_status lm_server_destroy(lm_server server);
 

@@ -437,6 +437,19 @@ struct Group {
   KmBufs km;
 };
 
+// Pinned host staging (hipHostMalloc) for the per-round copies, grown on demand.
+struct HostBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
 // One column's host update of a round: descriptors and coefficients with
 // offsets local to this column (rebased when the columns are merged).
 struct HostStep {
@@ -534,8 +547,11 @@ struct lm_server_s {
   double km_ms = 0.0, gs_ms = 0.0, gs_bytes = 0.0;  // phase times (HIP events) and Gram-Schmidt algorithmic bytes
   double m2l_ms = 0.0, m2l_flops = 0.0;              // M2L launches of the fused matvecs (HIP events)
   double round_ms = 0.0, finish_ms = 0.0;            // host wall time of rounds / of finishing columns
+  double launch_ms = 0.0, wait_ms = 0.0, step_ms = 0.0;  // host wall time: queueing a round, its wait, the host step
   int64_t m2l_launches = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+  hipEvent_t tu1 = nullptr, tu2 = nullptr;  // update pass of the last round, read after the next wait
+  bool tu_pending = false;
   hipEvent_t sev[SRV_STREAMS][16] = {};
   // worker state
   std::vector<Column*> cols;
@@ -546,13 +562,14 @@ struct lm_server_s {
   hipStream_t gs[SRV_STREAMS] = {};
   hipEvent_t ev_main = nullptr;
   hipEvent_t ev[SRV_STREAMS] = {};
-  DevBuf d_desc, d_h, d_nrm, d_dpart, d_npart, d_y;
+  // descriptors of a round's kernels (gather, dot products, updates), each
+  // with its own device buffer and pinned staging buffer
+  DevBuf d_desc, d_desc_h, d_desc_u, d_h, d_nrm, d_dpart, d_npart, d_y;
+  HostBuf h_desc, h_desc_h, h_desc_u, h_y, h_h, h_nrm;
   DevBuf d_fz, d_fphi, d_fff;  // finishing columns: z, phi = M z, far fields
   std::unique_ptr<HostPool> pool;  // per-column host updates
   std::vector<HostStep> steps;
   std::vector<ColDev> hdesc;
-  std::vector<double2> hh;
-  std::vector<double> hnrm;
 };
 
 namespace {
@@ -566,12 +583,57 @@ int64_t footprint(const lm_geom_s* g, const lm_gmres_opts& o, int R) {
   return per * R;
 }
 
-lm_status upload_desc(lm_server_s* S, const std::vector<ColDev>& d) {
-  const size_t b = d.size() * sizeof(ColDev);
-  if (S->d_desc.bytes < b) LM_TRY(S->d_desc.alloc(std::max<size_t>(b, 64 * sizeof(ColDev))));
-  LM_TRY_HIP(hipMemcpyAsync(S->d_desc.p, d.data(), b, hipMemcpyHostToDevice, S->s));
-  // the host vector may change before the copy runs: wait for it
+// Waits for everything queued on the server's streams (the side streams of
+// the fused launches join the main stream every round), before device
+// buffers that queued kernels may still use are freed or regrown.
+lm_status quiesce(lm_server_s* S) {
   LM_TRY_HIP(hipStreamSynchronize(S->s));
+  return LM_OK;
+}
+
+lm_status ensure(lm_server_s* S, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return LM_OK;
+  if (b.p) LM_TRY(quiesce(S));
+  LM_TRY(b.alloc(bytes));
+  return LM_OK;
+}
+
+lm_status host_ensure(lm_server_s* S, HostBuf& h, size_t bytes) {
+  if (h.bytes >= bytes) return LM_OK;
+  if (h.p) {
+    LM_TRY(quiesce(S));  // a copy from the old buffer may be queued
+    (void)hipHostFree(h.p);
+    h.p = nullptr;
+    h.bytes = 0;
+  }
+  const size_t n = std::max<size_t>(2 * bytes, 4096);
+  LM_TRY_HIP(hipHostMalloc(&h.p, n, hipHostMallocDefault));
+  h.bytes = n;
+  return LM_OK;
+}
+
+// Queues the copy of n bytes from src to device buffer d through the pinned
+// buffer h, without waiting.  Each staging buffer is written once per round,
+// after the round's wait, or before it when the previous round's copy from it
+// preceded that round's wait; so no queued copy still reads it.
+lm_status upload_async(lm_server_s* S, HostBuf& h, DevBuf& d, const void* src, size_t n) {
+  LM_TRY(host_ensure(S, h, n));
+  LM_TRY(ensure(S, d, std::max<size_t>(n, 64 * sizeof(ColDev))));
+  std::memcpy(h.p, src, n);
+  LM_TRY_HIP(hipMemcpyAsync(d.p, h.p, n, hipMemcpyHostToDevice, S->s));
+  return LM_OK;
+}
+
+// Adds the time of the last update pass to the phase times once its events
+// are complete (called after a wait that covers them).
+lm_status collect_update_time(lm_server_s* S) {
+  if (!S->tu_pending) return LM_OK;
+  float t = 0.f;
+  LM_TRY_HIP(hipEventSynchronize(S->tu2));
+  LM_TRY_HIP(hipEventElapsedTime(&t, S->tu1, S->tu2));
+  S->tu_pending = false;
+  std::lock_guard<std::mutex> lk(S->B.mu);
+  S->gs_ms += t;
   return LM_OK;
 }
 
@@ -582,13 +644,9 @@ int pre_precision(const lm_server_s* S) { return S->o.precond_fp64 ? LM_FP64 : S
 // Bytes per element of a column's Krylov basis.
 size_t basis_bytes(const lm_server_s* S) { return S->o.precision == LM_MIXED ? sizeof(float2) : sizeof(double2); }
 
-lm_status ensure(DevBuf& b, size_t bytes) {
-  if (b.bytes < bytes) LM_TRY(b.alloc(bytes));
-  return LM_OK;
-}
-
 // Allocate the columns of an admitted request and compute its right-hand sides.
 void drop_spares(lm_server_s* S) {
+  if (!S->spare.empty()) (void)quiesce(S);
   for (Column* c : S->spare) delete c;
   S->spare.clear();
 }
@@ -605,6 +663,7 @@ void trim_spares(lm_server_s* S, int64_t allow, const std::vector<Request*>& adm
       if (q->g->N == c->N && std::max(1, std::min(q->o.restart, q->o.max_iter)) == c->m) return true;
     return false;
   };
+  if (sb > allow) (void)quiesce(S);
   for (int pass = 0; pass < 2 && sb > allow; ++pass)
     for (auto it = S->spare.begin(); it != S->spare.end() && sb > allow;) {
       if (pass == 0 && reusable(*it)) {
@@ -621,6 +680,11 @@ void trim_spares(lm_server_s* S, int64_t allow, const std::vector<Request*>& adm
 // admitted column uses any more, and the round and finishing buffers when
 // nothing runs; then records the device bytes the server holds.
 void settle_memory(lm_server_s* S, bool idle) {
+  if (idle) {  // nothing is queued behind this wait
+    (void)quiesce(S);
+    (void)collect_update_time(S);
+  }
+  bool synced = idle;
   for (auto it = S->groups.begin(); it != S->groups.end();) {
     bool live = false;
     for (const Column* c : S->cols)
@@ -628,6 +692,10 @@ void settle_memory(lm_server_s* S, bool idle) {
         live = true;
         break;
       }
+    if (!live && !synced) {
+      (void)quiesce(S);  // the group's buffers may still be in use by queued kernels
+      synced = true;
+    }
     it = live ? std::next(it) : S->groups.erase(it);
   }
   if (idle)  // nothing admitted: the round and finishing buffers are regrown on demand
@@ -807,8 +875,8 @@ lm_status run_round(lm_server_s* S) {
   for (auto& kv : byg) {
     Group& G = S->groups[kv.first];
     const int R = (int)kv.second.size(), N = (int)kv.first.first->N;
-    LM_TRY(ensure(G.X, (size_t)R * N * sizeof(double2)));
-    LM_TRY(ensure(G.Y, (size_t)R * N * sizeof(double2)));
+    LM_TRY(ensure(S, G.X, (size_t)R * N * sizeof(double2)));
+    LM_TRY(ensure(S, G.Y, (size_t)R * N * sizeof(double2)));
     for (int k = 0; k < R; ++k) {
       Column* c = kv.second[k];
       ColDev d{};
@@ -839,7 +907,7 @@ lm_status run_round(lm_server_s* S) {
       gath.push_back(d);
     }
   if (!gath.empty()) {
-    LM_TRY(upload_desc(S, gath));
+    LM_TRY(upload_async(S, S->h_desc, S->d_desc, gath.data(), gath.size() * sizeof(ColDev)));
     if (f32)
       hipLaunchKernelGGL(k_s_gather<float2>, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s,
                          S->d_desc.as<ColDev>());
@@ -888,9 +956,9 @@ lm_status run_round(lm_server_s* S) {
   LM_TRY_HIP(hipEventRecord(S->t1, S->s));
   float km_round = 0.f;
   // ---- 2. dot products of the delayed two-pass Gram-Schmidt, residuals, norms
-  LM_TRY(ensure(S->d_npart, (size_t)nc * nwu * sizeof(double)));
-  LM_TRY(ensure(S->d_nrm, (size_t)nc * sizeof(double)));
-  LM_TRY(ensure(S->d_h, (size_t)nc * hs * sizeof(double2)));
+  LM_TRY(ensure(S, S->d_npart, (size_t)nc * nwu * sizeof(double)));
+  LM_TRY(ensure(S, S->d_nrm, (size_t)nc * sizeof(double)));
+  LM_TRY(ensure(S, S->d_h, (size_t)nc * hs * sizeof(double2)));
   S->hdesc.assign(nc, ColDev{});
   for (int i = 0; i < nc; ++i) {
     Column* c = cols[i];
@@ -907,12 +975,10 @@ lm_status run_round(lm_server_s* S) {
       d.g = (c->phase == PH_RESTART || c->phase == PH_FINAL) ? c->gv.as<double2>() : nullptr;
     }
   }
-  LM_TRY(upload_desc(S, S->hdesc));  // synchronises: the Gram-Schmidt timing starts after it
-  LM_TRY_HIP(hipEventElapsedTime(&km_round, S->t0, S->t1));
-  LM_TRY_HIP(hipEventRecord(S->t1, S->s));
-  const ColDev* dd = S->d_desc.as<ColDev>();
+  LM_TRY(upload_async(S, S->h_desc_h, S->d_desc_h, S->hdesc.data(), S->hdesc.size() * sizeof(ColDev)));
+  const ColDev* dd = S->d_desc_h.as<ColDev>();
   if (cntmax > 0) {
-    LM_TRY(ensure(S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
+    LM_TRY(ensure(S, S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
     double2* pa = S->d_dpart.as<double2>();
     double2* pb = pa + (size_t)nc * ldh * nbd;
     if (f32)
@@ -930,15 +996,22 @@ lm_status run_round(lm_server_s* S) {
   hipLaunchKernelGGL(k_s_norm_final, dim3(nc), dim3(64), 0, S->s, dd, S->d_npart.as<double>(), nwu,
                      S->d_nrm.as<double>());
   LM_TRY_HIP(hipGetLastError());
-  S->hh.resize((size_t)nc * hs);
-  S->hnrm.resize(nc);
+  LM_TRY(host_ensure(S, S->h_h, (size_t)nc * hs * sizeof(double2)));
+  LM_TRY(host_ensure(S, S->h_nrm, (size_t)nc * sizeof(double)));
   if (cntmax > 0)
-    LM_TRY_HIP(hipMemcpyAsync(S->hh.data(), S->d_h.p, (size_t)nc * hs * sizeof(double2), hipMemcpyDeviceToHost, S->s));
-  LM_TRY_HIP(hipMemcpyAsync(S->hnrm.data(), S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
+    LM_TRY_HIP(hipMemcpyAsync(S->h_h.p, S->d_h.p, (size_t)nc * hs * sizeof(double2), hipMemcpyDeviceToHost, S->s));
+  LM_TRY_HIP(hipMemcpyAsync(S->h_nrm.p, S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipEventRecord(S->t2, S->s));
+  // the round's one wait: the host step needs the dot products and norms
+  const double tw0 = now_s();
   LM_TRY_HIP(hipStreamSynchronize(S->s));
+  const double tw1 = now_s();
   float gs_a = 0.f;
+  LM_TRY_HIP(hipEventElapsedTime(&km_round, S->t0, S->t1));
   LM_TRY_HIP(hipEventElapsedTime(&gs_a, S->t1, S->t2));
+  LM_TRY(collect_update_time(S));  // the previous round's update pass
+  const double2* hhv = S->h_h.as<double2>();
+  const double* hnv = S->h_nrm.as<double>();
   // ---- 3. host updates ------------------------------------------------------------
   // Per column, independent of the others (its Hessenberg correction is
   // O(j^2)): spread over the host pool, each column's descriptors and
@@ -949,7 +1022,7 @@ lm_status run_round(lm_server_s* S) {
     HostStep& o = S->steps[i];
     o.clear();
     Column* c = cols[i];
-    const double nrm = std::sqrt(S->hnrm[i]);
+    const double nrm = std::sqrt(hnv[i]);
     const double tol = c->req->o.tol;
     const int N = c->N, m = c->m;
     const double n16 = 16.0 * N;
@@ -1016,7 +1089,7 @@ lm_status run_round(lm_server_s* S) {
     // basis vectors (bb bytes per element) and complex128 vectors moved by the
     // dot, residual-norm and update kernels of this step
     o.gsb += (c->km ? (2.0 * j + 5.0) * bb + 3.0 * 16.0 : (j + 2.0) * bb) * N;
-    const double2* ha = &S->hh[(size_t)i * hs];
+    const double2* ha = &hhv[(size_t)i * hs];
     const double2* hb = ha + ldh;
     std::vector<C> aQ(j), bQ(j);
     for (int k = 0; k < j; ++k) {
@@ -1127,10 +1200,7 @@ lm_status run_round(lm_server_s* S) {
   const size_t ncf = cf.size();
   std::vector<double2> coefs(cf);
   coefs.insert(coefs.end(), ys.begin(), ys.end());
-  if (!coefs.empty()) {
-    LM_TRY(ensure(S->d_y, coefs.size() * sizeof(double2)));
-    LM_TRY_HIP(hipMemcpyAsync(S->d_y.p, coefs.data(), coefs.size() * sizeof(double2), hipMemcpyHostToDevice, S->s));
-  }
+  if (!coefs.empty()) LM_TRY(upload_async(S, S->h_y, S->d_y, coefs.data(), coefs.size() * sizeof(double2)));
   for (auto& d : upd) {
     d.y = S->d_y.as<double2>() + (size_t)d.src;
     d.src = nullptr;
@@ -1142,13 +1212,12 @@ lm_status run_round(lm_server_s* S) {
   std::vector<ColDev> all(upd);
   all.insert(all.end(), scal.begin(), scal.end());
   all.insert(all.end(), comb.begin(), comb.end());
-  float gs_b = 0.f;
   if (!all.empty()) {
-    LM_TRY(upload_desc(S, all));
+    LM_TRY(upload_async(S, S->h_desc_u, S->d_desc_u, all.data(), all.size() * sizeof(ColDev)));
     int nm = 0;
     for (auto& d : all) nm = std::max(nm, d.N);
-    const ColDev* da = S->d_desc.as<ColDev>();
-    LM_TRY_HIP(hipEventRecord(S->t1, S->s));
+    const ColDev* da = S->d_desc_u.as<ColDev>();
+    LM_TRY_HIP(hipEventRecord(S->tu1, S->s));
     if (!upd.empty()) {
       if (f32)
         hipLaunchKernelGGL(k_s_update2<float2>, dim3(div_up(nm, SU_ELEM), upd.size()), dim3(256), 0, S->s, da,
@@ -1158,7 +1227,8 @@ lm_status run_round(lm_server_s* S) {
                            S->d_npart.as<double>(), nwu);
       hipLaunchKernelGGL(k_s_norm_to, dim3(upd.size()), dim3(64), 0, S->s, da, S->d_npart.as<double>(), nwu);
     }
-    LM_TRY_HIP(hipEventRecord(S->t2, S->s));
+    LM_TRY_HIP(hipEventRecord(S->tu2, S->s));
+    S->tu_pending = true;
     if (!scal.empty()) {
       if (f32)
         hipLaunchKernelGGL(k_s_copy<float2>, dim3(div_up(nm, 256), scal.size()), dim3(256), 0, S->s, da + upd.size());
@@ -1175,9 +1245,10 @@ lm_status run_round(lm_server_s* S) {
                            da + upd.size() + scal.size());
     }
     LM_TRY_HIP(hipGetLastError());
-    LM_TRY_HIP(hipStreamSynchronize(S->s));  // d_y / descriptors are reused next round
-    LM_TRY_HIP(hipEventElapsedTime(&gs_b, S->t1, S->t2));
+    // no wait here: the next round's copies and kernels are queued behind
+    // these on the same stream
   }
+  const double tw2 = now_s();
   {
     float m2l = 0.f;
     for (int si : timed_streams) {
@@ -1187,7 +1258,10 @@ lm_status run_round(lm_server_s* S) {
     }
     std::lock_guard<std::mutex> lk(S->B.mu);
     S->km_ms += km_round;
-    S->gs_ms += gs_a + gs_b;
+    S->gs_ms += gs_a;
+    S->launch_ms += 1e3 * (tw0 - tr0);
+    S->wait_ms += 1e3 * (tw1 - tw0);
+    S->step_ms += 1e3 * (tw2 - tw1);
     S->m2l_ms += m2l;
     S->m2l_flops += m2l_flops_round;
     S->m2l_launches += (int64_t)timed_streams.size();
@@ -1215,6 +1289,7 @@ lm_status run_round(lm_server_s* S) {
 // Removes the request's columns; up to max_active_rhs of them stay as spares
 // with their device buffers for the next admission of the same shape.
 void release_columns(lm_server_s* S, Request* q) {
+  (void)quiesce(S);  // queued kernels may still use the columns' buffers
   auto& v = S->cols;
   for (auto it = v.begin(); it != v.end();) {
     if ((*it)->req == q) {
@@ -1286,7 +1361,8 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
   bool ok = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&S->ev_main, hipEventDisableTiming) == hipSuccess &&
             hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
-            hipEventCreate(&S->t2) == hipSuccess;
+            hipEventCreate(&S->t2) == hipSuccess && hipEventCreate(&S->tu1) == hipSuccess &&
+            hipEventCreate(&S->tu2) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
     for (int e = 0; ok && e < 16; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
@@ -1402,8 +1478,9 @@ extern "C" lm_status lm_server_memory(lm_server S, int64_t* out3) {
   return LM_OK;
 }
 
-extern "C" lm_status lm_server_phase_times(lm_server S, double* out8) {
-  LM_CHECK(S && out8, LM_EINVAL, "bad arguments");
+extern "C" lm_status lm_server_phase_times(lm_server S, double* out11) {
+  LM_CHECK(S && out11, LM_EINVAL, "bad arguments");
+  double* out8 = out11;
   std::lock_guard<std::mutex> lk(S->B.mu);
   out8[0] = S->km_ms;
   out8[1] = S->gs_ms;
@@ -1413,6 +1490,9 @@ extern "C" lm_status lm_server_phase_times(lm_server S, double* out8) {
   out8[5] = (double)S->m2l_launches;
   out8[6] = S->round_ms;
   out8[7] = S->finish_ms;
+  out11[8] = S->launch_ms;
+  out11[9] = S->wait_ms;
+  out11[10] = S->step_ms;
   return LM_OK;
 }
 
@@ -1421,16 +1501,16 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
   S->B.request_stop();
   if (S->th.joinable()) S->th.join();
   S->B.clear();
+  (void)hipStreamSynchronize(S->s);
   for (Column* c : S->cols) delete c;
   S->cols.clear();
   S->groups.clear();
-  (void)hipStreamSynchronize(S->s);
   for (int i = 0; i < SRV_STREAMS; ++i) {
     if (S->gs[i]) (void)hipStreamDestroy(S->gs[i]);
     if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
   }
   if (S->ev_main) (void)hipEventDestroy(S->ev_main);
-  for (hipEvent_t e : {S->t0, S->t1, S->t2})
+  for (hipEvent_t e : {S->t0, S->t1, S->t2, S->tu1, S->tu2})
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < SRV_STREAMS; ++i)
     for (int e = 0; e < 16; ++e)

@@ -440,11 +440,13 @@ class Server:
 
     def phase_times(self):
         """dict: K M phase ms, Gram-Schmidt phase ms and algorithmic bytes,
-        M2L launch ms, flops and count (lm_server_phase_times)."""
-        out = np.zeros(8)
+        M2L launch ms, flops and count, host ms of rounds and finishing, and
+        the rounds' host split: queueing, waiting, host step
+        (lm_server_phase_times)."""
+        out = np.zeros(11)
         _check(lib().lm_server_phase_times(self.h, _dptr(out)))
-        return dict(zip(["km_ms", "gs_ms", "gs_bytes", "m2l_ms", "m2l_flops", "m2l_launches", "round_ms", "finish_ms"],
-                        [float(v) for v in out]))
+        return dict(zip(["km_ms", "gs_ms", "gs_bytes", "m2l_ms", "m2l_flops", "m2l_launches", "round_ms", "finish_ms",
+                         "launch_ms", "wait_ms", "step_ms"], [float(v) for v in out]))
 
     def close(self):
         if self.h:
