@@ -18,10 +18,15 @@
 // one add.  The input is the complex64 transpose xt [N][R] (k_to_nr), so a
 // neighbourhood row of all right-hand sides is one contiguous load; Z_B is
 // row-major complex64.  K runs over the neighbourhood in chunks of PA_KC
-// complex columns staged in LDS (Z chunk transposed to [c][r], row stride 80
-// complex).  Eight wavefronts in a 4 x 2 grid hold 1 x 2 tiles each.
+// complex columns staged in LDS: the Z chunk row-major with row stride PA_ZK
+// = 36 complex (a row's loads are stored side by side, and the fragment
+// reads of 16 rows x 4 columns meet every bank exactly twice), the X chunk
+// [c][j] with row stride 80 complex.  The next chunk is loaded into registers
+// while the current one is multiplied.  Eight wavefronts in a 4 x 2 grid
+// hold 1 x 2 tiles each.
 typedef float pa_v4f __attribute__((ext_vector_type(4)));
-constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80;
+constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80, PA_ZK = 36;
+constexpr int PA_UZ = PA_ROWS * PA_KC / (64 * PA_NW), PA_UX = PA_KC * 64 / (64 * PA_NW);  // loads per thread
 // The product of one work item.  Op describes the item:
 //   rows, q                  output rows (<= PA_ROWS) and K length (complex)
 //   zrow(r)                  row r of the item's matrix (q complex64)
@@ -29,14 +34,14 @@ constexpr int PA_ROWS = 64, PA_KC = 32, PA_NW = 8, PA_LS = 80;
 //   store(r, j, re, im)      writes (or adds) output row r, right-hand side j
 template <class Op>
 __device__ __forceinline__ void block_mfma_body(const Op& op, int R) {
-  constexpr int TC = 2;
-  __shared__ float2 Zs[PA_KC][PA_LS];
+  constexpr int TC = 2, NTH = 64 * PA_NW;
+  __shared__ float2 Zs[PA_ROWS][PA_ZK];
   __shared__ float2 Xs[PA_KC][PA_LS];
   const int rows = op.rows, q = op.q;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int rt = wv >> 1, wc = wv & 1;  // row tile, column-tile pair
-  const int aoff = kq * PA_LS + 16 * rt + l16;  // complex offsets of this lane's fragments at k-step 0
+  const int aoff = (16 * rt + l16) * PA_ZK + kq;  // complex offsets of this lane's fragments at k-step 0
   int boff[TC];
 #pragma unroll
   for (int c = 0; c < TC; ++c) boff[c] = kq * PA_LS + 16 * (wc * TC + c) + l16;
@@ -45,21 +50,40 @@ __device__ __forceinline__ void block_mfma_body(const Op& op, int R) {
   pa_v4f t1[TC], t2[TC], t3[TC];
 #pragma unroll
   for (int c = 0; c < TC; ++c) t1[c] = t2[c] = t3[c] = pa_v4f{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < q; c0 += PA_KC) {
+  // chunk c0 into registers: consecutive threads along a matrix row, and
+  // along the right-hand sides of a neighbourhood row
+  float2 zp[PA_UZ], xp[PA_UX];
+  auto fetch = [&](int c0) {
     const int kc = min(PA_KC, q - c0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < PA_KC * PA_ROWS; idx += 64 * PA_NW) {
-      const int rr = idx / PA_KC, jj = idx - rr * PA_KC;  // consecutive threads along a matrix row
-      Zs[jj][rr] = (rr < rows && jj < kc) ? op.zrow(rr)[c0 + jj] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < PA_UZ; ++u) {
+      const int idx = threadIdx.x + NTH * u, rr = idx / PA_KC, jj = idx - rr * PA_KC;
+      zp[u] = (rr < rows && jj < kc) ? op.zrow(rr)[c0 + jj] : make_float2(0.f, 0.f);
     }
-    for (int idx = threadIdx.x; idx < PA_KC * 64; idx += 64 * PA_NW) {
-      const int jj = idx >> 6, rr = idx & 63;
-      Xs[jj][rr] = (jj < kc && rr < R) ? op.brow(c0 + jj)[rr] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < PA_UX; ++u) {
+      const int idx = threadIdx.x + NTH * u, jj = idx >> 6, rr = idx & 63;
+      xp[u] = (jj < kc && rr < R) ? op.brow(c0 + jj)[rr] : make_float2(0.f, 0.f);
+    }
+  };
+  if (q > 0) fetch(0);
+  for (int c0 = 0; c0 < q; c0 += PA_KC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PA_UZ; ++u) {
+      const int idx = threadIdx.x + NTH * u, rr = idx / PA_KC, jj = idx - rr * PA_KC;
+      Zs[rr][jj] = zp[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PA_UX; ++u) {
+      const int idx = threadIdx.x + NTH * u, jj = idx >> 6, rr = idx & 63;
+      Xs[jj][rr] = xp[u];
     }
     __syncthreads();
+    if (c0 + PA_KC < q) fetch(c0 + PA_KC);
 #pragma unroll 2
     for (int ks = 0; ks < PA_KC / 4; ++ks) {
-      const float2 av = Zf[aoff + 4 * ks * PA_LS];
+      const float2 av = Zf[aoff + 4 * ks];
       const float as = av.x + av.y;
 #pragma unroll
       for (int c = 0; c < TC; ++c) {

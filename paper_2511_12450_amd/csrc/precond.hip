@@ -195,11 +195,14 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
 // or the halves swapped (rho = 1).
 typedef _Float16 ph4 __attribute__((ext_vector_type(4)));
 typedef float pf4 __attribute__((ext_vector_type(4)));
-constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZS = 136, PH_XS = 80;  // rows per item; LDS strides
+constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZR = 36, PH_XS = 80;  // rows per item; LDS strides
 constexpr int PH_XLD = 64;  // row stride of the split input (right-hand sides)
 constexpr int PH_KSEG = 1024;  // most columns per work item (a multiple of PH_KC)
 constexpr int PH_MAXSEG = 8;    // column ranges of a row block: PRE_QMAX / PH_KSEG
 static_assert(PH_MAXSEG * PH_KSEG >= PRE_QMAX, "slots per row block");
+// Stored binary16 rows are padded with zeros to a multiple of PH_KC columns
+// (256 bytes), so every chunk a work item loads is whole 128-byte lines.
+__host__ __device__ inline int h16_qp(int q) { return (q + PH_KC - 1) / PH_KC * PH_KC; }
 
 __device__ __forceinline__ uint32_t h16_pack(float re, float im) {
   const _Float16 a = (_Float16)re, b = (_Float16)im;
@@ -209,13 +212,13 @@ __device__ __forceinline__ float h16_lo(uint32_t v) { return (float)__builtin_bi
 __device__ __forceinline__ float h16_hi(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); }
 
 // Row r (global index) of the stored blocks: scale 2^e with max |Re|, |Im| < 2^e,
-// binary16 entries of the scaled row at rzh[r], zero up to the next multiple of 4.
+// binary16 entries of the scaled row at rzh[r], zero up to h16_qp(q).
 __global__ void __launch_bounds__(256) k_z_to_h16(const int64_t* __restrict__ rz, const int64_t* __restrict__ rzh,
                                                   const int* __restrict__ rq, const double2* __restrict__ Z,
                                                   uint32_t* __restrict__ Zh, float* __restrict__ rsc) {
   const int r = blockIdx.x;
   const int64_t o = rz[r], oh = rzh[r];
-  const int q = rq[r], qp = (q + 3) & ~3;
+  const int q = rq[r], qp = h16_qp(q);
   double m = 0.0;
   for (int c = threadIdx.x; c < q; c += 256) m = fmax(m, fmax(fabs(Z[o + c].x), fabs(Z[o + c].y)));
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
@@ -311,12 +314,15 @@ __global__ void __launch_bounds__(512) k_pre_h16(int R, const int* __restrict__ 
                                                  const uint32_t* __restrict__ xh, const uint32_t* __restrict__ xl,
                                                  float2* __restrict__ part) {
   constexpr int TR = PH_ROWS / 32, UZ = PH_ROWS * PH_KC / 2048, UX = PH_KC * 64 / 2048;  // 16-byte loads per thread
-  __shared__ uint2 Zs[PH_KC / 2][PH_ZS];  // [column pair][row]
+  // [row][column pair]: a row's 16-byte loads go to LDS as 16-byte stores
+  // side by side, and the fragment reads (8 rows x 4 column pairs) meet 32
+  // different bank pairs (row stride 72 words)
+  __shared__ uint2 Zs[PH_ROWS][PH_ZR];
   __shared__ uint2 Xh[PH_KC / 2][PH_XS];  // [column pair][right-hand side]
   __shared__ uint2 Xl[PH_KC / 2][PH_XS];
   const int* it = items + 5 * blockIdx.x;
   const int sd = it[0], r0 = it[1], cb = it[2], ce = it[3], slot = it[4];
-  const int j0 = jptr[sd], q = jptr[sd + 1] - j0, qp = (q + 3) & ~3;
+  const int j0 = jptr[sd], q = jptr[sd + 1] - j0, qp = h16_qp(q);
   const int rows = min(PH_ROWS, nb[sd] - r0);
   const int* J = jidx + j0;
   const uint32_t* Zl = Zh + zoff[sd] + (int64_t)r0 * qp;
@@ -330,8 +336,8 @@ __global__ void __launch_bounds__(512) k_pre_h16(int R, const int* __restrict__ 
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[t][c] = pf4{0.f, 0.f, 0.f, 0.f};
   uint4 zr[UZ], hr[UX], lr[UX];
-// Next chunk into registers: 4 consecutive columns of a Z row (rows padded to a
-// multiple of 4), 4 consecutive right-hand sides of an input row.
+// Next chunk into registers: 4 consecutive columns of a Z row (rows padded to
+// h16_qp), 4 consecutive right-hand sides of an input row.
 #define PH_FETCH(c0)                                                                                                   \
   do {                                                                                                                 \
 _Pragma("unroll")                                                                                                      \
@@ -357,8 +363,7 @@ _Pragma("unroll")                                                               
 #pragma unroll
     for (int u = 0; u < UZ; ++u) {
       const int idx = threadIdx.x + 512 * u, rr = idx / (PH_KC / 4), cq = 4 * (idx % (PH_KC / 4));
-      Zs[cq >> 1][rr] = make_uint2(zr[u].x, zr[u].y);
-      Zs[(cq >> 1) + 1][rr] = make_uint2(zr[u].z, zr[u].w);
+      *reinterpret_cast<uint4*>(&Zs[rr][cq >> 1]) = zr[u];
     }
 #pragma unroll
     for (int u = 0; u < UX; ++u) {
@@ -387,7 +392,7 @@ _Pragma("unroll")                                                               
       }
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
-        uint2 z = Zs[pr][8 * (TR * wr + t) + (l16 >> 1)];
+        uint2 z = Zs[8 * (TR * wr + t) + (l16 >> 1)][pr];
         if (rho) {
           z.x = (z.x >> 16) | (z.x << 16);
           z.y = (z.y >> 16) | (z.y << 16);
@@ -613,7 +618,7 @@ lm_status precond_build(lm_geom_s* g, int coarsen, hipStream_t s) {
     P->zhoff.clear();
     int64_t zh = 0;
     for (int b = 0; b < P->nleaf; ++b) {
-      const int q = P->jptr[b + 1] - P->jptr[b], qp = (q + 3) & ~3;
+      const int q = P->jptr[b + 1] - P->jptr[b], qp = h16_qp(q);
       P->zhoff.push_back(zh);
       for (int r = 0; r < P->nb[b]; ++r) {
         rz.push_back(P->zoff[b] + (int64_t)r * q);
