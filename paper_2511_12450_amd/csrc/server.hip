@@ -477,10 +477,10 @@ class HostPool {
     for (int t = 1; t < nt_; ++t) th_.emplace_back([this] { loop(); });
   }
   ~HostPool() {
+    stop_.store(true, std::memory_order_release);
     {
       std::lock_guard<std::mutex> lk(m_);
-      stop_ = true;
-      ++gen_;
+      gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     for (auto& t : th_) t.join();
@@ -490,49 +490,55 @@ class HostPool {
       for (int i = 0; i < n; ++i) f(i);
       return;
     }
-    {
+    f_ = &f;
+    n_ = n;
+    next_.store(0, std::memory_order_relaxed);
+    busy_.store(nt_ - 1, std::memory_order_relaxed);
+    {  // under the lock, so that a worker going to sleep cannot miss it
       std::lock_guard<std::mutex> lk(m_);
-      f_ = &f;
-      n_ = n;
-      next_.store(0);
-      busy_ = nt_ - 1;
-      ++gen_;
+      gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     work();
-    std::unique_lock<std::mutex> lk(m_);
-    done_.wait(lk, [this] { return busy_ == 0; });
+    // the workers end within microseconds of the last item
+    while (busy_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
   }
 
  private:
   void work() {
     for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*f_)(i);
   }
+  // Waits for the next generation: polls for up to kSpin (rounds come every
+  // few milliseconds while requests run), then sleeps.
   void loop() {
+    constexpr auto kSpin = std::chrono::microseconds(200);
     uint64_t seen = 0;
     while (true) {
-      {
+      const auto t0 = std::chrono::steady_clock::now();
+      uint64_t g;
+      while ((g = gen_.load(std::memory_order_acquire)) == seen) {
+        if (std::chrono::steady_clock::now() - t0 < kSpin) {
+          std::this_thread::yield();
+          continue;
+        }
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return gen_ != seen; });
-        seen = gen_;
-        if (stop_) return;
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
       }
+      seen = g;
+      if (stop_.load(std::memory_order_acquire)) return;
       work();
-      {
-        std::lock_guard<std::mutex> lk(m_);
-        if (--busy_ == 0) done_.notify_one();
-      }
+      busy_.fetch_sub(1, std::memory_order_release);
     }
   }
   int nt_;
   std::vector<std::thread> th_;
   std::mutex m_;
-  std::condition_variable cv_, done_;
+  std::condition_variable cv_;
   const std::function<void(int)>* f_ = nullptr;
-  int n_ = 0, busy_ = 0;
-  std::atomic<int> next_{0};
-  uint64_t gen_ = 0;
-  bool stop_ = false;
+  int n_ = 0;
+  std::atomic<int> next_{0}, busy_{0};
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<bool> stop_{false};
 };
 
 }  // namespace
@@ -551,6 +557,7 @@ struct lm_server_s {
   int64_t m2l_launches = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
   hipEvent_t tu1 = nullptr, tu2 = nullptr;  // update pass of the last round, read after the next wait
+  hipEvent_t ev_wait = nullptr;             // end of a round's copies to the host (polled)
   bool tu_pending = false;
   hipEvent_t sev[SRV_STREAMS][16] = {};
   // worker state
@@ -564,8 +571,11 @@ struct lm_server_s {
   hipEvent_t ev[SRV_STREAMS] = {};
   // descriptors of a round's kernels (gather, dot products, updates), each
   // with its own device buffer and pinned staging buffer
-  DevBuf d_desc, d_desc_h, d_desc_u, d_h, d_nrm, d_dpart, d_npart, d_y;
-  HostBuf h_desc, h_desc_h, h_desc_u, h_y, h_h, h_nrm;
+  // d_desc: descriptors of the gather and the dot products; d_hn: Hessenberg
+  // dot products then norms; d_desc_u: update descriptors then coefficients.
+  // Each goes through one pinned buffer and one copy per round.
+  DevBuf d_desc, d_desc_u, d_hn, d_dpart, d_npart;
+  HostBuf h_desc, h_desc_u, h_hn;
   DevBuf d_fz, d_fphi, d_fff;  // finishing columns: z, phi = M z, far fields
   std::unique_ptr<HostPool> pool;  // per-column host updates
   std::vector<HostStep> steps;
@@ -699,7 +709,7 @@ void settle_memory(lm_server_s* S, bool idle) {
     it = live ? std::next(it) : S->groups.erase(it);
   }
   if (idle)  // nothing admitted: the round and finishing buffers are regrown on demand
-    for (DevBuf* b : {&S->d_desc, &S->d_h, &S->d_nrm, &S->d_dpart, &S->d_npart, &S->d_y, &S->d_fz, &S->d_fphi,
+    for (DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
                       &S->d_fff})
       b->release();
   int64_t h = 0, hs = 0;
@@ -709,7 +719,7 @@ void settle_memory(lm_server_s* S, bool idle) {
     const Group& G = kv.second;
     h += (int64_t)(G.X.bytes + G.Y.bytes + G.km.x32.bytes + G.km.y32.bytes + G.km.mz.bytes);
   }
-  for (const DevBuf* b : {&S->d_desc, &S->d_h, &S->d_nrm, &S->d_dpart, &S->d_npart, &S->d_y, &S->d_fz, &S->d_fphi,
+  for (const DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
                           &S->d_fff})
     h += (int64_t)b->bytes;
   std::lock_guard<std::mutex> lk(S->B.mu);
@@ -756,8 +766,10 @@ lm_status start_request(lm_server_s* S, Request* q) {
     }
     LM_TRY_HIP(hipMemsetAsync(col->z.p, 0, (size_t)N * sizeof(double2), S->s));
     LM_TRY(rhs_launch(q->g, 1, &q->theta[c], col->gv.p, S->s));
-    col->H.assign((size_t)(m + 1) * m, 0.0);
-    col->Hraw.assign((size_t)(m + 1) * m, 0.0);
+    // an Arnoldi step writes rows 0..j+1 of its Hessenberg column before
+    // anything reads them, so a reused column's arrays need no clearing
+    col->H.resize((size_t)(m + 1) * m);
+    col->Hraw.resize((size_t)(m + 1) * m);
     col->cprev.assign(m + 1, 0.0);
     col->cs.assign(m, 0.0);
     col->sn.assign(m, 0.0);
@@ -906,13 +918,32 @@ lm_status run_round(lm_server_s* S) {
       d.nsrc = c->dn.as<double>();
       gath.push_back(d);
     }
-  if (!gath.empty()) {
-    LM_TRY(upload_async(S, S->h_desc, S->d_desc, gath.data(), gath.size() * sizeof(ColDev)));
+  // descriptors of the dot products (section 2), uploaded with the gather's
+  S->hdesc.assign(nc, ColDev{});
+  for (int i = 0; i < nc; ++i) {
+    Column* c = cols[i];
+    ColDev& d = S->hdesc[i];
+    d.V = c->V.p;
+    d.ld = c->ldv;
+    d.N = c->N;
+    if (c->phase == PH_ARNOLDI) {
+      d.cnt = c->j + 1;  // dots against V[0..j]; u = V[j]
+      d.w = c->km ? c->w : nullptr;
+      d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;  // norm of u before normalisation
+    } else {
+      d.w = c->w;
+      d.g = (c->phase == PH_RESTART || c->phase == PH_FINAL) ? c->gv.as<double2>() : nullptr;
+    }
+  }
+  const size_t ngath = gath.size();
+  gath.insert(gath.end(), S->hdesc.begin(), S->hdesc.end());
+  LM_TRY(upload_async(S, S->h_desc, S->d_desc, gath.data(), gath.size() * sizeof(ColDev)));
+  if (ngath > 0) {
     if (f32)
-      hipLaunchKernelGGL(k_s_gather<float2>, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s,
+      hipLaunchKernelGGL(k_s_gather<float2>, dim3(div_up(Nmax, 256), ngath), dim3(256), 0, S->s,
                          S->d_desc.as<ColDev>());
     else
-      hipLaunchKernelGGL(k_s_gather<double2>, dim3(div_up(Nmax, 256), gath.size()), dim3(256), 0, S->s,
+      hipLaunchKernelGGL(k_s_gather<double2>, dim3(div_up(Nmax, 256), ngath), dim3(256), 0, S->s,
                          S->d_desc.as<ColDev>());
     LM_TRY_HIP(hipGetLastError());
   }
@@ -957,26 +988,11 @@ lm_status run_round(lm_server_s* S) {
   float km_round = 0.f;
   // ---- 2. dot products of the delayed two-pass Gram-Schmidt, residuals, norms
   LM_TRY(ensure(S, S->d_npart, (size_t)nc * nwu * sizeof(double)));
-  LM_TRY(ensure(S, S->d_nrm, (size_t)nc * sizeof(double)));
-  LM_TRY(ensure(S, S->d_h, (size_t)nc * hs * sizeof(double2)));
-  S->hdesc.assign(nc, ColDev{});
-  for (int i = 0; i < nc; ++i) {
-    Column* c = cols[i];
-    ColDev& d = S->hdesc[i];
-    d.V = c->V.p;
-    d.ld = c->ldv;
-    d.N = c->N;
-    if (c->phase == PH_ARNOLDI) {
-      d.cnt = c->j + 1;  // dots against V[0..j]; u = V[j]
-      d.w = c->km ? c->w : nullptr;
-      d.nsrc = c->j >= 1 ? c->dn.as<double>() : nullptr;  // norm of u before normalisation
-    } else {
-      d.w = c->w;
-      d.g = (c->phase == PH_RESTART || c->phase == PH_FINAL) ? c->gv.as<double2>() : nullptr;
-    }
-  }
-  LM_TRY(upload_async(S, S->h_desc_h, S->d_desc_h, S->hdesc.data(), S->hdesc.size() * sizeof(ColDev)));
-  const ColDev* dd = S->d_desc_h.as<ColDev>();
+  const size_t hbytes = (size_t)nc * hs * sizeof(double2), hnbytes = hbytes + (size_t)nc * sizeof(double);
+  LM_TRY(ensure(S, S->d_hn, hnbytes));
+  double2* d_h = S->d_hn.as<double2>();
+  double* d_nrm = reinterpret_cast<double*>(S->d_hn.as<char>() + hbytes);
+  const ColDev* dd = S->d_desc.as<ColDev>() + ngath;
   if (cntmax > 0) {
     LM_TRY(ensure(S, S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
     double2* pa = S->d_dpart.as<double2>();
@@ -988,30 +1004,38 @@ lm_status run_round(lm_server_s* S) {
       hipLaunchKernelGGL(k_s_dots2<double2>, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb,
                          ldh, nbd);
     hipLaunchKernelGGL(k_s_dots2_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, pa, pb, ldh, nbd,
-                       S->d_h.as<double2>(), hs);
+                       d_h, hs);
   }
   // norms: of g - K M z (restart, final) or g (first round); Arnoldi columns
   // report the norm the previous update pass left
   hipLaunchKernelGGL(k_s_resid, dim3(div_up(Nmax, 256), nc), dim3(256), 0, S->s, dd, S->d_npart.as<double>(), nwu);
   hipLaunchKernelGGL(k_s_norm_final, dim3(nc), dim3(64), 0, S->s, dd, S->d_npart.as<double>(), nwu,
-                     S->d_nrm.as<double>());
+                     d_nrm);
   LM_TRY_HIP(hipGetLastError());
-  LM_TRY(host_ensure(S, S->h_h, (size_t)nc * hs * sizeof(double2)));
-  LM_TRY(host_ensure(S, S->h_nrm, (size_t)nc * sizeof(double)));
+  LM_TRY(host_ensure(S, S->h_hn, hnbytes));
   if (cntmax > 0)
-    LM_TRY_HIP(hipMemcpyAsync(S->h_h.p, S->d_h.p, (size_t)nc * hs * sizeof(double2), hipMemcpyDeviceToHost, S->s));
-  LM_TRY_HIP(hipMemcpyAsync(S->h_nrm.p, S->d_nrm.p, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, S->s));
+    LM_TRY_HIP(hipMemcpyAsync(S->h_hn.p, S->d_hn.p, hnbytes, hipMemcpyDeviceToHost, S->s));
+  else
+    LM_TRY_HIP(hipMemcpyAsync(S->h_hn.as<char>() + hbytes, d_nrm, hnbytes - hbytes, hipMemcpyDeviceToHost, S->s));
   LM_TRY_HIP(hipEventRecord(S->t2, S->s));
-  // the round's one wait: the host step needs the dot products and norms
+  // the round's one wait: the host step needs the dot products and norms.
+  // Polled rather than blocked on, so the host step starts within
+  // microseconds of the copy (the worker thread is busy-waiting meanwhile)
   const double tw0 = now_s();
-  LM_TRY_HIP(hipStreamSynchronize(S->s));
+  LM_TRY_HIP(hipEventRecord(S->ev_wait, S->s));
+  for (;;) {
+    const hipError_t q = hipEventQuery(S->ev_wait);
+    if (q == hipSuccess) break;
+    LM_CHECK(q == hipErrorNotReady, LM_EHIP, "HIP error: %s", hipGetErrorString(q));
+    std::this_thread::yield();
+  }
   const double tw1 = now_s();
   float gs_a = 0.f;
   LM_TRY_HIP(hipEventElapsedTime(&km_round, S->t0, S->t1));
   LM_TRY_HIP(hipEventElapsedTime(&gs_a, S->t1, S->t2));
   LM_TRY(collect_update_time(S));  // the previous round's update pass
-  const double2* hhv = S->h_h.as<double2>();
-  const double* hnv = S->h_nrm.as<double>();
+  const double2* hhv = S->h_hn.as<double2>();
+  const double* hnv = reinterpret_cast<const double*>(S->h_hn.as<char>() + hbytes);
   // ---- 3. host updates ------------------------------------------------------------
   // Per column, independent of the others (its Hessenberg correction is
   // O(j^2)): spread over the host pool, each column's descriptors and
@@ -1196,24 +1220,34 @@ lm_status run_round(lm_server_s* S) {
     to_finish.insert(to_finish.end(), o.to_finish.begin(), o.to_finish.end());
     gsb += o.gsb;
   }
-  // coefficient uploads (update passes, then solution combinations)
+  // one upload: the descriptors (update passes, copies, solution
+  // combinations), then their coefficients (update passes, combinations)
   const size_t ncf = cf.size();
-  std::vector<double2> coefs(cf);
-  coefs.insert(coefs.end(), ys.begin(), ys.end());
-  if (!coefs.empty()) LM_TRY(upload_async(S, S->h_y, S->d_y, coefs.data(), coefs.size() * sizeof(double2)));
+  const size_t nall = upd.size() + scal.size() + comb.size();
+  const size_t dbytes = (nall * sizeof(ColDev) + 255) / 256 * 256;
+  const size_t ubytes = dbytes + (ncf + ys.size()) * sizeof(double2);
+  if (nall > 0) {
+    LM_TRY(ensure(S, S->d_desc_u, ubytes));
+    LM_TRY(host_ensure(S, S->h_desc_u, ubytes));
+  }
+  double2* dy = reinterpret_cast<double2*>(S->d_desc_u.as<char>() + dbytes);
   for (auto& d : upd) {
-    d.y = S->d_y.as<double2>() + (size_t)d.src;
+    d.y = dy + (size_t)d.src;
     d.src = nullptr;
   }
   for (auto& d : comb) {
-    d.y = S->d_y.as<double2>() + ncf + (size_t)d.scale;
+    d.y = dy + ncf + (size_t)d.scale;
     d.scale = 0.0;
   }
   std::vector<ColDev> all(upd);
   all.insert(all.end(), scal.begin(), scal.end());
   all.insert(all.end(), comb.begin(), comb.end());
   if (!all.empty()) {
-    LM_TRY(upload_async(S, S->h_desc_u, S->d_desc_u, all.data(), all.size() * sizeof(ColDev)));
+    char* hb = S->h_desc_u.as<char>();
+    std::memcpy(hb, all.data(), all.size() * sizeof(ColDev));
+    std::memcpy(hb + dbytes, cf.data(), ncf * sizeof(double2));
+    std::memcpy(hb + dbytes + ncf * sizeof(double2), ys.data(), ys.size() * sizeof(double2));
+    LM_TRY_HIP(hipMemcpyAsync(S->d_desc_u.p, hb, ubytes, hipMemcpyHostToDevice, S->s));
     int nm = 0;
     for (auto& d : all) nm = std::max(nm, d.N);
     const ColDev* da = S->d_desc_u.as<ColDev>();
@@ -1362,7 +1396,8 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
             hipEventCreateWithFlags(&S->ev_main, hipEventDisableTiming) == hipSuccess &&
             hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
             hipEventCreate(&S->t2) == hipSuccess && hipEventCreate(&S->tu1) == hipSuccess &&
-            hipEventCreate(&S->tu2) == hipSuccess;
+            hipEventCreate(&S->tu2) == hipSuccess &&
+            hipEventCreateWithFlags(&S->ev_wait, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
     for (int e = 0; ok && e < 16; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
@@ -1510,7 +1545,7 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
     if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
   }
   if (S->ev_main) (void)hipEventDestroy(S->ev_main);
-  for (hipEvent_t e : {S->t0, S->t1, S->t2, S->tu1, S->tu2})
+  for (hipEvent_t e : {S->t0, S->t1, S->t2, S->tu1, S->tu2, S->ev_wait})
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < SRV_STREAMS; ++i)
     for (int e = 0; e < 16; ++e)
