@@ -27,6 +27,9 @@ acoustic wave scattering in two-dimensional layered media"):
                     (eq. integralrep) and top/bottom far-field patterns.
 * ``precond``    -- the overlapping domain-decomposition preconditioner
                     (Sec. 4.2), built densely.
+* ``kress``      -- beyond the paper's lowest-order rule: a spectrally
+                    accurate Nystrom rule (logarithmic product quadrature)
+                    for smooth closed scatterers inside one layer.
 
 Readings of garbled or silent passages are marked "reading" in the
 docstrings of the modules that depend on them.
