@@ -112,6 +112,25 @@ typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;
  * Neumann); collocated at the chord midpoints with the rectangle rule.  They
  * need the dense method (LM_EINVAL with LM_FMM). */
 typedef enum { LM_BC_DIRICHLET = 0, LM_BC_NEUMANN = 1, LM_BC_ROBIN = 2 } lm_bc;
+/* Quadrature of the single-layer operator.
+ * LM_QUAD_LOWEST: the paper's rule (Sec. 3.3, eqs. ApproximateComputation,
+ *   matrixelmemts): chord elements between consecutive nodes, midpoint
+ *   collocation, first order in the element size.
+ * LM_QUAD_SPECTRAL: beyond the paper, for scatterers that are smooth closed
+ *   curves sampled at equal parameter steps (an even number of nodes >= 6
+ *   per scatterer, counter-clockwise or clockwise) and lie inside one layer
+ *   without touching an interface.  The unknowns are the densities at the
+ *   nodes themselves (element i = node i: lm_geometry_elements returns the
+ *   nodes, their quadrature weights (2 pi / M) |x'(t_i)| with x' from the
+ *   trigonometric interpolant of the scatterer's M nodes, and their layers);
+ *   the free-space kernel on a node's own scatterer is split into
+ *   -J_0(k r)/(4 pi) ln(4 sin^2((t - s)/2)) plus a smooth part and the
+ *   logarithm integrated exactly against the trigonometric interpolant
+ *   (Martensen-Kussmaul product quadrature), every other part by the
+ *   trapezoidal rule: spectral order for analytic curves.  Dense method and
+ *   Dirichlet condition only; LM_EINVAL otherwise, for an odd node count or
+ *   for a scatterer whose nodes lie in more than one layer. */
+typedef enum { LM_QUAD_LOWEST = 0, LM_QUAD_SPECTRAL = 1 } lm_quad;
 typedef struct {
   int method;
   int p;
@@ -120,6 +139,7 @@ typedef struct {
   int top_fft;
   int bc;            /* lm_bc */
   double robin_beta; /* impedance beta of LM_BC_ROBIN */
+  int quad;          /* lm_quad */
 } lm_geom_opts;
 lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* node_offsets_host,
                              const double* nodes_xy_host, const lm_geom_opts* opts, void* hip_stream,

@@ -72,10 +72,74 @@ lm_geom_s::~lm_geom_s() {
 }
 
 int64_t lm_geom_s::device_bytes() const {
-  int64_t b = d_cx.bytes + d_cy.bytes + d_w.bytes + d_layer.bytes + d_nx.bytes + d_ny.bytes + d_K.bytes + d_K32.bytes;
+  int64_t b = d_cx.bytes + d_cy.bytes + d_w.bytes + d_layer.bytes + d_nx.bytes + d_ny.bytes + d_K.bytes + d_K32.bytes +
+              d_sid.bytes + d_loc.bytes + d_cnt.bytes + d_speed.bytes + d_logw.bytes + d_roff.bytes;
   if (fmm) b += fmm_bytes(fmm);
   if (pre) b += precond_bytes(pre);
   return b;
+}
+
+// Nodes of the spectral rule: the input nodes, x'(t_j) from the trigonometric
+// interpolant of each scatterer's M samples (the differentiation matrix of an
+// even M, D_ij = (-1)^(i-j) cot((i - j) pi / M) / 2 and 0 on the diagonal,
+// i.e. the unpaired mode dropped), weights (2 pi / M) |x'|, normals x'
+// turned out of the curve, and the logarithmic weights
+// R_k = -(2 pi / n) sum_{m=1}^{n-1} cos(2 pi k m / M) / m - (pi / n^2) (-1)^k,
+// n = M / 2, of the product quadrature.
+static lm_status spectral_nodes(lm_geom_s* g, int ns, const int64_t* off, const double* nodes, hipStream_t s) {
+  const int64_t N = g->N;
+  std::vector<int32_t> sid(N), loc(N), cnt(N);
+  std::vector<double> speed(N), logw;
+  std::vector<int64_t> roff(ns);
+  for (int j = 0; j < ns; ++j) {
+    const int64_t a = off[j];
+    const int M = (int)(off[j + 1] - a), n = M / 2;
+    std::vector<double> cotv(M, 0.0), dx(M, 0.0), dy(M, 0.0);
+    for (int d = 1; d < M; ++d) cotv[d] = 0.5 * ((d & 1) ? -1.0 : 1.0) / std::tan(M_PI * d / M);
+    for (int i = 0; i < M; ++i)
+      for (int q = 0; q < M; ++q)
+        if (q != i) {
+          const double c = cotv[(i - q + M) % M];
+          dx[i] += c * nodes[2 * (a + q)];
+          dy[i] += c * nodes[2 * (a + q) + 1];
+        }
+    double area2 = 0.0;
+    for (int i = 0; i < M; ++i) {
+      const int64_t p0 = a + i, p1 = a + (i + 1) % M;
+      area2 += nodes[2 * p0] * nodes[2 * p1 + 1] - nodes[2 * p1] * nodes[2 * p0 + 1];
+    }
+    const double o = area2 > 0 ? 1.0 : -1.0;
+    const int l0 = layer_of(g->m, nodes[2 * a + 1]);
+    for (int i = 0; i < M; ++i) {
+      const int64_t p = a + i;
+      const double sp = std::hypot(dx[i], dy[i]);
+      LM_CHECK(sp > 0, LM_EINVAL, "scatterer %d: zero speed at node %d", j, i);
+      g->cx[p] = nodes[2 * p];
+      g->cy[p] = nodes[2 * p + 1];
+      g->w[p] = 2.0 * M_PI / M * sp;
+      g->nx[p] = o * dy[i] / sp;
+      g->ny[p] = -o * dx[i] / sp;
+      g->layer[p] = layer_of(g->m, g->cy[p]);
+      LM_CHECK(g->layer[p] == l0, LM_EINVAL, "scatterer %d crosses an interface", j);
+      sid[p] = j;
+      loc[p] = i;
+      cnt[p] = M;
+      speed[p] = sp;
+    }
+    roff[j] = (int64_t)logw.size();
+    for (int k = 0; k < M; ++k) {
+      double r = -(M_PI / ((double)n * n)) * ((k & 1) ? -1.0 : 1.0);
+      for (int m = 1; m < n; ++m) r -= 2.0 * M_PI / n * std::cos(2.0 * M_PI * (double)k * m / M) / m;
+      logw.push_back(r);
+    }
+  }
+  LM_TRY(upload(g->d_sid, sid.data(), N * sizeof(int32_t), s));
+  LM_TRY(upload(g->d_loc, loc.data(), N * sizeof(int32_t), s));
+  LM_TRY(upload(g->d_cnt, cnt.data(), N * sizeof(int32_t), s));
+  LM_TRY(upload(g->d_speed, speed.data(), N * sizeof(double), s));
+  LM_TRY(upload(g->d_logw, logw.data(), logw.size() * sizeof(double), s));
+  LM_TRY(upload(g->d_roff, roff.data(), roff.size() * sizeof(int64_t), s));
+  return LM_OK;
 }
 
 extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, const int64_t* off,
@@ -99,8 +163,18 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   g->layers = layers;
   g->m = layers->m;
   g->N = N;
-  lm_geom_opts o = {LM_AUTO, 20, 48, -1, 0, LM_BC_DIRICHLET, 0.0};
+  lm_geom_opts o = {LM_AUTO, 20, 48, -1, 0, LM_BC_DIRICHLET, 0.0, LM_QUAD_LOWEST};
   if (opts) o = *opts;
+  LM_CHECK(o.quad == LM_QUAD_LOWEST || o.quad == LM_QUAD_SPECTRAL, LM_EINVAL, "bad quadrature");
+  g->quad = o.quad;
+  if (o.quad == LM_QUAD_SPECTRAL) {
+    LM_CHECK(o.method != LM_FMM, LM_EINVAL, "the spectral rule needs the dense method");
+    LM_CHECK(o.bc == LM_BC_DIRICHLET, LM_EINVAL, "the spectral rule is for Dirichlet scatterers");
+    o.method = LM_DENSE;
+    for (int j = 0; j < n_scatterers; ++j)
+      LM_CHECK((off[j + 1] - off[j]) % 2 == 0 && off[j + 1] - off[j] >= 6, LM_EINVAL,
+               "scatterer %d: the spectral rule needs an even number (>= 6) of nodes", j);
+  }
   LM_CHECK(o.bc >= LM_BC_DIRICHLET && o.bc <= LM_BC_ROBIN, LM_EINVAL, "bad boundary condition");
   LM_CHECK(std::isfinite(o.robin_beta), LM_EINVAL, "non-finite robin_beta");
   g->bc = o.bc;
@@ -120,7 +194,8 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   g->nx.resize(N);
   g->ny.resize(N);
   g->layer.resize(N);
-  for (int j = 0; j < n_scatterers; ++j) {
+  if (g->quad == LM_QUAD_SPECTRAL) LM_TRY(spectral_nodes(g.get(), n_scatterers, off, nodes, s));
+  for (int j = 0; j < n_scatterers && g->quad == LM_QUAD_LOWEST; ++j) {
     const int64_t a = off[j], n = off[j + 1] - off[j];
     double area2 = 0.0;  // twice the signed area: > 0 for counter-clockwise nodes
     for (int64_t i = 0; i < n; ++i) {

@@ -1,5 +1,6 @@
 // Dense plain path: assemble K by direct Sommerfeld quadrature, then y = K x.
-// (Dirichlet scatterers below; sound-hard and impedance ones further down.)
+// (Dirichlet scatterers below; sound-hard and impedance ones further down;
+// then the spectral rule for smooth scatterers.)
 //
 // Sec. 3.3, eq. matrixelmemts (unscaled rows):
 //   K_ie = |Gamma_e| [ delta_{l_i l_e} (i/4) H_0(k |c_i - c_e|) + G^r(c_i | c_e) ]  (e != i)
@@ -74,6 +75,46 @@ __global__ void __launch_bounds__(256) k_dense_assemble_bc(MediumDev m, int N, c
   K[idx] = make_double2(v.re, v.im);
 }
 
+// Spectral rule (smooth closed scatterers inside one layer, nodes at equal
+// parameter steps): the trapezoidal rule w_e [G^r + delta G^f] for nodes of
+// different scatterers, and on a node's own scatterer (same layer)
+//   w_e G^r(x_i | x_e) + R_{(i-e) mod M} m1 + (2 pi / M) m2,
+//   m1 = -J_0(k r) |x'_e| / (4 pi),
+//   m2 = (i/4) H_0(k r) |x'_e| - m1 ln(4 sin^2(pi (i - e) / M))   (e != i),
+//   m2 = (i/4 - gamma / (2 pi) - ln(k |x'_i| / 2) / (2 pi)) |x'_i|  (e == i).
+__global__ void __launch_bounds__(256) k_dense_assemble_spectral(
+    MediumDev m, int N, const double* __restrict__ cx, const double* __restrict__ cy, const double* __restrict__ w,
+    const int* __restrict__ lay, const int* __restrict__ sid, const int* __restrict__ loc, const int* __restrict__ cnt,
+    const double* __restrict__ speed, const double* __restrict__ logw, const int64_t* __restrict__ roff,
+    double2* __restrict__ K) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx / N), e = (int)(idx % N);
+  const int li = lay[i], le = lay[e];
+  const double dx = cx[i] - cx[e], dy = cy[i] - cy[e];
+  zd v = lmq::reaction_direct(m, li, le, fabs(dx), cy[i], cy[e]) * w[e];
+  const double k = m.k[li];
+  if (sid[i] != sid[e]) {
+    if (li == le) {
+      const double kr = k * sqrt(dx * dx + dy * dy);
+      v += zd(-0.25 * y0(kr), 0.25 * j0(kr)) * w[e];
+    }
+  } else {
+    const int M = cnt[i], d = ((loc[i] - loc[e]) % M + M) % M;
+    const double sp = speed[e], kr = k * sqrt(dx * dx + dy * dy);
+    const double m1 = -j0(kr) * sp / (4.0 * M_PI);
+    zd m2;
+    if (d == 0) {
+      m2 = zd(-kEulerGamma / (2.0 * M_PI) - log(0.5 * k * sp) / (2.0 * M_PI), 0.25) * sp;
+    } else {
+      const double sn = sin(M_PI * d / M);
+      m2 = zd(-0.25 * y0(kr), 0.25 * j0(kr)) * sp - zd(m1 * log(4.0 * sn * sn), 0.0);
+    }
+    v += zd(logw[roff[sid[i]] + d] * m1, 0.0) + m2 * (2.0 * M_PI / M);
+  }
+  K[idx] = make_double2(v.re, v.im);
+}
+
 __global__ void k_to_c64(const double2* __restrict__ a, float2* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -82,7 +123,12 @@ __global__ void k_to_c64(const double2* __restrict__ a, float2* __restrict__ b, 
 lm_status dense_assemble(lm_geom_s* g, hipStream_t s) {
   const int64_t N = g->N, NN = N * N;
   LM_TRY(g->d_K.alloc(NN * sizeof(double2)));
-  if (g->bc == LM_BC_DIRICHLET)
+  if (g->quad == LM_QUAD_SPECTRAL)
+    hipLaunchKernelGGL(k_dense_assemble_spectral, dim3(div_up(NN, 256)), dim3(256), 0, s, g->m, (int)N,
+                       g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
+                       g->d_sid.as<int>(), g->d_loc.as<int>(), g->d_cnt.as<int>(), g->d_speed.as<double>(),
+                       g->d_logw.as<double>(), g->d_roff.as<int64_t>(), g->d_K.as<double2>());
+  else if (g->bc == LM_BC_DIRICHLET)
     hipLaunchKernelGGL(k_dense_assemble, dim3(div_up(NN, 256)), dim3(256), 0, s, g->m, (int)N, g->d_cx.as<double>(),
                        g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(), g->d_K.as<double2>());
   else

@@ -96,11 +96,16 @@ struct lm_geom_s {
   int top_fft = 0;  // level-0 M2L by FFT: 0 when it pays, 1 always, -1 never
   int bc = LM_BC_DIRICHLET;  // boundary condition of the scatterers
   double robin_beta = 0.0;   // impedance of the Robin condition
+  int quad = LM_QUAD_LOWEST;  // quadrature of the single-layer operator
   // host element data, input numbering
   std::vector<double> cx, cy, w, nx, ny;  // nx, ny: unit normal out of the element's polygon
   std::vector<int32_t> layer;
   // device element data, input numbering
   DevBuf d_cx, d_cy, d_w, d_layer, d_nx, d_ny;
+  // spectral rule: per node its scatterer, local index, the scatterer's node
+  // count and |x'(t)|; per scatterer the logarithmic weights R_k, k = 0..M-1,
+  // at roff[scatterer]
+  DevBuf d_sid, d_loc, d_cnt, d_speed, d_logw, d_roff;
   // dense path
   DevBuf d_K;          // complex128 row-major [N][N]
   DevBuf d_K32;        // complex64 copy for the mixed form

@@ -18,6 +18,7 @@ LM_OK, LM_NOT_CONVERGED = 0, 1
 LM_FP64, LM_MIXED = 0, 1
 LM_AUTO, LM_DENSE, LM_FMM = 0, 1, 2
 LM_BC_DIRICHLET, LM_BC_NEUMANN, LM_BC_ROBIN = 0, 1, 2
+LM_QUAD_LOWEST, LM_QUAD_SPECTRAL = 0, 1
 
 _lib = None
 
@@ -30,7 +31,8 @@ class LmError(RuntimeError):
 
 class GeomOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int), ("precond", ctypes.c_int),
-                ("top_fft", ctypes.c_int), ("bc", ctypes.c_int), ("robin_beta", ctypes.c_double)]
+                ("top_fft", ctypes.c_int), ("bc", ctypes.c_int), ("robin_beta", ctypes.c_double),
+                ("quad", ctypes.c_int)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -161,13 +163,15 @@ class Layers:
 
 
 class Geometry:
-    """Elements of closed node polygons (Sec. 3.3) plus the operator data."""
+    """Elements of closed node polygons (Sec. 3.3) plus the operator data;
+    with quad=LM_QUAD_SPECTRAL the elements are the nodes of smooth closed
+    scatterers (see lm_quad in the header)."""
 
     def __init__(self, layers, node_offsets, nodes_xy, method=LM_AUTO, p=20, leaf_size=48, precond=-1, top_fft=0,
-                 bc=LM_BC_DIRICHLET, robin_beta=0.0):
+                 bc=LM_BC_DIRICHLET, robin_beta=0.0, quad=LM_QUAD_LOWEST):
         off = np.ascontiguousarray(node_offsets, dtype=np.int64)
         xy = np.ascontiguousarray(nodes_xy, dtype=np.float64)
-        o = GeomOpts(method, p, leaf_size, precond, top_fft, bc, robin_beta)
+        o = GeomOpts(method, p, leaf_size, precond, top_fft, bc, robin_beta, quad)
         h = ctypes.c_void_p()
         _check(lib().lm_create_geometry(layers.h, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                         _dptr(xy), ctypes.byref(o), _stream(), ctypes.byref(h)))

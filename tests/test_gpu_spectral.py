@@ -1,0 +1,118 @@
+"""The spectrally accurate Nystrom rule (lm_geom_opts.quad = LM_QUAD_SPECTRAL)
+against the oracle (oracle/kress.py) and closed forms, through the C-ABI:
+
+* nodes, quadrature weights and outward normals equal the oracle's (the
+  library differentiates with the trigonometric differentiation matrix, the
+  oracle by FFT: agreement to rounding);
+* the dense matrix, entry by entry through lm_matvec, within 1e-10 of the
+  oracle's on a three-layer eta != 1 medium with a scatterer in each layer
+  (reaction parts by direct Sommerfeld quadrature on both sides);
+* a sound-soft disk: the field at receivers (lm_field) against the Bessel
+  series, spectral convergence down to 1e-12;
+* the three-layer medium with Dirichlet data of a point source inside one
+  scatterer (lm_point_source_rhs): the far field and the field at receivers
+  of the GMRES solution reproduce the source's (lm_point_far_field,
+  lm_point_field) to 1e-9 in FP64 and to 1e-5 in the FP32 form;
+* invalid uses are rejected.
+"""
+
+import numpy as np
+import pytest
+from scipy.special import hankel1, jv
+
+torch = pytest.importorskip("torch")
+
+from oracle.kress import Nodes, matrix
+from oracle.medium import Medium
+from paper_2511_12450_amd import lmfmm
+from paper_2511_12450_amd import workloads as wl
+from tests.parity import check
+
+pytestmark = pytest.mark.gpu
+
+D3, K3, E3 = np.array([0.0, 1.3]), np.array([2.0, 3.5, 2.5]), np.array([1.0, 2.0, 1.5])
+
+
+def _polys(M):
+    # one scatterer in each layer (interfaces at y = 0 and y = -1.3)
+    return [wl.ellipse((0.3, -0.65), 0.35, 0.2, 0.4, M), wl.circle((1.5, 1.0), 0.3, M),
+            wl.star((-1.2, -2.1), 0.3, M, 0.3)]
+
+
+def _geo(polys, d=D3, k=K3, eta=E3, **kw):
+    w = wl.Workload("spectral", d, k, eta, polys, np.array([40.0]))
+    return w, lmfmm.Geometry.from_workload(w, method=lmfmm.LM_DENSE, quad=lmfmm.LM_QUAD_SPECTRAL, **kw)
+
+
+def test_nodes_weights_normals_match_oracle():
+    polys = _polys(40)
+    w, geo = _geo(polys)
+    nd = Nodes(Medium(D3, K3, E3), polys)
+    cx, cy, ww, lay = geo.elements()
+    nx, ny = geo.normals()
+    print("case: spectral nodes, N =", geo.n, flush=True)
+    assert np.array_equal(cx, nd.cx) and np.array_equal(cy, nd.cy) and np.array_equal(lay, nd.layer)
+    assert np.abs(ww - nd.w).max() < 1e-13 * nd.w.max()
+    assert np.abs(nx - nd.nx).max() < 1e-12 and np.abs(ny - nd.ny).max() < 1e-12
+
+
+def test_matrix_matches_oracle():
+    polys = _polys(32)
+    w, geo = _geo(polys)
+    med = Medium(D3, K3, E3)
+    A = matrix(med, Nodes(med, polys))
+    x = wl.random_vector(geo.n, seed=21, n_rhs=3)
+    print("case: spectral matrix, N =", geo.n, flush=True)
+    y = geo.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    check(y, (A @ x.T).T, 1e-10, "spectral-rule matrix vs oracle")
+
+
+def test_disk_field_spectral_convergence():
+    k, a, cy, th = 2.0, 1.0, 2.0, np.radians(30.0)
+    phi = np.linspace(0, 2 * np.pi, 12, endpoint=False)
+    pts = np.stack([2.5 * np.cos(phi), cy + 2.5 * np.sin(phi)], axis=1)
+    n = np.arange(-50, 51)
+    c = -(1j ** n) * jv(n, k * a) / hankel1(n, k * a)
+    exact = np.sum(c[:, None] * hankel1(n[:, None], k * 2.5) * np.exp(1j * n[:, None] * (phi[None, :] + th)), axis=0)
+    exact *= np.exp(-1j * k * np.sin(th) * cy)
+    errs = []
+    for M in (16, 24, 32, 48):
+        w, geo = _geo([wl.circle((0.0, cy), a, M)], d=np.array([0.0]), k=np.array([k, k]), eta=np.ones(2))
+        ph, rep, st = geo.solve(np.array([th]), tol=1e-14, max_iter=200, restart=200, precond=0)
+        assert st in (lmfmm.LM_OK, lmfmm.LM_NOT_CONVERGED)
+        u = geo.field(ph, pts).cpu().numpy()[0]
+        errs.append(np.abs(u - exact).max() / np.abs(exact).max())
+    print("disk, library spectral rule:", ["%.2e" % e for e in errs], flush=True)
+    assert errs[2] < 1e-9 and errs[3] < 1e-12
+    assert errs[1] < errs[0] / 30 and errs[2] < errs[1] / 30
+
+
+@pytest.mark.parametrize("src", [(0.3, -0.65), (-1.2, -2.1)])
+def test_layered_point_source_reproduced(src):
+    w, geo = _geo(_polys(64))
+    lay = lmfmm.Layers(D3, K3, E3)
+    s = np.array([src], dtype=float)
+    g = geo.point_source_rhs(s)
+    obs = lmfmm.far_field_angles()[::17]
+    ffr = lmfmm.point_far_field(lay, s, obs).cpu().numpy()
+    rec = np.array([[2.5, 0.4], [-2.0, 1.9], [0.0, -2.3], [1.2, -0.6], [-0.8, 0.9]])
+    ur = lmfmm.point_field(lay, s, rec).cpu().numpy()
+    print("case: spectral rule, point source", src, "N =", geo.n, flush=True)
+    for prec, tol, bar in ((lmfmm.LM_FP64, 1e-13, 1e-9), (lmfmm.LM_MIXED, 1e-7, 1e-5)):
+        ph, rep, st = geo.solve_rhs(g, tol=tol, max_iter=300, restart=300, precond=0, precision=prec)
+        print(f"precision {prec}: iterations {[r[0] for r in rep]}", flush=True)
+        check(geo.far_field(ph, obs).cpu().numpy(), ffr, bar, f"far field, precision {prec}")
+        check(geo.field(ph, rec).cpu().numpy(), ur, bar, f"field at receivers, precision {prec}")
+
+
+def test_invalid_uses_rejected():
+    for kw, polys in (({}, [wl.circle((0.0, -0.6), 0.3, 15)]),           # odd node count
+                      ({}, [wl.circle((0.0, -1.2), 0.3, 16)]),           # crosses y = -1.3
+                      ({"bc": lmfmm.LM_BC_NEUMANN}, _polys(16))):      # Dirichlet only
+        with pytest.raises(lmfmm.LmError) as e:
+            _geo(polys, **kw)
+        assert e.value.status == -1
+    w = wl.Workload("spectral", D3, K3, E3, _polys(16), np.array([40.0]))
+    with pytest.raises(lmfmm.LmError) as e:
+        lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, quad=lmfmm.LM_QUAD_SPECTRAL)
+    assert e.value.status == -1
