@@ -127,7 +127,11 @@ typedef enum { LM_BC_DIRICHLET = 0, LM_BC_NEUMANN = 1, LM_BC_ROBIN = 2 } lm_bc;
  *   -J_0(k r)/(4 pi) ln(4 sin^2((t - s)/2)) plus a smooth part and the
  *   logarithm integrated exactly against the trigonometric interpolant
  *   (Martensen-Kussmaul product quadrature), every other part by the
- *   trapezoidal rule: spectral order for analytic curves.  Dense method and
+ *   trapezoidal rule: spectral order for analytic curves.  On the FMM the
+ *   expansions and the near field keep the trapezoidal sums and a CSR of
+ *   same-scatterer corrections (the difference of the two rules, whose Hankel
+ *   parts cancel) plus the spectral self terms complete the operator (the
+ *   preconditioner blocks stay those of the lowest-order rule on the nodes).
  *   Dirichlet condition only; LM_EINVAL otherwise, for an odd node count or
  *   for a scatterer whose nodes lie in more than one layer. */
 typedef enum { LM_QUAD_LOWEST = 0, LM_QUAD_SPECTRAL = 1 } lm_quad;

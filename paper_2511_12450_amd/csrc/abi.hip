@@ -88,9 +88,18 @@ int64_t lm_geom_s::device_bytes() const {
 // n = M / 2, of the product quadrature.
 static lm_status spectral_nodes(lm_geom_s* g, int ns, const int64_t* off, const double* nodes, hipStream_t s) {
   const int64_t N = g->N;
-  std::vector<int32_t> sid(N), loc(N), cnt(N);
-  std::vector<double> speed(N), logw;
-  std::vector<int64_t> roff(ns);
+  std::vector<int32_t>& sid = g->sid;
+  std::vector<int32_t>& loc = g->loc;
+  std::vector<int32_t>& cnt = g->cnt;
+  std::vector<double>& speed = g->speed;
+  std::vector<double>& logw = g->logw;
+  std::vector<int64_t>& roff = g->roff;
+  sid.assign(N, 0);
+  loc.assign(N, 0);
+  cnt.assign(N, 0);
+  speed.assign(N, 0.0);
+  logw.clear();
+  roff.assign(ns, 0);
   for (int j = 0; j < ns; ++j) {
     const int64_t a = off[j];
     const int M = (int)(off[j + 1] - a), n = M / 2;
@@ -168,9 +177,7 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   LM_CHECK(o.quad == LM_QUAD_LOWEST || o.quad == LM_QUAD_SPECTRAL, LM_EINVAL, "bad quadrature");
   g->quad = o.quad;
   if (o.quad == LM_QUAD_SPECTRAL) {
-    LM_CHECK(o.method != LM_FMM, LM_EINVAL, "the spectral rule needs the dense method");
     LM_CHECK(o.bc == LM_BC_DIRICHLET, LM_EINVAL, "the spectral rule is for Dirichlet scatterers");
-    o.method = LM_DENSE;
     for (int j = 0; j < n_scatterers; ++j)
       LM_CHECK((off[j + 1] - off[j]) % 2 == 0 && off[j + 1] - off[j] >= 6, LM_EINVAL,
                "scatterer %d: the spectral rule needs an even number (>= 6) of nodes", j);

@@ -217,6 +217,27 @@ __global__ void k_near_block_values(MediumDev m, const int* __restrict__ jptr, c
   }
 }
 
+// Spectral rule, pairs (i, e != i) of one scatterer: the spectral entry minus
+// the trapezoidal w_e G^f the rest of the matvec computes for the pair.  The
+// Hankel parts cancel:
+//   -J_0(k r) |x'_e| / (4 pi) (R_d - (2 pi / M) ln(4 sin^2(pi d / M))),
+// d = (i - e) mod M.
+__global__ void k_spectral_corr(MediumDev m, int64_t n, const int* __restrict__ tgt, const int* __restrict__ src,
+                                const double* __restrict__ cx, const double* __restrict__ cy,
+                                const int* __restrict__ lay, const int* __restrict__ sid, const int* __restrict__ loc,
+                                const int* __restrict__ cnt, const double* __restrict__ speed,
+                                const double* __restrict__ logw, const int64_t* __restrict__ roff,
+                                double2* __restrict__ val) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = tgt[t], e = src[t];
+  const int M = cnt[i], d = ((loc[i] - loc[e]) % M + M) % M;
+  const double kr = m.k[lay[i]] * hypot(cx[i] - cx[e], cy[i] - cy[e]);
+  const double sn = sin(M_PI * d / M);
+  const double v = -j0(kr) * speed[e] / (4.0 * M_PI) * (logw[roff[sid[i]] + d] - 2.0 * M_PI / M * log(4.0 * sn * sn));
+  val[t] = make_double2(v, 0.0);
+}
+
 __global__ void k_c128_to_c64_fmm(int64_t n, const double2* __restrict__ a, float2* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -1941,7 +1962,16 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     std::vector<double2> self(N);
     for (int64_t e = 0; e < N; ++e) {
       const double k = m.k[g->layer[e]], w = g->w[e];
-      self[e] = make_double2(-(kEulerGamma + std::log(k * w / 4.0) - 1.0) / (2.0 * M_PI) * w, 0.25 * w);
+      if (g->quad == LM_QUAD_SPECTRAL) {
+        // free-space diagonal of the spectral rule: R_0 m1 + (2 pi / M) m2 at
+        // t = s, m1 = -|x'| / (4 pi), m2 = (i/4 - gamma/(2 pi) - ln(k |x'| / 2)/(2 pi)) |x'|
+        const double sp = g->speed[e], M = g->cnt[e], R0 = g->logw[g->roff[g->sid[e]]];
+        self[e] = make_double2(-R0 * sp / (4.0 * M_PI) +
+                                   2.0 * M_PI / M * (-kEulerGamma - std::log(0.5 * k * sp)) / (2.0 * M_PI) * sp,
+                               2.0 * M_PI / M * 0.25 * sp);
+      } else {
+        self[e] = make_double2(-(kEulerGamma + std::log(k * w / 4.0) - 1.0) / (2.0 * M_PI) * w, 0.25 * w);
+      }
     }
     LM_TRY(up(F->d_self, self, s));
   }
@@ -2087,6 +2117,38 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
                          g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), v64.as<double2>());
       hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nr, 256)), dim3(256), 0, s, nr, v64.as<double2>(),
                          F->d_rn_val32.as<float2>());
+    }
+    LM_TRY_HIP(hipGetLastError());
+    LM_TRY_HIP(hipStreamSynchronize(s));
+  }
+  if (g->quad == LM_QUAD_SPECTRAL) {  // same-scatterer corrections of the spectral rule
+    F->sc_ptr.assign(N + 1, 0);
+    F->sc_src.clear();
+    std::vector<int> st;
+    for (int64_t i = 0; i < N; ++i) {
+      const int64_t a = i - g->loc[i], M = g->cnt[i];
+      for (int64_t e = a; e < a + M; ++e)
+        if (e != i) {
+          F->sc_src.push_back((int)e);
+          st.push_back((int)i);
+        }
+      LM_CHECK(F->sc_src.size() < ((size_t)1 << 31), LM_ENOMEM, "too many same-scatterer pairs");
+      F->sc_ptr[i + 1] = (int)F->sc_src.size();
+    }
+    const int64_t nc = (int64_t)F->sc_src.size();
+    DevBuf dt;
+    LM_TRY(up(F->d_sc_ptr, F->sc_ptr, s));
+    LM_TRY(up(F->d_sc_src, F->sc_src, s));
+    LM_TRY(up(dt, st, s));
+    LM_TRY(F->d_sc_val.alloc(std::max<int64_t>(nc, 1) * sizeof(double2)));
+    LM_TRY(F->d_sc_val32.alloc(std::max<int64_t>(nc, 1) * sizeof(float2)));
+    if (nc) {
+      hipLaunchKernelGGL(k_spectral_corr, dim3(div_up(nc, 256)), dim3(256), 0, s, m, nc, dt.as<int>(),
+                         F->d_sc_src.as<int>(), g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_layer.as<int>(),
+                         g->d_sid.as<int>(), g->d_loc.as<int>(), g->d_cnt.as<int>(), g->d_speed.as<double>(),
+                         g->d_logw.as<double>(), g->d_roff.as<int64_t>(), F->d_sc_val.as<double2>());
+      hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nc, 256)), dim3(256), 0, s, nc, F->d_sc_val.as<double2>(),
+                         F->d_sc_val32.as<float2>());
     }
     LM_TRY_HIP(hipGetLastError());
     LM_TRY_HIP(hipStreamSynchronize(s));
@@ -2282,6 +2344,15 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     } else {
       hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, sn, N, N, (const int*)nullptr, R, 0,
                          F->d_nm_ptr.as<int>(), F->d_nm_src.as<int>(), nmv, x, y);
+    }
+    if (!F->sc_src.empty()) {  // spectral rule: same-scatterer corrections, accumulated
+      const V* scv = sizeof(RT) == 8 ? (const V*)F->d_sc_val.p : (const V*)F->d_sc_val32.p;
+      if (R >= 8)
+        hipLaunchKernelGGL((k_near_csr<RT, 8>), dim3(div_up(N, 4)), dim3(256), 0, sn, N, N, (const int*)nullptr, R, 1,
+                           F->d_sc_ptr.as<int>(), F->d_sc_src.as<int>(), scv, x, y);
+      else
+        hipLaunchKernelGGL((k_near_csr<RT, 4>), dim3(div_up(N, 4)), dim3(256), 0, sn, N, N, (const int*)nullptr, R, 1,
+                           F->d_sc_ptr.as<int>(), F->d_sc_src.as<int>(), scv, x, y);
     }
     if (ev) LM_TRY_HIP(hipEventRecord(ev[11], sn));
     LM_TRY_HIP(hipEventRecord(F->ev_join, sn));

@@ -53,6 +53,8 @@ struct FmmPlan {
   // mf_slot: each item's partial slot (slots in target order, mf_ptr: slots per target)
   std::vector<int> mf_item, mf_slot, mf_ptr;
   std::vector<int> tr_item, tr_src, tr_op;  // matrix-core M2M (per parent) and L2L (per box) items
+  // spectral rule: corrections of the same-scatterer pairs (CSR by node)
+  std::vector<int> sc_ptr, sc_src;
   // free-space near field + self terms as leaf blocks: rows = the leaf's
   // elements, columns = the leaf's and its neighbours' elements
   std::vector<int> nb_jptr, nb_jidx, nb_rows, nb_item;
@@ -91,6 +93,7 @@ struct FmmPlan {
   DevBuf d_top_grid, d_top_item, d_top_ptr, d_top_src, d_top_op, d_top_id, d_top_tw64, d_top_tw32;
   DevBuf d_top_T64, d_top_T32, d_top_mh, d_top_lh;
   DevBuf d_om_slot;  // per-entry M2L results of the few-right-hand-side (operator-major) launch
+  DevBuf d_sc_ptr, d_sc_src, d_sc_val, d_sc_val32;
   DevBuf d_p2m_dst, d_p2m_msel;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   // side stream of the near field (default priority) and its fork / join events
@@ -114,7 +117,8 @@ struct FmmPlan {
                            &d_box_id, &d_mf_item, &d_mf_slot, &d_mf_ptr, &d_mf_part, &d_tm_item, &d_tm_ptr, &d_tm_slot, &d_tm_src,
                            &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
                            &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh,
-                           &d_om_slot, &d_p2m_dst, &d_p2m_msel};
+                           &d_om_slot, &d_p2m_dst, &d_p2m_msel, &d_sc_ptr, &d_sc_src, &d_sc_val,
+                           &d_sc_val32};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;

@@ -104,7 +104,10 @@ struct lm_geom_s {
   DevBuf d_cx, d_cy, d_w, d_layer, d_nx, d_ny;
   // spectral rule: per node its scatterer, local index, the scatterer's node
   // count and |x'(t)|; per scatterer the logarithmic weights R_k, k = 0..M-1,
-  // at roff[scatterer]
+  // at roff[scatterer] (host and device copies)
+  std::vector<int32_t> sid, loc, cnt;
+  std::vector<double> speed, logw;
+  std::vector<int64_t> roff;
   DevBuf d_sid, d_loc, d_cnt, d_speed, d_logw, d_roff;
   // dense path
   DevBuf d_K;          // complex128 row-major [N][N]
