@@ -67,7 +67,8 @@ def _args():
                     help="arrival rates of the pool streams as fractions of the pool's served capacity")
     ap.add_argument("--replica", type=str, default="",
                     help="run a paper replica instead of the benchmark: 'example1', 'example2' or 'example3' "
-                         "(Sec. 5, Tables 5.1-5.3)")
+                         "(Sec. 5, Tables 5.1-5.3), or 'spectral' (the spectral rule against the lowest-order "
+                         "one; --replica-n gives the nodes per scatterer, e.g. 16,32,64,128,256)")
     ap.add_argument("--replica-n", type=str, default="960,1920,3840,7680,15360",
                     help="example1: nodes per unit length of the L-shape (N = 12.5 x this)")
     ap.add_argument("--pool-budget-gb", type=float, default=0.0,
@@ -321,6 +322,52 @@ def replica_plane_wave(a, which):
                       "paper_hardware": "not reported (CPU time)"}))
 
 
+def replica_spectral(a):
+    """The spectral Nystrom rule against the paper's lowest-order rule on
+    smooth scatterers: 100 circles, ellipses and stars inside the three
+    layers of the headline workload (none touching an interface), Dirichlet
+    data of a unit point source at the centre of scatterer 0 (manufactured
+    solution); per node count, both rules on the FMM with the
+    preconditioner, FP64 (tol 1e-10) and the FP32 form (tol 1e-6): the far
+    field's error against the source's, iterations and solve time."""
+    import torch
+
+    from paper_2511_12450_amd import lmfmm
+    from paper_2511_12450_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    obs = lmfmm.far_field_angles()
+    rows = []
+    for n in [int(v) for v in a.replica_n.split(",") if v]:
+        w = wl.three_layer_smooth(n_nodes=n)
+        src = w.extra["source"]
+        for quad, name in ((lmfmm.LM_QUAD_LOWEST, "lowest"), (lmfmm.LM_QUAD_SPECTRAL, "spectral")):
+            t0 = time.perf_counter()
+            geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, quad=quad)
+            torch.cuda.synchronize()
+            row = {"nodes_per_scatterer": n, "N": int(geo.n), "rule": name, "setup_s": time.perf_counter() - t0}
+            exact = lmfmm.point_far_field(geo.layers, src, obs).cpu().numpy()[0]
+            g = geo.point_source_rhs(src)
+            for prec, tol, key in ((lmfmm.LM_FP64, 1e-10, "fp64"), (lmfmm.LM_MIXED, 1e-6, "fp32")):
+                geo.solve_rhs(g, tol=tol, max_iter=3000, restart=500, precision=prec)  # warm-up
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                phi, rep, st = geo.solve_rhs(g, tol=tol, max_iter=3000, restart=500, precision=prec)
+                torch.cuda.synchronize()
+                ff = geo.far_field(phi, obs).cpu().numpy()[0]
+                row[key] = {"iterations": int(rep[0][0]), "solve_s": time.perf_counter() - t1, "status": int(st),
+                            "far_field_err_l2": _rel(ff, exact),
+                            "far_field_err_linf": float(np.abs(ff - exact).max() / np.abs(exact).max())}
+            _log(f"spectral replica n={n} {name}: N={geo.n}, err fp64 {row['fp64']['far_field_err_linf']:.2e} "
+                 f"fp32 {row['fp32']['far_field_err_linf']:.2e}, its {row['fp64']['iterations']}, "
+                 f"solve {row['fp64']['solve_s']:.3f} / {row['fp32']['solve_s']:.3f} s")
+            rows.append(row)
+            geo.close()
+            torch.cuda.empty_cache()
+    print(json.dumps({"replica": "spectral", "workload": wl.three_layer_smooth.__doc__.replace("\n", " "),
+                      "rows": rows}))
+
+
 def main():
     a = _args()
     if a.replica:
@@ -328,6 +375,8 @@ def main():
             replica_example1(a)
         elif a.replica in ("example2", "example3"):
             replica_plane_wave(a, a.replica)
+        elif a.replica == "spectral":
+            replica_spectral(a)
         else:
             sys.exit(f"unknown replica {a.replica}")
         return

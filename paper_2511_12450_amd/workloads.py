@@ -174,6 +174,28 @@ def three_layer_mini(seed=3, n_scat=25, n_nodes=160, angles=None):
     return three_layer(seed, n_scat, n_nodes, box, angles)
 
 
+def three_layer_smooth(n_nodes=64, seed=4, n_scat=100, box=((-5.0, 5.0), (-4.0, 2.0))):
+    """The three-layer medium (interfaces y=0, y=-2; k=(5,7,4)) with smooth
+    scatterers only, none touching an interface (every point 0.05 away):
+    circles, ellipses (axis ratio U[0.5,0.9]) and 5-petal stars in equal
+    thirds, R ~ U[0.1,0.25], gap >= 0.05, n_nodes nodes each at equal
+    parameter steps; a unit point source at the centre of scatterer 0 gives
+    a manufactured solution."""
+    rng = np.random.default_rng(seed)
+    d = np.array([0.0, 2.0])
+
+    def radius(rng_, kind):
+        R = rng_.uniform(0.1, 0.25)
+        return R, (1.2 * R if kind == "star" else R)
+
+    placed = _place(rng, n_scat, box, radius, 0.05, d, straddle_frac=0.0, iface_clear=0.05,
+                    kinds=("circle", "ellipse", "star"))
+    polys = _shapes(rng, placed, n_nodes)
+    w = Workload(f"three_layer_smooth_N{n_scat * n_nodes}", d, np.array([5.0, 7.0, 4.0]), np.ones(3), polys,
+                 np.array([30.0]), p=20, tol=1e-8, extra={"source": np.array([placed[0][1]], dtype=float)})
+    return w
+
+
 def multi_rhs(seed=3):
     """The 400-scatterer three-layer geometry with 64 incidence angles in
     [10, 170] deg solved as one block."""
