@@ -109,8 +109,11 @@ typedef enum { LM_AUTO = 0, LM_DENSE = 1, LM_FMM = 2 } lm_method;
  * representation u^s = S phi and the exterior limit of its normal derivative,
  * (-1/2 + K' + i beta S) phi = -(d_n + i beta)(u^inc + u^b) for the condition
  * (d_n + i beta) u = 0 (n out of the scatterer; beta = robin_beta, 0 for
- * Neumann); collocated at the chord midpoints with the rectangle rule.  They
- * need the dense method (LM_EINVAL with LM_FMM). */
+ * Neumann); collocated at the chord midpoints with the rectangle rule.  On the
+ * FMM the expansions are unchanged and the targets evaluate n . grad + i beta
+ * of the local expansions and of the near-field kernel; the second-kind
+ * system needs no preconditioner and none is built (precond >= 1 with
+ * Neumann or Robin on the FMM: LM_EINVAL). */
 typedef enum { LM_BC_DIRICHLET = 0, LM_BC_NEUMANN = 1, LM_BC_ROBIN = 2 } lm_bc;
 /* Quadrature of the single-layer operator.
  * LM_QUAD_LOWEST: the paper's rule (Sec. 3.3, eqs. ApproximateComputation,

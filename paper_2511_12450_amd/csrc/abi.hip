@@ -231,14 +231,14 @@ extern "C" lm_status lm_create_geometry(lm_layers layers, int n_scatterers, cons
   LM_TRY(upload(g->d_nx, g->nx.data(), N * sizeof(double), s));
   LM_TRY(upload(g->d_ny, g->ny.data(), N * sizeof(double), s));
 
-  LM_CHECK(g->bc == LM_BC_DIRICHLET || g->method == LM_DENSE, LM_EINVAL,
-           "Neumann and Robin conditions need the dense method");
+  LM_CHECK(g->bc == LM_BC_DIRICHLET || g->method == LM_DENSE || o.precond <= 0, LM_EINVAL,
+           "no domain-decomposition preconditioner for Neumann and Robin scatterers");
   if (g->method == LM_DENSE) {
     LM_CHECK(N <= 32768, LM_EINVAL, "dense method limited to N <= 32768");
     LM_TRY(dense_assemble(g.get(), s));
   } else {
     LM_TRY(fmm_build(g.get(), s));
-    if (o.precond) LM_TRY(precond_build(g.get(), o.precond < 0 ? -1 : o.precond - 1, s));
+    if (o.precond && g->bc == LM_BC_DIRICHLET) LM_TRY(precond_build(g.get(), o.precond < 0 ? -1 : o.precond - 1, s));
   }
   LM_TRY_HIP(hipStreamSynchronize(s));
   *out = g.release();

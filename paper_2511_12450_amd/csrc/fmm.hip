@@ -166,12 +166,28 @@ __global__ void __launch_bounds__(256) k_reac_tables(MediumDev m, int p, int nle
   }
 }
 
+// Free-space kernel seen by target i: (i/4) H_0(k r) for Dirichlet
+// scatterers, n_i . grad + i beta of it for sound-hard / impedance ones
+// (grad_i (i/4) H_0(k r) = -(i/4) k H_1(k r) (c_i - c_e) / r).
+struct BcTarget {
+  int bc;
+  double beta;
+  const double *nx, *ny;
+};
+__device__ __forceinline__ zd free_kernel(double k, double dx, double dy, int i, const BcTarget& t) {
+  const double r = hypot(dx, dy), kr = k * r;
+  const zd g(-0.25 * y0(kr), 0.25 * j0(kr));
+  if (t.bc == LM_BC_DIRICHLET) return g;
+  const zd d = zd(0.25 * y1(kr), -0.25 * j1(kr)) * (k / r);
+  return d * (dx * t.nx[i] + dy * t.ny[i]) + zd(0.0, t.beta) * g;
+}
+
 // Near-field matrix values: kind 0 free-space pair, all ones self term,
 // otherwise the component mask of a reaction pair.
 __global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tgt, const int* __restrict__ src,
                               const unsigned* __restrict__ kind, const double* __restrict__ cx,
                               const double* __restrict__ cy, const double* __restrict__ w,
-                              const int* __restrict__ lay, const double2* __restrict__ self,
+                              const int* __restrict__ lay, const double2* __restrict__ self, BcTarget bt,
                               double2* __restrict__ val) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -179,13 +195,16 @@ __global__ void k_near_values(MediumDev m, int64_t n, const int* __restrict__ tg
   const unsigned kd = kind[t];
   zd v(0.0, 0.0);
   if (kd == 0u) {
-    const double kr = m.k[lay[i]] * hypot(cx[i] - cx[e], cy[i] - cy[e]);
-    v = zd(-0.25 * y0(kr), 0.25 * j0(kr)) * w[e];
+    v = free_kernel(m.k[lay[i]], cx[i] - cx[e], cy[i] - cy[e], i, bt) * w[e];
   } else if (kd == 0xFFFFFFFFu) {
     const double2 sv = self[i];
     v = zd(sv.x, sv.y);
-  } else {
+  } else if (bt.bc == LM_BC_DIRICHLET) {
     v = lmq::reaction_direct(m, lay[i], lay[e], fabs(cx[i] - cx[e]), cy[i], cy[e], kd) * w[e];
+  } else {
+    zd g, gx, gy;
+    lmq::reaction_direct_grad(m, lay[i], lay[e], cx[i] - cx[e], cy[i], cy[e], g, gx, gy, kd);
+    v = (gx * bt.nx[i] + gy * bt.ny[i] + zd(0.0, bt.beta) * g) * w[e];
   }
   val[t] = make_double2(v.re, v.im);
 }
@@ -197,7 +216,7 @@ __global__ void k_near_block_values(MediumDev m, const int* __restrict__ jptr, c
                                     const int* __restrict__ nb, const int64_t* __restrict__ zoff,
                                     const double* __restrict__ cx, const double* __restrict__ cy,
                                     const double* __restrict__ w, const int* __restrict__ lay,
-                                    const double2* __restrict__ self, float2* __restrict__ Z) {
+                                    const double2* __restrict__ self, BcTarget bt, float2* __restrict__ Z) {
   const int b = blockIdx.x;
   const int* J = jidx + jptr[b];
   const int q = jptr[b + 1] - jptr[b], nB = nb[b];
@@ -210,8 +229,7 @@ __global__ void k_near_block_values(MediumDev m, const int* __restrict__ jptr, c
       const double2 sv = self[i];
       v = zd(sv.x, sv.y);
     } else {
-      const double kr = m.k[lay[i]] * hypot(cx[i] - cx[e], cy[i] - cy[e]);
-      v = zd(-0.25 * y0(kr), 0.25 * j0(kr)) * w[e];
+      v = free_kernel(m.k[lay[i]], cx[i] - cx[e], cy[i] - cy[e], i, bt) * w[e];
     }
     Zb[idx] = make_float2((float)v.re, (float)v.im);
   }
@@ -1050,12 +1068,19 @@ __global__ void __launch_bounds__(256) k_l2p(int p, int R, int nlev, int accumul
 // pos P: P2M [n][j] (P x c) = |Gamma_j| J_n(k rho_j) e^{-i n theta_j} / sig_|n|,
 // L2P [j][m] (c x P) = J_m(k rho_j) e^{i m theta_j} / sig_|m|, n, m = -p..p,
 // J_{-n} = (-1)^n J_n.  One thread per point.
+// Sound-hard / impedance targets (bt.bc != Dirichlet) see n . grad + i beta of
+// the local expansion: with F_m = J_m(k rho) e^{i m theta} in the tree's
+// (x, h) plane, d/dx F_m = k/2 (F_{m-1} - F_{m+1}), d/dh F_m = i k/2
+// (F_{m-1} + F_{m+1}), and h = +-y + const by the tree's side, the L2P row is
+// [k/2 ((a + i b) F_{m-1} - (a - i b) F_{m+1}) + i beta F_m] / sig_|m| with
+// (a, b) = (n_x, +-n_y); also kept in FP64 (zl64) for the FP64 matvec.
 __global__ void __launch_bounds__(64) k_leaf_basis(int p, int nlev, const int* __restrict__ items,
                                                    const BoxDev* __restrict__ boxes,
                                                    const int* __restrict__ tree_layer, const double* __restrict__ sig,
                                                    const int* __restrict__ pt_elem, const double2* __restrict__ pt_xh,
-                                                   const double* __restrict__ w, float2* __restrict__ zp,
-                                                   float2* __restrict__ zl) {
+                                                   const double* __restrict__ w, BcTarget bt,
+                                                   const int* __restrict__ tree_side, float2* __restrict__ zp,
+                                                   float2* __restrict__ zl, double2* __restrict__ zl64) {
   const int b = items[3 * blockIdx.x], pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
   const int j = threadIdx.x;
   if (j >= cnt) return;
@@ -1064,8 +1089,8 @@ __global__ void __launch_bounds__(64) k_leaf_basis(int p, int nlev, const int* _
   const double* sg = sig + (int64_t)(tree_layer[B.tree] * nlev + B.level) * (p + 1);
   const double2 xh = pt_xh[pos + j];
   const double dx = xh.x - B.cx, dh = xh.y - B.ch;
-  double J[MAXP + 1];
-  fm::bessel_j_seq(B.k * hypot(dx, dh), p, J);
+  double J[MAXP + 2];
+  fm::bessel_j_seq(B.k * hypot(dx, dh), p + 1, J);
   const zd e1 = fm::cis(atan2(dh, dx));
   const double we = w[pt_elem[pos + j]];
   float2* P2 = zp + (int64_t)pos * P;
@@ -1078,6 +1103,50 @@ __global__ void __launch_bounds__(64) k_leaf_basis(int p, int nlev, const int* _
     P2[(int64_t)(p + m) * cnt + j] = make_float2((float)(we * a * ep.re), (float)(-we * a * ep.im));
     P2[(int64_t)(p - m) * cnt + j] = make_float2((float)(we * an * ep.re), (float)(we * an * ep.im));
     ep = ep * e1;
+  }
+  if (bt.bc == LM_BC_DIRICHLET) return;
+  // F_n, n = -(p+1)..p+1, at F[n + p + 1]
+  zd F[2 * MAXP + 3];
+  zd en(1.0, 0.0);
+  for (int n = 0; n <= p + 1; ++n) {
+    const double jn = (n & 1) ? -J[n] : J[n];
+    F[p + 1 + n] = en * J[n];
+    F[p + 1 - n] = zd(en.re, -en.im) * jn;
+    en = en * e1;
+  }
+  const int e = pt_elem[pos + j];
+  const double na = bt.nx[e], nb = (tree_side[B.tree] == SIDE_B ? 1.0 : -1.0) * bt.ny[e];
+  const zd apb(na, nb), amb(na, -nb);
+  double2* L64 = zl64 + (int64_t)pos * P + (int64_t)j * P;
+  for (int m = -p; m <= p; ++m) {
+    const zd v = (apb * F[p + m] - amb * F[p + m + 2]) * (0.5 * B.k) + zd(0.0, bt.beta) * F[p + 1 + m];
+    const double sc = 1.0 / sg[m < 0 ? -m : m];
+    L2[p + m] = make_float2((float)(v.re * sc), (float)(v.im * sc));
+    L64[p + m] = make_double2(v.re * sc, v.im * sc);
+  }
+}
+
+// L2P from stored point rows (sound-hard / impedance targets, FP64 or one
+// right-hand side): y[r][e_j] += sum_m Z[j][m] le[leaf][m][r], one thread per
+// (point, right-hand side) of a work item.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_l2p_rows(int p, int R, int N, const int* __restrict__ items,
+                                                  const int* __restrict__ pt_elem,
+                                                  const typename C2T<RT>::T* __restrict__ Z,
+                                                  const typename C2T<RT>::T* __restrict__ le,
+                                                  typename C2T<RT>::T* __restrict__ y) {
+  typedef typename C2T<RT>::T V;
+  const int b = items[3 * blockIdx.x], pos = items[3 * blockIdx.x + 1], cnt = items[3 * blockIdx.x + 2];
+  const int P = 2 * p + 1;
+  const V* L = le + (int64_t)b * P * R;
+  for (int idx = threadIdx.x; idx < cnt * R; idx += blockDim.x) {
+    const int j = idx / R, r = idx - j * R;
+    const V* z = Z + (int64_t)(pos + j) * P;
+    RT re = 0, im = 0;
+    for (int m = 0; m < P; ++m) cmac(re, im, z[m], L[(int64_t)m * R + r]);
+    V* yp = y + (int64_t)r * N + pt_elem[pos + j];
+    const V o = *yp;
+    *yp = mk<V>(o.x + re, o.y + im);
   }
 }
 
@@ -1223,6 +1292,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   const int p = g->p;
   LM_CHECK(p >= 4 && p <= MAXP, LM_EINVAL, "the FMM needs 4 <= p <= %d", MAXP);
   F->p = p;
+  F->bc = g->bc;
+  F->beta = g->robin_beta;
   F->n_el = N;
   F->P = 2 * p + 1;
   F->n_layers = L + 1;
@@ -1956,6 +2027,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_rn_rows, F->rn_rows, s));
   LM_TRY(up(F->d_rn_src, F->rn_src, s));
   F->tree_layer = tree_layer;
+  F->tree_side.clear();
+  for (const TreeB& t : T) F->tree_side.push_back(t.side);
+  LM_TRY(up(F->d_tree_side, F->tree_side, s));
   LM_TRY(up(F->d_tree_layer, F->tree_layer, s));
   LM_TRY(up(F->d_sig, F->sig, s));
   {
@@ -1972,6 +2046,8 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       } else {
         self[e] = make_double2(-(kEulerGamma + std::log(k * w / 4.0) - 1.0) / (2.0 * M_PI) * w, 0.25 * w);
       }
+      if (g->bc != LM_BC_DIRICHLET)  // -1/2 + i beta I^s (the free-space K' self term of a chord is zero)
+        self[e] = make_double2(-0.5 - g->robin_beta * self[e].y, g->robin_beta * self[e].x);
     }
     LM_TRY(up(F->d_self, self, s));
   }
@@ -2069,7 +2145,9 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     LM_TRY(up(F->d_top_op, F->top_op, s));
     LM_TRY_HIP(hipStreamSynchronize(s));  // host staging vectors end with this scope
   }
-  // near-field matrix values
+  // near-field matrix values (what the targets see: the operator itself, or
+  // n . grad + i beta of it for sound-hard / impedance scatterers)
+  const BcTarget bct{g->bc, g->robin_beta, g->d_nx.as<double>(), g->d_ny.as<double>()};
   const int nrn = (int)F->rn_src.size();
   {
     const int64_t nnz = F->nm_ptr[N];
@@ -2081,7 +2159,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     LM_TRY(F->d_nm_val.alloc(std::max<int64_t>(nnz, 1) * sizeof(double2)));
     hipLaunchKernelGGL(k_near_values, dim3(div_up(nnz, 128)), dim3(128), 0, s, m, nnz, dt.as<int>(),
                        F->d_nm_src.as<int>(), dk.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
-                       g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), F->d_nm_val.as<double2>());
+                       g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), bct, F->d_nm_val.as<double2>());
     LM_TRY_HIP(hipGetLastError());
     LM_TRY(F->d_nm_val32.alloc(std::max<int64_t>(nnz, 1) * sizeof(float2)));
     hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nnz, 256)), dim3(256), 0, s, nnz, F->d_nm_val.as<double2>(),
@@ -2100,7 +2178,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
       hipLaunchKernelGGL(k_near_block_values, dim3(F->nb_rows.size()), dim3(256), 0, s, m, F->d_nb_jptr.as<int>(),
                          F->d_nb_jidx.as<int>(), F->d_nb_rows.as<int>(), F->d_nb_zoff.as<int64_t>(),
                          g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
-                         F->d_self.as<double2>(), F->d_nb_Z32.as<float2>());
+                         F->d_self.as<double2>(), bct, F->d_nb_Z32.as<float2>());
     // reaction near pairs alone, as CSR (the rest of the near field is in the blocks)
     const int64_t nr = (int64_t)F->rn_src.size();
     std::vector<int> rt(nr);
@@ -2114,7 +2192,7 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     if (nr) {
       hipLaunchKernelGGL(k_near_values, dim3(div_up(nr, 128)), dim3(128), 0, s, m, nr, dt.as<int>(),
                          F->d_rn_src.as<int>(), dk.as<unsigned>(), g->d_cx.as<double>(), g->d_cy.as<double>(),
-                         g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), v64.as<double2>());
+                         g->d_w.as<double>(), g->d_layer.as<int>(), F->d_self.as<double2>(), bct, v64.as<double2>());
       hipLaunchKernelGGL(k_c128_to_c64_fmm, dim3(div_up(nr, 256)), dim3(256), 0, s, nr, v64.as<double2>(),
                          F->d_rn_val32.as<float2>());
     }
@@ -2165,11 +2243,14 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
     const size_t npt = std::max<size_t>(F->pt_elem.size(), 1) * F->P * sizeof(float2);
     LM_TRY(F->d_p2m_Z32.alloc(npt));
     LM_TRY(F->d_l2p_Z32.alloc(npt));
+    if (g->bc != LM_BC_DIRICHLET) LM_TRY(F->d_l2p_Z64.alloc(2 * npt));
     if (F->item_ptr[3])
       hipLaunchKernelGGL(k_leaf_basis, dim3(F->item_ptr[3]), dim3(64), 0, s, p, F->nlev, F->d_pt_item.as<int>(),
                          F->d_boxes.as<BoxDev>(), F->d_tree_layer.as<int>(), F->d_sig.as<double>(),
                          F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), g->d_w.as<double>(),
-                         F->d_p2m_Z32.as<float2>(), F->d_l2p_Z32.as<float2>());
+                         BcTarget{g->bc, g->robin_beta, g->d_nx.as<double>(), g->d_ny.as<double>()},
+                         F->d_tree_side.as<int>(), F->d_p2m_Z32.as<float2>(), F->d_l2p_Z32.as<float2>(),
+                         F->d_l2p_Z64.as<double2>());
     LM_TRY_HIP(hipGetLastError());
   }
   LM_TRY(fmm_reserve(F, 1));
@@ -2485,6 +2566,9 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     if (pt_mfma)
       hipLaunchKernelGGL(k_l2p_mfma, dim3(ni), dim3(64 * PA_NW), 0, s, p, R, N, 1, it,
                          F->d_pt_elem.as<int>(), F->d_l2p_Z32.as<float2>(), (const float2*)le, (float2*)y);
+    else if (F->bc != LM_BC_DIRICHLET)  // stored n . grad + i beta rows
+      hipLaunchKernelGGL((k_l2p_rows<RT>), dim3(ni), dim3(256), 0, s, p, R, N, it, F->d_pt_elem.as<int>(),
+                         sizeof(RT) == 8 ? (const V*)F->d_l2p_Z64.p : (const V*)F->d_l2p_Z32.p, le, y);
     else if (R == 1)
       hipLaunchKernelGGL((k_l2p<RT, 64>), dim3(ni), dim3(blk), lds_pr, s, p, R, nlev, 1, it, boxes, tl,
                          sig, F->d_pt_elem.as<int>(), F->d_pt_xh.as<double2>(), le, N, y);

@@ -178,9 +178,9 @@ LM_HD void integrand_dy(const MediumDev& m, int lt, int ls, const PairSides& p, 
 // oscillating factor of the folded integral (e^{+i lam X} gains i lam,
 // e^{-i lam X} gains -i lam; times the sign of dx), d/dy on the target factor.
 LM_HD void reaction_direct_grad(const MediumDev& m, int lt, int ls, double dx, double yt, double ys, zd& g, zd& gx,
-                                zd& gy) {
+                                zd& gy, unsigned want = 0xFu) {
   g = gx = gy = zd(0.0, 0.0);
-  PairSides p = pair_sides(m, lt, ls, yt, ys, 0xFu);
+  PairSides p = pair_sides(m, lt, ls, yt, ys, want);
   if (!p.mask) return;
   const double X = fabs(dx), sx = dx < 0.0 ? -1.0 : 1.0;
   const double T = m.kmax + 1.5;

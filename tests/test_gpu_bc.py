@@ -9,6 +9,9 @@ oracle, through the C-ABI:
   gradients by direct Sommerfeld quadrature on both sides);
 * the right-hand side within 1e-13; the far field of the GMRES solution
   within 1e-6 (FP64 form) and 1e-4 (FP32 form) of the oracle's LU solution;
+* the same on the FMM path: matvec within 1e-8 (FP64) / 2e-5 (FP32, one and
+  eight right-hand sides), far fields of GMRES solutions against the
+  oracle's LU solution;
 * a sound-hard disk in a homogeneous medium: the scattered field at
   receivers (lm_field) against the Bessel series, at the oracle's own
   discretisation error.
@@ -63,6 +66,45 @@ def test_neumann_robin_dense_vs_oracle(bc, beta):
         assert st == lmfmm.LM_OK, rep
         print(f"bc={bc} precision={prec} iterations {[r[0] for r in rep]}", flush=True)
         check(geo.far_field(phi, obs).cpu().numpy(), fref, bar, f"bc={bc} precision={prec} far field vs oracle LU")
+
+
+@pytest.mark.parametrize("bc,beta", [(lmfmm.LM_BC_NEUMANN, None), (lmfmm.LM_BC_ROBIN, 1.7)])
+def test_neumann_robin_fmm_vs_oracle(bc, beta):
+    """The same operators on the FMM (targets evaluate n . grad + i beta of
+    the local expansions and of the near-field kernel; reaction near pairs
+    by direct quadrature of the gradient), leaf boxes of 8 elements so that
+    the expansions carry most pairs."""
+    w = _case()
+    print(f"case: straddle3 FMM bc={bc} beta={beta}", flush=True)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, bc=bc, robin_beta=beta or 0.0, leaf_size=8,
+                                       precond=0)
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    A = matrix_bc(med, el, beta)
+    x1 = wl.random_vector(el.n, seed=31, n_rhs=1)
+    y = geo.matvec(torch.from_numpy(x1).cuda()).cpu().numpy()
+    check(y, (A @ x1.T).T, 1e-8, f"bc={bc} FMM FP64 matvec (R = 1)")
+    y = geo.matvec(torch.from_numpy(x1).to(torch.complex64).cuda(), precision=lmfmm.LM_MIXED).cpu().numpy()
+    check(y, (A @ x1.T).T, 2e-5, f"bc={bc} FMM FP32 matvec (R = 1)")
+    x8 = wl.random_vector(el.n, seed=32, n_rhs=8)
+    y = geo.matvec(torch.from_numpy(x8).to(torch.complex64).cuda(), precision=lmfmm.LM_MIXED).cpu().numpy()
+    check(y, (A @ x8.T).T, 2e-5, f"bc={bc} FMM FP32 matvec (R = 8, matrix cores)")
+    th = np.radians(w.angles_deg)
+    gref = np.array([boundary_data_bc(med, t, el.cx, el.cy, el.nx, el.ny, beta) for t in th])
+    obs = lmfmm.far_field_angles()[::11]
+    fref = np.array([far_field(med, el, lu_solve(A, gref[r]), obs) for r in range(len(th))])
+    for prec, tol, bar in ((lmfmm.LM_FP64, 1e-11, 1e-6), (lmfmm.LM_MIXED, 1e-6, 1e-4)):
+        phi, rep, st = geo.solve(th, tol=tol, max_iter=400, restart=400, precond=0, precision=prec)
+        assert st == lmfmm.LM_OK, rep
+        print(f"FMM bc={bc} precision={prec} iterations {[r[0] for r in rep]}", flush=True)
+        check(geo.far_field(phi, obs).cpu().numpy(), fref, bar, f"FMM bc={bc} precision={prec} far field vs oracle LU")
+
+
+def test_fmm_rejects_preconditioner_for_neumann():
+    w = _case()
+    with pytest.raises(lmfmm.LmError) as e:
+        lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, bc=lmfmm.LM_BC_NEUMANN, precond=1)
+    assert e.value.status == -1
 
 
 def test_sound_hard_disk_field_vs_bessel_series():
