@@ -195,13 +195,13 @@ __global__ void __launch_bounds__(256) k_pre_apply(int N, int R, const int* __re
 // or the halves swapped (rho = 1).
 typedef _Float16 ph4 __attribute__((ext_vector_type(4)));
 typedef float pf4 __attribute__((ext_vector_type(4)));
-constexpr int PH_ROWS = 128, PH_KC = 64, PH_ZR = 36, PH_XS = 80;  // rows per item; LDS strides
+constexpr int PH_ROWS = 128, PH_KC = 32, PH_ZR = 20, PH_XS = 80;  // rows per item; LDS strides
 constexpr int PH_XLD = 64;  // row stride of the split input (right-hand sides)
 constexpr int PH_KSEG = 1024;  // most columns per work item (a multiple of PH_KC)
 constexpr int PH_MAXSEG = 8;    // column ranges of a row block: PRE_QMAX / PH_KSEG
 static_assert(PH_MAXSEG * PH_KSEG >= PRE_QMAX, "slots per row block");
 // Stored binary16 rows are padded with zeros to a multiple of PH_KC columns
-// (256 bytes), so every chunk a work item loads is whole 128-byte lines.
+// (128 bytes), so every chunk a work item loads is whole 128-byte lines.
 __host__ __device__ inline int h16_qp(int q) { return (q + PH_KC - 1) / PH_KC * PH_KC; }
 
 __device__ __forceinline__ uint32_t h16_pack(float re, float im) {
@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) k_h16_split(int N, int R, const double2* 
 // every item leaves its FP32 sums in a partial slot and k_pre_h16_sum adds
 // the slots of a row block in order (so the operator stays fixed), scales
 // them and writes y along the rows.
-__global__ void __launch_bounds__(512) k_pre_h16(int R, const int* __restrict__ items, const int* __restrict__ jptr,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_pre_h16(int R, const int* __restrict__ items, const int* __restrict__ jptr,
                                                  const int* __restrict__ jidx, const int* __restrict__ nb,
                                                  const int64_t* __restrict__ zoff, const uint32_t* __restrict__ Zh,
                                                  const uint32_t* __restrict__ xh, const uint32_t* __restrict__ xl,
@@ -316,7 +316,9 @@ __global__ void __launch_bounds__(512) k_pre_h16(int R, const int* __restrict__ 
   constexpr int TR = PH_ROWS / 32, UZ = PH_ROWS * PH_KC / 2048, UX = PH_KC * 64 / 2048;  // 16-byte loads per thread
   // [row][column pair]: a row's 16-byte loads go to LDS as 16-byte stores
   // side by side, and the fragment reads (8 rows x 4 column pairs) meet 32
-  // different bank pairs (row stride 72 words)
+  // different bank pairs (row stride 40 words).  Chunks of 32 columns keep
+  // the LDS of a workgroup at 41 KB and its registers at 79, so three
+  // workgroups share a CU
   __shared__ uint2 Zs[PH_ROWS][PH_ZR];
   __shared__ uint2 Xh[PH_KC / 2][PH_XS];  // [column pair][right-hand side]
   __shared__ uint2 Xl[PH_KC / 2][PH_XS];
