@@ -586,6 +586,14 @@ __global__ void __launch_bounds__(256) k_top_inv(int lgL, int lgc, int nx, int P
   }
 }
 
+// le[box] = 0 for the boxes of the list (those whose local expansion no
+// M2L or level-0 launch writes; the L2L adds into it).
+template <typename V>
+__global__ void __launch_bounds__(256) k_zero_boxes(int PR, const int* __restrict__ boxes, V* __restrict__ le) {
+  V* o = le + (int64_t)boxes[blockIdx.x] * PR;
+  for (int idx = threadIdx.x; idx < PR; idx += blockDim.x) o[idx] = mk<V>(0, 0);
+}
+
 // Transformed operator sequences (setup, FP64): class blockIdx.y, operator
 // entries [CH blockIdx.x, +CH) of P x P.  Offset di in [-(nx-1), nx-1] sits at
 // position di mod L; the adjacent offsets of a near class are zero.
@@ -2017,6 +2025,14 @@ lm_status fmm_build(lm_geom_s* g, hipStream_t s) {
   LM_TRY(up(F->d_p2m_msel, F->p2m_msel, s));
   LM_TRY(up(F->d_parents, F->parents_by_level, s));
   LM_TRY(up(F->d_m2l_tgt, F->m2l_tgt, s));
+  {  // every other box starts its local expansion from zero
+    std::vector<char> written(F->n_boxes, 0);
+    for (int b : F->m2l_tgt) written[b] = 1;
+    F->le_zero.clear();
+    for (int b = 0; b < F->n_boxes; ++b)
+      if (!written[b] && !(F->top_on && F->boxes[b].level == 0)) F->le_zero.push_back(b);
+    LM_TRY(up(F->d_le_zero, F->le_zero, s));
+  }
   LM_TRY(up(F->d_m2l_ptr, F->m2l_ptr, s));
   LM_TRY(up(F->d_m2l_src, F->m2l_src, s));
   LM_TRY(up(F->d_m2l_tab, F->m2l_tab, s));
@@ -2457,8 +2473,10 @@ lm_status matvec_chunk(lm_geom_s* g, int R, const typename C2T<RT>::T* x, typena
     }
   }
   LM_STAGE(1, 0);
-  // M2L (every level at once); boxes without a list start from zero
-  LM_TRY_HIP(hipMemsetAsync(le, 0, (size_t)F->n_boxes * PR * sizeof(V), s));
+  // M2L (every level at once); the M2L and level-0 launches overwrite their
+  // targets, boxes without either start from zero
+  if (!F->le_zero.empty())
+    hipLaunchKernelGGL(k_zero_boxes<V>, dim3(F->le_zero.size()), dim3(256), 0, s, PR, F->d_le_zero.as<int>(), le);
   // level 0 as a convolution along x (stage 7): transform the level-0
   // expansions of every row, one product per row pair and frequency,
   // transform back into the level-0 local expansions

@@ -98,6 +98,8 @@ struct FmmPlan {
   DevBuf d_om_slot;  // per-entry M2L results of the few-right-hand-side (operator-major) launch
   DevBuf d_sc_ptr, d_sc_src, d_sc_val, d_sc_val32;
   DevBuf d_tree_side, d_l2p_Z64;  // sound-hard / impedance: per-tree side, FP64 L2P rows
+  std::vector<int> le_zero;  // boxes no M2L or level-0 launch writes: their local expansions start at zero
+  DevBuf d_le_zero;
   DevBuf d_p2m_dst, d_p2m_msel;
   int r_cap = 0;  // right-hand sides the expansion buffers hold
   // side stream of the near field (default priority) and its fork / join events
@@ -122,7 +124,7 @@ struct FmmPlan {
                            &d_m2l_out, &d_top_grid, &d_top_item, &d_top_ptr, &d_top_src, &d_top_op, &d_top_id,
                            &d_top_tw64, &d_top_tw32, &d_top_T64, &d_top_T32, &d_top_mh, &d_top_lh,
                            &d_om_slot, &d_p2m_dst, &d_p2m_msel, &d_sc_ptr, &d_sc_src, &d_sc_val,
-                           &d_sc_val32, &d_tree_side, &d_l2p_Z64};
+                           &d_sc_val32, &d_tree_side, &d_l2p_Z64, &d_le_zero};
     int64_t b = 0;
     for (auto* d : all) b += d->bytes;
     return b;
