@@ -62,7 +62,7 @@ def _args():
     ap.add_argument("--pool-geometries", type=int, default=6,
                     help="serve open-loop streams over this many pool geometries (2-4 layers, N in "
                          "[4,000, 250,000], 1-16 angles per request); 0: skip")
-    ap.add_argument("--pool-requests", type=int, default=30, help="requests per pool stream")
+    ap.add_argument("--pool-requests", type=int, default=20, help="requests per pool stream")
     ap.add_argument("--pool-rho", type=str, default="0.5,0.9",
                     help="arrival rates of the pool streams as fractions of the pool's served capacity")
     ap.add_argument("--replica", type=str, default="",
