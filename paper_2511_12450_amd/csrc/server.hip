@@ -952,6 +952,10 @@ lm_status run_round(lm_server_s* S) {
   std::vector<int> timed_streams;
   double m2l_flops_round = 0.0;
   int64_t n_launch = 0, n_fused = 0;
+  // one group: its fused launch runs on the round's own stream (a wait on
+  // another stream's event costs about 15 us each way); several: one stream
+  // per geometry, so that different geometries overlap
+  const bool one_group = byg.size() == 1;
   for (auto& kv : byg) {
     lm_geom_s* g = kv.first.first;
     const bool pre = kv.first.second && g->pre;
@@ -959,9 +963,9 @@ lm_status run_round(lm_server_s* S) {
     auto it = S->stream_of.find(g);
     if (it == S->stream_of.end()) it = S->stream_of.emplace(g, (int)(S->stream_of.size() % SRV_STREAMS)).first;
     const int si = it->second;
-    hipStream_t st = S->gs[si];
-    if (!used_stream[si]) LM_TRY_HIP(hipStreamWaitEvent(st, S->ev_main, 0));
-    used_stream[si] = 1;
+    hipStream_t st = one_group ? S->s : S->gs[si];
+    if (!one_group && !used_stream[si]) LM_TRY_HIP(hipStreamWaitEvent(st, S->ev_main, 0));
+    used_stream[si] = one_group ? 0 : 1;
     Group& G = S->groups[kv.first];
     const bool time_m2l = g->method == LM_FMM && !stream_timed[si];
     G.km.stage_ev = time_m2l ? S->sev[si] : nullptr;
