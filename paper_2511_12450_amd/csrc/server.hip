@@ -863,10 +863,9 @@ lm_status run_round(lm_server_s* S) {
   const int prec = S->o.precision;
   const bool f32 = prec == LM_MIXED;  // complex64 Krylov basis
   const int nc = (int)cols.size();
-  int Nmax = 0, ldh = 1, cntmax = 0;
+  int Nmax = 0, cntmax = 0;
   for (Column* c : cols) {
     Nmax = std::max(Nmax, c->N);
-    ldh = std::max(ldh, c->m + 1);
     // an Arnoldi step needs K M u_j unless it can only finalise column j-1
     // (restart length reached or the last allowed iteration)
     c->km = c->phase == PH_RESTART || c->phase == PH_FINAL ||
@@ -874,7 +873,9 @@ lm_status run_round(lm_server_s* S) {
     if (c->phase == PH_ARNOLDI) cntmax = std::max(cntmax, c->j + 1);
   }
   const int nwu = 4 * (int)div_up(Nmax, 256), nbd = (int)div_up(Nmax, SD_SLICE);
-  const int hs = 2 * ldh;
+  // dot products per column: V^H u then V^H z, cntmax each (the longest
+  // basis of the round), so the copy to the host holds no unused rows
+  const int ldh = std::max(1, cntmax), hs = 2 * ldh;
   LM_TRY_HIP(hipEventRecord(S->t0, S->s));
   // ---- 1. K M v for every column that needs it, fused per (geometry, precond)
   std::map<std::pair<lm_geom_s*, int>, std::vector<Column*>> byg;
