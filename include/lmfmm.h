@@ -407,9 +407,10 @@ lm_status lm_server_memory(lm_server server, int64_t* out3);
  * plus the norms), [2] bytes that phase must move at minimum: per Arnoldi
  * column at step j, with b = 16 bytes per basis element (LM_FP64) or 8
  * (LM_MIXED: the Krylov basis is stored in complex64, every sum is
- * accumulated in FP64), (2 j + 5) N b + 3 N x 16 (dot pass: V[0..j], u and
- * the K M output; residual norm of the K M output; update pass: V[0..j-1],
- * u and the K M output read, v_j and the next vector written); [3] ms in the M2L
+ * accumulated in FP64), (2 j + 5) N b + 2 N x 16 (dot pass: V[0..j], u and
+ * the K M output; update pass: V[0..j-1], u and the K M output read, v_j
+ * and the next vector written; at j = 0 one more N x 16 for the norm of the
+ * K M output); [3] ms in the M2L
  * launches of the fused FMM matvecs (first launch of each geometry stream
  * per round), [4] their algorithmic flops, 8 (2p+1)^2 R per M2L list entry,
  * [5] the number of those launches, [6] host wall-clock ms of the rounds

@@ -122,10 +122,12 @@ __device__ __forceinline__ double s_wave_sum(double v) {
 }
 
 // w = g - w when g is set; wave partials of |w|^2 into part[col nw + wave].
+// Columns whose norm an earlier pass left (nsrc) are skipped: k_s_norm_final
+// reports that one.
 __global__ void __launch_bounds__(256) k_s_resid(const ColDev* __restrict__ d, double* __restrict__ part, int nw) {
   const ColDev c = d[blockIdx.y];
   const int n = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= c.N || !c.w) return;  // beyond this column, or nothing to do
+  if (blockIdx.x * 256 >= c.N || !c.w || c.nsrc) return;  // beyond this column, or nothing to do
   double q = 0.0;
   if (n < c.N) {
     double2 v = c.w[n];
@@ -1117,7 +1119,7 @@ lm_status run_round(lm_server_s* S) {
     const int j = c->j;
     // basis vectors (bb bytes per element) and complex128 vectors moved by the
     // dot, residual-norm and update kernels of this step
-    o.gsb += (c->km ? (2.0 * j + 5.0) * bb + 3.0 * 16.0 : (j + 2.0) * bb) * N;
+    o.gsb += (c->km ? (2.0 * j + 5.0) * bb + (j == 0 ? 3.0 : 2.0) * 16.0 : (j + 2.0) * bb) * N;
     const double2* ha = &hhv[(size_t)i * hs];
     const double2* hb = ha + ldh;
     std::vector<C> aQ(j), bQ(j);
