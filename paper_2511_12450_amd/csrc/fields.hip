@@ -1,4 +1,7 @@
 // Right-hand side (incident + background field) and far-field patterns.
+#include <algorithm>
+#include <cstring>
+
 #include "lm_internal.hpp"
 
 // ------------------------------------------------------------------- rhs --
@@ -76,22 +79,54 @@ __global__ void k_rhs_bc(int N, int R, const BgAmp* __restrict__ amp, const doub
   g[(int64_t)r * N + i] = make_double2(v.re, v.im);
 }
 
-lm_status rhs_launch(lm_geom_s* g, int R, const double* theta_host, void* g_dev, hipStream_t s) {
-  DevBuf th, amp;
-  LM_TRY(upload(th, theta_host, R * sizeof(double), s));
-  LM_TRY(amp.alloc(R * sizeof(BgAmp)));
-  hipLaunchKernelGGL(k_background, dim3(div_up(R, 64)), dim3(64), 0, s, g->m, R, th.as<double>(), amp.as<BgAmp>());
+size_t rhs_scratch_bytes(int R) { return (size_t)std::max(R, 1) * sizeof(BgAmp); }
+
+lm_status rhs_launch_dev(lm_geom_s* g, int R, const double* theta_dev, void* scratch, void* g_dev, hipStream_t s) {
+  BgAmp* amp = static_cast<BgAmp*>(scratch);
+  hipLaunchKernelGGL(k_background, dim3(div_up(R, 64)), dim3(64), 0, s, g->m, R, theta_dev, amp);
   LM_TRY_HIP(hipGetLastError());
   const int N = (int)g->N;
   if (g->bc == LM_BC_DIRICHLET)
-    hipLaunchKernelGGL(k_rhs, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(), g->d_cx.as<double>(),
-                       g->d_cy.as<double>(), g->d_layer.as<int>(), th.as<double>(), g->m, (double2*)g_dev);
+    hipLaunchKernelGGL(k_rhs, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp, g->d_cx.as<double>(),
+                       g->d_cy.as<double>(), g->d_layer.as<int>(), theta_dev, g->m, (double2*)g_dev);
   else
-    hipLaunchKernelGGL(k_rhs_bc, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp.as<BgAmp>(),
-                       g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_nx.as<double>(), g->d_ny.as<double>(),
-                       g->d_layer.as<int>(), th.as<double>(), g->m, g->robin_beta, (double2*)g_dev);
+    hipLaunchKernelGGL(k_rhs_bc, dim3(div_up(N, 256), R), dim3(256), 0, s, N, R, amp, g->d_cx.as<double>(),
+                       g->d_cy.as<double>(), g->d_nx.as<double>(), g->d_ny.as<double>(), g->d_layer.as<int>(),
+                       theta_dev, g->m, g->robin_beta, (double2*)g_dev);
   LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+lm_status rhs_launch(lm_geom_s* g, int R, const double* theta_host, void* g_dev, hipStream_t s) {
+  DevBuf th, amp;
+  LM_TRY(upload(th, theta_host, R * sizeof(double), s));
+  LM_TRY(amp.alloc(rhs_scratch_bytes(R)));
+  LM_TRY(rhs_launch_dev(g, R, th.as<double>(), amp.p, g_dev, s));
   LM_TRY_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+  return LM_OK;
+}
+
+// ------------------------------------------------------ values by value --
+// Up to PUT_F64 doubles travel in the kernel arguments, so the copy reads no
+// host memory after the launch call returns (no staging buffer to keep alive).
+constexpr int PUT_F64 = 128;
+struct F64Chunk {
+  double v[PUT_F64];
+};
+
+__global__ void __launch_bounds__(PUT_F64) k_put_f64(F64Chunk a, int n, double* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = a.v[i];
+}
+
+lm_status put_f64_async(const double* host, int n, double* dev, hipStream_t s) {
+  for (int o = 0; o < n; o += PUT_F64) {
+    F64Chunk a;
+    const int k = std::min(PUT_F64, n - o);
+    std::memcpy(a.v, host + o, (size_t)k * sizeof(double));
+    hipLaunchKernelGGL(k_put_f64, dim3(1), dim3(PUT_F64), 0, s, a, k, dev + o);
+    LM_TRY_HIP(hipGetLastError());
+  }
   return LM_OK;
 }
 
@@ -180,16 +215,22 @@ __global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, co
   }
 }
 
+lm_status farfield_launch_dev(lm_geom_s* g, int R, const void* phi, int n_obs, const double* obs_dev, void* out,
+                              hipStream_t s) {
+  const int N = (int)g->N;
+  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, g->m, N, R, obs_dev,
+                     g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
+                     (const double2*)phi, (double2*)out, n_obs);
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
 lm_status farfield_launch(lm_geom_s* g, int R, const void* phi, int n_obs, const double* obs_host, void* out,
                           hipStream_t s) {
   DevBuf ob;
   LM_TRY(upload(ob, obs_host, n_obs * sizeof(double), s));
-  const int N = (int)g->N;
-  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, g->m, N, R, ob.as<double>(),
-                     g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
-                     (const double2*)phi, (double2*)out, n_obs);
-  LM_TRY_HIP(hipGetLastError());
-  LM_TRY_HIP(hipStreamSynchronize(s));
+  LM_TRY(farfield_launch_dev(g, R, phi, n_obs, ob.as<double>(), out, s));
+  LM_TRY_HIP(hipStreamSynchronize(s));  // before ob is freed
   return LM_OK;
 }
 

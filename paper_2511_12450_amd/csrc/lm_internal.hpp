@@ -127,6 +127,16 @@ lm_status geom_matvec(lm_geom_s* g, int precision, int n_rhs, const void* x, voi
 lm_status rhs_launch(lm_geom_s* g, int n_rhs, const double* theta_host, void* g_dev, hipStream_t s);
 lm_status farfield_launch(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_host,
                           void* out, hipStream_t s);
+// Queued forms (no allocation, no wait): angles already on the device, and a
+// scratch buffer of rhs_scratch_bytes(n_rhs) for the right-hand side.
+size_t rhs_scratch_bytes(int n_rhs);
+lm_status rhs_launch_dev(lm_geom_s* g, int n_rhs, const double* theta_dev, void* scratch, void* g_dev,
+                         hipStream_t s);
+lm_status farfield_launch_dev(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_dev,
+                              void* out, hipStream_t s);
+// Copies n doubles from host memory to the device in kernel arguments
+// (stream-ordered; the host array may be reused as soon as this returns).
+lm_status put_f64_async(const double* host, int n, double* dev, hipStream_t s);
 lm_status point_far_field_launch(const MediumDev& m, int n_src, const double* src_xy_host, int n_obs,
                                  const double* obs_host, void* out, hipStream_t s);
 struct KmBufs {

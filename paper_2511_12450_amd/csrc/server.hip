@@ -23,6 +23,11 @@
 //      and norms per round;
 //   3. Givens rotations and convergence tests on the host, then the batched
 //      update pass and solution updates.
+// The host waits once per round (for the dot products); everything else is
+// queued behind it without waiting: round buffers that must grow are
+// replaced by larger ones and the old ones freed at the next idle point, and
+// finished columns copy phi and the far field to pinned staging memory, from
+// which the host fills the requests' arrays while the next round runs.
 // Requests that arrive while others run are admitted at the next round as
 // soon as right-hand-side slots and the HBM budget allow; a request whose
 // footprint can never fit is rejected at submission.  Admission, cancel,
@@ -389,7 +394,9 @@ __global__ void __launch_bounds__(64) k_s_norm_to(const ColDev* __restrict__ d, 
   if (threadIdx.x == 0) *c.ndst = q;
 }
 
-enum Phase { PH_INIT = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_FINAL = 3 };
+// PH_STAGED: solved; phi and the far field are being copied to pinned host
+// memory, and the column is marked finished once those copies are done.
+enum Phase { PH_INIT = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_FINAL = 3, PH_STAGED = 4 };
 
 struct Request;
 
@@ -505,27 +512,47 @@ class HostPool {
     // the workers end within microseconds of the last item
     while (busy_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
   }
+  // A run() follows within milliseconds: sleeping workers wake now and poll
+  // (up to kArmSpin), so that the run does not wait for their wake-up.
+  void arm() {
+    if (nt_ == 1) return;
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      arm_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+  }
 
  private:
   void work() {
     for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*f_)(i);
   }
-  // Waits for the next generation: polls for up to kSpin (rounds come every
-  // few milliseconds while requests run), then sleeps.
+  // Waits for the next generation: polls for up to kSpin after a run and up
+  // to kArmSpin after an arm(), then sleeps until either comes.
   void loop() {
-    constexpr auto kSpin = std::chrono::microseconds(200);
-    uint64_t seen = 0;
+    constexpr auto kSpin = std::chrono::microseconds(200), kArmSpin = std::chrono::microseconds(20000);
+    uint64_t seen = 0, seen_arm = arm_.load(std::memory_order_acquire);
+    auto limit = kSpin;
     while (true) {
-      const auto t0 = std::chrono::steady_clock::now();
+      auto t0 = std::chrono::steady_clock::now();
       uint64_t g;
       while ((g = gen_.load(std::memory_order_acquire)) == seen) {
-        if (std::chrono::steady_clock::now() - t0 < kSpin) {
+        const uint64_t a = arm_.load(std::memory_order_acquire);
+        if (a != seen_arm) {
+          seen_arm = a;
+          t0 = std::chrono::steady_clock::now();
+          limit = kArmSpin;
+        }
+        if (std::chrono::steady_clock::now() - t0 < limit) {
           std::this_thread::yield();
           continue;
         }
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+        cv_.wait(lk, [&] {
+          return gen_.load(std::memory_order_acquire) != seen || arm_.load(std::memory_order_acquire) != seen_arm;
+        });
       }
+      limit = kSpin;
       seen = g;
       if (stop_.load(std::memory_order_acquire)) return;
       work();
@@ -539,7 +566,7 @@ class HostPool {
   const std::function<void(int)>* f_ = nullptr;
   int n_ = 0;
   std::atomic<int> next_{0}, busy_{0};
-  std::atomic<uint64_t> gen_{0};
+  std::atomic<uint64_t> gen_{0}, arm_{0};
   std::atomic<bool> stop_{false};
 };
 
@@ -579,6 +606,21 @@ struct lm_server_s {
   DevBuf d_desc, d_desc_u, d_hn, d_dpart, d_npart;
   HostBuf h_desc, h_desc_u, h_hn;
   DevBuf d_fz, d_fphi, d_fff;  // finishing columns: z, phi = M z, far fields
+  DevBuf d_fobs, d_adm;        // far-field angles; admission: right-hand-side scratch, then angles
+  // finishing columns whose phi / far field copies into h_fin are queued
+  // (behind ev_fin); their requests' host arrays are filled once it fires
+  struct Staged {
+    Column* c;
+    size_t phi_off, ff_off;  // byte offsets into h_fin
+    int no;                  // far-field angles
+  };
+  std::vector<Staged> staged;
+  HostBuf h_fin;
+  hipEvent_t ev_fin = nullptr;
+  // allocations replaced by larger ones while queued work may still use
+  // them: freed at the next point where the streams are idle (quiesce)
+  std::vector<void*> retired, retired_host;
+  int64_t retired_bytes = 0;
   std::unique_ptr<HostPool> pool;  // per-column host updates
   std::vector<HostStep> steps;
   std::vector<ColDev> hdesc;
@@ -598,23 +640,42 @@ int64_t footprint(const lm_geom_s* g, const lm_gmres_opts& o, int R) {
 // Waits for everything queued on the server's streams (the side streams of
 // the fused launches join the main stream every round), before device
 // buffers that queued kernels may still use are freed or regrown.
+void free_retired(lm_server_s* S) {
+  for (void* p : S->retired) (void)hipFree(p);
+  for (void* p : S->retired_host) (void)hipHostFree(p);
+  S->retired.clear();
+  S->retired_host.clear();
+  S->retired_bytes = 0;
+}
+
 lm_status quiesce(lm_server_s* S) {
   LM_TRY_HIP(hipStreamSynchronize(S->s));
+  free_retired(S);
   return LM_OK;
 }
 
+// Grows a round buffer without waiting for the kernels queued on it: the old
+// allocation is retired (freed at the next quiesce) and the new one is at
+// least twice as large, so that buffers growing by a row each round (the
+// dot products of a lengthening basis) are reallocated O(log j) times and
+// the host keeps queueing ahead of the GPU.
 lm_status ensure(lm_server_s* S, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return LM_OK;
-  if (b.p) LM_TRY(quiesce(S));
-  LM_TRY(b.alloc(bytes));
+  const size_t n = b.p ? std::max(bytes, 2 * b.bytes) : bytes;
+  if (b.p) {
+    S->retired.push_back(b.p);
+    S->retired_bytes += (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  LM_TRY(b.alloc(n));
   return LM_OK;
 }
 
 lm_status host_ensure(lm_server_s* S, HostBuf& h, size_t bytes) {
   if (h.bytes >= bytes) return LM_OK;
-  if (h.p) {
-    LM_TRY(quiesce(S));  // a copy from the old buffer may be queued
-    (void)hipHostFree(h.p);
+  if (h.p) {  // a copy from the old buffer may be queued
+    S->retired_host.push_back(h.p);
     h.p = nullptr;
     h.bytes = 0;
   }
@@ -712,7 +773,7 @@ void settle_memory(lm_server_s* S, bool idle) {
   }
   if (idle)  // nothing admitted: the round and finishing buffers are regrown on demand
     for (DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
-                      &S->d_fff})
+                      &S->d_fff, &S->d_fobs, &S->d_adm})
       b->release();
   int64_t h = 0, hs = 0;
   for (const Column* c : S->cols) h += col_bytes(c);
@@ -722,8 +783,9 @@ void settle_memory(lm_server_s* S, bool idle) {
     h += (int64_t)(G.X.bytes + G.Y.bytes + G.km.x32.bytes + G.km.y32.bytes + G.km.mz.bytes);
   }
   for (const DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
-                          &S->d_fff})
+                          &S->d_fff, &S->d_fobs, &S->d_adm})
     h += (int64_t)b->bytes;
+  h += S->retired_bytes;
   std::lock_guard<std::mutex> lk(S->B.mu);
   S->held = h + hs;
   S->held_spare = hs;
@@ -732,6 +794,12 @@ void settle_memory(lm_server_s* S, bool idle) {
 lm_status start_request(lm_server_s* S, Request* q) {
   const int m = std::max(1, std::min(q->o.restart, q->o.max_iter));
   const int N = (int)q->g->N;
+  // the angles go down in kernel arguments and the right-hand sides are
+  // queued: admission does not wait for the rounds in flight
+  const size_t sb = (rhs_scratch_bytes(1) + 255) / 256 * 256;
+  LM_TRY(ensure(S, S->d_adm, sb + (size_t)q->R * sizeof(double)));
+  double* d_th = reinterpret_cast<double*>(S->d_adm.as<char>() + sb);
+  LM_TRY(put_f64_async(q->theta.data(), q->R, d_th, S->s));
   for (int c = 0; c < q->R; ++c) {
     // a spare column of the same shape keeps its device buffers
     Column* col = nullptr;
@@ -767,7 +835,7 @@ lm_status start_request(lm_server_s* S, Request* q) {
       }
     }
     LM_TRY_HIP(hipMemsetAsync(col->z.p, 0, (size_t)N * sizeof(double2), S->s));
-    LM_TRY(rhs_launch(q->g, 1, &q->theta[c], col->gv.p, S->s));
+    LM_TRY(rhs_launch_dev(q->g, 1, d_th + c, S->d_adm.p, col->gv.p, S->s));
     // an Arnoldi step writes rows 0..j+1 of its Hessenberg column before
     // anything reads them, so a reused column's arrays need no clearing
     col->H.resize((size_t)(m + 1) * m);
@@ -783,12 +851,46 @@ lm_status start_request(lm_server_s* S, Request* q) {
   return LM_OK;
 }
 
-// phi = M z, far fields and copies to host memory for the columns that
-// finished this round; marks them finished.  Columns on one geometry share
-// one preconditioner launch (several right-hand sides), columns of requests
-// with the same observation angles one far-field launch.  Returns the first failure; the columns of a
-// failed group are reported through *failed.
+// Fills the requests' host arrays of the staged columns from h_fin and marks
+// the columns finished, once the staging copies are done: at once if `block`,
+// else only if ev_fin has fired.  Returns whether nothing stays staged.
+bool complete_staged(lm_server_s* S, bool block) {
+  if (S->staged.empty()) return true;
+  if (block) {
+    if (hipEventSynchronize(S->ev_fin) != hipSuccess) return false;
+  } else if (hipEventQuery(S->ev_fin) != hipSuccess) {
+    return false;
+  }
+  const char* hb = S->h_fin.as<char>();
+  auto copy = [&](int i) {
+    const lm_server_s::Staged& e = S->staged[i];
+    Column* c = e.c;
+    std::memcpy(c->req->phi.data() + (size_t)c->col * c->N, hb + e.phi_off, (size_t)c->N * sizeof(double2));
+    if (e.no)
+      std::memcpy(c->req->ff.data() + (size_t)c->col * e.no, hb + e.ff_off, (size_t)e.no * sizeof(double2));
+  };
+  S->pool->run((int)S->staged.size(), copy);
+  for (const lm_server_s::Staged& e : S->staged) e.c->finished = true;
+  S->staged.clear();
+  return true;
+}
+
+// Drops the staged entries of a request that leaves (cancelled or failed):
+// its columns are about to be released.
+void unstage(lm_server_s* S, const Request* q) {
+  auto& v = S->staged;
+  v.erase(std::remove_if(v.begin(), v.end(), [&](const lm_server_s::Staged& e) { return e.c->req == q; }), v.end());
+}
+
+// phi = M z, far fields and their copies to pinned host memory for the
+// columns that finished this round; the copies are not waited for (the
+// columns are PH_STAGED until complete_staged sees them done, normally while
+// the next round runs).  Columns on one geometry share one preconditioner
+// launch (several right-hand sides), columns of requests with the same
+// observation angles one far-field launch.  Returns the first failure; the
+// columns of a failed group are reported through *failed.
 lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<Request*>* failed) {
+  LM_CHECK(complete_staged(S, true), LM_EHIP, "HIP error while copying solutions to host memory");
   std::stable_sort(fin.begin(), fin.end(), [](const Column* a, const Column* b) {
     if (a->g != b->g) return a->g < b->g;
     const bool pa = a->req->o.precond != 0, pb = b->req->o.precond != 0;
@@ -796,6 +898,11 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
     if (a->req != b->req) return a->req->id < b->req->id;
     return a->col < b->col;
   });
+  size_t hbytes = 0;
+  for (const Column* c : fin) hbytes += ((size_t)c->N + c->req->obs.size()) * sizeof(double2);
+  LM_TRY(host_ensure(S, S->h_fin, hbytes));
+  char* hb = S->h_fin.as<char>();
+  size_t off = 0;
   lm_status first = LM_OK;
   for (size_t i0 = 0; i0 < fin.size();) {
     lm_geom_s* g = fin[i0]->g;
@@ -805,19 +912,22 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
       ++i1;
     const int k = (int)(i1 - i0), N = fin[i0]->N;
     const size_t vb = (size_t)N * sizeof(double2);
+    const size_t s0 = S->staged.size();
     auto group = [&]() -> lm_status {
-      if (S->d_fz.bytes < k * vb) LM_TRY(S->d_fz.alloc(k * vb));
-      if (S->d_fphi.bytes < k * vb) LM_TRY(S->d_fphi.alloc(k * vb));
+      // d_fz / d_fphi / d_fff: earlier finishing work that used them is
+      // queued before this on the one stream, and grown buffers are retired
+      LM_TRY(ensure(S, S->d_fz, k * vb));
+      LM_TRY(ensure(S, S->d_fphi, k * vb));
       char* zb = (char*)S->d_fz.p;
       char* pb = (char*)S->d_fphi.p;
       for (int i = 0; i < k; ++i)
         LM_TRY_HIP(hipMemcpyAsync((pre ? zb : pb) + i * vb, fin[i0 + i]->z.p, vb, hipMemcpyDeviceToDevice, S->s));
       if (pre) LM_TRY(precond_apply(g, pre_precision(S), k, zb, pb, S->s));
-      for (int i = 0; i < k; ++i) {
-        Column* c = fin[i0 + i];
-        LM_TRY_HIP(hipMemcpyAsync(c->req->phi.data() + (size_t)c->col * N, pb + i * vb, vb, hipMemcpyDeviceToHost,
-                                  S->s));
-      }
+      // phi of the group: one copy (its columns are contiguous in d_fphi)
+      const size_t phi0 = off;
+      LM_TRY_HIP(hipMemcpyAsync(hb + phi0, pb, k * vb, hipMemcpyDeviceToHost, S->s));
+      off += k * vb;
+      for (int i = 0; i < k; ++i) S->staged.push_back({fin[i0 + i], phi0 + i * vb, 0, 0});
       for (int a = 0; a < k;) {  // one far-field launch per run of requests with the same angles
         const std::vector<double>& obs = fin[i0 + a]->req->obs;
         int b = a;
@@ -825,19 +935,24 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
         const int no = (int)obs.size();
         if (no) {
           const size_t fb = (size_t)(b - a) * no * sizeof(double2);
-          if (S->d_fff.bytes < fb) LM_TRY(S->d_fff.alloc(fb));
-          LM_TRY(farfield_launch(g, b - a, pb + a * vb, no, obs.data(), S->d_fff.p, S->s));
-          for (int i = a; i < b; ++i)
-            LM_TRY_HIP(hipMemcpyAsync(fin[i0 + i]->req->ff.data() + (size_t)fin[i0 + i]->col * no,
-                                      (const double2*)S->d_fff.p + (size_t)(i - a) * no, (size_t)no * sizeof(double2),
-                                      hipMemcpyDeviceToHost, S->s));
+          LM_TRY(ensure(S, S->d_fff, fb));
+          LM_TRY(ensure(S, S->d_fobs, (size_t)no * sizeof(double)));
+          LM_TRY(put_f64_async(obs.data(), no, S->d_fobs.as<double>(), S->s));
+          LM_TRY(farfield_launch_dev(g, b - a, pb + a * vb, no, S->d_fobs.as<double>(), S->d_fff.p, S->s));
+          LM_TRY_HIP(hipMemcpyAsync(hb + off, S->d_fff.p, fb, hipMemcpyDeviceToHost, S->s));
+          for (int i = a; i < b; ++i) {
+            lm_server_s::Staged& e = S->staged[s0 + i];
+            e.ff_off = off + (size_t)(i - a) * no * sizeof(double2);
+            e.no = no;
+          }
+          off += fb;
         }
         a = b;
       }
-      LM_TRY_HIP(hipStreamSynchronize(S->s));
       return LM_OK;
     };
     const lm_status st = group();
+    if (st < 0) S->staged.resize(s0);
     for (size_t i = i0; i < i1; ++i) {
       Column* c = fin[i];
       if (st < 0) {
@@ -846,11 +961,12 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
       }
       c->req->rep[c->col].iterations = c->its;
       c->req->rep[c->col].rel_residual = c->res;
-      c->finished = true;
+      c->phase = PH_STAGED;
     }
     if (st < 0 && first == LM_OK) first = st;
     i0 = i1;
   }
+  if (!S->staged.empty()) LM_TRY_HIP(hipEventRecord(S->ev_fin, S->s));
   return first;
 }
 
@@ -860,8 +976,11 @@ lm_status run_round(lm_server_s* S) {
   const double tr0 = now_s();
   std::vector<Column*> cols;
   for (Column* c : S->cols)
-    if (!c->finished) cols.push_back(c);
-  if (cols.empty()) return LM_OK;
+    if (!c->finished && c->phase != PH_STAGED) cols.push_back(c);
+  if (cols.empty()) {  // only staged columns left
+    LM_CHECK(complete_staged(S, true), LM_EHIP, "HIP error while copying solutions to host memory");
+    return LM_OK;
+  }
   const int prec = S->o.precision;
   const bool f32 = prec == LM_MIXED;  // complex64 Krylov basis
   const int nc = (int)cols.size();
@@ -1030,6 +1149,10 @@ lm_status run_round(lm_server_s* S) {
   // microseconds of the copy (the worker thread is busy-waiting meanwhile)
   const double tw0 = now_s();
   LM_TRY_HIP(hipEventRecord(S->ev_wait, S->s));
+  // the previous round's staging copies ran before this round's kernels:
+  // copy them out while those run
+  (void)complete_staged(S, true);
+  S->pool->arm();  // the host step follows the wait
   for (;;) {
     const hipError_t q = hipEventQuery(S->ev_wait);
     if (q == hipSuccess) break;
@@ -1328,9 +1451,12 @@ lm_status run_round(lm_server_s* S) {
 }
 
 // Removes the request's columns; up to max_active_rhs of them stay as spares
-// with their device buffers for the next admission of the same shape.
+// with their device buffers for the next admission of the same shape.  A
+// spare is only written by work queued after what may still use it (one
+// stream), so only freeing a column waits for the queued kernels.
 void release_columns(lm_server_s* S, Request* q) {
-  (void)quiesce(S);  // queued kernels may still use the columns' buffers
+  unstage(S, q);
+  bool synced = false;
   auto& v = S->cols;
   for (auto it = v.begin(); it != v.end();) {
     if ((*it)->req == q) {
@@ -1340,6 +1466,8 @@ void release_columns(lm_server_s* S, Request* q) {
         (*it)->req = nullptr;
         S->spare.push_back(*it);
       } else {
+        if (!synced) (void)quiesce(S);  // queued kernels may still use the column's buffers
+        synced = true;
         delete *it;
       }
       it = v.erase(it);
@@ -1404,7 +1532,8 @@ extern "C" lm_status lm_server_create(const lm_server_opts* o, lm_server* out) {
             hipEventCreate(&S->t0) == hipSuccess && hipEventCreate(&S->t1) == hipSuccess &&
             hipEventCreate(&S->t2) == hipSuccess && hipEventCreate(&S->tu1) == hipSuccess &&
             hipEventCreate(&S->tu2) == hipSuccess &&
-            hipEventCreateWithFlags(&S->ev_wait, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&S->ev_wait, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&S->ev_fin, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
     for (int e = 0; ok && e < 16; ++e) ok = hipEventCreate(&S->sev[i][e]) == hipSuccess;
   for (int i = 0; ok && i < SRV_STREAMS; ++i)
@@ -1543,7 +1672,7 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
   S->B.request_stop();
   if (S->th.joinable()) S->th.join();
   S->B.clear();
-  (void)hipStreamSynchronize(S->s);
+  (void)quiesce(S);
   for (Column* c : S->cols) delete c;
   S->cols.clear();
   S->groups.clear();
@@ -1552,7 +1681,8 @@ extern "C" lm_status lm_server_destroy(lm_server S) {
     if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
   }
   if (S->ev_main) (void)hipEventDestroy(S->ev_main);
-  for (hipEvent_t e : {S->t0, S->t1, S->t2, S->tu1, S->tu2, S->ev_wait})
+  S->staged.clear();
+  for (hipEvent_t e : {S->t0, S->t1, S->t2, S->tu1, S->tu2, S->ev_wait, S->ev_fin})
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < SRV_STREAMS; ++i)
     for (int e = 0; e < 16; ++e)
