@@ -56,8 +56,11 @@ namespace {
 
 typedef std::complex<double> C;
 constexpr int SRV_STREAMS = 4;
-constexpr int SD_SLICE = 2048;  // elements per workgroup in the dot kernel
-constexpr int SD_IBLK = 64;     // basis vectors per workgroup in the dot kernel
+// elements per workgroup in the dot kernel: 4096 for the complex64 basis
+// (16 elements of each vector in flight per thread), 2048 for complex128
+template <typename BT> constexpr int sd_slice() { return sizeof(BT) == 8 ? 4096 : 2048; }
+constexpr int SD_IBLK = 64;  // basis vectors per LDS flush of the dot kernel
+constexpr int SD_WGS = 1024;  // workgroups a dot launch aims for (split over the basis below that)
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -221,17 +224,45 @@ __global__ void __launch_bounds__(256) k_s_gather(const ColDev* __restrict__ d) 
   if (c.dst) c.dst[n] = v;
 }
 
+// Two consecutive basis elements of one vector, as loaded (converted to
+// FP64 when used): the next pair of vectors is loaded while this one is
+// reduced.
+template <typename BT> struct BPair;
+template <> struct BPair<float2> {
+  float4 v;
+  __device__ void load(const float2* p) { v = *reinterpret_cast<const float4*>(p); }
+  __device__ void get(double2& a, double2& b) const {
+    a = make_double2((double)v.x, (double)v.y);
+    b = make_double2((double)v.z, (double)v.w);
+  }
+};
+template <> struct BPair<double2> {
+  double2 x, y;
+  __device__ void load(const double2* p) {
+    x = p[0];
+    y = p[1];
+  }
+  __device__ void get(double2& a, double2& b) const {
+    a = x;
+    b = y;
+  }
+};
+
 // Workgroup partials of conj(V[i]) . u and conj(V[i]) . z, u = V[cnt-1],
-// z = the K M output (or none), for the basis vectors of this workgroup.
-// Each thread takes EPT / 2 pairs of consecutive elements of a SD_SLICE slice.
+// z = the K M output (or none), for basis vectors [z blk, (z+1) blk) of the
+// column (grid (ceil(Nmax / slice), ncols, nz)).  Each thread takes EP pairs
+// of consecutive elements of a slice; u and z stay in registers while the
+// block's vectors stream past, two per step with the next two in flight.
+// Partials go through LDS, flushed every SD_IBLK vectors.
 template <typename BT>
 __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, double2* __restrict__ pa,
-                                                 double2* __restrict__ pb, int ldh, int nb) {
+                                                 double2* __restrict__ pb, int ldh, int nb, int blk) {
+  constexpr int SL = sd_slice<BT>();
   const ColDev c = d[blockIdx.y];
-  const int ib = blockIdx.z * SD_IBLK;
-  if (ib >= c.cnt || blockIdx.x * SD_SLICE >= c.N) return;  // uniform per workgroup
-  const int ie = min(c.cnt, ib + SD_IBLK);
-  constexpr int EP = SD_SLICE / 512;  // pairs per thread
+  const int ib = blockIdx.z * blk;
+  if (ib >= c.cnt || blockIdx.x * SL >= c.N) return;  // uniform per workgroup
+  const int ie = min(c.cnt, ib + blk);
+  constexpr int EP = SL / 512;  // pairs per thread
   const BT* V = (const BT*)c.V;
   const BT* u = V + (int64_t)(c.cnt - 1) * c.ld;
   double2 xu[2 * EP], xz[2 * EP];
@@ -239,7 +270,7 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
   bool ok[2 * EP];
 #pragma unroll
   for (int e = 0; e < EP; ++e) {
-    const int n = blockIdx.x * SD_SLICE + 2 * (threadIdx.x + 256 * e);
+    const int n = blockIdx.x * SL + 2 * (threadIdx.x + 256 * e);
     ok[2 * e] = n < c.N;
     ok[2 * e + 1] = n + 1 < c.N;
     idx[e] = ok[2 * e] ? n : 0;
@@ -250,24 +281,47 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
     for (int h = 0; h < 2; ++h)
       if (!ok[2 * e + h]) xu[2 * e + h] = make_double2(0.0, 0.0);
   }
-  // two basis vectors per iteration; the eight sums (re / im of V^H u and
-  // V^H z for each) are reduced over the wavefront by a transposing
-  // butterfly (after the xor-32, -16 and -8 steps lane l holds sum number
-  // l / 8 of its lane group, then three plain steps finish it), and the
-  // per-wave results of the whole block meet in LDS behind one barrier
+  // the eight sums of a step (re / im of V^H u and V^H z for each of two
+  // vectors) are reduced over the wavefront by a transposing butterfly
+  // (after the xor-32, -16 and -8 steps lane l holds sum number l / 8 of its
+  // lane group, then three plain steps finish it); the per-wave results of
+  // the whole block meet in LDS
   __shared__ double red[SD_IBLK][4][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  BPair<BT> n0[EP], n1[EP];
+  {
+    const BT* v0 = V + (int64_t)ib * c.ld;
+    const BT* v1 = V + (int64_t)min(ib + 1, ie - 1) * c.ld;
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      n0[e].load(v0 + idx[e]);
+      n1[e].load(v1 + idx[e]);
+    }
+  }
 #pragma unroll 1
   for (int i = ib; i < ie; i += 2) {
     const bool two = i + 1 < ie;
-    const BT* v0 = V + (int64_t)i * c.ld;
-    const BT* v1 = V + (int64_t)(two ? i + 1 : i) * c.ld;
+    BPair<BT> c0[EP], c1[EP];
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      c0[e] = n0[e];
+      c1[e] = n1[e];
+    }
+    if (i + 2 < ie) {
+      const BT* v0 = V + (int64_t)(i + 2) * c.ld;
+      const BT* v1 = V + (int64_t)min(i + 3, ie - 1) * c.ld;
+#pragma unroll
+      for (int e = 0; e < EP; ++e) {
+        n0[e].load(v0 + idx[e]);
+        n1[e].load(v1 + idx[e]);
+      }
+    }
     double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       double2 a0[2], a1[2];
-      bld2(v0 + idx[e], a0[0], a0[1]);
-      bld2(v1 + idx[e], a1[0], a1[1]);
+      c0[e].get(a0[0], a0[1]);
+      c1[e].get(a1[0], a1[1]);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = 2 * e + h;
@@ -299,25 +353,32 @@ __global__ void __launch_bounds__(256) k_s_dots2(const ColDev* __restrict__ d, d
     r += __shfl_xor(r, 2, 64);
     r += __shfl_xor(r, 1, 64);
     const int q = lane >> 3;  // sum number: vector q / 4, component q % 4
-    if ((lane & 7) == 0 && (q < 4 || two)) red[i - ib + (q >> 2)][wv][q & 3] = r;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < ie - ib; t += 256) {
-    const double(*r)[4] = red[t];
-    const int64_t o = ((int64_t)blockIdx.y * ldh + ib + t) * nb + blockIdx.x;
-    pa[o] = make_double2((r[0][0] + r[1][0]) + (r[2][0] + r[3][0]), (r[0][1] + r[1][1]) + (r[2][1] + r[3][1]));
-    pb[o] = make_double2((r[0][2] + r[1][2]) + (r[2][2] + r[3][2]), (r[0][3] + r[1][3]) + (r[2][3] + r[3][3]));
+    const int slot = (i - ib) % SD_IBLK;  // i - ib is even: both vectors in one chunk
+    if ((lane & 7) == 0 && (q < 4 || two)) red[slot + (q >> 2)][wv][q & 3] = r;
+    if (slot + 2 == SD_IBLK || i + 2 >= ie) {  // chunk full or block done (uniform)
+      __syncthreads();
+      const int i0 = i - slot, cn = min(ie, i0 + SD_IBLK) - i0;
+      for (int t = threadIdx.x; t < cn; t += 256) {
+        const double(*rr)[4] = red[t];
+        const int64_t o = ((int64_t)blockIdx.y * ldh + i0 + t) * nb + blockIdx.x;
+        pa[o] = make_double2((rr[0][0] + rr[1][0]) + (rr[2][0] + rr[3][0]),
+                             (rr[0][1] + rr[1][1]) + (rr[2][1] + rr[3][1]));
+        pb[o] = make_double2((rr[0][2] + rr[1][2]) + (rr[2][2] + rr[3][2]),
+                             (rr[0][3] + rr[1][3]) + (rr[2][3] + rr[3][3]));
+      }
+      __syncthreads();
+    }
   }
 }
 
 // h[col hs + i] = sum of a-partials, h[col hs + ldh + i] = sum of b-partials.
 __global__ void __launch_bounds__(64) k_s_dots2_final(const ColDev* __restrict__ d, const double2* __restrict__ pa,
-                                                      const double2* __restrict__ pb, int ldh, int nb,
+                                                      const double2* __restrict__ pb, int ldh, int nb, int slice,
                                                       double2* __restrict__ h, int hs) {
   const ColDev c = d[blockIdx.y];
   const int i = blockIdx.x;
   if (i >= c.cnt) return;
-  const int nbc = (c.N + SD_SLICE - 1) / SD_SLICE;
+  const int nbc = (c.N + slice - 1) / slice;
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
   for (int k = threadIdx.x; k < nbc; k += 64) {
     const int64_t o = ((int64_t)blockIdx.y * ldh + i) * nb + k;
@@ -1025,7 +1086,8 @@ lm_status run_round(lm_server_s* S) {
             (c->phase == PH_ARNOLDI && !(c->j >= 1 && (c->j == c->m || c->its + 1 >= c->req->o.max_iter)));
     if (c->phase == PH_ARNOLDI) cntmax = std::max(cntmax, c->j + 1);
   }
-  const int nwu = 4 * (int)div_up(Nmax, 256), nbd = (int)div_up(Nmax, SD_SLICE);
+  const int slice = f32 ? sd_slice<float2>() : sd_slice<double2>();
+  const int nwu = 4 * (int)div_up(Nmax, 256), nbd = (int)div_up(Nmax, slice);
   // dot products per column: V^H u then V^H z, cntmax each (the longest
   // basis of the round), so the copy to the host holds no unused rows
   const int ldh = std::max(1, cntmax), hs = 2 * ldh;
@@ -1155,13 +1217,16 @@ lm_status run_round(lm_server_s* S) {
     LM_TRY(ensure(S, S->d_dpart, (size_t)2 * nc * ldh * nbd * sizeof(double2)));
     double2* pa = S->d_dpart.as<double2>();
     double2* pb = pa + (size_t)nc * ldh * nbd;
+    // split the basis over the grid's z only as far as needed for SD_WGS
+    // workgroups (each split reloads u and z), in near-equal blocks of at
+    // least 16 vectors
+    const int nz = std::max(1, std::min((int)div_up(SD_WGS, (int64_t)nbd * nc), (int)div_up(cntmax, 16)));
+    const int blk = (int)div_up(cntmax, nz);
     if (f32)
-      hipLaunchKernelGGL(k_s_dots2<float2>, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb,
-                         ldh, nbd);
+      hipLaunchKernelGGL(k_s_dots2<float2>, dim3(nbd, nc, nz), dim3(256), 0, S->s, dd, pa, pb, ldh, nbd, blk);
     else
-      hipLaunchKernelGGL(k_s_dots2<double2>, dim3(nbd, nc, div_up(cntmax, SD_IBLK)), dim3(256), 0, S->s, dd, pa, pb,
-                         ldh, nbd);
-    hipLaunchKernelGGL(k_s_dots2_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, pa, pb, ldh, nbd,
+      hipLaunchKernelGGL(k_s_dots2<double2>, dim3(nbd, nc, nz), dim3(256), 0, S->s, dd, pa, pb, ldh, nbd, blk);
+    hipLaunchKernelGGL(k_s_dots2_final, dim3(cntmax, nc), dim3(64), 0, S->s, dd, pa, pb, ldh, nbd, slice,
                        d_h, hs);
   }
   // norms: of g - K M z (restart, final) or g (first round); Arnoldi columns
