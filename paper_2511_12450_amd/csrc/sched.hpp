@@ -8,7 +8,10 @@
 // over indefinitely); every admitted request advances one step per round;
 // a cancelled running request leaves at the start of the next round, a
 // queued one at once; destroying the scheduler stops the worker after its
-// current round and frees every request.
+// current round and frees every request.  Device memory kept for reuse when
+// the last request leaves (fused-launch and round buffers) is given back
+// only when no request arrives within idle_release: a request that follows
+// at once does not wait for that memory to be freed and allocated again.
 //
 // Ownership: a request stays LM_QUEUED or LM_RUNNING, so that no client can
 // release (free) it, until the worker has given back its device work and its
@@ -27,10 +30,13 @@
 //   bool finished(Req*, bool* conv)  the request is complete (conv: converged)
 //   void trim(int64_t allow, const std::vector<Req*>& admitted)
 //   void settle(bool idle)           after the round (idle: nothing admitted)
+//   void release_idle()              give back what was kept for reuse, once
+//                                    the worker has stayed idle for idle_release
 //   double now()
 //   std::string last_error()         message of the last failed call
 #pragma once
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -55,6 +61,7 @@ struct Book {
   int active = 0;    // admitted right-hand sides
   int max_rhs = 64;
   int64_t budget = (int64_t)64 << 30;
+  std::chrono::microseconds idle_release{20000};
 
   // --- called by clients (each takes the lock) ---------------------------------
   // Queues q (already validated); LM_ENOMEM if it can never be admitted, in
@@ -133,6 +140,7 @@ struct Book {
 template <class Req, class Dev>
 void run_worker(Book<Req>& B, Dev& D) {
   std::vector<Req*> running;
+  bool kept = false;  // the device keeps memory for reuse since the last request left
   // Gives back q's slots and ends it (lock held); q may be freed by a client after this.
   auto finish = [&](Req* q, lm_state state, lm_status status) {
     B.used -= q->bytes;
@@ -175,7 +183,19 @@ void run_worker(Book<Req>& B, Dev& D) {
       }
       allow = B.budget - B.used;
       if (running.empty() && admit.empty()) {
-        B.cv.wait(lk, [&] { return B.stop || !B.queue.empty(); });
+        auto work = [&] { return B.stop || !B.queue.empty(); };
+        if (kept) {
+          // system_clock: its timed wait is pthread_cond_timedwait, which
+          // the thread sanitizer understands (steady_clock's is not)
+          if (!B.cv.wait_until(lk, std::chrono::system_clock::now() + B.idle_release, work)) {
+            lk.unlock();
+            D.release_idle();
+            lk.lock();
+            kept = false;
+          }
+          continue;
+        }
+        B.cv.wait(lk, work);
         continue;
       }
     }
@@ -215,6 +235,7 @@ void run_worker(Book<Req>& B, Dev& D) {
       }
     }
     D.settle(running.empty());
+    if (running.empty()) kept = true;
   }
   // stopped: what still runs is released; the requests are freed with the book
   for (Req* q : running) D.release(q);

@@ -41,9 +41,11 @@
 #include <complex>
 #include <condition_variable>
 #include <cstring>
+#include <cstdlib>
 #include <deque>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -527,7 +529,15 @@ struct Request {
   lm_status status = LM_OK, fail_status = LM_OK;  // fail_status: a failure pending until the worker lets go
   std::string err;
   std::vector<lm_solve_report> rep;
-  std::vector<double2> phi, ff;
+  // phi: R x N, malloc'd without touching it (a zero-filled vector costs a
+  // page fault and a fill per 4 KiB on the submitting thread); every column's
+  // slice is written before the request is done
+  struct FreeHost {
+    void operator()(double2* p) const { std::free(p); }
+  };
+  std::unique_ptr<double2, FreeHost> phi;
+  size_t phi_n = 0;
+  std::vector<double2> ff;
   int cols_left = 0;
   bool cancel = false;
   double t_submit = 0.0, t_done = 0.0;
@@ -819,11 +829,52 @@ void drop_spares(lm_server_s* S) {
 
 int64_t col_bytes(const Column* c) { return (int64_t)(c->V.bytes + c->z.bytes + c->gv.bytes + c->y.bytes + c->dn.bytes); }
 
-// Frees spare columns until they hold at most `allow` bytes: first those no
-// admitted request can reuse (another N or restart length), oldest first.
+bool group_live(const lm_server_s* S, const std::pair<lm_geom_s*, int>& key) {
+  for (const Column* c : S->cols)
+    if (c->g == key.first && c->req && (c->req->o.precond ? 1 : 0) == key.second) return true;
+  return false;
+}
+
+int64_t group_bytes(const Group& G) {
+  return (int64_t)(G.X.bytes + G.Y.bytes + G.km.x32.bytes + G.km.y32.bytes + G.km.mz.bytes);
+}
+
+// Frees the fused-launch buffers of the groups that no admitted column uses
+// and `drop` selects, waiting first for queued kernels that may use them.
+template <typename F> void drop_groups(lm_server_s* S, F drop) {
+  bool synced = false;
+  for (auto it = S->groups.begin(); it != S->groups.end();) {
+    if (group_live(S, it->first) || !drop(it->first)) {
+      ++it;
+      continue;
+    }
+    if (!synced) (void)quiesce(S);
+    synced = true;
+    it = S->groups.erase(it);
+  }
+}
+
+// Before admitting: the fused-launch buffers kept from an idle period stay
+// only for the admitted requests' (geometry, preconditioner) groups and only
+// if they fit beside the spare columns in what the budget leaves (`allow`);
+// then spare columns are freed until they hold at most `allow` bytes: first
+// those no admitted request can reuse (another N or restart length), oldest
+// first.
 void trim_spares(lm_server_s* S, int64_t allow, const std::vector<Request*>& admit) {
-  int64_t sb = 0;
+  auto wanted = [&](const std::pair<lm_geom_s*, int>& key) {
+    for (const Request* q : admit)
+      if (q->g == key.first && (q->o.precond ? 1 : 0) == key.second) return true;
+    return false;
+  };
+  drop_groups(S, [&](const std::pair<lm_geom_s*, int>& key) { return !wanted(key); });
+  int64_t sb = 0, kept = 0;
   for (Column* c : S->spare) sb += col_bytes(c);
+  for (const auto& kv : S->groups)
+    if (!group_live(S, kv.first)) kept += group_bytes(kv.second);
+  if (sb + kept > allow) {
+    drop_groups(S, [](const std::pair<lm_geom_s*, int>&) { return true; });
+    kept = 0;
+  }
   auto reusable = [&](const Column* c) {
     for (const Request* q : admit)
       if (q->g->N == c->N && std::max(1, std::min(q->o.restart, q->o.max_iter)) == c->m) return true;
@@ -842,39 +893,12 @@ void trim_spares(lm_server_s* S, int64_t allow, const std::vector<Request*>& adm
     }
 }
 
-// Frees the fused-launch buffers of (geometry, preconditioner) groups that no
-// admitted column uses any more, and the round and finishing buffers when
-// nothing runs; then records the device bytes the server holds.
-void settle_memory(lm_server_s* S, bool idle) {
-  if (idle) {  // nothing is queued behind this wait
-    (void)quiesce(S);
-    (void)collect_update_time(S);
-  }
-  bool synced = idle;
-  for (auto it = S->groups.begin(); it != S->groups.end();) {
-    bool live = false;
-    for (const Column* c : S->cols)
-      if (c->g == it->first.first && c->req && (c->req->o.precond ? 1 : 0) == it->first.second) {
-        live = true;
-        break;
-      }
-    if (!live && !synced) {
-      (void)quiesce(S);  // the group's buffers may still be in use by queued kernels
-      synced = true;
-    }
-    it = live ? std::next(it) : S->groups.erase(it);
-  }
-  if (idle)  // nothing admitted: the round and finishing buffers are regrown on demand
-    for (DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
-                      &S->d_fff, &S->d_fobs, &S->d_adm})
-      b->release();
+// Records the device bytes the server holds (all / spare columns).
+void record_held(lm_server_s* S) {
   int64_t h = 0, hs = 0;
   for (const Column* c : S->cols) h += col_bytes(c);
   for (const Column* c : S->spare) hs += col_bytes(c);
-  for (const auto& kv : S->groups) {
-    const Group& G = kv.second;
-    h += (int64_t)(G.X.bytes + G.Y.bytes + G.km.x32.bytes + G.km.y32.bytes + G.km.mz.bytes);
-  }
+  for (const auto& kv : S->groups) h += group_bytes(kv.second);
   for (const DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
                           &S->d_fff, &S->d_fobs, &S->d_adm})
     h += (int64_t)b->bytes;
@@ -882,6 +906,31 @@ void settle_memory(lm_server_s* S, bool idle) {
   std::lock_guard<std::mutex> lk(S->B.mu);
   S->held = h + hs;
   S->held_spare = hs;
+}
+
+// After a round.  While requests run, the fused-launch buffers of groups no
+// admitted column uses any more are freed.  When the last request has left,
+// everything is kept for the next one (the worker calls release_idle_memory
+// if none comes soon).
+void settle_memory(lm_server_s* S, bool idle) {
+  if (idle) {  // nothing is queued behind the last results
+    (void)hipStreamSynchronize(S->s);
+    (void)collect_update_time(S);
+  } else {
+    drop_groups(S, [](const std::pair<lm_geom_s*, int>&) { return true; });
+  }
+  record_held(S);
+}
+
+// The worker has stayed idle: frees the fused-launch buffers, the round and
+// finishing buffers and the retired allocations.
+void release_idle_memory(lm_server_s* S) {
+  (void)quiesce(S);
+  drop_groups(S, [](const std::pair<lm_geom_s*, int>&) { return true; });
+  for (DevBuf* b : {&S->d_desc, &S->d_desc_u, &S->d_hn, &S->d_dpart, &S->d_npart, &S->d_fz, &S->d_fphi,
+                    &S->d_fff, &S->d_fobs, &S->d_adm})
+    b->release();
+  record_held(S);
 }
 
 lm_status start_request(lm_server_s* S, Request* q) {
@@ -958,7 +1007,7 @@ bool complete_staged(lm_server_s* S, bool block) {
   auto copy = [&](int i) {
     const lm_server_s::Staged& e = S->staged[i];
     Column* c = e.c;
-    std::memcpy(c->req->phi.data() + (size_t)c->col * c->N, hb + e.phi_off, (size_t)c->N * sizeof(double2));
+    std::memcpy(c->req->phi.get() + (size_t)c->col * c->N, hb + e.phi_off, (size_t)c->N * sizeof(double2));
     if (e.no)
       std::memcpy(c->req->ff.data() + (size_t)c->col * e.no, hb + e.ff_off, (size_t)e.no * sizeof(double2));
   };
@@ -1595,6 +1644,7 @@ struct GpuDev {
   // footprints leave no room for
   void trim(int64_t allow, const std::vector<Request*>& admit) { trim_spares(S, allow, admit); }
   void settle(bool idle) { settle_memory(S, idle); }
+  void release_idle() { release_idle_memory(S); }
   double now() const { return now_s(); }
   std::string last_error() const { return lm_last_error(); }
 };
@@ -1674,7 +1724,12 @@ extern "C" lm_status lm_submit(lm_server S, const lm_request* r, uint64_t* id) {
   if (r->n_obs) q->obs.assign(r->obs_rad, r->obs_rad + r->n_obs);
   q->o = r->gmres;
   q->bytes = footprint(q->g, q->o, q->R);
-  q->phi.assign((size_t)q->R * q->g->N, make_double2(0.0, 0.0));
+  q->phi_n = (size_t)q->R * q->g->N;
+  q->phi.reset(static_cast<double2*>(std::malloc(q->phi_n * sizeof(double2))));
+  if (!q->phi) {
+    delete q;
+    LM_CHECK(false, LM_ENOMEM, "host allocation failed");
+  }
   q->ff.assign((size_t)q->R * r->n_obs, make_double2(0.0, 0.0));
   if (q->R > S->o.max_active_rhs || q->bytes > S->o.hbm_budget_bytes)
     lm_set_error("request can never be admitted (%d right-hand sides, %lld bytes)", r->n_rhs, (long long)q->bytes);
@@ -1691,7 +1746,7 @@ extern "C" lm_status lm_poll(lm_server S, uint64_t id, lm_state* state, lm_solve
   if (latency_s) *latency_s = q->t_done > 0 ? q->t_done - q->t_submit : now_s() - q->t_submit;
   if (q->state == LM_DONE) {
     if (reports) std::copy(q->rep.begin(), q->rep.end(), reports);
-    if (phi_host) std::memcpy(phi_host, q->phi.data(), q->phi.size() * sizeof(double2));
+    if (phi_host) std::memcpy(phi_host, q->phi.get(), q->phi_n * sizeof(double2));
     if (far_field_host) std::memcpy(far_field_host, q->ff.data(), q->ff.size() * sizeof(double2));
     return q->status;
   }

@@ -56,7 +56,7 @@ struct FakeDev {
   std::mutex m;  // guards the records below (read by the test thread)
   std::vector<int> start_order;
   std::set<Req*> live;
-  int starts = 0, releases = 0, rounds = 0, trims = 0, settles_idle = 0;
+  int starts = 0, releases = 0, rounds = 0, trims = 0, settles_idle = 0, idle_releases = 0;
   int max_active = 0;
   int64_t max_used = 0;
   int fail_round_at = -1;  // this round fails (once)
@@ -120,6 +120,11 @@ struct FakeDev {
       CHECK(live.empty());
       ++settles_idle;
     }
+  }
+  void release_idle() {
+    std::lock_guard<std::mutex> lk(m);
+    CHECK(live.empty());
+    ++idle_releases;
   }
   double now() const { return ::now(); }
   std::string last_error() {
@@ -426,13 +431,50 @@ void case_concurrent_clients() {
   CHECK(s.D.max_active <= 6 && s.D.max_used <= 2000);
 }
 
+// Kept memory is given back only after the worker has stayed idle for
+// idle_release; a request arriving sooner finds it still there.
+void case_idle_release() {
+  Sched s(4, 1000);
+  {
+    std::lock_guard<std::mutex> lk(s.B.mu);
+    s.B.idle_release = std::chrono::microseconds(100000);
+  }
+  uint64_t a = s.submit(2, 100, 3, 0);
+  s.wait_all({a});
+  uint64_t b = s.submit(2, 100, 3, 1);  // at once: before the idle release
+  s.wait_all({b});
+  {
+    std::lock_guard<std::mutex> lk(s.D.m);
+    CHECK(s.D.idle_releases == 0 && s.D.settles_idle >= 1);
+  }
+  const double t0 = now();
+  while (true) {
+    {
+      std::lock_guard<std::mutex> lk(s.D.m);
+      if (s.D.idle_releases == 1) break;
+    }
+    CHECK(now() - t0 < 5.0);
+    std::this_thread::sleep_for(std::chrono::milliseconds(5));
+  }
+  CHECK(now() - t0 > 0.05);  // not before the idle time has passed
+  std::this_thread::sleep_for(std::chrono::milliseconds(300));
+  {
+    std::lock_guard<std::mutex> lk(s.D.m);
+    CHECK(s.D.idle_releases == 1);  // once per idle period
+  }
+  uint64_t c = s.submit(1, 100, 2, 2);
+  s.wait_all({c});
+  for (uint64_t id : {a, b, c}) CHECK(s.B.release(id) == LM_OK);
+  s.check_idle();
+}
+
 const std::pair<const char*, void (*)()> kCases[] = {
     {"admission_fifo", case_admission_fifo},     {"head_of_line", case_head_of_line},
     {"reject", case_reject},                     {"cancel_queued", case_cancel_queued},
     {"cancel_running", case_cancel_running},     {"release", case_release},
     {"not_converged", case_not_converged},       {"start_failure", case_start_failure},
     {"round_failure", case_round_failure},       {"destroy_in_flight", case_destroy_in_flight},
-    {"concurrent_clients", case_concurrent_clients},
+    {"concurrent_clients", case_concurrent_clients}, {"idle_release", case_idle_release},
 };
 
 }  // namespace

@@ -10,7 +10,8 @@ The cases (tests/sched_fake.cpp): admission under both limits in submission
 order, head-of-line blocking, rejection at submission, cancel of queued and
 running requests, release only in a terminal state, LM_NOT_CONVERGED, a
 failed start, a failed round, destruction with requests queued and running,
-and four client threads submitting, cancelling and releasing at random.
+four client threads submitting, cancelling and releasing at random, and the
+release of kept device memory only after the worker has stayed idle.
 """
 
 import os
@@ -24,7 +25,7 @@ SRC = os.path.join(ROOT, "tests", "sched_fake.cpp")
 INC = [os.path.join(ROOT, "paper_2511_12450_amd", "csrc"), os.path.join(ROOT, "include")]
 
 CASES = ["admission_fifo", "head_of_line", "reject", "cancel_queued", "cancel_running", "release", "not_converged",
-         "start_failure", "round_failure", "destroy_in_flight", "concurrent_clients"]
+         "start_failure", "round_failure", "destroy_in_flight", "concurrent_clients", "idle_release"]
 
 SANITIZERS = {"asan_ubsan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
               "tsan": ["-fsanitize=thread"]}
