@@ -138,16 +138,22 @@ lm_status put_f64_async(const double* host, int n, double* dev, hipStream_t s) {
 //   a_e = [l_e = 0] i/(2 k_{0,y}) e^{-i k_{0,y} y_e}
 //       + e^{i k_{0,y} d_0} sum_s S^{(B,s)}_{0 l_e}(lam) e^{i k_{l_e,y} h_s(y_e)},
 // lam = k_0 cos t; the bottom layer mirrors this with side T of layer L.
+// One workgroup: an angle, FF_RB right-hand sides (the amplitudes a_e are
+// evaluated once for all of them) and a chunk of elements; with several
+// chunks (grid z) each writes its partial sums to out + z R n_obs and
+// k_far_field_sum adds them in chunk order.
 constexpr int FF_RB = 8;
 
 __global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, const double* __restrict__ obs,
                                                    const double* __restrict__ cx, const double* __restrict__ cy,
                                                    const double* __restrict__ w, const int* __restrict__ lay,
                                                    const double2* __restrict__ phi, double2* __restrict__ out,
-                                                   int n_obs) {
+                                                   int n_obs, int chunk) {
   const int o = blockIdx.x;
   const int r0 = blockIdx.y * FF_RB;
   const int nr = min(FF_RB, R - r0);
+  const int e0 = blockIdx.z * chunk, e1 = min(N, e0 + chunk);
+  out += (int64_t)blockIdx.z * R * n_obs;
   const double th = obs[o];
   const bool top = sin(th) > 0.0;
   const int lt = top ? 0 : m.L;
@@ -173,7 +179,7 @@ __global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, co
   }
   __syncthreads();
   zd acc[FF_RB];
-  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
     const int l = lay[e];
     const double y = cy[e];
     zd a(0.0, 0.0);
@@ -215,22 +221,63 @@ __global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, co
   }
 }
 
+// out[i] = sum over z of part[z n + i], z = 0..nz-1 in order.
+__global__ void __launch_bounds__(256) k_far_field_sum(int64_t n, int nz, const double2* __restrict__ part,
+                                                       double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double2 v = part[i];
+  for (int z = 1; z < nz; ++z) {
+    const double2 p = part[(int64_t)z * n + i];
+    v.x += p.x;
+    v.y += p.y;
+  }
+  out[i] = v;
+}
+
+namespace {
+// Element chunks of a far-field launch: enough workgroups to fill the GPU
+// (about 2048), chunks of at least 4096 elements, at most FF_MAXZ of them.
+constexpr int FF_MAXZ = 8;
+int ff_chunks(int N, int R, int n_obs) {
+  const int64_t wg = (int64_t)n_obs * div_up(R, FF_RB);
+  const int want = (int)std::min<int64_t>(FF_MAXZ, std::max<int64_t>(1, div_up(2048, std::max<int64_t>(wg, 1))));
+  return std::max(1, std::min(want, (int)div_up(N, 4096)));
+}
+}  // namespace
+
+size_t farfield_work_bytes(lm_geom_s* g, int R, int n_obs) {
+  const int nz = ff_chunks((int)g->N, R, n_obs);
+  return nz > 1 ? (size_t)nz * R * n_obs * sizeof(double2) : 0;
+}
+
 lm_status farfield_launch_dev(lm_geom_s* g, int R, const void* phi, int n_obs, const double* obs_dev, void* out,
-                              hipStream_t s) {
+                              void* work, hipStream_t s) {
   const int N = (int)g->N;
-  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, g->m, N, R, obs_dev,
+  const int nz = ff_chunks(N, R, n_obs);
+  const int chunk = (int)div_up(div_up(N, nz), 256) * 256;
+  double2* dst = nz > 1 ? (double2*)work : (double2*)out;
+  LM_CHECK(nz == 1 || work, LM_EINVAL, "far field: a work buffer is needed");
+  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB), nz), dim3(256), 0, s, g->m, N, R, obs_dev,
                      g->d_cx.as<double>(), g->d_cy.as<double>(), g->d_w.as<double>(), g->d_layer.as<int>(),
-                     (const double2*)phi, (double2*)out, n_obs);
+                     (const double2*)phi, dst, n_obs, chunk);
   LM_TRY_HIP(hipGetLastError());
+  if (nz > 1) {
+    const int64_t n = (int64_t)R * n_obs;
+    hipLaunchKernelGGL(k_far_field_sum, dim3(div_up(n, 256)), dim3(256), 0, s, n, nz, (const double2*)work,
+                       (double2*)out);
+    LM_TRY_HIP(hipGetLastError());
+  }
   return LM_OK;
 }
 
 lm_status farfield_launch(lm_geom_s* g, int R, const void* phi, int n_obs, const double* obs_host, void* out,
                           hipStream_t s) {
-  DevBuf ob;
+  DevBuf ob, wk;
   LM_TRY(upload(ob, obs_host, n_obs * sizeof(double), s));
-  LM_TRY(farfield_launch_dev(g, R, phi, n_obs, ob.as<double>(), out, s));
-  LM_TRY_HIP(hipStreamSynchronize(s));  // before ob is freed
+  LM_TRY(wk.alloc(farfield_work_bytes(g, R, n_obs)));
+  LM_TRY(farfield_launch_dev(g, R, phi, n_obs, ob.as<double>(), out, wk.p, s));
+  LM_TRY_HIP(hipStreamSynchronize(s));  // before ob and wk are freed
   return LM_OK;
 }
 
@@ -255,9 +302,9 @@ lm_status point_far_field_launch(const MediumDev& m, int R, const double* src_xy
   LM_TRY(upload(dw, w.data(), R * sizeof(double), s));
   LM_TRY(upload(dl, lay.data(), R * sizeof(int32_t), s));
   LM_TRY(upload(dphi, eye.data(), eye.size() * sizeof(double2), s));
-  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB)), dim3(256), 0, s, m, R, R, ob.as<double>(),
+  hipLaunchKernelGGL(k_far_field, dim3(n_obs, div_up(R, FF_RB), 1), dim3(256), 0, s, m, R, R, ob.as<double>(),
                      dx.as<double>(), dy.as<double>(), dw.as<double>(), dl.as<int>(), dphi.as<double2>(),
-                     (double2*)out, n_obs);
+                     (double2*)out, n_obs, R);
   LM_TRY_HIP(hipGetLastError());
   LM_TRY_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
   return LM_OK;

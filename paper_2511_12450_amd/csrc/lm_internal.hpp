@@ -133,7 +133,9 @@ size_t rhs_scratch_bytes(int n_rhs);
 lm_status rhs_launch_dev(lm_geom_s* g, int n_rhs, const double* theta_dev, void* scratch, void* g_dev,
                          hipStream_t s);
 lm_status farfield_launch_dev(lm_geom_s* g, int n_rhs, const void* phi, int n_obs, const double* obs_dev,
-                              void* out, hipStream_t s);
+                              void* out, void* work, hipStream_t s);
+// bytes of the work buffer farfield_launch_dev needs (0: none)
+size_t farfield_work_bytes(lm_geom_s* g, int n_rhs, int n_obs);
 // Copies n doubles from host memory to the device in kernel arguments
 // (stream-ordered; the host array may be reused as soon as this returns).
 lm_status put_f64_async(const double* host, int n, double* dev, hipStream_t s);

@@ -1077,10 +1077,13 @@ lm_status finish_columns(lm_server_s* S, std::vector<Column*>& fin, std::vector<
         const int no = (int)obs.size();
         if (no) {
           const size_t fb = (size_t)(b - a) * no * sizeof(double2);
-          LM_TRY(ensure(S, S->d_fff, fb));
+          // far fields, then the chunk partials of the launch behind them
+          const size_t fw = farfield_work_bytes(g, b - a, no);
+          LM_TRY(ensure(S, S->d_fff, fb + fw));
           LM_TRY(ensure(S, S->d_fobs, (size_t)no * sizeof(double)));
           LM_TRY(put_f64_async(obs.data(), no, S->d_fobs.as<double>(), S->s));
-          LM_TRY(farfield_launch_dev(g, b - a, pb + a * vb, no, S->d_fobs.as<double>(), S->d_fff.p, S->s));
+          LM_TRY(farfield_launch_dev(g, b - a, pb + a * vb, no, S->d_fobs.as<double>(), S->d_fff.p,
+                                     S->d_fff.as<char>() + fb, S->s));
           LM_TRY_HIP(hipMemcpyAsync(hb + off, S->d_fff.p, fb, hipMemcpyDeviceToHost, S->s));
           for (int i = a; i < b; ++i) {
             lm_server_s::Staged& e = S->staged[s0 + i];
