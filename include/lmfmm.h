@@ -352,8 +352,11 @@ lm_status lm_point_field(lm_layers layers, int n_src, const double* src_xy_host,
  * same budget and are freed (those no admitted request can reuse first) when
  * an admission needs the room, when an allocation fails and at
  * lm_server_destroy.  The buffers of the fused launches of a geometry are
- * freed once none of its solves is admitted, so the device memory the server
- * holds (lm_server_memory) stays within the budget.
+ * freed once none of its solves is admitted while other solves run; when the
+ * last request leaves they are kept, with the per-round buffers, for 20 ms
+ * and freed if no request arrives meanwhile (an admission keeps them only for
+ * its own geometries and only within the budget), so the device memory the
+ * server holds (lm_server_memory) stays within the budget.
  * All server entry points are thread-safe. */
 typedef struct {
   int64_t hbm_budget_bytes;
