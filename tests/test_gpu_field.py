@@ -7,6 +7,11 @@ at 0.01 and 0.001 from each interface (the spectral reaction sum extends its
 nodes with the inverse of that distance).  Bar: 1e-9 relative to the largest
 value per right-hand side, entry by entry (both sides FP64; the oracle's
 quadrature is converged to about 1e-13 per Green's function value).
+
+Far field (lm_far_field) of given densities on a geometry large enough that
+the launch splits its elements over several workgroup chunks and adds their
+partial sums: entry by entry against the oracle's closed form (eq.
+integralrep at large distance), top and bottom directions.
 """
 
 import numpy as np
@@ -14,7 +19,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.farfield import scattered_field
+from oracle.farfield import far_field, scattered_field
 from oracle.green import LayeredGreen
 from oracle.medium import Medium
 from oracle.nystrom import Elements
@@ -68,3 +73,17 @@ def test_point_field_vs_oracle():
         for p, q in enumerate(pts):
             ref[r, p] = G.green(q[0], q[1], [s[0]], [s[1]], lp=ls)[0]
     check(u, ref, 1e-9, "point-source field at receivers vs oracle")
+
+
+def test_far_field_chunked_vs_oracle():
+    w = wl.three_layer_mini(seed=6, n_scat=80)
+    med = Medium(w.d, w.k, w.eta)
+    el = Elements(med, w.polygons)
+    assert el.n >= 3 * 4096  # three or more element chunks in the launch below
+    obs = np.concatenate([np.radians(np.linspace(5.0, 175.0, 24)), np.radians(np.linspace(185.0, 355.0, 16))])
+    print(f"case: chunked far field, N={el.n}, {obs.size} angles", flush=True)
+    geo = lmfmm.Geometry.from_workload(w, method=lmfmm.LM_FMM, precond=0)
+    phi = wl.random_vector(el.n, seed=9, n_rhs=3)
+    ff = geo.far_field(torch.from_numpy(phi).cuda(), obs).cpu().numpy()
+    ref = np.array([far_field(med, el, phi[r], obs) for r in range(3)])
+    check(ff, ref, 1e-11, "chunked far field vs oracle")
