@@ -141,8 +141,10 @@ lm_status put_f64_async(const double* host, int n, double* dev, hipStream_t s) {
 // One workgroup: an angle, FF_RB right-hand sides (the amplitudes a_e are
 // evaluated once for all of them) and a chunk of elements; with several
 // chunks (grid z) each writes its partial sums to out + z R n_obs and
-// k_far_field_sum adds them in chunk order.
-constexpr int FF_RB = 8;
+// k_far_field_sum adds them in chunk order.  16 right-hand sides per
+// workgroup (64k elements, 682 angles: 2.61 -> 2.24 ms at R = 21 and
+// 7.42 -> 5.86 ms at R = 64 against 8; 12 was no better).
+constexpr int FF_RB = 16;
 
 __global__ void __launch_bounds__(256) k_far_field(MediumDev m, int N, int R, const double* __restrict__ obs,
                                                    const double* __restrict__ cx, const double* __restrict__ cy,
