@@ -299,3 +299,33 @@ def test_odd_n_basis_padding():
             check(ff, want, bar, f"N={el.n} precision {prec}: far field vs oracle")
         finally:
             srv.close()
+
+
+def test_same_results_with_kept_and_released_buffers(geoms):
+    """A request submitted at once after another (fused-launch, round and
+    finishing buffers kept), and again after the server has been idle long
+    enough to give them back, returns the same phi and far field bit for bit
+    (each column is computed independently of what the buffers held)."""
+    mini, g_mini, small, g_small = geoms
+    srv = lmfmm.Server(precision=lmfmm.LM_MIXED)
+    try:
+        th = np.radians([35.0, 80.0, 125.0])
+        outs = []
+        for pause in (0.0, 0.0, 0.2):
+            time.sleep(pause)
+            rid = srv.submit(g_mini, th, tol=1e-6, max_iter=800, restart=400, obs_rad=OBS)
+            st, s, lat, rep, phi, ff = srv.wait(rid)
+            assert st == lmfmm.LM_DONE and s == lmfmm.LM_OK
+            outs.append((phi, ff, [r[0] for r in rep]))
+            srv.release(rid)
+            if pause > 0.0:
+                assert srv.memory()["held"] > 0
+        time.sleep(0.1)
+        m = srv.memory()
+        print("iterations", [o[2] for o in outs], "memory at rest", m, flush=True)
+        assert m["held"] == m["spare"]  # the idle release ran
+        for phi, ff, its in outs[1:]:
+            assert its == outs[0][2]
+            assert np.array_equal(phi, outs[0][0]) and np.array_equal(ff, outs[0][1])
+    finally:
+        srv.close()
